@@ -1,0 +1,447 @@
+/*
+ * FP64 CPU oracle for the FLA source projection and the PSI-CELL comparator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU library is checked against.  Only the tests, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
+ * code, header or constant with the GPU library.
+ *
+ * Everything is IEEE binary64, evaluated in the order written (build with
+ * -ffp-contract=off so that no multiply-add is fused).  Paper references are
+ * to Stafford & Rybdylova, "Interphase coupling for gas-droplet flows using
+ * the fully Lagrangian approach" (arXiv 2512.20829).
+ *
+ * Readings of the paper taken here (the paper is silent on them):
+ *  - the Gaussian kernel (eq. "kernel") is truncated: a trajectory contributes
+ *    to a cell centre only if sum_a (d_a/h)^2 <= c^2 (c = cutoff, 4 by
+ *    default), where d_a is the per-axis offset (minimum image on periodic
+ *    axes).  The test itself is evaluated either in binary64 or, for the
+ *    single-precision product path, by rounding each (d_a/h)^2 to binary32 and
+ *    summing in binary32 in axis order, so that both sides take the same
+ *    integer decision;
+ *  - the kernel keeps the paper's 1/h prefactor in every dimension;
+ *  - each source term is returned with the minus sign of the averaged coupling
+ *    terms (eq. "coupling-terms-averaged");
+ *  - a cell with zero kernel denominator gets S = 0;
+ *  - trajectories with det J = 0 or any non-finite input are skipped.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Mesh geometry: uniform Cartesian cells on [lo, hi), cell centres at       */
+/* lo + (i + 1/2) * (hi - lo)/n.  Linear cell index: i0 + n0*(i1 + n1*i2).   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int dim;
+    int n[3];
+    double lo[3];
+    double hi[3];
+    int periodic[3];
+} orc_mesh;
+
+static double cell_width(const orc_mesh* m, int a) { return (m->hi[a] - m->lo[a]) / (double)m->n[a]; }
+
+static double cell_centre(const orc_mesh* m, int a, int64_t i)
+{
+    double w = cell_width(m, a);
+    double t = ((double)i + 0.5) * w;
+    return m->lo[a] + t;
+}
+
+static void cell_coords(const orc_mesh* m, int64_t c, int64_t idx[3])
+{
+    idx[0] = c % m->n[0];
+    c /= m->n[0];
+    idx[1] = c % m->n[1];
+    idx[2] = (m->dim == 3) ? c / m->n[1] : 0;
+}
+
+static double cell_volume(const orc_mesh* m)
+{
+    double v = 1.0;
+    for (int a = 0; a < m->dim; ++a) v *= cell_width(m, a);
+    return v;
+}
+
+/* Offset from a point to a cell centre along one axis; minimum image on a
+ * periodic axis. */
+static double axis_offset(const orc_mesh* m, int a, double xc, double xp)
+{
+    double d = xc - xp;
+    if (m->periodic[a]) {
+        double L = m->hi[a] - m->lo[a];
+        double k = rint(d / L);
+        double s = L * k;
+        d = d - s;
+    }
+    return d;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Determinant by cofactor expansion along the first row (row-major J).      */
+/* ------------------------------------------------------------------------ */
+double orc_det(int dim, const double* J)
+{
+    if (dim == 2) {
+        double p = J[0] * J[3];
+        double q = J[1] * J[2];
+        return p - q;
+    }
+    double m0 = J[4] * J[8] - J[5] * J[7];
+    double m1 = J[3] * J[8] - J[5] * J[6];
+    double m2 = J[3] * J[7] - J[4] * J[6];
+    double t0 = J[0] * m0;
+    double t1 = J[1] * m1;
+    double t2 = J[2] * m2;
+    return (t0 - t1) + t2;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Droplet physics for one droplet (dimensional forms of eqs. 3-5).          */
+/*   m     = (4/3) pi rho_d r^3               (sphere volume x density)     */
+/*   tau   = 2 rho_d r^2 / (9 mu)             (Stokes relaxation, eq. 5)    */
+/*   F     = m (u_g - v) / tau                (F = m x'', x'' from eq. 3)   */
+/*   mdot  = 4 pi rho_d r^2 rdot, rdot = delta/(2 r)   (eq. 4)               */
+/* Channel vector phi = [mdot, F_a + mdot v_a] (eq. coupling-terms-spec.).   */
+/* ------------------------------------------------------------------------ */
+void orc_droplet_phi(int dim, double r, const double* v, const double* ug,
+                     double rho_d, double mu, double delta, double* phi,
+                     double* m_out, double* tau_out, double* mdot_out)
+{
+    double m = (4.0 / 3.0) * ORC_PI * rho_d * r * r * r;
+    double tau = 2.0 * rho_d * r * r / (9.0 * mu);
+    double rdot = delta / (2.0 * r);
+    double mdot = 4.0 * ORC_PI * rho_d * r * r * rdot;
+    phi[0] = mdot;
+    for (int a = 0; a < dim; ++a) {
+        double F = m * (ug[a] - v[a]) / tau;
+        phi[1 + a] = F + mdot * v[a];
+    }
+    if (m_out) *m_out = m;
+    if (tau_out) *tau_out = tau;
+    if (mdot_out) *mdot_out = mdot;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-trajectory terms: det J, n = n0/|det J| (eq. FLA-COM), h = h0|det J| */
+/* (eq. smoothing-length) times an optional bandwidth factor, and           */
+/* q = n * phi (eq. coupling-terms-kernel numerators).                      */
+/* Arrays: x, v, ug are dim x N planes; J is dim*dim x N planes.            */
+/* ------------------------------------------------------------------------ */
+static int all_finite(const double* a, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(a[i])) return 0;
+    return 1;
+}
+
+int64_t orc_trajectory_terms(int dim, int64_t N, const double* x, const double* J,
+                             const double* v, const double* ug, const double* r,
+                             const double* n0, double n0_scalar, double rho_d, double mu,
+                             double delta, double h0, const double* hfac,
+                             double* det_out, double* h_out, double* n_out, double* q_out,
+                             int* valid_out)
+{
+    int C = 1 + dim;
+    int64_t skipped = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        double Ji[9], xi[3], vi[3], ui[3];
+        for (int e = 0; e < dim * dim; ++e) Ji[e] = J[e * N + i];
+        for (int a = 0; a < dim; ++a) {
+            xi[a] = x[a * N + i];
+            vi[a] = v[a * N + i];
+            ui[a] = ug[a * N + i];
+        }
+        double ri = r[i];
+        double n0i = n0 ? n0[i] : n0_scalar;
+        double det = orc_det(dim, Ji);
+        double adet = fabs(det);
+        double fac = hfac ? hfac[i] : 1.0;
+        int ok = all_finite(Ji, dim * dim) && all_finite(xi, dim) && all_finite(vi, dim) &&
+                 all_finite(ui, dim) && isfinite(ri) && isfinite(n0i) && isfinite(det) &&
+                 det != 0.0 && isfinite(fac) && fac > 0.0;
+        double h = h0 * adet;
+        h = h * fac;
+        double n = n0i / adet;
+        double phi[4] = {0, 0, 0, 0};
+        if (ok) orc_droplet_phi(dim, ri, vi, ui, rho_d, mu, delta, phi, 0, 0, 0);
+        if (ok && !(isfinite(h) && h > 0.0 && isfinite(n) && all_finite(phi, C))) ok = 0;
+        if (!ok) ++skipped;
+        if (det_out) det_out[i] = det;
+        h_out[i] = ok ? h : 0.0;
+        if (n_out) n_out[i] = ok ? n : 0.0;
+        for (int k = 0; k < C; ++k) q_out[k * N + i] = ok ? n * phi[k] : 0.0;
+        valid_out[i] = ok;
+    }
+    return skipped;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Truncation test (reading of the infinite-support kernel, see header).    */
+/* ------------------------------------------------------------------------ */
+static int pair_included(int dim, const double s[3], double cutoff, int f32_decision)
+{
+    if (f32_decision) {
+        float c = (float)cutoff;
+        float c2 = c * c;
+        float acc = (float)s[0];
+        acc = acc + (float)s[1];
+        if (dim == 3) acc = acc + (float)s[2];
+        return acc <= c2;
+    }
+    double acc = s[0] + s[1];
+    if (dim == 3) acc = acc + s[2];
+    return acc <= cutoff * cutoff;
+}
+
+/* Kernel of eq. "kernel": K_h(x, x_i) = (1/h) exp(-|x - x_i|^2 / (2 h^2)). */
+static double gauss_kernel(double r2, double h) { return (1.0 / h) * exp(-r2 / (2.0 * h * h)); }
+
+/* Evaluate the kernel between one cell centre and one trajectory.  Returns 1
+ * and the weight if the pair passes the truncation test. */
+static int cell_traj_weight(const orc_mesh* m, const int64_t idx[3], const double* x, int64_t N,
+                            int64_t i, double h, double cutoff, int f32_decision, double* K)
+{
+    double s[3] = {0, 0, 0};
+    double r2 = 0.0;
+    double inv_h = 1.0 / h;
+    for (int a = 0; a < m->dim; ++a) {
+        double d = axis_offset(m, a, cell_centre(m, a, idx[a]), x[a * N + i]);
+        double u = d * inv_h;
+        s[a] = u * u;
+        r2 += d * d;
+    }
+    if (!pair_included(m->dim, s, cutoff, f32_decision)) return 0;
+    *K = gauss_kernel(r2, h);
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Nadaraya-Watson projection, evaluated at listed cell centres by brute    */
+/* force over all trajectories (eq. kernel-estimator applied as in           */
+/* eq. coupling-terms-kernel; App. B steps 1c, 1d, 2a and 2c).               */
+/*   num_k(c) = sum_i K(x_c, x_i) q_ik,  den(c) = sum_i K(x_c, x_i)          */
+/*   S_k(c)   = -scale * cell_scale(c) * num_k(c) / den(c), 0 if den = 0     */
+/* Outputs are C x ncells (S), ncells (den), ncells (pair counts).           */
+/* ------------------------------------------------------------------------ */
+void orc_nw_cells(const orc_mesh* m, int64_t N, const double* x, const double* h,
+                  const double* q, const int* valid, double cutoff, int f32_decision,
+                  double scale, const double* cell_scale, int64_t ncells, const int64_t* cells,
+                  double* S, double* den_out, int64_t* pairs_out)
+{
+    int C = 1 + m->dim;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t j = 0; j < ncells; ++j) {
+        int64_t idx[3];
+        cell_coords(m, cells[j], idx);
+        double num[4] = {0, 0, 0, 0};
+        double den = 0.0;
+        int64_t np = 0;
+        for (int64_t i = 0; i < N; ++i) {
+            if (!valid[i]) continue;
+            double K;
+            if (!cell_traj_weight(m, idx, x, N, i, h[i], cutoff, f32_decision, &K)) continue;
+            den += K;
+            for (int k = 0; k < C; ++k) num[k] += K * q[k * N + i];
+            ++np;
+        }
+        double cs = cell_scale ? cell_scale[cells[j]] : 1.0;
+        for (int k = 0; k < C; ++k) S[k * ncells + j] = (den > 0.0) ? -scale * cs * (num[k] / den) : 0.0;
+        if (den_out) den_out[j] = den;
+        if (pairs_out) pairs_out[j] = np;
+    }
+}
+
+/* Home cell of a point: the cell containing it; periodic axes wrap, other  */
+/* axes clamp to the nearest cell.                                           */
+static int64_t home_cell(const orc_mesh* m, const double* x, int64_t N, int64_t i)
+{
+    int64_t lin = 0, stride = 1;
+    for (int a = 0; a < m->dim; ++a) {
+        double g = floor((x[a * N + i] - m->lo[a]) / cell_width(m, a));
+        int64_t k = (int64_t)g;
+        if (m->periodic[a]) {
+            k %= m->n[a];
+            if (k < 0) k += m->n[a];
+        } else {
+            if (k < 0) k = 0;
+            if (k >= m->n[a]) k = m->n[a] - 1;
+        }
+        lin += k * stride;
+        stride *= m->n[a];
+    }
+    return lin;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Normalised-kernel deposition (conservative companion of the estimator).  */
+/* Each trajectory carries the amount Q_i = q_i * V_seed * |det J_i|         */
+/* (= n0_i V_seed phi_i), spread over the cells it reaches with weights     */
+/* K_ci / Z_i, Z_i = sum_c K_ci; if Z_i = 0 the whole amount goes to its     */
+/* home cell.  S(c) = -scale * cell_scale(c) / V_c * sum_i Q_i K_ci / Z_i.   */
+/* Z is returned per trajectory (0 for skipped ones).                        */
+/* ------------------------------------------------------------------------ */
+void orc_deposit(const orc_mesh* m, int64_t N, const double* x, const double* h,
+                 const double* q, const double* det, const int* valid, double seed_volume,
+                 double cutoff, int f32_decision, double scale, const double* cell_scale,
+                 double* S /* C x M */, double* Z_out)
+{
+    int C = 1 + m->dim;
+    int64_t M = 1;
+    for (int a = 0; a < m->dim; ++a) M *= m->n[a];
+    double Vc = cell_volume(m);
+    double* Z = (double*)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < N; ++i) {
+        if (!valid[i]) continue;
+        double z = 0.0;
+        for (int64_t c = 0; c < M; ++c) {
+            int64_t idx[3];
+            double K;
+            cell_coords(m, c, idx);
+            if (cell_traj_weight(m, idx, x, N, i, h[i], cutoff, f32_decision, &K)) z += K;
+        }
+        Z[i] = z;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t c = 0; c < M; ++c) {
+        int64_t idx[3];
+        cell_coords(m, c, idx);
+        double acc[4] = {0, 0, 0, 0};
+        for (int64_t i = 0; i < N; ++i) {
+            if (!valid[i]) continue;
+            double w;
+            if (Z[i] > 0.0) {
+                double K;
+                if (!cell_traj_weight(m, idx, x, N, i, h[i], cutoff, f32_decision, &K)) continue;
+                w = K / Z[i];
+            } else {
+                if (home_cell(m, x, N, i) != c) continue;
+                w = 1.0;
+            }
+            double amount_scale = seed_volume * fabs(det[i]);
+            for (int k = 0; k < C; ++k) acc[k] += w * (q[k * N + i] * amount_scale);
+        }
+        double cs = cell_scale ? cell_scale[c] : 1.0;
+        for (int k = 0; k < C; ++k) S[k * M + c] = -scale * cs * acc[k] / Vc;
+    }
+    if (Z_out)
+        for (int64_t i = 0; i < N; ++i) Z_out[i] = Z[i];
+    free(Z);
+}
+
+/* ------------------------------------------------------------------------ */
+/* PSI-CELL box counting (eqs. vol-avg-discrete and coupling-terms-         */
+/* definition): S(c) = -(w / V_c) * cell_scale(c) * sum_{p in c} phi_p,     */
+/* with w the statistical weight of one computational particle (real        */
+/* droplets it stands for).  Cell of a particle: floor((x - lo)/dx) per      */
+/* axis; periodic axes wrap; on a closed axis x == hi goes to the last cell */
+/* and any other outside position is skipped.  Particles with non-finite    */
+/* inputs are skipped.  Returns the number of particles skipped.            */
+/* ------------------------------------------------------------------------ */
+int64_t orc_psicell_cell_of(const orc_mesh* m, const double* xp)
+{
+    int64_t lin = 0, stride = 1;
+    for (int a = 0; a < m->dim; ++a) {
+        if (!isfinite(xp[a])) return -1;
+        double g = floor((xp[a] - m->lo[a]) / cell_width(m, a));
+        if (!(fabs(g) < 9.0e15)) return -1;
+        int64_t k = (int64_t)g;
+        if (m->periodic[a]) {
+            k %= m->n[a];
+            if (k < 0) k += m->n[a];
+        } else if (k < 0 || k >= m->n[a]) {
+            if (k == m->n[a] && xp[a] == m->hi[a])
+                k = m->n[a] - 1;
+            else
+                return -1;
+        }
+        lin += k * stride;
+        stride *= m->n[a];
+    }
+    return lin;
+}
+
+int64_t orc_psicell(const orc_mesh* m, int64_t Np, const double* x, const double* v,
+                    const double* ug, const double* r, double rho_d, double mu, double delta,
+                    double weight, const double* cell_scale, double* S /* C x M */,
+                    int64_t* counts /* M, nullable */)
+{
+    int C = 1 + m->dim;
+    int64_t M = 1;
+    for (int a = 0; a < m->dim; ++a) M *= m->n[a];
+    double* acc = (double*)calloc((size_t)(C * M), sizeof(double));
+    if (counts) memset(counts, 0, sizeof(int64_t) * (size_t)M);
+    int64_t skipped = 0;
+    for (int64_t p = 0; p < Np; ++p) {
+        double xp[3], vp[3], up[3], phi[4];
+        for (int a = 0; a < m->dim; ++a) {
+            xp[a] = x[a * Np + p];
+            vp[a] = v[a * Np + p];
+            up[a] = ug[a * Np + p];
+        }
+        int64_t c = orc_psicell_cell_of(m, xp);
+        if (c < 0 || !all_finite(vp, m->dim) || !all_finite(up, m->dim) || !isfinite(r[p])) {
+            ++skipped;
+            continue;
+        }
+        orc_droplet_phi(m->dim, r[p], vp, up, rho_d, mu, delta, phi, 0, 0, 0);
+        if (!all_finite(phi, C)) {
+            ++skipped;
+            continue;
+        }
+        for (int k = 0; k < C; ++k) acc[k * M + c] += phi[k];
+        if (counts) counts[c] += 1;
+    }
+    double Vc = cell_volume(m);
+    for (int64_t c = 0; c < M; ++c) {
+        double cs = cell_scale ? cell_scale[c] : 1.0;
+        for (int k = 0; k < C; ++k) S[k * M + c] = -(weight / Vc) * cs * acc[k * M + c];
+    }
+    free(acc);
+    return skipped;
+}
+
+/* ------------------------------------------------------------------------ */
+/* App. A scaling factors.                                                   */
+/*   M_scal = N_ref tau_FLA / (N_FLA tau_ref)                   (eq. A.6)    */
+/*   V_scal = V_cell N_FLA / (A_inj v_inj tau_FLA)              (eq. A.12)   */
+/*   n_hat  = M_scal * V_scal                                   (eq. A.13)   */
+/* ------------------------------------------------------------------------ */
+void orc_app_a_scaling(double N_ref, double tau_ref, double N_fla, double tau_fla,
+                       double V_cell, double A_inj, double v_inj, double out[3])
+{
+    double M_scal = (N_ref * tau_fla) / (N_fla * tau_ref);
+    double V_fla = (A_inj * (v_inj * tau_fla)) / N_fla;
+    double V_scal = V_cell / V_fla;
+    out[0] = M_scal;
+    out[1] = V_scal;
+    out[2] = M_scal * V_scal;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -1,0 +1,392 @@
+"""Seeded synthetic inputs for the FLA source projection and its PSI-CELL comparator.
+
+This module is the only code shared by the oracle side and the GPU side.  It
+produces *inputs* (trajectory positions, deformation Jacobians, velocities,
+radii, particle clouds, meshes) and contains none of the projection's
+arithmetic: no determinant, number density, smoothing length, source term,
+kernel weight or average is evaluated here.
+
+Random numbers come from a counter-based hash (murmur3's 32-bit finaliser
+applied to (seed, stream, index)), written with int64 torch ops so that the
+same seed gives bit-identical uniforms on the CPU and on a GPU.  Normal
+variates use the Box-Muller transform; their last bits may differ between
+devices (libm differs), which is harmless because every test generates its
+inputs once and hands the same tensors to both sides.
+
+Flow maps (the paper's cylinder case is not available, so analytic maps stand
+in for the trajectory producer; each map is one step of length T = 1 s):
+
+* Taylor-Green, 2-D, amplitude a on the unit square (non-periodic).
+* ABC flow, 3-D, amplitude a, coefficients A, B, C, optional phases and
+  wavenumber, on the periodic unit cube.
+* multi-vortex: composition of two ABC maps (amplitudes 0.2 and 0.1,
+  wavenumbers 1 and 2, seeded phases); its Jacobian is the chain-rule product.
+
+For every map the droplet velocity is v = (x' - x)/T and the gas velocity is
+the same field shape evaluated at x' with the map's amplitude in m/s.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+TWO_PI = 2.0 * math.pi
+MASK32 = 0xFFFFFFFF
+
+# Physical constants used by every configuration: water droplets in air.
+RHO_D = 1000.0          # droplet density, kg/m^3
+MU_AIR = 1.81e-5        # gas dynamic viscosity, Pa s
+DELTA_EVAP = -1.0e-9    # rate of change of droplet surface area, m^2/s
+N0_DEFAULT = 1.0e10     # initial number density, m^-3
+
+
+# --------------------------------------------------------------------------
+# counter-based random numbers
+# --------------------------------------------------------------------------
+def _fmix32(h: torch.Tensor) -> torch.Tensor:
+    h = h & MASK32
+    h = h ^ (h >> 16)
+    h = (h * 0x85EBCA6B) & MASK32
+    h = h ^ (h >> 13)
+    h = (h * 0xC2B2AE35) & MASK32
+    h = h ^ (h >> 16)
+    return h
+
+
+def _hash32(seed: int, stream: int, idx: torch.Tensor) -> torch.Tensor:
+    lo = idx & MASK32
+    hi = (idx >> 32) & MASK32
+    key = (seed * 0x9E3779B1 + stream * 0x7F4A7C15 + 0x632BE59B) & MASK32
+    h = _fmix32(lo ^ key)
+    h = _fmix32(h ^ hi ^ ((key * 0x27D4EB2F) & MASK32))
+    return h
+
+
+def counter_uniform(seed: int, stream: int, n: int, device="cpu", offset: int = 0) -> torch.Tensor:
+    """n float64 uniforms in the open interval (0, 1), 53 random bits each."""
+    idx = torch.arange(offset, offset + n, dtype=torch.int64, device=device)
+    a = _hash32(seed, 2 * stream, idx) >> 5          # 27 bits
+    b = _hash32(seed, 2 * stream + 1, idx) >> 6      # 26 bits
+    m = (a << 26) | b                                # 53 bits
+    return (m.to(torch.float64) + 0.5) * (1.0 / 9007199254740992.0)
+
+
+def counter_normal(seed: int, stream: int, n: int, device="cpu", offset: int = 0) -> torch.Tensor:
+    u1 = counter_uniform(seed, 2 * stream + 1000, n, device, offset)
+    u2 = counter_uniform(seed, 2 * stream + 1001, n, device, offset)
+    return torch.sqrt(-2.0 * torch.log(u1)) * torch.cos(TWO_PI * u2)
+
+
+# --------------------------------------------------------------------------
+# meshes and seeding
+# --------------------------------------------------------------------------
+@dataclass
+class Mesh:
+    dim: int
+    n: Tuple[int, ...]
+    lo: Tuple[float, ...]
+    hi: Tuple[float, ...]
+    periodic: Tuple[bool, ...]
+
+    @property
+    def cells(self) -> int:
+        c = 1
+        for k in self.n:
+            c *= k
+        return c
+
+    @property
+    def cell_volume(self) -> float:
+        v = 1.0
+        for a in range(self.dim):
+            v *= (self.hi[a] - self.lo[a]) / self.n[a]
+        return v
+
+    @property
+    def domain_volume(self) -> float:
+        v = 1.0
+        for a in range(self.dim):
+            v *= self.hi[a] - self.lo[a]
+        return v
+
+
+def unit_mesh(dim: int, n: int, periodic: bool) -> Mesh:
+    return Mesh(dim, (n,) * dim, (0.0,) * dim, (1.0,) * dim, (periodic,) * dim)
+
+
+def lattice(dim: int, per_axis: int, device="cpu") -> torch.Tensor:
+    """Cell-centred lattice (i + 1/2)/L on the unit cube, shape (dim, L^dim);
+    axis 0 varies fastest."""
+    g = (torch.arange(per_axis, dtype=torch.float64, device=device) + 0.5) / per_axis
+    grids = torch.meshgrid(*([g] * dim), indexing="ij")  # grids[a][i0, i1, ...]
+    # flatten so that axis 0 is fastest: permute to (i_{d-1}, ..., i_0)
+    out = [grids[a].permute(*reversed(range(dim))).reshape(-1) for a in range(dim)]
+    return torch.stack(out)
+
+
+def random_points(dim: int, n: int, seed: int, device="cpu", offset: int = 0) -> torch.Tensor:
+    return torch.stack([counter_uniform(seed, 10 + a, n, device, offset) for a in range(dim)])
+
+
+# --------------------------------------------------------------------------
+# flow maps: each returns (x', J, ug) with J stored as (dim*dim, N), entry a*dim+b = dx'_a/dx0_b
+# --------------------------------------------------------------------------
+def taylor_green_map(x0: torch.Tensor, amp: float = 0.1):
+    X, Y = x0[0], x0[1]
+    k = TWO_PI
+    sx, cx = torch.sin(k * X), torch.cos(k * X)
+    sy, cy = torch.sin(k * Y), torch.cos(k * Y)
+    xp = torch.stack([X + amp * sx * cy, Y - amp * cx * sy])
+    ka = k * amp
+    J = torch.stack([1.0 + ka * cx * cy, -ka * sx * sy,
+                     ka * sx * sy, 1.0 - ka * cx * cy])
+    sxp, cxp = torch.sin(k * xp[0]), torch.cos(k * xp[0])
+    syp, cyp = torch.sin(k * xp[1]), torch.cos(k * xp[1])
+    ug = torch.stack([amp * sxp * cyp, -amp * cxp * syp])   # m/s
+    return xp, J, ug
+
+
+@dataclass
+class ABC:
+    amp: float = 0.2
+    A: float = 1.0
+    B: float = 1.0
+    C: float = 1.0
+    k: float = 1.0              # wavenumber (periods per unit length)
+    phase: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+
+    def field(self, x: torch.Tensor) -> torch.Tensor:
+        w = TWO_PI * self.k
+        px, py, pz = self.phase
+        X, Y, Z = x[0], x[1], x[2]
+        return torch.stack([
+            self.A * torch.sin(w * Z + pz) + self.C * torch.cos(w * Y + py),
+            self.B * torch.sin(w * X + px) + self.A * torch.cos(w * Z + pz),
+            self.C * torch.sin(w * Y + py) + self.B * torch.cos(w * X + px),
+        ])
+
+    def grad(self, x: torch.Tensor) -> torch.Tensor:
+        """d field_a / d x_b as (9, N)."""
+        w = TWO_PI * self.k
+        px, py, pz = self.phase
+        X, Y, Z = x[0], x[1], x[2]
+        z = torch.zeros_like(X)
+        return torch.stack([
+            z, -self.C * w * torch.sin(w * Y + py), self.A * w * torch.cos(w * Z + pz),
+            self.B * w * torch.cos(w * X + px), z, -self.A * w * torch.sin(w * Z + pz),
+            -self.B * w * torch.sin(w * X + px), self.C * w * torch.cos(w * Y + py), z,
+        ])
+
+    def apply(self, x0: torch.Tensor):
+        xp = x0 + self.amp * self.field(x0)
+        G = self.grad(x0) * self.amp
+        G[0] += 1.0
+        G[4] += 1.0
+        G[8] += 1.0
+        return xp, G
+
+
+def _matmul3(A: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+    out = []
+    for a in range(3):
+        for b in range(3):
+            out.append(A[3 * a] * B[b] + A[3 * a + 1] * B[3 + b] + A[3 * a + 2] * B[6 + b])
+    return torch.stack(out)
+
+
+def abc_map(x0: torch.Tensor, abc: ABC):
+    xp, J = abc.apply(x0)
+    ug = abc.amp * abc.field(xp)
+    return xp, J, ug
+
+
+def multi_vortex_map(x0: torch.Tensor, maps: Sequence[ABC]):
+    x = x0
+    J = None
+    for m in maps:
+        xn, G = m.apply(x)
+        J = G if J is None else _matmul3(G, J)
+        x = xn
+    ug = sum(m.amp * m.field(x) for m in maps)
+    return x, J, ug
+
+
+def multi_vortex_default(seed: int = 0) -> List[ABC]:
+    ph = counter_uniform(seed, 900, 6).tolist()
+    return [ABC(amp=0.2, k=1.0, phase=tuple(TWO_PI * p for p in ph[:3])),
+            ABC(amp=0.1, k=2.0, phase=tuple(TWO_PI * p for p in ph[3:]))]
+
+
+def wrap_unit(x: torch.Tensor) -> torch.Tensor:
+    return x - torch.floor(x)
+
+
+# --------------------------------------------------------------------------
+# trajectory sets
+# --------------------------------------------------------------------------
+@dataclass
+class Trajectories:
+    """Structure-of-arrays trajectory record (all float64 on `device`).
+
+    x: (dim, N) positions; J: (dim*dim, N) deformation Jacobian, entry
+    a*dim+b; v, ug: (dim, N) droplet and gas velocity; r: (N,) radius;
+    n0: scalar initial number density (or (N,) tensor)."""
+    x: torch.Tensor
+    J: torch.Tensor
+    v: torch.Tensor
+    ug: torch.Tensor
+    r: torch.Tensor
+    n0: object = N0_DEFAULT
+    seed_volume: float = 0.0
+
+    @property
+    def count(self) -> int:
+        return int(self.r.shape[0])
+
+    @property
+    def dim(self) -> int:
+        return int(self.x.shape[0])
+
+    def to(self, device) -> "Trajectories":
+        n0 = self.n0.to(device) if isinstance(self.n0, torch.Tensor) else self.n0
+        return Trajectories(self.x.to(device), self.J.to(device), self.v.to(device),
+                            self.ug.to(device), self.r.to(device), n0, self.seed_volume)
+
+    def subset(self, idx: torch.Tensor) -> "Trajectories":
+        n0 = self.n0[idx] if isinstance(self.n0, torch.Tensor) else self.n0
+        return Trajectories(self.x[:, idx], self.J[:, idx], self.v[:, idx],
+                            self.ug[:, idx], self.r[idx], n0, self.seed_volume)
+
+
+def radius_uniform(n, seed, lo_um, hi_um, device="cpu", stream=50, offset=0):
+    u = counter_uniform(seed, stream, n, device, offset)
+    return (lo_um + (hi_um - lo_um) * u) * 1e-6
+
+
+def radius_lognormal(n, seed, median_um=10.0, sigma=0.3, device="cpu", stream=51, offset=0):
+    z = counter_normal(seed, stream, n, device, offset)
+    return median_um * 1e-6 * torch.exp(sigma * z)
+
+
+def from_map(x0: torch.Tensor, kind: str, params=None, wrap: bool = False):
+    if kind == "tg":
+        xp, J, ug = taylor_green_map(x0, **(params or {}))
+    elif kind == "abc":
+        xp, J, ug = abc_map(x0, params if params is not None else ABC())
+    elif kind == "multi":
+        xp, J, ug = multi_vortex_map(x0, params if params is not None else multi_vortex_default())
+    else:
+        raise ValueError(kind)
+    v = xp - x0                         # one map step of T = 1 s
+    if wrap:
+        xp = wrap_unit(xp)
+    return xp, J, v, ug
+
+
+# --------------------------------------------------------------------------
+# the benchmark configurations (sizes as stated by the workload definitions)
+# --------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    traj: Trajectories
+    h0: float
+    precision: str                  # "f64" or "f32"
+    rho_d: float = RHO_D
+    mu: float = MU_AIR
+    delta: float = DELTA_EVAP
+    cutoff: float = 4.0
+    extra: Dict = field(default_factory=dict)
+
+
+def c1_taylor_green(per_axis: int = 64, mesh_n: int = 64, seed: int = 0, device="cpu",
+                    delta: float = DELTA_EVAP) -> Workload:
+    """2-D FP64: unit square, Taylor-Green map amplitude 0.1, lattice seeding,
+    r ~ U[5, 20] um, n0 = 1e10 m^-3, h0 = lattice pitch."""
+    x0 = lattice(2, per_axis, device)
+    xp, J, v, ug = from_map(x0, "tg", {"amp": 0.1})
+    r = radius_uniform(x0.shape[1], seed, 5.0, 20.0, device)
+    tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / per_axis ** 2)
+    return Workload("c1_tg2d_f64", unit_mesh(2, mesh_n, False), tr, 1.0 / per_axis, "f64", delta=delta)
+
+
+def c1_cloud(n_particles: int = 400_000, seed: int = 0, device="cpu"):
+    """PSI-CELL comparator cloud for the 2-D case: X0 ~ U[0,1]^2, same map and radius law."""
+    x0 = random_points(2, n_particles, seed, device)
+    xp, J, v, ug = from_map(x0, "tg", {"amp": 0.1})
+    r = radius_uniform(n_particles, seed, 5.0, 20.0, device, stream=60)
+    return Trajectories(xp, J, v, ug, r, 1.0)
+
+
+def c2_abc(per_axis: int = 128, mesh_n: int = 128, seed: int = 0, device="cpu",
+           amp: float = 0.2) -> Workload:
+    """3-D: periodic unit cube, ABC map amplitude 0.2 (A=B=C=1), lattice seeding,
+    r ~ lognormal(ln 10 um, 0.3), h0 = lattice pitch, FP32 kernel evaluation."""
+    x0 = lattice(3, per_axis, device)
+    xp, J, v, ug = from_map(x0, "abc", ABC(amp=amp), wrap=True)
+    r = radius_lognormal(x0.shape[1], seed, device=device)
+    tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / per_axis ** 3)
+    return Workload("c2_abc3d_f32", unit_mesh(3, mesh_n, True), tr, 1.0 / per_axis, "f32")
+
+
+def abc_cloud(n_particles: int, seed: int = 0, device="cpu", abc: Optional[ABC] = None,
+              offset: int = 0, radius="lognormal"):
+    x0 = random_points(3, n_particles, seed, device, offset)
+    xp, J, v, ug = from_map(x0, "abc", abc if abc is not None else ABC(), wrap=True)
+    if radius == "lognormal":
+        r = radius_lognormal(n_particles, seed, device=device, stream=61, offset=offset)
+    else:
+        r = radius_uniform(n_particles, seed, 5.0, 20.0, device, stream=61, offset=offset)
+    return Trajectories(xp, J, v, ug, r, 1.0)
+
+
+def c5_multi_vortex(per_axis: int = 320, mesh_n: int = 256, seed: int = 0, device="cpu") -> Workload:
+    x0 = lattice(3, per_axis, device)
+    xp, J, v, ug = from_map(x0, "multi", multi_vortex_default(seed), wrap=True)
+    r = radius_lognormal(x0.shape[1], seed, device=device)
+    tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / per_axis ** 3)
+    return Workload("c5_multivortex3d_f32", unit_mesh(3, mesh_n, True), tr, 1.0 / per_axis, "f32")
+
+
+def c3_snapshot(s: int, device="cpu") -> Workload:
+    """One snapshot of the uneven batch: edge L = round(32*4^u), N = round(1e4*200^u'),
+    random seeding, ABC amplitude U[0.05, 0.2] with random phases, h0 = N^(-1/3)."""
+    u = counter_uniform(1000 + s, 0, 6)
+    L = int(round(32 * 4 ** float(u[0])))
+    N = int(round(1e4 * 200 ** float(u[1])))
+    amp = 0.05 + 0.15 * float(u[2])
+    abc = ABC(amp=amp, phase=(TWO_PI * float(u[3]), TWO_PI * float(u[4]), TWO_PI * float(u[5])))
+    x0 = random_points(3, N, 1000 + s, device)
+    xp, J, v, ug = from_map(x0, "abc", abc, wrap=True)
+    r = radius_lognormal(N, 1000 + s, device=device)
+    tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / N)
+    return Workload(f"c3_snap{s}", unit_mesh(3, L, True), tr, N ** (-1.0 / 3.0), "f32")
+
+
+def c4_snapshot(s: int, n_traj: int = 200_000, mesh_n: int = 64, device="cpu") -> Tuple[Workload, ABC]:
+    """Training snapshot: random seeding, ABC with A,B,C ~ U[0.5,1.5], amplitude
+    U[0.05,0.25], random phases; h0 = N^(-1/3)."""
+    u = counter_uniform(2000 + s, 0, 7)
+    abc = ABC(amp=0.05 + 0.2 * float(u[0]), A=0.5 + float(u[1]), B=0.5 + float(u[2]),
+              C=0.5 + float(u[3]),
+              phase=(TWO_PI * float(u[4]), TWO_PI * float(u[5]), TWO_PI * float(u[6])))
+    x0 = random_points(3, n_traj, 2000 + s, device)
+    xp, J, v, ug = from_map(x0, "abc", abc, wrap=True)
+    r = radius_lognormal(n_traj, 2000 + s, device=device)
+    tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / n_traj)
+    return Workload(f"c4_snap{s}", unit_mesh(3, mesh_n, True), tr, n_traj ** (-1.0 / 3.0), "f32"), abc
+
+
+def small_random_3d(n_traj: int, mesh_n: int, seed: int, device="cpu", periodic=True,
+                    amp: float = 0.2, h0: Optional[float] = None) -> Workload:
+    """Small 3-D case for parity tests: random seeding through an ABC map."""
+    x0 = random_points(3, n_traj, seed, device)
+    xp, J, v, ug = from_map(x0, "abc", ABC(amp=amp), wrap=periodic)
+    r = radius_lognormal(n_traj, seed, device=device)
+    tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / n_traj)
+    return Workload(f"rand3d_{n_traj}_{mesh_n}", unit_mesh(3, mesh_n, periodic), tr,
+                    h0 if h0 is not None else n_traj ** (-1.0 / 3.0), "f32")
