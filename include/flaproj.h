@@ -1,0 +1,203 @@
+/*
+ * flaproj.h - C ABI of the MI355X (gfx950) FLA source-projection library.
+ *
+ * The library projects the mass and momentum exchange terms carried by
+ * fully-Lagrangian-approach (FLA) droplet trajectories onto a uniform
+ * Cartesian Eulerian mesh with the Nadaraya-Watson kernel estimator of
+ * Stafford & Rybdylova (arXiv 2512.20829), and accumulates the PSI-CELL
+ * box-counting source terms of a particle cloud as the comparison path.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers inside the argument structs are DEVICE pointers (HIP device
+ *    memory of the context's device) unless marked "host".  The structs
+ *    themselves are host memory and are read during the call only.
+ *  - All work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *    and the call returns without waiting, except where stated.
+ *  - The caller owns every input and output buffer; the library never frees
+ *    or retains them.  The context owns a grow-only device workspace.
+ *  - Invalid arguments are detected on the host before anything is enqueued:
+ *    the call returns FLA_ERR_INVALID_ARG, writes nothing and records a
+ *    message readable with fla_last_error.  No C++ exception crosses the ABI.
+ *  - Data-dependent conditions are not errors: trajectories with det J = 0 or
+ *    any non-finite input, and PSI-CELL particles outside a closed box, are
+ *    skipped and counted (fla_get_stats).
+ *  - Results are deterministic: the same inputs give bitwise-identical
+ *    outputs (no floating-point atomics; fixed summation orders).
+ *  - Mesh cells are indexed i0 + n0*(i1 + n1*i2); a field is a plane of
+ *    M = n0*n1(*n2) values in that order.
+ */
+#ifndef FLAPROJ_H
+#define FLAPROJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FLA_OK = 0,
+    FLA_ERR_INVALID_ARG = 1,
+    FLA_ERR_OUT_OF_MEMORY = 2,
+    FLA_ERR_DEVICE = 3,
+    FLA_ERR_UNSUPPORTED = 4
+} fla_status;
+
+/* Arithmetic of a call.  FLA_F32: velocities, radii and outputs are binary32
+ * and kernel weights are evaluated in binary32 with compensated binary32
+ * sums; det J, number density, smoothing length and cell offsets stay in
+ * binary64.  FLA_F64: everything in binary64. */
+typedef enum { FLA_F32 = 0, FLA_F64 = 1 } fla_precision;
+
+/* FLA_NW: the Nadaraya-Watson estimator of the paper (eqs. kernel-estimator,
+ * kernel, smoothing-length and coupling-terms-kernel).  FLA_DEPOSIT: the
+ * normalised-kernel deposition that conserves the carried totals exactly:
+ * trajectory i carries Q_i = n0_i V_seed phi_i, spread over the cells it
+ * reaches with weights K_ci / Z_i, Z_i = sum_c K_ci, and the cell value is
+ * divided by the cell volume; if no cell centre is within reach (Z_i = 0)
+ * the whole of Q_i goes to the cell containing x_i. */
+typedef enum { FLA_NW = 0, FLA_DEPOSIT = 1 } fla_mode;
+
+typedef struct fla_ctx fla_ctx;
+
+/* Uniform Cartesian mesh on [lo, hi) with n[a] cells along axis a; cell
+ * centres at lo + (i + 1/2)(hi - lo)/n.  Periodic axes use minimum-image
+ * offsets.  cell_scale (nullable, device, M values in the call's precision)
+ * multiplies every source term of a cell: the per-cell factor n_hat of
+ * App. A, eqs. (A.13)-(A.14), on a mesh where it varies. */
+typedef struct {
+    int32_t dim;            /* 2 or 3 */
+    int32_t n[3];           /* cells per axis, >= 1; n[2] ignored if dim == 2 */
+    double lo[3];
+    double hi[3];           /* hi[a] > lo[a] */
+    int32_t periodic[3];    /* nonzero = periodic axis */
+    const void* cell_scale; /* nullable */
+} fla_mesh;
+
+/* Trajectory (or particle) records, structure of arrays, count values each.
+ *   x[a]   binary64 positions (eq. Stokes-drag trajectory x_d)
+ *   J      binary64 deformation Jacobian dx_d/dx_0 (eq. for J), dim*dim planes:
+ *          entry (a, b) of trajectory i at J[(a*dim + b)*count + i]
+ *   v[a]   droplet velocity, ug[a] gas velocity at the droplet, r radius:
+ *          binary32 if prec == FLA_F32, binary64 if FLA_F64
+ *   n0     nullable per-trajectory initial number density n_d(x_0, t_0)
+ *          (eq. FLA-COM); if NULL, n0_scalar is used for all
+ *   seed_volume  volume represented by one seed, V_seed (FLA_DEPOSIT only)
+ * For psicell_accumulate, J, n0 and seed_volume are ignored. */
+typedef struct {
+    int64_t count;          /* >= 0, < 2^31 */
+    int32_t prec;           /* fla_precision */
+    int32_t reserved;
+    const double* x[3];
+    const double* J;
+    const void* v[3];
+    const void* ug[3];
+    const void* r;
+    const double* n0;
+    double n0_scalar;
+    double seed_volume;
+} fla_trajectories;
+
+/* Physical and kernel parameters.
+ *   rho_d   droplet density; mu gas dynamic viscosity; delta the rate of
+ *           change of droplet surface area (eqs. evap-model and 5, SI units):
+ *           m = 4/3 pi rho_d r^3, tau = 2 rho_d r^2/(9 mu),
+ *           F = m (ug - v)/tau, mdot = 4 pi rho_d r^2 delta/(2 r)
+ *   h0      initial smoothing length (eq. smoothing-length), > 0
+ *   cutoff  truncation of the Gaussian kernel in bandwidths, > 0: a pair is
+ *           included iff sum_a (d_a/h)^2 <= cutoff^2 (per-axis terms rounded
+ *           to binary32 and summed in binary32 for FLA_F32)
+ *   scale   global multiplier of every source term (n_hat of App. A when
+ *           it is uniform; 1 when n0 is already physical)
+ *   mode    fla_mode
+ *   count_pairs  nonzero: also count included (trajectory, cell) pairs into
+ *           the statistics (costs extra ALU work)
+ *   h_factor nullable device binary32 array of count positive factors that
+ *           multiply h_i (the learned bandwidth correction); NULL = 1 */
+typedef struct {
+    double rho_d;
+    double mu;
+    double delta;
+    double h0;
+    double cutoff;
+    double scale;
+    int32_t mode;
+    int32_t count_pairs;
+    const float* h_factor;
+} fla_params;
+
+/* Output fields: device planes of M values in the call's precision.
+ * S_mass = S_Mass, S_mom[a] = component a of S_Mom (eq. coupling-terms-
+ * kernel, with the minus sign of eq. coupling-terms-averaged); den
+ * (nullable) receives the estimator denominator sum_i K(x_c, x_i)
+ * (FLA_NW) or, for psicell_accumulate, the particle count as a real. */
+typedef struct {
+    void* S_mass;
+    void* S_mom[3];
+    void* den;
+} fla_fields;
+
+typedef struct {
+    int64_t trajectories;     /* records seen by the last call */
+    int64_t skipped;          /* det J == 0 or non-finite input */
+    int64_t no_support;       /* valid, but no cell of a closed box within reach */
+    int64_t pairs;            /* included pairs (only if count_pairs was set) */
+    int64_t outside;          /* PSI-CELL particles outside a closed box */
+    int64_t zero_support;     /* FLA_DEPOSIT: trajectories with Z_i = 0 */
+    int64_t max_class;        /* largest neighbourhood class used by the gather */
+    int64_t reserved;
+} fla_stats;
+
+/* Create a context on HIP device `device` (host pointer out).  Errors:
+ * INVALID_ARG for a bad device or NULL out, DEVICE if HIP fails. */
+fla_status fla_ctx_create(fla_ctx** out, int device);
+
+/* Destroy a context; waits for the device first.  NULL is accepted. */
+fla_status fla_ctx_destroy(fla_ctx* ctx);
+
+/* FLA source projection (paper: eqs. FLA-COM, smoothing-length, kernel,
+ * kernel-estimator, coupling-terms-kernel; App. B steps 1c-1d and 2a-2c).
+ * For every cell centre x_c, over trajectories i that are not skipped:
+ *   detJ_i = det J_i (binary64), n_i = n0_i/|detJ_i|, h_i = h0 |detJ_i| f_i,
+ *   q_i = n_i [mdot_i, F_i + mdot_i v_i],
+ *   K_ci = (1/h_i) exp(-|x_c - x_i|^2 / (2 h_i^2)) if included, else 0,
+ *   S_k(c) = -scale * cell_scale(c) * sum_i K_ci q_ik / sum_i K_ci
+ *            (0 where the denominator is 0)                  [FLA_NW]
+ *   S_k(c) = -scale * cell_scale(c) / V_c * sum_i Q_ik K_ci / Z_i
+ *                                                            [FLA_DEPOSIT]
+ * Output channels: S_mass and S_mom[0..dim-1] (all required), den optional.
+ * count == 0 writes zeros.  Errors: INVALID_ARG (checked on the host),
+ * OUT_OF_MEMORY (workspace), DEVICE (launch failure). */
+fla_status fla_project_sources(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                               const fla_params* params, const fla_fields* out, void* stream);
+
+/* PSI-CELL box counting (paper: eqs. vol-avg-discrete and coupling-terms-
+ * definition): every particle p with finite inputs is assigned the cell
+ * floor((x_p - lo)/dx) per axis (periodic axes wrap; on a closed axis
+ * x == hi goes to the last cell and any other outside position is skipped
+ * and counted) and
+ *   S_k(c) = -(particle_weight / V_c) * cell_scale(c) * sum_{p in c} phi_pk,
+ *   phi_p = [mdot_p, F_p + mdot_p v_p]   (n = 1 per droplet),
+ * particle_weight being the number of real droplets one computational
+ * particle stands for.  Sums are exact integer sums of per-particle values
+ * quantised to 2^-e (e chosen per channel from the largest |phi| so that no
+ * sum can overflow), hence order-independent.  den, if given, receives the
+ * particle count per cell.  Errors as fla_project_sources. */
+fla_status psicell_accumulate(fla_ctx* ctx, const fla_mesh* mesh,
+                              const fla_trajectories* particles, double particle_weight,
+                              const fla_params* params, const fla_fields* out, void* stream);
+
+/* Statistics of the last call on ctx.  Synchronises the device, then copies
+ * into *out (host).  Errors: INVALID_ARG for NULL, DEVICE. */
+fla_status fla_get_stats(fla_ctx* ctx, fla_stats* out);
+
+/* Message of the last error on ctx (host string owned by ctx, valid until
+ * the next call on ctx); "" if the last call succeeded.  NULL ctx returns
+ * the message of the last failed fla_ctx_create. */
+const char* fla_last_error(const fla_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLAPROJ_H */

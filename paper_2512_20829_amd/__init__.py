@@ -1,0 +1,258 @@
+"""Python binding of libflaproj.so, the gfx950 FLA source-projection library.
+
+Argument marshalling only: torch tensors (device memory) are turned into the
+C structs of ``include/flaproj.h`` and every step runs in the library's HIP
+kernels.  There is no CPU fallback; importing this module fails if the
+shared library has not been built (``python paper_2512_20829_amd/build.py``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libflaproj.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python {os.path.join(HERE, 'build.py')}`")
+
+_lib = C.CDLL(LIB_PATH)
+
+FLA_OK, FLA_ERR_INVALID_ARG, FLA_ERR_OUT_OF_MEMORY, FLA_ERR_DEVICE, FLA_ERR_UNSUPPORTED = range(5)
+FLA_F32, FLA_F64 = 0, 1
+FLA_NW, FLA_DEPOSIT = 0, 1
+STATUS_NAMES = {0: "FLA_OK", 1: "FLA_ERR_INVALID_ARG", 2: "FLA_ERR_OUT_OF_MEMORY", 3: "FLA_ERR_DEVICE",
+                4: "FLA_ERR_UNSUPPORTED"}
+
+
+class fla_mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("periodic", C.c_int32 * 3), ("cell_scale", C.c_void_p)]
+
+
+class fla_trajectories(C.Structure):
+    _fields_ = [("count", C.c_int64), ("prec", C.c_int32), ("reserved", C.c_int32),
+                ("x", C.c_void_p * 3), ("J", C.c_void_p), ("v", C.c_void_p * 3), ("ug", C.c_void_p * 3),
+                ("r", C.c_void_p), ("n0", C.c_void_p), ("n0_scalar", C.c_double),
+                ("seed_volume", C.c_double)]
+
+
+class fla_params(C.Structure):
+    _fields_ = [("rho_d", C.c_double), ("mu", C.c_double), ("delta", C.c_double), ("h0", C.c_double),
+                ("cutoff", C.c_double), ("scale", C.c_double), ("mode", C.c_int32),
+                ("count_pairs", C.c_int32), ("h_factor", C.c_void_p)]
+
+
+class fla_fields(C.Structure):
+    _fields_ = [("S_mass", C.c_void_p), ("S_mom", C.c_void_p * 3), ("den", C.c_void_p)]
+
+
+class fla_stats(C.Structure):
+    _fields_ = [("trajectories", C.c_int64), ("skipped", C.c_int64), ("no_support", C.c_int64),
+                ("pairs", C.c_int64), ("outside", C.c_int64), ("zero_support", C.c_int64),
+                ("max_class", C.c_int64), ("reserved", C.c_int64)]
+
+
+_vp = C.c_void_p
+_lib.fla_ctx_create.restype = C.c_int
+_lib.fla_ctx_create.argtypes = [C.POINTER(_vp), C.c_int]
+_lib.fla_ctx_destroy.restype = C.c_int
+_lib.fla_ctx_destroy.argtypes = [_vp]
+_lib.fla_project_sources.restype = C.c_int
+_lib.fla_project_sources.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories),
+                                     C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
+_lib.psicell_accumulate.restype = C.c_int
+_lib.psicell_accumulate.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories), C.c_double,
+                                    C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
+_lib.fla_get_stats.restype = C.c_int
+_lib.fla_get_stats.argtypes = [_vp, C.POINTER(fla_stats)]
+_lib.fla_last_error.restype = C.c_char_p
+_lib.fla_last_error.argtypes = [_vp]
+
+
+def lib() -> C.CDLL:
+    return _lib
+
+
+class FlaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+@dataclass
+class Params:
+    rho_d: float
+    mu: float
+    delta: float
+    h0: float
+    cutoff: float = 4.0
+    scale: float = 1.0
+    mode: int = FLA_NW
+    count_pairs: bool = False
+    h_factor: object = None      # optional float32 device tensor (N,)
+
+    def to_c(self) -> fla_params:
+        p = fla_params()
+        p.rho_d, p.mu, p.delta, p.h0, p.cutoff, p.scale = (self.rho_d, self.mu, self.delta, self.h0,
+                                                            self.cutoff, self.scale)
+        p.mode = int(self.mode)
+        p.count_pairs = int(bool(self.count_pairs))
+        p.h_factor = _ptr(self.h_factor)
+        return p
+
+
+def make_mesh(dim: int, n: Sequence[int], lo: Sequence[float], hi: Sequence[float],
+              periodic: Sequence[bool], cell_scale=None) -> fla_mesh:
+    m = fla_mesh()
+    m.dim = dim
+    for a in range(3):
+        m.n[a] = int(n[a]) if a < dim else 1
+        m.lo[a] = float(lo[a]) if a < dim else 0.0
+        m.hi[a] = float(hi[a]) if a < dim else 1.0
+        m.periodic[a] = int(bool(periodic[a])) if a < dim else 0
+    m.cell_scale = _ptr(cell_scale)
+    return m
+
+
+def mesh_of(obj, cell_scale=None) -> fla_mesh:
+    """From an object with dim, n, lo, hi, periodic attributes."""
+    return make_mesh(obj.dim, obj.n, obj.lo, obj.hi, obj.periodic, cell_scale)
+
+
+def make_trajectories(x, J, v, ug, r, n0=1.0, seed_volume: float = 0.0) -> tuple:
+    """Build the C struct from device tensors.  x: (dim, N) float64, J: (dim*dim, N)
+    float64, v, ug: (dim, N) and r: (N,) float32 or float64 (that dtype sets the
+    call's precision), n0: float or (N,) float64 tensor.  Returns (struct, keepalive)."""
+    import torch
+    dim, N = int(x.shape[0]), int(x.shape[1])
+    prec = FLA_F64 if v.dtype == torch.float64 else FLA_F32
+    want = torch.float64 if prec == FLA_F64 else torch.float32
+    for name, t in (("v", v), ("ug", ug), ("r", r)):
+        if t.dtype != want:
+            raise ValueError(f"{name} must be {want}")
+    if x.dtype != torch.float64 or (J is not None and J.dtype != torch.float64):
+        raise ValueError("x and J must be float64")
+    keep = []
+    tr = fla_trajectories()
+    tr.count = N
+    tr.prec = prec
+    rows = lambda t: [t[a].contiguous() for a in range(dim)]
+    xs, vs, us = rows(x), rows(v), rows(ug)
+    keep += xs + vs + us
+    for a in range(dim):
+        tr.x[a] = xs[a].data_ptr()
+        tr.v[a] = vs[a].data_ptr()
+        tr.ug[a] = us[a].data_ptr()
+    if J is not None:
+        Jc = J.contiguous()
+        keep.append(Jc)
+        tr.J = Jc.data_ptr()
+    rc = r.contiguous()
+    keep.append(rc)
+    tr.r = rc.data_ptr()
+    if isinstance(n0, (int, float)):
+        tr.n0 = None
+        tr.n0_scalar = float(n0)
+    else:
+        n0c = n0.to(torch.float64).contiguous()
+        keep.append(n0c)
+        tr.n0 = n0c.data_ptr()
+        tr.n0_scalar = 0.0
+    tr.seed_volume = float(seed_volume)
+    return tr, keep
+
+
+def make_fields(S_mass, S_mom: Sequence, den=None) -> fla_fields:
+    f = fla_fields()
+    f.S_mass = _ptr(S_mass)
+    for a, t in enumerate(S_mom):
+        f.S_mom[a] = _ptr(t)
+    f.den = _ptr(den)
+    return f
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Context:
+    """Owns one fla_ctx (workspace and statistics) on a device."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        st = _lib.fla_ctx_create(C.byref(h), int(device))
+        if st != FLA_OK:
+            raise FlaError(st, _lib.fla_last_error(None).decode())
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fla_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def last_error(self) -> str:
+        return _lib.fla_last_error(self._h).decode()
+
+    def _check(self, st: int):
+        if st != FLA_OK:
+            raise FlaError(st, self.last_error())
+
+    # -- raw struct entry points ---------------------------------------------------------
+    def project_sources_raw(self, mesh: fla_mesh, traj: fla_trajectories, params: fla_params,
+                            out: fla_fields, stream=None) -> int:
+        return _lib.fla_project_sources(self._h, C.byref(mesh), C.byref(traj), C.byref(params),
+                                        C.byref(out), _stream_handle(stream))
+
+    def psicell_raw(self, mesh, particles, weight, params, out, stream=None) -> int:
+        return _lib.psicell_accumulate(self._h, C.byref(mesh), C.byref(particles), float(weight),
+                                       C.byref(params), C.byref(out), _stream_handle(stream))
+
+    # -- tensor-level helpers ------------------------------------------------------------
+    def project_sources(self, mesh: fla_mesh, traj: fla_trajectories, params: Params, S_mass, S_mom,
+                        den=None, stream=None):
+        st = self.project_sources_raw(mesh, traj, params.to_c(), make_fields(S_mass, S_mom, den), stream)
+        self._check(st)
+
+    def psicell_accumulate(self, mesh: fla_mesh, particles: fla_trajectories, weight: float,
+                           params: Params, S_mass, S_mom, den=None, stream=None):
+        st = self.psicell_raw(mesh, particles, weight, params.to_c(), make_fields(S_mass, S_mom, den), stream)
+        self._check(st)
+
+    def stats(self) -> dict:
+        s = fla_stats()
+        self._check(_lib.fla_get_stats(self._h, C.byref(s)))
+        return {k: int(getattr(s, k)) for k, _ in fla_stats._fields_}
+
+
+def alloc_fields(M: int, dim: int, dtype, device="cuda", den: bool = True):
+    """Allocate output planes: returns (S_mass, [S_mom...], den or None)."""
+    import torch
+    S_mass = torch.empty(M, dtype=dtype, device=device)
+    S_mom = [torch.empty(M, dtype=dtype, device=device) for _ in range(dim)]
+    d = torch.empty(M, dtype=dtype, device=device) if den else None
+    return S_mass, S_mom, d

@@ -1,0 +1,464 @@
+// Host runtime and C ABI of the FLA projection library: argument validation,
+// the grow-only workspace, and the launch sequence of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "flaproj.h"
+#include "internal.hpp"
+#include "kernels.hpp"
+
+using namespace flp;
+
+struct fla_ctx {
+    int device = 0;
+    std::string err;
+    void* ws = nullptr;
+    size_t ws_size = 0;
+    unsigned long long* stats = nullptr;   // ST_N counters
+};
+
+static thread_local std::string g_create_error;
+
+namespace {
+
+struct Fail {
+    fla_status st;
+};
+
+#define FLA_EXPORT __attribute__((visibility("default")))
+
+#define CHECK_ARG(cond, msg)                    \
+    do {                                        \
+        if (!(cond)) {                          \
+            ctx->err = std::string(msg);        \
+            return FLA_ERR_INVALID_ARG;         \
+        }                                       \
+    } while (0)
+
+#define HIP_OK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess) {                                                            \
+            ctx->err = std::string("HIP error in ") + #expr + ": " + hipGetErrorString(_e); \
+            return _e == hipErrorOutOfMemory ? FLA_ERR_OUT_OF_MEMORY : FLA_ERR_DEVICE;      \
+        }                                                                                  \
+    } while (0)
+
+// Carves aligned sub-buffers out of one device allocation.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <typename T> T* take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+fla_status ensure_ws(fla_ctx* ctx, size_t need)
+{
+    if (need <= ctx->ws_size) return FLA_OK;
+    if (ctx->ws) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            ctx->err = std::string("hipDeviceSynchronize: ") + hipGetErrorString(e);
+            return FLA_ERR_DEVICE;
+        }
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_size = 0;
+    }
+    size_t sz = need + need / 4 + (1 << 20);
+    hipError_t e = hipMalloc(&ctx->ws, sz);
+    if (e != hipSuccess) {
+        ctx->ws = nullptr;
+        ctx->err = "workspace allocation of " + std::to_string(sz) + " bytes failed: " + hipGetErrorString(e);
+        return FLA_ERR_OUT_OF_MEMORY;
+    }
+    ctx->ws_size = sz;
+    return FLA_OK;
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+fla_status check_mesh(fla_ctx* ctx, const fla_mesh* mesh, MeshDev* md, int te)
+{
+    CHECK_ARG(mesh != nullptr, "mesh is NULL");
+    CHECK_ARG(mesh->dim == 2 || mesh->dim == 3, "mesh.dim must be 2 or 3");
+    MeshDev m{};
+    m.dim = mesh->dim;
+    m.te = te;
+    int64_t M = 1, NT = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a < mesh->dim) {
+            CHECK_ARG(mesh->n[a] >= 1 && mesh->n[a] <= (1 << 24), "mesh.n out of range");
+            CHECK_ARG(is_fin(mesh->lo[a]) && is_fin(mesh->hi[a]) && mesh->hi[a] > mesh->lo[a],
+                      "mesh.lo/hi must be finite with hi > lo");
+            m.n[a] = mesh->n[a];
+            m.periodic[a] = mesh->periodic[a] ? 1 : 0;
+            m.lo[a] = mesh->lo[a];
+            m.hi[a] = mesh->hi[a];
+            m.L[a] = mesh->hi[a] - mesh->lo[a];
+            m.w[a] = m.L[a] / (double)mesh->n[a];
+            CHECK_ARG(m.w[a] > 0.0 && is_fin(m.w[a]), "mesh cell width is not a positive finite number");
+            m.nt[a] = (mesh->n[a] + te - 1) / te;
+        } else {
+            m.n[a] = 1;
+            m.periodic[a] = 0;
+            m.lo[a] = 0.0;
+            m.hi[a] = 1.0;
+            m.L[a] = 1.0;
+            m.w[a] = 1.0;
+            m.nt[a] = 1;
+        }
+        M *= m.n[a];
+        NT *= m.nt[a];
+    }
+    CHECK_ARG(M <= (int64_t(1) << 31), "mesh has more than 2^31 cells");
+    CHECK_ARG(NT * kClasses + 1 < (int64_t(1) << 31), "mesh has too many tiles");
+    m.M = M;
+    m.ntiles = (int)NT;
+    m.vol = 1.0;
+    for (int a = 0; a < mesh->dim; ++a) m.vol *= m.w[a];
+    *md = m;
+    return FLA_OK;
+}
+
+fla_status check_traj(fla_ctx* ctx, const fla_trajectories* t, int dim, bool need_J, TrajDev* td)
+{
+    CHECK_ARG(t != nullptr, "trajectories is NULL");
+    CHECK_ARG(t->count >= 0 && t->count < (int64_t(1) << 31), "count must be in [0, 2^31)");
+    CHECK_ARG(t->prec == FLA_F32 || t->prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
+    TrajDev d{};
+    d.count = t->count;
+    if (t->count > 0) {
+        for (int a = 0; a < dim; ++a) {
+            CHECK_ARG(t->x[a] && t->v[a] && t->ug[a], "x, v and ug must be non-NULL for every axis");
+            d.x[a] = t->x[a];
+            d.v[a] = t->v[a];
+            d.ug[a] = t->ug[a];
+        }
+        CHECK_ARG(t->r != nullptr, "r is NULL");
+        if (need_J) {
+            CHECK_ARG(t->J != nullptr, "J is NULL");
+            CHECK_ARG(t->n0 != nullptr || is_fin(t->n0_scalar), "n0_scalar must be finite when n0 is NULL");
+        }
+    }
+    d.J = t->J;
+    d.r = t->r;
+    d.n0 = t->n0;
+    d.n0_scalar = t->n0_scalar;
+    d.seed_volume = t->seed_volume;
+    *td = d;
+    return FLA_OK;
+}
+
+fla_status check_fields(fla_ctx* ctx, const fla_fields* out, int dim)
+{
+    CHECK_ARG(out != nullptr, "out is NULL");
+    CHECK_ARG(out->S_mass != nullptr, "out.S_mass is NULL");
+    for (int a = 0; a < dim; ++a) CHECK_ARG(out->S_mom[a] != nullptr, "out.S_mom[a] is NULL for an axis a < dim");
+    return FLA_OK;
+}
+
+template <typename R>
+fla_status zero_outputs(fla_ctx* ctx, const MeshDev& m, const fla_fields* out, hipStream_t s)
+{
+    HIP_OK(launch_fill_real<R>((R*)out->S_mass, m.M, s));
+    for (int a = 0; a < m.dim; ++a) HIP_OK(launch_fill_real<R>((R*)out->S_mom[a], m.M, s));
+    if (out->den) HIP_OK(launch_fill_real<R>((R*)out->den, m.M, s));
+    return FLA_OK;
+}
+
+int bits_for(uint64_t maxval)
+{
+    int b = 0;
+    while (b < 32 && (uint64_t(1) << b) <= maxval) ++b;
+    return b;
+}
+
+template <typename R, int D>
+fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const fla_params* p,
+                        const fla_mesh* mesh, const fla_fields* out, hipStream_t s)
+{
+    const int64_t N = t.count;
+    const int deposit = p->mode == FLA_DEPOSIT;
+    const uint32_t nb = (uint32_t)kClasses * (uint32_t)m.ntiles;
+    const int key_bits = bits_for(nb);
+    const int64_t hist_w = radix_hist_words(N);
+    const int64_t scan_w = scan_tmp_words(hist_w > (int64_t)nb + 1 ? hist_w : (int64_t)nb + 1);
+    const int C = D + 1;
+
+    auto layout = [&](Carver& c, uint32_t** keys, uint32_t** vals, uint32_t** keys2, uint32_t** vals2,
+                      double4** rpos_u, double4** rpos, R** rw_u, R** rw, double** qd, uint32_t** bstart,
+                      uint32_t** hist, uint32_t** scan) {
+        *keys = c.take<uint32_t>(N);
+        *vals = c.take<uint32_t>(N);
+        *keys2 = c.take<uint32_t>(N);
+        *vals2 = c.take<uint32_t>(N);
+        *rpos_u = c.take<double4>(N);
+        *rpos = c.take<double4>(N);
+        *rw_u = c.take<R>((size_t)N * kRecW);
+        *rw = c.take<R>((size_t)N * kRecW);
+        *qd = c.take<double>(deposit ? (size_t)N * C : 1);
+        *bstart = c.take<uint32_t>(nb + 1);
+        *hist = c.take<uint32_t>(hist_w > 0 ? hist_w : 1);
+        *scan = c.take<uint32_t>(scan_w);
+    };
+    uint32_t *keys, *vals, *keys2, *vals2, *bstart, *hist, *scan;
+    double4 *rpos_u, *rpos;
+    R *rw_u, *rw;
+    double* qd;
+    {
+        Carver probe(nullptr);
+        layout(probe, &keys, &vals, &keys2, &vals2, &rpos_u, &rpos, &rw_u, &rw, &qd, &bstart, &hist, &scan);
+        fla_status st = ensure_ws(ctx, probe.off + 256);
+        if (st != FLA_OK) return st;
+    }
+    Carver c(ctx->ws);
+    layout(c, &keys, &vals, &keys2, &vals2, &rpos_u, &rpos, &rw_u, &rw, &qd, &bstart, &hist, &scan);
+
+    PhysDev ph{p->rho_d, p->mu, p->delta, p->h0, p->cutoff, p->scale};
+    HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
+    HIP_OK(launch_fill_u64(ctx->stats + ST_TRAJ, 1, (unsigned long long)N, s));
+    HIP_OK((launch_prepass<R, D>(t, m, ph, p->h_factor, deposit, keys, vals, rpos_u, rw_u, qd, ctx->stats, s)));
+    bool in_alt = false;
+    HIP_OK(radix_sort_pairs(keys, vals, keys2, vals2, N, key_bits, hist, hist_w, scan, scan_w, s, &in_alt));
+    uint32_t* skeys = in_alt ? keys2 : keys;
+    uint32_t* svals = in_alt ? vals2 : vals;
+    HIP_OK(launch_bucket_bounds(skeys, N, nb, bstart, s));
+    HIP_OK(launch_permute<R>(svals, N, rpos_u, rw_u, rpos, rw, deposit ? 0 : 1, s));
+    if (deposit)
+        HIP_OK((launch_deposit_norm<R, D>(m, ph, bstart + nb, svals, qd, N, rpos, rw, ctx->stats, s)));
+
+    GatherArgs g{};
+    g.m = m;
+    g.rpos = rpos;
+    g.rw = rw;
+    g.bstart = bstart;
+    g.cutoff = p->cutoff;
+    double cf = p->cutoff * (1.0 + kSupportMargin);
+    g.filt2 = cf * cf;
+    g.scale = p->scale;
+    g.cell_scale = mesh->cell_scale;
+    g.out[0] = out->S_mass;
+    for (int a = 0; a < D; ++a) g.out[1 + a] = out->S_mom[a];
+    g.den = out->den;
+    g.stats = ctx->stats;
+    HIP_OK((launch_gather<R, D>(g, p->mode, p->count_pairs != 0, s)));
+    return FLA_OK;
+}
+
+template <typename R, int D>
+fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double weight, const fla_params* p,
+                        const fla_mesh* mesh, const fla_fields* out, hipStream_t s)
+{
+    const int C = D + 1;
+    auto layout = [&](Carver& c, unsigned long long** acc, unsigned int** counts, unsigned long long** maxbits,
+                      double** qscale) {
+        *acc = c.take<unsigned long long>((size_t)C * m.M);
+        *counts = c.take<unsigned int>(m.M);
+        *maxbits = c.take<unsigned long long>(4);
+        *qscale = c.take<double>(4);
+    };
+    unsigned long long *acc, *maxbits;
+    unsigned int* counts;
+    double* qscale;
+    {
+        Carver probe(nullptr);
+        layout(probe, &acc, &counts, &maxbits, &qscale);
+        fla_status st = ensure_ws(ctx, probe.off + 256);
+        if (st != FLA_OK) return st;
+    }
+    Carver c(ctx->ws);
+    layout(c, &acc, &counts, &maxbits, &qscale);
+    HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
+    HIP_OK(launch_fill_u64(ctx->stats + ST_TRAJ, 1, (unsigned long long)t.count, s));
+    PsiArgs a{};
+    a.m = m;
+    a.p = t;
+    a.ph = PhysDev{p->rho_d, p->mu, p->delta, p->h0, p->cutoff, p->scale};
+    a.weight = weight;
+    a.cell_scale = mesh->cell_scale;
+    a.out[0] = out->S_mass;
+    for (int ax = 0; ax < D; ++ax) a.out[1 + ax] = out->S_mom[ax];
+    a.den = out->den;
+    a.acc = acc;
+    a.counts = counts;
+    a.maxbits = maxbits;
+    a.qscale = qscale;
+    a.stats = ctx->stats;
+    HIP_OK((launch_psicell<R, D>(a, s)));
+    return FLA_OK;
+}
+
+fla_status check_params(fla_ctx* ctx, const fla_params* p, bool projection)
+{
+    CHECK_ARG(p != nullptr, "params is NULL");
+    CHECK_ARG(is_fin(p->rho_d) && p->rho_d > 0.0, "rho_d must be positive and finite");
+    CHECK_ARG(is_fin(p->mu) && p->mu > 0.0, "mu must be positive and finite");
+    CHECK_ARG(is_fin(p->delta), "delta must be finite");
+    if (projection) {
+        CHECK_ARG(is_fin(p->h0) && p->h0 > 0.0, "h0 must be positive and finite");
+        CHECK_ARG(is_fin(p->cutoff) && p->cutoff > 0.0 && p->cutoff < 1.0e3, "cutoff must be in (0, 1000)");
+        CHECK_ARG(is_fin(p->scale), "scale must be finite");
+        CHECK_ARG(p->mode == FLA_NW || p->mode == FLA_DEPOSIT, "mode must be FLA_NW or FLA_DEPOSIT");
+    }
+    return FLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+FLA_EXPORT fla_status fla_ctx_create(fla_ctx** out, int device)
+{
+    g_create_error.clear();
+    if (!out) {
+        g_create_error = "out is NULL";
+        return FLA_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) {
+        g_create_error = std::string("no HIP device: ") + hipGetErrorString(e);
+        return FLA_ERR_DEVICE;
+    }
+    if (device < 0 || device >= ndev) {
+        g_create_error = "device index out of range";
+        return FLA_ERR_INVALID_ARG;
+    }
+    fla_ctx* ctx = new (std::nothrow) fla_ctx();
+    if (!ctx) {
+        g_create_error = "host allocation failed";
+        return FLA_ERR_OUT_OF_MEMORY;
+    }
+    ctx->device = device;
+    e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->stats, sizeof(unsigned long long) * ST_N);
+    if (e == hipSuccess) e = hipMemset(ctx->stats, 0, sizeof(unsigned long long) * ST_N);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        g_create_error = std::string("HIP initialisation failed: ") + hipGetErrorString(e);
+        if (ctx->stats) (void)hipFree(ctx->stats);
+        delete ctx;
+        return FLA_ERR_DEVICE;
+    }
+    *out = ctx;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_ctx_destroy(fla_ctx* ctx)
+{
+    if (!ctx) return FLA_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->stats) (void)hipFree(ctx->stats);
+    delete ctx;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_project_sources(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                               const fla_params* params, const fla_fields* out, void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    try {
+        MeshDev m;
+        fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+        if (st != FLA_OK) return st;
+        TrajDev t;
+        st = check_traj(ctx, traj, m.dim, true, &t);
+        if (st != FLA_OK) return st;
+        st = check_params(ctx, params, true);
+        if (st != FLA_OK) return st;
+        st = check_fields(ctx, out, m.dim);
+        if (st != FLA_OK) return st;
+        if (params->mode == FLA_DEPOSIT)
+            CHECK_ARG(is_fin(traj->seed_volume) && traj->seed_volume > 0.0,
+                      "seed_volume must be positive and finite in FLA_DEPOSIT mode");
+        HIP_OK(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        bool f64 = traj->prec == FLA_F64;
+        if (t.count == 0) {
+            HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
+            return f64 ? zero_outputs<double>(ctx, m, out, s) : zero_outputs<float>(ctx, m, out, s);
+        }
+        if (m.dim == 2)
+            return f64 ? project_impl<double, 2>(ctx, m, t, params, mesh, out, s)
+                       : project_impl<float, 2>(ctx, m, t, params, mesh, out, s);
+        return f64 ? project_impl<double, 3>(ctx, m, t, params, mesh, out, s)
+                   : project_impl<float, 3>(ctx, m, t, params, mesh, out, s);
+    } catch (...) {
+        ctx->err = "internal error";
+        return FLA_ERR_DEVICE;
+    }
+}
+
+FLA_EXPORT fla_status psicell_accumulate(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* particles,
+                              double particle_weight, const fla_params* params, const fla_fields* out,
+                              void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    try {
+        MeshDev m;
+        fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+        if (st != FLA_OK) return st;
+        TrajDev t;
+        st = check_traj(ctx, particles, m.dim, false, &t);
+        if (st != FLA_OK) return st;
+        st = check_params(ctx, params, false);
+        if (st != FLA_OK) return st;
+        st = check_fields(ctx, out, m.dim);
+        if (st != FLA_OK) return st;
+        CHECK_ARG(is_fin(particle_weight), "particle_weight must be finite");
+        HIP_OK(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        bool f64 = particles->prec == FLA_F64;
+        if (m.dim == 2)
+            return f64 ? psicell_impl<double, 2>(ctx, m, t, particle_weight, params, mesh, out, s)
+                       : psicell_impl<float, 2>(ctx, m, t, particle_weight, params, mesh, out, s);
+        return f64 ? psicell_impl<double, 3>(ctx, m, t, particle_weight, params, mesh, out, s)
+                   : psicell_impl<float, 3>(ctx, m, t, particle_weight, params, mesh, out, s);
+    } catch (...) {
+        ctx->err = "internal error";
+        return FLA_ERR_DEVICE;
+    }
+}
+
+FLA_EXPORT fla_status fla_get_stats(fla_ctx* ctx, fla_stats* out)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    CHECK_ARG(out != nullptr, "out is NULL");
+    HIP_OK(hipSetDevice(ctx->device));
+    HIP_OK(hipDeviceSynchronize());
+    unsigned long long h[ST_N];
+    HIP_OK(hipMemcpy(h, ctx->stats, sizeof(h), hipMemcpyDeviceToHost));
+    out->trajectories = (int64_t)h[ST_TRAJ];
+    out->skipped = (int64_t)h[ST_SKIPPED];
+    out->no_support = (int64_t)h[ST_NOSUPPORT];
+    out->pairs = (int64_t)h[ST_PAIRS];
+    out->outside = (int64_t)h[ST_OUTSIDE];
+    out->zero_support = (int64_t)h[ST_ZERO];
+    out->max_class = (int64_t)h[ST_MAXCLASS];
+    out->reserved = 0;
+    return FLA_OK;
+}
+
+FLA_EXPORT const char* fla_last_error(const fla_ctx* ctx)
+{
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

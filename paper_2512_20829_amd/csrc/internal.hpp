@@ -1,0 +1,195 @@
+// Internal declarations of the gfx950 FLA projection library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "flaproj.h"
+
+namespace flp {
+
+constexpr int kWave = 64;
+constexpr int kClasses = 8;          // neighbourhood classes (reach 0..6 tiles, 7 = whole axis)
+constexpr int kXcds = 8;             // XCDs per MI355X
+constexpr int kRecW = 8;             // reals per weight record: w0, wq[0..C-1], padding
+constexpr double kSupportMargin = 1e-5;  // relative widening of conservative support tests
+
+// Tile geometry of the gather: a tile is TE^D cells processed by one wave,
+// split into 2^D sub-blocks of SB^D cells; each lane owns one cell per sub-block.
+template <int D> struct Geo;
+template <> struct Geo<3> { static constexpr int TE = 8, SB = 4, NSB = 8; };
+template <> struct Geo<2> { static constexpr int TE = 16, SB = 8, NSB = 4; };
+
+struct MeshDev {
+    int dim;
+    int n[3];
+    int periodic[3];
+    int te;          // tile edge in cells
+    int nt[3];       // tiles per axis
+    int ntiles;
+    int64_t M;
+    double lo[3];
+    double hi[3];
+    double w[3];     // cell width (hi - lo)/n, computed on the host
+    double L[3];     // box length hi - lo
+    double vol;      // cell volume
+};
+
+struct TrajDev {
+    int64_t count;
+    const double* x[3];
+    const double* J;
+    const void* v[3];
+    const void* ug[3];
+    const void* r;
+    const double* n0;
+    double n0_scalar;
+    double seed_volume;
+};
+
+struct PhysDev {
+    double rho_d, mu, delta, h0, cutoff, scale;
+};
+
+// statistics slots (device int64 array)
+enum StatSlot { ST_TRAJ = 0, ST_SKIPPED, ST_NOSUPPORT, ST_PAIRS, ST_OUTSIDE, ST_ZERO, ST_MAXCLASS, ST_N };
+
+// ---------------------------------------------------------------------------
+// Exact-arithmetic helpers: binary64 operations whose rounding must not be
+// altered by multiply-add contraction (they decide which pairs are included).
+// ---------------------------------------------------------------------------
+__device__ inline double cell_centre(const MeshDev& m, int a, int64_t i)
+{
+#pragma clang fp contract(off)
+    double t = ((double)i + 0.5) * m.w[a];
+    return m.lo[a] + t;
+}
+
+// offset from point xp to centre xc along axis a; minimum image on periodic axes
+__device__ inline double axis_offset(const MeshDev& m, int a, double xc, double xp)
+{
+#pragma clang fp contract(off)
+    double d = xc - xp;
+    if (m.periodic[a]) {
+        double k = rint(d / m.L[a]);
+        double s = m.L[a] * k;
+        d = d - s;
+    }
+    return d;
+}
+
+__device__ inline double scaled_sq(double d, double inv_h)
+{
+#pragma clang fp contract(off)
+    double u = d * inv_h;
+    return u * u;
+}
+
+template <int D> __device__ inline double det_rn(const double* J);
+template <> __device__ inline double det_rn<2>(const double* J)
+{
+#pragma clang fp contract(off)
+    double p = J[0] * J[3];
+    double q = J[1] * J[2];
+    return p - q;
+}
+template <> __device__ inline double det_rn<3>(const double* J)
+{
+#pragma clang fp contract(off)
+    double m0 = J[4] * J[8] - J[5] * J[7];
+    double m1 = J[3] * J[8] - J[5] * J[6];
+    double m2 = J[3] * J[7] - J[4] * J[6];
+    double t0 = J[0] * m0;
+    double t1 = J[1] * m1;
+    double t2 = J[2] * m2;
+    return (t0 - t1) + t2;
+}
+
+// Per-axis factors of the separable Gaussian for the cell centre with index
+// ci on axis a and a trajectory at coordinate xp with bandwidth 1/inv_h:
+//   s = (d/h)^2 in binary64, rounded to the working precision R,
+//   e = exp(-s/2) in R.
+// The product of e over the axes is exp(-|x_c - x_i|^2 / (2 h^2)); the sum of
+// s over the axes (in R, axis order) decides inclusion against cutoff^2.
+template <typename R>
+__device__ inline void axis_factor(const MeshDev& m, int a, int64_t ci, double xp, double inv_h, R& s, R& e)
+{
+    double d = axis_offset(m, a, cell_centre(m, a, ci), xp);
+    R sr = (R)scaled_sq(d, inv_h);
+    s = sr;
+    e = exp((R)-0.5 * sr);
+}
+
+// Droplet source channels of one droplet (binary64):
+//   m = 4/3 pi rho r^3, tau = 2 rho r^2/(9 mu), F = m (ug - v)/tau,
+//   mdot = 4 pi rho r^2 * delta/(2 r), phi = [mdot, F + mdot v]   (eqs. 3-5, 9)
+template <int D>
+__device__ inline void droplet_phi(double r, const double* v, const double* ug, const PhysDev& ph,
+                                   double* phi)
+{
+    constexpr double kPi = 3.14159265358979323846;
+    double m = (4.0 / 3.0) * kPi * ph.rho_d * r * r * r;
+    double tau = 2.0 * ph.rho_d * r * r / (9.0 * ph.mu);
+    double rdot = ph.delta / (2.0 * r);
+    double mdot = 4.0 * kPi * ph.rho_d * r * r * rdot;
+    phi[0] = mdot;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double F = m * (ug[a] - v[a]) / tau;
+        phi[1 + a] = F + mdot * v[a];
+    }
+}
+
+// Floor division for possibly negative integers.
+__device__ inline int64_t floordiv(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+__device__ inline int64_t posmod(int64_t a, int64_t b)
+{
+    int64_t r = a % b;
+    return r < 0 ? r + b : r;
+}
+
+// Cell index of coordinate x on axis a: floor((x - lo)/w), wrapped on a periodic
+// axis, clamped to the box on a closed one (the trajectory's home cell).
+__device__ inline int64_t home_index(const MeshDev& m, int a, double x)
+{
+    double g = floor((x - m.lo[a]) / m.w[a]);
+    g = fmin(fmax(g, -4.0e15), 4.0e15);
+    int64_t k = (int64_t)g;
+    if (m.periodic[a]) return posmod(k, m.n[a]);
+    return k < 0 ? 0 : (k >= m.n[a] ? m.n[a] - 1 : k);
+}
+
+// Block remapping so that each XCD (workgroups are dealt round-robin over
+// the XCDs) receives a contiguous range of tiles.
+__device__ inline int xcd_remap(int bid, int nblocks)
+{
+    int q = nblocks / kXcds, rem = nblocks % kXcds;
+    int x = bid % kXcds, j = bid / kXcds;
+    return x * q + (x < rem ? x : rem) + j;
+}
+
+template <typename R> struct V4;
+template <> struct V4<float> { using T = float4; };
+template <> struct V4<double> { using T = double4; };
+
+// ---------------------------------------------------------------------------
+// host-side helpers shared by the translation units
+// ---------------------------------------------------------------------------
+struct Workspace;
+
+hipError_t launch_exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* tmp, int64_t tmp_words,
+                                     hipStream_t s);
+int64_t scan_tmp_words(int64_t n);
+
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                            int64_t n, int key_bits, uint32_t* hist, int64_t hist_words,
+                            uint32_t* scan_tmp, int64_t scan_tmp_words_, hipStream_t s,
+                            bool* result_in_alt);
+int64_t radix_hist_words(int64_t n);
+
+}  // namespace flp

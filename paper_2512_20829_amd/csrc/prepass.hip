@@ -1,0 +1,331 @@
+// Per-trajectory prepass, bucket bounds, record permutation and the
+// per-trajectory normaliser of the conservative deposition mode.
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace flp {
+
+__device__ inline void block_add_stats(unsigned long long* stats, int slot, unsigned long long v)
+{
+    // wave-level reduction, then one atomic per wave (integer: order-independent)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    if ((threadIdx.x % kWave) == 0 && v) atomicAdd(&stats[slot], v);
+}
+
+// One thread per trajectory.  Writes the sort key (neighbourhood class and
+// home tile), the unsorted position record {x, y, z, 1/h} and weight record
+// {1/h, q/h} (or, in deposition mode, the binary64 amounts Q to qd).
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_prepass(TrajDev t, MeshDev m, PhysDev ph, const float* hfac,
+                                                 int deposit, uint32_t* keys, uint32_t* vals,
+                                                 double4* rpos, R* rw, double* qd,
+                                                 unsigned long long* stats)
+{
+    constexpr int TE = Geo<D>::TE;
+    constexpr int C = D + 1;
+    const int64_t N = t.count;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t sentinel = (uint32_t)kClasses * (uint32_t)m.ntiles;
+    unsigned long long skipped = 0, nosup = 0;
+    int cls_used = -1;
+    if (i < N) {
+        double x[3] = {0, 0, 0}, J[9], v[3], ug[3];
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            x[a] = t.x[a][i];
+            v[a] = (double)((const R*)t.v[a])[i];
+            ug[a] = (double)((const R*)t.ug[a])[i];
+            ok = ok && isfinite(x[a]) && isfinite(v[a]) && isfinite(ug[a]);
+        }
+#pragma unroll
+        for (int e = 0; e < D * D; ++e) {
+            J[e] = t.J[(int64_t)e * N + i];
+            ok = ok && isfinite(J[e]);
+        }
+        double r = (double)((const R*)t.r)[i];
+        double n0 = t.n0 ? t.n0[i] : t.n0_scalar;
+        double fac = hfac ? (double)hfac[i] : 1.0;
+        double det = det_rn<D>(J);
+        double adet = fabs(det);
+        ok = ok && isfinite(r) && isfinite(n0) && isfinite(det) && det != 0.0 && isfinite(fac) && fac > 0.0;
+        double h, n, phi[4] = {0, 0, 0, 0};
+        {
+#pragma clang fp contract(off)
+            h = ph.h0 * adet;
+            h = h * fac;
+        }
+        n = n0 / adet;
+        if (ok) droplet_phi<D>(r, v, ug, ph, phi);
+        if (ok) {
+            ok = isfinite(h) && h > 0.0 && isfinite(n);
+#pragma unroll
+            for (int k = 0; k < C; ++k) ok = ok && isfinite(phi[k]);
+        }
+        uint32_t key = sentinel;
+        if (!ok) {
+            skipped = 1;
+        } else {
+            double inv_h = 1.0 / h;
+            double rc = ph.cutoff * h * (1.0 + kSupportMargin);
+            int64_t ht[3] = {0, 0, 0};
+            int reach = 0;
+            bool support = true;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double g = floor((x[a] - m.lo[a]) / m.w[a]);
+                g = fmin(fmax(g, -4.0e15), 4.0e15);
+                int64_t hc = (int64_t)g;
+                double flo = (x[a] - rc - m.lo[a]) / m.w[a] - 0.5 - 1e-9;
+                double fhi = (x[a] + rc - m.lo[a]) / m.w[a] - 0.5 + 1e-9;
+                flo = fmin(fmax(flo, -4.0e15), 4.0e15);
+                fhi = fmin(fmax(fhi, -4.0e15), 4.0e15);
+                int64_t ilo = (int64_t)ceil(flo), ihi = (int64_t)floor(fhi);
+                int64_t ra;
+                if (m.periodic[a]) {
+                    // tile distances are circular: the last tile of an axis whose
+                    // cell count is not a multiple of TE is short, so wrapped cells
+                    // are mapped back into [0, n) before taking their tile
+                    int64_t wrapped = posmod(hc, m.n[a]);
+                    int64_t sh = wrapped - hc;
+                    hc = wrapped;
+                    ilo += sh;
+                    ihi += sh;
+                    ht[a] = hc / TE;
+                    if (ilo > ihi) {
+                        support = false;
+                        ra = 0;
+                    } else if (ihi - ilo + 1 >= m.n[a]) {
+                        ra = m.nt[a];
+                    } else {
+                        int64_t tl = posmod(ilo, m.n[a]) / TE, tr = posmod(ihi, m.n[a]) / TE;
+                        int64_t dl = ilo > hc ? 0 : posmod(ht[a] - tl, m.nt[a]);
+                        int64_t dr = ihi < hc ? 0 : posmod(tr - ht[a], m.nt[a]);
+                        ra = dl > dr ? dl : dr;
+                    }
+                } else {
+                    hc = hc < 0 ? 0 : (hc >= m.n[a] ? m.n[a] - 1 : hc);
+                    ilo = ilo < 0 ? 0 : ilo;
+                    ihi = ihi >= m.n[a] ? m.n[a] - 1 : ihi;
+                    if (ilo > ihi) support = false;
+                    ht[a] = hc / TE;
+                    int64_t tlo = floordiv(ilo, TE), thi = floordiv(ihi, TE);
+                    ra = ht[a] - tlo;
+                    if (thi - ht[a] > ra) ra = thi - ht[a];
+                }
+                if (ra < 0) ra = 0;
+                if (ra > kClasses) ra = kClasses;
+                if ((int)ra > reach) reach = (int)ra;
+            }
+            // In deposition mode a trajectory that reaches no cell centre still
+            // deposits its whole amount into its home cell, so it is kept.
+            if (!support) nosup = 1;
+            if (support || deposit) {
+                int cls = !support ? 0 : (reach < kClasses - 1 ? reach : kClasses - 1);
+                cls_used = cls;
+                int64_t tl = ht[0] + (int64_t)m.nt[0] * (ht[1] + (int64_t)m.nt[1] * ht[2]);
+                key = (uint32_t)cls * (uint32_t)m.ntiles + (uint32_t)tl;
+            }
+            rpos[i] = make_double4(x[0], x[1], x[2], inv_h);
+            R* w = rw + i * kRecW;
+            w[0] = (R)inv_h;
+            if (deposit) {
+                double sc = t.seed_volume * adet;
+#pragma unroll
+                for (int k = 0; k < C; ++k) qd[(int64_t)k * N + i] = (n * phi[k]) * sc;
+            } else {
+#pragma unroll
+                for (int k = 0; k < C; ++k) w[1 + k] = (R)(inv_h * (n * phi[k]));
+            }
+        }
+        keys[i] = key;
+        vals[i] = (uint32_t)i;
+    }
+    block_add_stats(stats, ST_SKIPPED, skipped);
+    block_add_stats(stats, ST_NOSUPPORT, nosup);
+    if (cls_used >= 0) atomicMax(&stats[ST_MAXCLASS], (unsigned long long)cls_used);
+}
+
+// Bucket starts from sorted keys: bstart[b] = first position with key >= b,
+// for b in [0, nb]; each entry is written by exactly one thread.
+__global__ void k_bucket_bounds(const uint32_t* keys, int64_t n, uint32_t nb, uint32_t* bstart)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > n) return;
+    int64_t prev = (p == 0) ? -1 : (int64_t)keys[p - 1];
+    int64_t cur = (p == n) ? (int64_t)nb : (int64_t)keys[p];
+    if (cur > (int64_t)nb) cur = nb;
+    for (int64_t b = prev + 1; b <= cur; ++b) bstart[b] = (uint32_t)p;
+}
+
+template <typename R>
+__global__ void k_permute(const uint32_t* order, int64_t n, const double4* rpos_u, const R* rw_u,
+                          double4* rpos, R* rw, int copy_w)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t i = order[p];
+    rpos[p] = rpos_u[i];
+    if (copy_w) {
+#pragma unroll
+        for (int k = 0; k < kRecW; ++k) rw[p * kRecW + k] = rw_u[(int64_t)i * kRecW + k];
+    }
+}
+
+// Deposition normaliser Z_i = sum over cells within reach of K(x_c, x_i),
+// one wave per sorted trajectory.  Per-axis factors of the cells in the
+// trajectory's support box go to LDS (same binary64 offsets and the same
+// inclusion test as the gather), lanes sweep the box, and a fixed butterfly
+// reduces the wave.  Then the weight record becomes {1/h, Q/(h Z)}; with
+// Z = 0 it becomes a delta record {0, Q} flagged by 1/h < 0.
+constexpr int kZTab = 128;
+template <typename R, int D>
+__global__ __launch_bounds__(64) void k_deposit_norm(MeshDev m, PhysDev ph, const uint32_t* nvalid,
+                                                     const uint32_t* order, const double* qd,
+                                                     int64_t N, double4* rpos, R* rw,
+                                                     unsigned long long* stats)
+{
+    constexpr int C = D + 1;
+    __shared__ R S[3][kZTab];
+    __shared__ R E[3][kZTab];
+    int64_t p = blockIdx.x;
+    if (p >= (int64_t)*nvalid) return;
+    int lane = threadIdx.x;
+    double4 P = rpos[p];
+    double x[3] = {P.x, P.y, P.z};
+    double inv_h = P.w;
+    double h = 1.0 / inv_h;
+    double rc = ph.cutoff * h * (1.0 + kSupportMargin);
+    (void)C;
+    R c2;
+    {
+        R c = (R)ph.cutoff;
+        c2 = c * c;
+    }
+    int64_t lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+    for (int a = 0; a < D; ++a) {
+        double flo = (x[a] - rc - m.lo[a]) / m.w[a] - 0.5 - 1e-9;
+        double fhi = (x[a] + rc - m.lo[a]) / m.w[a] - 0.5 + 1e-9;
+        flo = fmin(fmax(flo, -4.0e15), 4.0e15);
+        fhi = fmin(fmax(fhi, -4.0e15), 4.0e15);
+        int64_t ilo = (int64_t)ceil(flo), ihi = (int64_t)floor(fhi);
+        if (m.periodic[a]) {
+            if (ihi - ilo + 1 >= m.n[a]) { ilo = 0; ihi = m.n[a] - 1; }
+        } else {
+            ilo = ilo < 0 ? 0 : ilo;
+            ihi = ihi >= m.n[a] ? m.n[a] - 1 : ihi;
+        }
+        lo[a] = ilo;
+        cnt[a] = ihi - ilo + 1;
+        if (cnt[a] < 0) cnt[a] = 0;
+    }
+    double z = 0.0;
+    // sweep the support box in blocks of at most kZTab cells per axis
+    for (int64_t bz = 0; bz < cnt[2]; bz += kZTab)
+    for (int64_t by = 0; by < cnt[1]; by += kZTab)
+    for (int64_t bx = 0; bx < cnt[0]; bx += kZTab) {
+        int64_t b0[3] = {bx, by, bz};
+        int len[3];
+        for (int a = 0; a < 3; ++a) {
+            int64_t l = cnt[a] - b0[a];
+            len[a] = (int)(l < kZTab ? l : kZTab);
+        }
+        __syncthreads();
+        for (int a = 0; a < D; ++a) {
+            for (int j = lane; j < len[a]; j += kWave) {
+                int64_t ci = lo[a] + b0[a] + j;
+                if (m.periodic[a]) ci = posmod(ci, m.n[a]);
+                axis_factor<R>(m, a, ci, x[a], inv_h, S[a][j], E[a][j]);
+            }
+        }
+        if (D == 2 && lane == 0) { S[2][0] = 0; E[2][0] = 1; }
+        __syncthreads();
+        int64_t tot = (int64_t)len[0] * len[1] * (D == 3 ? len[2] : 1);
+        for (int64_t j = lane; j < tot; j += kWave) {
+            int jx = (int)(j % len[0]);
+            int64_t r2 = j / len[0];
+            int jy = (int)(r2 % len[1]);
+            int jz = (int)(r2 / len[1]);
+            R s = S[0][jx] + S[1][jy];
+            if (D == 3) s = s + S[2][jz];
+            if (s <= c2) z += (double)(E[0][jx] * E[1][jy] * (D == 3 ? E[2][jz] : (R)1));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o, kWave);
+    if (lane == 0) {
+        // K_ci / Z_i = E_ci / z_i with z_i = sum_c E_ci (the 1/h factors cancel)
+        uint32_t i = order[p];
+        R* w = rw + p * kRecW;
+        if (z > 0.0) {
+            w[0] = (R)inv_h;
+            for (int k = 0; k < C; ++k) w[1 + k] = (R)(qd[(int64_t)k * N + i] / z);
+        } else {
+            w[0] = (R)0;
+            for (int k = 0; k < C; ++k) w[1 + k] = (R)qd[(int64_t)k * N + i];
+            rpos[p].w = -inv_h;
+            atomicAdd(&stats[ST_ZERO], 1ull);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename R, int D>
+hipError_t launch_prepass(const TrajDev& t, const MeshDev& m, const PhysDev& ph, const float* hfac,
+                          int deposit, uint32_t* keys, uint32_t* vals, double4* rpos, R* rw,
+                          double* qd, unsigned long long* stats, hipStream_t s)
+{
+    if (t.count == 0) return hipSuccess;
+    unsigned nb = (unsigned)((t.count + 255) / 256);
+    hipLaunchKernelGGL((k_prepass<R, D>), dim3(nb), dim3(256), 0, s, t, m, ph, hfac, deposit, keys, vals,
+                       rpos, rw, qd, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_bounds(const uint32_t* keys, int64_t n, uint32_t nb, uint32_t* bstart,
+                                hipStream_t s)
+{
+    unsigned g = (unsigned)((n + 1 + 255) / 256);
+    hipLaunchKernelGGL(k_bucket_bounds, dim3(g), dim3(256), 0, s, keys, n, nb, bstart);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_permute(const uint32_t* order, int64_t n, const double4* rpos_u, const R* rw_u,
+                          double4* rpos, R* rw, int copy_w, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL((k_permute<R>), dim3(g), dim3(256), 0, s, order, n, rpos_u, rw_u, rpos, rw, copy_w);
+    return hipGetLastError();
+}
+
+template <typename R, int D>
+hipError_t launch_deposit_norm(const MeshDev& m, const PhysDev& ph, const uint32_t* nvalid,
+                               const uint32_t* order, const double* qd, int64_t N, double4* rpos, R* rw,
+                               unsigned long long* stats, hipStream_t s)
+{
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_deposit_norm<R, D>), dim3((unsigned)N), dim3(64), 0, s, m, ph, nvalid, order,
+                       qd, N, rpos, rw, stats);
+    return hipGetLastError();
+}
+
+#define FLP_INST(R, D)                                                                              \
+    template hipError_t launch_prepass<R, D>(const TrajDev&, const MeshDev&, const PhysDev&,        \
+                                             const float*, int, uint32_t*, uint32_t*, double4*, R*, \
+                                             double*, unsigned long long*, hipStream_t);            \
+    template hipError_t launch_deposit_norm<R, D>(const MeshDev&, const PhysDev&, const uint32_t*,  \
+                                                  const uint32_t*, const double*, int64_t,          \
+                                                  double4*, R*, unsigned long long*, hipStream_t);
+FLP_INST(float, 2)
+FLP_INST(float, 3)
+FLP_INST(double, 2)
+FLP_INST(double, 3)
+template hipError_t launch_permute<float>(const uint32_t*, int64_t, const double4*, const float*, double4*,
+                                          float*, int, hipStream_t);
+template hipError_t launch_permute<double>(const uint32_t*, int64_t, const double4*, const double*,
+                                           double4*, double*, int, hipStream_t);
+
+}  // namespace flp
