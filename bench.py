@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the FLA source projection on one MI355X.
+
+Workload: the 3-D ABC-map case -- 128^3 periodic mesh on the unit cube,
+2,097,152 lattice trajectories deformed by an ABC map of amplitude 0.2 (with
+folds), radius lognormal(ln 10 um, 0.3), h0 = 1/128, cutoff 4 bandwidths,
+binary32 kernel evaluation with binary64 det J.  Inputs are synthetic and
+generated on the GPU before timing; they are resident in HBM when the timed
+region starts.
+
+One step = one fla_project_sources call: prepass (det J, n, h, physics,
+keys), key sort and bucket bounds, record permutation, and the gather with
+its fused epilogue.  Printed as one JSON line (rank 0):
+  value        mesh cells per second (M / step time)
+  pairs_per_s  included trajectory-cell pairs per second
+  roofline     the gather kernel, timed with HIP events on the library's
+               stream: algorithmic flops per launch / average launch time
+  cpu_baseline the FP64 oracle on a bounded sample of the same workload
+  psicell      PSI-CELL accumulation of a 200M-particle cloud (context)
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "mesh cells/s + traj-cell pairs/s; learned vs plain form at fixed rel L2 error"
+# Algorithmic work of one included (cell, trajectory) pair in 3-D with C = 4
+# channels, evaluated directly from the kernel and estimator definitions:
+# 3 offsets, |d|^2 (3 mul + 2 add), scaling by 1/(2h^2) (1), exp (1), the
+# denominator add (1) and 4 numerator multiply-adds (8) = 19 flops.
+FLOPS_PER_PAIR_3D = 19
+# Non-packed fp32 vector peak: 256 CUs x 64 lanes x 2.4 GHz x 2 flops/FMA.
+# The library is compiled with packed fp32 instructions disabled, so the
+# packed figure (157.3 TFLOP/s) is out of reach by construction.
+ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 * 2 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seconds: float):
+    """FP64 oracle, brute force per cell, on a random sample of cells of the
+    same workload; full-field time extrapolated from the sample."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads as W
+    cores = len(os.sched_getaffinity(0))
+    oracle.set_threads(cores)
+    wl = W.c2_abc(device="cpu")
+    f = lambda t: t.to(torch.float32).to(torch.float64)
+    tr = W.Trajectories(wl.traj.x, wl.traj.J, f(wl.traj.v), f(wl.traj.ug), f(wl.traj.r), wl.traj.n0)
+    t0 = time.perf_counter()
+    terms = oracle.trajectory_terms(tr, wl.rho_d, wl.mu, wl.delta, wl.h0)
+    t_terms = time.perf_counter() - t0
+    M = wl.mesh.cells
+    rng = np.random.default_rng(0)
+    probe = rng.choice(M, 4 * cores, replace=False)
+    t0 = time.perf_counter()
+    oracle.nw_cells(wl.mesh, tr.x, terms, probe, wl.cutoff, True)
+    per_cell = (time.perf_counter() - t0) / probe.size
+    n = int(min(M, max(probe.size, seconds / per_cell)))
+    cells = rng.choice(M, n, replace=False)
+    t0 = time.perf_counter()
+    oracle.nw_cells(wl.mesh, tr.x, terms, cells, wl.cutoff, True)
+    t_cells = time.perf_counter() - t0
+    full = t_terms + t_cells * M / n
+    return {
+        "value": M / full,
+        "unit": "cells/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"{n} random cells of the 128^3 mesh, each by brute force over all "
+                   f"{tr.count} trajectories, plus the per-trajectory terms of all trajectories "
+                   f"({t_terms:.2f} s); full field extrapolated as t_terms + t_cells*M/n = {full:.0f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-psicell", action="store_true")
+    ap.add_argument("--psicell-particles", type=int, default=200_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build targets a single GPU; the projection of one snapshot runs on one "
+              "MI355X and --gpus must be 1 (the multi-GPU sharding is a design note only).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2512_20829_amd as F
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    log("generating the 128^3 / 2M-trajectory ABC workload on the GPU")
+    wl = W.c2_abc(device=dev)
+    tr = wl.traj
+    x = tr.x.contiguous()
+    J = tr.J.contiguous()
+    v = tr.v.to(torch.float32).contiguous()
+    ug = tr.ug.to(torch.float32).contiguous()
+    r = tr.r.to(torch.float32).contiguous()
+    st, keep = F.make_trajectories(x, J, v, ug, r, tr.n0, tr.seed_volume)
+    M = wl.mesh.cells
+    mesh = F.mesh_of(wl.mesh)
+    S_mass, S_mom, den = F.alloc_fields(M, 3, torch.float32, dev, den=False)
+    ctx = F.Context(0)
+    params = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
+    counted = F.Params(**{**params.__dict__, "count_pairs": True})
+    ctx.project_sources(mesh, st, counted, S_mass, S_mom)
+    torch.cuda.synchronize()
+    stats = ctx.stats()
+    P = stats["pairs"]
+    log(f"pairs per call: {P} ({P / tr.count:.1f} per trajectory); skipped {stats['skipped']}")
+
+    for _ in range(args.warmup):
+        ctx.project_sources(mesh, st, params, S_mass, S_mom)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        ctx.project_sources(mesh, st, params, S_mass, S_mom)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    g_ms = prof["gather"][0] / max(prof["gather"][1], 1)
+    stages = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1]}
+    log(f"{ms_step:.3f} ms/step; stages (ms/launch): {stages}")
+
+    achieved = P * FLOPS_PER_PAIR_3D / (g_ms * 1e-3) / 1e12
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "gather_c2_traffic.json")
+    if os.path.exists(tpath):
+        try:
+            with open(tpath) as fh:
+                traffic = json.load(fh).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic,
+                "kernel": "k_gather<float,3,NW>", "launch_ms": round(g_ms, 4),
+                "flops_per_pair": FLOPS_PER_PAIR_3D, "pairs_per_launch": P}
+
+    psi = None
+    if not args.no_psicell:
+        Np = args.psicell_particles
+        log(f"generating the {Np}-particle PSI-CELL cloud on the GPU")
+        cl = W.abc_cloud(Np, seed=0, device=dev, jacobian=False)
+        cv, cu, cr = (cl.v.to(torch.float32).contiguous(), cl.ug.to(torch.float32).contiguous(),
+                      cl.r.to(torch.float32).contiguous())
+        pst, pkeep = F.make_trajectories(cl.x.contiguous(), None, cv, cu, cr, 1.0)
+        del cl
+        Pm, Pv, _ = F.alloc_fields(M, 3, torch.float32, dev, den=False)
+        w = W.N0_DEFAULT / Np
+        ctx.psicell_accumulate(mesh, pst, w, params, Pm, Pv)
+        torch.cuda.synchronize()
+        reps = 3
+        ctx.profile_enable(True)
+        e0.record()
+        for _ in range(reps):
+            ctx.psicell_accumulate(mesh, pst, w, params, Pm, Pv)
+        e1.record()
+        torch.cuda.synchronize()
+        psi_ms = e0.elapsed_time(e1) / reps
+        pp = ctx.profile_read()["psicell"]
+        ctx.profile_enable(False)
+        psi = {"particles": Np, "ms": round(psi_ms, 3),
+               "particles_per_s": Np / (psi_ms * 1e-3),
+               "hbm_gbs_input": round(Np * 40 / (psi_ms * 1e-3) / 1e9, 1),
+               "psicell_over_fla_time": round(psi_ms / ms_step, 3),
+               "paper_context": "paper: FLA 32 CPU-h vs PSI-CELL 4030 CPU-h for the whole coupled "
+                                "solver at 100x seeding, University of Brighton CPU cluster"}
+        del pst, pkeep, Pm, Pv
+        torch.cuda.empty_cache()
+        log(f"psicell {Np}: {psi_ms:.3f} ms")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"timing the FP64 oracle on host cores (~{args.cpu_seconds:.0f} s)")
+        cpu = cpu_baseline(args.cpu_seconds)
+        log(f"oracle: {cpu['value']:.1f} cells/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": M / (ms_step * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3-D ABC map (amplitude 0.2, folds), 128^3 periodic mesh, 2,097,152 "
+                               "lattice trajectories, FP32 kernel with FP64 det J, h0 = 1/128, cutoff 4",
+                   "mesh": [128, 128, 128], "trajectories": tr.count, "mode": "NW"},
+        "pairs_per_s": P / (ms_step * 1e-3),
+        "pairs": P,
+        "stage_ms": stages,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "psicell": psi,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

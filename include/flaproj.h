@@ -191,6 +191,23 @@ fla_status psicell_accumulate(fla_ctx* ctx, const fla_mesh* mesh,
  * into *out (host).  Errors: INVALID_ARG for NULL, DEVICE. */
 fla_status fla_get_stats(fla_ctx* ctx, fla_stats* out);
 
+/* Per-stage device timing.  While enabled, every call records a pair of HIP
+ * events around each of its stages on the call's stream; fla_profile_read
+ * synchronises the device and returns, per stage, the summed elapsed time
+ * and the number of timed launches since profiling was enabled.  Stages:
+ * 0 prepass, 1 key sort + bucket bounds + record permutation, 2 deposition
+ * normaliser, 3 gather with fused epilogue, 4 PSI-CELL accumulation.
+ * Errors: INVALID_ARG for NULL, DEVICE. */
+#define FLA_PROFILE_STAGES 8
+typedef struct {
+    double ms[FLA_PROFILE_STAGES];
+    int64_t launches[FLA_PROFILE_STAGES];
+} fla_profile;
+
+/* on != 0: clear previous records and start recording; on == 0: stop. */
+fla_status fla_profile_enable(fla_ctx* ctx, int on);
+fla_status fla_profile_read(fla_ctx* ctx, fla_profile* out);
+
 /* Message of the last error on ctx (host string owned by ctx, valid until
  * the next call on ctx); "" if the last call succeeded.  NULL ctx returns
  * the message of the last failed fla_ctx_create. */

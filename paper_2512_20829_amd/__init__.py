@@ -55,6 +55,13 @@ class fla_stats(C.Structure):
                 ("max_class", C.c_int64), ("reserved", C.c_int64)]
 
 
+PROFILE_STAGES = ["prepass", "sort", "deposit_norm", "gather", "psicell", "s5", "s6", "s7"]
+
+
+class fla_profile(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
+
+
 _vp = C.c_void_p
 _lib.fla_ctx_create.restype = C.c_int
 _lib.fla_ctx_create.argtypes = [C.POINTER(_vp), C.c_int]
@@ -68,6 +75,10 @@ _lib.psicell_accumulate.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_traj
                                     C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
 _lib.fla_get_stats.restype = C.c_int
 _lib.fla_get_stats.argtypes = [_vp, C.POINTER(fla_stats)]
+_lib.fla_profile_enable.restype = C.c_int
+_lib.fla_profile_enable.argtypes = [_vp, C.c_int]
+_lib.fla_profile_read.restype = C.c_int
+_lib.fla_profile_read.argtypes = [_vp, C.POINTER(fla_profile)]
 _lib.fla_last_error.restype = C.c_char_p
 _lib.fla_last_error.argtypes = [_vp]
 
@@ -242,6 +253,15 @@ class Context:
                            params: Params, S_mass, S_mom, den=None, stream=None):
         st = self.psicell_raw(mesh, particles, weight, params.to_c(), make_fields(S_mass, S_mom, den), stream)
         self._check(st)
+
+    def profile_enable(self, on: bool = True):
+        self._check(_lib.fla_profile_enable(self._h, int(bool(on))))
+
+    def profile_read(self) -> dict:
+        """{stage: (total_ms, launches)} since profiling was enabled."""
+        p = fla_profile()
+        self._check(_lib.fla_profile_read(self._h, C.byref(p)))
+        return {PROFILE_STAGES[k]: (float(p.ms[k]), int(p.launches[k])) for k in range(8)}
 
     def stats(self) -> dict:
         s = fla_stats()

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "flaproj.h"
 #include "internal.hpp"
@@ -19,6 +20,12 @@ struct fla_ctx {
     void* ws = nullptr;
     size_t ws_size = 0;
     unsigned long long* stats = nullptr;   // ST_N counters
+    bool prof = false;
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
 };
 
 static thread_local std::string g_create_error;
@@ -87,6 +94,29 @@ fla_status ensure_ws(fla_ctx* ctx, size_t need)
 }
 
 bool is_fin(double v) { return std::isfinite(v); }
+
+// Records a pair of events around one stage when profiling is on.
+struct StageTimer {
+    fla_ctx* ctx;
+    int stage;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(fla_ctx* c, int st, hipStream_t str) : ctx(c), stage(st), s(str)
+    {
+        if (!ctx->prof) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            a = b = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, s);
+    }
+    ~StageTimer()
+    {
+        if (!a) return;
+        (void)hipEventRecord(b, s);
+        ctx->recs.push_back({stage, a, b});
+    }
+};
 
 fla_status check_mesh(fla_ctx* ctx, const fla_mesh* mesh, MeshDev* md, int te)
 {
@@ -228,15 +258,24 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
     PhysDev ph{p->rho_d, p->mu, p->delta, p->h0, p->cutoff, p->scale};
     HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
     HIP_OK(launch_fill_u64(ctx->stats + ST_TRAJ, 1, (unsigned long long)N, s));
-    HIP_OK((launch_prepass<R, D>(t, m, ph, p->h_factor, deposit, keys, vals, rpos_u, rw_u, qd, ctx->stats, s)));
+    {
+        StageTimer tm(ctx, 0, s);
+        HIP_OK((launch_prepass<R, D>(t, m, ph, p->h_factor, deposit, keys, vals, rpos_u, rw_u, qd, ctx->stats, s)));
+    }
     bool in_alt = false;
-    HIP_OK(radix_sort_pairs(keys, vals, keys2, vals2, N, key_bits, hist, hist_w, scan, scan_w, s, &in_alt));
-    uint32_t* skeys = in_alt ? keys2 : keys;
-    uint32_t* svals = in_alt ? vals2 : vals;
-    HIP_OK(launch_bucket_bounds(skeys, N, nb, bstart, s));
-    HIP_OK(launch_permute<R>(svals, N, rpos_u, rw_u, rpos, rw, deposit ? 0 : 1, s));
-    if (deposit)
+    uint32_t *skeys, *svals;
+    {
+        StageTimer tm(ctx, 1, s);
+        HIP_OK(radix_sort_pairs(keys, vals, keys2, vals2, N, key_bits, hist, hist_w, scan, scan_w, s, &in_alt));
+        skeys = in_alt ? keys2 : keys;
+        svals = in_alt ? vals2 : vals;
+        HIP_OK(launch_bucket_bounds(skeys, N, nb, bstart, s));
+        HIP_OK(launch_permute<R>(svals, N, rpos_u, rw_u, rpos, rw, deposit ? 0 : 1, s));
+    }
+    if (deposit) {
+        StageTimer tm(ctx, 2, s);
         HIP_OK((launch_deposit_norm<R, D>(m, ph, bstart + nb, svals, qd, N, rpos, rw, ctx->stats, s)));
+    }
 
     GatherArgs g{};
     g.m = m;
@@ -252,7 +291,10 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
     for (int a = 0; a < D; ++a) g.out[1 + a] = out->S_mom[a];
     g.den = out->den;
     g.stats = ctx->stats;
-    HIP_OK((launch_gather<R, D>(g, p->mode, p->count_pairs != 0, s)));
+    {
+        StageTimer tm(ctx, 3, s);
+        HIP_OK((launch_gather<R, D>(g, p->mode, p->count_pairs != 0, s)));
+    }
     return FLA_OK;
 }
 
@@ -295,7 +337,10 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
     a.maxbits = maxbits;
     a.qscale = qscale;
     a.stats = ctx->stats;
-    HIP_OK((launch_psicell<R, D>(a, s)));
+    {
+        StageTimer tm(ctx, 4, s);
+        HIP_OK((launch_psicell<R, D>(a, s)));
+    }
     return FLA_OK;
 }
 
@@ -315,6 +360,8 @@ fla_status check_params(fla_ctx* ctx, const fla_params* p, bool projection)
 }
 
 }  // namespace
+
+static void drop_records(fla_ctx* ctx);
 
 extern "C" {
 
@@ -361,6 +408,7 @@ FLA_EXPORT fla_status fla_ctx_destroy(fla_ctx* ctx)
     if (!ctx) return FLA_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    drop_records(ctx);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->stats) (void)hipFree(ctx->stats);
     delete ctx;
@@ -452,6 +500,49 @@ FLA_EXPORT fla_status fla_get_stats(fla_ctx* ctx, fla_stats* out)
     out->zero_support = (int64_t)h[ST_ZERO];
     out->max_class = (int64_t)h[ST_MAXCLASS];
     out->reserved = 0;
+    return FLA_OK;
+}
+
+static void drop_records(fla_ctx* ctx)
+{
+    for (auto& r : ctx->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    ctx->recs.clear();
+}
+
+FLA_EXPORT fla_status fla_profile_enable(fla_ctx* ctx, int on)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    HIP_OK(hipSetDevice(ctx->device));
+    if (!ctx->recs.empty()) {
+        HIP_OK(hipDeviceSynchronize());
+        drop_records(ctx);
+    }
+    ctx->prof = on != 0;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_profile_read(fla_ctx* ctx, fla_profile* out)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    CHECK_ARG(out != nullptr, "out is NULL");
+    HIP_OK(hipSetDevice(ctx->device));
+    HIP_OK(hipDeviceSynchronize());
+    for (int k = 0; k < FLA_PROFILE_STAGES; ++k) {
+        out->ms[k] = 0.0;
+        out->launches[k] = 0;
+    }
+    for (auto& r : ctx->recs) {
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+        if (r.stage >= 0 && r.stage < FLA_PROFILE_STAGES) {
+            out->ms[r.stage] += (double)ms;
+            out->launches[r.stage] += 1;
+        }
+    }
     return FLA_OK;
 }
 

@@ -43,29 +43,43 @@ __device__ inline void two_sum_acc(R& hi, R& lo, R p)
     lo += err;
 }
 
+constexpr int kGatherWaves = 4;     // waves per workgroup; all work on one tile
+
+template <typename R, int D>
+struct GatherLds {
+    using R4 = typename V4<R>::T;
+    static constexpr int SB = Geo<D>::SB, NA = D + 2;
+    uint32_t cand[kCap];               // compacted candidate record indices
+    R4 tab[kWave][D][SB];              // {s, e} at in-block position l and l + SB
+    R wts[kWave][NA];                  // {1/h, q/h ...} of each staged record
+    int mask[kWave];                   // sub-blocks holding at least one included pair
+};
+
 template <typename R, int D, int MODE, bool COUNT>
-__global__ __launch_bounds__(64) void k_gather(GatherArgs g)
+__global__ __launch_bounds__(kWave * kGatherWaves) void k_gather(GatherArgs g)
 {
     using G = Geo<D>;
     constexpr int TE = G::TE, SB = G::SB, NSB = G::NSB, C = D + 1, NA = C + 1;
     constexpr bool kComp = sizeof(R) == 4;
     using R4 = typename V4<R>::T;
-    __shared__ uint32_t cand[kCap];
-    __shared__ R4 tab[kWave][D][SB];
-    __shared__ R mins[kWave][D][2];
-    __shared__ R wts[kWave][NA];
+    using L = GatherLds<R, D>;
+    static_assert(sizeof(L) * kGatherWaves >= sizeof(R) * kGatherWaves * NSB * NA * kWave,
+                  "reduction buffer must fit in the staging space");
+    __shared__ L lds[kGatherWaves];
     __shared__ double xcs[D][TE];
 
     const MeshDev& m = g.m;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
+    const int wave = threadIdx.x / kWave;
+    L& my = lds[wave];
     const int tile = xcd_remap(blockIdx.x, m.ntiles);
     int tc[3];
     tc[0] = tile % m.nt[0];
     tc[1] = (tile / m.nt[0]) % m.nt[1];
     tc[2] = (D == 3) ? tile / (m.nt[0] * m.nt[1]) : 0;
 
-    if (lane < D * TE) {
-        int a = lane / TE, p = lane % TE;
+    if (threadIdx.x < D * TE) {
+        int a = threadIdx.x / TE, p = threadIdx.x % TE;
         xcs[a][p] = cell_centre(m, a, (int64_t)tc[a] * TE + p);
     }
     int lc[3];
@@ -110,75 +124,81 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g)
     const uint64_t ltmask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     __syncthreads();
 
-    // ---- one batch of L <= 64 candidates: tables, then accumulation
-    auto process = [&](int L) {
-        __syncthreads();
-        if (lane < L) {
-            uint32_t p = cand[lane];
+    // ---- one batch of n <= 64 staged candidates of this wave
+    auto process = [&](int n) {
+        wave_sync();
+        if (lane < n) {
+            uint32_t p = my.cand[lane];
             double4 P = g.rpos[p];
             const R* w = (const R*)g.rw + (size_t)p * kRecW;
 #pragma unroll
-            for (int k = 0; k < NA; ++k) wts[lane][k] = w[k];
+            for (int k = 0; k < NA; ++k) my.wts[lane][k] = w[k];
             double x[3] = {P.x, P.y, P.z};
             bool delta = P.w < 0.0;
             double inv_h = delta ? -P.w : P.w;
+            R mn[3][2];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 int64_t hcell = delta ? home_index(m, a, x[a]) : -1;
                 R mlo = r_inf<R>(), mhi = r_inf<R>();
 #pragma unroll
                 for (int l = 0; l < SB; ++l) {
-                    R s[2], e[2];
+                    R sv[2], ev[2];
 #pragma unroll
                     for (int hh = 0; hh < 2; ++hh) {
                         int pp = l + hh * SB;
                         int64_t idx = (int64_t)tc[a] * TE + pp;
                         if (idx >= m.n[a]) {
-                            s[hh] = r_inf<R>();
-                            e[hh] = 0;
+                            sv[hh] = r_inf<R>();
+                            ev[hh] = 0;
                         } else if (delta) {
                             bool home = idx == hcell;
-                            s[hh] = home ? (R)0 : r_inf<R>();
-                            e[hh] = home ? (R)1 : (R)0;
+                            sv[hh] = home ? (R)0 : r_inf<R>();
+                            ev[hh] = home ? (R)1 : (R)0;
                         } else {
                             double d = axis_offset(m, a, xcs[a][pp], x[a]);
                             R sr = (R)scaled_sq(d, inv_h);
-                            s[hh] = sr;
-                            e[hh] = exp((R)-0.5 * sr);
+                            sv[hh] = sr;
+                            ev[hh] = exp((R)-0.5 * sr);
                         }
                     }
                     R4 t4;
-                    t4.x = s[0];
-                    t4.y = e[0];
-                    t4.z = s[1];
-                    t4.w = e[1];
-                    tab[lane][a][l] = t4;
-                    mlo = fmin(mlo, s[0]);
-                    mhi = fmin(mhi, s[1]);
+                    t4.x = sv[0];
+                    t4.y = ev[0];
+                    t4.z = sv[1];
+                    t4.w = ev[1];
+                    my.tab[lane][a][l] = t4;
+                    mlo = fmin(mlo, sv[0]);
+                    mhi = fmin(mhi, sv[1]);
                 }
-                mins[lane][a][0] = mlo;
-                mins[lane][a][1] = mhi;
+                mn[a][0] = mlo;
+                mn[a][1] = mhi;
             }
+            // a sub-block can hold an included pair only if the sum of the
+            // per-axis minima passes the test (sums are monotone in each term)
+            int mk = 0;
+#pragma unroll
+            for (int b = 0; b < NSB; ++b) {
+                R smin = mn[0][b & 1] + mn[1][(b >> 1) & 1];
+                if (D == 3) smin = smin + mn[2][(b >> 2) & 1];
+                mk |= (smin <= c2) ? (1 << b) : 0;
+            }
+            my.mask[lane] = mk;
         }
-        __syncthreads();
-        for (int e = 0; e < L; ++e) {
-            R mn[3][2];
+        wave_sync();
+        for (int e = 0; e < n; ++e) {
+            const int mk = __builtin_amdgcn_readfirstlane(my.mask[e]);
+            if (mk == 0) continue;
             R4 t[3];
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-                mn[a][0] = mins[e][a][0];
-                mn[a][1] = mins[e][a][1];
-                t[a] = tab[e][a][lc[a]];
-            }
+            for (int a = 0; a < D; ++a) t[a] = my.tab[e][a][lc[a]];
             R wv[NA];
 #pragma unroll
-            for (int k = 0; k < NA; ++k) wv[k] = wts[e][k];
+            for (int k = 0; k < NA; ++k) wv[k] = my.wts[e][k];
 #pragma unroll
             for (int b = 0; b < NSB; ++b) {
                 const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-                R smin = mn[0][bx] + mn[1][by];
-                if (D == 3) smin = smin + mn[2][bz];
-                if (smin <= c2) {
+                if (mk & (1 << b)) {
                     R s = (bx ? t[0].z : t[0].x) + (by ? t[1].z : t[1].x);
                     R ew = (bx ? t[0].w : t[0].y) * (by ? t[1].w : t[1].y);
                     if (D == 3) {
@@ -202,9 +222,11 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g)
                     part[b][k] = 0;
                 }
         }
+        wave_sync();
     };
 
     int ncand = 0;
+    uint32_t chunk = 0;          // chunks of 64 candidates are dealt round-robin to the waves
     const int ntl = m.ntiles;
     for (int k = 0; k < kClasses; ++k) {
         const uint32_t kb = (uint32_t)k * (uint32_t)ntl;
@@ -261,6 +283,7 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g)
                     const uint32_t s0 = g.bstart[rowb + runs[q][0]];
                     const uint32_t s1 = g.bstart[rowb + runs[q][1] + 1];
                     for (uint32_t base = s0; base < s1; base += kWave) {
+                        if ((chunk++ % kGatherWaves) != (uint32_t)wave) continue;
                         uint32_t p = base + lane;
                         bool ok = false;
                         if (p < s1) {
@@ -285,15 +308,14 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g)
                             }
                         }
                         uint64_t bal = __ballot(ok);
-                        if (ok) cand[ncand + __popcll(bal & ltmask)] = p;
+                        if (ok) my.cand[ncand + __popcll(bal & ltmask)] = p;
                         ncand += __popcll(bal);
                         if (ncand >= kWave) {
                             process(kWave);
-                            __syncthreads();
                             int rem = ncand - kWave;
-                            uint32_t mv = (lane < rem) ? cand[kWave + lane] : 0u;
-                            __syncthreads();
-                            if (lane < rem) cand[lane] = mv;
+                            uint32_t mv = (lane < rem) ? my.cand[kWave + lane] : 0u;
+                            wave_sync();
+                            if (lane < rem) my.cand[lane] = mv;
                             ncand = rem;
                         }
                     }
@@ -303,9 +325,18 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g)
     }
     if (ncand > 0) process(ncand);
 
-    // ---- epilogue: divide (NW) or scale by 1/V_c (deposition), sign, scale
+    // ---- fixed-order reduction of the waves' partial sums through LDS
+    __syncthreads();
+    R* red = reinterpret_cast<R*>(lds);   // [wave][b][k][lane]
 #pragma unroll
-    for (int b = 0; b < NSB; ++b) {
+    for (int b = 0; b < NSB; ++b)
+#pragma unroll
+        for (int k = 0; k < NA; ++k)
+            red[((wave * NSB + b) * NA + k) * kWave + lane] = kComp ? hi[b][k] + lo[b][k] : part[b][k];
+    __syncthreads();
+
+    // ---- epilogue: divide (NW) or scale by 1/V_c (deposition), sign, scale
+    for (int b = wave; b < NSB; b += kGatherWaves) {
         int64_t cidx[3] = {0, 0, 0};
         bool inside = true;
 #pragma unroll
@@ -314,21 +345,27 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g)
             inside = inside && cidx[a] < m.n[a];
         }
         if (!inside) continue;
+        double tot[NA];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            double acc = 0.0;
+            for (int v = 0; v < kGatherWaves; ++v) acc += (double)red[((v * NSB + b) * NA + k) * kWave + lane];
+            tot[k] = acc;
+        }
         int64_t lin = cidx[0] + (int64_t)m.n[0] * (cidx[1] + (int64_t)m.n[1] * cidx[2]);
-        R den = kComp ? hi[b][0] + lo[b][0] : part[b][0];
+        double den = tot[0];
         double cs = g.cell_scale ? (double)((const R*)g.cell_scale)[lin] : 1.0;
         double f = -g.scale * cs;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            R num = kComp ? hi[b][1 + k] + lo[b][1 + k] : part[b][1 + k];
             double val;
             if (MODE == FLA_NW)
-                val = (den > (R)0) ? f * ((double)num / (double)den) : 0.0;
+                val = (den > 0.0) ? f * (tot[1 + k] / den) : 0.0;
             else
-                val = f * (double)num / m.vol;
+                val = f * tot[1 + k] / m.vol;
             ((R*)g.out[k])[lin] = (R)val;
         }
-        if (g.den) ((R*)g.den)[lin] = den;
+        if (g.den) ((R*)g.den)[lin] = (R)den;
     }
     if (COUNT) {
 #pragma unroll
@@ -340,7 +377,7 @@ __global__ __launch_bounds__(64) void k_gather(GatherArgs g)
 template <typename R, int D>
 hipError_t launch_gather(const GatherArgs& g, int mode, bool count, hipStream_t s)
 {
-    dim3 grid((unsigned)g.m.ntiles), block(kWave);
+    dim3 grid((unsigned)g.m.ntiles), block(kWave * kGatherWaves);
     if (mode == FLA_NW) {
         if (count)
             hipLaunchKernelGGL((k_gather<R, D, FLA_NW, true>), grid, block, 0, s, g);

@@ -70,7 +70,10 @@ __device__ inline double axis_offset(const MeshDev& m, int a, double xc, double 
 {
 #pragma clang fp contract(off)
     double d = xc - xp;
-    if (m.periodic[a]) {
+    // |d| < L/2 implies rint(d/L) == 0 (a quotient rounded up to exactly 1/2
+    // still rounds to the even integer 0), so the division is only needed
+    // for offsets of half a box or more; the result is unchanged.
+    if (m.periodic[a] && !(fabs(d) < 0.5 * m.L[a])) {
         double k = rint(d / m.L[a]);
         double s = m.L[a] * k;
         d = d - s;
@@ -171,6 +174,15 @@ __device__ inline int xcd_remap(int bid, int nblocks)
     int q = nblocks / kXcds, rem = nblocks % kXcds;
     int x = bid % kXcds, j = bid / kXcds;
     return x * q + (x < rem ? x : rem) + j;
+}
+
+// Wave-level LDS synchronisation: orders this wave's LDS accesses across lanes
+// without a workgroup barrier.
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename R> struct V4;

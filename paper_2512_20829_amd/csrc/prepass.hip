@@ -144,19 +144,30 @@ __global__ __launch_bounds__(256) void k_prepass(TrajDev t, MeshDev m, PhysDev p
     }
     block_add_stats(stats, ST_SKIPPED, skipped);
     block_add_stats(stats, ST_NOSUPPORT, nosup);
-    if (cls_used >= 0) atomicMax(&stats[ST_MAXCLASS], (unsigned long long)cls_used);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        int other = __shfl_xor(cls_used, o, kWave);
+        cls_used = other > cls_used ? other : cls_used;
+    }
+    if ((threadIdx.x % kWave) == 0 && cls_used >= 0)
+        atomicMax(&stats[ST_MAXCLASS], (unsigned long long)cls_used);
 }
 
-// Bucket starts from sorted keys: bstart[b] = first position with key >= b,
-// for b in [0, nb]; each entry is written by exactly one thread.
+// Bucket starts from sorted keys: bstart[b] = first position with key >= b
+// (binary search), one thread per bucket b in [0, nb].
 __global__ void k_bucket_bounds(const uint32_t* keys, int64_t n, uint32_t nb, uint32_t* bstart)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > n) return;
-    int64_t prev = (p == 0) ? -1 : (int64_t)keys[p - 1];
-    int64_t cur = (p == n) ? (int64_t)nb : (int64_t)keys[p];
-    if (cur > (int64_t)nb) cur = nb;
-    for (int64_t b = prev + 1; b <= cur; ++b) bstart[b] = (uint32_t)p;
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > (int64_t)nb) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)keys[mid] < b)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    bstart[b] = (uint32_t)lo;
 }
 
 template <typename R>
@@ -286,7 +297,7 @@ hipError_t launch_prepass(const TrajDev& t, const MeshDev& m, const PhysDev& ph,
 hipError_t launch_bucket_bounds(const uint32_t* keys, int64_t n, uint32_t nb, uint32_t* bstart,
                                 hipStream_t s)
 {
-    unsigned g = (unsigned)((n + 1 + 255) / 256);
+    unsigned g = (unsigned)(((int64_t)nb + 1 + 255) / 256);
     hipLaunchKernelGGL(k_bucket_bounds, dim3(g), dim3(256), 0, s, keys, n, nb, bstart);
     return hipGetLastError();
 }

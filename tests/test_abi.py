@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layout_matches_header(tmp_path):
     import paper_2512_20829_amd as F
-    structs = [F.fla_mesh, F.fla_trajectories, F.fla_params, F.fla_fields, F.fla_stats]
+    structs = [F.fla_mesh, F.fla_trajectories, F.fla_params, F.fla_fields, F.fla_stats, F.fla_profile]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "flaproj.h"', "int main(void){"]
     for s in structs:
         nm = s.__name__

@@ -334,9 +334,20 @@ def c2_abc(per_axis: int = 128, mesh_n: int = 128, seed: int = 0, device="cpu",
 
 
 def abc_cloud(n_particles: int, seed: int = 0, device="cpu", abc: Optional[ABC] = None,
-              offset: int = 0, radius="lognormal"):
+              offset: int = 0, radius="lognormal", jacobian: bool = True):
+    """Dense PSI-CELL cloud: X0 ~ U[0,1)^3 through the ABC map.  With
+    jacobian=False the (unused) Jacobian is not formed and J is empty."""
     x0 = random_points(3, n_particles, seed, device, offset)
-    xp, J, v, ug = from_map(x0, "abc", abc if abc is not None else ABC(), wrap=True)
+    abc = abc if abc is not None else ABC()
+    if jacobian:
+        xp, J, v, ug = from_map(x0, "abc", abc, wrap=True)
+    else:
+        xp = x0 + abc.amp * abc.field(x0)
+        v = xp - x0
+        del x0
+        ug = abc.amp * abc.field(xp)
+        xp = wrap_unit(xp)
+        J = torch.empty(0, dtype=torch.float64, device=device)
     if radius == "lognormal":
         r = radius_lognormal(n_particles, seed, device=device, stream=61, offset=offset)
     else:
