@@ -179,10 +179,12 @@ fla_status fla_project_sources(fla_ctx* ctx, const fla_mesh* mesh, const fla_tra
  *   S_k(c) = -(particle_weight / V_c) * cell_scale(c) * sum_{p in c} phi_pk,
  *   phi_p = [mdot_p, F_p + mdot_p v_p]   (n = 1 per droplet),
  * particle_weight being the number of real droplets one computational
- * particle stands for.  Sums are exact integer sums of per-particle values
+ * particle stands for.  phi is evaluated in binary64 and rounded to the
+ * call's precision; the sums are exact integer sums of these values
  * quantised to 2^-e (e chosen per channel from the largest |phi| so that no
  * sum can overflow), hence order-independent.  den, if given, receives the
- * particle count per cell.  Errors as fla_project_sources. */
+ * particle count per cell.  Meshes of more than 16384 * 1024 cells return
+ * INVALID_ARG.  Other errors as fla_project_sources. */
 fla_status psicell_accumulate(fla_ctx* ctx, const fla_mesh* mesh,
                               const fla_trajectories* particles, double particle_weight,
                               const fla_params* params, const fla_fields* out, void* stream);
@@ -207,6 +209,26 @@ typedef struct {
 /* on != 0: clear previous records and start recording; on == 0: stop. */
 fla_status fla_profile_enable(fla_ctx* ctx, int on);
 fla_status fla_profile_read(fla_ctx* ctx, fla_profile* out);
+
+/* Gather plan: the granularity at which the gather skips parts of a tile
+ * that a trajectory cannot reach (0: each sub-block, 1: pairs of sub-blocks
+ * along the last axis, 2: half tiles, 3: no skips).  Every plan produces the
+ * same values (up to the sign of zero); they differ only in speed.  Plans are
+ * kept per (dim, prec) in the context; -1 restores the library default.
+ * Errors: INVALID_ARG for out-of-range arguments. */
+#define FLA_GATHER_PLANS 4
+fla_status fla_set_plan(fla_ctx* ctx, int dim, int prec, int gather_plan);
+fla_status fla_get_plan(fla_ctx* ctx, int dim, int prec, int* gather_plan);
+
+/* Autotuner: runs fla_project_sources once per gather plan on the given
+ * inputs (a warm-up call, then a call timed with HIP events), keeps the
+ * fastest plan for (mesh->dim, traj->prec) in the context and, if times_ms
+ * (host, FLA_GATHER_PLANS values) is not NULL, returns the gather time of
+ * each plan.  Synchronises the device.  out receives the projection.
+ * Errors as fla_project_sources. */
+fla_status fla_autotune(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                        const fla_params* params, const fla_fields* out, void* stream,
+                        double* times_ms);
 
 /* Message of the last error on ctx (host string owned by ctx, valid until
  * the next call on ctx); "" if the last call succeeded.  NULL ctx returns

@@ -79,6 +79,13 @@ _lib.fla_profile_enable.restype = C.c_int
 _lib.fla_profile_enable.argtypes = [_vp, C.c_int]
 _lib.fla_profile_read.restype = C.c_int
 _lib.fla_profile_read.argtypes = [_vp, C.POINTER(fla_profile)]
+_lib.fla_set_plan.restype = C.c_int
+_lib.fla_set_plan.argtypes = [_vp, C.c_int, C.c_int, C.c_int]
+_lib.fla_get_plan.restype = C.c_int
+_lib.fla_get_plan.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_int)]
+_lib.fla_autotune.restype = C.c_int
+_lib.fla_autotune.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories), C.POINTER(fla_params),
+                              C.POINTER(fla_fields), _vp, C.POINTER(C.c_double)]
 _lib.fla_last_error.restype = C.c_char_p
 _lib.fla_last_error.argtypes = [_vp]
 
@@ -262,6 +269,22 @@ class Context:
         p = fla_profile()
         self._check(_lib.fla_profile_read(self._h, C.byref(p)))
         return {PROFILE_STAGES[k]: (float(p.ms[k]), int(p.launches[k])) for k in range(8)}
+
+    def set_plan(self, dim: int, prec: int, plan: int):
+        self._check(_lib.fla_set_plan(self._h, dim, prec, plan))
+
+    def get_plan(self, dim: int, prec: int) -> int:
+        v = C.c_int()
+        self._check(_lib.fla_get_plan(self._h, dim, prec, C.byref(v)))
+        return int(v.value)
+
+    def autotune(self, mesh: fla_mesh, traj: fla_trajectories, params: Params, S_mass, S_mom, den=None,
+                 stream=None):
+        """Time every gather plan on these inputs, keep the fastest; returns the per-plan ms."""
+        t = (C.c_double * 4)()
+        self._check(_lib.fla_autotune(self._h, C.byref(mesh), C.byref(traj), C.byref(params.to_c()),
+                                      C.byref(make_fields(S_mass, S_mom, den)), _stream_handle(stream), t))
+        return [float(v) for v in t]
 
     def stats(self) -> dict:
         s = fla_stats()

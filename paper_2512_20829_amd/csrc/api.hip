@@ -20,6 +20,7 @@ struct fla_ctx {
     void* ws = nullptr;
     size_t ws_size = 0;
     unsigned long long* stats = nullptr;   // ST_N counters
+    int plan[2][2] = {{-1, -1}, {-1, -1}};  // gather plan per (dim - 2, precision); -1 = default
     bool prof = false;
     struct Rec {
         int stage;
@@ -29,6 +30,9 @@ struct fla_ctx {
 };
 
 static thread_local std::string g_create_error;
+
+// gather plan used until fla_set_plan or fla_autotune chooses one
+static constexpr int kDefaultPlan = 0;
 
 namespace {
 
@@ -270,6 +274,7 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
         skeys = in_alt ? keys2 : keys;
         svals = in_alt ? vals2 : vals;
         HIP_OK(launch_bucket_bounds(skeys, N, nb, bstart, s));
+        HIP_OK(launch_max_class(bstart, m.ntiles, ctx->stats, s));
         HIP_OK(launch_permute<R>(svals, N, rpos_u, rw_u, rpos, rw, deposit ? 0 : 1, s));
     }
     if (deposit) {
@@ -293,7 +298,9 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
     g.stats = ctx->stats;
     {
         StageTimer tm(ctx, 3, s);
-        HIP_OK((launch_gather<R, D>(g, p->mode, p->count_pairs != 0, s)));
+        int plan = ctx->plan[D - 2][sizeof(R) == 8 ? 1 : 0];
+        if (plan < 0) plan = kDefaultPlan;
+        HIP_OK((launch_gather<R, D>(g, p->mode, p->count_pairs != 0, plan, s)));
     }
     return FLA_OK;
 }
@@ -303,27 +310,51 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
                         const fla_mesh* mesh, const fla_fields* out, hipStream_t s)
 {
     const int C = D + 1;
-    auto layout = [&](Carver& c, unsigned long long** acc, unsigned int** counts, unsigned long long** maxbits,
-                      double** qscale) {
-        *acc = c.take<unsigned long long>((size_t)C * m.M);
-        *counts = c.take<unsigned int>(m.M);
-        *maxbits = c.take<unsigned long long>(4);
-        *qscale = c.take<double>(4);
+    PsiArgs a{};
+    // coarse tiles: 8^3 (32^2 in 2-D) cells, widened axis by axis until at
+    // most kPsiMaxTiles tiles remain (cells per tile stay <= kPsiMaxCellsPerTile)
+    int pt[3] = {D == 3 ? 8 : 32, D == 3 ? 8 : 32, D == 3 ? 8 : 1};
+    auto ntiles = [&]() {
+        int64_t nt = 1;
+        for (int ax = 0; ax < D; ++ax) nt *= (m.n[ax] + pt[ax] - 1) / pt[ax];
+        return nt;
     };
-    unsigned long long *acc, *maxbits;
-    unsigned int* counts;
-    double* qscale;
+    for (int it = 0; ntiles() > kPsiMaxTiles && it < 64; ++it) {
+        int ax = it % D;
+        if ((int64_t)pt[0] * pt[1] * pt[2] * 2 > kPsiMaxCellsPerTile) break;
+        if (pt[ax] < m.n[ax]) pt[ax] *= 2;
+    }
+    CHECK_ARG(ntiles() <= kPsiMaxTiles, "psicell_accumulate supports at most 16384 * 1024 cells");
+    for (int ax = 0; ax < 3; ++ax) {
+        a.pt[ax] = ax < D ? pt[ax] : 1;
+        a.pnt[ax] = ax < D ? (m.n[ax] + pt[ax] - 1) / pt[ax] : 1;
+    }
+    a.pntiles = (int)ntiles();
+    a.cpt = a.pt[0] * a.pt[1] * a.pt[2];
+    a.nblocks = kPsiBlocks;
+    const int64_t N = t.count;
+    const int64_t hw = (int64_t)a.pntiles * a.nblocks + 1;
+    const int64_t sw = scan_tmp_words(hw);
+    auto layout = [&](Carver& c) {
+        a.maxbits = c.take<unsigned long long>(4);
+        a.qscale = c.take<double>(4);
+        a.codes = c.take<int>(N > 0 ? N : 1);
+        a.blockhist = c.take<unsigned int>(hw);
+        a.bucket = c.take<PsiRec<R>>(N > 0 ? N : 1);
+        a.blockmax = c.take<unsigned long long>((size_t)a.nblocks * 4);
+        a.scan_tmp = c.take<uint32_t>(sw);
+    };
     {
         Carver probe(nullptr);
-        layout(probe, &acc, &counts, &maxbits, &qscale);
+        layout(probe);
         fla_status st = ensure_ws(ctx, probe.off + 256);
         if (st != FLA_OK) return st;
     }
     Carver c(ctx->ws);
-    layout(c, &acc, &counts, &maxbits, &qscale);
+    layout(c);
+    a.scan_words = sw;
     HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
     HIP_OK(launch_fill_u64(ctx->stats + ST_TRAJ, 1, (unsigned long long)t.count, s));
-    PsiArgs a{};
     a.m = m;
     a.p = t;
     a.ph = PhysDev{p->rho_d, p->mu, p->delta, p->h0, p->cutoff, p->scale};
@@ -332,10 +363,6 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
     a.out[0] = out->S_mass;
     for (int ax = 0; ax < D; ++ax) a.out[1 + ax] = out->S_mom[ax];
     a.den = out->den;
-    a.acc = acc;
-    a.counts = counts;
-    a.maxbits = maxbits;
-    a.qscale = qscale;
     a.stats = ctx->stats;
     {
         StageTimer tm(ctx, 4, s);
@@ -543,6 +570,79 @@ FLA_EXPORT fla_status fla_profile_read(fla_ctx* ctx, fla_profile* out)
             out->launches[r.stage] += 1;
         }
     }
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_set_plan(fla_ctx* ctx, int dim, int prec, int gather_plan)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(dim == 2 || dim == 3, "dim must be 2 or 3");
+    CHECK_ARG(prec == FLA_F32 || prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
+    CHECK_ARG(gather_plan >= -1 && gather_plan < kGatherPlans, "gather_plan out of range");
+    ctx->plan[dim - 2][prec] = gather_plan;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_get_plan(fla_ctx* ctx, int dim, int prec, int* gather_plan)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(dim == 2 || dim == 3, "dim must be 2 or 3");
+    CHECK_ARG(prec == FLA_F32 || prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
+    CHECK_ARG(gather_plan != nullptr, "gather_plan is NULL");
+    int p = ctx->plan[dim - 2][prec];
+    *gather_plan = p < 0 ? kDefaultPlan : p;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_autotune(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                                   const fla_params* params, const fla_fields* out, void* stream,
+                                   double* times_ms)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(mesh && traj && params && out, "NULL argument");
+    CHECK_ARG(mesh->dim == 2 || mesh->dim == 3, "mesh.dim must be 2 or 3");
+    CHECK_ARG(traj->prec == FLA_F32 || traj->prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
+    HIP_OK(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int d = mesh->dim - 2, pr = traj->prec;
+    const int saved = ctx->plan[d][pr];
+    const bool was_prof = ctx->prof;
+    fla_status st = fla_profile_enable(ctx, 1);
+    if (st != FLA_OK) return st;
+    double best = 1e300;
+    int best_plan = saved < 0 ? kDefaultPlan : saved;
+    for (int plan = 0; plan < kGatherPlans; ++plan) {
+        ctx->plan[d][pr] = plan;
+        // first call warms the workspace, the second is timed
+        for (int rep = 0; rep < 2; ++rep) {
+            if (rep == 1) {
+                st = fla_profile_enable(ctx, 1);
+                if (st != FLA_OK) break;
+            }
+            st = fla_project_sources(ctx, mesh, traj, params, out, stream);
+            if (st != FLA_OK) break;
+        }
+        if (st != FLA_OK) break;
+        fla_profile pf;
+        st = fla_profile_read(ctx, &pf);
+        if (st != FLA_OK) break;
+        double ms = pf.launches[3] ? pf.ms[3] / (double)pf.launches[3] : 1e300;
+        if (times_ms) times_ms[plan] = ms;
+        if (ms < best) {
+            best = ms;
+            best_plan = plan;
+        }
+    }
+    (void)fla_profile_enable(ctx, was_prof ? 1 : 0);
+    if (st != FLA_OK) {
+        ctx->plan[d][pr] = saved;
+        return st;
+    }
+    ctx->plan[d][pr] = best_plan;
+    (void)s;
     return FLA_OK;
 }
 

@@ -5,7 +5,9 @@
 // the trajectories of its tile in a fixed order, so results are bitwise
 // reproducible.
 //
-// Work decomposition (one 64-lane wave per tile):
+// Work decomposition (one workgroup of four 64-lane waves per tile; the
+// waves take the tile's candidate chunks in turn and their partial sums are
+// added in wave order at the end):
 //  * a tile is TE^D cells, split into 2^D sub-blocks of SB^D cells; lane l
 //    owns the cell with in-block coordinates lc(l) in every sub-block;
 //  * candidate trajectories come from the buckets (class k, home tile) of
@@ -55,7 +57,7 @@ struct GatherLds {
     int mask[kWave];                   // sub-blocks holding at least one included pair
 };
 
-template <typename R, int D, int MODE, bool COUNT>
+template <typename R, int D, int MODE, bool COUNT, int PLAN>
 __global__ __launch_bounds__(kWave * kGatherWaves) void k_gather(GatherArgs g)
 {
     using G = Geo<D>;
@@ -80,7 +82,8 @@ __global__ __launch_bounds__(kWave * kGatherWaves) void k_gather(GatherArgs g)
 
     if (threadIdx.x < D * TE) {
         int a = threadIdx.x / TE, p = threadIdx.x % TE;
-        xcs[a][p] = cell_centre(m, a, (int64_t)tc[a] * TE + p);
+        int64_t idx = (int64_t)tc[a] * TE + p;
+        xcs[a][p] = idx < m.n[a] ? cell_centre(m, a, idx) : __builtin_nan("");
     }
     int lc[3];
     if (D == 3) {
@@ -121,6 +124,14 @@ __global__ __launch_bounds__(kWave * kGatherWaves) void k_gather(GatherArgs g)
             lo[b][k] = 0;
         }
     unsigned long long npairs = 0;
+    int lane_in = 0;   // bit b: this lane's cell of sub-block b lies inside the mesh
+#pragma unroll
+    for (int b = 0; b < NSB; ++b) {
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) in = in && ((int64_t)tc[a] * TE + ((b >> a) & 1) * SB + lc[a] < m.n[a]);
+        lane_in |= in ? (1 << b) : 0;
+    }
     const uint64_t ltmask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     __syncthreads();
 
@@ -147,19 +158,18 @@ __global__ __launch_bounds__(kWave * kGatherWaves) void k_gather(GatherArgs g)
 #pragma unroll
                     for (int hh = 0; hh < 2; ++hh) {
                         int pp = l + hh * SB;
-                        int64_t idx = (int64_t)tc[a] * TE + pp;
-                        if (idx >= m.n[a]) {
-                            sv[hh] = r_inf<R>();
-                            ev[hh] = 0;
-                        } else if (delta) {
-                            bool home = idx == hcell;
+                        if (delta) {
+                            // whole amount into the home cell: factor 1 there, 0 elsewhere
+                            bool home = (int64_t)tc[a] * TE + pp == hcell;
                             sv[hh] = home ? (R)0 : r_inf<R>();
                             ev[hh] = home ? (R)1 : (R)0;
                         } else {
+                            // centres of cells beyond the mesh are NaN: s is NaN, never
+                            // passes the test, and is ignored by the min/max below
                             double d = axis_offset(m, a, xcs[a][pp], x[a]);
                             R sr = (R)scaled_sq(d, inv_h);
                             sv[hh] = sr;
-                            ev[hh] = exp((R)-0.5 * sr);
+                            ev[hh] = gauss_factor(sr);
                         }
                     }
                     R4 t4;
@@ -174,8 +184,9 @@ __global__ __launch_bounds__(kWave * kGatherWaves) void k_gather(GatherArgs g)
                 mn[a][0] = mlo;
                 mn[a][1] = mhi;
             }
-            // a sub-block can hold an included pair only if the sum of the
-            // per-axis minima passes the test (sums are monotone in each term)
+            // visit mask: the sub-block can hold an included pair (the sum of
+            // the per-axis minima passes; binary32/64 sums are monotone in each
+            // term, so the skip never drops an included pair)
             int mk = 0;
 #pragma unroll
             for (int b = 0; b < NSB; ++b) {
@@ -186,32 +197,79 @@ __global__ __launch_bounds__(kWave * kGatherWaves) void k_gather(GatherArgs g)
             my.mask[lane] = mk;
         }
         wave_sync();
-        for (int e = 0; e < n; ++e) {
-            const int mk = __builtin_amdgcn_readfirstlane(my.mask[e]);
-            if (mk == 0) continue;
-            R4 t[3];
-#pragma unroll
-            for (int a = 0; a < D; ++a) t[a] = my.tab[e][a][lc[a]];
-            R wv[NA];
-#pragma unroll
-            for (int k = 0; k < NA; ++k) wv[k] = my.wts[e][k];
-#pragma unroll
-            for (int b = 0; b < NSB; ++b) {
-                const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-                if (mk & (1 << b)) {
-                    R s = (bx ? t[0].z : t[0].x) + (by ? t[1].z : t[1].x);
-                    R ew = (bx ? t[0].w : t[0].y) * (by ? t[1].w : t[1].y);
-                    if (D == 3) {
-                        s = s + (bz ? t[2].z : t[2].x);
-                        ew = ew * (bz ? t[2].w : t[2].y);
-                    }
-                    bool in = s <= c2;
-                    ew = in ? ew : (R)0;
-#pragma unroll
-                    for (int k = 0; k < NA; ++k) part[b][k] = fma(ew, wv[k], part[b][k]);
-                    if (COUNT) npairs += in ? 1ull : 0ull;
-                }
+        // every lane keeps the masks of one staged record (read with readlane,
+        // no LDS round trip); the factors of the next record are loaded into
+        // the other register set while the current one is accumulated
+        const int maskv = (lane < n) ? my.mask[lane] : 0;
+        // one sub-block of one record: the per-pair inclusion test, then the
+        // C + 1 multiply-adds
+        auto sub = [&](int b, const R4* t, const R* wv) {
+            const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+            R s = (bx ? t[0].z : t[0].x) + (by ? t[1].z : t[1].x);
+            R ew = (bx ? t[0].w : t[0].y) * (by ? t[1].w : t[1].y);
+            if (D == 3) {
+                s = s + (bz ? t[2].z : t[2].x);
+                ew = ew * (bz ? t[2].w : t[2].y);
             }
+            bool in = s <= c2;
+            ew = in ? ew : (R)0;
+#pragma unroll
+            for (int k = 0; k < NA; ++k) part[b][k] = fma(ew, wv[k], part[b][k]);
+            if (COUNT) npairs += in ? 1ull : 0ull;
+        };
+        // PLAN sets the granularity of the wave-uniform skips: 0 one branch per
+        // sub-block, 1 per pair of sub-blocks along the last axis, 2 per half
+        // tile, 3 none (every sub-block evaluated, masked by the pair test).
+        // All plans add the same products; a skipped sub-block only saves
+        // additions of zero.
+        auto accumulate = [&](int e, const R4* t, const R* wv) {
+            const int mk = __builtin_amdgcn_readlane(maskv, e);
+            if (mk == 0) return;
+            if (PLAN == 3 || (D == 2 && PLAN != 0)) {
+#pragma unroll
+                for (int b = 0; b < NSB; ++b) sub(b, t, wv);
+            } else if (PLAN == 2) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    if (mk & (0x0F << (4 * h))) {
+#pragma unroll
+                        for (int b = 4 * h; b < 4 * h + 4; ++b) sub(b, t, wv);
+                    }
+            } else if (PLAN == 1) {
+#pragma unroll
+                for (int q = 0; q < NSB / 2; ++q)
+                    if (mk & (((1 << (NSB / 2)) | 1) << q)) {
+                        sub(q, t, wv);
+                        sub(q + NSB / 2, t, wv);
+                    }
+            } else {
+#pragma unroll
+                for (int b = 0; b < NSB; ++b)
+                    if (mk & (1 << b)) sub(b, t, wv);
+            }
+        };
+        R4 tA[3], tB[3];
+        R wA[NA], wB[NA];
+#pragma unroll
+        for (int a = 0; a < D; ++a) tA[a] = my.tab[0][a][lc[a]];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) wA[k] = my.wts[0][k];
+        for (int e = 0; e < n; e += 2) {
+            if (e + 1 < n) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) tB[a] = my.tab[e + 1][a][lc[a]];
+#pragma unroll
+                for (int k = 0; k < NA; ++k) wB[k] = my.wts[e + 1][k];
+            }
+            accumulate(e, tA, wA);
+            if (e + 1 >= n) break;
+            if (e + 2 < n) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) tA[a] = my.tab[e + 2][a][lc[a]];
+#pragma unroll
+                for (int k = 0; k < NA; ++k) wA[k] = my.wts[e + 2][k];
+            }
+            accumulate(e + 1, tB, wB);
         }
         if (kComp) {
 #pragma unroll
@@ -282,12 +340,20 @@ __global__ __launch_bounds__(kWave * kGatherWaves) void k_gather(GatherArgs g)
                 for (int q = 0; q < nruns; ++q) {
                     const uint32_t s0 = g.bstart[rowb + runs[q][0]];
                     const uint32_t s1 = g.bstart[rowb + runs[q][1] + 1];
-                    for (uint32_t base = s0; base < s1; base += kWave) {
-                        if ((chunk++ % kGatherWaves) != (uint32_t)wave) continue;
+                    // this wave's chunks of the run: base0, base0 + 4*64, ...
+                    const uint32_t nch = (s1 - s0 + kWave - 1) / kWave;
+                    const uint32_t first = (uint32_t)((wave - (int)(chunk % kGatherWaves) + kGatherWaves) % kGatherWaves);
+                    chunk += nch;
+                    double4 Pn = make_double4(0, 0, 0, 0);
+                    if (first < nch && s0 + first * kWave + lane < s1) Pn = g.rpos[s0 + first * kWave + lane];
+                    for (uint32_t c = first; c < nch; c += kGatherWaves) {
+                        const uint32_t base = s0 + c * kWave;
                         uint32_t p = base + lane;
+                        double4 P = Pn;
+                        const uint32_t pn = base + kGatherWaves * kWave + lane;
+                        if (pn < s1) Pn = g.rpos[pn];
                         bool ok = false;
                         if (p < s1) {
-                            double4 P = g.rpos[p];
                             double x[3] = {P.x, P.y, P.z};
                             if (P.w < 0.0) {
                                 ok = true;
@@ -374,27 +440,38 @@ __global__ __launch_bounds__(kWave * kGatherWaves) void k_gather(GatherArgs g)
     }
 }
 
+template <typename R, int D, int MODE, bool COUNT>
+static void launch_plan(const GatherArgs& g, int plan, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (plan) {
+    case 1: hipLaunchKernelGGL((k_gather<R, D, MODE, COUNT, 1>), grid, block, 0, s, g); break;
+    case 2: hipLaunchKernelGGL((k_gather<R, D, MODE, COUNT, 2>), grid, block, 0, s, g); break;
+    case 3: hipLaunchKernelGGL((k_gather<R, D, MODE, COUNT, 3>), grid, block, 0, s, g); break;
+    default: hipLaunchKernelGGL((k_gather<R, D, MODE, COUNT, 0>), grid, block, 0, s, g); break;
+    }
+}
+
 template <typename R, int D>
-hipError_t launch_gather(const GatherArgs& g, int mode, bool count, hipStream_t s)
+hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hipStream_t s)
 {
     dim3 grid((unsigned)g.m.ntiles), block(kWave * kGatherWaves);
     if (mode == FLA_NW) {
         if (count)
-            hipLaunchKernelGGL((k_gather<R, D, FLA_NW, true>), grid, block, 0, s, g);
+            launch_plan<R, D, FLA_NW, true>(g, plan, grid, block, s);
         else
-            hipLaunchKernelGGL((k_gather<R, D, FLA_NW, false>), grid, block, 0, s, g);
+            launch_plan<R, D, FLA_NW, false>(g, plan, grid, block, s);
     } else {
         if (count)
-            hipLaunchKernelGGL((k_gather<R, D, FLA_DEPOSIT, true>), grid, block, 0, s, g);
+            launch_plan<R, D, FLA_DEPOSIT, true>(g, plan, grid, block, s);
         else
-            hipLaunchKernelGGL((k_gather<R, D, FLA_DEPOSIT, false>), grid, block, 0, s, g);
+            launch_plan<R, D, FLA_DEPOSIT, false>(g, plan, grid, block, s);
     }
     return hipGetLastError();
 }
 
-template hipError_t launch_gather<float, 2>(const GatherArgs&, int, bool, hipStream_t);
-template hipError_t launch_gather<float, 3>(const GatherArgs&, int, bool, hipStream_t);
-template hipError_t launch_gather<double, 2>(const GatherArgs&, int, bool, hipStream_t);
-template hipError_t launch_gather<double, 3>(const GatherArgs&, int, bool, hipStream_t);
+template hipError_t launch_gather<float, 2>(const GatherArgs&, int, bool, int, hipStream_t);
+template hipError_t launch_gather<float, 3>(const GatherArgs&, int, bool, int, hipStream_t);
+template hipError_t launch_gather<double, 2>(const GatherArgs&, int, bool, int, hipStream_t);
+template hipError_t launch_gather<double, 3>(const GatherArgs&, int, bool, int, hipStream_t);
 
 }  // namespace flp

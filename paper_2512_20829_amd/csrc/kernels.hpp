@@ -27,6 +27,7 @@ hipError_t launch_prepass(const TrajDev& t, const MeshDev& m, const PhysDev& ph,
 
 hipError_t launch_bucket_bounds(const uint32_t* keys, int64_t n, uint32_t nb, uint32_t* bstart,
                                 hipStream_t s);
+hipError_t launch_max_class(const uint32_t* bstart, int ntiles, unsigned long long* stats, hipStream_t s);
 
 template <typename R>
 hipError_t launch_permute(const uint32_t* order, int64_t n, const double4* rpos_u, const R* rw_u,
@@ -37,8 +38,9 @@ hipError_t launch_deposit_norm(const MeshDev& m, const PhysDev& ph, const uint32
                                const uint32_t* order, const double* qd, int64_t N, double4* rpos, R* rw,
                                unsigned long long* stats, hipStream_t s);
 
+constexpr int kGatherPlans = 4;
 template <typename R, int D>
-hipError_t launch_gather(const GatherArgs& g, int mode, bool count, hipStream_t s);
+hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hipStream_t s);
 
 // PSI-CELL
 struct PsiArgs {
@@ -49,12 +51,32 @@ struct PsiArgs {
     const void* cell_scale;
     void* out[4];
     void* den;
-    unsigned long long* acc;     // C x M fixed-point sums
-    unsigned int* counts;        // M
     unsigned long long* maxbits; // C: bit patterns of max |phi_k| (binary64)
     double* qscale;              // C: 2^e_k
     unsigned long long* stats;
+    // tile buckets
+    int pt[3];                   // tile edge per axis (cells)
+    int pnt[3];                  // tiles per axis
+    int pntiles;
+    int cpt;                     // cells per tile
+    int nblocks;                 // blocks of the count / scatter passes
+    int* codes;                  // per particle: tile * cpt + cell in tile, or -1
+    unsigned int* blockhist;     // pntiles * nblocks + 1, scanned in place
+    void* bucket;                // bucketed records: R phi[4] then uint32 cell-in-tile
+    unsigned long long* blockmax; // nblocks x C bit patterns of per-block max |phi_k|
+    uint32_t* scan_tmp;
+    int64_t scan_words;
 };
+
+// One bucketed PSI-CELL particle, written and read as one contiguous record.
+template <typename R> struct PsiRec {
+    R phi[4];
+    uint32_t loc;
+};
+
+constexpr int kPsiMaxTiles = 16384;   // LDS histogram of the count/scatter passes <= 64 KiB
+constexpr int kPsiMaxCellsPerTile = 1024;  // LDS sums of the reduce pass <= 36 KiB
+constexpr int kPsiBlocks = 1024;
 
 template <typename R, int D>
 hipError_t launch_psicell(const PsiArgs& a, hipStream_t s);

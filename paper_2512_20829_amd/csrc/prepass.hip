@@ -28,7 +28,6 @@ __global__ __launch_bounds__(256) void k_prepass(TrajDev t, MeshDev m, PhysDev p
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t sentinel = (uint32_t)kClasses * (uint32_t)m.ntiles;
     unsigned long long skipped = 0, nosup = 0;
-    int cls_used = -1;
     if (i < N) {
         double x[3] = {0, 0, 0}, J[9], v[3], ug[3];
         bool ok = true;
@@ -123,7 +122,6 @@ __global__ __launch_bounds__(256) void k_prepass(TrajDev t, MeshDev m, PhysDev p
             if (!support) nosup = 1;
             if (support || deposit) {
                 int cls = !support ? 0 : (reach < kClasses - 1 ? reach : kClasses - 1);
-                cls_used = cls;
                 int64_t tl = ht[0] + (int64_t)m.nt[0] * (ht[1] + (int64_t)m.nt[1] * ht[2]);
                 key = (uint32_t)cls * (uint32_t)m.ntiles + (uint32_t)tl;
             }
@@ -144,13 +142,16 @@ __global__ __launch_bounds__(256) void k_prepass(TrajDev t, MeshDev m, PhysDev p
     }
     block_add_stats(stats, ST_SKIPPED, skipped);
     block_add_stats(stats, ST_NOSUPPORT, nosup);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        int other = __shfl_xor(cls_used, o, kWave);
-        cls_used = other > cls_used ? other : cls_used;
-    }
-    if ((threadIdx.x % kWave) == 0 && cls_used >= 0)
-        atomicMax(&stats[ST_MAXCLASS], (unsigned long long)cls_used);
+}
+
+// Largest non-empty neighbourhood class, read off the bucket bounds.
+__global__ void k_max_class(const uint32_t* bstart, int ntiles, unsigned long long* stats)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    unsigned long long mc = 0;
+    for (int k = 0; k < kClasses; ++k)
+        if (bstart[(int64_t)k * ntiles] != bstart[(int64_t)(k + 1) * ntiles]) mc = (unsigned long long)k;
+    stats[ST_MAXCLASS] = mc;
 }
 
 // Bucket starts from sorted keys: bstart[b] = first position with key >= b
@@ -299,6 +300,12 @@ hipError_t launch_bucket_bounds(const uint32_t* keys, int64_t n, uint32_t nb, ui
 {
     unsigned g = (unsigned)(((int64_t)nb + 1 + 255) / 256);
     hipLaunchKernelGGL(k_bucket_bounds, dim3(g), dim3(256), 0, s, keys, n, nb, bstart);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_class(const uint32_t* bstart, int ntiles, unsigned long long* stats, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_max_class, dim3(1), dim3(64), 0, s, bstart, ntiles, stats);
     return hipGetLastError();
 }
 

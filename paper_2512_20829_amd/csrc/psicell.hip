@@ -1,13 +1,23 @@
 // PSI-CELL box counting (eqs. vol-avg-discrete and coupling-terms-definition)
 // and small fill kernels.
 //
-// The sum over the particles of a cell is made order-independent by exact
-// integer arithmetic: a first pass finds max |phi_k| per channel, each phi is
-// then quantised to a multiple of 2^-e_k with e_k chosen so that
-// count * max|phi_k| * 2^e_k <= 2^62 (no partial sum can overflow int64),
-// and the integers are added with 64-bit atomics.  The quantisation error of
-// one particle is at most 2^-(e_k+1), i.e. relative to the largest |phi|
-// about count * 2^-63.  One HBM pass for the bound plus one for the sums.
+// The per-cell sums are made order-independent by exact integer arithmetic:
+// each phi_k is quantised to a multiple of 2^-e_k, e_k chosen from the
+// largest |phi_k| so that count * max|phi_k| * 2^e_k < 2^62 (no partial sum
+// can overflow int64), and the integers are added.  The quantisation error of
+// one particle is at most 2^-(e_k+1).
+//
+// Particles arrive in arbitrary spatial order, so the sums are not formed by
+// global atomics (one contended 64-bit atomic per particle and channel) but
+// in three streaming passes over coarse tiles of cells:
+//   count   per particle: validity and (tile, cell in tile) code; per-block
+//           tile histograms in LDS, written tile-major for an exclusive scan
+//           that yields every (tile, block) output range;
+//   scatter per particle: phi, the per-channel max |phi|, and the record
+//           (cell in tile, phi) appended to its tile bucket (slot from an LDS
+//           cursor; the order inside a bucket does not matter);
+//   reduce  one workgroup per tile: quantise and add in LDS (integer atomics),
+//           then scale by -w/V_c and write the tile's cells.
 #include "internal.hpp"
 #include "kernels.hpp"
 
@@ -50,36 +60,108 @@ __device__ inline bool psi_particle(const PsiArgs& a, int64_t p, int64_t& cell, 
     return true;
 }
 
-template <typename R, int D>
-__global__ __launch_bounds__(256) void k_psi_bound(PsiArgs a)
+// (tile, cell-in-tile) code of a valid particle, -1 otherwise
+template <int D>
+__device__ inline int64_t psi_code(const PsiArgs& a, int64_t cell)
 {
-    constexpr int C = D + 1;
-    double mx[C];
+    const MeshDev& m = a.m;
+    int64_t idx[3];
+    idx[0] = cell % m.n[0];
+    int64_t r = cell / m.n[0];
+    idx[1] = r % m.n[1];
+    idx[2] = (D == 3) ? r / m.n[1] : 0;
+    int64_t tile = 0, loc = 0, ts = 1, ls = 1;
 #pragma unroll
-    for (int k = 0; k < C; ++k) mx[k] = 0.0;
+    for (int ax = 0; ax < D; ++ax) {
+        tile += (idx[ax] / a.pt[ax]) * ts;
+        ts *= a.pnt[ax];
+        loc += (idx[ax] % a.pt[ax]) * ls;
+        ls *= a.pt[ax];
+    }
+    return tile * a.cpt + loc;
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_psi_count(PsiArgs a)
+{
+    extern __shared__ unsigned int hist[];
+    const int ntl = a.pntiles;
+    for (int t = threadIdx.x; t < ntl; t += blockDim.x) hist[t] = 0;
+    __syncthreads();
+    const int64_t N = a.p.count;
+    const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = beg + chunk < N ? beg + chunk : N;
     unsigned long long outside = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.p.count; p += stride) {
+    for (int64_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
         int64_t c;
         double phi[4];
+        int64_t code = -1;
         if (psi_particle<R, D>(a, p, c, phi)) {
-#pragma unroll
-            for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], fabs(phi[k]));
+            code = psi_code<D>(a, c);
+            atomicAdd(&hist[code / a.cpt], 1u);
         } else {
             ++outside;
         }
+        a.codes[p] = (int)code;
     }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntl; t += blockDim.x) a.blockhist[(int64_t)t * gridDim.x + blockIdx.x] = hist[t];
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.blockhist[(int64_t)ntl * gridDim.x] = 0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        outside += __shfl_xor(outside, o, kWave);
+    for (int o = 32; o > 0; o >>= 1) outside += __shfl_xor(outside, o, kWave);
+    if ((threadIdx.x % kWave) == 0 && outside) atomicAdd(&a.stats[ST_OUTSIDE], outside);
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
+{
+    constexpr int C = D + 1;
+    extern __shared__ unsigned int cursor[];
+    const int ntl = a.pntiles;
+    for (int t = threadIdx.x; t < ntl; t += blockDim.x) cursor[t] = a.blockhist[(int64_t)t * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const int64_t N = a.p.count;
+    const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = beg + chunk < N ? beg + chunk : N;
+    PsiRec<R>* bucket = (PsiRec<R>*)a.bucket;
+    double mx[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) mx[k] = 0.0;
+    for (int64_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
+        int code = a.codes[p];
+        if (code < 0) continue;
+        double v[3], ug[3], phi[4];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            v[ax] = (double)((const R*)a.p.v[ax])[p];
+            ug[ax] = (double)((const R*)a.p.ug[ax])[p];
+        }
+        droplet_phi<D>((double)((const R*)a.p.r)[p], v, ug, a.ph, phi);
+        unsigned int slot = atomicAdd(&cursor[code / a.cpt], 1u);
+        PsiRec<R> rec;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) rec.phi[k] = (k < C) ? (R)phi[k] : (R)0;
+        rec.loc = (uint32_t)(code % a.cpt);
+        bucket[slot] = rec;
+#pragma unroll
+        for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], fabs((double)rec.phi[k]));
+    }
+    // per-block maxima (a separate pass reduces them: no contended atomics)
+    __shared__ double bm[256 / kWave][4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
         for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], __shfl_xor(mx[k], o, kWave));
-    }
-    if ((threadIdx.x % kWave) == 0) {
-        if (outside) atomicAdd(&a.stats[ST_OUTSIDE], outside);
+    if ((threadIdx.x % kWave) == 0)
 #pragma unroll
-        for (int k = 0; k < C; ++k)
-            if (mx[k] > 0.0) atomicMax(&a.maxbits[k], (unsigned long long)__double_as_longlong(mx[k]));
+        for (int k = 0; k < C; ++k) bm[threadIdx.x / kWave][k] = mx[k];
+    __syncthreads();
+    if (threadIdx.x < C) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) v = fmax(v, bm[w][threadIdx.x]);
+        a.blockmax[(int64_t)blockIdx.x * 4 + threadIdx.x] = (unsigned long long)__double_as_longlong(v);
     }
 }
 
@@ -87,6 +169,18 @@ template <int D>
 __global__ void k_psi_scale(PsiArgs a)
 {
     constexpr int C = D + 1;
+    // max over the per-block maxima: one wave per channel
+    const int lane = threadIdx.x % kWave;
+    for (int k = threadIdx.x / kWave; k < C; k += blockDim.x / kWave) {
+        double v = 0.0;
+        if (a.p.count > 0)
+            for (int b = lane; b < a.nblocks; b += kWave)
+                v = fmax(v, __longlong_as_double((long long)a.blockmax[(int64_t)b * 4 + k]));
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+        if (lane == 0) a.maxbits[k] = (unsigned long long)__double_as_longlong(v);
+    }
+    __syncthreads();
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double n = (double)(a.p.count > 0 ? a.p.count : 1);
     for (int k = 0; k < C; ++k) {
@@ -102,43 +196,60 @@ __global__ void k_psi_scale(PsiArgs a)
     }
 }
 
+// One workgroup per tile: exact integer sums in LDS, then the tile's cells.
 template <typename R, int D>
-__global__ __launch_bounds__(256) void k_psi_accum(PsiArgs a)
+__global__ __launch_bounds__(256) void k_psi_reduce(PsiArgs a)
 {
     constexpr int C = D + 1;
-    const int64_t M = a.m.M;
+    extern __shared__ unsigned long long sacc[];    // C * cpt sums, then cpt counts (u32)
+    const int cpt = a.cpt;
+    unsigned int* scnt = reinterpret_cast<unsigned int*>(sacc + (size_t)C * cpt);
+    for (int i = threadIdx.x; i < C * cpt; i += blockDim.x) sacc[i] = 0ull;
+    for (int i = threadIdx.x; i < cpt; i += blockDim.x) scnt[i] = 0u;
     double qs[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) qs[k] = a.qscale[k];
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.p.count; p += stride) {
-        int64_t c;
-        double phi[4];
-        if (!psi_particle<R, D>(a, p, c, phi)) continue;
+    __syncthreads();
+    const int tile = blockIdx.x;
+    const int64_t nbk = a.nblocks;
+    const int64_t beg = a.blockhist[(int64_t)tile * nbk];
+    const int64_t end = a.blockhist[(int64_t)(tile + 1) * nbk];
+    const PsiRec<R>* bucket = (const PsiRec<R>*)a.bucket;
+    for (int64_t sl = beg + threadIdx.x; sl < end; sl += blockDim.x) {
+        PsiRec<R> rec = bucket[sl];
+        int loc = (int)rec.loc;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            long long qv = llrint(phi[k] * qs[k]);
-            atomicAdd(&a.acc[(int64_t)k * M + c], (unsigned long long)qv);
+            long long qv = llrint((double)rec.phi[k] * qs[k]);
+            atomicAdd(&sacc[k * cpt + loc], (unsigned long long)qv);
         }
-        atomicAdd(&a.counts[c], 1u);
+        atomicAdd(&scnt[loc], 1u);
     }
-}
-
-template <typename R, int D>
-__global__ __launch_bounds__(256) void k_psi_finalize(PsiArgs a)
-{
-    constexpr int C = D + 1;
-    const int64_t M = a.m.M;
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= M) return;
-    double cs = a.cell_scale ? (double)((const R*)a.cell_scale)[c] : 1.0;
-    double f = -(a.weight / a.m.vol) * cs;
+    __syncthreads();
+    const MeshDev& m = a.m;
+    int tc[3];
+    tc[0] = tile % a.pnt[0];
+    tc[1] = (tile / a.pnt[0]) % a.pnt[1];
+    tc[2] = (D == 3) ? tile / (a.pnt[0] * a.pnt[1]) : 0;
+    const double fw = -(a.weight / m.vol);
+    for (int loc = threadIdx.x; loc < cpt; loc += blockDim.x) {
+        int l0 = loc % a.pt[0];
+        int l1 = (loc / a.pt[0]) % a.pt[1];
+        int l2 = (D == 3) ? loc / (a.pt[0] * a.pt[1]) : 0;
+        int64_t i0 = (int64_t)tc[0] * a.pt[0] + l0;
+        int64_t i1 = (int64_t)tc[1] * a.pt[1] + l1;
+        int64_t i2 = (int64_t)tc[2] * a.pt[2] + l2;
+        if (i0 >= m.n[0] || i1 >= m.n[1] || (D == 3 && i2 >= m.n[2])) continue;
+        int64_t c = i0 + (int64_t)m.n[0] * (i1 + (int64_t)m.n[1] * i2);
+        double cs = a.cell_scale ? (double)((const R*)a.cell_scale)[c] : 1.0;
+        double f = fw * cs;
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-        double sum = (double)(long long)a.acc[(int64_t)k * M + c] / a.qscale[k];
-        ((R*)a.out[k])[c] = (R)(f * sum);
+        for (int k = 0; k < C; ++k) {
+            double sum = (double)(long long)sacc[k * cpt + loc] / qs[k];
+            ((R*)a.out[k])[c] = (R)(f * sum);
+        }
+        if (a.den) ((R*)a.den)[c] = (R)scnt[loc];
     }
-    if (a.den) ((R*)a.den)[c] = (R)a.counts[c];
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
@@ -192,18 +303,22 @@ template <typename R, int D>
 hipError_t launch_psicell(const PsiArgs& a, hipStream_t s)
 {
     constexpr int C = D + 1;
-    hipError_t e = launch_fill_u64(a.acc, (int64_t)C * a.m.M, 0ull, s);
-    if (e == hipSuccess) e = launch_fill_u32(a.counts, a.m.M, 0u, s);
-    if (e == hipSuccess) e = launch_fill_u64(a.maxbits, C, 0ull, s);
+    hipError_t e = launch_fill_u64(a.maxbits, C, 0ull, s);
     if (e != hipSuccess) return e;
-    // enough waves to stream HBM: 8 blocks of 256 per CU
-    unsigned g = grid_for(a.p.count);
-    if (g > 2048) g = 2048;
-    hipLaunchKernelGGL((k_psi_bound<R, D>), dim3(g), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_psi_scale<D>), dim3(1), dim3(64), 0, s, a);
-    hipLaunchKernelGGL((k_psi_accum<R, D>), dim3(g), dim3(256), 0, s, a);
-    unsigned gm = (unsigned)((a.m.M + 255) / 256);
-    hipLaunchKernelGGL((k_psi_finalize<R, D>), dim3(gm), dim3(256), 0, s, a);
+    if (a.p.count == 0) {
+        // no particle: every tile reduces an empty bucket
+        e = launch_fill_u32(a.blockhist, (int64_t)a.pntiles * a.nblocks + 1, 0u, s);
+        if (e != hipSuccess) return e;
+    } else {
+        size_t lds_t = sizeof(unsigned int) * (size_t)a.pntiles;
+        hipLaunchKernelGGL((k_psi_count<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
+        e = launch_exclusive_scan_u32(a.blockhist, (int64_t)a.pntiles * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_psi_scatter<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
+    }
+    hipLaunchKernelGGL((k_psi_scale<D>), dim3(1), dim3(256), 0, s, a);
+    size_t lds_r = (sizeof(unsigned long long) * C + sizeof(unsigned int)) * (size_t)a.cpt;
+    hipLaunchKernelGGL((k_psi_reduce<R, D>), dim3(a.pntiles), dim3(256), lds_r, s, a);
     return hipGetLastError();
 }
 
