@@ -46,6 +46,28 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def gather_traffic():
+    """HBM bytes per gather launch from the committed counter summary, or None
+    when the gather source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gather_c2_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2512_20829_amd", "csrc", "gather.hip")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("gather.hip sha256[:16]") != digest:
+        return None
+    try:
+        return float(vals["bytes per launch (calibrated)"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(seconds: float):
     """FP64 oracle, brute force per cell, on a random sample of cells of the
     same workload; full-field time extrapolated from the sample."""
@@ -94,6 +116,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psicell", action="store_true")
     ap.add_argument("--psicell-particles", type=int, default=200_000_000)
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build targets a single GPU; the projection of one snapshot runs on one "
@@ -148,14 +172,7 @@ def main():
     log(f"{ms_step:.3f} ms/step; stages (ms/launch): {stages}")
 
     achieved = P * FLOPS_PER_PAIR_3D / (g_ms * 1e-3) / 1e12
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "gather_c2_traffic.json")
-    if os.path.exists(tpath):
-        try:
-            with open(tpath) as fh:
-                traffic = json.load(fh).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = gather_traffic()
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_gather<float,3,NW>", "launch_ms": round(g_ms, 4),
@@ -224,6 +241,13 @@ def main():
         "psicell": psi,
     }
     print(json.dumps(out), flush=True)
+    if args.calibration_copy_mib > 0:
+        n = args.calibration_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calibration_copy_mib} MiB done")
     ctx.close()
 
 

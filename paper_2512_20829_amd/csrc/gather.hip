@@ -45,7 +45,9 @@ __device__ inline void two_sum_acc(R& hi, R& lo, R p)
     lo += err;
 }
 
-constexpr int kGatherWaves = 4;     // waves per workgroup; all work on one tile
+// waves per workgroup (all work on one tile): four in 3-D; two in 2-D, whose
+// tiles have twice the cells per axis and whose staging tables are larger
+template <int D> struct GatherWaves { static constexpr int value = D == 3 ? 4 : 2; };
 
 template <typename R, int D>
 struct GatherLds {
@@ -58,8 +60,9 @@ struct GatherLds {
 };
 
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
-__global__ __launch_bounds__(kWave * kGatherWaves) void k_gather(GatherArgs g)
+__global__ __launch_bounds__(kWave * GatherWaves<D>::value, 2) void k_gather(GatherArgs g)
 {
+    constexpr int kGatherWaves = GatherWaves<D>::value;
     using G = Geo<D>;
     constexpr int TE = G::TE, SB = G::SB, NSB = G::NSB, C = D + 1, NA = C + 1;
     constexpr bool kComp = sizeof(R) == 4;
@@ -454,7 +457,7 @@ static void launch_plan(const GatherArgs& g, int plan, dim3 grid, dim3 block, hi
 template <typename R, int D>
 hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hipStream_t s)
 {
-    dim3 grid((unsigned)g.m.ntiles), block(kWave * kGatherWaves);
+    dim3 grid((unsigned)g.m.ntiles), block(kWave * GatherWaves<D>::value);
     if (mode == FLA_NW) {
         if (count)
             launch_plan<R, D, FLA_NW, true>(g, plan, grid, block, s);

@@ -190,3 +190,36 @@ def test_psicell_deterministic(ctx):
     S1, _, _ = gpu_run(ctx, wl, prec="f32", psicell_cloud=cloud, weight=1.0)
     S2, _, _ = gpu_run(ctx, wl, prec="f32", psicell_cloud=cloud, weight=1.0)
     assert np.array_equal(S1, S2)
+
+
+# ------------------------------------------------------------------ plans / autotuner
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_every_gather_plan_gives_the_same_values(ctx, prec):
+    import paper_2512_20829_amd as F
+    wl = W.small_random_3d(6000, 30, seed=15)
+    outs = []
+    for plan in range(4):
+        ctx.set_plan(3, F.FLA_F64 if prec == "f64" else F.FLA_F32, plan)
+        S, den, st = gpu_run(ctx, wl, prec=prec)
+        outs.append((S, den, st["pairs"]))
+    ctx.set_plan(3, F.FLA_F64 if prec == "f64" else F.FLA_F32, -1)
+    for S, den, P in outs[1:]:
+        assert np.array_equal(S, outs[0][0]) and np.array_equal(den, outs[0][1]) and P == outs[0][2]
+    ref, _ = oracle_run(wl, prec=prec)
+    assert_fields_close(outs[0][0], ref.S, TOL[prec], "plans")
+
+
+def test_autotune_picks_a_plan(ctx):
+    import paper_2512_20829_amd as F
+    wl = W.small_random_3d(20000, 32, seed=16)
+    dev = torch.device("cuda", 0)
+    tr = wl.traj
+    st, keep = F.make_trajectories(tr.x.to(dev), tr.J.to(dev), tr.v.to(dev, torch.float32),
+                                   tr.ug.to(dev, torch.float32), tr.r.to(dev, torch.float32), tr.n0,
+                                   tr.seed_volume)
+    S, Sm, den = F.alloc_fields(wl.mesh.cells, 3, torch.float32, dev)
+    p = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
+    times = ctx.autotune(F.mesh_of(wl.mesh), st, p, S, Sm, den)
+    assert all(t > 0 for t in times)
+    assert ctx.get_plan(3, F.FLA_F32) == int(np.argmin(times))
+    ctx.set_plan(3, F.FLA_F32, -1)
