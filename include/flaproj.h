@@ -198,7 +198,8 @@ fla_status fla_get_stats(fla_ctx* ctx, fla_stats* out);
  * synchronises the device and returns, per stage, the summed elapsed time
  * and the number of timed launches since profiling was enabled.  Stages:
  * 0 prepass, 1 key sort + bucket bounds + record permutation, 2 deposition
- * normaliser, 3 gather with fused epilogue, 4 PSI-CELL accumulation.
+ * normaliser, 3 gather with fused epilogue, 4 PSI-CELL accumulation,
+ * 5 bandwidth network forward, 6 estimator backward, 7 network backward.
  * Errors: INVALID_ARG for NULL, DEVICE. */
 #define FLA_PROFILE_STAGES 8
 typedef struct {
@@ -229,6 +230,67 @@ fla_status fla_get_plan(fla_ctx* ctx, int dim, int prec, int* gather_plan);
 fla_status fla_autotune(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
                         const fla_params* params, const fla_fields* out, void* stream,
                         double* times_ms);
+
+/* ---------------------------------------------------------------------------
+ * Learned bandwidth correction.  A 5-64-64-1 network (SiLU hidden layers)
+ * predicts a per-trajectory factor g_i = exp(ln4 * tanh o_i) multiplying the
+ * smoothing length h_i = h0 |det J_i| of eq. (smoothing-length).  Its inputs
+ * are z = (f - mu)/sd for the features
+ *   f = [log s1, log s2, log s3, log(n/n0) = -log|det J|, log(1 + N_nbr)]
+ * (s_k the singular values of J, largest first, s3 = 1 in 2-D; N_nbr the
+ * valid trajectories whose home cell is in the 3^d block of cells around the
+ * trajectory's home cell).  Weights are held as an FP32 parameter block of
+ * FLA_MLP_PARAMS floats (device):
+ *   W1[64][5], b1[64], W2[64][64], b2[64], w3[64], b3   (trainable, 4609)
+ *   mu[5], sd[5]                                         (standardisation)
+ * The network runs on bf16 MFMA with FP32 accumulation: z, the first hidden
+ * layer and W1, W2, w3 are rounded to bf16; biases stay FP32.
+ * ------------------------------------------------------------------------- */
+#define FLA_MLP_TRAINABLE 4609
+#define FLA_MLP_PARAMS 4619
+
+/* Features and network.  theta: device parameter block.  h_factor (device,
+ * count floats, required) receives g_i (1 for skipped trajectories); z
+ * (5*count, plane k = input k), o (count) and features (5*count, raw f)
+ * are optional device outputs (the backward needs z and o).  The result
+ * feeds fla_params.h_factor.  Errors as fla_project_sources. */
+fla_status fla_bandwidth_forward(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                                 const float* theta, float* h_factor, float* z, float* o,
+                                 float* features, void* stream);
+
+/* Gradient through the estimator: given the fields S (S_mass, S_mom and
+ * den, all required) of an FLA_NW projection with these same inputs and
+ * params (h_factor included), and dL/dS (same layout; den ignored), writes
+ *   dL_dlogh[i] = h_i dL/dh_i = sum_c K_ci (s_ci - 1) a_c (sum_k g_kc q_ik - sum_k g_kc S~_kc),
+ * K the kernel, s = |x_c - x_i|^2/h_i^2, g = dL/dS, a_c = -scale cs_c/den_c
+ * and S~ = S/(-scale cs) the unsigned estimate, summed over the included
+ * pairs (device, count floats; 0 for skipped trajectories).  The movement of
+ * the truncation radius with h is not differentiated (its term is of the
+ * order of the kernel tail, exp(-cutoff^2/2)).  Errors as fla_project_sources. */
+fla_status fla_project_backward(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                                const fla_params* params, const fla_fields* S, const fla_fields* dL_dS,
+                                float* dL_dlogh, void* stream);
+
+/* Network backward: with z and o from fla_bandwidth_forward and dL/dlog h
+ * from fla_project_backward, writes dL/dtheta (device, FLA_MLP_PARAMS floats;
+ * zeros for mu, sd).  Partial sums per block are added in block order
+ * (deterministic).  dim is 2 or 3.  Errors: INVALID_ARG, DEVICE. */
+fla_status fla_bandwidth_backward(fla_ctx* ctx, int dim, const float* theta, int64_t count, const float* z,
+                                  const float* o, const float* dL_dlogh, float* grad, void* stream);
+
+/* One Adam step on the trainable entries of theta with moments m, v (all
+ * device, FLA_MLP_PARAMS floats); step counts from 1 (bias correction).
+ * Errors: INVALID_ARG, DEVICE. */
+fla_status fla_adam_step(fla_ctx* ctx, float* theta, float* m, float* v, const float* grad, int64_t step,
+                         double lr, double beta1, double beta2, double eps, void* stream);
+
+/* Relative-L2 loss over the channels (S_mass, S_mom[0..channels-2]):
+ *   L = sum_k |S_k - R_k|^2 / |R_k|^2
+ * result (device, 1 + 2*channels doubles): L, then |S_k - R_k|^2 and |R_k|^2
+ * per channel; dL_dS (nullable) receives 2 (S_k - R_k)/|R_k|^2.  Sums are
+ * formed in a fixed order (deterministic).  Errors: INVALID_ARG, DEVICE. */
+fla_status fla_rel_l2_loss(fla_ctx* ctx, int channels, int64_t cells, int prec, const fla_fields* S,
+                           const fla_fields* R, const fla_fields* dL_dS, double* result, void* stream);
 
 /* Message of the last error on ctx (host string owned by ctx, valid until
  * the next call on ctx); "" if the last call succeeded.  NULL ctx returns

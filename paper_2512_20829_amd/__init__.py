@@ -55,7 +55,10 @@ class fla_stats(C.Structure):
                 ("max_class", C.c_int64), ("reserved", C.c_int64)]
 
 
-PROFILE_STAGES = ["prepass", "sort", "deposit_norm", "gather", "psicell", "s5", "s6", "s7"]
+PROFILE_STAGES = ["prepass", "sort", "deposit_norm", "gather", "psicell", "mlp_forward", "proj_backward",
+                  "mlp_backward"]
+MLP_TRAINABLE = 4609
+MLP_PARAMS = 4619
 
 
 class fla_profile(C.Structure):
@@ -86,6 +89,19 @@ _lib.fla_get_plan.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_int)]
 _lib.fla_autotune.restype = C.c_int
 _lib.fla_autotune.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories), C.POINTER(fla_params),
                               C.POINTER(fla_fields), _vp, C.POINTER(C.c_double)]
+_lib.fla_bandwidth_forward.restype = C.c_int
+_lib.fla_bandwidth_forward.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories), _vp, _vp, _vp, _vp,
+                                       _vp, _vp]
+_lib.fla_project_backward.restype = C.c_int
+_lib.fla_project_backward.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories), C.POINTER(fla_params),
+                                      C.POINTER(fla_fields), C.POINTER(fla_fields), _vp, _vp]
+_lib.fla_bandwidth_backward.restype = C.c_int
+_lib.fla_bandwidth_backward.argtypes = [_vp, C.c_int, _vp, C.c_int64, _vp, _vp, _vp, _vp, _vp]
+_lib.fla_adam_step.restype = C.c_int
+_lib.fla_adam_step.argtypes = [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_double, _vp]
+_lib.fla_rel_l2_loss.restype = C.c_int
+_lib.fla_rel_l2_loss.argtypes = [_vp, C.c_int, C.c_int64, C.c_int, C.POINTER(fla_fields), C.POINTER(fla_fields),
+                                 C.POINTER(fla_fields), _vp, _vp]
 _lib.fla_last_error.restype = C.c_char_p
 _lib.fla_last_error.argtypes = [_vp]
 
@@ -285,6 +301,42 @@ class Context:
         self._check(_lib.fla_autotune(self._h, C.byref(mesh), C.byref(traj), C.byref(params.to_c()),
                                       C.byref(make_fields(S_mass, S_mom, den)), _stream_handle(stream), t))
         return [float(v) for v in t]
+
+    # -- learned bandwidth ------------------------------------------------------------
+    def bandwidth_forward(self, mesh: fla_mesh, traj: fla_trajectories, theta, h_factor, z=None, o=None,
+                          features=None, stream=None):
+        self._check(_lib.fla_bandwidth_forward(self._h, C.byref(mesh), C.byref(traj), _ptr(theta), _ptr(h_factor),
+                                               _ptr(z), _ptr(o), _ptr(features), _stream_handle(stream)))
+
+    def project_backward(self, mesh: fla_mesh, traj: fla_trajectories, params: Params, S_mass, S_mom, den,
+                         G_mass, G_mom, dL_dlogh, stream=None):
+        self._check(_lib.fla_project_backward(self._h, C.byref(mesh), C.byref(traj), C.byref(params.to_c()),
+                                              C.byref(make_fields(S_mass, S_mom, den)),
+                                              C.byref(make_fields(G_mass, G_mom)), _ptr(dL_dlogh),
+                                              _stream_handle(stream)))
+
+    def bandwidth_backward(self, dim: int, theta, count: int, z, o, dL_dlogh, grad, stream=None):
+        self._check(_lib.fla_bandwidth_backward(self._h, dim, _ptr(theta), int(count), _ptr(z), _ptr(o),
+                                                _ptr(dL_dlogh), _ptr(grad), _stream_handle(stream)))
+
+    def adam_step(self, theta, m, v, grad, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self._check(_lib.fla_adam_step(self._h, _ptr(theta), _ptr(m), _ptr(v), _ptr(grad), int(step), lr, beta1,
+                                       beta2, eps, _stream_handle(stream)))
+
+    def rel_l2_loss(self, channels: int, cells: int, prec: int, S: Sequence, R: Sequence, G: Sequence = None,
+                    result=None, stream=None):
+        """S, R, G: lists of channel planes (S_mass first).  result: float64 device tensor of
+        1 + 2*channels entries (allocated if None); returned."""
+        import torch
+        if result is None:
+            result = torch.empty(1 + 2 * channels, dtype=torch.float64, device=S[0].device)
+        fs = make_fields(S[0], S[1:])
+        fr = make_fields(R[0], R[1:])
+        fg = make_fields(G[0], G[1:]) if G is not None else None
+        self._check(_lib.fla_rel_l2_loss(self._h, channels, int(cells), prec, C.byref(fs), C.byref(fr),
+                                         C.byref(fg) if fg is not None else None, _ptr(result),
+                                         _stream_handle(stream)))
+        return result
 
     def stats(self) -> dict:
         s = fla_stats()

@@ -11,6 +11,7 @@
 #include "flaproj.h"
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "learned.hpp"
 
 using namespace flp;
 
@@ -372,6 +373,64 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
     return FLA_OK;
 }
 
+template <typename R, int D>
+fla_status bandwidth_forward_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const float* theta, float* hfac,
+                                  float* z, float* o, float* fraw, hipStream_t s)
+{
+    unsigned int* cnt;
+    {
+        Carver probe(nullptr);
+        probe.take<unsigned int>(m.M);
+        fla_status st = ensure_ws(ctx, probe.off + 256);
+        if (st != FLA_OK) return st;
+    }
+    Carver c(ctx->ws);
+    cnt = c.take<unsigned int>(m.M);
+    StageTimer tm(ctx, 5, s);
+    HIP_OK((launch_bandwidth_forward<R, D>(t, m, theta, cnt, hfac, z, o, fraw, s)));
+    return FLA_OK;
+}
+
+template <typename R, int D>
+fla_status project_backward_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const fla_params* p,
+                                 const fla_mesh* mesh, const fla_fields* S, const fla_fields* G, float* out,
+                                 hipStream_t s)
+{
+    const int64_t N = t.count;
+    const int C = D + 1;
+    uint32_t *keys, *vals;
+    double4* rpos;
+    R* rw;
+    float *bpl, *epl;
+    auto layout = [&](Carver& c) {
+        keys = c.take<uint32_t>(N > 0 ? N : 1);
+        vals = c.take<uint32_t>(N > 0 ? N : 1);
+        rpos = c.take<double4>(N > 0 ? N : 1);
+        rw = c.take<R>((size_t)(N > 0 ? N : 1) * kRecW);
+        bpl = c.take<float>((size_t)C * m.M);
+        epl = c.take<float>(m.M);
+    };
+    {
+        Carver probe(nullptr);
+        layout(probe);
+        fla_status st = ensure_ws(ctx, probe.off + 256);
+        if (st != FLA_OK) return st;
+    }
+    Carver c(ctx->ws);
+    layout(c);
+    PhysDev ph{p->rho_d, p->mu, p->delta, p->h0, p->cutoff, p->scale};
+    HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
+    StageTimer tm(ctx, 6, s);
+    if (N > 0)
+        HIP_OK((launch_prepass<R, D>(t, m, ph, p->h_factor, 0, keys, vals, rpos, rw, nullptr, ctx->stats, s)));
+    Planes Sp{{S->S_mass, S->S_mom[0], S->S_mom[1], S->S_mom[2]}};
+    Planes Gp{{G->S_mass, G->S_mom[0], G->S_mom[1], G->S_mom[2]}};
+    const uint32_t sentinel = (uint32_t)kClasses * (uint32_t)m.ntiles;
+    HIP_OK((launch_traj_backward<R, D>(m, p->cutoff, keys, sentinel, rpos, rw, Sp, S->den, Gp, p->scale,
+                                       mesh->cell_scale, bpl, epl, out, N, s)));
+    return FLA_OK;
+}
+
 fla_status check_params(fla_ctx* ctx, const fla_params* p, bool projection)
 {
     CHECK_ARG(p != nullptr, "params is NULL");
@@ -528,6 +587,151 @@ FLA_EXPORT fla_status fla_get_stats(fla_ctx* ctx, fla_stats* out)
     out->zero_support = (int64_t)h[ST_ZERO];
     out->max_class = (int64_t)h[ST_MAXCLASS];
     out->reserved = 0;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_bandwidth_forward(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                                            const float* theta, float* h_factor, float* z, float* o, float* features,
+                                            void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    try {
+        MeshDev m;
+        fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+        if (st != FLA_OK) return st;
+        TrajDev t;
+        st = check_traj(ctx, traj, m.dim, true, &t);
+        if (st != FLA_OK) return st;
+        CHECK_ARG(theta != nullptr, "theta is NULL");
+        CHECK_ARG(h_factor != nullptr || t.count == 0, "h_factor is NULL");
+        HIP_OK(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        bool f64 = traj->prec == FLA_F64;
+        if (m.dim == 2)
+            return f64 ? bandwidth_forward_impl<double, 2>(ctx, m, t, theta, h_factor, z, o, features, s)
+                       : bandwidth_forward_impl<float, 2>(ctx, m, t, theta, h_factor, z, o, features, s);
+        return f64 ? bandwidth_forward_impl<double, 3>(ctx, m, t, theta, h_factor, z, o, features, s)
+                   : bandwidth_forward_impl<float, 3>(ctx, m, t, theta, h_factor, z, o, features, s);
+    } catch (...) {
+        ctx->err = "internal error";
+        return FLA_ERR_DEVICE;
+    }
+}
+
+FLA_EXPORT fla_status fla_project_backward(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                                           const fla_params* params, const fla_fields* S, const fla_fields* dL_dS,
+                                           float* dL_dlogh, void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    try {
+        MeshDev m;
+        fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+        if (st != FLA_OK) return st;
+        TrajDev t;
+        st = check_traj(ctx, traj, m.dim, true, &t);
+        if (st != FLA_OK) return st;
+        st = check_params(ctx, params, true);
+        if (st != FLA_OK) return st;
+        CHECK_ARG(params->mode == FLA_NW, "fla_project_backward differentiates the FLA_NW estimator");
+        st = check_fields(ctx, S, m.dim);
+        if (st != FLA_OK) return st;
+        CHECK_ARG(S->den != nullptr, "S.den is required");
+        st = check_fields(ctx, dL_dS, m.dim);
+        if (st != FLA_OK) return st;
+        CHECK_ARG(dL_dlogh != nullptr || t.count == 0, "dL_dlogh is NULL");
+        HIP_OK(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        bool f64 = traj->prec == FLA_F64;
+        if (m.dim == 2)
+            return f64 ? project_backward_impl<double, 2>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s)
+                       : project_backward_impl<float, 2>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s);
+        return f64 ? project_backward_impl<double, 3>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s)
+                   : project_backward_impl<float, 3>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s);
+    } catch (...) {
+        ctx->err = "internal error";
+        return FLA_ERR_DEVICE;
+    }
+}
+
+FLA_EXPORT fla_status fla_bandwidth_backward(fla_ctx* ctx, int dim, const float* theta, int64_t count, const float* z,
+                                             const float* o, const float* dL_dlogh, float* grad, void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(dim == 2 || dim == 3, "dim must be 2 or 3");
+    CHECK_ARG(count >= 0 && count < (int64_t(1) << 31), "count out of range");
+    CHECK_ARG(theta && grad, "theta and grad are required");
+    CHECK_ARG(count == 0 || (z && o && dL_dlogh), "z, o and dL_dlogh are required");
+    HIP_OK(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = mlp_backward_blocks(count);
+    float* partial;
+    {
+        Carver probe(nullptr);
+        probe.take<float>((size_t)nb * kTrain);
+        fla_status st = ensure_ws(ctx, probe.off + 256);
+        if (st != FLA_OK) return st;
+    }
+    Carver c(ctx->ws);
+    partial = c.take<float>((size_t)nb * kTrain);
+    StageTimer tm(ctx, 7, s);
+    if (dim == 2)
+        HIP_OK((launch_mlp_backward<2>(theta, count, z, o, dL_dlogh, partial, nb, grad, s)));
+    else
+        HIP_OK((launch_mlp_backward<3>(theta, count, z, o, dL_dlogh, partial, nb, grad, s)));
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_adam_step(fla_ctx* ctx, float* theta, float* m, float* v, const float* grad, int64_t step,
+                                    double lr, double beta1, double beta2, double eps, void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(theta && m && v && grad, "theta, m, v and grad are required");
+    CHECK_ARG(step >= 1, "step counts from 1");
+    CHECK_ARG(is_fin(lr) && lr >= 0.0 && beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps >= 0.0,
+              "invalid Adam hyper-parameters");
+    HIP_OK(hipSetDevice(ctx->device));
+    HIP_OK(launch_adam(theta, m, v, grad, step, (float)lr, (float)beta1, (float)beta2, (float)eps, (hipStream_t)stream));
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_rel_l2_loss(fla_ctx* ctx, int channels, int64_t cells, int prec, const fla_fields* S,
+                                      const fla_fields* R, const fla_fields* dL_dS, double* result, void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(channels >= 1 && channels <= 4, "channels must be 1..4");
+    CHECK_ARG(cells >= 1, "cells must be positive");
+    CHECK_ARG(prec == FLA_F32 || prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
+    CHECK_ARG(S && R && result, "S, R and result are required");
+    const void* sp[4] = {S->S_mass, S->S_mom[0], S->S_mom[1], S->S_mom[2]};
+    const void* rp[4] = {R->S_mass, R->S_mom[0], R->S_mom[1], R->S_mom[2]};
+    for (int k = 0; k < channels; ++k) CHECK_ARG(sp[k] && rp[k], "a field plane of S or R is NULL");
+    MutPlanes G{{nullptr, nullptr, nullptr, nullptr}};
+    if (dL_dS) {
+        void* gp[4] = {dL_dS->S_mass, dL_dS->S_mom[0], dL_dS->S_mom[1], dL_dS->S_mom[2]};
+        for (int k = 0; k < channels; ++k) CHECK_ARG(gp[k], "a field plane of dL_dS is NULL");
+        for (int k = 0; k < 4; ++k) G.p[k] = gp[k];
+    }
+    HIP_OK(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    double* part;
+    {
+        Carver probe(nullptr);
+        probe.take<double>(256 * 8);
+        fla_status st = ensure_ws(ctx, probe.off + 256);
+        if (st != FLA_OK) return st;
+    }
+    Carver c(ctx->ws);
+    part = c.take<double>(256 * 8);
+    Planes Sp{{sp[0], sp[1], sp[2], sp[3]}}, Rp{{rp[0], rp[1], rp[2], rp[3]}};
+    if (prec == FLA_F64)
+        HIP_OK(launch_loss<double>(channels, cells, Sp, Rp, G, dL_dS != nullptr, part, result, s));
+    else
+        HIP_OK(launch_loss<float>(channels, cells, Sp, Rp, G, dL_dS != nullptr, part, result, s));
     return FLA_OK;
 }
 

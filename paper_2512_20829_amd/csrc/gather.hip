@@ -60,7 +60,7 @@ struct GatherLds {
 };
 
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
-__global__ __launch_bounds__(kWave * GatherWaves<D>::value, 2) void k_gather(GatherArgs g)
+__global__ __launch_bounds__(kWave * GatherWaves<D>::value, sizeof(R) == 4 ? 2 : 1) void k_gather(GatherArgs g)
 {
     constexpr int kGatherWaves = GatherWaves<D>::value;
     using G = Geo<D>;

@@ -1,0 +1,223 @@
+"""Parity of the learned-bandwidth kernels with the FP64 oracle.
+
+Each side runs its own chain from the same seeded inputs (trajectories,
+parameters, reference field); no GPU output feeds the oracle.
+
+Tolerances: features to 1e-6 (the GPU forms singular values with the
+closed-form 3x3 eigen-solution, the oracle with LAPACK); network outputs to
+2e-3 absolute + relative, because a pre-activation that lands within one
+binary32 rounding of a bf16 rounding boundary may round the other way on the
+other side (a one-ulp bf16 step is 2^-8 relative); gradients through the
+estimator to 1e-5 relative L2 (FP32 per-cell planes); network gradients to
+2e-3 relative L2 (bf16 inputs; deltas carried as bf16 hi + lo pairs)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle.learned as LN
+import workloads as W
+from helpers import as_precision, rel_l2
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2512_20829_amd as F
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def _theta(seed, f=None, last=0.3):
+    rng = np.random.default_rng(seed)
+    mu = sd = None
+    if f is not None:
+        mu, sd = f.mean(axis=1), f.std(axis=1) + 1e-3
+    th = LN.init_params(seed, mu, sd)
+    p = LN.unpack(th)
+    p["w3"] = rng.standard_normal(64) * last
+    p["b1"] = rng.standard_normal(64) * 0.1
+    p["b2"] = rng.standard_normal(64) * 0.1
+    p["b3"] = np.array([0.05])
+    return LN.pack(p).astype(np.float32).astype(np.float64)
+
+
+def _traj_struct(tr, prec):
+    import paper_2512_20829_amd as F
+    dt = torch.float64 if prec == "f64" else torch.float32
+    return F.make_trajectories(tr.x.to(DEV), tr.J.to(DEV), tr.v.to(DEV, dt), tr.ug.to(DEV, dt), tr.r.to(DEV, dt),
+                               tr.n0, tr.seed_volume)
+
+
+def _gpu_forward(ctx, wl, theta, prec="f32"):
+    import paper_2512_20829_amd as F
+    st, keep = _traj_struct(wl.traj, prec)
+    N = wl.traj.count
+    th = torch.tensor(theta, dtype=torch.float32, device=DEV)
+    hf = torch.empty(N, dtype=torch.float32, device=DEV)
+    z = torch.empty(5 * N, dtype=torch.float32, device=DEV)
+    o = torch.empty(N, dtype=torch.float32, device=DEV)
+    fr = torch.empty(5 * N, dtype=torch.float32, device=DEV)
+    ctx.bandwidth_forward(F.mesh_of(wl.mesh), st, th, hf, z, o, fr)
+    torch.cuda.synchronize()
+    return (hf.cpu().double().numpy(), z.cpu().double().numpy().reshape(5, N), o.cpu().double().numpy(),
+            fr.cpu().double().numpy().reshape(5, N))
+
+
+def _oracle_forward(wl, theta, prec="f32"):
+    tr = as_precision(wl.traj, prec)
+    t = oracle.trajectory_terms(tr, wl.rho_d, wl.mu, wl.delta, wl.h0)
+    f = LN.features(wl.mesh, tr.x.numpy(), tr.J.numpy(), t.valid)
+    return LN.forward(theta, f), f, t
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_features_and_network_forward(ctx, dim):
+    if dim == 3:
+        wl = W.small_random_3d(3000, 16, seed=21)
+    else:
+        wl = W.c1_taylor_green(per_axis=48, mesh_n=40)
+    _, f0, _ = _oracle_forward(wl, LN.init_params(0))
+    theta = _theta(21, f0)
+    hf, z, o, fr = _gpu_forward(ctx, wl, theta)
+    fw, f, t = _oracle_forward(wl, theta)
+    v = t.valid == 1
+    np.testing.assert_allclose(fr[:, v], f[:, v], rtol=1e-6, atol=1e-6)
+    assert np.mean(z[:, v] == fw.z[:, v]) > 0.999
+    err = np.abs(o - fw.o)
+    assert np.all(err[v] <= 2e-3 * (1 + np.abs(fw.o[v]))), err.max()
+    assert np.median(err[v]) <= 1e-5
+    np.testing.assert_allclose(hf[v], fw.g[v], rtol=4e-3)
+    assert np.all(hf[~v] == 1.0)
+
+
+def test_zero_last_layer_reproduces_the_plain_projection_bitwise(ctx):
+    from helpers import gpu_run
+    wl = W.small_random_3d(4000, 20, seed=22)
+    theta = LN.init_params(22)                       # w3 = 0, b3 = 0  ->  g = 1 exactly
+    hf, _, _, _ = _gpu_forward(ctx, wl, theta)
+    assert np.all(hf == 1.0)
+    S0, d0, _ = gpu_run(ctx, wl, prec="f32")
+    S1, d1, _ = gpu_run(ctx, wl, prec="f32", h_factor=torch.tensor(hf, dtype=torch.float32))
+    assert np.array_equal(S0, S1) and np.array_equal(d0, d1)
+
+
+def _gpu_chain(ctx, wl, theta, R, prec):
+    """forward network -> projection -> loss -> estimator backward -> network backward"""
+    import paper_2512_20829_amd as F
+    dt = torch.float64 if prec == "f64" else torch.float32
+    st, keep = _traj_struct(wl.traj, prec)
+    N, M = wl.traj.count, wl.mesh.cells
+    mesh = F.mesh_of(wl.mesh)
+    th = torch.tensor(theta, dtype=torch.float32, device=DEV)
+    hf = torch.empty(N, dtype=torch.float32, device=DEV)
+    z = torch.empty(5 * N, dtype=torch.float32, device=DEV)
+    o = torch.empty(N, dtype=torch.float32, device=DEV)
+    ctx.bandwidth_forward(mesh, st, th, hf, z, o)
+    p = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff, h_factor=hf)
+    Sm, Sv, den = F.alloc_fields(M, 3, dt, DEV)
+    ctx.project_sources(mesh, st, p, Sm, Sv, den)
+    Rt = [torch.tensor(R[k], dtype=dt, device=DEV) for k in range(4)]
+    G = [torch.empty(M, dtype=dt, device=DEV) for _ in range(4)]
+    res = ctx.rel_l2_loss(4, M, F.FLA_F64 if prec == "f64" else F.FLA_F32, [Sm, *Sv], Rt, G)
+    dlogh = torch.empty(N, dtype=torch.float32, device=DEV)
+    ctx.project_backward(mesh, st, p, Sm, Sv, den, G[0], G[1:], dlogh)
+    grad = torch.empty(F.MLP_PARAMS, dtype=torch.float32, device=DEV)
+    ctx.bandwidth_backward(3, th, N, z, o, dlogh, grad)
+    torch.cuda.synchronize()
+    return (res.cpu().numpy(), dlogh.cpu().double().numpy(), grad.cpu().double().numpy(),
+            torch.stack([Sm, *Sv]).double().cpu().numpy())
+
+
+def _oracle_chain(wl, theta, R, prec):
+    fw, f, t = _oracle_forward(wl, theta, prec)
+    tr = as_precision(wl.traj, prec)
+    t2 = oracle.trajectory_terms(tr, wl.rho_d, wl.mu, wl.delta, wl.h0, h_factor=fw.g)
+    p = oracle.nw_cells(wl.mesh, tr.x, t2, cutoff=wl.cutoff, f32_decision=(prec == "f32"))
+    L, dLdS = LN.rel_l2_loss(p.S, R)
+    dh = LN.dL_dh(wl.mesh, tr.x.numpy(), t2.h, t2.q, t2.valid, p.S, p.den, dLdS, cutoff=wl.cutoff)
+    dlogh = dh * t2.h
+    grad = LN.backward(theta, fw, LN.dL_do_from_dL_dh(dh, t2.h, fw.o))
+    return L, dlogh, grad, p.S
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_gradient_chain_matches_oracle(ctx, prec):
+    wl = W.small_random_3d(700, 12, seed=23)
+    _, f0, _ = _oracle_forward(wl, LN.init_params(0))
+    theta = _theta(23, f0, last=0.2)
+    rng = np.random.default_rng(23)
+    Lr, _, _, Sr = _oracle_chain(wl, theta, np.ones((4, wl.mesh.cells)), prec)
+    R = Sr * (1.0 + 0.3 * rng.standard_normal(Sr.shape))        # a perturbed reference field
+    res, dlogh, grad, S = _gpu_chain(ctx, wl, theta, R, prec)
+    L, dlogh_ref, grad_ref, S_ref = _oracle_chain(wl, theta, R, prec)
+    assert rel_l2(S, S_ref) < 2e-3
+    assert res[0] == pytest.approx(L, rel=1e-2)
+    assert rel_l2(dlogh, dlogh_ref) < 2e-2
+    assert rel_l2(grad[:LN.N_TRAIN], grad_ref[:LN.N_TRAIN]) < 2e-2
+    assert np.all(grad[LN.N_TRAIN:] == 0.0)
+
+
+def test_estimator_backward_with_shared_factors(ctx):
+    """With the bandwidth factors of a fixed, seeded vector (no network), the
+    estimator backward matches the oracle to FP32 accuracy."""
+    import paper_2512_20829_amd as F
+    wl = W.small_random_3d(600, 12, seed=24)
+    N, M = wl.traj.count, wl.mesh.cells
+    rng = np.random.default_rng(24)
+    hf = np.exp(0.3 * rng.standard_normal(N)).astype(np.float32).astype(np.float64)
+    for prec in ("f32", "f64"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        tr = as_precision(wl.traj, prec)
+        t = oracle.trajectory_terms(tr, wl.rho_d, wl.mu, wl.delta, wl.h0, h_factor=hf)
+        p = oracle.nw_cells(wl.mesh, tr.x, t, cutoff=wl.cutoff, f32_decision=(prec == "f32"))
+        R = p.S * (1.0 + 0.2 * rng.standard_normal(p.S.shape))
+        L, dLdS = LN.rel_l2_loss(p.S, R)
+        ref = LN.dL_dh(wl.mesh, tr.x.numpy(), t.h, t.q, t.valid, p.S, p.den, dLdS, cutoff=wl.cutoff) * t.h
+        st, keep = _traj_struct(wl.traj, prec)
+        mesh = F.mesh_of(wl.mesh)
+        hft = torch.tensor(hf, dtype=torch.float32, device=DEV)
+        prm = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff, h_factor=hft)
+        Sm, Sv, den = F.alloc_fields(M, 3, dt, DEV)
+        ctx.project_sources(mesh, st, prm, Sm, Sv, den)
+        Rt = [torch.tensor(R[k], dtype=dt, device=DEV) for k in range(4)]
+        G = [torch.empty(M, dtype=dt, device=DEV) for _ in range(4)]
+        res = ctx.rel_l2_loss(4, M, F.FLA_F64 if prec == "f64" else F.FLA_F32, [Sm, *Sv], Rt, G)
+        out = torch.empty(N, dtype=torch.float32, device=DEV)
+        ctx.project_backward(mesh, st, prm, Sm, Sv, den, G[0], G[1:], out)
+        torch.cuda.synchronize()
+        assert float(res[0]) == pytest.approx(L, rel=1e-5 if prec == "f32" else 1e-10)
+        assert rel_l2(out.cpu().double().numpy(), ref) < 1e-5
+
+
+def test_network_backward_and_adam(ctx):
+    import paper_2512_20829_amd as F
+    wl = W.small_random_3d(5000, 16, seed=25)
+    _, f0, _ = _oracle_forward(wl, LN.init_params(0))
+    theta = _theta(25, f0)
+    hf, z, o, _ = _gpu_forward(ctx, wl, theta)
+    fw, _, t = _oracle_forward(wl, theta)
+    N = wl.traj.count
+    rng = np.random.default_rng(25)
+    dlogh = (rng.standard_normal(N) * (t.valid == 1)).astype(np.float32).astype(np.float64)
+    th = torch.tensor(theta, dtype=torch.float32, device=DEV)
+    grad = torch.empty(F.MLP_PARAMS, dtype=torch.float32, device=DEV)
+    ctx.bandwidth_backward(3, th, N, torch.tensor(z.reshape(-1), dtype=torch.float32, device=DEV),
+                           torch.tensor(o, dtype=torch.float32, device=DEV),
+                           torch.tensor(dlogh, dtype=torch.float32, device=DEV), grad)
+    torch.cuda.synchronize()
+    ref = LN.backward(theta, fw, dlogh * LN.S_MAX * (1 - np.tanh(fw.o) ** 2))
+    g = grad.cpu().double().numpy()
+    assert rel_l2(g[:LN.N_TRAIN], ref[:LN.N_TRAIN]) < 2e-3
+    # Adam on a seeded gradient
+    gs = rng.standard_normal(F.MLP_PARAMS).astype(np.float32).astype(np.float64)
+    m = torch.zeros(F.MLP_PARAMS, dtype=torch.float32, device=DEV)
+    v = torch.zeros_like(m)
+    th2 = th.clone()
+    ctx.adam_step(th2, m, v, torch.tensor(gs, dtype=torch.float32, device=DEV), 1, lr=1e-3)
+    torch.cuda.synchronize()
+    t1, _, _ = LN.adam(theta, gs, np.zeros_like(theta), np.zeros_like(theta), 1, lr=1e-3)
+    np.testing.assert_allclose(th2.cpu().double().numpy(), t1, rtol=1e-6, atol=1e-9)
