@@ -17,6 +17,11 @@ its fused epilogue.  Printed as one JSON line (rank 0):
                stream: algorithmic flops per launch / average launch time
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
   psicell      PSI-CELL accumulation of a 200M-particle cloud (context)
+  learned_vs_plain  the learned bandwidth network trained on 500 generated
+               64^3 snapshots (200k trajectories, 50M-particle PSI-CELL each),
+               then plain, learned and deposition errors on the 128^3 case at
+               2M..125k lattice trajectories against the 200M-particle
+               reference, and cells/s of both forms
 """
 import argparse
 import json
@@ -68,6 +73,114 @@ def gather_traffic():
         return None
 
 
+def _psicell_reference(ctx, F, W, torch, mesh, abc, n_particles, seed, params, dev):
+    """Dense PSI-CELL reference as the mean of two independent half clouds,
+    with the per-channel noise floor |A - B|^2 / (4 |R|^2)."""
+    halves = []
+    for h in range(2):
+        cl = W.abc_cloud(n_particles // 2, seed=seed, device=dev, abc=abc, jacobian=False, offset=h * (n_particles // 2))
+        st, keep = F.make_trajectories(cl.x, None, cl.v.float(), cl.ug.float(), cl.r.float(), 1.0)
+        Sm, Sv, _ = F.alloc_fields(mesh.cells, mesh.dim, torch.float32, dev, den=False)
+        ctx.psicell_accumulate(F.mesh_of(mesh), st, W.N0_DEFAULT / (n_particles // 2), params, Sm, Sv)
+        halves.append([Sm, *Sv])
+        del cl, st, keep
+    ref = [(a + b) * 0.5 for a, b in zip(*halves)]
+    floor = [float(((a - b) ** 2).double().sum() / (4 * (r.double() ** 2).sum())) for a, b, r in zip(*halves, ref)]
+    return ref, floor
+
+
+def learned_vs_plain(ctx, args, dev):
+    """Train the bandwidth network on the library's own projections of 64^3
+    snapshots against dense PSI-CELL, then compare plain and learned forms
+    (and the conservative deposition) on the 128^3 ABC case at several
+    seeding densities against the 200M-particle reference."""
+    import numpy as np
+    import torch
+
+    import paper_2512_20829_amd as F
+    import workloads as W
+    from paper_2512_20829_amd import train as T
+
+    def snap_of(wl, ref):
+        tr = wl.traj
+        st, keep = F.make_trajectories(tr.x, tr.J, tr.v.float(), tr.ug.float(), tr.r.float(), tr.n0, tr.seed_volume)
+        keep.append(tr)
+        p = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
+        return T.Snapshot(wl.mesh, st, keep, tr.count, p, ref)
+
+    t0 = time.perf_counter()
+    train = []
+    for s in range(args.train_snapshots):
+        wl, abc = W.c4_snapshot(s, n_traj=args.train_trajectories, mesh_n=64, device=dev)
+        p = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
+        ref, _ = _psicell_reference(ctx, F, W, torch, wl.mesh, abc, args.train_particles, 10_000 + s, p, dev)
+        train.append(snap_of(wl, ref))
+        if s % 100 == 99:
+            log(f"training snapshots: {s + 1}")
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    wl2 = W.c2_abc(device=dev)
+    p2 = F.Params(rho_d=wl2.rho_d, mu=wl2.mu, delta=wl2.delta, h0=wl2.h0, cutoff=wl2.cutoff)
+    ref2, floor = _psicell_reference(ctx, F, W, torch, wl2.mesh, W.ABC(), args.psicell_particles, 0, p2, dev)
+    del wl2
+    theta = T.fit_standardisation(ctx, train[:16], T.initial_theta(0))
+    model = T.BandwidthModel(ctx, theta, lr=1e-3)
+    t0 = time.perf_counter()
+    for it in range(args.train_steps):
+        model.train_step(train[it % len(train)])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"trained {args.train_steps} steps on {len(train)} snapshots in {t_train:.1f} s (data {t_data:.1f} s)")
+    del train
+
+    def deb(res):
+        r = res.cpu().numpy()
+        e = [math.sqrt(max(r[1 + 2 * k] / r[2 + 2 * k] - floor[k], 0.0)) for k in range(4)]
+        return float(np.mean(e))
+
+    rows = []
+    for pa in (128, 100, 80, 64, 50):
+        wl = W.c2_abc(per_axis=pa, mesh_n=128, device=dev)
+        sn = snap_of(wl, ref2)
+        out = {"trajectories": pa ** 3}
+        hf = model.factors(sn)[0]
+        for name, h, mode in (("plain", None, F.FLA_NW), ("learned", hf, F.FLA_NW), ("deposit", None, F.FLA_DEPOSIT)):
+            prm = F.Params(**{**sn.params.__dict__, "h_factor": h, "mode": mode})
+            Sm, Sv, den = F.alloc_fields(sn.cells, 3, torch.float32, dev)
+            ctx.project_sources(F.mesh_of(wl.mesh), sn.traj, prm, Sm, Sv, den)
+            res, _ = model.loss(sn, [Sm, *Sv], False)
+            out[name] = round(deb(res), 5)
+        rows.append(out)
+        if pa == 128:
+            # throughput of both forms on the full workload (the learned form
+            # includes the feature and network kernels)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            Sm, Sv, den = F.alloc_fields(sn.cells, 3, torch.float32, dev, den=False)
+            for learned in (False, True):
+                for rep in range(args.warmup + args.steps):
+                    if rep == args.warmup:
+                        e0.record()
+                    h = model.factors(sn)[0] if learned else None
+                    ctx.project_sources(F.mesh_of(wl.mesh), sn.traj, F.Params(**{**sn.params.__dict__, "h_factor": h}),
+                                        Sm, Sv)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / args.steps
+                out["cells_per_s_learned" if learned else "cells_per_s_plain"] = sn.cells / (ms * 1e-3)
+        del sn, wl
+    target = rows[0]["plain"]
+    matched = [r["trajectories"] for r in rows if r["learned"] <= target]
+    return {
+        "train": {"snapshots": args.train_snapshots, "trajectories": args.train_trajectories, "mesh": [64, 64, 64],
+                  "psicell_particles": args.train_particles, "steps": args.train_steps, "seconds": round(t_train, 2)},
+        "reference": {"psicell_particles": args.psicell_particles, "noise_floor_rel_l2": [round(math.sqrt(f), 4) for f in floor]},
+        "error": "mean over the 4 source fields of the noise-debiased rel L2 against dense PSI-CELL",
+        "eval": rows,
+        "plain_error_at_2M": target,
+        "fewest_trajectories_learned_within_plain_error_at_2M": min(matched) if matched else None,
+    }
+
+
 def cpu_baseline(seconds: float):
     """FP64 oracle, brute force per cell, on a random sample of cells of the
     same workload; full-field time extrapolated from the sample."""
@@ -116,6 +229,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psicell", action="store_true")
     ap.add_argument("--psicell-particles", type=int, default=200_000_000)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain section")
+    ap.add_argument("--train-snapshots", type=int, default=500)
+    ap.add_argument("--train-trajectories", type=int, default=200_000)
+    ap.add_argument("--train-particles", type=int, default=50_000_000)
+    ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -211,6 +329,12 @@ def main():
         torch.cuda.empty_cache()
         log(f"psicell {Np}: {psi_ms:.3f} ms")
 
+    learned = None
+    if not args.no_learned:
+        log("learned-vs-plain section: training the bandwidth network")
+        learned = learned_vs_plain(ctx, args, dev)
+        log(f"learned: {learned['eval']}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the FP64 oracle on host cores (~{args.cpu_seconds:.0f} s)")
@@ -239,6 +363,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "psicell": psi,
+        "learned_vs_plain": learned,
     }
     print(json.dumps(out), flush=True)
     if args.calibration_copy_mib > 0:
