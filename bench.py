@@ -16,6 +16,9 @@ its fused epilogue.  Printed as one JSON line (rank 0):
   roofline     the gather kernel, timed with HIP events on the library's
                stream: algorithmic flops per launch / average launch time
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
+  batch        64 uneven snapshots (32^3..128^3 meshes, 10k..2M trajectories)
+               through fla_project_batch: graph replays, direct launches and
+               one single call per snapshot, after the batch autotuner
   psicell      PSI-CELL accumulation of a 200M-particle cloud (context)
   learned_vs_plain  the learned bandwidth network trained on 500 generated
                64^3 snapshots (200k trajectories, 50M-particle PSI-CELL each),
@@ -181,6 +184,100 @@ def learned_vs_plain(ctx, args, dev):
     }
 
 
+def batch_section(ctx, args, dev):
+    """The uneven batch: 64 snapshots, meshes 32^3..128^3, 10k..2M random
+    trajectories each through ABC maps of random amplitude and phase, FP32.
+    Times graph replays of fla_project_batch after the batch autotuner has
+    chosen the gather plan and XCD chunk, direct launches of the same batch,
+    and one fla_project_sources call per snapshot for comparison."""
+    import torch
+
+    import paper_2512_20829_amd as F
+    import workloads as W
+
+    t0 = time.time()
+    wls = [W.c3_snapshot(s, device=dev) for s in range(args.batch_snapshots)]
+    meshes, trajs, keeps, outs, params = [], [], [], [], []
+    for wl in wls:
+        tr = wl.traj
+        st, keep = F.make_trajectories(tr.x.contiguous(), tr.J.contiguous(), tr.v.to(torch.float32).contiguous(),
+                                       tr.ug.to(torch.float32).contiguous(), tr.r.to(torch.float32).contiguous(),
+                                       tr.n0, tr.seed_volume)
+        wl.traj = None
+        meshes.append(F.mesh_of(wl.mesh))
+        trajs.append(st)
+        keeps.append(keep)
+        Sm, Sv, _ = F.alloc_fields(wl.mesh.cells, 3, torch.float32, dev, den=False)
+        outs.append((Sm, Sv, None))
+        params.append(F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff))
+    torch.cuda.synchronize()
+    N = sum(t.count for t in trajs)
+    M = sum(wl.mesh.cells for wl in wls)
+    log(f"batch: {len(wls)} snapshots, {N} trajectories, {M} cells (generated in {time.time() - t0:.1f} s)")
+
+    counted = [F.Params(**{**p.__dict__, "count_pairs": True}) for p in params]
+    ctx.set_batch_graph(False)
+    ctx.project_batch(meshes, trajs, counted, outs)
+    torch.cuda.synchronize()
+    P = ctx.stats()["pairs"]
+    times = ctx.autotune_batch(meshes, trajs, params, outs)
+    plan, chunk = ctx.get_batch_plan(3, F.FLA_F32)
+    log(f"batch autotune: plan {plan}, chunk {chunk}; gather ms {[round(t, 3) for t in times]}")
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    run = lambda: ctx.project_batch(meshes, trajs, params, outs)
+    ms_direct = timed(run, args.steps)
+    ctx.profile_enable(True)
+    for _ in range(3):
+        run()
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    stages = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1]}
+    g_ms = stages["gather"]
+
+    ctx.set_batch_graph(True)
+    r0 = ctx.stats()["graph_replays"]
+    ms_graph = timed(run, args.steps)
+    replays = ctx.stats()["graph_replays"] - r0
+
+    def singles():
+        for m, t, p, o in zip(meshes, trajs, params, outs):
+            ctx.project_sources(m, t, p, o[0], o[1])
+    ctx.set_plan(3, F.FLA_F32, plan)
+    ms_single = timed(singles, max(args.steps // 4, 2))
+    ctx.set_plan(3, F.FLA_F32, -1)
+    achieved = P * FLOPS_PER_PAIR_3D / (g_ms * 1e-3) / 1e12
+    log(f"batch: graph {ms_graph:.3f} ms, direct {ms_direct:.3f} ms, 64 single calls {ms_single:.3f} ms; "
+        f"stages {stages}")
+    out = {"workload": "64 uneven snapshots: meshes round(32*4^u)^3 (32^3..128^3), round(1e4*200^u') random "
+                       "trajectories (10k..2M), ABC amplitude U[0.05, 0.2] with random phases, h0 = N^(-1/3), FP32",
+           "snapshots": len(wls), "trajectories": N, "cells": M, "pairs": P,
+           "ms_graph": round(ms_graph, 4), "ms_direct": round(ms_direct, 4),
+           "ms_single_calls": round(ms_single, 4), "graph_replays": replays,
+           "cells_per_s": M / (ms_graph * 1e-3), "pairs_per_s": P / (ms_graph * 1e-3),
+           "stage_ms": stages, "plan": plan, "chunk": chunk,
+           "autotune_gather_ms": [round(t, 4) for t in times],
+           "gather": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
+                      "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "launch_ms": g_ms,
+                      "kernel": "k_gather_batch<float,3,NW>"}}
+    del wls, trajs, keeps, outs
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(seconds: float):
     """FP64 oracle, brute force per cell, on a random sample of cells of the
     same workload; full-field time extrapolated from the sample."""
@@ -228,6 +325,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psicell", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch section")
+    ap.add_argument("--batch-snapshots", type=int, default=64)
     ap.add_argument("--psicell-particles", type=int, default=200_000_000)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain section")
     ap.add_argument("--train-snapshots", type=int, default=500)
@@ -296,6 +395,10 @@ def main():
                 "kernel": "k_gather<float,3,NW>", "launch_ms": round(g_ms, 4),
                 "flops_per_pair": FLOPS_PER_PAIR_3D, "pairs_per_launch": P}
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_section(ctx, args, dev)
+
     psi = None
     if not args.no_psicell:
         Np = args.psicell_particles
@@ -362,6 +465,7 @@ def main():
         "stage_ms": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batch": batch,
         "psicell": psi,
         "learned_vs_plain": learned,
     }

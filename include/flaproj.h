@@ -145,7 +145,8 @@ typedef struct {
     int64_t outside;          /* PSI-CELL particles outside a closed box */
     int64_t zero_support;     /* FLA_DEPOSIT: trajectories with Z_i = 0 */
     int64_t max_class;        /* largest neighbourhood class used by the gather */
-    int64_t reserved;
+    int64_t graph_replays;    /* fla_project_batch calls on this context that replayed
+                                 a captured graph (host counter, never reset) */
 } fla_stats;
 
 /* Create a context on HIP device `device` (host pointer out).  Errors:
@@ -199,7 +200,9 @@ fla_status fla_get_stats(fla_ctx* ctx, fla_stats* out);
  * and the number of timed launches since profiling was enabled.  Stages:
  * 0 prepass, 1 key sort + bucket bounds + record permutation, 2 deposition
  * normaliser, 3 gather with fused epilogue, 4 PSI-CELL accumulation,
- * 5 bandwidth network forward, 6 estimator backward, 7 network backward.
+ * 5 bandwidth network forward, 6 estimator backward, 7 network backward
+ * (fla_project_batch records stages 0, 1 and 3 once for the whole batch and
+ * runs without a graph while profiling is on).
  * Errors: INVALID_ARG for NULL, DEVICE. */
 #define FLA_PROFILE_STAGES 8
 typedef struct {
@@ -291,6 +294,61 @@ fla_status fla_adam_step(fla_ctx* ctx, float* theta, float* m, float* v, const f
  * formed in a fixed order (deterministic).  Errors: INVALID_ARG, DEVICE. */
 fla_status fla_rel_l2_loss(fla_ctx* ctx, int channels, int64_t cells, int prec, const fla_fields* S,
                            const fla_fields* R, const fla_fields* dL_dS, double* result, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched projection of many independent snapshots of uneven size.  Each
+ * snapshot is projected with the estimator of fla_project_sources; batching
+ * changes only how the work is launched.
+ * meshes, trajs, params and outs are host arrays of nsnap structs; snapshot s
+ * writes outs[s] bit for bit as fla_project_sources(meshes[s], trajs[s],
+ * params[s], outs[s]) does under the same gather plan.  All snapshots share
+ * dim and prec; every mode must be FLA_NW.  Statistics are summed over the
+ * batch (max_class is the largest over the snapshots); pairs are counted
+ * if any params[s].count_pairs is set.
+ * Launch sequence: one prepass over the trajectories of all snapshots, one
+ * key sort whose buckets are (snapshot, class, tile), one record permutation
+ * and one gather launch with a workgroup per (snapshot, tile).  Snapshots
+ * are ordered by estimated work per tile, largest first, so that the
+ * longest workgroups start first.
+ * Graphs (default on, see fla_set_batch_graph) while profiling is off: the
+ * first call with a given set of arguments (every field of every struct,
+ * the stream, the batch plan, the context's workspace) waits for the
+ * previous batch call's work, uploads a snapshot table, captures the launch
+ * sequence into a HIP graph and launches it; a later call with identical
+ * arguments only launches that graph.  Buffer contents may change between
+ * such calls; pointers, sizes and parameters may not.  The context keeps
+ * one graph.  Errors: INVALID_ARG (nsnap outside [1, FLA_BATCH_MAX], mixed
+ * dim or prec, a mode other than FLA_NW, more than 2^31 - 1 trajectories or
+ * buckets in total, or any check of fla_project_sources on a snapshot),
+ * OUT_OF_MEMORY, DEVICE. */
+#define FLA_BATCH_MAX 65536
+fla_status fla_project_batch(fla_ctx* ctx, int nsnap, const fla_mesh* meshes, const fla_trajectories* trajs,
+                             const fla_params* params, const fla_fields* outs, void* stream);
+
+/* enable != 0: batch calls go through the cached graph (default);
+ * enable == 0: every batch call uploads its table and enqueues the
+ * launches directly.  Drops the cached graph.  Errors: INVALID_ARG. */
+fla_status fla_set_batch_graph(fla_ctx* ctx, int enable);
+
+/* Batch plan per (dim, prec): the gather plan (as fla_set_plan) and the
+ * XCD chunk, the number of consecutive work items (tiles) that one of the
+ * eight XCDs receives from each run of 8 * chunk items, 1..4096.
+ * gather_plan == -1 restores the library defaults (chunk is then ignored).
+ * Errors: INVALID_ARG for out-of-range arguments. */
+fla_status fla_set_batch_plan(fla_ctx* ctx, int dim, int prec, int gather_plan, int chunk);
+fla_status fla_get_batch_plan(fla_ctx* ctx, int dim, int prec, int* gather_plan, int* chunk);
+
+/* Batch autotuner: runs fla_project_batch directly (no graph) for every
+ * gather plan and every chunk in {1, 4, 16, 64} (a warm-up call, then a call
+ * whose gather launch is timed with HIP events), keeps the fastest pair for
+ * (dim, prec) and, if times_ms (host, FLA_GATHER_PLANS * FLA_BATCH_CHUNKS
+ * values, index plan * FLA_BATCH_CHUNKS + chunk index) is not NULL, returns
+ * every gather time.  Synchronises the device; outs receive the projection.
+ * Errors as fla_project_batch. */
+#define FLA_BATCH_CHUNKS 4
+fla_status fla_autotune_batch(fla_ctx* ctx, int nsnap, const fla_mesh* meshes, const fla_trajectories* trajs,
+                              const fla_params* params, const fla_fields* outs, void* stream,
+                              double* times_ms);
 
 /* Message of the last error on ctx (host string owned by ctx, valid until
  * the next call on ctx); "" if the last call succeeded.  NULL ctx returns

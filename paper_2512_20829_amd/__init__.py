@@ -52,13 +52,16 @@ class fla_fields(C.Structure):
 class fla_stats(C.Structure):
     _fields_ = [("trajectories", C.c_int64), ("skipped", C.c_int64), ("no_support", C.c_int64),
                 ("pairs", C.c_int64), ("outside", C.c_int64), ("zero_support", C.c_int64),
-                ("max_class", C.c_int64), ("reserved", C.c_int64)]
+                ("max_class", C.c_int64), ("graph_replays", C.c_int64)]
 
 
 PROFILE_STAGES = ["prepass", "sort", "deposit_norm", "gather", "psicell", "mlp_forward", "proj_backward",
                   "mlp_backward"]
 MLP_TRAINABLE = 4609
 MLP_PARAMS = 4619
+GATHER_PLANS = 4
+BATCH_CHUNKS = 4
+BATCH_MAX = 65536
 
 
 class fla_profile(C.Structure):
@@ -102,6 +105,18 @@ _lib.fla_adam_step.argtypes = [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_double, C
 _lib.fla_rel_l2_loss.restype = C.c_int
 _lib.fla_rel_l2_loss.argtypes = [_vp, C.c_int, C.c_int64, C.c_int, C.POINTER(fla_fields), C.POINTER(fla_fields),
                                  C.POINTER(fla_fields), _vp, _vp]
+_lib.fla_project_batch.restype = C.c_int
+_lib.fla_project_batch.argtypes = [_vp, C.c_int, C.POINTER(fla_mesh), C.POINTER(fla_trajectories),
+                                   C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
+_lib.fla_set_batch_graph.restype = C.c_int
+_lib.fla_set_batch_graph.argtypes = [_vp, C.c_int]
+_lib.fla_set_batch_plan.restype = C.c_int
+_lib.fla_set_batch_plan.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int]
+_lib.fla_get_batch_plan.restype = C.c_int
+_lib.fla_get_batch_plan.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+_lib.fla_autotune_batch.restype = C.c_int
+_lib.fla_autotune_batch.argtypes = [_vp, C.c_int, C.POINTER(fla_mesh), C.POINTER(fla_trajectories),
+                                    C.POINTER(fla_params), C.POINTER(fla_fields), _vp, C.POINTER(C.c_double)]
 _lib.fla_last_error.restype = C.c_char_p
 _lib.fla_last_error.argtypes = [_vp]
 
@@ -337,6 +352,43 @@ class Context:
                                          C.byref(fg) if fg is not None else None, _ptr(result),
                                          _stream_handle(stream)))
         return result
+
+    # -- batched snapshots --------------------------------------------------------------
+    @staticmethod
+    def _batch_arrays(meshes: Sequence, trajs: Sequence, params: Sequence, outs: Sequence):
+        n = len(meshes)
+        if not (len(trajs) == len(params) == len(outs) == n) or n == 0:
+            raise ValueError("meshes, trajs, params and outs must be non-empty and of equal length")
+        M = (fla_mesh * n)(*meshes)
+        T = (fla_trajectories * n)(*trajs)
+        P = (fla_params * n)(*[p.to_c() if isinstance(p, Params) else p for p in params])
+        F = (fla_fields * n)(*[o if isinstance(o, fla_fields) else make_fields(o[0], o[1], o[2] if len(o) > 2 else None)
+                               for o in outs])
+        return n, M, T, P, F
+
+    def project_batch(self, meshes: Sequence, trajs: Sequence, params: Sequence, outs: Sequence, stream=None):
+        """outs[s]: fla_fields or (S_mass, [S_mom...], den or None)."""
+        n, M, T, P, F = self._batch_arrays(meshes, trajs, params, outs)
+        self._check(_lib.fla_project_batch(self._h, n, M, T, P, F, _stream_handle(stream)))
+
+    def set_batch_graph(self, enable: bool):
+        self._check(_lib.fla_set_batch_graph(self._h, int(bool(enable))))
+
+    def set_batch_plan(self, dim: int, prec: int, plan: int, chunk: int = 16):
+        self._check(_lib.fla_set_batch_plan(self._h, dim, prec, plan, chunk))
+
+    def get_batch_plan(self, dim: int, prec: int) -> tuple:
+        p, c = C.c_int(), C.c_int()
+        self._check(_lib.fla_get_batch_plan(self._h, dim, prec, C.byref(p), C.byref(c)))
+        return p.value, c.value
+
+    def autotune_batch(self, meshes: Sequence, trajs: Sequence, params: Sequence, outs: Sequence,
+                       stream=None) -> list:
+        """Returns the gather time (ms) of every (plan, chunk) tried, plan-major."""
+        n, M, T, P, F = self._batch_arrays(meshes, trajs, params, outs)
+        times = (C.c_double * (GATHER_PLANS * BATCH_CHUNKS))()
+        self._check(_lib.fla_autotune_batch(self._h, n, M, T, P, F, _stream_handle(stream), times))
+        return list(times)
 
     def stats(self) -> dict:
         s = fla_stats()

@@ -2,9 +2,11 @@
 // the grow-only workspace, and the launch sequence of each entry point.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -28,6 +30,19 @@ struct fla_ctx {
         hipEvent_t a, b;
     };
     std::vector<Rec> recs;
+    // batched projection: plan per (dim - 2, precision), snapshot table, cached graph
+    int batch_plan[2][2] = {{-1, -1}, {-1, -1}};
+    int batch_chunk[2][2] = {{-1, -1}, {-1, -1}};
+    bool batch_graph = true;
+    void* items = nullptr;                 // device snapshot table
+    size_t items_size = 0;
+    hipEvent_t items_done = nullptr;       // recorded after the last batch call's work
+    bool items_pending = false;
+    hipStream_t capture = nullptr;         // stream the launch sequence is captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<unsigned char> graph_key;
+    int64_t graph_replays = 0;
 };
 
 static thread_local std::string g_create_error;
@@ -35,6 +50,10 @@ static thread_local std::string g_create_error;
 // gather plan used until fla_set_plan or fla_autotune chooses one: skips at
 // the granularity of sub-block pairs, the fastest plan on the 128^3 ABC case
 static constexpr int kDefaultPlan = 1;
+// XCD chunk of the batched gather until fla_set_batch_plan or
+// fla_autotune_batch chooses one, and the candidates the autotuner tries
+static constexpr int kDefaultChunk = 16;
+static constexpr int kChunkChoices[FLA_BATCH_CHUNKS] = {1, 4, 16, 64};
 
 namespace {
 
@@ -307,6 +326,205 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
     return FLA_OK;
 }
 
+void drop_graph(fla_ctx* ctx)
+{
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_key.clear();
+}
+
+// Batched projection (see fla_project_batch).  md, td: validated snapshots.
+template <typename R, int D>
+fla_status batch_impl(fla_ctx* ctx, int nsnap, const MeshDev* md, const TrajDev* td, const fla_params* ps,
+                      const fla_mesh* meshes, const fla_fields* outs, hipStream_t s, int plan, int chunk,
+                      bool use_graph)
+{
+    constexpr int TE = Geo<D>::TE;
+    // work-list order: estimated candidates per tile (trajectory density
+    // times the volume within reach of a tile at the initial bandwidth),
+    // largest first; ties keep the caller's order
+    std::vector<double> cost(nsnap);
+    for (int i = 0; i < nsnap; ++i) {
+        double vol = 1.0, reach = 1.0;
+        for (int a = 0; a < D; ++a) {
+            vol *= md[i].L[a];
+            reach *= TE * md[i].w[a] + 2.0 * ps[i].cutoff * ps[i].h0;
+        }
+        cost[i] = (double)td[i].count / vol * reach;
+    }
+    std::vector<int> order(nsnap);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+
+    std::vector<BatchItem> items(nsnap);
+    std::memset((void*)items.data(), 0, sizeof(BatchItem) * nsnap);
+    int64_t total = 0, nbk = 0, nwork = 0;
+    bool count = false;
+    for (int j = 0; j < nsnap; ++j) {
+        const int i = order[j];
+        BatchItem& it = items[j];
+        it.t = td[i];
+        it.ph = PhysDev{ps[i].rho_d, ps[i].mu, ps[i].delta, ps[i].h0, ps[i].cutoff, ps[i].scale};
+        it.hfac = ps[i].h_factor;
+        it.base = total;
+        it.key_base = (uint32_t)nbk;
+        it.tile_base = (int)nwork;
+        total += td[i].count;
+        nbk += (int64_t)kClasses * md[i].ntiles;
+        nwork += md[i].ntiles;
+        count = count || ps[i].count_pairs != 0;
+        CHECK_ARG(total < (int64_t(1) << 31), "the batch holds 2^31 or more trajectories");
+        CHECK_ARG(nbk < (int64_t(1) << 31) - 1, "the batch meshes hold too many tiles");
+    }
+    const uint32_t nb = (uint32_t)nbk;
+    const int key_bits = bits_for(nb);
+    const int64_t hist_w = radix_hist_words(total);
+    const int64_t scan_w = scan_tmp_words(hist_w > (int64_t)nb + 1 ? hist_w : (int64_t)nb + 1);
+    const int64_t n1 = total > 0 ? total : 1;
+
+    uint32_t *keys, *vals, *keys2, *vals2, *bstart, *hist, *scan;
+    double4 *rpos_u, *rpos;
+    R *rw_u, *rw;
+    auto layout = [&](Carver& c) {
+        keys = c.take<uint32_t>(n1);
+        vals = c.take<uint32_t>(n1);
+        keys2 = c.take<uint32_t>(n1);
+        vals2 = c.take<uint32_t>(n1);
+        rpos_u = c.take<double4>(n1);
+        rpos = c.take<double4>(n1);
+        rw_u = c.take<R>((size_t)n1 * kRecW);
+        rw = c.take<R>((size_t)n1 * kRecW);
+        bstart = c.take<uint32_t>((size_t)nb + 1);
+        hist = c.take<uint32_t>(hist_w > 0 ? hist_w : 1);
+        scan = c.take<uint32_t>(scan_w);
+    };
+    {
+        Carver probe(nullptr);
+        layout(probe);
+        fla_status st = ensure_ws(ctx, probe.off + 256);
+        if (st != FLA_OK) return st;
+    }
+    Carver c(ctx->ws);
+    layout(c);
+    const double cf0 = 1.0 + kSupportMargin;
+    for (int j = 0; j < nsnap; ++j) {
+        const int i = order[j];
+        GatherArgs& g = items[j].g;
+        g.m = md[i];
+        g.rpos = rpos;
+        g.rw = rw;
+        g.bstart = bstart + items[j].key_base;
+        g.cutoff = ps[i].cutoff;
+        const double cf = ps[i].cutoff * cf0;
+        g.filt2 = cf * cf;
+        g.scale = ps[i].scale;
+        g.cell_scale = meshes[i].cell_scale;
+        g.out[0] = outs[i].S_mass;
+        for (int a = 0; a < D; ++a) g.out[1 + a] = outs[i].S_mom[a];
+        g.den = outs[i].den;
+        g.stats = ctx->stats;
+    }
+
+    // the arguments a captured graph depends on
+    std::vector<unsigned char> key;
+    auto put = [&](const void* p, size_t n) {
+        const unsigned char* b = (const unsigned char*)p;
+        key.insert(key.end(), b, b + n);
+    };
+    const int shape[6] = {nsnap, D, (int)sizeof(R), plan, chunk, count ? 1 : 0};
+    put(shape, sizeof(shape));
+    put(&s, sizeof(s));
+    put(items.data(), sizeof(BatchItem) * nsnap);
+
+    if (use_graph && ctx->graph_exec && key == ctx->graph_key) {
+        HIP_OK(hipGraphLaunch(ctx->graph_exec, s));
+        HIP_OK(hipEventRecord(ctx->items_done, s));
+        ctx->items_pending = true;
+        ++ctx->graph_replays;
+        return FLA_OK;
+    }
+
+    // a new snapshot table: wait until no earlier batch call can read the old one
+    if (ctx->items_pending) HIP_OK(hipEventSynchronize(ctx->items_done));
+    ctx->items_pending = false;
+    drop_graph(ctx);
+    const size_t isz = sizeof(BatchItem) * (size_t)nsnap;
+    if (isz > ctx->items_size) {
+        if (ctx->items) HIP_OK(hipFree(ctx->items));
+        ctx->items = nullptr;
+        ctx->items_size = 0;
+        hipError_t e = hipMalloc(&ctx->items, isz);
+        if (e != hipSuccess) {
+            ctx->items = nullptr;
+            ctx->err = std::string("snapshot table allocation failed: ") + hipGetErrorString(e);
+            return FLA_ERR_OUT_OF_MEMORY;
+        }
+        ctx->items_size = isz;
+    }
+    HIP_OK(hipMemcpy(ctx->items, items.data(), isz, hipMemcpyHostToDevice));
+    if (!ctx->items_done) HIP_OK(hipEventCreateWithFlags(&ctx->items_done, hipEventDisableTiming));
+    const BatchItem* dev_items = (const BatchItem*)ctx->items;
+    const uint32_t sentinel = nb;
+
+    auto enqueue = [&](hipStream_t q) -> fla_status {
+        HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, q));
+        HIP_OK(launch_fill_u64(ctx->stats + ST_TRAJ, 1, (unsigned long long)total, q));
+        {
+            StageTimer tm(ctx, 0, q);
+            HIP_OK((launch_prepass_batch<R, D>(dev_items, nsnap, total, sentinel, keys, vals, rpos_u, rw_u, ctx->stats,
+                                               q)));
+        }
+        {
+            StageTimer tm(ctx, 1, q);
+            bool in_alt = false;
+            HIP_OK(radix_sort_pairs(keys, vals, keys2, vals2, total, key_bits, hist, hist_w, scan, scan_w, q, &in_alt));
+            const uint32_t* skeys = in_alt ? keys2 : keys;
+            const uint32_t* svals = in_alt ? vals2 : vals;
+            HIP_OK(launch_bucket_bounds(skeys, total, nb, bstart, q));
+            HIP_OK(launch_max_class_batch(dev_items, nsnap, bstart, ctx->stats, q));
+            HIP_OK(launch_permute<R>(svals, total, rpos_u, rw_u, rpos, rw, 1, q));
+        }
+        {
+            StageTimer tm(ctx, 3, q);
+            HIP_OK((launch_gather_batch<R, D>(dev_items, nsnap, (int)nwork, chunk, count, plan, q)));
+        }
+        return FLA_OK;
+    };
+
+    if (use_graph) {
+        if (!ctx->capture) HIP_OK(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+        HIP_OK(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+        const fla_status st = enqueue(ctx->capture);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
+        if (st != FLA_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            if (st != FLA_OK) return st;
+            ctx->err = std::string("graph capture failed: ") + hipGetErrorString(e);
+            return FLA_ERR_DEVICE;
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            ctx->err = std::string("graph instantiation failed: ") + hipGetErrorString(ei);
+            return FLA_ERR_DEVICE;
+        }
+        ctx->graph = graph;
+        ctx->graph_exec = exec;
+        ctx->graph_key.swap(key);
+        HIP_OK(hipGraphLaunch(exec, s));
+    } else {
+        const fla_status st = enqueue(s);
+        if (st != FLA_OK) return st;
+    }
+    HIP_OK(hipEventRecord(ctx->items_done, s));
+    ctx->items_pending = true;
+    return FLA_OK;
+}
+
 template <typename R, int D>
 fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double weight, const fla_params* p,
                         const fla_mesh* mesh, const fla_fields* out, hipStream_t s)
@@ -446,6 +664,57 @@ fla_status check_params(fla_ctx* ctx, const fla_params* p, bool projection)
     return FLA_OK;
 }
 
+// Validates a batch and runs it with the given plan and chunk (-1: the
+// context's choice) and launch form.
+fla_status batch_entry(fla_ctx* ctx, int nsnap, const fla_mesh* meshes, const fla_trajectories* trajs,
+                       const fla_params* params, const fla_fields* outs, void* stream, int plan, int chunk,
+                       bool use_graph)
+{
+    CHECK_ARG(nsnap >= 1 && nsnap <= FLA_BATCH_MAX, "nsnap must be in [1, FLA_BATCH_MAX]");
+    CHECK_ARG(meshes && trajs && params && outs, "meshes, trajs, params and outs are required");
+    const int dim = meshes[0].dim;
+    const int prec = trajs[0].prec;
+    std::vector<MeshDev> md(nsnap);
+    std::vector<TrajDev> td(nsnap);
+    for (int k = 0; k < nsnap; ++k) {
+        fla_status st = check_mesh(ctx, &meshes[k], &md[k], meshes[k].dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+        if (st == FLA_OK && meshes[k].dim != dim) {
+            ctx->err = "all snapshots must have the same mesh.dim";
+            st = FLA_ERR_INVALID_ARG;
+        }
+        if (st == FLA_OK) st = check_traj(ctx, &trajs[k], dim, true, &td[k]);
+        if (st == FLA_OK && trajs[k].prec != prec) {
+            ctx->err = "all snapshots must have the same prec";
+            st = FLA_ERR_INVALID_ARG;
+        }
+        if (st == FLA_OK) st = check_params(ctx, &params[k], true);
+        if (st == FLA_OK && params[k].mode != FLA_NW) {
+            ctx->err = "fla_project_batch supports FLA_NW only";
+            st = FLA_ERR_INVALID_ARG;
+        }
+        if (st == FLA_OK) st = check_fields(ctx, &outs[k], dim);
+        if (st != FLA_OK) {
+            ctx->err = "snapshot " + std::to_string(k) + ": " + ctx->err;
+            return st;
+        }
+    }
+    HIP_OK(hipSetDevice(ctx->device));
+    const int d = dim - 2;
+    if (plan < 0) plan = ctx->batch_plan[d][prec] < 0 ? kDefaultPlan : ctx->batch_plan[d][prec];
+    if (chunk < 0) chunk = ctx->batch_chunk[d][prec] < 0 ? kDefaultChunk : ctx->batch_chunk[d][prec];
+    hipStream_t s = (hipStream_t)stream;
+    const bool f64 = prec == FLA_F64;
+    if (dim == 2)
+        return f64 ? batch_impl<double, 2>(ctx, nsnap, md.data(), td.data(), params, meshes, outs, s, plan, chunk,
+                                           use_graph)
+                   : batch_impl<float, 2>(ctx, nsnap, md.data(), td.data(), params, meshes, outs, s, plan, chunk,
+                                          use_graph);
+    return f64 ? batch_impl<double, 3>(ctx, nsnap, md.data(), td.data(), params, meshes, outs, s, plan, chunk,
+                                       use_graph)
+               : batch_impl<float, 3>(ctx, nsnap, md.data(), td.data(), params, meshes, outs, s, plan, chunk,
+                                      use_graph);
+}
+
 }  // namespace
 
 static void drop_records(fla_ctx* ctx);
@@ -496,6 +765,10 @@ FLA_EXPORT fla_status fla_ctx_destroy(fla_ctx* ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     drop_records(ctx);
+    drop_graph(ctx);
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
+    if (ctx->items_done) (void)hipEventDestroy(ctx->items_done);
+    if (ctx->items) (void)hipFree(ctx->items);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->stats) (void)hipFree(ctx->stats);
     delete ctx;
@@ -586,7 +859,7 @@ FLA_EXPORT fla_status fla_get_stats(fla_ctx* ctx, fla_stats* out)
     out->outside = (int64_t)h[ST_OUTSIDE];
     out->zero_support = (int64_t)h[ST_ZERO];
     out->max_class = (int64_t)h[ST_MAXCLASS];
-    out->reserved = 0;
+    out->graph_replays = ctx->graph_replays;
     return FLA_OK;
 }
 
@@ -848,6 +1121,106 @@ FLA_EXPORT fla_status fla_autotune(fla_ctx* ctx, const fla_mesh* mesh, const fla
     }
     ctx->plan[d][pr] = best_plan;
     (void)s;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_project_batch(fla_ctx* ctx, int nsnap, const fla_mesh* meshes,
+                                        const fla_trajectories* trajs, const fla_params* params,
+                                        const fla_fields* outs, void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    try {
+        return batch_entry(ctx, nsnap, meshes, trajs, params, outs, stream, -1, -1, ctx->batch_graph && !ctx->prof);
+    } catch (...) {
+        ctx->err = "internal error";
+        return FLA_ERR_DEVICE;
+    }
+}
+
+FLA_EXPORT fla_status fla_set_batch_graph(fla_ctx* ctx, int enable)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    HIP_OK(hipSetDevice(ctx->device));
+    if (ctx->items_pending) HIP_OK(hipEventSynchronize(ctx->items_done));
+    ctx->items_pending = false;
+    drop_graph(ctx);
+    ctx->batch_graph = enable != 0;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_set_batch_plan(fla_ctx* ctx, int dim, int prec, int gather_plan, int chunk)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(dim == 2 || dim == 3, "dim must be 2 or 3");
+    CHECK_ARG(prec == FLA_F32 || prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
+    CHECK_ARG(gather_plan >= -1 && gather_plan < kGatherPlans, "gather_plan out of range");
+    CHECK_ARG(gather_plan == -1 || (chunk >= 1 && chunk <= 4096), "chunk must be in [1, 4096]");
+    ctx->batch_plan[dim - 2][prec] = gather_plan;
+    ctx->batch_chunk[dim - 2][prec] = gather_plan < 0 ? -1 : chunk;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_get_batch_plan(fla_ctx* ctx, int dim, int prec, int* gather_plan, int* chunk)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(dim == 2 || dim == 3, "dim must be 2 or 3");
+    CHECK_ARG(prec == FLA_F32 || prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
+    CHECK_ARG(gather_plan != nullptr && chunk != nullptr, "gather_plan and chunk are required");
+    const int p = ctx->batch_plan[dim - 2][prec], c = ctx->batch_chunk[dim - 2][prec];
+    *gather_plan = p < 0 ? kDefaultPlan : p;
+    *chunk = c < 0 ? kDefaultChunk : c;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_autotune_batch(fla_ctx* ctx, int nsnap, const fla_mesh* meshes,
+                                         const fla_trajectories* trajs, const fla_params* params,
+                                         const fla_fields* outs, void* stream, double* times_ms)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(nsnap >= 1 && meshes && trajs, "meshes and trajs are required");
+    CHECK_ARG(meshes[0].dim == 2 || meshes[0].dim == 3, "mesh.dim must be 2 or 3");
+    CHECK_ARG(trajs[0].prec == FLA_F32 || trajs[0].prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
+    const int d = meshes[0].dim - 2, pr = trajs[0].prec;
+    const bool was_prof = ctx->prof;
+    double best = 1e300;
+    int best_plan = -1, best_chunk = -1;
+    fla_status st = FLA_OK;
+    try {
+        for (int plan = 0; plan < kGatherPlans && st == FLA_OK; ++plan)
+            for (int ci = 0; ci < FLA_BATCH_CHUNKS && st == FLA_OK; ++ci) {
+                // first call warms the workspace, the second is timed
+                st = fla_profile_enable(ctx, 0);
+                if (st == FLA_OK)
+                    st = batch_entry(ctx, nsnap, meshes, trajs, params, outs, stream, plan, kChunkChoices[ci], false);
+                if (st == FLA_OK) st = fla_profile_enable(ctx, 1);
+                if (st == FLA_OK)
+                    st = batch_entry(ctx, nsnap, meshes, trajs, params, outs, stream, plan, kChunkChoices[ci], false);
+                fla_profile pf;
+                if (st == FLA_OK) st = fla_profile_read(ctx, &pf);
+                if (st != FLA_OK) break;
+                const double ms = pf.launches[3] ? pf.ms[3] / (double)pf.launches[3] : 1e300;
+                if (times_ms) times_ms[plan * FLA_BATCH_CHUNKS + ci] = ms;
+                if (ms < best) {
+                    best = ms;
+                    best_plan = plan;
+                    best_chunk = kChunkChoices[ci];
+                }
+            }
+    } catch (...) {
+        ctx->err = "internal error";
+        st = FLA_ERR_DEVICE;
+    }
+    const std::string err = ctx->err;
+    (void)fla_profile_enable(ctx, was_prof ? 1 : 0);
+    ctx->err = err;
+    if (st != FLA_OK) return st;
+    ctx->batch_plan[d][pr] = best_plan;
+    ctx->batch_chunk[d][pr] = best_chunk;
     return FLA_OK;
 }
 

@@ -59,8 +59,9 @@ struct GatherLds {
     int mask[kWave];                   // sub-blocks holding at least one included pair
 };
 
+// The work of one workgroup: every cell of tile `tile` of the mesh of g.
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
-__global__ __launch_bounds__(kWave * GatherWaves<D>::value, sizeof(R) == 4 ? 2 : 1) void k_gather(GatherArgs g)
+__device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
 {
     constexpr int kGatherWaves = GatherWaves<D>::value;
     using G = Geo<D>;
@@ -77,7 +78,6 @@ __global__ __launch_bounds__(kWave * GatherWaves<D>::value, sizeof(R) == 4 ? 2 :
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     L& my = lds[wave];
-    const int tile = xcd_remap(blockIdx.x, m.ntiles);
     int tc[3];
     tc[0] = tile % m.nt[0];
     tc[1] = (tile / m.nt[0]) % m.nt[1];
@@ -443,6 +443,43 @@ __global__ __launch_bounds__(kWave * GatherWaves<D>::value, sizeof(R) == 4 ? 2 :
     }
 }
 
+template <typename R, int D, int MODE, bool COUNT, int PLAN>
+__global__ __launch_bounds__(kWave * GatherWaves<D>::value, sizeof(R) == 4 ? 2 : 1) void k_gather(GatherArgs g)
+{
+    gather_tile<R, D, MODE, COUNT, PLAN>(g, xcd_remap(blockIdx.x, g.m.ntiles));
+}
+
+// Work item of workgroup `bid` of a batch of `nwork` items.  Workgroups are
+// dealt round-robin over the XCDs in launch order; in every full chunk of
+// kXcds * chunk items, XCD x receives the `chunk` consecutive items
+// x * chunk ... x * chunk + chunk - 1, so neighbouring tiles of one snapshot
+// share an L2 while the chunks still start in work-list order.
+__device__ inline int batch_work_item(int bid, int nwork, int chunk)
+{
+    const int span = kXcds * chunk;
+    const int c = bid / span, off = bid % span;
+    if ((c + 1) * span > nwork) return bid;
+    return c * span + (off % kXcds) * chunk + off / kXcds;
+}
+
+// One workgroup per (snapshot, tile) of a batch.  The snapshots are stored in
+// work-list order: items[s].tile_base is the first work item of snapshot s.
+template <typename R, int D, int MODE, bool COUNT, int PLAN>
+__global__ __launch_bounds__(kWave * GatherWaves<D>::value, sizeof(R) == 4 ? 2 : 1) void k_gather_batch(
+    const BatchItem* __restrict__ items, int nsnap, int nwork, int chunk)
+{
+    const int j = batch_work_item(blockIdx.x, nwork, chunk);
+    int lo = 0, hi = nsnap - 1;   // last snapshot whose first work item is <= j
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile_base <= j)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    gather_tile<R, D, MODE, COUNT, PLAN>(items[lo].g, j - items[lo].tile_base);
+}
+
 template <typename R, int D, int MODE, bool COUNT>
 static void launch_plan(const GatherArgs& g, int plan, dim3 grid, dim3 block, hipStream_t s)
 {
@@ -452,6 +489,30 @@ static void launch_plan(const GatherArgs& g, int plan, dim3 grid, dim3 block, hi
     case 3: hipLaunchKernelGGL((k_gather<R, D, MODE, COUNT, 3>), grid, block, 0, s, g); break;
     default: hipLaunchKernelGGL((k_gather<R, D, MODE, COUNT, 0>), grid, block, 0, s, g); break;
     }
+}
+
+template <typename R, int D, bool COUNT>
+static void launch_batch_plan(const BatchItem* items, int nsnap, int nwork, int chunk, int plan, hipStream_t s)
+{
+    dim3 grid((unsigned)nwork), block(kWave * GatherWaves<D>::value);
+    switch (plan) {
+    case 1: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 1>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    case 2: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 2>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    case 3: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 3>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    default: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 0>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    }
+}
+
+template <typename R, int D>
+hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan,
+                               hipStream_t s)
+{
+    if (nwork <= 0) return hipSuccess;
+    if (count)
+        launch_batch_plan<R, D, true>(items, nsnap, nwork, chunk, plan, s);
+    else
+        launch_batch_plan<R, D, false>(items, nsnap, nwork, chunk, plan, s);
+    return hipGetLastError();
 }
 
 template <typename R, int D>
@@ -476,5 +537,9 @@ template hipError_t launch_gather<float, 2>(const GatherArgs&, int, bool, int, h
 template hipError_t launch_gather<float, 3>(const GatherArgs&, int, bool, int, hipStream_t);
 template hipError_t launch_gather<double, 2>(const GatherArgs&, int, bool, int, hipStream_t);
 template hipError_t launch_gather<double, 3>(const GatherArgs&, int, bool, int, hipStream_t);
+template hipError_t launch_gather_batch<float, 2>(const BatchItem*, int, int, int, bool, int, hipStream_t);
+template hipError_t launch_gather_batch<float, 3>(const BatchItem*, int, int, int, bool, int, hipStream_t);
+template hipError_t launch_gather_batch<double, 2>(const BatchItem*, int, int, int, bool, int, hipStream_t);
+template hipError_t launch_gather_batch<double, 3>(const BatchItem*, int, int, int, bool, int, hipStream_t);
 
 }  // namespace flp

@@ -20,6 +20,26 @@ struct GatherArgs {
     unsigned long long* stats;
 };
 
+// One snapshot of a batched projection (device table entry).
+struct BatchItem {
+    GatherArgs g;            // mesh, sorted-record views and outputs of the snapshot
+    TrajDev t;
+    PhysDev ph;
+    const float* hfac;
+    int64_t base;            // first global trajectory index of the snapshot
+    uint32_t key_base;       // first global bucket of the snapshot
+    int tile_base;           // first work item (tile) of the snapshot in the gather launch
+};
+
+template <typename R, int D>
+hipError_t launch_prepass_batch(const BatchItem* items, int nsnap, int64_t total, uint32_t sentinel, uint32_t* keys,
+                                uint32_t* vals, double4* rpos, R* rw, unsigned long long* stats, hipStream_t s);
+hipError_t launch_max_class_batch(const BatchItem* items, int nsnap, const uint32_t* bstart,
+                                  unsigned long long* stats, hipStream_t s);
+template <typename R, int D>
+hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan,
+                               hipStream_t s);
+
 template <typename R, int D>
 hipError_t launch_prepass(const TrajDev& t, const MeshDev& m, const PhysDev& ph, const float* hfac,
                           int deposit, uint32_t* keys, uint32_t* vals, double4* rpos, R* rw,

@@ -13,132 +13,171 @@ __device__ inline void block_add_stats(unsigned long long* stats, int slot, unsi
     if ((threadIdx.x % kWave) == 0 && v) atomicAdd(&stats[slot], v);
 }
 
-// One thread per trajectory.  Writes the sort key (neighbourhood class and
-// home tile), the unsorted position record {x, y, z, 1/h} and weight record
-// {1/h, q/h} (or, in deposition mode, the binary64 amounts Q to qd).
+// Per-trajectory prepass of trajectory i of one snapshot, written at global
+// index gi.  Writes the sort key (key_base + neighbourhood class * ntiles +
+// home tile, or `sentinel`), the unsorted position record {x, y, z, 1/h} and
+// weight record {1/h, q/h} (or, in deposition mode, the binary64 amounts Q to
+// qd).  Returns 1 in `skipped` / `nosup` when the trajectory is skipped or
+// reaches no cell centre.
+template <typename R, int D>
+__device__ inline void prepass_one(const TrajDev& t, const MeshDev& m, const PhysDev& ph, const float* hfac,
+                                   int deposit, int64_t i, int64_t gi, uint32_t key_base, uint32_t sentinel,
+                                   uint32_t* keys, uint32_t* vals, double4* rpos, R* rw, double* qd,
+                                   unsigned long long& skipped, unsigned long long& nosup)
+{
+    constexpr int TE = Geo<D>::TE;
+    constexpr int C = D + 1;
+    const int64_t N = t.count;
+    double x[3] = {0, 0, 0}, J[9], v[3], ug[3];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        x[a] = t.x[a][i];
+        v[a] = (double)((const R*)t.v[a])[i];
+        ug[a] = (double)((const R*)t.ug[a])[i];
+        ok = ok && isfinite(x[a]) && isfinite(v[a]) && isfinite(ug[a]);
+    }
+#pragma unroll
+    for (int e = 0; e < D * D; ++e) {
+        J[e] = t.J[(int64_t)e * N + i];
+        ok = ok && isfinite(J[e]);
+    }
+    double r = (double)((const R*)t.r)[i];
+    double n0 = t.n0 ? t.n0[i] : t.n0_scalar;
+    double fac = hfac ? (double)hfac[i] : 1.0;
+    double det = det_rn<D>(J);
+    double adet = fabs(det);
+    ok = ok && isfinite(r) && isfinite(n0) && isfinite(det) && det != 0.0 && isfinite(fac) && fac > 0.0;
+    double h, n, phi[4] = {0, 0, 0, 0};
+    {
+#pragma clang fp contract(off)
+        h = ph.h0 * adet;
+        h = h * fac;
+    }
+    n = n0 / adet;
+    if (ok) droplet_phi<D>(r, v, ug, ph, phi);
+    if (ok) {
+        ok = isfinite(h) && h > 0.0 && isfinite(n);
+#pragma unroll
+        for (int k = 0; k < C; ++k) ok = ok && isfinite(phi[k]);
+    }
+    uint32_t key = sentinel;
+    if (!ok) {
+        skipped = 1;
+    } else {
+        double inv_h = 1.0 / h;
+        double rc = ph.cutoff * h * (1.0 + kSupportMargin);
+        int64_t ht[3] = {0, 0, 0};
+        int reach = 0;
+        bool support = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double g = floor((x[a] - m.lo[a]) / m.w[a]);
+            g = fmin(fmax(g, -4.0e15), 4.0e15);
+            int64_t hc = (int64_t)g;
+            double flo = (x[a] - rc - m.lo[a]) / m.w[a] - 0.5 - 1e-9;
+            double fhi = (x[a] + rc - m.lo[a]) / m.w[a] - 0.5 + 1e-9;
+            flo = fmin(fmax(flo, -4.0e15), 4.0e15);
+            fhi = fmin(fmax(fhi, -4.0e15), 4.0e15);
+            int64_t ilo = (int64_t)ceil(flo), ihi = (int64_t)floor(fhi);
+            int64_t ra;
+            if (m.periodic[a]) {
+                // tile distances are circular: the last tile of an axis whose
+                // cell count is not a multiple of TE is short, so wrapped cells
+                // are mapped back into [0, n) before taking their tile
+                int64_t wrapped = posmod(hc, m.n[a]);
+                int64_t sh = wrapped - hc;
+                hc = wrapped;
+                ilo += sh;
+                ihi += sh;
+                ht[a] = hc / TE;
+                if (ilo > ihi) {
+                    support = false;
+                    ra = 0;
+                } else if (ihi - ilo + 1 >= m.n[a]) {
+                    ra = m.nt[a];
+                } else {
+                    int64_t tl = posmod(ilo, m.n[a]) / TE, tr = posmod(ihi, m.n[a]) / TE;
+                    int64_t dl = ilo > hc ? 0 : posmod(ht[a] - tl, m.nt[a]);
+                    int64_t dr = ihi < hc ? 0 : posmod(tr - ht[a], m.nt[a]);
+                    ra = dl > dr ? dl : dr;
+                }
+            } else {
+                hc = hc < 0 ? 0 : (hc >= m.n[a] ? m.n[a] - 1 : hc);
+                ilo = ilo < 0 ? 0 : ilo;
+                ihi = ihi >= m.n[a] ? m.n[a] - 1 : ihi;
+                if (ilo > ihi) support = false;
+                ht[a] = hc / TE;
+                int64_t tlo = floordiv(ilo, TE), thi = floordiv(ihi, TE);
+                ra = ht[a] - tlo;
+                if (thi - ht[a] > ra) ra = thi - ht[a];
+            }
+            if (ra < 0) ra = 0;
+            if (ra > kClasses) ra = kClasses;
+            if ((int)ra > reach) reach = (int)ra;
+        }
+        // In deposition mode a trajectory that reaches no cell centre still
+        // deposits its whole amount into its home cell, so it is kept.
+        if (!support) nosup = 1;
+        if (support || deposit) {
+            int cls = !support ? 0 : (reach < kClasses - 1 ? reach : kClasses - 1);
+            int64_t tl = ht[0] + (int64_t)m.nt[0] * (ht[1] + (int64_t)m.nt[1] * ht[2]);
+            key = key_base + (uint32_t)cls * (uint32_t)m.ntiles + (uint32_t)tl;
+        }
+        rpos[gi] = make_double4(x[0], x[1], x[2], inv_h);
+        R* w = rw + gi * kRecW;
+        w[0] = (R)inv_h;
+        if (deposit) {
+            double sc = t.seed_volume * adet;
+#pragma unroll
+            for (int k = 0; k < C; ++k) qd[(int64_t)k * N + i] = (n * phi[k]) * sc;
+        } else {
+#pragma unroll
+            for (int k = 0; k < C; ++k) w[1 + k] = (R)(inv_h * (n * phi[k]));
+        }
+    }
+    keys[gi] = key;
+    vals[gi] = (uint32_t)gi;
+}
+
+// One thread per trajectory of one snapshot.
 template <typename R, int D>
 __global__ __launch_bounds__(256) void k_prepass(TrajDev t, MeshDev m, PhysDev ph, const float* hfac,
                                                  int deposit, uint32_t* keys, uint32_t* vals,
                                                  double4* rpos, R* rw, double* qd,
                                                  unsigned long long* stats)
 {
-    constexpr int TE = Geo<D>::TE;
-    constexpr int C = D + 1;
-    const int64_t N = t.count;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t sentinel = (uint32_t)kClasses * (uint32_t)m.ntiles;
     unsigned long long skipped = 0, nosup = 0;
-    if (i < N) {
-        double x[3] = {0, 0, 0}, J[9], v[3], ug[3];
-        bool ok = true;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            x[a] = t.x[a][i];
-            v[a] = (double)((const R*)t.v[a])[i];
-            ug[a] = (double)((const R*)t.ug[a])[i];
-            ok = ok && isfinite(x[a]) && isfinite(v[a]) && isfinite(ug[a]);
+    if (i < t.count)
+        prepass_one<R, D>(t, m, ph, hfac, deposit, i, i, 0u, sentinel, keys, vals, rpos, rw, qd, skipped, nosup);
+    block_add_stats(stats, ST_SKIPPED, skipped);
+    block_add_stats(stats, ST_NOSUPPORT, nosup);
+}
+
+// One thread per trajectory of a batch of snapshots: trajectories of
+// snapshot s occupy global indices [item.base, item.base + count) and their
+// keys the bucket range [item.key_base, item.key_base + kClasses * ntiles).
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_prepass_batch(const BatchItem* items, int nsnap, int64_t total,
+                                                       uint32_t sentinel, uint32_t* keys, uint32_t* vals,
+                                                       double4* rpos, R* rw, unsigned long long* stats)
+{
+    int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long skipped = 0, nosup = 0;
+    if (gi < total) {
+        int lo = 0, hi = nsnap - 1;      // last item with base <= gi
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (items[mid].base <= gi)
+                lo = mid;
+            else
+                hi = mid - 1;
         }
-#pragma unroll
-        for (int e = 0; e < D * D; ++e) {
-            J[e] = t.J[(int64_t)e * N + i];
-            ok = ok && isfinite(J[e]);
-        }
-        double r = (double)((const R*)t.r)[i];
-        double n0 = t.n0 ? t.n0[i] : t.n0_scalar;
-        double fac = hfac ? (double)hfac[i] : 1.0;
-        double det = det_rn<D>(J);
-        double adet = fabs(det);
-        ok = ok && isfinite(r) && isfinite(n0) && isfinite(det) && det != 0.0 && isfinite(fac) && fac > 0.0;
-        double h, n, phi[4] = {0, 0, 0, 0};
-        {
-#pragma clang fp contract(off)
-            h = ph.h0 * adet;
-            h = h * fac;
-        }
-        n = n0 / adet;
-        if (ok) droplet_phi<D>(r, v, ug, ph, phi);
-        if (ok) {
-            ok = isfinite(h) && h > 0.0 && isfinite(n);
-#pragma unroll
-            for (int k = 0; k < C; ++k) ok = ok && isfinite(phi[k]);
-        }
-        uint32_t key = sentinel;
-        if (!ok) {
-            skipped = 1;
-        } else {
-            double inv_h = 1.0 / h;
-            double rc = ph.cutoff * h * (1.0 + kSupportMargin);
-            int64_t ht[3] = {0, 0, 0};
-            int reach = 0;
-            bool support = true;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                double g = floor((x[a] - m.lo[a]) / m.w[a]);
-                g = fmin(fmax(g, -4.0e15), 4.0e15);
-                int64_t hc = (int64_t)g;
-                double flo = (x[a] - rc - m.lo[a]) / m.w[a] - 0.5 - 1e-9;
-                double fhi = (x[a] + rc - m.lo[a]) / m.w[a] - 0.5 + 1e-9;
-                flo = fmin(fmax(flo, -4.0e15), 4.0e15);
-                fhi = fmin(fmax(fhi, -4.0e15), 4.0e15);
-                int64_t ilo = (int64_t)ceil(flo), ihi = (int64_t)floor(fhi);
-                int64_t ra;
-                if (m.periodic[a]) {
-                    // tile distances are circular: the last tile of an axis whose
-                    // cell count is not a multiple of TE is short, so wrapped cells
-                    // are mapped back into [0, n) before taking their tile
-                    int64_t wrapped = posmod(hc, m.n[a]);
-                    int64_t sh = wrapped - hc;
-                    hc = wrapped;
-                    ilo += sh;
-                    ihi += sh;
-                    ht[a] = hc / TE;
-                    if (ilo > ihi) {
-                        support = false;
-                        ra = 0;
-                    } else if (ihi - ilo + 1 >= m.n[a]) {
-                        ra = m.nt[a];
-                    } else {
-                        int64_t tl = posmod(ilo, m.n[a]) / TE, tr = posmod(ihi, m.n[a]) / TE;
-                        int64_t dl = ilo > hc ? 0 : posmod(ht[a] - tl, m.nt[a]);
-                        int64_t dr = ihi < hc ? 0 : posmod(tr - ht[a], m.nt[a]);
-                        ra = dl > dr ? dl : dr;
-                    }
-                } else {
-                    hc = hc < 0 ? 0 : (hc >= m.n[a] ? m.n[a] - 1 : hc);
-                    ilo = ilo < 0 ? 0 : ilo;
-                    ihi = ihi >= m.n[a] ? m.n[a] - 1 : ihi;
-                    if (ilo > ihi) support = false;
-                    ht[a] = hc / TE;
-                    int64_t tlo = floordiv(ilo, TE), thi = floordiv(ihi, TE);
-                    ra = ht[a] - tlo;
-                    if (thi - ht[a] > ra) ra = thi - ht[a];
-                }
-                if (ra < 0) ra = 0;
-                if (ra > kClasses) ra = kClasses;
-                if ((int)ra > reach) reach = (int)ra;
-            }
-            // In deposition mode a trajectory that reaches no cell centre still
-            // deposits its whole amount into its home cell, so it is kept.
-            if (!support) nosup = 1;
-            if (support || deposit) {
-                int cls = !support ? 0 : (reach < kClasses - 1 ? reach : kClasses - 1);
-                int64_t tl = ht[0] + (int64_t)m.nt[0] * (ht[1] + (int64_t)m.nt[1] * ht[2]);
-                key = (uint32_t)cls * (uint32_t)m.ntiles + (uint32_t)tl;
-            }
-            rpos[i] = make_double4(x[0], x[1], x[2], inv_h);
-            R* w = rw + i * kRecW;
-            w[0] = (R)inv_h;
-            if (deposit) {
-                double sc = t.seed_volume * adet;
-#pragma unroll
-                for (int k = 0; k < C; ++k) qd[(int64_t)k * N + i] = (n * phi[k]) * sc;
-            } else {
-#pragma unroll
-                for (int k = 0; k < C; ++k) w[1 + k] = (R)(inv_h * (n * phi[k]));
-            }
-        }
-        keys[i] = key;
-        vals[i] = (uint32_t)i;
+        const BatchItem& it = items[lo];
+        prepass_one<R, D>(it.t, it.g.m, it.ph, it.hfac, 0, gi - it.base, gi, it.key_base, sentinel, keys, vals, rpos,
+                          rw, nullptr, skipped, nosup);
     }
     block_add_stats(stats, ST_SKIPPED, skipped);
     block_add_stats(stats, ST_NOSUPPORT, nosup);
@@ -152,6 +191,25 @@ __global__ void k_max_class(const uint32_t* bstart, int ntiles, unsigned long lo
     for (int k = 0; k < kClasses; ++k)
         if (bstart[(int64_t)k * ntiles] != bstart[(int64_t)(k + 1) * ntiles]) mc = (unsigned long long)k;
     stats[ST_MAXCLASS] = mc;
+}
+
+// Largest non-empty class over the snapshots of a batch (one wave).
+__global__ void k_max_class_batch(const BatchItem* items, int nsnap, const uint32_t* bstart,
+                                  unsigned long long* stats)
+{
+    unsigned long long mc = 0;
+    for (int s = threadIdx.x; s < nsnap; s += kWave) {
+        const uint32_t* b = bstart + items[s].key_base;
+        const int64_t nt = items[s].g.m.ntiles;
+        for (int k = 0; k < kClasses; ++k)
+            if (b[k * nt] != b[(k + 1) * nt] && (unsigned long long)k > mc) mc = (unsigned long long)k;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long t = __shfl_xor(mc, o, kWave);
+        mc = t > mc ? t : mc;
+    }
+    if (threadIdx.x == 0) stats[ST_MAXCLASS] = mc;
 }
 
 // Bucket starts from sorted keys: bstart[b] = first position with key >= b
@@ -309,6 +367,13 @@ hipError_t launch_max_class(const uint32_t* bstart, int ntiles, unsigned long lo
     return hipGetLastError();
 }
 
+hipError_t launch_max_class_batch(const BatchItem* items, int nsnap, const uint32_t* bstart,
+                                  unsigned long long* stats, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_max_class_batch, dim3(1), dim3(kWave), 0, s, items, nsnap, bstart, stats);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_permute(const uint32_t* order, int64_t n, const double4* rpos_u, const R* rw_u,
                           double4* rpos, R* rw, int copy_w, hipStream_t s)
@@ -330,7 +395,21 @@ hipError_t launch_deposit_norm(const MeshDev& m, const PhysDev& ph, const uint32
     return hipGetLastError();
 }
 
+template <typename R, int D>
+hipError_t launch_prepass_batch(const BatchItem* items, int nsnap, int64_t total, uint32_t sentinel, uint32_t* keys,
+                                uint32_t* vals, double4* rpos, R* rw, unsigned long long* stats, hipStream_t s)
+{
+    if (total == 0) return hipSuccess;
+    unsigned nb = (unsigned)((total + 255) / 256);
+    hipLaunchKernelGGL((k_prepass_batch<R, D>), dim3(nb), dim3(256), 0, s, items, nsnap, total, sentinel, keys, vals,
+                       rpos, rw, stats);
+    return hipGetLastError();
+}
+
 #define FLP_INST(R, D)                                                                              \
+    template hipError_t launch_prepass_batch<R, D>(const BatchItem*, int, int64_t, uint32_t, uint32_t*, \
+                                                   uint32_t*, double4*, R*, unsigned long long*,     \
+                                                   hipStream_t);                                     \
     template hipError_t launch_prepass<R, D>(const TrajDev&, const MeshDev&, const PhysDev&,        \
                                              const float*, int, uint32_t*, uint32_t*, double4*, R*, \
                                              double*, unsigned long long*, hipStream_t);            \

@@ -27,6 +27,18 @@ def as_precision(tr: W.Trajectories, prec: str) -> W.Trajectories:
     return W.Trajectories(tr.x, tr.J, f(tr.v), f(tr.ug), f(tr.r), tr.n0, tr.seed_volume)
 
 
+def device_traj(tr: W.Trajectories, prec: str):
+    """Device copies of a trajectory record in the call's precision; returns
+    (fla_trajectories struct, tensors to keep alive)."""
+    import paper_2512_20829_amd as F
+    dt = torch.float64 if prec == "f64" else torch.float32
+    dev = torch.device("cuda", 0)
+    n0 = tr.n0.to(dev) if isinstance(tr.n0, torch.Tensor) else tr.n0
+    return F.make_trajectories(tr.x.to(dev, torch.float64).contiguous(), tr.J.to(dev, torch.float64).contiguous(),
+                               tr.v.to(dev, dt).contiguous(), tr.ug.to(dev, dt).contiguous(),
+                               tr.r.to(dev, dt).contiguous(), n0, tr.seed_volume)
+
+
 def gpu_run(ctx, wl: W.Workload, prec: str = None, mode: int = 0, count_pairs: bool = True,
             scale: float = 1.0, cell_scale=None, h_factor=None, psicell_cloud=None, weight: float = 1.0,
             traj: W.Trajectories = None):
