@@ -15,6 +15,9 @@ its fused epilogue.  Printed as one JSON line (rank 0):
   pairs_per_s  included trajectory-cell pairs per second
   roofline     the gather kernel, timed with HIP events on the library's
                stream: algorithmic flops per launch / average launch time
+  large        the 256^3 multi-vortex case (32.8M trajectories, caustics):
+               plain and learned throughput, plain / learned / deposition
+               errors against a 1.68G-particle PSI-CELL reference
   cpu_baseline the FP64 oracle on a bounded sample of the same workload
   batch        64 uneven snapshots (32^3..128^3 meshes, 10k..2M trajectories)
                through fla_project_batch: graph replays, direct launches and
@@ -90,6 +93,118 @@ def _psicell_reference(ctx, F, W, torch, mesh, abc, n_particles, seed, params, d
     ref = [(a + b) * 0.5 for a, b in zip(*halves)]
     floor = [float(((a - b) ** 2).double().sum() / (4 * (r.double() ** 2).sum())) for a, b, r in zip(*halves, ref)]
     return ref, floor
+
+
+def _psicell_reference_chunked(ctx, F, torch, mesh, cloud_fn, n_particles, chunk, params, dev):
+    """Dense PSI-CELL reference as the mean of two independent half clouds,
+    each accumulated in chunks of at most `chunk` particles (cloud_fn(n,
+    offset) draws particles offset..offset+n-1 of one seeded stream), with
+    the per-channel noise floor |A - B|^2 / (4 |R|^2)."""
+    import workloads as W
+    half = n_particles // 2
+    halves = []
+    for h in range(2):
+        acc, done = None, 0
+        while done < half:
+            n = min(chunk, half - done)
+            cl = cloud_fn(n, h * half + done)
+            st, keep = F.make_trajectories(cl.x, None, cl.v.float(), cl.ug.float(), cl.r.float(), 1.0)
+            del cl
+            Sm, Sv, _ = F.alloc_fields(mesh.cells, mesh.dim, torch.float32, dev, den=False)
+            ctx.psicell_accumulate(F.mesh_of(mesh), st, W.N0_DEFAULT / half, params, Sm, Sv)
+            part = [t.double() for t in (Sm, *Sv)]
+            acc = part if acc is None else [a + b for a, b in zip(acc, part)]
+            del st, keep, Sm, Sv, part
+            done += n
+        halves.append(acc)
+    ref = [((a + b) * 0.5).float() for a, b in zip(*halves)]
+    floor = [float(((a - b) ** 2).sum() / ((a + b) ** 2).sum()) for a, b in zip(*halves)]
+    del halves
+    torch.cuda.empty_cache()
+    return ref, floor
+
+
+def large_section(ctx, args, dev, model):
+    """The 256^3 multi-vortex case with strong caustics: 32.8M lattice
+    trajectories (320^3), plain throughput, and the plain, learned (the
+    network trained on the 64^3 ABC snapshots, if available) and deposition
+    errors against a chunked PSI-CELL reference, at 320^3, 256^3 and 200^3
+    trajectories."""
+    import numpy as np
+    import torch
+
+    import paper_2512_20829_amd as F
+    import workloads as W
+    from paper_2512_20829_amd import train as T
+
+    t0 = time.time()
+    mesh = W.unit_mesh(3, 256, True)
+    p = F.Params(rho_d=W.RHO_D, mu=W.MU_AIR, delta=W.DELTA_EVAP, h0=1.0 / 320, cutoff=4.0)
+    ref, floor = _psicell_reference_chunked(
+        ctx, F, torch, mesh, lambda n, off: W.multi_vortex_cloud(n, seed=0, device=dev, offset=off),
+        args.large_particles, 200_000_000, p, dev)
+    log(f"large: PSI-CELL reference of {args.large_particles} particles in {time.time() - t0:.1f} s; "
+        f"noise floor {[round(math.sqrt(f), 4) for f in floor]}")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows, perf = [], None
+    for pa in (320, 256, 200):
+        wl = W.c5_multi_vortex(per_axis=pa, mesh_n=256, device=dev)
+        tr = wl.traj
+        st, keep = F.make_trajectories(tr.x, tr.J, tr.v.float(), tr.ug.float(), tr.r.float(), tr.n0, tr.seed_volume)
+        wl.traj = None
+        del tr
+        prm = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
+        snap = T.Snapshot(wl.mesh, st, keep, pa ** 3, prm, ref)
+        M = wl.mesh.cells
+        Sm, Sv, den = F.alloc_fields(M, 3, torch.float32, dev)
+        out = {"trajectories": pa ** 3}
+        if pa == 320:
+            counted = F.Params(**{**prm.__dict__, "count_pairs": True})
+            ctx.project_sources(F.mesh_of(wl.mesh), st, counted, Sm, Sv, den)
+            torch.cuda.synchronize()
+            stt = ctx.stats()
+            reps = 3
+            forms = [("plain", None)] + ([("learned", model)] if model is not None else [])
+            perf = {"pairs": stt["pairs"], "skipped": stt["skipped"], "no_support": stt["no_support"],
+                    "max_class": stt["max_class"]}
+            for name, mdl in forms:
+                ctx.project_sources(F.mesh_of(wl.mesh), st, prm, Sm, Sv)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    h = mdl.factors(snap)[0] if mdl is not None else None
+                    ctx.project_sources(F.mesh_of(wl.mesh), st, F.Params(**{**prm.__dict__, "h_factor": h}), Sm, Sv)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                perf[f"ms_{name}"] = round(ms, 3)
+                perf[f"cells_per_s_{name}"] = M / (ms * 1e-3)
+            perf["pairs_per_s_plain"] = stt["pairs"] / (perf["ms_plain"] * 1e-3)
+        helper = model if model is not None else T.BandwidthModel(ctx, T.initial_theta(0))
+        forms = [("plain", None, F.FLA_NW), ("deposit", None, F.FLA_DEPOSIT)]
+        if model is not None:
+            forms.insert(1, ("learned", model.factors(snap)[0], F.FLA_NW))
+        for name, h, mode in forms:
+            q = F.Params(**{**prm.__dict__, "h_factor": h, "mode": mode})
+            ctx.project_sources(F.mesh_of(wl.mesh), st, q, Sm, Sv, den)
+            res, _ = helper.loss(snap, [Sm, *Sv], False)
+            r = res.cpu().numpy()
+            out[name] = round(float(np.mean([math.sqrt(max(r[1 + 2 * k] / r[2 + 2 * k] - floor[k], 0.0))
+                                             for k in range(4)])), 5)
+        rows.append(out)
+        log(f"large: {out}")
+        del snap, st, keep, Sm, Sv, den, wl
+        torch.cuda.empty_cache()
+    target = rows[0]["plain"]
+    matched = [r["trajectories"] for r in rows if "learned" in r and r["learned"] <= target]
+    return {"workload": "3-D multi-vortex map (two ABC maps, amplitudes 0.2 and 0.1, wavenumbers 1 and 2), "
+                        "256^3 periodic mesh, 320^3 lattice trajectories, h0 = 1/320, FP32 kernel with FP64 det J",
+            "performance": perf,
+            "reference": {"psicell_particles": args.large_particles,
+                          "noise_floor_rel_l2": [round(math.sqrt(f), 4) for f in floor]},
+            "error": "mean over the 4 source fields of the noise-debiased rel L2 against dense PSI-CELL",
+            "eval": rows, "plain_error_at_32.8M": target,
+            "fewest_trajectories_learned_within_plain_error": min(matched) if matched else None}
 
 
 def learned_vs_plain(ctx, args, dev):
@@ -173,7 +288,7 @@ def learned_vs_plain(ctx, args, dev):
         del sn, wl
     target = rows[0]["plain"]
     matched = [r["trajectories"] for r in rows if r["learned"] <= target]
-    return {
+    return model, {
         "train": {"snapshots": args.train_snapshots, "trajectories": args.train_trajectories, "mesh": [64, 64, 64],
                   "psicell_particles": args.train_particles, "steps": args.train_steps, "seconds": round(t_train, 2)},
         "reference": {"psicell_particles": args.psicell_particles, "noise_floor_rel_l2": [round(math.sqrt(f), 4) for f in floor]},
@@ -326,6 +441,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psicell", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch section")
+    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 multi-vortex section")
+    ap.add_argument("--large-particles", type=int, default=1_677_721_600)
     ap.add_argument("--batch-snapshots", type=int, default=64)
     ap.add_argument("--psicell-particles", type=int, default=200_000_000)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain section")
@@ -432,11 +549,16 @@ def main():
         torch.cuda.empty_cache()
         log(f"psicell {Np}: {psi_ms:.3f} ms")
 
-    learned = None
+    learned, model = None, None
     if not args.no_learned:
         log("learned-vs-plain section: training the bandwidth network")
-        learned = learned_vs_plain(ctx, args, dev)
+        model, learned = learned_vs_plain(ctx, args, dev)
         log(f"learned: {learned['eval']}")
+
+    large = None
+    if not args.no_large:
+        log("large section: 256^3 multi-vortex case")
+        large = large_section(ctx, args, dev, model)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -468,6 +590,7 @@ def main():
         "batch": batch,
         "psicell": psi,
         "learned_vs_plain": learned,
+        "large": large,
     }
     print(json.dumps(out), flush=True)
     if args.calibration_copy_mib > 0:

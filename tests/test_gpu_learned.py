@@ -221,3 +221,48 @@ def test_network_backward_and_adam(ctx):
     torch.cuda.synchronize()
     t1, _, _ = LN.adam(theta, gs, np.zeros_like(theta), np.zeros_like(theta), 1, lr=1e-3)
     np.testing.assert_allclose(th2.cpu().double().numpy(), t1, rtol=1e-6, atol=1e-9)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(400)
+def test_learned_form_full_size(ctx):
+    """The learned form on the 128^3 / 2M-trajectory ABC evaluation case:
+    features, network output and factor of every trajectory against the
+    oracle, then the projection with the oracle's factors on 256 sampled
+    cells (the factors are an input of the projection)."""
+    from helpers import gpu_run, oracle_run
+    wl = W.c2_abc()
+    print(f"[case] learned full size N={wl.traj.count}", flush=True)
+    _, f0, _ = _oracle_forward(wl, LN.init_params(0))
+    theta = _theta(23, f0)
+    hf, z, o, fr = _gpu_forward(ctx, wl, theta)
+    fw, f, t = _oracle_forward(wl, theta)
+    v = t.valid == 1
+    np.testing.assert_allclose(fr[:, v], f[:, v], rtol=1e-6, atol=1e-6)
+    assert np.mean(z[:, v] == fw.z[:, v]) > 0.999
+    err = np.abs(o - fw.o)
+    # The GPU forms first-layer pre-activations in binary32 (MFMA), the
+    # oracle in binary64, and both round the activations to bf16: where a
+    # value lies within one binary32 rounding of a bf16 midpoint the two
+    # sides round it to neighbouring bf16 values, one ulp (at most 2^-7 of
+    # the magnitude) apart.  Per trajectory, the output can then differ by at
+    # most the effect of every first-layer activation moving by one ulp,
+    # propagated through the oracle's second and output layers (linearised,
+    # with a 1.5 margin for the change of the SiLU slope), plus binary32
+    # rounding.  Such flips are rare: few outputs leave the 2e-3 band.
+    p = LN.unpack(theta)
+    W2, w3 = LN.bf16(p["W2"]), LN.bf16(p["w3"])
+    do_dh1 = (w3[:, None] * LN.dsilu(fw.a2)).T @ W2
+    bound = 1.5 * 2.0 ** -7 * np.sum(np.abs(fw.h1.T) * np.abs(do_dh1), axis=1) + 1e-5 * (1 + np.abs(fw.o))
+    assert np.all(err[v] <= bound[v]), (err[v] - bound[v]).max()
+    assert np.mean(err[v] > 2e-3 * (1 + np.abs(fw.o[v]))) <= 1e-4
+    assert np.median(err[v]) <= 1e-5
+    np.testing.assert_allclose(hf[v], fw.g[v], rtol=4e-3)
+    g32 = torch.tensor(fw.g, dtype=torch.float32)
+    S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False, h_factor=g32)
+    cells = np.sort(np.random.default_rng(2).choice(wl.mesh.cells, 256, replace=False))
+    oracle.set_threads(16)
+    ref, _ = oracle_run(wl, prec="f32", cells=cells, h_factor=g32)
+    for k in range(ref.S.shape[0]):
+        assert rel_l2(S[k, cells], ref.S[k]) <= 1e-5, k
+    assert rel_l2(den[cells], ref.den) <= 1e-5

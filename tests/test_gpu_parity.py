@@ -134,6 +134,28 @@ def test_c2_full_size_sampled_cells(ctx):
     assert st["skipped"] == 0
 
 
+@pytest.mark.slow
+@pytest.mark.timeout(400)
+def test_c5_full_size_sampled_cells(ctx):
+    """The 256^3 / 32.8M-trajectory multi-vortex case (|det J| down to ~1e-8,
+    sign changes) in the benchmark's launch configuration, checked on 256
+    sampled cells computed one by one by the oracle over all trajectories."""
+    dev = torch.device("cuda", 0)
+    wl = W.c5_multi_vortex(device=dev)
+    wl.traj = wl.traj.to("cpu")
+    print(f"[case] c5 N={wl.traj.count} mesh={wl.mesh.n}", flush=True)
+    S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False)
+    assert np.isfinite(S).all()
+    g = np.random.default_rng(1)
+    cells = np.sort(g.choice(wl.mesh.cells, 256, replace=False))
+    oracle.set_threads(16)
+    ref, terms = oracle_run(wl, prec="f32", cells=cells)
+    assert_fields_close(S[:, cells], ref.S, TOL["f32"], "c5 sampled")
+    assert rel_l2(den[cells], ref.den) <= TOL["f32"]
+    assert st["skipped"] == terms.skipped
+    assert st["max_class"] == 7          # the widest bandwidths span whole axes
+
+
 # ------------------------------------------------------------------ deposition
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_deposit_matches_oracle_and_conserves(ctx, prec):

@@ -355,6 +355,23 @@ def abc_cloud(n_particles: int, seed: int = 0, device="cpu", abc: Optional[ABC] 
     return Trajectories(xp, J, v, ug, r, 1.0)
 
 
+def multi_vortex_cloud(n_particles: int, seed: int = 0, device="cpu", maps: Optional[Sequence[ABC]] = None,
+                       offset: int = 0):
+    """Dense PSI-CELL cloud: X0 ~ U[0,1)^3 through the multi-vortex map (the
+    composition of the given ABC maps, same positions and velocities as
+    multi_vortex_map), radius lognormal; no Jacobian."""
+    maps = maps if maps is not None else multi_vortex_default()
+    x0 = random_points(3, n_particles, seed, device, offset)
+    x = x0
+    for m in maps:
+        x = x + m.amp * m.field(x)
+    v = x - x0
+    del x0
+    ug = sum(m.amp * m.field(x) for m in maps)
+    r = radius_lognormal(n_particles, seed, device=device, stream=61, offset=offset)
+    return Trajectories(wrap_unit(x), torch.empty(0, dtype=torch.float64, device=device), v, ug, r, 1.0)
+
+
 def c5_multi_vortex(per_axis: int = 320, mesh_n: int = 256, seed: int = 0, device="cpu") -> Workload:
     x0 = lattice(3, per_axis, device)
     xp, J, v, ug = from_map(x0, "multi", multi_vortex_default(seed), wrap=True)
