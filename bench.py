@@ -61,7 +61,7 @@ def gather_traffic():
     """HBM bytes per gather launch from the committed counter summary, or None
     when the gather source changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "gather_c2_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", "gather_abc128_hbm_traffic.md")
     src = os.path.join(ROOT, "paper_2512_20829_amd", "csrc", "gather.hip")
     if not os.path.exists(path):
         return None
@@ -69,7 +69,7 @@ def gather_traffic():
     vals = {}
     for line in open(path):
         if ":" in line and line.startswith("- "):
-            k, v = line[2:].split(":", 1)
+            k, v = line[2:].rsplit(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("gather.hip sha256[:16]") != digest:
         return None

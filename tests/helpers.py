@@ -90,6 +90,7 @@ def oracle_run(wl: W.Workload, prec: str = None, scale: float = 1.0, cell_scale=
 
 
 def assert_fields_close(S_gpu, S_ref, tol: float, what: str = ""):
-    for k in range(S_ref.shape[0]):
-        e = rel_l2(S_gpu[k], S_ref[k])
+    errs = [rel_l2(S_gpu[k], S_ref[k]) for k in range(S_ref.shape[0])]
+    print(f"[rel-l2] {what}: " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    for k, e in enumerate(errs):
         assert e <= tol, f"{what} field {k}: rel L2 {e:.3e} > {tol:.1e}"
