@@ -31,6 +31,8 @@ namespace flp {
 
 constexpr int kCap = 2 * kWave;
 
+typedef float F4 __attribute__((ext_vector_type(4)));
+
 template <typename R> __device__ inline R r_inf();
 template <> __device__ inline float r_inf<float>() { return __builtin_inff(); }
 template <> __device__ inline double r_inf<double>() { return __builtin_inf(); }
@@ -115,17 +117,23 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
         faxis[a] = !(m.periodic[a] && 4.0 * bhalf[a] >= m.L[a]);
     }
 
+    // Binary32: the C source channels of a sub-block are accumulated on the
+    // matrix unit (see `sub` below), the denominator on the vector unit.
+    constexpr bool kMfma = sizeof(R) == 4;
     R part[NSB][NA];
     R hi[NSB][NA];
     R lo[NSB][NA];
+    F4 acc[NSB];
 #pragma unroll
-    for (int b = 0; b < NSB; ++b)
+    for (int b = 0; b < NSB; ++b) {
+        acc[b] = F4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
             part[b][k] = 0;
             hi[b][k] = 0;
             lo[b][k] = 0;
         }
+    }
     unsigned long long npairs = 0;
     int lane_in = 0;   // bit b: this lane's cell of sub-block b lies inside the mesh
 #pragma unroll
@@ -205,8 +213,15 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
         // the other register set while the current one is accumulated
         const int maskv = (lane < n) ? my.mask[lane] : 0;
         // one sub-block of one record: the per-pair inclusion test, then the
-        // C + 1 multiply-adds
-        auto sub = [&](int b, const R4* t, const R* wv) {
+        // denominator multiply-add and the C channel multiply-adds.  In
+        // binary32 the channels go to one v_mfma_f32_4x4x1_16b_f32: with A
+        // broadcast from lanes 0..3 (cbsz 4, abid 0) it forms, in every
+        // 4-lane block, the outer product of the record's channel weights
+        // (lane m of A holds q_m/h) and the four lanes' kernel weights (B),
+        // so that register k of lane l accumulates channel k of the lane's
+        // cell: the layout of the vector path, with 4 multiply-adds per lane
+        // moved off the vector unit.
+        auto sub = [&](int b, const R4* t, const R* wv, float wq) {
             const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
             R s = (bx ? t[0].z : t[0].x) + (by ? t[1].z : t[1].x);
             R ew = (bx ? t[0].w : t[0].y) * (by ? t[1].w : t[1].y);
@@ -216,8 +231,13 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
             }
             bool in = s <= c2;
             ew = in ? ew : (R)0;
+            if constexpr (kMfma) {
+                part[b][0] = fma(ew, wv[0], part[b][0]);
+                acc[b] = __builtin_amdgcn_mfma_f32_4x4x1f32(wq, (float)ew, acc[b], 4, 0, 0);
+            } else {
 #pragma unroll
-            for (int k = 0; k < NA; ++k) part[b][k] = fma(ew, wv[k], part[b][k]);
+                for (int k = 0; k < NA; ++k) part[b][k] = fma(ew, wv[k], part[b][k]);
+            }
             if (COUNT) npairs += in ? 1ull : 0ull;
         };
         // PLAN sets the granularity of the wave-uniform skips: 0 one branch per
@@ -225,63 +245,79 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
         // tile, 3 none (every sub-block evaluated, masked by the pair test).
         // All plans add the same products; a skipped sub-block only saves
         // additions of zero.
-        auto accumulate = [&](int e, const R4* t, const R* wv) {
+        auto accumulate = [&](int e, const R4* t, const R* wv, float wq) {
             const int mk = __builtin_amdgcn_readlane(maskv, e);
             if (mk == 0) return;
             if (PLAN == 3 || (D == 2 && PLAN != 0)) {
 #pragma unroll
-                for (int b = 0; b < NSB; ++b) sub(b, t, wv);
+                for (int b = 0; b < NSB; ++b) sub(b, t, wv, wq);
             } else if (PLAN == 2) {
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
                     if (mk & (0x0F << (4 * h))) {
 #pragma unroll
-                        for (int b = 4 * h; b < 4 * h + 4; ++b) sub(b, t, wv);
+                        for (int b = 4 * h; b < 4 * h + 4; ++b) sub(b, t, wv, wq);
                     }
             } else if (PLAN == 1) {
 #pragma unroll
                 for (int q = 0; q < NSB / 2; ++q)
                     if (mk & (((1 << (NSB / 2)) | 1) << q)) {
-                        sub(q, t, wv);
-                        sub(q + NSB / 2, t, wv);
+                        sub(q, t, wv, wq);
+                        sub(q + NSB / 2, t, wv, wq);
                     }
             } else {
 #pragma unroll
                 for (int b = 0; b < NSB; ++b)
-                    if (mk & (1 << b)) sub(b, t, wv);
+                    if (mk & (1 << b)) sub(b, t, wv, wq);
+            }
+        };
+        // weights of staged record e: {1/h, q/h ...} on every lane, and, for
+        // the matrix unit, q_m/h on lane m < C of each 4-lane group (0 on the
+        // others)
+        const int wm = lane & 3;
+        auto load_w = [&](int e, R* w, float& wq) {
+            if constexpr (kMfma) {
+                w[0] = my.wts[e][0];
+                wq = wm < C ? (float)my.wts[e][1 + (wm < C ? wm : 0)] : 0.0f;
+            } else {
+#pragma unroll
+                for (int k = 0; k < NA; ++k) w[k] = my.wts[e][k];
+                wq = 0.0f;
             }
         };
         R4 tA[3], tB[3];
         R wA[NA], wB[NA];
+        float qA, qB;
 #pragma unroll
         for (int a = 0; a < D; ++a) tA[a] = my.tab[0][a][lc[a]];
-#pragma unroll
-        for (int k = 0; k < NA; ++k) wA[k] = my.wts[0][k];
+        load_w(0, wA, qA);
         for (int e = 0; e < n; e += 2) {
             if (e + 1 < n) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) tB[a] = my.tab[e + 1][a][lc[a]];
-#pragma unroll
-                for (int k = 0; k < NA; ++k) wB[k] = my.wts[e + 1][k];
+                load_w(e + 1, wB, qB);
             }
-            accumulate(e, tA, wA);
+            accumulate(e, tA, wA, qA);
             if (e + 1 >= n) break;
             if (e + 2 < n) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) tA[a] = my.tab[e + 2][a][lc[a]];
-#pragma unroll
-                for (int k = 0; k < NA; ++k) wA[k] = my.wts[e + 2][k];
+                load_w(e + 2, wA, qA);
             }
-            accumulate(e + 1, tB, wB);
+            accumulate(e + 1, tB, wB, qB);
         }
         if (kComp) {
 #pragma unroll
-            for (int b = 0; b < NSB; ++b)
+            for (int b = 0; b < NSB; ++b) {
+                two_sum_acc(hi[b][0], lo[b][0], part[b][0]);
+                part[b][0] = 0;
 #pragma unroll
-                for (int k = 0; k < NA; ++k) {
-                    two_sum_acc(hi[b][k], lo[b][k], part[b][k]);
+                for (int k = 1; k < NA; ++k) {
+                    two_sum_acc(hi[b][k], lo[b][k], kMfma ? (R)acc[b][k - 1] : part[b][k]);
                     part[b][k] = 0;
                 }
+                acc[b] = F4{0.f, 0.f, 0.f, 0.f};
+            }
         }
         wave_sync();
     };
