@@ -250,6 +250,19 @@ __global__ void k_permute(const uint32_t* order, int64_t n, const double4* rpos_
 // reduces the wave.  Then the weight record becomes {1/h, Q/(h Z)}; with
 // Z = 0 it becomes a delta record {0, Q} flagged by 1/h < 0.
 constexpr int kZTab = 128;
+
+// Normaliser Z_i = sum over the cells in reach of the kernel factors, one
+// wave per valid trajectory (sorted order), written into its weight record
+// as q/Z (the 1/h factors cancel).  The support box is swept in blocks of
+// at most kZTab cells per axis.  Within a block, a cell (jx, jy, jz) is
+// included iff (S0[jx] + S1[jy]) + S2[jz] <= c^2, evaluated in the working
+// precision exactly as the gather does.  Floating-point addition is monotone,
+// so on every row (jy, jz) the included cells are those whose S0 does not
+// exceed a threshold: a prefix of the block's S0 values in ascending order.
+// The block's S0 values are therefore ranked once, their factors E0 summed
+// in binary64 in that order, and each row costs one binary search instead of
+// one test per cell.  This holds for any shape of S0 (also across the
+// periodic wrap of a support that spans a whole axis).
 template <typename R, int D>
 __global__ __launch_bounds__(64) void k_deposit_norm(MeshDev m, PhysDev ph, const uint32_t* nvalid,
                                                      const uint32_t* order, const double* qd,
@@ -259,6 +272,9 @@ __global__ __launch_bounds__(64) void k_deposit_norm(MeshDev m, PhysDev ph, cons
     constexpr int C = D + 1;
     __shared__ R S[3][kZTab];
     __shared__ R E[3][kZTab];
+    __shared__ R Ss[kZTab];               // S0 of the block in ascending order
+    __shared__ double Pf[kZTab + 1];      // Pf[k] = sum of E0 over the k smallest S0
+    __shared__ R Es[kZTab];
     int64_t p = blockIdx.x;
     if (p >= (int64_t)*nvalid) return;
     int lane = threadIdx.x;
@@ -267,7 +283,6 @@ __global__ __launch_bounds__(64) void k_deposit_norm(MeshDev m, PhysDev ph, cons
     double inv_h = P.w;
     double h = 1.0 / inv_h;
     double rc = ph.cutoff * h * (1.0 + kSupportMargin);
-    (void)C;
     R c2;
     {
         R c = (R)ph.cutoff;
@@ -291,7 +306,6 @@ __global__ __launch_bounds__(64) void k_deposit_norm(MeshDev m, PhysDev ph, cons
         if (cnt[a] < 0) cnt[a] = 0;
     }
     double z = 0.0;
-    // sweep the support box in blocks of at most kZTab cells per axis
     for (int64_t bz = 0; bz < cnt[2]; bz += kZTab)
     for (int64_t by = 0; by < cnt[1]; by += kZTab)
     for (int64_t bx = 0; bx < cnt[0]; bx += kZTab) {
@@ -311,15 +325,57 @@ __global__ __launch_bounds__(64) void k_deposit_norm(MeshDev m, PhysDev ph, cons
         }
         if (D == 2 && lane == 0) { S[2][0] = 0; E[2][0] = 1; }
         __syncthreads();
-        int64_t tot = (int64_t)len[0] * len[1] * (D == 3 ? len[2] : 1);
-        for (int64_t j = lane; j < tot; j += kWave) {
-            int jx = (int)(j % len[0]);
-            int64_t r2 = j / len[0];
-            int jy = (int)(r2 % len[1]);
-            int jz = (int)(r2 / len[1]);
-            R s = S[0][jx] + S[1][jy];
-            if (D == 3) s = s + S[2][jz];
-            if (s <= c2) z += (double)(E[0][jx] * E[1][jy] * (D == 3 ? E[2][jz] : (R)1));
+        // rank of each S0 (ties broken by index): a permutation of 0..len0-1
+        for (int j = lane; j < len[0]; j += kWave) {
+            const R v = S[0][j];
+            int r = 0;
+            for (int i = 0; i < len[0]; ++i) {
+                const R u = S[0][i];
+                r += (u < v || (u == v && i < j)) ? 1 : 0;
+            }
+            Ss[r] = v;
+            Es[r] = E[0][j];
+        }
+        __syncthreads();
+        // prefix sums of E0 in rank order: lane l owns ranks 2l and 2l + 1
+        {
+            const int r0 = 2 * lane, r1 = 2 * lane + 1;
+            const double e0 = r0 < len[0] ? (double)Es[r0] : 0.0;
+            const double e1 = r1 < len[0] ? (double)Es[r1] : 0.0;
+            double incl = e0 + e1;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                double t = __shfl_up(incl, o, kWave);
+                if (lane >= o) incl += t;
+            }
+            const double excl = incl - (e0 + e1);
+            if (lane == 0) Pf[0] = 0.0;
+            if (r0 < len[0]) Pf[r0 + 1] = excl + e0;
+            if (r1 < len[0]) Pf[r1 + 1] = incl;
+        }
+        __syncthreads();
+        const int n0 = len[0];
+        const R smin = Ss[0];
+        const int64_t rows = (int64_t)len[1] * (D == 3 ? len[2] : 1);
+        for (int64_t j = lane; j < rows; j += kWave) {
+            const int jy = (int)(j % len[1]);
+            const int jz = (int)(j / len[1]);
+            const R sy = S[1][jy], sz = S[2][jz];
+            // number of ranks k with (Ss[k] + sy) + sz <= c^2 (a prefix)
+            R s = smin + sy;
+            if (D == 3) s = s + sz;
+            if (!(s <= c2)) continue;
+            int klo = 1, khi = n0;
+            while (klo < khi) {
+                const int mid = (klo + khi + 1) >> 1;
+                R t = Ss[mid - 1] + sy;
+                if (D == 3) t = t + sz;
+                if (t <= c2)
+                    klo = mid;
+                else
+                    khi = mid - 1;
+            }
+            z += Pf[klo] * ((double)E[1][jy] * (double)E[2][jz]);
         }
     }
 #pragma unroll
