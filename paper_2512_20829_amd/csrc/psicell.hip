@@ -10,52 +10,51 @@
 // Particles arrive in arbitrary spatial order, so the sums are not formed by
 // global atomics (one contended 64-bit atomic per particle and channel) but
 // in three streaming passes over coarse tiles of cells:
-//   count   per particle: validity and (tile, cell in tile) code; per-block
-//           tile histograms in LDS, written tile-major for an exclusive scan
-//           that yields every (tile, block) output range;
-//   scatter per particle: phi, the per-channel max |phi|, and the record
-//           (cell in tile, phi) appended to its tile bucket (slot from an LDS
-//           cursor; the order inside a bucket does not matter);
+//   count   per particle, from its position only: the (tile, cell in tile)
+//           code (-1 outside a closed box or for a non-finite position);
+//           per-block tile histograms in LDS, written tile-major for an
+//           exclusive scan that yields every (tile, block) output range;
+//   scatter per particle with a code: phi, the per-channel max |phi|, and
+//           the record (cell in tile, phi) appended to its tile bucket (slot
+//           from an LDS cursor; the order inside a bucket does not matter);
+//           a particle whose velocities, radius or phi are not finite gets a
+//           record with cell kPsiSkip and is counted as skipped;
 //   reduce  one workgroup per tile: quantise and add in LDS (integer atomics),
 //           then scale by -w/V_c and write the tile's cells.
+// The count and reduce passes give each thread kPsiUnroll particles per step
+// and issue all their loads before any use, to keep enough reads in flight.
 #include "internal.hpp"
 #include "kernels.hpp"
 
 namespace flp {
 
-template <typename R, int D>
-__device__ inline bool psi_particle(const PsiArgs& a, int64_t p, int64_t& cell, double* phi)
+constexpr int kPsiUnroll = 4;          // count and reduce
+constexpr int kPsiUnrollScatter = 1;   // scatter: the binary64 phi of several particles costs occupancy
+constexpr uint32_t kPsiSkip = 0xFFFFFFFFu;
+
+// Cell of a particle from its position alone: false for a non-finite
+// position or one outside a closed box (x == hi goes to the last cell).
+template <int D>
+__device__ inline bool psi_cell(const MeshDev& m, const double* x, int64_t& cell)
 {
-    const MeshDev& m = a.m;
     int64_t lin = 0, stride = 1;
-    double v[3], ug[3];
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
-        double x = a.p.x[ax][p];
-        if (!isfinite(x)) return false;
-        double g = floor((x - m.lo[ax]) / m.w[ax]);
+        if (!isfinite(x[ax])) return false;
+        double g = floor((x[ax] - m.lo[ax]) / m.w[ax]);
         if (!(fabs(g) < 9.0e15)) return false;
         int64_t k = (int64_t)g;
         if (m.periodic[ax]) {
             k = posmod(k, m.n[ax]);
         } else if (k < 0 || k >= m.n[ax]) {
-            if (k == m.n[ax] && x == m.hi[ax])
+            if (k == m.n[ax] && x[ax] == m.hi[ax])
                 k = m.n[ax] - 1;
             else
                 return false;
         }
         lin += k * stride;
         stride *= m.n[ax];
-        v[ax] = (double)((const R*)a.p.v[ax])[p];
-        ug[ax] = (double)((const R*)a.p.ug[ax])[p];
-        if (!isfinite(v[ax]) || !isfinite(ug[ax])) return false;
     }
-    double r = (double)((const R*)a.p.r)[p];
-    if (!isfinite(r)) return false;
-    droplet_phi<D>(r, v, ug, a.ph, phi);
-#pragma unroll
-    for (int k = 0; k < D + 1; ++k)
-        if (!isfinite(phi[k])) return false;
     cell = lin;
     return true;
 }
@@ -92,18 +91,30 @@ __global__ __launch_bounds__(256) void k_psi_count(PsiArgs a)
     const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
     const int64_t beg = (int64_t)blockIdx.x * chunk;
     const int64_t end = beg + chunk < N ? beg + chunk : N;
+    const int64_t stepw = (int64_t)blockDim.x * kPsiUnroll;
     unsigned long long outside = 0;
-    for (int64_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
-        int64_t c;
-        double phi[4];
-        int64_t code = -1;
-        if (psi_particle<R, D>(a, p, c, phi)) {
-            code = psi_code<D>(a, c);
-            atomicAdd(&hist[code / a.cpt], 1u);
-        } else {
-            ++outside;
+    for (int64_t p0 = beg + threadIdx.x; p0 < end; p0 += stepw) {
+        double x[kPsiUnroll][3];
+#pragma unroll
+        for (int u = 0; u < kPsiUnroll; ++u) {
+            const int64_t p = p0 + (int64_t)u * blockDim.x;
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) x[u][ax] = p < end ? a.p.x[ax][p] : 0.0;
         }
-        a.codes[p] = (int)code;
+#pragma unroll
+        for (int u = 0; u < kPsiUnroll; ++u) {
+            const int64_t p = p0 + (int64_t)u * blockDim.x;
+            if (p >= end) break;
+            int64_t c;
+            int64_t code = -1;
+            if (psi_cell<D>(a.m, x[u], c)) {
+                code = psi_code<D>(a, c);
+                atomicAdd(&hist[code / a.cpt], 1u);
+            } else {
+                ++outside;
+            }
+            a.codes[p] = (int)code;
+        }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < ntl; t += blockDim.x) a.blockhist[(int64_t)t * gridDim.x + blockIdx.x] = hist[t];
@@ -125,29 +136,61 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
     const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
     const int64_t beg = (int64_t)blockIdx.x * chunk;
     const int64_t end = beg + chunk < N ? beg + chunk : N;
+    const int64_t stepw = (int64_t)blockDim.x * kPsiUnrollScatter;
     PsiRec<R>* bucket = (PsiRec<R>*)a.bucket;
     double mx[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) mx[k] = 0.0;
-    for (int64_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
-        int code = a.codes[p];
-        if (code < 0) continue;
-        double v[3], ug[3], phi[4];
+    unsigned long long bad = 0;
+    for (int64_t p0 = beg + threadIdx.x; p0 < end; p0 += stepw) {
+        int code[kPsiUnrollScatter];
+        R v[kPsiUnrollScatter][3], ug[kPsiUnrollScatter][3], r[kPsiUnrollScatter];
 #pragma unroll
-        for (int ax = 0; ax < D; ++ax) {
-            v[ax] = (double)((const R*)a.p.v[ax])[p];
-            ug[ax] = (double)((const R*)a.p.ug[ax])[p];
+        for (int u = 0; u < kPsiUnrollScatter; ++u) {
+            const int64_t p = p0 + (int64_t)u * blockDim.x;
+            code[u] = p < end ? a.codes[p] : -1;
         }
-        droplet_phi<D>((double)((const R*)a.p.r)[p], v, ug, a.ph, phi);
-        unsigned int slot = atomicAdd(&cursor[code / a.cpt], 1u);
-        PsiRec<R> rec;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) rec.phi[k] = (k < C) ? (R)phi[k] : (R)0;
-        rec.loc = (uint32_t)(code % a.cpt);
-        bucket[slot] = rec;
+        for (int u = 0; u < kPsiUnrollScatter; ++u) {
+            const int64_t p = p0 + (int64_t)u * blockDim.x;
+            const bool live = code[u] >= 0;
 #pragma unroll
-        for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], fabs((double)rec.phi[k]));
+            for (int ax = 0; ax < D; ++ax) {
+                v[u][ax] = live ? ((const R*)a.p.v[ax])[p] : (R)0;
+                ug[u][ax] = live ? ((const R*)a.p.ug[ax])[p] : (R)0;
+            }
+            r[u] = live ? ((const R*)a.p.r)[p] : (R)1;
+        }
+#pragma unroll
+        for (int u = 0; u < kPsiUnrollScatter; ++u) {
+            if (code[u] < 0) continue;
+            double vd[3], ud[3], phi[4];
+            bool ok = isfinite((double)r[u]);
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                vd[ax] = (double)v[u][ax];
+                ud[ax] = (double)ug[u][ax];
+                ok = ok && isfinite(vd[ax]) && isfinite(ud[ax]);
+            }
+            PsiRec<R> rec;
+            if (ok) {
+                droplet_phi<D>((double)r[u], vd, ud, a.ph, phi);
+#pragma unroll
+                for (int k = 0; k < C; ++k) ok = ok && isfinite(phi[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rec.phi[k] = (ok && k < C) ? (R)phi[k] : (R)0;
+            rec.loc = ok ? (uint32_t)(code[u] % a.cpt) : kPsiSkip;
+            bad += ok ? 0ull : 1ull;
+            unsigned int slot = atomicAdd(&cursor[code[u] / a.cpt], 1u);
+            bucket[slot] = rec;
+#pragma unroll
+            for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], fabs((double)rec.phi[k]));
+        }
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, kWave);
+    if ((threadIdx.x % kWave) == 0 && bad) atomicAdd(&a.stats[ST_OUTSIDE], bad);
     // per-block maxima (a separate pass reduces them: no contended atomics)
     __shared__ double bm[256 / kWave][4];
 #pragma unroll
@@ -215,15 +258,26 @@ __global__ __launch_bounds__(256) void k_psi_reduce(PsiArgs a)
     const int64_t beg = a.blockhist[(int64_t)tile * nbk];
     const int64_t end = a.blockhist[(int64_t)(tile + 1) * nbk];
     const PsiRec<R>* bucket = (const PsiRec<R>*)a.bucket;
-    for (int64_t sl = beg + threadIdx.x; sl < end; sl += blockDim.x) {
-        PsiRec<R> rec = bucket[sl];
-        int loc = (int)rec.loc;
+    const int64_t stepw = (int64_t)blockDim.x * kPsiUnroll;
+    for (int64_t s0 = beg + threadIdx.x; s0 < end; s0 += stepw) {
+        PsiRec<R> rec[kPsiUnroll];
 #pragma unroll
-        for (int k = 0; k < C; ++k) {
-            long long qv = llrint((double)rec.phi[k] * qs[k]);
-            atomicAdd(&sacc[k * cpt + loc], (unsigned long long)qv);
+        for (int u = 0; u < kPsiUnroll; ++u) {
+            const int64_t sl = s0 + (int64_t)u * blockDim.x;
+            if (sl < end) rec[u] = bucket[sl];
+            else rec[u].loc = kPsiSkip;
         }
-        atomicAdd(&scnt[loc], 1u);
+#pragma unroll
+        for (int u = 0; u < kPsiUnroll; ++u) {
+            if (rec[u].loc == kPsiSkip) continue;
+            const int loc = (int)rec[u].loc;
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                long long qv = llrint((double)rec[u].phi[k] * qs[k]);
+                atomicAdd(&sacc[k * cpt + loc], (unsigned long long)qv);
+            }
+            atomicAdd(&scnt[loc], 1u);
+        }
     }
     __syncthreads();
     const MeshDev& m = a.m;
