@@ -208,9 +208,8 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
             my.mask[lane] = mk;
         }
         wave_sync();
-        // every lane keeps the masks of one staged record (read with readlane,
-        // no LDS round trip); the factors of the next record are loaded into
-        // the other register set while the current one is accumulated
+        // every lane keeps the mask of one staged record (read with readlane,
+        // no LDS round trip)
         const int maskv = (lane < n) ? my.mask[lane] : 0;
         // one sub-block of one record: the per-pair inclusion test, then the
         // denominator multiply-add and the C channel multiply-adds.  In
@@ -221,7 +220,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
         // so that register k of lane l accumulates channel k of the lane's
         // cell: the layout of the vector path, with 4 multiply-adds per lane
         // moved off the vector unit.
-        auto sub = [&](int b, const R4* t, const R* wv, float wq) {
+        auto sub = [&](int b, const R4* t, const R* wv, float wq, bool live = true) {
             const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
             R s = (bx ? t[0].z : t[0].x) + (by ? t[1].z : t[1].x);
             R ew = (bx ? t[0].w : t[0].y) * (by ? t[1].w : t[1].y);
@@ -238,7 +237,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
 #pragma unroll
                 for (int k = 0; k < NA; ++k) part[b][k] = fma(ew, wv[k], part[b][k]);
             }
-            if (COUNT) npairs += in ? 1ull : 0ull;
+            if (COUNT) npairs += (in && live) ? 1ull : 0ull;
         };
         // PLAN sets the granularity of the wave-uniform skips: 0 one branch per
         // sub-block, 1 per pair of sub-blocks along the last axis, 2 per half
@@ -288,23 +287,87 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
         R4 tA[3], tB[3];
         R wA[NA], wB[NA];
         float qA, qB;
+        if (PLAN == 1 && D == 3 && kMfma) {
+            // Four records per step.  A pair of sub-blocks is evaluated for
+            // all four records when any of them reaches it: a record that
+            // reaches no cell there adds exact zeros (its kernel weights are
+            // 0 on every lane), so the sums are those of one record at a
+            // time, while the tests and branches are shared by four records
+            // and the four independent chains fill the issue slots.  Slots
+            // past the batch end repeat record e with zero weights and are
+            // not counted as pairs.
+            R4 tC[3], tD[3];
+            R wC[NA], wD[NA];
+            float qC, qD;
+            for (int e = 0; e < n; e += 4) {
+                const bool l1 = e + 1 < n, l2 = e + 2 < n, l3 = e + 3 < n;
+                const int e1 = l1 ? e + 1 : e;
+                const int e2 = l2 ? e + 2 : e;
+                const int e3 = l3 ? e + 3 : e;
 #pragma unroll
-        for (int a = 0; a < D; ++a) tA[a] = my.tab[0][a][lc[a]];
-        load_w(0, wA, qA);
-        for (int e = 0; e < n; e += 2) {
-            if (e + 1 < n) {
+                for (int a = 0; a < D; ++a) {
+                    tA[a] = my.tab[e][a][lc[a]];
+                    tB[a] = my.tab[e1][a][lc[a]];
+                    tC[a] = my.tab[e2][a][lc[a]];
+                    tD[a] = my.tab[e3][a][lc[a]];
+                }
+                load_w(e, wA, qA);
+                load_w(e1, wB, qB);
+                load_w(e2, wC, qC);
+                load_w(e3, wD, qD);
+                if (!l1) {
 #pragma unroll
-                for (int a = 0; a < D; ++a) tB[a] = my.tab[e + 1][a][lc[a]];
-                load_w(e + 1, wB, qB);
+                    for (int k = 0; k < NA; ++k) wB[k] = 0;
+                    qB = 0.0f;
+                }
+                if (!l2) {
+#pragma unroll
+                    for (int k = 0; k < NA; ++k) wC[k] = 0;
+                    qC = 0.0f;
+                }
+                if (!l3) {
+#pragma unroll
+                    for (int k = 0; k < NA; ++k) wD[k] = 0;
+                    qD = 0.0f;
+                }
+                const int mk = __builtin_amdgcn_readlane(maskv, e) | (l1 ? __builtin_amdgcn_readlane(maskv, e1) : 0) |
+                               (l2 ? __builtin_amdgcn_readlane(maskv, e2) : 0) |
+                               (l3 ? __builtin_amdgcn_readlane(maskv, e3) : 0);
+                if (mk == 0) continue;
+#pragma unroll
+                for (int q = 0; q < NSB / 2; ++q)
+                    if (mk & (((1 << (NSB / 2)) | 1) << q)) {
+                        sub(q, tA, wA, qA);
+                        sub(q + NSB / 2, tA, wA, qA);
+                        sub(q, tB, wB, qB, l1);
+                        sub(q + NSB / 2, tB, wB, qB, l1);
+                        sub(q, tC, wC, qC, l2);
+                        sub(q + NSB / 2, tC, wC, qC, l2);
+                        sub(q, tD, wD, qD, l3);
+                        sub(q + NSB / 2, tD, wD, qD, l3);
+                    }
             }
-            accumulate(e, tA, wA, qA);
-            if (e + 1 >= n) break;
-            if (e + 2 < n) {
+        } else {
+            // one record at a time; the factors of the next record are read
+            // while the current one is accumulated
 #pragma unroll
-                for (int a = 0; a < D; ++a) tA[a] = my.tab[e + 2][a][lc[a]];
-                load_w(e + 2, wA, qA);
+            for (int a = 0; a < D; ++a) tA[a] = my.tab[0][a][lc[a]];
+            load_w(0, wA, qA);
+            for (int e = 0; e < n; e += 2) {
+                if (e + 1 < n) {
+#pragma unroll
+                    for (int a = 0; a < D; ++a) tB[a] = my.tab[e + 1][a][lc[a]];
+                    load_w(e + 1, wB, qB);
+                }
+                accumulate(e, tA, wA, qA);
+                if (e + 1 >= n) break;
+                if (e + 2 < n) {
+#pragma unroll
+                    for (int a = 0; a < D; ++a) tA[a] = my.tab[e + 2][a][lc[a]];
+                    load_w(e + 2, wA, qA);
+                }
+                accumulate(e + 1, tB, wB, qB);
             }
-            accumulate(e + 1, tB, wB, qB);
         }
         if (kComp) {
 #pragma unroll
