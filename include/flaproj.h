@@ -25,6 +25,11 @@
  *    outputs (no floating-point atomics; fixed summation orders).
  *  - Mesh cells are indexed i0 + n0*(i1 + n1*i2); a field is a plane of
  *    M = n0*n1(*n2) values in that order.
+ *  - A context is used by one host thread at a time.  Its workspace and
+ *    statistics are shared by every call on it, so work enqueued on
+ *    different streams must not overlap in time: order such streams (or
+ *    use one context per stream).  Growing the workspace synchronises the
+ *    device.
  */
 #ifndef FLAPROJ_H
 #define FLAPROJ_H
