@@ -312,7 +312,7 @@ class Context:
     def autotune(self, mesh: fla_mesh, traj: fla_trajectories, params: Params, S_mass, S_mom, den=None,
                  stream=None):
         """Time every gather plan on these inputs, keep the fastest; returns the per-plan ms."""
-        t = (C.c_double * 4)()
+        t = (C.c_double * GATHER_PLANS)()
         self._check(_lib.fla_autotune(self._h, C.byref(mesh), C.byref(traj), C.byref(params.to_c()),
                                       C.byref(make_fields(S_mass, S_mom, den)), _stream_handle(stream), t))
         return [float(v) for v in t]

@@ -61,6 +61,171 @@ struct GatherLds {
     int mask[kWave];                   // sub-blocks holding at least one included pair
 };
 
+// Per-axis factors of one record for the tile at tile coordinates tc, whose
+// cell centres are xcs: tab[a][l] = {s, e} at in-block positions l and
+// l + SB of axis a, with s = (d/h)^2 (binary64 rounded to R) and
+// e = exp(-s/2); a delta record (1/h < 0) has factor 1 at its home cell and
+// 0 elsewhere.  Returns the sub-block visit mask: bit b is set iff the sum of
+// the per-axis minima of s over sub-block b passes the cutoff (sums are
+// monotone in each term, so no sub-block holding an included pair is
+// skipped).
+template <typename R, int D>
+__device__ __forceinline__ int stage_record(const MeshDev& m, const double (*xcs)[Geo<D>::TE], const int* tc,
+                                            const double4 P, const R c2, typename V4<R>::T (*tab)[Geo<D>::SB])
+{
+    using G = Geo<D>;
+    constexpr int TE = G::TE, SB = G::SB, NSB = G::NSB;
+    using R4 = typename V4<R>::T;
+    double x[3] = {P.x, P.y, P.z};
+    bool delta = P.w < 0.0;
+    double inv_h = delta ? -P.w : P.w;
+    R mn[3][2];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        int64_t hcell = delta ? home_index(m, a, x[a]) : -1;
+        R mlo = r_inf<R>(), mhi = r_inf<R>();
+#pragma unroll
+        for (int l = 0; l < SB; ++l) {
+            R sv[2], ev[2];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                int pp = l + hh * SB;
+                if (delta) {
+                    // whole amount into the home cell: factor 1 there, 0 elsewhere
+                    bool home = (int64_t)tc[a] * TE + pp == hcell;
+                    sv[hh] = home ? (R)0 : r_inf<R>();
+                    ev[hh] = home ? (R)1 : (R)0;
+                } else {
+                    // centres of cells beyond the mesh are NaN: s is NaN, never
+                    // passes the test, and is ignored by the min/max below
+                    double d = axis_offset(m, a, xcs[a][pp], x[a]);
+                    R sr = (R)scaled_sq(d, inv_h);
+                    sv[hh] = sr;
+                    ev[hh] = gauss_factor(sr);
+                }
+            }
+            R4 t4;
+            t4.x = sv[0];
+            t4.y = ev[0];
+            t4.z = sv[1];
+            t4.w = ev[1];
+            tab[a][l] = t4;
+            mlo = fmin(mlo, sv[0]);
+            mhi = fmin(mhi, sv[1]);
+        }
+        mn[a][0] = mlo;
+        mn[a][1] = mhi;
+    }
+    // visit mask: the sub-block can hold an included pair (the sum of
+    // the per-axis minima passes; binary32/64 sums are monotone in each
+    // term, so the skip never drops an included pair)
+    int mk = 0;
+#pragma unroll
+    for (int b = 0; b < NSB; ++b) {
+        R smin = mn[0][b & 1] + mn[1][(b >> 1) & 1];
+        if (D == 3) smin = smin + mn[2][(b >> 2) & 1];
+        mk |= (smin <= c2) ? (1 << b) : 0;
+    }
+    return mk;
+}
+
+// Calls fn(s0, s1) for every run [s0, s1) of sorted records that the tile at
+// tile coordinates tc must consider, in a fixed order: for each neighbourhood
+// class k present in the mesh, the home tiles within k tiles of tc on every
+// axis (the last class: whole axes), row by row; along x the home tiles of a
+// row are contiguous in the sorted order (one run, or two across a periodic
+// wrap).
+template <int D, typename F>
+__device__ __forceinline__ void for_each_run(const MeshDev& m, const uint32_t* bstart, const int* tc, F&& fn)
+{
+    const int ntl = m.ntiles;
+    for (int k = 0; k < kClasses; ++k) {
+        const uint32_t kb = (uint32_t)k * (uint32_t)ntl;
+        if (bstart[kb] == bstart[kb + ntl]) continue;
+        const int r = (k == kClasses - 1) ? (1 << 28) : k;
+        int lo_t[3], cnt_t[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a >= D) {
+                lo_t[a] = 0;
+                cnt_t[a] = 1;
+                continue;
+            }
+            int nt = m.nt[a];
+            if (2 * (int64_t)r + 1 >= nt) {
+                lo_t[a] = 0;
+                cnt_t[a] = nt;
+            } else if (m.periodic[a]) {
+                lo_t[a] = tc[a] - r;
+                cnt_t[a] = 2 * r + 1;
+            } else {
+                int l0 = tc[a] - r < 0 ? 0 : tc[a] - r;
+                int l1 = tc[a] + r >= nt ? nt - 1 : tc[a] + r;
+                lo_t[a] = l0;
+                cnt_t[a] = l1 - l0 + 1;
+            }
+        }
+        for (int jz = 0; jz < cnt_t[2]; ++jz) {
+            int hz = lo_t[2] + jz;
+            if (D == 3) hz = (int)posmod(hz, m.nt[2]);
+            for (int jy = 0; jy < cnt_t[1]; ++jy) {
+                int hy = (int)posmod(lo_t[1] + jy, m.nt[1]);
+                int x0 = lo_t[0], x1 = lo_t[0] + cnt_t[0] - 1;
+                int runs[2][2];
+                int nruns = 1;
+                if (x0 < 0) {
+                    runs[0][0] = x0 + m.nt[0];
+                    runs[0][1] = m.nt[0] - 1;
+                    runs[1][0] = 0;
+                    runs[1][1] = x1;
+                    nruns = 2;
+                } else if (x1 >= m.nt[0]) {
+                    runs[0][0] = x0;
+                    runs[0][1] = m.nt[0] - 1;
+                    runs[1][0] = 0;
+                    runs[1][1] = x1 - m.nt[0];
+                    nruns = 2;
+                } else {
+                    runs[0][0] = x0;
+                    runs[0][1] = x1;
+                }
+                const uint32_t rowb = kb + (uint32_t)m.nt[0] * ((uint32_t)hy + (uint32_t)m.nt[1] * (uint32_t)hz);
+                for (int q = 0; q < nruns; ++q) fn(bstart[rowb + runs[q][0]], bstart[rowb + runs[q][1] + 1]);
+            }
+        }
+    }
+}
+
+// Conservative test of one record against the tile: a delta record (1/h < 0)
+// belongs to the tile of its home cell; any other record passes if the
+// scaled binary64 distance from its position to the tile's box of cell
+// centres (mid bmid, half-widths bhalf; axes where the box spans half a
+// periodic box or more are not tested) is within filt2.
+template <int D>
+__device__ __forceinline__ bool candidate_ok(const MeshDev& m, const double4 P, const int* tc, const double* bmid,
+                                             const double* bhalf, const bool* faxis, double filt2)
+{
+    constexpr int TE = Geo<D>::TE;
+    double x[3] = {P.x, P.y, P.z};
+    if (P.w < 0.0) {
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) ok = ok && (home_index(m, a, x[a]) / TE == tc[a]);
+        return ok;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (!faxis[a]) continue;
+        double d = fabs(axis_offset(m, a, bmid[a], x[a])) - bhalf[a];
+        if (d > 0.0) {
+            double u = d * P.w;
+            acc += u * u;
+        }
+    }
+    return acc <= filt2;
+}
+
 // The work of one workgroup: every cell of tile `tile` of the mesh of g.
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
 __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
@@ -135,14 +300,6 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
         }
     }
     unsigned long long npairs = 0;
-    int lane_in = 0;   // bit b: this lane's cell of sub-block b lies inside the mesh
-#pragma unroll
-    for (int b = 0; b < NSB; ++b) {
-        bool in = true;
-#pragma unroll
-        for (int a = 0; a < D; ++a) in = in && ((int64_t)tc[a] * TE + ((b >> a) & 1) * SB + lc[a] < m.n[a]);
-        lane_in |= in ? (1 << b) : 0;
-    }
     const uint64_t ltmask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     __syncthreads();
 
@@ -155,57 +312,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
             const R* w = (const R*)g.rw + (size_t)p * kRecW;
 #pragma unroll
             for (int k = 0; k < NA; ++k) my.wts[lane][k] = w[k];
-            double x[3] = {P.x, P.y, P.z};
-            bool delta = P.w < 0.0;
-            double inv_h = delta ? -P.w : P.w;
-            R mn[3][2];
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                int64_t hcell = delta ? home_index(m, a, x[a]) : -1;
-                R mlo = r_inf<R>(), mhi = r_inf<R>();
-#pragma unroll
-                for (int l = 0; l < SB; ++l) {
-                    R sv[2], ev[2];
-#pragma unroll
-                    for (int hh = 0; hh < 2; ++hh) {
-                        int pp = l + hh * SB;
-                        if (delta) {
-                            // whole amount into the home cell: factor 1 there, 0 elsewhere
-                            bool home = (int64_t)tc[a] * TE + pp == hcell;
-                            sv[hh] = home ? (R)0 : r_inf<R>();
-                            ev[hh] = home ? (R)1 : (R)0;
-                        } else {
-                            // centres of cells beyond the mesh are NaN: s is NaN, never
-                            // passes the test, and is ignored by the min/max below
-                            double d = axis_offset(m, a, xcs[a][pp], x[a]);
-                            R sr = (R)scaled_sq(d, inv_h);
-                            sv[hh] = sr;
-                            ev[hh] = gauss_factor(sr);
-                        }
-                    }
-                    R4 t4;
-                    t4.x = sv[0];
-                    t4.y = ev[0];
-                    t4.z = sv[1];
-                    t4.w = ev[1];
-                    my.tab[lane][a][l] = t4;
-                    mlo = fmin(mlo, sv[0]);
-                    mhi = fmin(mhi, sv[1]);
-                }
-                mn[a][0] = mlo;
-                mn[a][1] = mhi;
-            }
-            // visit mask: the sub-block can hold an included pair (the sum of
-            // the per-axis minima passes; binary32/64 sums are monotone in each
-            // term, so the skip never drops an included pair)
-            int mk = 0;
-#pragma unroll
-            for (int b = 0; b < NSB; ++b) {
-                R smin = mn[0][b & 1] + mn[1][(b >> 1) & 1];
-                if (D == 3) smin = smin + mn[2][(b >> 2) & 1];
-                mk |= (smin <= c2) ? (1 << b) : 0;
-            }
-            my.mask[lane] = mk;
+            my.mask[lane] = stage_record<R, D>(m, xcs, tc, P, c2, my.tab[lane]);
         }
         wave_sync();
         // every lane keeps the mask of one staged record (read with readlane,
@@ -387,110 +494,33 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
 
     int ncand = 0;
     uint32_t chunk = 0;          // chunks of 64 candidates are dealt round-robin to the waves
-    const int ntl = m.ntiles;
-    for (int k = 0; k < kClasses; ++k) {
-        const uint32_t kb = (uint32_t)k * (uint32_t)ntl;
-        if (g.bstart[kb] == g.bstart[kb + ntl]) continue;
-        const int r = (k == kClasses - 1) ? (1 << 28) : k;
-        int lo_t[3], cnt_t[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (a >= D) {
-                lo_t[a] = 0;
-                cnt_t[a] = 1;
-                continue;
-            }
-            int nt = m.nt[a];
-            if (2 * (int64_t)r + 1 >= nt) {
-                lo_t[a] = 0;
-                cnt_t[a] = nt;
-            } else if (m.periodic[a]) {
-                lo_t[a] = tc[a] - r;
-                cnt_t[a] = 2 * r + 1;
-            } else {
-                int l0 = tc[a] - r < 0 ? 0 : tc[a] - r;
-                int l1 = tc[a] + r >= nt ? nt - 1 : tc[a] + r;
-                lo_t[a] = l0;
-                cnt_t[a] = l1 - l0 + 1;
-            }
-        }
-        for (int jz = 0; jz < cnt_t[2]; ++jz) {
-            int hz = lo_t[2] + jz;
-            if (D == 3) hz = (int)posmod(hz, m.nt[2]);
-            for (int jy = 0; jy < cnt_t[1]; ++jy) {
-                int hy = (int)posmod(lo_t[1] + jy, m.nt[1]);
-                int x0 = lo_t[0], x1 = lo_t[0] + cnt_t[0] - 1;
-                int runs[2][2];
-                int nruns = 1;
-                if (x0 < 0) {
-                    runs[0][0] = x0 + m.nt[0];
-                    runs[0][1] = m.nt[0] - 1;
-                    runs[1][0] = 0;
-                    runs[1][1] = x1;
-                    nruns = 2;
-                } else if (x1 >= m.nt[0]) {
-                    runs[0][0] = x0;
-                    runs[0][1] = m.nt[0] - 1;
-                    runs[1][0] = 0;
-                    runs[1][1] = x1 - m.nt[0];
-                    nruns = 2;
-                } else {
-                    runs[0][0] = x0;
-                    runs[0][1] = x1;
-                }
-                const uint32_t rowb = kb + (uint32_t)m.nt[0] * ((uint32_t)hy + (uint32_t)m.nt[1] * (uint32_t)hz);
-                for (int q = 0; q < nruns; ++q) {
-                    const uint32_t s0 = g.bstart[rowb + runs[q][0]];
-                    const uint32_t s1 = g.bstart[rowb + runs[q][1] + 1];
-                    // this wave's chunks of the run: base0, base0 + 4*64, ...
-                    const uint32_t nch = (s1 - s0 + kWave - 1) / kWave;
-                    const uint32_t first = (uint32_t)((wave - (int)(chunk % kGatherWaves) + kGatherWaves) % kGatherWaves);
-                    chunk += nch;
-                    double4 Pn = make_double4(0, 0, 0, 0);
-                    if (first < nch && s0 + first * kWave + lane < s1) Pn = g.rpos[s0 + first * kWave + lane];
-                    for (uint32_t c = first; c < nch; c += kGatherWaves) {
-                        const uint32_t base = s0 + c * kWave;
-                        uint32_t p = base + lane;
-                        double4 P = Pn;
-                        const uint32_t pn = base + kGatherWaves * kWave + lane;
-                        if (pn < s1) Pn = g.rpos[pn];
-                        bool ok = false;
-                        if (p < s1) {
-                            double x[3] = {P.x, P.y, P.z};
-                            if (P.w < 0.0) {
-                                ok = true;
-#pragma unroll
-                                for (int a = 0; a < D; ++a) ok = ok && (home_index(m, a, x[a]) / TE == tc[a]);
-                            } else {
-                                double acc = 0.0;
-#pragma unroll
-                                for (int a = 0; a < D; ++a) {
-                                    if (!faxis[a]) continue;
-                                    double d = fabs(axis_offset(m, a, bmid[a], x[a])) - bhalf[a];
-                                    if (d > 0.0) {
-                                        double u = d * P.w;
-                                        acc += u * u;
-                                    }
-                                }
-                                ok = acc <= g.filt2;
-                            }
-                        }
-                        uint64_t bal = __ballot(ok);
-                        if (ok) my.cand[ncand + __popcll(bal & ltmask)] = p;
-                        ncand += __popcll(bal);
-                        if (ncand >= kWave) {
-                            process(kWave);
-                            int rem = ncand - kWave;
-                            uint32_t mv = (lane < rem) ? my.cand[kWave + lane] : 0u;
-                            wave_sync();
-                            if (lane < rem) my.cand[lane] = mv;
-                            ncand = rem;
-                        }
-                    }
-                }
+    for_each_run<D>(m, g.bstart, tc, [&](const uint32_t s0, const uint32_t s1) {
+        // this wave's chunks of the run: base0, base0 + 4*64, ...
+        const uint32_t nch = (s1 - s0 + kWave - 1) / kWave;
+        const uint32_t first = (uint32_t)((wave - (int)(chunk % kGatherWaves) + kGatherWaves) % kGatherWaves);
+        chunk += nch;
+        double4 Pn = make_double4(0, 0, 0, 0);
+        if (first < nch && s0 + first * kWave + lane < s1) Pn = g.rpos[s0 + first * kWave + lane];
+        for (uint32_t c = first; c < nch; c += kGatherWaves) {
+            const uint32_t base = s0 + c * kWave;
+            uint32_t p = base + lane;
+            double4 P = Pn;
+            const uint32_t pn = base + kGatherWaves * kWave + lane;
+            if (pn < s1) Pn = g.rpos[pn];
+            const bool ok = p < s1 && candidate_ok<D>(m, P, tc, bmid, bhalf, faxis, g.filt2);
+            uint64_t bal = __ballot(ok);
+            if (ok) my.cand[ncand + __popcll(bal & ltmask)] = p;
+            ncand += __popcll(bal);
+            if (ncand >= kWave) {
+                process(kWave);
+                int rem = ncand - kWave;
+                uint32_t mv = (lane < rem) ? my.cand[kWave + lane] : 0u;
+                wave_sync();
+                if (lane < rem) my.cand[lane] = mv;
+                ncand = rem;
             }
         }
-    }
+    });
     if (ncand > 0) process(ncand);
 
     // ---- fixed-order reduction of the waves' partial sums through LDS
