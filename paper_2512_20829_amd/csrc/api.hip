@@ -551,6 +551,8 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
     }
     a.pntiles = (int)ntiles();
     a.cpt = a.pt[0] * a.pt[1] * a.pt[2];
+    for (int ax = 0; ax < 3; ++ax) a.ptlog[ax] = __builtin_ctz((unsigned)a.pt[ax]);
+    a.cptlog = a.ptlog[0] + a.ptlog[1] + a.ptlog[2];
     a.nblocks = kPsiBlocks;
     const int64_t N = t.count;
     const int64_t hw = (int64_t)a.pntiles * a.nblocks + 1;

@@ -79,6 +79,8 @@ struct PsiArgs {
     int pnt[3];                  // tiles per axis
     int pntiles;
     int cpt;                     // cells per tile
+    int ptlog[3];                // log2 of pt (tile edges are powers of two)
+    int cptlog;                  // log2 of cpt
     int nblocks;                 // blocks of the count / scatter passes
     int* codes;                  // per particle: tile * cpt + cell in tile, or -1
     unsigned int* blockhist;     // pntiles * nblocks + 1, scanned in place

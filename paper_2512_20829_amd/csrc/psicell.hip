@@ -32,12 +32,12 @@ constexpr int kPsiUnroll = 4;          // count and reduce
 constexpr int kPsiUnrollScatter = 1;   // scatter: the binary64 phi of several particles costs occupancy
 constexpr uint32_t kPsiSkip = 0xFFFFFFFFu;
 
-// Cell of a particle from its position alone: false for a non-finite
-// position or one outside a closed box (x == hi goes to the last cell).
+// Cell indices of a particle from its position alone: false for a
+// non-finite position or one outside a closed box (x == hi goes to the last
+// cell).
 template <int D>
-__device__ inline bool psi_cell(const MeshDev& m, const double* x, int64_t& cell)
+__device__ inline bool psi_cell(const MeshDev& m, const double* x, int* idx)
 {
-    int64_t lin = 0, stride = 1;
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
         if (!isfinite(x[ax])) return false;
@@ -52,32 +52,25 @@ __device__ inline bool psi_cell(const MeshDev& m, const double* x, int64_t& cell
             else
                 return false;
         }
-        lin += k * stride;
-        stride *= m.n[ax];
+        idx[ax] = (int)k;
     }
-    cell = lin;
     return true;
 }
 
-// (tile, cell-in-tile) code of a valid particle, -1 otherwise
+// (tile, cell-in-tile) code of a valid particle: tile * cpt + cell in tile
+// (tile edges and cpt are powers of two)
 template <int D>
-__device__ inline int64_t psi_code(const PsiArgs& a, int64_t cell)
+__device__ inline int psi_code(const PsiArgs& a, const int* idx)
 {
-    const MeshDev& m = a.m;
-    int64_t idx[3];
-    idx[0] = cell % m.n[0];
-    int64_t r = cell / m.n[0];
-    idx[1] = r % m.n[1];
-    idx[2] = (D == 3) ? r / m.n[1] : 0;
-    int64_t tile = 0, loc = 0, ts = 1, ls = 1;
+    int tile = 0, loc = 0, ts = 1, lsh = 0;
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
-        tile += (idx[ax] / a.pt[ax]) * ts;
+        tile += (idx[ax] >> a.ptlog[ax]) * ts;
         ts *= a.pnt[ax];
-        loc += (idx[ax] % a.pt[ax]) * ls;
-        ls *= a.pt[ax];
+        loc += (idx[ax] & (a.pt[ax] - 1)) << lsh;
+        lsh += a.ptlog[ax];
     }
-    return tile * a.cpt + loc;
+    return (tile << a.cptlog) | loc;
 }
 
 template <typename R, int D>
@@ -105,15 +98,15 @@ __global__ __launch_bounds__(256) void k_psi_count(PsiArgs a)
         for (int u = 0; u < kPsiUnroll; ++u) {
             const int64_t p = p0 + (int64_t)u * blockDim.x;
             if (p >= end) break;
-            int64_t c;
-            int64_t code = -1;
-            if (psi_cell<D>(a.m, x[u], c)) {
-                code = psi_code<D>(a, c);
-                atomicAdd(&hist[code / a.cpt], 1u);
+            int idx[3] = {0, 0, 0};
+            int code = -1;
+            if (psi_cell<D>(a.m, x[u], idx)) {
+                code = psi_code<D>(a, idx);
+                atomicAdd(&hist[code >> a.cptlog], 1u);
             } else {
                 ++outside;
             }
-            a.codes[p] = (int)code;
+            a.codes[p] = code;
         }
     }
     __syncthreads();
@@ -180,9 +173,9 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) rec.phi[k] = (ok && k < C) ? (R)phi[k] : (R)0;
-            rec.loc = ok ? (uint32_t)(code[u] % a.cpt) : kPsiSkip;
+            rec.loc = ok ? (uint32_t)(code[u] & (a.cpt - 1)) : kPsiSkip;
             bad += ok ? 0ull : 1ull;
-            unsigned int slot = atomicAdd(&cursor[code[u] / a.cpt], 1u);
+            unsigned int slot = atomicAdd(&cursor[code[u] >> a.cptlog], 1u);
             bucket[slot] = rec;
 #pragma unroll
             for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], fabs((double)rec.phi[k]));
