@@ -148,7 +148,7 @@ def large_section(ctx, args, dev, model):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     rows, perf = [], None
     for pa in (320, 256, 200):
-        wl = W.c5_multi_vortex(per_axis=pa, mesh_n=256, device=dev)
+        wl = W.multi_vortex_lattice_3d(per_axis=pa, mesh_n=256, device=dev)
         tr = wl.traj
         st, keep = F.make_trajectories(tr.x, tr.J, tr.v.float(), tr.ug.float(), tr.r.float(), tr.n0, tr.seed_volume)
         wl.traj = None
@@ -229,7 +229,7 @@ def learned_vs_plain(ctx, args, dev):
     t0 = time.perf_counter()
     train = []
     for s in range(args.train_snapshots):
-        wl, abc = W.c4_snapshot(s, n_traj=args.train_trajectories, mesh_n=64, device=dev)
+        wl, abc = W.training_snapshot(s, n_traj=args.train_trajectories, mesh_n=64, device=dev)
         p = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
         ref, _ = _psicell_reference(ctx, F, W, torch, wl.mesh, abc, args.train_particles, 10_000 + s, p, dev)
         train.append(snap_of(wl, ref))
@@ -237,7 +237,7 @@ def learned_vs_plain(ctx, args, dev):
             log(f"training snapshots: {s + 1}")
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    wl2 = W.c2_abc(device=dev)
+    wl2 = W.abc_lattice_3d(device=dev)
     p2 = F.Params(rho_d=wl2.rho_d, mu=wl2.mu, delta=wl2.delta, h0=wl2.h0, cutoff=wl2.cutoff)
     ref2, floor = _psicell_reference(ctx, F, W, torch, wl2.mesh, W.ABC(), args.psicell_particles, 0, p2, dev)
     del wl2
@@ -258,7 +258,7 @@ def learned_vs_plain(ctx, args, dev):
 
     rows = []
     for pa in (128, 100, 80, 64, 50):
-        wl = W.c2_abc(per_axis=pa, mesh_n=128, device=dev)
+        wl = W.abc_lattice_3d(per_axis=pa, mesh_n=128, device=dev)
         sn = snap_of(wl, ref2)
         out = {"trajectories": pa ** 3}
         hf = model.factors(sn)[0]
@@ -311,7 +311,7 @@ def batch_section(ctx, args, dev):
     import workloads as W
 
     t0 = time.time()
-    wls = [W.c3_snapshot(s, device=dev) for s in range(args.batch_snapshots)]
+    wls = [W.uneven_snapshot(s, device=dev) for s in range(args.batch_snapshots)]
     meshes, trajs, keeps, outs, params = [], [], [], [], []
     for wl in wls:
         tr = wl.traj
@@ -403,7 +403,7 @@ def cpu_baseline(seconds: float):
     import workloads as W
     cores = len(os.sched_getaffinity(0))
     oracle.set_threads(cores)
-    wl = W.c2_abc(device="cpu")
+    wl = W.abc_lattice_3d(device="cpu")
     f = lambda t: t.to(torch.float32).to(torch.float64)
     tr = W.Trajectories(wl.traj.x, wl.traj.J, f(wl.traj.v), f(wl.traj.ug), f(wl.traj.r), wl.traj.n0)
     t0 = time.perf_counter()
@@ -466,7 +466,7 @@ def main():
 
     dev = torch.device("cuda", 0)
     log("generating the 128^3 / 2M-trajectory ABC workload on the GPU")
-    wl = W.c2_abc(device=dev)
+    wl = W.abc_lattice_3d(device=dev)
     tr = wl.traj
     x = tr.x.contiguous()
     J = tr.J.contiguous()

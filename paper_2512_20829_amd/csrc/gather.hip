@@ -5,9 +5,9 @@
 // the trajectories of its tile in a fixed order, so results are bitwise
 // reproducible.
 //
-// Work decomposition (one workgroup of four 64-lane waves per tile; the
-// waves take the tile's candidate chunks in turn and their partial sums are
-// added in wave order at the end):
+// Work decomposition (one workgroup of four 64-lane waves per tile in 3-D,
+// two in 2-D; the waves take the tile's candidate chunks in turn and their
+// partial sums are added in wave order at the end):
 //  * a tile is TE^D cells, split into 2^D sub-blocks of SB^D cells; lane l
 //    owns the cell with in-block coordinates lc(l) in every sub-block;
 //  * candidate trajectories come from the buckets (class k, home tile) of
@@ -21,7 +21,11 @@
 //    per-half minima of s;
 //  * every lane then walks the batch: a sub-block is visited only if the
 //    minima admit a pair there (an exact, wave-uniform skip); a pair costs
-//    2 adds, 1 compare, 2 multiplies, 1 select and C+1 multiply-adds;
+//    2 adds, 1 compare, 2 multiplies, 1 select and C+1 multiply-adds; in
+//    binary32 the C channel multiply-adds of a sub-block run as one
+//    4x4x1 matrix instruction, and the 3-D plan-1 loop takes four records
+//    per step under the union of their skips (records that reach no cell
+//    of a visited pair of sub-blocks add exact zeros);
 //  * binary32 partial sums of one batch are folded into compensated
 //    (TwoSum) totals, binary64 sums need no compensation.
 #include "internal.hpp"

@@ -154,7 +154,7 @@ def test_batch_matches_oracle(ctx, prec):
 
 
 def test_batch_2d(ctx):
-    wls = [W.c1_taylor_green(), W.c1_taylor_green()]
+    wls = [W.taylor_green_2d(), W.taylor_green_2d()]
     wls[1] = W.Workload("tg_small_h", wls[1].mesh, wls[1].traj, wls[1].h0 * 0.5, "f64")
     b = Batch(wls, "f64")
     b.run(ctx)
@@ -246,7 +246,7 @@ def test_batch_rejects_bad_arguments(ctx):
     with pytest.raises(F.FlaError, match="same prec"):
         ctx.project_batch(b.meshes, [b.trajs[0], st64], b.params, b.outs)
     # mixed dimensions
-    tg = W.c1_taylor_green()
+    tg = W.taylor_green_2d()
     with pytest.raises(F.FlaError, match="same mesh.dim"):
         ctx.project_batch([b.meshes[0], F.mesh_of(tg.mesh)], b.trajs, b.params, b.outs)
     # an invalid h0 names its snapshot
@@ -265,7 +265,7 @@ def test_uneven_batch_full_size_sampled(ctx):
     about 24M in all) in the launch form the benchmark times, checked against
     the oracle on sampled cells of every snapshot."""
     import paper_2512_20829_amd as F
-    wls = [W.c3_snapshot(s, device=DEV) for s in range(64)]
+    wls = [W.uneven_snapshot(s, device=DEV) for s in range(64)]
     b = Batch(wls, "f32")
     print(f"[case] c3 batch N={sum(w.traj.count for w in wls)} cells={sum(w.mesh.cells for w in wls)}", flush=True)
     b.run(ctx)
@@ -294,4 +294,4 @@ def test_uneven_batch_full_size_sampled(ctx):
             assert err <= 1e-5, f"snapshot {s} field {k}: sampled max rel error {err:.2e}"
         dref = ref.den
         assert np.abs(den[cells] - dref).max() <= 1e-5 * max(np.abs(dref).max(), 1e-300)
-    print(f"[c3] worst sampled relative error {worst:.2e}", flush=True)
+    print(f"[uneven snapshots] worst sampled relative error {worst:.2e}", flush=True)

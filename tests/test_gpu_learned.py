@@ -79,7 +79,7 @@ def test_features_and_network_forward(ctx, dim):
     if dim == 3:
         wl = W.small_random_3d(3000, 16, seed=21)
     else:
-        wl = W.c1_taylor_green(per_axis=48, mesh_n=40)
+        wl = W.taylor_green_2d(per_axis=48, mesh_n=40)
     _, f0, _ = _oracle_forward(wl, LN.init_params(0))
     theta = _theta(21, f0)
     hf, z, o, fr = _gpu_forward(ctx, wl, theta)
@@ -231,7 +231,7 @@ def test_learned_form_full_size(ctx):
     oracle, then the projection with the oracle's factors on 256 sampled
     cells (the factors are an input of the projection)."""
     from helpers import gpu_run, oracle_run
-    wl = W.c2_abc()
+    wl = W.abc_lattice_3d()
     print(f"[case] learned full size N={wl.traj.count}", flush=True)
     _, f0, _ = _oracle_forward(wl, LN.init_params(0))
     theta = _theta(23, f0)

@@ -40,20 +40,20 @@ def _check(ctx, wl, prec=None, **kw):
     return S, den, st, ref
 
 
-def test_c1_taylor_green_2d_f64(ctx):
-    wl = W.c1_taylor_green()
+def test_taylor_green_2d_f64(ctx):
+    wl = W.taylor_green_2d()
     S, den, st, ref = _check(ctx, wl, "f64")
     assert (ref.den > 0).all()
 
 
-def test_c1_non_evaporating(ctx):
-    wl = W.c1_taylor_green(delta=0.0)
+def test_taylor_green_non_evaporating(ctx):
+    wl = W.taylor_green_2d(delta=0.0)
     S, _, _, _ = _check(ctx, wl, "f64")
     assert np.all(S[0] == 0.0)
 
 
 def test_2d_f32_small(ctx):
-    wl = W.c1_taylor_green(per_axis=40, mesh_n=37)
+    wl = W.taylor_green_2d(per_axis=40, mesh_n=37)
     _check(ctx, wl, "f32")
 
 
@@ -119,29 +119,29 @@ def test_bitwise_deterministic(ctx):
     assert np.array_equal(S1, S2) and np.array_equal(d1, d2)
 
 
-def test_c2_full_size_sampled_cells(ctx):
+def test_abc_full_size_sampled_cells(ctx):
     """The 128^3 / 2M-trajectory ABC case in the launch configuration the
     benchmark times, checked on 256 sampled cells computed one by one by the
     oracle over all trajectories."""
-    wl = W.c2_abc()
+    wl = W.abc_lattice_3d()
     S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False)
     g = np.random.default_rng(0)
     cells = np.sort(g.choice(wl.mesh.cells, 256, replace=False))
     oracle.set_threads(16)
     ref, _ = oracle_run(wl, prec="f32", cells=cells)
-    assert_fields_close(S[:, cells], ref.S, TOL["f32"], "c2 sampled")
+    assert_fields_close(S[:, cells], ref.S, TOL["f32"], "abc 128^3 sampled")
     assert rel_l2(den[cells], ref.den) <= TOL["f32"]
     assert st["skipped"] == 0
 
 
 @pytest.mark.slow
 @pytest.mark.timeout(400)
-def test_c5_full_size_sampled_cells(ctx):
+def test_multi_vortex_full_size_sampled_cells(ctx):
     """The 256^3 / 32.8M-trajectory multi-vortex case (|det J| down to ~1e-8,
     sign changes) in the benchmark's launch configuration, checked on 256
     sampled cells computed one by one by the oracle over all trajectories."""
     dev = torch.device("cuda", 0)
-    wl = W.c5_multi_vortex(device=dev)
+    wl = W.multi_vortex_lattice_3d(device=dev)
     wl.traj = wl.traj.to("cpu")
     print(f"[case] c5 N={wl.traj.count} mesh={wl.mesh.n}", flush=True)
     S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False)
@@ -150,7 +150,7 @@ def test_c5_full_size_sampled_cells(ctx):
     cells = np.sort(g.choice(wl.mesh.cells, 256, replace=False))
     oracle.set_threads(16)
     ref, terms = oracle_run(wl, prec="f32", cells=cells)
-    assert_fields_close(S[:, cells], ref.S, TOL["f32"], "c5 sampled")
+    assert_fields_close(S[:, cells], ref.S, TOL["f32"], "multi-vortex sampled")
     assert rel_l2(den[cells], ref.den) <= TOL["f32"]
     assert st["skipped"] == terms.skipped
     assert st["max_class"] == 7          # the widest bandwidths span whole axes
@@ -182,9 +182,9 @@ def test_deposit_zero_support_goes_home(ctx):
 
 
 # ------------------------------------------------------------------ PSI-CELL
-def test_psicell_c1_cloud_f64(ctx):
-    wl = W.c1_taylor_green()
-    cloud = W.c1_cloud()
+def test_psicell_taylor_green_cloud_f64(ctx):
+    wl = W.taylor_green_2d()
+    cloud = W.taylor_green_cloud()
     w = W.N0_DEFAULT / cloud.count
     S, den, st = gpu_run(ctx, wl, prec="f64", psicell_cloud=cloud, weight=w)
     Sref, counts, sk = oracle.psicell(wl.mesh, cloud, w, wl.rho_d, wl.mu, wl.delta)

@@ -20,7 +20,7 @@ def setup():
     ctx = F.Context(0)
     snaps = []
     for s in range(6):
-        wl, abc = W.c4_snapshot(s, n_traj=6000, mesh_n=16, device=DEV)
+        wl, abc = W.training_snapshot(s, n_traj=6000, mesh_n=16, device=DEV)
         tr = wl.traj
         st, keep = F.make_trajectories(tr.x, tr.J, tr.v.float(), tr.ug.float(), tr.r.float(), tr.n0, tr.seed_volume)
         keep.append(tr)

@@ -17,7 +17,7 @@ def _rel(a, b):
 
 def test_nw_converges_to_psicell_on_taylor_green():
     mesh_n = 32
-    cloud = W.c1_cloud(n_particles=400_000, seed=0)
+    cloud = W.taylor_green_cloud(n_particles=400_000, seed=0)
     mesh = W.unit_mesh(2, mesh_n, False)
     Np = cloud.count
     w = W.N0_DEFAULT * 1.0 / Np
@@ -32,7 +32,7 @@ def test_nw_converges_to_psicell_on_taylor_green():
     floor2 = np.sum((SA - SB) ** 2) / (4 * np.sum(S_psi ** 2))
     errs = []
     for per_axis in (8, 16, 32, 64):
-        wl = W.c1_taylor_green(per_axis=per_axis, mesh_n=mesh_n)
+        wl = W.taylor_green_2d(per_axis=per_axis, mesh_n=mesh_n)
         p, t = oracle.project(wl.mesh, wl.traj, RHO, MU, DELTA, wl.h0)
         assert (p.den > 0).all()
         e2 = np.sum((p.S - S_psi) ** 2) / np.sum(S_psi ** 2)

@@ -310,7 +310,7 @@ def test_skips_degenerate_trajectories():
 # ---------------------------------------------------------------- number density
 def test_number_density_conservation_on_lattice():
     """n |det J| V_seed summed over a lattice equals n0 times the seeded volume."""
-    wl = W.c1_taylor_green(per_axis=32, mesh_n=32)
+    wl = W.taylor_green_2d(per_axis=32, mesh_n=32)
     t = oracle.trajectory_terms(wl.traj, RHO, MU, DELTA, wl.h0)
     total = np.sum(t.n * np.abs(t.det) * wl.traj.seed_volume)
     assert total == pytest.approx(W.N0_DEFAULT * 1.0, rel=1e-13)

@@ -303,7 +303,7 @@ class Workload:
     extra: Dict = field(default_factory=dict)
 
 
-def c1_taylor_green(per_axis: int = 64, mesh_n: int = 64, seed: int = 0, device="cpu",
+def taylor_green_2d(per_axis: int = 64, mesh_n: int = 64, seed: int = 0, device="cpu",
                     delta: float = DELTA_EVAP) -> Workload:
     """2-D FP64: unit square, Taylor-Green map amplitude 0.1, lattice seeding,
     r ~ U[5, 20] um, n0 = 1e10 m^-3, h0 = lattice pitch."""
@@ -311,10 +311,10 @@ def c1_taylor_green(per_axis: int = 64, mesh_n: int = 64, seed: int = 0, device=
     xp, J, v, ug = from_map(x0, "tg", {"amp": 0.1})
     r = radius_uniform(x0.shape[1], seed, 5.0, 20.0, device)
     tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / per_axis ** 2)
-    return Workload("c1_tg2d_f64", unit_mesh(2, mesh_n, False), tr, 1.0 / per_axis, "f64", delta=delta)
+    return Workload("tg2d_f64", unit_mesh(2, mesh_n, False), tr, 1.0 / per_axis, "f64", delta=delta)
 
 
-def c1_cloud(n_particles: int = 400_000, seed: int = 0, device="cpu"):
+def taylor_green_cloud(n_particles: int = 400_000, seed: int = 0, device="cpu"):
     """PSI-CELL comparator cloud for the 2-D case: X0 ~ U[0,1]^2, same map and radius law."""
     x0 = random_points(2, n_particles, seed, device)
     xp, J, v, ug = from_map(x0, "tg", {"amp": 0.1})
@@ -322,7 +322,7 @@ def c1_cloud(n_particles: int = 400_000, seed: int = 0, device="cpu"):
     return Trajectories(xp, J, v, ug, r, 1.0)
 
 
-def c2_abc(per_axis: int = 128, mesh_n: int = 128, seed: int = 0, device="cpu",
+def abc_lattice_3d(per_axis: int = 128, mesh_n: int = 128, seed: int = 0, device="cpu",
            amp: float = 0.2) -> Workload:
     """3-D: periodic unit cube, ABC map amplitude 0.2 (A=B=C=1), lattice seeding,
     r ~ lognormal(ln 10 um, 0.3), h0 = lattice pitch, FP32 kernel evaluation."""
@@ -330,7 +330,7 @@ def c2_abc(per_axis: int = 128, mesh_n: int = 128, seed: int = 0, device="cpu",
     xp, J, v, ug = from_map(x0, "abc", ABC(amp=amp), wrap=True)
     r = radius_lognormal(x0.shape[1], seed, device=device)
     tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / per_axis ** 3)
-    return Workload("c2_abc3d_f32", unit_mesh(3, mesh_n, True), tr, 1.0 / per_axis, "f32")
+    return Workload("abc3d_f32", unit_mesh(3, mesh_n, True), tr, 1.0 / per_axis, "f32")
 
 
 def abc_cloud(n_particles: int, seed: int = 0, device="cpu", abc: Optional[ABC] = None,
@@ -372,15 +372,15 @@ def multi_vortex_cloud(n_particles: int, seed: int = 0, device="cpu", maps: Opti
     return Trajectories(wrap_unit(x), torch.empty(0, dtype=torch.float64, device=device), v, ug, r, 1.0)
 
 
-def c5_multi_vortex(per_axis: int = 320, mesh_n: int = 256, seed: int = 0, device="cpu") -> Workload:
+def multi_vortex_lattice_3d(per_axis: int = 320, mesh_n: int = 256, seed: int = 0, device="cpu") -> Workload:
     x0 = lattice(3, per_axis, device)
     xp, J, v, ug = from_map(x0, "multi", multi_vortex_default(seed), wrap=True)
     r = radius_lognormal(x0.shape[1], seed, device=device)
     tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / per_axis ** 3)
-    return Workload("c5_multivortex3d_f32", unit_mesh(3, mesh_n, True), tr, 1.0 / per_axis, "f32")
+    return Workload("multivortex3d_f32", unit_mesh(3, mesh_n, True), tr, 1.0 / per_axis, "f32")
 
 
-def c3_snapshot(s: int, device="cpu") -> Workload:
+def uneven_snapshot(s: int, device="cpu") -> Workload:
     """One snapshot of the uneven batch: edge L = round(32*4^u), N = round(1e4*200^u'),
     random seeding, ABC amplitude U[0.05, 0.2] with random phases, h0 = N^(-1/3)."""
     u = counter_uniform(1000 + s, 0, 6)
@@ -392,10 +392,10 @@ def c3_snapshot(s: int, device="cpu") -> Workload:
     xp, J, v, ug = from_map(x0, "abc", abc, wrap=True)
     r = radius_lognormal(N, 1000 + s, device=device)
     tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / N)
-    return Workload(f"c3_snap{s}", unit_mesh(3, L, True), tr, N ** (-1.0 / 3.0), "f32")
+    return Workload(f"uneven_snap{s}", unit_mesh(3, L, True), tr, N ** (-1.0 / 3.0), "f32")
 
 
-def c4_snapshot(s: int, n_traj: int = 200_000, mesh_n: int = 64, device="cpu") -> Tuple[Workload, ABC]:
+def training_snapshot(s: int, n_traj: int = 200_000, mesh_n: int = 64, device="cpu") -> Tuple[Workload, ABC]:
     """Training snapshot: random seeding, ABC with A,B,C ~ U[0.5,1.5], amplitude
     U[0.05,0.25], random phases; h0 = N^(-1/3)."""
     u = counter_uniform(2000 + s, 0, 7)
@@ -406,7 +406,7 @@ def c4_snapshot(s: int, n_traj: int = 200_000, mesh_n: int = 64, device="cpu") -
     xp, J, v, ug = from_map(x0, "abc", abc, wrap=True)
     r = radius_lognormal(n_traj, 2000 + s, device=device)
     tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / n_traj)
-    return Workload(f"c4_snap{s}", unit_mesh(3, mesh_n, True), tr, n_traj ** (-1.0 / 3.0), "f32"), abc
+    return Workload(f"training_snap{s}", unit_mesh(3, mesh_n, True), tr, n_traj ** (-1.0 / 3.0), "f32"), abc
 
 
 def small_random_3d(n_traj: int, mesh_n: int, seed: int, device="cpu", periodic=True,
