@@ -5,27 +5,31 @@
 // the trajectories of its tile in a fixed order, so results are bitwise
 // reproducible.
 //
-// Work decomposition (one workgroup of four 64-lane waves per tile in 3-D,
-// two in 2-D; the waves take the tile's candidate chunks in turn and their
-// partial sums are added in wave order at the end):
+// Work decomposition (one workgroup of four 64-lane waves per half tile in
+// 3-D, the tile cut across x; two waves per tile in 2-D; the waves take the
+// candidate chunks in turn and their partial sums are added in wave order at
+// the end):
 //  * a tile is TE^D cells, split into 2^D sub-blocks of SB^D cells; lane l
-//    owns the cell with in-block coordinates lc(l) in every sub-block;
+//    owns the cell with in-block coordinates lc(l) in every sub-block of its
+//    workgroup;
 //  * candidate trajectories come from the buckets (class k, home tile) of
 //    the neighbourhood of the tile: a class-k trajectory reaches at most k
 //    tiles from its home tile (the last class spans whole axes);
 //  * a conservative binary64 sphere/box test compacts candidates into an
 //    LDS list (order preserved with wave ballots);
 //  * per batch of 64 candidates the lanes build, in LDS, the per-axis factors
-//    s = (d/h)^2 and e = exp(-s/2) for the TE cell centres of the tile on
+//    s = (d/h)^2 and e = exp(-s/2) for the cell centres of the workgroup on
 //    every axis (the Gaussian is separable on a Cartesian mesh), plus the
-//    per-half minima of s;
+//    per-half minima of s, in straight-line code (the minimum image and the
+//    delta records take one branch per axis);
 //  * every lane then walks the batch: a sub-block is visited only if the
 //    minima admit a pair there (an exact, wave-uniform skip); a pair costs
 //    2 adds, 1 compare, 2 multiplies, 1 select and C+1 multiply-adds; in
 //    binary32 the C channel multiply-adds of a sub-block run as one
 //    4x4x1 matrix instruction, and the 3-D plan-1 loop takes four records
 //    per step under the union of their skips (records that reach no cell
-//    of a visited pair of sub-blocks add exact zeros);
+//    of a visited pair of sub-blocks add exact zeros; the unions come from
+//    two lane permutations of the masks);
 //  * binary32 partial sums of one batch are folded into compensated
 //    (TwoSum) totals, binary64 sums need no compensation.
 #include "internal.hpp"
@@ -55,12 +59,27 @@ __device__ inline void two_sum_acc(R& hi, R& lo, R p)
 // tiles have twice the cells per axis and whose staging tables are larger
 template <int D> struct GatherWaves { static constexpr int value = D == 3 ? 4 : 2; };
 
+// Workgroups per tile: in 3-D each workgroup owns one half of the tile along
+// x (4 of its 8 sub-blocks), which halves the registers of its sums and its
+// staging space, so that more workgroups share a compute unit.  (Along x: the
+// inclusion sum is ((s_x + s_y) + s_z), so sub-blocks paired along z still
+// share their partial sum s_x + s_y.)
+template <int D> struct ZSplit { static constexpr int value = D == 3 ? 2 : 1; };
+
+// Waves per SIMD the register allocation is held to.
+template <typename R, int D> struct GatherOcc {
+    static constexpr int value = sizeof(R) == 4 ? (ZSplit<D>::value == 2 ? 3 : 2) : 1;
+};
+
 template <typename R, int D>
 struct GatherLds {
     using R4 = typename V4<R>::T;
-    static constexpr int SB = Geo<D>::SB, NA = D + 2;
+    using R2 = typename V2<R>::T;
+    static constexpr int SB = Geo<D>::SB, NA = D + 2, ZS = ZSplit<D>::value;
+    static constexpr int NT = ZS == 2 ? D - 1 : D;   // axes staged for both halves (split: y, z)
     uint32_t cand[kCap];               // compacted candidate record indices
-    R4 tab[kWave][D][SB];              // {s, e} at in-block position l and l + SB
+    R4 tab[kWave][NT][SB];             // {s, e} at in-block position l and l + SB
+    R2 tabs[kWave][ZS == 2 ? SB : 1];  // split axis x: {s, e} of the owned half
     R wts[kWave][NA];                  // {1/h, q/h ...} of each staged record
     int mask[kWave];                   // sub-blocks holding at least one included pair
 };
@@ -68,54 +87,95 @@ struct GatherLds {
 // Per-axis factors of one record for the tile at tile coordinates tc, whose
 // cell centres are xcs: tab[a][l] = {s, e} at in-block positions l and
 // l + SB of axis a, with s = (d/h)^2 (binary64 rounded to R) and
-// e = exp(-s/2); a delta record (1/h < 0) has factor 1 at its home cell and
-// 0 elsewhere.  Returns the sub-block visit mask: bit b is set iff the sum of
-// the per-axis minima of s over sub-block b passes the cutoff (sums are
-// monotone in each term, so no sub-block holding an included pair is
-// skipped).
+// e = exp(-s/2); with the split, axis x is staged for the owned half
+// only, tabs[l] = {s, e} at position soff + l.  A delta record (1/h < 0) has
+// factor 1 at its home cell and 0 elsewhere.  Returns the visit mask of the
+// workgroup's sub-blocks: bit b is set iff the sum of the per-axis minima of
+// s over sub-block b passes the cutoff (sums are monotone in each term, so
+// no sub-block holding an included pair is skipped).
 template <typename R, int D>
 __device__ __forceinline__ int stage_record(const MeshDev& m, const double (*xcs)[Geo<D>::TE], const int* tc,
-                                            const double4 P, const R c2, typename V4<R>::T (*tab)[Geo<D>::SB])
+                                            const int soff, const double4 P, const R c2,
+                                            typename V4<R>::T (*tab)[Geo<D>::SB], typename V2<R>::T* tabs)
 {
     using G = Geo<D>;
-    constexpr int TE = G::TE, SB = G::SB, NSB = G::NSB;
+    constexpr int TE = G::TE, SB = G::SB, NP = 2 * SB, ZS = ZSplit<D>::value, NSB = G::NSB / ZS;
     using R4 = typename V4<R>::T;
+    using R2 = typename V2<R>::T;
     double x[3] = {P.x, P.y, P.z};
-    bool delta = P.w < 0.0;
-    double inv_h = delta ? -P.w : P.w;
+    const bool delta = P.w < 0.0;
+    const double inv_h = delta ? -P.w : P.w;
     R mn[3][2];
+    // Straight-line code per axis (the positions are independent chains);
+    // the minimum image and the delta records take one branch per axis.
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        int64_t hcell = delta ? home_index(m, a, x[a]) : -1;
+        const bool one = ZS == 2 && a == 0;   // one half of this axis, at soff
+        const int np = one ? SB : NP;
+        double d[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            // positions l and l + SB of the sub-blocks, or soff + l
+            const int pp = one ? soff + p : p;
+            d[p] = (p < np) ? xcs[a][pp] - x[a] : 0.0;
+        }
+        if (m.periodic[a]) {
+            // centres of cells beyond the mesh are NaN, ignored by fmax
+            double dm = 0.0;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) dm = fmax(dm, fabs(d[p]));
+            const double L = m.L[a];
+            if (dm > 0.5 * L) {
+                if (dm < L) {
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+#pragma clang fp contract(off)
+                        const double w = d[p] > 0.0 ? d[p] - L : d[p] + L;
+                        d[p] = fabs(d[p]) <= 0.5 * L ? d[p] : w;
+                    }
+                } else {
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) d[p] = min_image(d[p], L);
+                }
+            }
+        }
+        // s = (d/h)^2 rounded to R, e = exp(-s/2); a NaN centre gives a NaN s,
+        // which never passes the test and is ignored by the minima
+        R sv[NP], ev[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            sv[p] = (R)scaled_sq(d[p], inv_h);
+            ev[p] = gauss_factor(sv[p]);
+        }
+        if (delta) {
+            // whole amount into the home cell: factor 1 there, 0 elsewhere
+            const int64_t hcell = home_index(m, a, x[a]);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int pp = one ? soff + p : p;
+                const bool home = (int64_t)tc[a] * TE + pp == hcell;
+                sv[p] = home ? (R)0 : r_inf<R>();
+                ev[p] = home ? (R)1 : (R)0;
+            }
+        }
         R mlo = r_inf<R>(), mhi = r_inf<R>();
 #pragma unroll
         for (int l = 0; l < SB; ++l) {
-            R sv[2], ev[2];
-#pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-                int pp = l + hh * SB;
-                if (delta) {
-                    // whole amount into the home cell: factor 1 there, 0 elsewhere
-                    bool home = (int64_t)tc[a] * TE + pp == hcell;
-                    sv[hh] = home ? (R)0 : r_inf<R>();
-                    ev[hh] = home ? (R)1 : (R)0;
-                } else {
-                    // centres of cells beyond the mesh are NaN: s is NaN, never
-                    // passes the test, and is ignored by the min/max below
-                    double d = axis_offset(m, a, xcs[a][pp], x[a]);
-                    R sr = (R)scaled_sq(d, inv_h);
-                    sv[hh] = sr;
-                    ev[hh] = gauss_factor(sr);
-                }
+            if (one) {
+                R2 t2;
+                t2.x = sv[l];
+                t2.y = ev[l];
+                tabs[l] = t2;
+            } else {
+                R4 t4;
+                t4.x = sv[l];
+                t4.y = ev[l];
+                t4.z = sv[l + SB];
+                t4.w = ev[l + SB];
+                tab[ZS == 2 ? a - 1 : a][l] = t4;
+                mhi = fmin(mhi, sv[l + SB]);
             }
-            R4 t4;
-            t4.x = sv[0];
-            t4.y = ev[0];
-            t4.z = sv[1];
-            t4.w = ev[1];
-            tab[a][l] = t4;
-            mlo = fmin(mlo, sv[0]);
-            mhi = fmin(mhi, sv[1]);
+            mlo = fmin(mlo, sv[l]);
         }
         mn[a][0] = mlo;
         mn[a][1] = mhi;
@@ -126,8 +186,12 @@ __device__ __forceinline__ int stage_record(const MeshDev& m, const double (*xcs
     int mk = 0;
 #pragma unroll
     for (int b = 0; b < NSB; ++b) {
-        R smin = mn[0][b & 1] + mn[1][(b >> 1) & 1];
-        if (D == 3) smin = smin + mn[2][(b >> 2) & 1];
+        // sub-block bits: (x, y, z), or (y, z) with x split
+        const int bx = ZS == 2 ? 0 : b & 1;
+        const int by = ZS == 2 ? b & 1 : (b >> 1) & 1;
+        const int bz = ZS == 2 ? (b >> 1) & 1 : (b >> 2) & 1;
+        R smin = mn[0][bx] + mn[1][by];
+        if (D == 3) smin = smin + mn[2][bz];
         mk |= (smin <= c2) ? (1 << b) : 0;
     }
     return mk;
@@ -230,15 +294,19 @@ __device__ __forceinline__ bool candidate_ok(const MeshDev& m, const double4 P, 
     return acc <= filt2;
 }
 
-// The work of one workgroup: every cell of tile `tile` of the mesh of g.
+// The work of one workgroup: every cell of its part `work % ZS` of tile
+// `work / ZS` of the mesh of g.
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
-__device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
+__device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
 {
     constexpr int kGatherWaves = GatherWaves<D>::value;
     using G = Geo<D>;
-    constexpr int TE = G::TE, SB = G::SB, NSB = G::NSB, C = D + 1, NA = C + 1;
+    constexpr int ZS = ZSplit<D>::value;
+    constexpr int TE = G::TE, SB = G::SB, NSB = G::NSB / ZS, C = D + 1, NA = C + 1;
+    constexpr int NT = GatherLds<R, D>::NT;
     constexpr bool kComp = sizeof(R) == 4;
     using R4 = typename V4<R>::T;
+    using R2 = typename V2<R>::T;
     using L = GatherLds<R, D>;
     static_assert(sizeof(L) * kGatherWaves >= sizeof(R) * kGatherWaves * NSB * NA * kWave,
                   "reduction buffer must fit in the staging space");
@@ -249,10 +317,14 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     L& my = lds[wave];
+    const int tile = work / ZS;
+    const int soff = (ZS == 2) ? (work % ZS) * SB : 0;   // first owned cell of the tile along x
     int tc[3];
     tc[0] = tile % m.nt[0];
     tc[1] = (tile / m.nt[0]) % m.nt[1];
     tc[2] = (D == 3) ? tile / (m.nt[0] * m.nt[1]) : 0;
+    // a part lying wholly beyond the mesh has no cells (uniform over the workgroup)
+    if (ZS == 2 && (int64_t)tc[0] * TE + soff >= m.n[0]) return;
 
     if (threadIdx.x < D * TE) {
         int a = threadIdx.x / TE, p = threadIdx.x % TE;
@@ -279,8 +351,10 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
     bool faxis[3] = {false, false, false};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        double f = cell_centre(m, a, (int64_t)tc[a] * TE);
-        double l = cell_centre(m, a, (int64_t)tc[a] * TE + TE - 1);
+        const bool one = ZS == 2 && a == 0;
+        const int64_t c0 = (int64_t)tc[a] * TE + (one ? soff : 0);
+        double f = cell_centre(m, a, c0);
+        double l = cell_centre(m, a, c0 + (one ? SB : TE) - 1);
         bmid[a] = 0.5 * (f + l);
         bhalf[a] = 0.5 * (l - f);
         faxis[a] = !(m.periodic[a] && 4.0 * bhalf[a] >= m.L[a]);
@@ -316,12 +390,15 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
             const R* w = (const R*)g.rw + (size_t)p * kRecW;
 #pragma unroll
             for (int k = 0; k < NA; ++k) my.wts[lane][k] = w[k];
-            my.mask[lane] = stage_record<R, D>(m, xcs, tc, P, c2, my.tab[lane]);
+            my.mask[lane] = stage_record<R, D>(m, xcs, tc, soff, P, c2, my.tab[lane], my.tabs[lane]);
         }
         wave_sync();
         // every lane keeps the mask of one staged record (read with readlane,
         // no LDS round trip)
         const int maskv = (lane < n) ? my.mask[lane] : 0;
+        // union of the masks of records 4q .. 4q + 3, on the lanes of quad q
+        int mask4 = maskv | __builtin_amdgcn_mov_dpp(maskv, 0xB1, 0xF, 0xF, false);
+        mask4 = mask4 | __builtin_amdgcn_mov_dpp(mask4, 0x4E, 0xF, 0xF, false);
         // one sub-block of one record: the per-pair inclusion test, then the
         // denominator multiply-add and the C channel multiply-adds.  In
         // binary32 the channels go to one v_mfma_f32_4x4x1_16b_f32: with A
@@ -331,13 +408,23 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
         // so that register k of lane l accumulates channel k of the lane's
         // cell: the layout of the vector path, with 4 multiply-adds per lane
         // moved off the vector unit.
-        auto sub = [&](int b, const R4* t, const R* wv, float wq, bool live = true) {
-            const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
-            R s = (bx ? t[0].z : t[0].x) + (by ? t[1].z : t[1].x);
-            R ew = (bx ? t[0].w : t[0].y) * (by ? t[1].w : t[1].y);
-            if (D == 3) {
-                s = s + (bz ? t[2].z : t[2].x);
-                ew = ew * (bz ? t[2].w : t[2].y);
+        auto sub = [&](int b, const R4* t, const R2& ts, const R* wv, float wq, bool live = true) {
+            R s, ew;
+            if constexpr (ZS == 2) {
+                // x split: ts holds the owned half of x, t the y and z tables
+                const int by = b & 1, bz = (b >> 1) & 1;
+                s = ts.x + (by ? t[0].z : t[0].x);
+                ew = ts.y * (by ? t[0].w : t[0].y);
+                s = s + (bz ? t[1].z : t[1].x);
+                ew = ew * (bz ? t[1].w : t[1].y);
+            } else {
+                const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+                s = (bx ? t[0].z : t[0].x) + (by ? t[1].z : t[1].x);
+                ew = (bx ? t[0].w : t[0].y) * (by ? t[1].w : t[1].y);
+                if constexpr (D == 3) {
+                    s = s + (bz ? t[2].z : t[2].x);
+                    ew = ew * (bz ? t[2].w : t[2].y);
+                }
             }
             bool in = s <= c2;
             ew = in ? ew : (R)0;
@@ -355,30 +442,30 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
         // tile, 3 none (every sub-block evaluated, masked by the pair test).
         // All plans add the same products; a skipped sub-block only saves
         // additions of zero.
-        auto accumulate = [&](int e, const R4* t, const R* wv, float wq) {
+        auto accumulate = [&](int e, const R4* t, const R2& ts, const R* wv, float wq) {
             const int mk = __builtin_amdgcn_readlane(maskv, e);
             if (mk == 0) return;
-            if (PLAN == 3 || (D == 2 && PLAN != 0)) {
+            if (PLAN == 3 || (D == 2 && PLAN != 0) || (PLAN == 2 && NSB == 4)) {
 #pragma unroll
-                for (int b = 0; b < NSB; ++b) sub(b, t, wv, wq);
+                for (int b = 0; b < NSB; ++b) sub(b, t, ts, wv, wq);
             } else if (PLAN == 2) {
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
                     if (mk & (0x0F << (4 * h))) {
 #pragma unroll
-                        for (int b = 4 * h; b < 4 * h + 4; ++b) sub(b, t, wv, wq);
+                        for (int b = 4 * h; b < 4 * h + 4; ++b) sub(b, t, ts, wv, wq);
                     }
             } else if (PLAN == 1) {
 #pragma unroll
                 for (int q = 0; q < NSB / 2; ++q)
                     if (mk & (((1 << (NSB / 2)) | 1) << q)) {
-                        sub(q, t, wv, wq);
-                        sub(q + NSB / 2, t, wv, wq);
+                        sub(q, t, ts, wv, wq);
+                        sub(q + NSB / 2, t, ts, wv, wq);
                     }
             } else {
 #pragma unroll
                 for (int b = 0; b < NSB; ++b)
-                    if (mk & (1 << b)) sub(b, t, wv, wq);
+                    if (mk & (1 << b)) sub(b, t, ts, wv, wq);
             }
         };
         // weights of staged record e: {1/h, q/h ...} on every lane, and, for
@@ -395,7 +482,14 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
                 wq = 0.0f;
             }
         };
-        R4 tA[3], tB[3];
+        // factors of staged record e at the lane's cells
+        auto load_t = [&](int e, R4* t, R2& ts) {
+#pragma unroll
+            for (int a = 0; a < NT; ++a) t[a] = my.tab[e][a][lc[ZS == 2 ? a + 1 : a]];
+            if (ZS == 2) ts = my.tabs[e][lc[0]];
+        };
+        R4 tA[NT], tB[NT];
+        R2 hA, hB;
         R wA[NA], wB[NA];
         float qA, qB;
         if (PLAN == 1 && D == 3 && kMfma) {
@@ -407,7 +501,8 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
             // and the four independent chains fill the issue slots.  Slots
             // past the batch end repeat record e with zero weights and are
             // not counted as pairs.
-            R4 tC[3], tD[3];
+            R4 tC[NT], tD[NT];
+            R2 hC, hD;
             R wC[NA], wD[NA];
             float qC, qD;
             for (int e = 0; e < n; e += 4) {
@@ -415,13 +510,10 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
                 const int e1 = l1 ? e + 1 : e;
                 const int e2 = l2 ? e + 2 : e;
                 const int e3 = l3 ? e + 3 : e;
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    tA[a] = my.tab[e][a][lc[a]];
-                    tB[a] = my.tab[e1][a][lc[a]];
-                    tC[a] = my.tab[e2][a][lc[a]];
-                    tD[a] = my.tab[e3][a][lc[a]];
-                }
+                load_t(e, tA, hA);
+                load_t(e1, tB, hB);
+                load_t(e2, tC, hC);
+                load_t(e3, tD, hD);
                 load_w(e, wA, qA);
                 load_w(e1, wB, qB);
                 load_w(e2, wC, qC);
@@ -441,43 +533,38 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
                     for (int k = 0; k < NA; ++k) wD[k] = 0;
                     qD = 0.0f;
                 }
-                const int mk = __builtin_amdgcn_readlane(maskv, e) | (l1 ? __builtin_amdgcn_readlane(maskv, e1) : 0) |
-                               (l2 ? __builtin_amdgcn_readlane(maskv, e2) : 0) |
-                               (l3 ? __builtin_amdgcn_readlane(maskv, e3) : 0);
+                const int mk = __builtin_amdgcn_readlane(mask4, e);
                 if (mk == 0) continue;
 #pragma unroll
                 for (int q = 0; q < NSB / 2; ++q)
                     if (mk & (((1 << (NSB / 2)) | 1) << q)) {
-                        sub(q, tA, wA, qA);
-                        sub(q + NSB / 2, tA, wA, qA);
-                        sub(q, tB, wB, qB, l1);
-                        sub(q + NSB / 2, tB, wB, qB, l1);
-                        sub(q, tC, wC, qC, l2);
-                        sub(q + NSB / 2, tC, wC, qC, l2);
-                        sub(q, tD, wD, qD, l3);
-                        sub(q + NSB / 2, tD, wD, qD, l3);
+                        sub(q, tA, hA, wA, qA);
+                        sub(q + NSB / 2, tA, hA, wA, qA);
+                        sub(q, tB, hB, wB, qB, l1);
+                        sub(q + NSB / 2, tB, hB, wB, qB, l1);
+                        sub(q, tC, hC, wC, qC, l2);
+                        sub(q + NSB / 2, tC, hC, wC, qC, l2);
+                        sub(q, tD, hD, wD, qD, l3);
+                        sub(q + NSB / 2, tD, hD, wD, qD, l3);
                     }
             }
         } else {
             // one record at a time; the factors of the next record are read
             // while the current one is accumulated
-#pragma unroll
-            for (int a = 0; a < D; ++a) tA[a] = my.tab[0][a][lc[a]];
+            load_t(0, tA, hA);
             load_w(0, wA, qA);
             for (int e = 0; e < n; e += 2) {
                 if (e + 1 < n) {
-#pragma unroll
-                    for (int a = 0; a < D; ++a) tB[a] = my.tab[e + 1][a][lc[a]];
+                    load_t(e + 1, tB, hB);
                     load_w(e + 1, wB, qB);
                 }
-                accumulate(e, tA, wA, qA);
+                accumulate(e, tA, hA, wA, qA);
                 if (e + 1 >= n) break;
                 if (e + 2 < n) {
-#pragma unroll
-                    for (int a = 0; a < D; ++a) tA[a] = my.tab[e + 2][a][lc[a]];
+                    load_t(e + 2, tA, hA);
                     load_w(e + 2, wA, qA);
                 }
-                accumulate(e + 1, tB, wB, qB);
+                accumulate(e + 1, tB, hB, wB, qB);
             }
         }
         if (kComp) {
@@ -543,7 +630,12 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
         bool inside = true;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            cidx[a] = (int64_t)tc[a] * TE + ((b >> a) & 1) * SB + lc[a];
+            int half;
+            if (ZS == 2)
+                half = a == 0 ? soff : ((b >> (a > 0 ? a - 1 : 0)) & 1) * SB;
+            else
+                half = ((b >> a) & 1) * SB;
+            cidx[a] = (int64_t)tc[a] * TE + half + lc[a];
             inside = inside && cidx[a] < m.n[a];
         }
         if (!inside) continue;
@@ -577,9 +669,9 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int tile)
 }
 
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
-__global__ __launch_bounds__(kWave * GatherWaves<D>::value, sizeof(R) == 4 ? 2 : 1) void k_gather(GatherArgs g)
+__global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::value)) void k_gather(GatherArgs g)
 {
-    gather_tile<R, D, MODE, COUNT, PLAN>(g, xcd_remap(blockIdx.x, g.m.ntiles));
+    gather_tile<R, D, MODE, COUNT, PLAN>(g, xcd_remap(blockIdx.x, g.m.ntiles * ZSplit<D>::value));
 }
 
 // Work item of workgroup `bid` of a batch of `nwork` items.  Workgroups are
@@ -598,10 +690,12 @@ __device__ inline int batch_work_item(int bid, int nwork, int chunk)
 // One workgroup per (snapshot, tile) of a batch.  The snapshots are stored in
 // work-list order: items[s].tile_base is the first work item of snapshot s.
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
-__global__ __launch_bounds__(kWave * GatherWaves<D>::value, sizeof(R) == 4 ? 2 : 1) void k_gather_batch(
+__global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::value)) void k_gather_batch(
     const BatchItem* __restrict__ items, int nsnap, int nwork, int chunk)
 {
-    const int j = batch_work_item(blockIdx.x, nwork, chunk);
+    constexpr int ZS = ZSplit<D>::value;
+    const int u = batch_work_item(blockIdx.x, nwork * ZS, chunk);
+    const int j = u / ZS;         // tile-level work item
     int lo = 0, hi = nsnap - 1;   // last snapshot whose first work item is <= j
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -610,7 +704,7 @@ __global__ __launch_bounds__(kWave * GatherWaves<D>::value, sizeof(R) == 4 ? 2 :
         else
             hi = mid - 1;
     }
-    gather_tile<R, D, MODE, COUNT, PLAN>(items[lo].g, j - items[lo].tile_base);
+    gather_tile<R, D, MODE, COUNT, PLAN>(items[lo].g, (j - items[lo].tile_base) * ZS + u % ZS);
 }
 
 template <typename R, int D, int MODE, bool COUNT>
@@ -627,7 +721,7 @@ static void launch_plan(const GatherArgs& g, int plan, dim3 grid, dim3 block, hi
 template <typename R, int D, bool COUNT>
 static void launch_batch_plan(const BatchItem* items, int nsnap, int nwork, int chunk, int plan, hipStream_t s)
 {
-    dim3 grid((unsigned)nwork), block(kWave * GatherWaves<D>::value);
+    dim3 grid((unsigned)(nwork * ZSplit<D>::value)), block(kWave * GatherWaves<D>::value);
     switch (plan) {
     case 1: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 1>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
     case 2: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 2>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
@@ -651,7 +745,7 @@ hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int
 template <typename R, int D>
 hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hipStream_t s)
 {
-    dim3 grid((unsigned)g.m.ntiles), block(kWave * GatherWaves<D>::value);
+    dim3 grid((unsigned)(g.m.ntiles * ZSplit<D>::value)), block(kWave * GatherWaves<D>::value);
     if (mode == FLA_NW) {
         if (count)
             launch_plan<R, D, FLA_NW, true>(g, plan, grid, block, s);

@@ -65,19 +65,31 @@ __device__ inline double cell_centre(const MeshDev& m, int a, int64_t i)
     return m.lo[a] + t;
 }
 
+// Minimum image d - L rint(d/L) of an offset d on a periodic axis of length
+// L, with the division only for |d| >= L.  For |d| < L the rounded quotient
+// lies in [0, 1] in magnitude and exceeds 1/2 exactly when |d| > L/2: the
+// binary64 numbers above 1/2 start at 1/2 + 2^-53, the midpoint 1/2 + 2^-54
+// rounds to the even 1/2, and L/2 < L (1/2 + 2^-54) < succ(L/2), so for a
+// binary64 d the test d/L > 1/2 + 2^-54 is d > L/2.  Hence rint(d/L) is 1
+// for d > L/2, -1 for d < -L/2 and 0 otherwise (rint(1/2) = 0), and the
+// result is d - L, d + L or d, each rounded once as in d - L*rint(d/L).
+__device__ inline double min_image(double d, double L)
+{
+#pragma clang fp contract(off)
+    const double ad = fabs(d);
+    if (ad <= 0.5 * L) return d;
+    if (ad < L) return d > 0.0 ? d - L : d + L;
+    double k = rint(d / L);
+    double s = L * k;
+    return d - s;
+}
+
 // offset from point xp to centre xc along axis a; minimum image on periodic axes
 __device__ inline double axis_offset(const MeshDev& m, int a, double xc, double xp)
 {
 #pragma clang fp contract(off)
     double d = xc - xp;
-    // |d| < L/2 implies rint(d/L) == 0 (a quotient rounded up to exactly 1/2
-    // still rounds to the even integer 0), so the division is only needed
-    // for offsets of half a box or more; the result is unchanged.
-    if (m.periodic[a] && !(fabs(d) < 0.5 * m.L[a])) {
-        double k = rint(d / m.L[a]);
-        double s = m.L[a] * k;
-        d = d - s;
-    }
+    if (m.periodic[a]) d = min_image(d, m.L[a]);
     return d;
 }
 
@@ -194,6 +206,9 @@ __device__ inline void wave_sync()
 template <typename R> struct V4;
 template <> struct V4<float> { using T = float4; };
 template <> struct V4<double> { using T = double4; };
+template <typename R> struct V2;
+template <> struct V2<float> { using T = float2; };
+template <> struct V2<double> { using T = double2; };
 
 // ---------------------------------------------------------------------------
 // host-side helpers shared by the translation units
