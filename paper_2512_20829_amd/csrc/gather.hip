@@ -41,6 +41,20 @@ constexpr int kCap = 2 * kWave;
 
 typedef float F4 __attribute__((ext_vector_type(4)));
 
+// A value that is the same on every lane, moved to scalar registers (the
+// vector unit computes binary64 and binary32 values into vector registers).
+__device__ inline double uniform_value(double v)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ inline float uniform_value(float v)
+{
+    return __int_as_float((int)__builtin_amdgcn_readfirstlane((unsigned)__float_as_int(v)));
+}
+
 template <typename R> __device__ inline R r_inf();
 template <> __device__ inline float r_inf<float>() { return __builtin_inff(); }
 template <> __device__ inline double r_inf<double>() { return __builtin_inf(); }
@@ -197,14 +211,17 @@ __device__ __forceinline__ int stage_record(const MeshDev& m, const double (*xcs
     return mk;
 }
 
-// Calls fn(s0, s1) for every run [s0, s1) of sorted records that the tile at
-// tile coordinates tc must consider, in a fixed order: for each neighbourhood
-// class k present in the mesh, the home tiles within k tiles of tc on every
-// axis (the last class: whole axes), row by row; along x the home tiles of a
-// row are contiguous in the sorted order (one run, or two across a periodic
-// wrap).
+// Calls fn(s0, s1) for every non-empty run [s0, s1) of sorted records that
+// the tile at tile coordinates tc must consider, in a fixed order: for each
+// neighbourhood class k present in the mesh, the home tiles within k tiles of
+// tc on every axis (the last class: whole axes), row by row; along x the home
+// tiles of a row are contiguous in the sorted order (one run, or two across a
+// periodic wrap).  The bucket bounds of up to 64 rows are fetched at once,
+// one row per lane, and read back with readlane, so the rows do not wait on
+// one scalar load each.
 template <int D, typename F>
-__device__ __forceinline__ void for_each_run(const MeshDev& m, const uint32_t* bstart, const int* tc, F&& fn)
+__device__ __forceinline__ void for_each_run(const MeshDev& m, const uint32_t* bstart, const int* tc,
+                                             const int lane, F&& fn)
 {
     const int ntl = m.ntiles;
     for (int k = 0; k < kClasses; ++k) {
@@ -233,32 +250,55 @@ __device__ __forceinline__ void for_each_run(const MeshDev& m, const uint32_t* b
                 cnt_t[a] = l1 - l0 + 1;
             }
         }
-        for (int jz = 0; jz < cnt_t[2]; ++jz) {
-            int hz = lo_t[2] + jz;
-            if (D == 3) hz = (int)posmod(hz, m.nt[2]);
-            for (int jy = 0; jy < cnt_t[1]; ++jy) {
-                int hy = (int)posmod(lo_t[1] + jy, m.nt[1]);
-                int x0 = lo_t[0], x1 = lo_t[0] + cnt_t[0] - 1;
-                int runs[2][2];
-                int nruns = 1;
-                if (x0 < 0) {
-                    runs[0][0] = x0 + m.nt[0];
-                    runs[0][1] = m.nt[0] - 1;
-                    runs[1][0] = 0;
-                    runs[1][1] = x1;
-                    nruns = 2;
-                } else if (x1 >= m.nt[0]) {
-                    runs[0][0] = x0;
-                    runs[0][1] = m.nt[0] - 1;
-                    runs[1][0] = 0;
-                    runs[1][1] = x1 - m.nt[0];
-                    nruns = 2;
-                } else {
-                    runs[0][0] = x0;
-                    runs[0][1] = x1;
-                }
+        // home-tile ranges along x, the same for every row
+        const int x0 = lo_t[0], x1 = lo_t[0] + cnt_t[0] - 1;
+        int runs[2][2];
+        int nruns = 1;
+        if (x0 < 0) {
+            runs[0][0] = x0 + m.nt[0];
+            runs[0][1] = m.nt[0] - 1;
+            runs[1][0] = 0;
+            runs[1][1] = x1;
+            nruns = 2;
+        } else if (x1 >= m.nt[0]) {
+            runs[0][0] = x0;
+            runs[0][1] = m.nt[0] - 1;
+            runs[1][0] = 0;
+            runs[1][1] = x1 - m.nt[0];
+            nruns = 2;
+        } else {
+            runs[0][0] = x0;
+            runs[0][1] = x1;
+            runs[1][0] = 0;
+            runs[1][1] = -1;
+        }
+        const int nrows = cnt_t[1] * cnt_t[2];
+        for (int g0 = 0; g0 < nrows; g0 += kWave) {
+            // lane j fetches the bounds of row g0 + j (rows ordered z, then y)
+            uint32_t b00 = 0, b01 = 0, b10 = 0, b11 = 0;
+            const int row = g0 + lane;
+            if (row < nrows) {
+                const int jz = row / cnt_t[1], jy = row - jz * cnt_t[1];
+                int hz = lo_t[2] + jz;
+                if (D == 3) hz = (int)posmod(hz, m.nt[2]);
+                const int hy = (int)posmod(lo_t[1] + jy, m.nt[1]);
                 const uint32_t rowb = kb + (uint32_t)m.nt[0] * ((uint32_t)hy + (uint32_t)m.nt[1] * (uint32_t)hz);
-                for (int q = 0; q < nruns; ++q) fn(bstart[rowb + runs[q][0]], bstart[rowb + runs[q][1] + 1]);
+                b00 = bstart[rowb + runs[0][0]];
+                b01 = bstart[rowb + runs[0][1] + 1];
+                if (nruns == 2) {
+                    b10 = bstart[rowb + runs[1][0]];
+                    b11 = bstart[rowb + runs[1][1] + 1];
+                }
+            }
+            // runs in order: row by row, the runs of a row in x order
+            const int nr = nrows - g0 < kWave ? nrows - g0 : kWave;
+            for (int j = 0; j < nr * nruns; ++j) {
+                const int jr = nruns == 2 ? j >> 1 : j;
+                const bool second = nruns == 2 && (j & 1);
+                const uint32_t a0 = __builtin_amdgcn_readlane(b00, jr), a1 = __builtin_amdgcn_readlane(b01, jr);
+                const uint32_t c0 = __builtin_amdgcn_readlane(b10, jr), c1 = __builtin_amdgcn_readlane(b11, jr);
+                const uint32_t s0 = second ? c0 : a0, s1 = second ? c1 : a1;
+                if (s0 < s1) fn(s0, s1);
             }
         }
     }
@@ -344,7 +384,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
     R c2;
     {
         R c = (R)g.cutoff;
-        c2 = c * c;
+        c2 = uniform_value(c * c);
     }
     // conservative tile box of cell centres for the candidate filter
     double bmid[3] = {0, 0, 0}, bhalf[3] = {0, 0, 0};
@@ -355,8 +395,8 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
         const int64_t c0 = (int64_t)tc[a] * TE + (one ? soff : 0);
         double f = cell_centre(m, a, c0);
         double l = cell_centre(m, a, c0 + (one ? SB : TE) - 1);
-        bmid[a] = 0.5 * (f + l);
-        bhalf[a] = 0.5 * (l - f);
+        bmid[a] = uniform_value(0.5 * (f + l));
+        bhalf[a] = uniform_value(0.5 * (l - f));
         faxis[a] = !(m.periodic[a] && 4.0 * bhalf[a] >= m.L[a]);
     }
 
@@ -427,6 +467,26 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
                 }
             }
             bool in = s <= c2;
+            ew = in ? ew : (R)0;
+            if constexpr (kMfma) {
+                part[b][0] = fma(ew, wv[0], part[b][0]);
+                acc[b] = __builtin_amdgcn_mfma_f32_4x4x1f32(wq, (float)ew, acc[b], 4, 0, 0);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NA; ++k) part[b][k] = fma(ew, wv[k], part[b][k]);
+            }
+            if (COUNT) npairs += (in && live) ? 1ull : 0ull;
+        };
+        // x split, sub-block b = by + 2 bz: the pair (by, 0), (by, 1) shares
+        // s_x + s_y and e_x e_y
+        auto pre = [&](int by, const R4* t, const R2& ts, R& sxy, R& exy) {
+            sxy = ts.x + (by ? t[0].z : t[0].x);
+            exy = ts.y * (by ? t[0].w : t[0].y);
+        };
+        auto fin = [&](int b, int bz, R sxy, R exy, const R4* t, const R* wv, float wq, bool live) {
+            const R s = sxy + (bz ? t[1].z : t[1].x);
+            R ew = exy * (bz ? t[1].w : t[1].y);
+            const bool in = s <= c2;
             ew = in ? ew : (R)0;
             if constexpr (kMfma) {
                 part[b][0] = fma(ew, wv[0], part[b][0]);
@@ -535,6 +595,31 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
                 }
                 const int mk = __builtin_amdgcn_readlane(mask4, e);
                 if (mk == 0) continue;
+                if constexpr (ZS == 2) {
+#pragma unroll
+                    for (int q = 0; q < NSB / 2; ++q) {
+                        const bool m0 = (mk >> q) & 1, m1 = (mk >> (q + NSB / 2)) & 1;
+                        if (!(m0 || m1)) continue;
+                        R sxy[4], exy[4];
+                        pre(q, tA, hA, sxy[0], exy[0]);
+                        pre(q, tB, hB, sxy[1], exy[1]);
+                        pre(q, tC, hC, sxy[2], exy[2]);
+                        pre(q, tD, hD, sxy[3], exy[3]);
+                        if (m0) {
+                            fin(q, 0, sxy[0], exy[0], tA, wA, qA, true);
+                            fin(q, 0, sxy[1], exy[1], tB, wB, qB, l1);
+                            fin(q, 0, sxy[2], exy[2], tC, wC, qC, l2);
+                            fin(q, 0, sxy[3], exy[3], tD, wD, qD, l3);
+                        }
+                        if (m1) {
+                            fin(q + NSB / 2, 1, sxy[0], exy[0], tA, wA, qA, true);
+                            fin(q + NSB / 2, 1, sxy[1], exy[1], tB, wB, qB, l1);
+                            fin(q + NSB / 2, 1, sxy[2], exy[2], tC, wC, qC, l2);
+                            fin(q + NSB / 2, 1, sxy[3], exy[3], tD, wD, qD, l3);
+                        }
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int q = 0; q < NSB / 2; ++q)
                     if (mk & (((1 << (NSB / 2)) | 1) << q)) {
@@ -585,7 +670,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
 
     int ncand = 0;
     uint32_t chunk = 0;          // chunks of 64 candidates are dealt round-robin to the waves
-    for_each_run<D>(m, g.bstart, tc, [&](const uint32_t s0, const uint32_t s1) {
+    for_each_run<D>(m, g.bstart, tc, lane, [&](const uint32_t s0, const uint32_t s1) {
         // this wave's chunks of the run: base0, base0 + 4*64, ...
         const uint32_t nch = (s1 - s0 + kWave - 1) / kWave;
         const uint32_t first = (uint32_t)((wave - (int)(chunk % kGatherWaves) + kGatherWaves) % kGatherWaves);
