@@ -253,7 +253,7 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
 
     auto layout = [&](Carver& c, uint32_t** keys, uint32_t** vals, uint32_t** keys2, uint32_t** vals2,
                       double4** rpos_u, double4** rpos, R** rw_u, R** rw, double** qd, uint32_t** bstart,
-                      uint32_t** hist, uint32_t** scan) {
+                      uint32_t** hist, uint32_t** scan, uint32_t** tcost, int** order) {
         *keys = c.take<uint32_t>(N);
         *vals = c.take<uint32_t>(N);
         *keys2 = c.take<uint32_t>(N);
@@ -266,19 +266,23 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
         *bstart = c.take<uint32_t>(nb + 1);
         *hist = c.take<uint32_t>(hist_w > 0 ? hist_w : 1);
         *scan = c.take<uint32_t>(scan_w);
+        *tcost = c.take<uint32_t>(m.ntiles > 0 ? m.ntiles : 1);
+        *order = c.take<int>(m.ntiles > 0 ? 2 * (size_t)m.ntiles : 1);
     };
-    uint32_t *keys, *vals, *keys2, *vals2, *bstart, *hist, *scan;
+    uint32_t *keys, *vals, *keys2, *vals2, *bstart, *hist, *scan, *tcost;
+    int* order;
     double4 *rpos_u, *rpos;
     R *rw_u, *rw;
     double* qd;
     {
         Carver probe(nullptr);
-        layout(probe, &keys, &vals, &keys2, &vals2, &rpos_u, &rpos, &rw_u, &rw, &qd, &bstart, &hist, &scan);
+        layout(probe, &keys, &vals, &keys2, &vals2, &rpos_u, &rpos, &rw_u, &rw, &qd, &bstart, &hist, &scan, &tcost,
+               &order);
         fla_status st = ensure_ws(ctx, probe.off + 256);
         if (st != FLA_OK) return st;
     }
     Carver c(ctx->ws);
-    layout(c, &keys, &vals, &keys2, &vals2, &rpos_u, &rpos, &rw_u, &rw, &qd, &bstart, &hist, &scan);
+    layout(c, &keys, &vals, &keys2, &vals2, &rpos_u, &rpos, &rw_u, &rw, &qd, &bstart, &hist, &scan, &tcost, &order);
 
     PhysDev ph{p->rho_d, p->mu, p->delta, p->h0, p->cutoff, p->scale};
     HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
@@ -317,6 +321,8 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
     for (int a = 0; a < D; ++a) g.out[1 + a] = out->S_mom[a];
     g.den = out->den;
     g.stats = ctx->stats;
+    g.tile_cost = tcost;
+    g.order = order;
     {
         StageTimer tm(ctx, 3, s);
         int plan = ctx->plan[D - 2][sizeof(R) == 8 ? 1 : 0];

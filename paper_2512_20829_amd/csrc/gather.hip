@@ -211,90 +211,110 @@ __device__ __forceinline__ int stage_record(const MeshDev& m, const double (*xcs
     return mk;
 }
 
+// Rows of home tiles that the tile at tile coordinates tc must consider for
+// neighbourhood class k: the home tiles within k tiles of tc on every axis
+// (the last class: whole axes), in rows along x, ordered z, then y; along x
+// the home tiles of a row are contiguous in the sorted order (one run, or two
+// across a periodic wrap, with tile ranges runs[q]).
+struct ClassRows {
+    uint32_t kb;        // first bucket of the class
+    int lo_t[3], cnt_t[3];
+    int runs[2][2];
+    int nruns, nrows;
+};
+
+template <int D>
+__device__ __forceinline__ void class_rows(const MeshDev& m, const int* tc, int k, ClassRows& cr)
+{
+    cr.kb = (uint32_t)k * (uint32_t)m.ntiles;
+    const int r = (k == kClasses - 1) ? (1 << 28) : k;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a >= D) {
+            cr.lo_t[a] = 0;
+            cr.cnt_t[a] = 1;
+            continue;
+        }
+        int nt = m.nt[a];
+        if (2 * (int64_t)r + 1 >= nt) {
+            cr.lo_t[a] = 0;
+            cr.cnt_t[a] = nt;
+        } else if (m.periodic[a]) {
+            cr.lo_t[a] = tc[a] - r;
+            cr.cnt_t[a] = 2 * r + 1;
+        } else {
+            int l0 = tc[a] - r < 0 ? 0 : tc[a] - r;
+            int l1 = tc[a] + r >= nt ? nt - 1 : tc[a] + r;
+            cr.lo_t[a] = l0;
+            cr.cnt_t[a] = l1 - l0 + 1;
+        }
+    }
+    const int x0 = cr.lo_t[0], x1 = cr.lo_t[0] + cr.cnt_t[0] - 1;
+    cr.nruns = 1;
+    if (x0 < 0) {
+        cr.runs[0][0] = x0 + m.nt[0];
+        cr.runs[0][1] = m.nt[0] - 1;
+        cr.runs[1][0] = 0;
+        cr.runs[1][1] = x1;
+        cr.nruns = 2;
+    } else if (x1 >= m.nt[0]) {
+        cr.runs[0][0] = x0;
+        cr.runs[0][1] = m.nt[0] - 1;
+        cr.runs[1][0] = 0;
+        cr.runs[1][1] = x1 - m.nt[0];
+        cr.nruns = 2;
+    } else {
+        cr.runs[0][0] = x0;
+        cr.runs[0][1] = x1;
+        cr.runs[1][0] = 0;
+        cr.runs[1][1] = -1;
+    }
+    cr.nrows = cr.cnt_t[1] * cr.cnt_t[2];
+}
+
+// First bucket of row `row` of a class.
+template <int D>
+__device__ __forceinline__ uint32_t row_bucket(const MeshDev& m, const ClassRows& cr, int row)
+{
+    const int jz = row / cr.cnt_t[1], jy = row - jz * cr.cnt_t[1];
+    int hz = cr.lo_t[2] + jz;
+    if (D == 3) hz = (int)posmod(hz, m.nt[2]);
+    const int hy = (int)posmod(cr.lo_t[1] + jy, m.nt[1]);
+    return cr.kb + (uint32_t)m.nt[0] * ((uint32_t)hy + (uint32_t)m.nt[1] * (uint32_t)hz);
+}
+
 // Calls fn(s0, s1) for every non-empty run [s0, s1) of sorted records that
-// the tile at tile coordinates tc must consider, in a fixed order: for each
-// neighbourhood class k present in the mesh, the home tiles within k tiles of
-// tc on every axis (the last class: whole axes), row by row; along x the home
-// tiles of a row are contiguous in the sorted order (one run, or two across a
-// periodic wrap).  The bucket bounds of up to 64 rows are fetched at once,
-// one row per lane, and read back with readlane, so the rows do not wait on
-// one scalar load each.
+// the tile at tile coordinates tc must consider, class by class, row by row
+// (class_rows).  The bucket bounds of up to 64 rows are fetched at once, one
+// row per lane, and read back with readlane, so the rows do not wait on one
+// scalar load each.
 template <int D, typename F>
 __device__ __forceinline__ void for_each_run(const MeshDev& m, const uint32_t* bstart, const int* tc,
                                              const int lane, F&& fn)
 {
-    const int ntl = m.ntiles;
     for (int k = 0; k < kClasses; ++k) {
-        const uint32_t kb = (uint32_t)k * (uint32_t)ntl;
-        if (bstart[kb] == bstart[kb + ntl]) continue;
-        const int r = (k == kClasses - 1) ? (1 << 28) : k;
-        int lo_t[3], cnt_t[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (a >= D) {
-                lo_t[a] = 0;
-                cnt_t[a] = 1;
-                continue;
-            }
-            int nt = m.nt[a];
-            if (2 * (int64_t)r + 1 >= nt) {
-                lo_t[a] = 0;
-                cnt_t[a] = nt;
-            } else if (m.periodic[a]) {
-                lo_t[a] = tc[a] - r;
-                cnt_t[a] = 2 * r + 1;
-            } else {
-                int l0 = tc[a] - r < 0 ? 0 : tc[a] - r;
-                int l1 = tc[a] + r >= nt ? nt - 1 : tc[a] + r;
-                lo_t[a] = l0;
-                cnt_t[a] = l1 - l0 + 1;
-            }
-        }
-        // home-tile ranges along x, the same for every row
-        const int x0 = lo_t[0], x1 = lo_t[0] + cnt_t[0] - 1;
-        int runs[2][2];
-        int nruns = 1;
-        if (x0 < 0) {
-            runs[0][0] = x0 + m.nt[0];
-            runs[0][1] = m.nt[0] - 1;
-            runs[1][0] = 0;
-            runs[1][1] = x1;
-            nruns = 2;
-        } else if (x1 >= m.nt[0]) {
-            runs[0][0] = x0;
-            runs[0][1] = m.nt[0] - 1;
-            runs[1][0] = 0;
-            runs[1][1] = x1 - m.nt[0];
-            nruns = 2;
-        } else {
-            runs[0][0] = x0;
-            runs[0][1] = x1;
-            runs[1][0] = 0;
-            runs[1][1] = -1;
-        }
-        const int nrows = cnt_t[1] * cnt_t[2];
-        for (int g0 = 0; g0 < nrows; g0 += kWave) {
-            // lane j fetches the bounds of row g0 + j (rows ordered z, then y)
+        const uint32_t kb = (uint32_t)k * (uint32_t)m.ntiles;
+        if (bstart[kb] == bstart[kb + m.ntiles]) continue;
+        ClassRows cr;
+        class_rows<D>(m, tc, k, cr);
+        for (int g0 = 0; g0 < cr.nrows; g0 += kWave) {
+            // lane j fetches the bounds of row g0 + j
             uint32_t b00 = 0, b01 = 0, b10 = 0, b11 = 0;
             const int row = g0 + lane;
-            if (row < nrows) {
-                const int jz = row / cnt_t[1], jy = row - jz * cnt_t[1];
-                int hz = lo_t[2] + jz;
-                if (D == 3) hz = (int)posmod(hz, m.nt[2]);
-                const int hy = (int)posmod(lo_t[1] + jy, m.nt[1]);
-                const uint32_t rowb = kb + (uint32_t)m.nt[0] * ((uint32_t)hy + (uint32_t)m.nt[1] * (uint32_t)hz);
-                b00 = bstart[rowb + runs[0][0]];
-                b01 = bstart[rowb + runs[0][1] + 1];
-                if (nruns == 2) {
-                    b10 = bstart[rowb + runs[1][0]];
-                    b11 = bstart[rowb + runs[1][1] + 1];
+            if (row < cr.nrows) {
+                const uint32_t rowb = row_bucket<D>(m, cr, row);
+                b00 = bstart[rowb + cr.runs[0][0]];
+                b01 = bstart[rowb + cr.runs[0][1] + 1];
+                if (cr.nruns == 2) {
+                    b10 = bstart[rowb + cr.runs[1][0]];
+                    b11 = bstart[rowb + cr.runs[1][1] + 1];
                 }
             }
             // runs in order: row by row, the runs of a row in x order
-            const int nr = nrows - g0 < kWave ? nrows - g0 : kWave;
-            for (int j = 0; j < nr * nruns; ++j) {
-                const int jr = nruns == 2 ? j >> 1 : j;
-                const bool second = nruns == 2 && (j & 1);
+            const int nr = cr.nrows - g0 < kWave ? cr.nrows - g0 : kWave;
+            for (int j = 0; j < nr * cr.nruns; ++j) {
+                const int jr = cr.nruns == 2 ? j >> 1 : j;
+                const bool second = cr.nruns == 2 && (j & 1);
                 const uint32_t a0 = __builtin_amdgcn_readlane(b00, jr), a1 = __builtin_amdgcn_readlane(b01, jr);
                 const uint32_t c0 = __builtin_amdgcn_readlane(b10, jr), c1 = __builtin_amdgcn_readlane(b11, jr);
                 const uint32_t s0 = second ? c0 : a0, s1 = second ? c1 : a1;
@@ -756,7 +776,75 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
 __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::value)) void k_gather(GatherArgs g)
 {
-    gather_tile<R, D, MODE, COUNT, PLAN>(g, xcd_remap(blockIdx.x, g.m.ntiles * ZSplit<D>::value));
+    int w = xcd_remap(blockIdx.x, g.m.ntiles * ZSplit<D>::value);
+    if (g.order) w = g.order[w];
+    gather_tile<R, D, MODE, COUNT, PLAN>(g, w);
+}
+
+// Estimated work of every tile: the number of candidate records its scan
+// visits (the bucket sizes over its class neighbourhoods).
+template <int D>
+__global__ void k_tile_cost(GatherArgs g)
+{
+    const MeshDev& m = g.m;
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= m.ntiles) return;
+    int tc[3];
+    tc[0] = tile % m.nt[0];
+    tc[1] = (tile / m.nt[0]) % m.nt[1];
+    tc[2] = (D == 3) ? tile / (m.nt[0] * m.nt[1]) : 0;
+    uint32_t c = 0;
+    for (int k = 0; k < kClasses; ++k) {
+        const uint32_t kb = (uint32_t)k * (uint32_t)m.ntiles;
+        if (g.bstart[kb] == g.bstart[kb + m.ntiles]) continue;
+        ClassRows cr;
+        class_rows<D>(m, tc, k, cr);
+        for (int row = 0; row < cr.nrows; ++row) {
+            const uint32_t rowb = row_bucket<D>(m, cr, row);
+            for (int q = 0; q < cr.nruns; ++q)
+                c += g.bstart[rowb + cr.runs[q][1] + 1] - g.bstart[rowb + cr.runs[q][0]];
+        }
+    }
+    g.tile_cost[tile] = c;
+}
+
+// Work order of the single-snapshot gather.  Workgroups are dealt
+// round-robin over the XCDs and xcd_remap gives each XCD a contiguous range
+// of slots; inside its range (one workgroup of this kernel per XCD) the work
+// units are placed in descending classes of their tile's cost (four classes
+// per power of two), so that the heaviest tiles start first and the light
+// ones fill the end.  The order inside a class is immaterial: a work unit's
+// results do not depend on the slot that computes it.
+constexpr int kOrderBins = 33 * 4;
+__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ cost, int nunits, int zs,
+                                                     int* __restrict__ order)
+{
+    __shared__ uint32_t cnt[kOrderBins];
+    const int x = blockIdx.x;
+    const int q = nunits / kXcds, rem = nunits % kXcds;
+    const int s0 = x * q + (x < rem ? x : rem), n = q + (x < rem ? 1 : 0);
+    auto bin = [](uint32_t c) {
+        const int b = 32 - __clz(c);   // 0 for c = 0, else 1 + floor(log2 c)
+        const int sub = b >= 3 ? (int)((c >> (b - 3)) & 3u) : 0;
+        return b * 4 + sub;
+    };
+    for (int i = threadIdx.x; i < kOrderBins; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&cnt[bin(cost[(s0 + i) / zs])], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = kOrderBins - 1; b >= 0; --b) {
+            const uint32_t t = cnt[b];
+            cnt[b] = acc;
+            acc += t;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t pos = atomicAdd(&cnt[bin(cost[(s0 + i) / zs])], 1u);
+        order[s0 + pos] = s0 + i;
+    }
 }
 
 // Work item of workgroup `bid` of a batch of `nwork` items.  Workgroups are
@@ -830,6 +918,12 @@ hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int
 template <typename R, int D>
 hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hipStream_t s)
 {
+    if (g.m.ntiles <= 0) return hipSuccess;
+    if (g.order) {
+        hipLaunchKernelGGL(k_tile_cost<D>, dim3((unsigned)((g.m.ntiles + 255) / 256)), dim3(256), 0, s, g);
+        hipLaunchKernelGGL(k_tile_order, dim3(kXcds), dim3(1024), 0, s, (const uint32_t*)g.tile_cost,
+                           g.m.ntiles * ZSplit<D>::value, ZSplit<D>::value, g.order);
+    }
     dim3 grid((unsigned)(g.m.ntiles * ZSplit<D>::value)), block(kWave * GatherWaves<D>::value);
     if (mode == FLA_NW) {
         if (count)

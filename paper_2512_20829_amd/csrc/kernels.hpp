@@ -18,6 +18,10 @@ struct GatherArgs {
     void* out[4];
     void* den;
     unsigned long long* stats;
+    // optional (both set or both null): workspace for the work order of the
+    // single-snapshot gather, ntiles cost words and 2 * ntiles slot entries
+    uint32_t* tile_cost;
+    int* order;
 };
 
 // One snapshot of a batched projection (device table entry).
