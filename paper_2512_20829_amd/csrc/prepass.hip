@@ -5,12 +5,12 @@
 
 namespace flp {
 
-__device__ inline void block_add_stats(unsigned long long* stats, int slot, unsigned long long v)
+// Adds the number of lanes of the wave with `flag` set to stats[slot]: one
+// ballot and one atomic per wave (integer: order-independent).
+__device__ inline void wave_count_flags(unsigned long long* stats, int slot, bool flag)
 {
-    // wave-level reduction, then one atomic per wave (integer: order-independent)
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    if ((threadIdx.x % kWave) == 0 && v) atomicAdd(&stats[slot], v);
+    const uint64_t b = __ballot(flag);
+    if ((threadIdx.x % kWave) == 0 && b) atomicAdd(&stats[slot], (unsigned long long)__popcll(b));
 }
 
 // Per-trajectory prepass of trajectory i of one snapshot, written at global
@@ -125,7 +125,10 @@ __device__ inline void prepass_one(const TrajDev& t, const MeshDev& m, const Phy
             key = key_base + (uint32_t)cls * (uint32_t)m.ntiles + (uint32_t)tl;
         }
         rpos[gi] = make_double4(x[0], x[1], x[2], inv_h);
-        R* w = rw + gi * kRecW;
+        // the weight record is built in registers and stored whole (16-byte stores)
+        R w[kRecW];
+#pragma unroll
+        for (int k = 0; k < kRecW; ++k) w[k] = (R)0;
         w[0] = (R)inv_h;
         if (deposit) {
             double sc = t.seed_volume * adet;
@@ -135,6 +138,11 @@ __device__ inline void prepass_one(const TrajDev& t, const MeshDev& m, const Phy
 #pragma unroll
             for (int k = 0; k < C; ++k) w[1 + k] = (R)(inv_h * (n * phi[k]));
         }
+        static_assert(kRecW * sizeof(R) % sizeof(uint4) == 0, "weight records are whole 16-byte words");
+        uint4* wd = reinterpret_cast<uint4*>(rw + gi * kRecW);
+        const uint4* ws = reinterpret_cast<const uint4*>(w);
+#pragma unroll
+        for (int k = 0; k < (int)(kRecW * sizeof(R) / sizeof(uint4)); ++k) wd[k] = ws[k];
     }
     keys[gi] = key;
     vals[gi] = (uint32_t)gi;
@@ -152,8 +160,8 @@ __global__ __launch_bounds__(256) void k_prepass(TrajDev t, MeshDev m, PhysDev p
     unsigned long long skipped = 0, nosup = 0;
     if (i < t.count)
         prepass_one<R, D>(t, m, ph, hfac, deposit, i, i, 0u, sentinel, keys, vals, rpos, rw, qd, skipped, nosup);
-    block_add_stats(stats, ST_SKIPPED, skipped);
-    block_add_stats(stats, ST_NOSUPPORT, nosup);
+    wave_count_flags(stats, ST_SKIPPED, skipped != 0);
+    wave_count_flags(stats, ST_NOSUPPORT, nosup != 0);
 }
 
 // One thread per trajectory of a batch of snapshots: trajectories of
@@ -179,8 +187,8 @@ __global__ __launch_bounds__(256) void k_prepass_batch(const BatchItem* items, i
         prepass_one<R, D>(it.t, it.g.m, it.ph, it.hfac, 0, gi - it.base, gi, it.key_base, sentinel, keys, vals, rpos,
                           rw, nullptr, skipped, nosup);
     }
-    block_add_stats(stats, ST_SKIPPED, skipped);
-    block_add_stats(stats, ST_NOSUPPORT, nosup);
+    wave_count_flags(stats, ST_SKIPPED, skipped != 0);
+    wave_count_flags(stats, ST_NOSUPPORT, nosup != 0);
 }
 
 // Largest non-empty neighbourhood class, read off the bucket bounds.
@@ -238,8 +246,12 @@ __global__ void k_permute(const uint32_t* order, int64_t n, const double4* rpos_
     uint32_t i = order[p];
     rpos[p] = rpos_u[i];
     if (copy_w) {
+        // whole records in 16-byte words
+        constexpr int NQ = (int)(kRecW * sizeof(R) / sizeof(uint4));
+        const uint4* src = reinterpret_cast<const uint4*>(rw_u + (int64_t)i * kRecW);
+        uint4* dst = reinterpret_cast<uint4*>(rw + p * kRecW);
 #pragma unroll
-        for (int k = 0; k < kRecW; ++k) rw[p * kRecW + k] = rw_u[(int64_t)i * kRecW + k];
+        for (int k = 0; k < NQ; ++k) dst[k] = src[k];
     }
 }
 
