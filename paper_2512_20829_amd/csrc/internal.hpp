@@ -154,9 +154,10 @@ __device__ inline void droplet_phi(double r, const double* v, const double* ug, 
     double rdot = ph.delta / (2.0 * r);
     double mdot = 4.0 * kPi * ph.rho_d * r * r * rdot;
     phi[0] = mdot;
+    const double m_tau = m / tau;   // one division for the D drag components
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        double F = m * (ug[a] - v[a]) / tau;
+        double F = m_tau * (ug[a] - v[a]);
         phi[1 + a] = F + mdot * v[a];
     }
 }
@@ -168,8 +169,14 @@ __device__ inline int64_t floordiv(int64_t a, int64_t b)
     if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
     return q;
 }
+// a mod b in [0, b) for b > 0.  Indices within one period of [0, b) (all
+// positions inside or next to the box) take no 64-bit division, which is a
+// long instruction sequence on this hardware.
 __device__ inline int64_t posmod(int64_t a, int64_t b)
 {
+    if (a >= 0 && a < b) return a;
+    if (a < 0 && a >= -b) return a + b;
+    if (a >= b && a - b < b) return a - b;
     int64_t r = a % b;
     return r < 0 ? r + b : r;
 }

@@ -72,11 +72,17 @@ __device__ inline void prepass_one(const TrajDev& t, const MeshDev& m, const Phy
         bool support = true;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
+            // home cell by division, exactly as the gather's home_index; the
+            // support bounds (they only choose the bucket class) by a
+            // multiply with 1/w, widened by 1e-9 plus 1e-15 of the quotient,
+            // far more than the few ulps by which the product can differ
             double g = floor((x[a] - m.lo[a]) / m.w[a]);
             g = fmin(fmax(g, -4.0e15), 4.0e15);
             int64_t hc = (int64_t)g;
-            double flo = (x[a] - rc - m.lo[a]) / m.w[a] - 0.5 - 1e-9;
-            double fhi = (x[a] + rc - m.lo[a]) / m.w[a] - 0.5 + 1e-9;
+            const double iw = 1.0 / m.w[a];
+            const double qlo = (x[a] - rc - m.lo[a]) * iw, qhi = (x[a] + rc - m.lo[a]) * iw;
+            double flo = qlo - 0.5 - (1e-9 + 1e-15 * fabs(qlo));
+            double fhi = qhi - 0.5 + (1e-9 + 1e-15 * fabs(qhi));
             flo = fmin(fmax(flo, -4.0e15), 4.0e15);
             fhi = fmin(fmax(fhi, -4.0e15), 4.0e15);
             int64_t ilo = (int64_t)ceil(flo), ihi = (int64_t)floor(fhi);
