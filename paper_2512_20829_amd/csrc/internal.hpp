@@ -141,25 +141,31 @@ __device__ inline void axis_factor(const MeshDev& m, int a, int64_t ci, double x
     e = gauss_factor(sr);
 }
 
-// Droplet source channels of one droplet (binary64):
+// Droplet source channels of one droplet (in T; binary64 for the projection):
 //   m = 4/3 pi rho r^3, tau = 2 rho r^2/(9 mu), F = m (ug - v)/tau,
 //   mdot = 4 pi rho r^2 * delta/(2 r), phi = [mdot, F + mdot v]   (eqs. 3-5, 9)
-template <int D>
-__device__ inline void droplet_phi(double r, const double* v, const double* ug, const PhysDev& ph,
-                                   double* phi)
+template <int D, typename T>
+__device__ inline void droplet_phi_t(T r, const T* v, const T* ug, const PhysDev& ph, T* phi)
 {
-    constexpr double kPi = 3.14159265358979323846;
-    double m = (4.0 / 3.0) * kPi * ph.rho_d * r * r * r;
-    double tau = 2.0 * ph.rho_d * r * r / (9.0 * ph.mu);
-    double rdot = ph.delta / (2.0 * r);
-    double mdot = 4.0 * kPi * ph.rho_d * r * r * rdot;
+    constexpr T kPi = (T)3.14159265358979323846;
+    const T rho = (T)ph.rho_d;
+    T m = ((T)4.0 / (T)3.0) * kPi * rho * r * r * r;
+    T tau = (T)2.0 * rho * r * r / ((T)9.0 * (T)ph.mu);
+    T rdot = (T)ph.delta / ((T)2.0 * r);
+    T mdot = (T)4.0 * kPi * rho * r * r * rdot;
     phi[0] = mdot;
-    const double m_tau = m / tau;   // one division for the D drag components
+    const T m_tau = m / tau;   // one division for the D drag components
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        double F = m_tau * (ug[a] - v[a]);
+        T F = m_tau * (ug[a] - v[a]);
         phi[1 + a] = F + mdot * v[a];
     }
+}
+
+template <int D>
+__device__ inline void droplet_phi(double r, const double* v, const double* ug, const PhysDev& ph, double* phi)
+{
+    droplet_phi_t<D, double>(r, v, ug, ph, phi);
 }
 
 // Floor division for possibly negative integers.

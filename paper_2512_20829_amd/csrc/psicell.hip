@@ -29,7 +29,7 @@
 namespace flp {
 
 constexpr int kPsiUnroll = 4;          // count and reduce
-constexpr int kPsiUnrollScatter = 1;   // scatter: the binary64 phi of several particles costs occupancy
+constexpr int kPsiUnrollScatter = 2;   // scatter
 constexpr uint32_t kPsiSkip = 0xFFFFFFFFu;
 
 // Cell indices of a particle from its position alone: false for a
@@ -41,7 +41,13 @@ __device__ inline bool psi_cell(const MeshDev& m, const double* x, int* idx)
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
         if (!isfinite(x[ax])) return false;
-        double g = floor((x[ax] - m.lo[ax]) / m.w[ax]);
+        // floor((x - lo)/w): a multiply by 1/w differs from the rounded
+        // quotient by a few ulps, which can change the floor only next to an
+        // integer; there the quotient is formed exactly
+        const double dx = x[ax] - m.lo[ax];
+        double q = dx * (1.0 / m.w[ax]);
+        if (fabs(q - rint(q)) < 1e-6 * (1.0 + fabs(q))) q = dx / m.w[ax];
+        double g = floor(q);
         if (!(fabs(g) < 9.0e15)) return false;
         int64_t k = (int64_t)g;
         if (m.periodic[ax]) {
@@ -157,22 +163,21 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
 #pragma unroll
         for (int u = 0; u < kPsiUnrollScatter; ++u) {
             if (code[u] < 0) continue;
-            double vd[3], ud[3], phi[4];
-            bool ok = isfinite((double)r[u]);
+            // the source terms in the precision of the records (binary32
+            // records: binary32 arithmetic, within a few ulps of the binary64
+            // terms rounded)
+            R phi[4];
+            bool ok = isfinite(r[u]);
 #pragma unroll
-            for (int ax = 0; ax < D; ++ax) {
-                vd[ax] = (double)v[u][ax];
-                ud[ax] = (double)ug[u][ax];
-                ok = ok && isfinite(vd[ax]) && isfinite(ud[ax]);
-            }
+            for (int ax = 0; ax < D; ++ax) ok = ok && isfinite(v[u][ax]) && isfinite(ug[u][ax]);
             PsiRec<R> rec;
             if (ok) {
-                droplet_phi<D>((double)r[u], vd, ud, a.ph, phi);
+                droplet_phi_t<D, R>(r[u], v[u], ug[u], a.ph, phi);
 #pragma unroll
                 for (int k = 0; k < C; ++k) ok = ok && isfinite(phi[k]);
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) rec.phi[k] = (ok && k < C) ? (R)phi[k] : (R)0;
+            for (int k = 0; k < 4; ++k) rec.phi[k] = (ok && k < C) ? phi[k] : (R)0;
             rec.loc = ok ? (uint32_t)(code[u] & (a.cpt - 1)) : kPsiSkip;
             bad += ok ? 0ull : 1ull;
             unsigned int slot = atomicAdd(&cursor[code[u] >> a.cptlog], 1u);
