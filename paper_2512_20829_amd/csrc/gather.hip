@@ -782,13 +782,15 @@ __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::va
 }
 
 // Estimated work of every tile: the number of candidate records its scan
-// visits (the bucket sizes over its class neighbourhoods).
+// visits (the bucket sizes over its class neighbourhoods).  One wave per
+// tile, a row per lane.
 template <int D>
-__global__ void k_tile_cost(GatherArgs g)
+__global__ __launch_bounds__(256) void k_tile_cost(GatherArgs g)
 {
     const MeshDev& m = g.m;
-    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tile >= m.ntiles) return;
+    const int tile = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+    const int lane = threadIdx.x % kWave;
+    if (tile >= m.ntiles) return;   // whole waves
     int tc[3];
     tc[0] = tile % m.nt[0];
     tc[1] = (tile / m.nt[0]) % m.nt[1];
@@ -799,13 +801,15 @@ __global__ void k_tile_cost(GatherArgs g)
         if (g.bstart[kb] == g.bstart[kb + m.ntiles]) continue;
         ClassRows cr;
         class_rows<D>(m, tc, k, cr);
-        for (int row = 0; row < cr.nrows; ++row) {
+        for (int row = lane; row < cr.nrows; row += kWave) {
             const uint32_t rowb = row_bucket<D>(m, cr, row);
             for (int q = 0; q < cr.nruns; ++q)
                 c += g.bstart[rowb + cr.runs[q][1] + 1] - g.bstart[rowb + cr.runs[q][0]];
         }
     }
-    g.tile_cost[tile] = c;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+    if (lane == 0) g.tile_cost[tile] = c;
 }
 
 // Work order of the single-snapshot gather.  Workgroups are dealt
@@ -920,7 +924,7 @@ hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hi
 {
     if (g.m.ntiles <= 0) return hipSuccess;
     if (g.order) {
-        hipLaunchKernelGGL(k_tile_cost<D>, dim3((unsigned)((g.m.ntiles + 255) / 256)), dim3(256), 0, s, g);
+        hipLaunchKernelGGL(k_tile_cost<D>, dim3((unsigned)((g.m.ntiles + 3) / 4)), dim3(256), 0, s, g);
         hipLaunchKernelGGL(k_tile_order, dim3(kXcds), dim3(1024), 0, s, (const uint32_t*)g.tile_cost,
                            g.m.ntiles * ZSplit<D>::value, ZSplit<D>::value, g.order);
     }
