@@ -78,22 +78,22 @@ template <int D> struct GatherWaves { static constexpr int value = D == 3 ? 4 : 
 // staging space, so that more workgroups share a compute unit.  (Along x: the
 // inclusion sum is ((s_x + s_y) + s_z), so sub-blocks paired along z still
 // share their partial sum s_x + s_y.)
-template <int D> struct ZSplit { static constexpr int value = D == 3 ? 2 : 1; };
+template <int D> struct TileParts { static constexpr int value = D == 3 ? 2 : 1; };
 
 // Waves per SIMD the register allocation is held to.
 template <typename R, int D> struct GatherOcc {
-    static constexpr int value = sizeof(R) == 4 ? (ZSplit<D>::value == 2 ? 3 : 2) : 1;
+    static constexpr int value = sizeof(R) == 4 ? (TileParts<D>::value == 2 ? 3 : 2) : 1;
 };
 
 template <typename R, int D>
 struct GatherLds {
     using R4 = typename V4<R>::T;
     using R2 = typename V2<R>::T;
-    static constexpr int SB = Geo<D>::SB, NA = D + 2, ZS = ZSplit<D>::value;
-    static constexpr int NT = ZS == 2 ? D - 1 : D;   // axes staged for both halves (split: y, z)
+    static constexpr int SB = Geo<D>::SB, NA = D + 2, TP = TileParts<D>::value;
+    static constexpr int NT = TP == 2 ? D - 1 : D;   // axes staged for both halves (split: y, z)
     uint32_t cand[kCap];               // compacted candidate record indices
     R4 tab[kWave][NT][SB];             // {s, e} at in-block position l and l + SB
-    R2 tabs[kWave][ZS == 2 ? SB : 1];  // split axis x: {s, e} of the owned half
+    R2 tabs[kWave][TP == 2 ? SB : 1];  // split axis x: {s, e} of the owned half
     R wts[kWave][NA];                  // {1/h, q/h ...} of each staged record
     int mask[kWave];                   // sub-blocks holding at least one included pair
 };
@@ -113,7 +113,7 @@ __device__ __forceinline__ int stage_record(const MeshDev& m, const double (*xcs
                                             typename V4<R>::T (*tab)[Geo<D>::SB], typename V2<R>::T* tabs)
 {
     using G = Geo<D>;
-    constexpr int TE = G::TE, SB = G::SB, NP = 2 * SB, ZS = ZSplit<D>::value, NSB = G::NSB / ZS;
+    constexpr int TE = G::TE, SB = G::SB, NP = 2 * SB, TP = TileParts<D>::value, NSB = G::NSB / TP;
     using R4 = typename V4<R>::T;
     using R2 = typename V2<R>::T;
     double x[3] = {P.x, P.y, P.z};
@@ -124,7 +124,7 @@ __device__ __forceinline__ int stage_record(const MeshDev& m, const double (*xcs
     // the minimum image and the delta records take one branch per axis.
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const bool one = ZS == 2 && a == 0;   // one half of this axis, at soff
+        const bool one = TP == 2 && a == 0;   // one half of this axis, at soff
         const int np = one ? SB : NP;
         double d[NP];
 #pragma unroll
@@ -186,7 +186,7 @@ __device__ __forceinline__ int stage_record(const MeshDev& m, const double (*xcs
                 t4.y = ev[l];
                 t4.z = sv[l + SB];
                 t4.w = ev[l + SB];
-                tab[ZS == 2 ? a - 1 : a][l] = t4;
+                tab[TP == 2 ? a - 1 : a][l] = t4;
                 mhi = fmin(mhi, sv[l + SB]);
             }
             mlo = fmin(mlo, sv[l]);
@@ -201,9 +201,9 @@ __device__ __forceinline__ int stage_record(const MeshDev& m, const double (*xcs
 #pragma unroll
     for (int b = 0; b < NSB; ++b) {
         // sub-block bits: (x, y, z), or (y, z) with x split
-        const int bx = ZS == 2 ? 0 : b & 1;
-        const int by = ZS == 2 ? b & 1 : (b >> 1) & 1;
-        const int bz = ZS == 2 ? (b >> 1) & 1 : (b >> 2) & 1;
+        const int bx = TP == 2 ? 0 : b & 1;
+        const int by = TP == 2 ? b & 1 : (b >> 1) & 1;
+        const int bz = TP == 2 ? (b >> 1) & 1 : (b >> 2) & 1;
         R smin = mn[0][bx] + mn[1][by];
         if (D == 3) smin = smin + mn[2][bz];
         mk |= (smin <= c2) ? (1 << b) : 0;
@@ -354,15 +354,15 @@ __device__ __forceinline__ bool candidate_ok(const MeshDev& m, const double4 P, 
     return acc <= filt2;
 }
 
-// The work of one workgroup: every cell of its part `work % ZS` of tile
-// `work / ZS` of the mesh of g.
+// The work of one workgroup: every cell of its part `work % TP` of tile
+// `work / TP` of the mesh of g.
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
 __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
 {
     constexpr int kGatherWaves = GatherWaves<D>::value;
     using G = Geo<D>;
-    constexpr int ZS = ZSplit<D>::value;
-    constexpr int TE = G::TE, SB = G::SB, NSB = G::NSB / ZS, C = D + 1, NA = C + 1;
+    constexpr int TP = TileParts<D>::value;
+    constexpr int TE = G::TE, SB = G::SB, NSB = G::NSB / TP, C = D + 1, NA = C + 1;
     constexpr int NT = GatherLds<R, D>::NT;
     constexpr bool kComp = sizeof(R) == 4;
     using R4 = typename V4<R>::T;
@@ -377,14 +377,14 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
     const int lane = threadIdx.x % kWave;
     const int wave = threadIdx.x / kWave;
     L& my = lds[wave];
-    const int tile = work / ZS;
-    const int soff = (ZS == 2) ? (work % ZS) * SB : 0;   // first owned cell of the tile along x
+    const int tile = work / TP;
+    const int soff = (TP == 2) ? (work % TP) * SB : 0;   // first owned cell of the tile along x
     int tc[3];
     tc[0] = tile % m.nt[0];
     tc[1] = (tile / m.nt[0]) % m.nt[1];
     tc[2] = (D == 3) ? tile / (m.nt[0] * m.nt[1]) : 0;
     // a part lying wholly beyond the mesh has no cells (uniform over the workgroup)
-    if (ZS == 2 && (int64_t)tc[0] * TE + soff >= m.n[0]) return;
+    if (TP == 2 && (int64_t)tc[0] * TE + soff >= m.n[0]) return;
 
     if (threadIdx.x < D * TE) {
         int a = threadIdx.x / TE, p = threadIdx.x % TE;
@@ -411,7 +411,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
     bool faxis[3] = {false, false, false};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const bool one = ZS == 2 && a == 0;
+        const bool one = TP == 2 && a == 0;
         const int64_t c0 = (int64_t)tc[a] * TE + (one ? soff : 0);
         double f = cell_centre(m, a, c0);
         double l = cell_centre(m, a, c0 + (one ? SB : TE) - 1);
@@ -470,7 +470,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
         // moved off the vector unit.
         auto sub = [&](int b, const R4* t, const R2& ts, const R* wv, float wq, bool live = true) {
             R s, ew;
-            if constexpr (ZS == 2) {
+            if constexpr (TP == 2) {
                 // x split: ts holds the owned half of x, t the y and z tables
                 const int by = b & 1, bz = (b >> 1) & 1;
                 s = ts.x + (by ? t[0].z : t[0].x);
@@ -565,8 +565,8 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
         // factors of staged record e at the lane's cells
         auto load_t = [&](int e, R4* t, R2& ts) {
 #pragma unroll
-            for (int a = 0; a < NT; ++a) t[a] = my.tab[e][a][lc[ZS == 2 ? a + 1 : a]];
-            if (ZS == 2) ts = my.tabs[e][lc[0]];
+            for (int a = 0; a < NT; ++a) t[a] = my.tab[e][a][lc[TP == 2 ? a + 1 : a]];
+            if (TP == 2) ts = my.tabs[e][lc[0]];
         };
         R4 tA[NT], tB[NT];
         R2 hA, hB;
@@ -615,7 +615,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
                 }
                 const int mk = __builtin_amdgcn_readlane(mask4, e);
                 if (mk == 0) continue;
-                if constexpr (ZS == 2) {
+                if constexpr (TP == 2) {
 #pragma unroll
                     for (int q = 0; q < NSB / 2; ++q) {
                         const bool m0 = (mk >> q) & 1, m1 = (mk >> (q + NSB / 2)) & 1;
@@ -736,7 +736,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             int half;
-            if (ZS == 2)
+            if (TP == 2)
                 half = a == 0 ? soff : ((b >> (a > 0 ? a - 1 : 0)) & 1) * SB;
             else
                 half = ((b >> a) & 1) * SB;
@@ -776,7 +776,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
 __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::value)) void k_gather(GatherArgs g)
 {
-    int w = xcd_remap(blockIdx.x, g.m.ntiles * ZSplit<D>::value);
+    int w = xcd_remap(blockIdx.x, g.m.ntiles * TileParts<D>::value);
     if (g.order) w = g.order[w];
     gather_tile<R, D, MODE, COUNT, PLAN>(g, w);
 }
@@ -870,9 +870,9 @@ template <typename R, int D, int MODE, bool COUNT, int PLAN>
 __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::value)) void k_gather_batch(
     const BatchItem* __restrict__ items, int nsnap, int nwork, int chunk)
 {
-    constexpr int ZS = ZSplit<D>::value;
-    const int u = batch_work_item(blockIdx.x, nwork * ZS, chunk);
-    const int j = u / ZS;         // tile-level work item
+    constexpr int TP = TileParts<D>::value;
+    const int u = batch_work_item(blockIdx.x, nwork * TP, chunk);
+    const int j = u / TP;         // tile-level work item
     int lo = 0, hi = nsnap - 1;   // last snapshot whose first work item is <= j
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -881,7 +881,7 @@ __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::va
         else
             hi = mid - 1;
     }
-    gather_tile<R, D, MODE, COUNT, PLAN>(items[lo].g, (j - items[lo].tile_base) * ZS + u % ZS);
+    gather_tile<R, D, MODE, COUNT, PLAN>(items[lo].g, (j - items[lo].tile_base) * TP + u % TP);
 }
 
 template <typename R, int D, int MODE, bool COUNT>
@@ -898,7 +898,7 @@ static void launch_plan(const GatherArgs& g, int plan, dim3 grid, dim3 block, hi
 template <typename R, int D, bool COUNT>
 static void launch_batch_plan(const BatchItem* items, int nsnap, int nwork, int chunk, int plan, hipStream_t s)
 {
-    dim3 grid((unsigned)(nwork * ZSplit<D>::value)), block(kWave * GatherWaves<D>::value);
+    dim3 grid((unsigned)(nwork * TileParts<D>::value)), block(kWave * GatherWaves<D>::value);
     switch (plan) {
     case 1: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 1>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
     case 2: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 2>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
@@ -926,9 +926,9 @@ hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hi
     if (g.order) {
         hipLaunchKernelGGL(k_tile_cost<D>, dim3((unsigned)((g.m.ntiles + 3) / 4)), dim3(256), 0, s, g);
         hipLaunchKernelGGL(k_tile_order, dim3(kXcds), dim3(1024), 0, s, (const uint32_t*)g.tile_cost,
-                           g.m.ntiles * ZSplit<D>::value, ZSplit<D>::value, g.order);
+                           g.m.ntiles * TileParts<D>::value, TileParts<D>::value, g.order);
     }
-    dim3 grid((unsigned)(g.m.ntiles * ZSplit<D>::value)), block(kWave * GatherWaves<D>::value);
+    dim3 grid((unsigned)(g.m.ntiles * TileParts<D>::value)), block(kWave * GatherWaves<D>::value);
     if (mode == FLA_NW) {
         if (count)
             launch_plan<R, D, FLA_NW, true>(g, plan, grid, block, s);
