@@ -29,7 +29,7 @@
 namespace flp {
 
 constexpr int kPsiUnroll = 4;          // count and reduce
-constexpr int kPsiUnrollScatter = 2;   // scatter
+constexpr int kPsiUnrollScatter = 4;   // scatter
 constexpr uint32_t kPsiSkip = 0xFFFFFFFFu;
 
 // Cell indices of a particle from its position alone: false for a
