@@ -279,17 +279,16 @@ __global__ void k_permute(const uint32_t* order, int64_t n, const double4* rpos_
     }
 }
 
-// Deposition normaliser Z_i = sum over cells within reach of K(x_c, x_i),
-// one wave per sorted trajectory.  Per-axis factors of the cells in the
-// trajectory's support box go to LDS (same binary64 offsets and the same
-// inclusion test as the gather), lanes sweep the box, and a fixed butterfly
-// reduces the wave.  Then the weight record becomes {1/h, Q/(h Z)}; with
-// Z = 0 it becomes a delta record {0, Q} flagged by 1/h < 0.
 constexpr int kZTab = 128;
 
-// Normaliser Z_i = sum over the cells in reach of the kernel factors, one
-// wave per valid trajectory (sorted order), written into its weight record
-// as q/Z (the 1/h factors cancel).  The support box is swept in blocks of
+// Deposition normaliser Z_i = sum over the cells in reach of the kernel
+// factors, one wave per valid trajectory (sorted order; the waves of a
+// workgroup take trajectories in turn), written into its weight record as
+// {1/h, Q/(h Z)} (the 1/h factors cancel); with Z = 0 the record becomes a
+// delta record {0, Q} flagged by 1/h < 0.  Per-axis factors of the cells in
+// the trajectory's support box go to LDS (same binary64 offsets and the same
+// inclusion test as the gather), lanes sweep the rows, and a fixed butterfly
+// reduces the wave.  The support box is swept in blocks of
 // at most kZTab cells per axis.  Within a block, a cell (jx, jy, jz) is
 // included iff (S0[jx] + S1[jy]) + S2[jz] <= c^2, evaluated in the working
 // precision exactly as the gather does.  Floating-point addition is monotone,
