@@ -219,10 +219,16 @@ typedef struct {
 fla_status fla_profile_enable(fla_ctx* ctx, int on);
 fla_status fla_profile_read(fla_ctx* ctx, fla_profile* out);
 
-/* Gather plan: the granularity at which the gather skips parts of a tile
- * that a trajectory cannot reach (0: each sub-block, 1: pairs of sub-blocks
- * along the last axis, 2: half tiles, 3: no skips).  Every plan produces the
- * same values (up to the sign of zero); they differ only in speed.  Plans are
+/* Gather plan: the granularity at which the gather skips the sub-blocks
+ * (blocks of 4^3 or 8^2 cells) that a trajectory cannot reach.  In 3-D a
+ * workgroup owns half of a tile along x (4 sub-blocks); in 2-D a whole tile
+ * (4 sub-blocks).
+ *   0: each sub-block;
+ *   1: pairs of sub-blocks along z (3-D, the default; the binary32 loop,
+ *      which takes four trajectories per step, adds a test per sub-block);
+ *   2, 3: only the workgroup's whole part.
+ * In 2-D, plans 1-3 skip only the whole tile.  Every plan produces the same
+ * values (up to the sign of zero); they differ only in speed.  Plans are
  * kept per (dim, prec) in the context; -1 restores the library default.
  * Errors: INVALID_ARG for out-of-range arguments. */
 #define FLA_GATHER_PLANS 4

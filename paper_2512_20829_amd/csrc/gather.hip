@@ -517,11 +517,13 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
             }
             if (COUNT) npairs += (in && live) ? 1ull : 0ull;
         };
-        // PLAN sets the granularity of the wave-uniform skips: 0 one branch per
-        // sub-block, 1 per pair of sub-blocks along the last axis, 2 per half
-        // tile, 3 none (every sub-block evaluated, masked by the pair test).
-        // All plans add the same products; a skipped sub-block only saves
-        // additions of zero.
+        // PLAN sets the granularity of the wave-uniform skips of a record that
+        // reaches the workgroup's part: 0 one branch per sub-block, 1 per
+        // pair of sub-blocks along z (3-D), 2 per half tile (whole tiles
+        // have 8 sub-blocks; with the x split the part has 4, so 2 and 3
+        // coincide), 3 none (every sub-block evaluated, masked by the pair
+        // test); in 2-D, 1 and 2 evaluate the whole tile.  All plans add the
+        // same products; a skipped sub-block only saves additions of zero.
         auto accumulate = [&](int e, const R4* t, const R2& ts, const R* wv, float wq) {
             const int mk = __builtin_amdgcn_readlane(maskv, e);
             if (mk == 0) return;
