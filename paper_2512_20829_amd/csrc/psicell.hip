@@ -21,8 +21,10 @@
 //           record with cell kPsiSkip and is counted as skipped;
 //   reduce  one workgroup per tile: quantise and add in LDS (integer atomics),
 //           then scale by -w/V_c and write the tile's cells.
-// The count and reduce passes give each thread kPsiUnroll particles per step
-// and issue all their loads before any use, to keep enough reads in flight.
+// Every pass gives each thread several particles per step (kPsiUnroll,
+// kPsiUnrollScatter) and issues all their loads before any use, to keep
+// enough reads in flight; the scatter forms the binary32 source terms of
+// binary32 records in binary32.
 #include "internal.hpp"
 #include "kernels.hpp"
 
