@@ -560,14 +560,21 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
     for (int ax = 0; ax < 3; ++ax) a.ptlog[ax] = __builtin_ctz((unsigned)a.pt[ax]);
     a.cptlog = a.ptlog[0] + a.ptlog[1] + a.ptlog[2];
     a.nblocks = kPsiBlocks;
+    a.pnbins = (a.pntiles + kPsiTilesPerBin - 1) / kPsiTilesPerBin;
+    // about 2048 workgroups in the tile pass
+    a.nsplit = a.pnbins >= 2048 ? 1 : 2048 / a.pnbins;
     const int64_t N = t.count;
     const int64_t hw = (int64_t)a.pntiles * a.nblocks + 1;
-    const int64_t sw = scan_tmp_words(hw);
+    const int64_t hb = (int64_t)a.pnbins * a.nblocks + 1;
+    const int64_t sw = scan_tmp_words(hw > hb ? hw : hb);
     auto layout = [&](Carver& c) {
         a.maxbits = c.take<unsigned long long>(4);
         a.qscale = c.take<double>(4);
         a.codes = c.take<int>(N > 0 ? N : 1);
         a.blockhist = c.take<unsigned int>(hw);
+        a.binhist = c.take<unsigned int>(hb);
+        a.tcursor = c.take<unsigned int>(a.pntiles);
+        a.binned = c.take<PsiRec<R>>(N > 0 ? N : 1);
         a.bucket = c.take<PsiRec<R>>(N > 0 ? N : 1);
         a.blockmax = c.take<unsigned long long>((size_t)a.nblocks * 4);
         a.scan_tmp = c.take<uint32_t>(sw);

@@ -88,7 +88,12 @@ struct PsiArgs {
     int nblocks;                 // blocks of the count / scatter passes
     int* codes;                  // per particle: tile * cpt + cell in tile, or -1
     unsigned int* blockhist;     // pntiles * nblocks + 1, scanned in place
-    void* bucket;                // bucketed records: R phi[4] then uint32 cell-in-tile
+    int pnbins;                  // bins of kPsiTilesPerBin consecutive tiles
+    int nsplit;                  // workgroups per bin in the tile pass
+    unsigned int* binhist;       // pnbins * nblocks + 1, scanned in place
+    unsigned int* tcursor;       // pntiles: next free slot of each tile bucket
+    void* binned;                // records grouped by bin (loc = code, top bit = skip)
+    void* bucket;                // records grouped by tile (loc = cell in tile or kPsiSkip)
     unsigned long long* blockmax; // nblocks x C bit patterns of per-block max |phi_k|
     uint32_t* scan_tmp;
     int64_t scan_words;
@@ -100,7 +105,10 @@ template <typename R> struct PsiRec {
     uint32_t loc;
 };
 
-constexpr int kPsiMaxTiles = 16384;   // LDS histogram of the count/scatter passes <= 64 KiB
+constexpr int kPsiMaxTiles = 16384;   // LDS histogram of the count pass <= 64 KiB
+constexpr int kPsiTilesPerBinLog = 6;
+constexpr int kPsiTilesPerBin = 1 << kPsiTilesPerBinLog;    // tiles per bin of the first partition
+constexpr int kPsiMaxBins = kPsiMaxTiles / kPsiTilesPerBin; // one bin per thread in the bin scans
 constexpr int kPsiMaxCellsPerTile = 1024;  // LDS sums of the reduce pass <= 36 KiB
 constexpr int kPsiBlocks = 1024;
 

@@ -9,22 +9,28 @@
 //
 // Particles arrive in arbitrary spatial order, so the sums are not formed by
 // global atomics (one contended 64-bit atomic per particle and channel) but
-// in three streaming passes over coarse tiles of cells:
+// in streaming passes over coarse tiles of cells, grouped into bins of
+// kPsiTilesPerBin consecutive tiles:
 //   count   per particle, from its position only: the (tile, cell in tile)
 //           code (-1 outside a closed box or for a non-finite position);
-//           per-block tile histograms in LDS, written tile-major for an
-//           exclusive scan that yields every (tile, block) output range;
+//           per-block tile and bin histograms in LDS, written tile-major
+//           and bin-major for exclusive scans that give every tile's bucket
+//           and every (bin, block) output range;
 //   scatter per particle with a code: phi, the per-channel max |phi|, and
-//           the record (cell in tile, phi) appended to its tile bucket (slot
-//           from an LDS cursor; the order inside a bucket does not matter);
-//           a particle whose velocities, radius or phi are not finite gets a
-//           record with cell kPsiSkip and is counted as skipped;
+//           the record (code, phi), sorted by bin in LDS round by round and
+//           written out as one contiguous run per bin; a particle whose
+//           velocities, radius or phi are not finite gets a record marked
+//           skip and is counted as skipped;
+//   tiles   per bin: its records sorted by tile in LDS round by round and
+//           written to the tile buckets in contiguous runs;
 //   reduce  one workgroup per tile: quantise and add in LDS (integer atomics),
 //           then scale by -w/V_c and write the tile's cells.
-// Every pass gives each thread several particles per step (kPsiUnroll,
-// kPsiUnrollScatter) and issues all their loads before any use, to keep
-// enough reads in flight; the scatter forms the binary32 source terms of
-// binary32 records in binary32.
+// Storing each record straight into one of thousands of tile buckets would
+// leave every 20-byte store on its own and the cache lines partly written;
+// the two sorted partitions write whole runs instead.  Every pass gives each
+// thread several particles per step (kPsiUnroll, kPsiUnrollScatter) and
+// issues all their loads before any use, to keep enough reads in flight; the
+// scatter forms the binary32 source terms of binary32 records in binary32.
 #include "internal.hpp"
 #include "kernels.hpp"
 
@@ -32,7 +38,10 @@ namespace flp {
 
 constexpr int kPsiUnroll = 4;          // count and reduce
 constexpr int kPsiUnrollScatter = 4;   // scatter
-constexpr uint32_t kPsiSkip = 0xFFFFFFFFu;
+constexpr uint32_t kPsiSkip = 0xFFFFFFFFu;     // cell of a skipped record in a tile bucket
+constexpr uint32_t kPsiSkipBit = 0x80000000u;  // skip mark of a binned record (codes < 2^24)
+static_assert(kPsiTilesPerBin == kWave, "the tile pass scans one tile per lane of one wave");
+static_assert(kPsiMaxBins <= 256, "the bin scans take one bin per thread of a 256-thread block");
 
 // Cell indices of a particle from its position alone: false for a
 // non-finite position or one outside a closed box (x == hi goes to the last
@@ -120,40 +129,104 @@ __global__ __launch_bounds__(256) void k_psi_count(PsiArgs a)
     __syncthreads();
     for (int t = threadIdx.x; t < ntl; t += blockDim.x) a.blockhist[(int64_t)t * gridDim.x + blockIdx.x] = hist[t];
     if (blockIdx.x == 0 && threadIdx.x == 0) a.blockhist[(int64_t)ntl * gridDim.x] = 0;
+    // the same counts summed over the tiles of each bin (the tiles are read
+    // in a rotated order so that the lanes hit different LDS banks)
+    for (int c = threadIdx.x; c < a.pnbins; c += blockDim.x) {
+        const int t0 = c << kPsiTilesPerBinLog;
+        unsigned int sum = 0;
+        for (int j = 0; j < kPsiTilesPerBin; ++j) {
+            const int t = t0 + ((j + c) & (kPsiTilesPerBin - 1));
+            if (t < ntl) sum += hist[t];
+        }
+        a.binhist[(int64_t)c * gridDim.x + blockIdx.x] = sum;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.binhist[(int64_t)a.pnbins * gridDim.x] = 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) outside += __shfl_xor(outside, o, kWave);
     if ((threadIdx.x % kWave) == 0 && outside) atomicAdd(&a.stats[ST_OUTSIDE], outside);
 }
 
+// Exclusive prefix sum of one value per thread of a 256-thread block, and
+// the block total.  ws holds 4 words of LDS; the call contains a barrier.
+__device__ inline unsigned int block_exclusive_sum(unsigned int v, unsigned int* ws, unsigned int& total)
+{
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    unsigned int inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const unsigned int t = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += t;
+    }
+    if (lane == kWave - 1) ws[w] = inc;
+    __syncthreads();
+    unsigned int pre = 0;
+    total = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const unsigned int t = ws[j];
+        pre += j < w ? t : 0u;
+        total += t;
+    }
+    return pre + inc - v;
+}
+
+// Exclusive prefix sum over the 64 lanes of one wave, and the wave total.
+__device__ inline unsigned int wave_exclusive_sum(unsigned int v, unsigned int& total)
+{
+    const int lane = threadIdx.x % kWave;
+    unsigned int inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const unsigned int t = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += t;
+    }
+    total = __shfl(inc, kWave - 1, kWave);
+    return inc - v;
+}
+
+// First partition: each block takes its contiguous range of particles in
+// rounds of kPsiRound, forms their records, orders a round's records by bin
+// in LDS (counting sort) and writes them out bin by bin, so a round gives
+// one contiguous run of records per bin and the stores are coalesced.  The
+// slots come from the scanned per-block bin counts of the count pass.
 template <typename R, int D>
 __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
 {
     constexpr int C = D + 1;
-    extern __shared__ unsigned int cursor[];
-    const int ntl = a.pntiles;
-    for (int t = threadIdx.x; t < ntl; t += blockDim.x) cursor[t] = a.blockhist[(int64_t)t * gridDim.x + blockIdx.x];
+    constexpr int U = kPsiUnrollScatter;
+    constexpr int RB = 256 * U;
+    __shared__ PsiRec<R> stage[RB];
+    __shared__ uint32_t sslot[RB];
+    __shared__ unsigned int cnt[kPsiMaxBins], off[kPsiMaxBins], gbase[kPsiMaxBins], cursor[kPsiMaxBins];
+    __shared__ unsigned int ws[4];
+    const int tid = threadIdx.x;
+    const int nbin = a.pnbins;
+    const int bsh = a.cptlog + kPsiTilesPerBinLog;
+    if (tid < nbin) {
+        cursor[tid] = a.binhist[(int64_t)tid * gridDim.x + blockIdx.x];
+        cnt[tid] = 0;
+    }
     __syncthreads();
     const int64_t N = a.p.count;
     const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
     const int64_t beg = (int64_t)blockIdx.x * chunk;
     const int64_t end = beg + chunk < N ? beg + chunk : N;
-    const int64_t stepw = (int64_t)blockDim.x * kPsiUnrollScatter;
-    PsiRec<R>* bucket = (PsiRec<R>*)a.bucket;
+    PsiRec<R>* binned = (PsiRec<R>*)a.binned;
     double mx[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) mx[k] = 0.0;
     unsigned long long bad = 0;
-    for (int64_t p0 = beg + threadIdx.x; p0 < end; p0 += stepw) {
-        int code[kPsiUnrollScatter];
-        R v[kPsiUnrollScatter][3], ug[kPsiUnrollScatter][3], r[kPsiUnrollScatter];
+    for (int64_t r0 = beg; r0 < end; r0 += RB) {
+        int code[U];
+        R v[U][3], ug[U][3], r[U];
 #pragma unroll
-        for (int u = 0; u < kPsiUnrollScatter; ++u) {
-            const int64_t p = p0 + (int64_t)u * blockDim.x;
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = r0 + (int64_t)u * 256 + tid;
             code[u] = p < end ? a.codes[p] : -1;
         }
 #pragma unroll
-        for (int u = 0; u < kPsiUnrollScatter; ++u) {
-            const int64_t p = p0 + (int64_t)u * blockDim.x;
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = r0 + (int64_t)u * 256 + tid;
             const bool live = code[u] >= 0;
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) {
@@ -162,8 +235,11 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
             }
             r[u] = live ? ((const R*)a.p.r)[p] : (R)1;
         }
+        PsiRec<R> rec[U];
+        unsigned int rank[U];
 #pragma unroll
-        for (int u = 0; u < kPsiUnrollScatter; ++u) {
+        for (int u = 0; u < U; ++u) {
+            rank[u] = 0;
             if (code[u] < 0) continue;
             // the source terms in the precision of the records (binary32
             // records: binary32 arithmetic, within a few ulps of the binary64
@@ -172,21 +248,40 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
             bool ok = isfinite(r[u]);
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) ok = ok && isfinite(v[u][ax]) && isfinite(ug[u][ax]);
-            PsiRec<R> rec;
             if (ok) {
                 droplet_phi_t<D, R>(r[u], v[u], ug[u], a.ph, phi);
 #pragma unroll
                 for (int k = 0; k < C; ++k) ok = ok && isfinite(phi[k]);
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) rec.phi[k] = (ok && k < C) ? phi[k] : (R)0;
-            rec.loc = ok ? (uint32_t)(code[u] & (a.cpt - 1)) : kPsiSkip;
+            for (int k = 0; k < 4; ++k) rec[u].phi[k] = (ok && k < C) ? phi[k] : (R)0;
+            rec[u].loc = (uint32_t)code[u] | (ok ? 0u : kPsiSkipBit);
             bad += ok ? 0ull : 1ull;
-            unsigned int slot = atomicAdd(&cursor[code[u] >> a.cptlog], 1u);
-            bucket[slot] = rec;
 #pragma unroll
-            for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], fabs((double)rec.phi[k]));
+            for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], fabs((double)rec[u].phi[k]));
+            rank[u] = atomicAdd(&cnt[code[u] >> bsh], 1u);
         }
+        __syncthreads();
+        const unsigned int c = tid < nbin ? cnt[tid] : 0u;
+        unsigned int total;
+        const unsigned int ex = block_exclusive_sum(c, ws, total);
+        if (tid < nbin) {
+            off[tid] = ex;
+            gbase[tid] = cursor[tid];
+            cursor[tid] += c;
+            cnt[tid] = 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (code[u] < 0) continue;
+            const int b = code[u] >> bsh;
+            const unsigned int pos = off[b] + rank[u];
+            stage[pos] = rec[u];
+            sslot[pos] = gbase[b] + rank[u];
+        }
+        __syncthreads();
+        for (unsigned int i = tid; i < total; i += 256) binned[sslot[i]] = stage[i];
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, kWave);
@@ -208,6 +303,84 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
     }
 }
 
+// Second partition: nsplit workgroups per bin each take a contiguous share
+// of the bin's records in rounds, order a round by tile in LDS and reserve
+// each tile's run with one atomic add on the tile's cursor, so the stores
+// are again contiguous runs.  The order of records inside a tile bucket then
+// depends on the schedule; the reduce adds integers, so the sums do not.
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_psi_tiles(PsiArgs a)
+{
+    constexpr int U = kPsiUnroll;
+    constexpr int RB = 256 * U;
+    __shared__ PsiRec<R> stage[RB];
+    __shared__ uint32_t sslot[RB];
+    __shared__ unsigned int cnt[kPsiTilesPerBin], off[kPsiTilesPerBin], gbase[kPsiTilesPerBin];
+    __shared__ unsigned int stotal;
+    const int tid = threadIdx.x;
+    const int bin = blockIdx.x / a.nsplit, part = blockIdx.x % a.nsplit;
+    const int64_t nbk = a.nblocks;
+    const int64_t c0 = a.binhist[(int64_t)bin * nbk], c1 = a.binhist[(int64_t)(bin + 1) * nbk];
+    const int64_t len = c1 - c0;
+    const int64_t beg = c0 + len * part / a.nsplit, end = c0 + len * (part + 1) / a.nsplit;
+    const uint32_t tile0 = (uint32_t)bin << kPsiTilesPerBinLog;
+    const uint32_t cmask = (uint32_t)a.cpt - 1u;
+    if (tid < kPsiTilesPerBin) cnt[tid] = 0;
+    __syncthreads();
+    const PsiRec<R>* src = (const PsiRec<R>*)a.binned;
+    PsiRec<R>* dst = (PsiRec<R>*)a.bucket;
+    for (int64_t r0 = beg; r0 < end; r0 += RB) {
+        R ph[U][4];
+        uint32_t lc[U];
+        int t[U];
+        unsigned int rank[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = r0 + (int64_t)u * 256 + tid;
+            const bool in = i < end;
+            const PsiRec<R>* q = src + (in ? i : 0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ph[u][k] = in ? q->phi[k] : (R)0;
+            lc[u] = in ? q->loc : 0u;
+            t[u] = -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            rank[u] = 0;
+            const int64_t i = r0 + (int64_t)u * 256 + tid;
+            if (i >= end) continue;
+            const uint32_t code = lc[u] & ~kPsiSkipBit;
+            t[u] = (int)((code >> a.cptlog) - tile0);
+            lc[u] = (lc[u] & kPsiSkipBit) ? kPsiSkip : (code & cmask);
+            rank[u] = atomicAdd(&cnt[t[u]], 1u);
+        }
+        __syncthreads();
+        if (tid < kWave) {
+            // wave 0: one tile per lane
+            const unsigned int c = cnt[tid];
+            unsigned int total;
+            const unsigned int ex = wave_exclusive_sum(c, total);
+            off[tid] = ex;
+            gbase[tid] = c ? atomicAdd(&a.tcursor[tile0 + tid], c) : 0u;
+            cnt[tid] = 0;
+            if (tid == 0) stotal = total;
+        }
+        __syncthreads();
+        const unsigned int total = stotal;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (t[u] < 0) continue;
+            const unsigned int pos = off[t[u]] + rank[u];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) stage[pos].phi[k] = ph[u][k];
+            stage[pos].loc = lc[u];
+            sslot[pos] = gbase[t[u]] + rank[u];
+        }
+        __syncthreads();
+        for (unsigned int i = tid; i < total; i += 256) dst[sslot[i]] = stage[i];
+    }
+}
+
 template <int D>
 __global__ void k_psi_scale(PsiArgs a)
 {
@@ -223,6 +396,8 @@ __global__ void k_psi_scale(PsiArgs a)
         for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
         if (lane == 0) a.maxbits[k] = (unsigned long long)__double_as_longlong(v);
     }
+    // cursors of the tile buckets for the tile pass
+    for (int t = threadIdx.x; t < a.pntiles; t += blockDim.x) a.tcursor[t] = a.blockhist[(int64_t)t * a.nblocks];
     __syncthreads();
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double n = (double)(a.p.count > 0 ? a.p.count : 1);
@@ -368,9 +543,13 @@ hipError_t launch_psicell(const PsiArgs& a, hipStream_t s)
         hipLaunchKernelGGL((k_psi_count<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
         e = launch_exclusive_scan_u32(a.blockhist, (int64_t)a.pntiles * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_psi_scatter<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
+        e = launch_exclusive_scan_u32(a.binhist, (int64_t)a.pnbins * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_psi_scatter<R, D>), dim3(a.nblocks), dim3(256), 0, s, a);
     }
     hipLaunchKernelGGL((k_psi_scale<D>), dim3(1), dim3(256), 0, s, a);
+    if (a.p.count > 0)
+        hipLaunchKernelGGL((k_psi_tiles<R, D>), dim3(a.pnbins * a.nsplit), dim3(256), 0, s, a);
     size_t lds_r = (sizeof(unsigned long long) * C + sizeof(unsigned int)) * (size_t)a.cpt;
     hipLaunchKernelGGL((k_psi_reduce<R, D>), dim3(a.pntiles), dim3(256), lds_r, s, a);
     return hipGetLastError();

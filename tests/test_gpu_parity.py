@@ -214,6 +214,36 @@ def test_psicell_deterministic(ctx):
     assert np.array_equal(S1, S2)
 
 
+def test_psicell_many_bins_with_skipped_records_f32(ctx):
+    # 100^3 cells: 13^3 = 2197 tiles of 8^3 cells, so 35 bins of 64 tiles
+    # with a partial last bin; particles outside the closed box and records
+    # with non-finite velocity or radius are spread over all of them
+    wl = W.small_random_3d(10, 100, seed=21, periodic=False)
+    cloud = W.abc_cloud(2_000_000, seed=21)
+    cloud.x = cloud.x * 1.1 - 0.05
+    cloud.r[::997] = float("nan")
+    cloud.v[1, 5::1013] = float("inf")
+    w = 0.5
+    S, den, st = gpu_run(ctx, wl, prec="f32", psicell_cloud=cloud, weight=w)
+    c64 = as_precision(cloud, "f32")
+    Sref, counts, sk = oracle.psicell(wl.mesh, c64, w, wl.rho_d, wl.mu, wl.delta)
+    assert_fields_close(S, Sref, TOL["f32"], "psicell many bins f32")
+    assert np.array_equal(den.astype(np.int64), counts)
+    assert st["outside"] == sk and sk > 4000
+
+
+def test_psicell_many_bins_2d_f64(ctx):
+    # 2-D tiles are 32^2 cells: a 1000 x 1000 mesh has 32^2 = 1024 tiles in 16 bins
+    wl = W.taylor_green_2d(per_axis=8, mesh_n=1000)
+    cloud = W.taylor_green_cloud(3_000_000, seed=22)
+    w = W.N0_DEFAULT / cloud.count
+    S, den, st = gpu_run(ctx, wl, prec="f64", psicell_cloud=cloud, weight=w)
+    Sref, counts, sk = oracle.psicell(wl.mesh, cloud, w, wl.rho_d, wl.mu, wl.delta)
+    assert_fields_close(S, Sref, TOL["f64"], "psicell many bins f64")
+    assert np.array_equal(den.astype(np.int64), counts)
+    assert st["outside"] == sk
+
+
 # ------------------------------------------------------------------ plans / autotuner
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_every_gather_plan_gives_the_same_values(ctx, prec):
