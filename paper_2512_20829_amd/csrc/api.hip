@@ -537,19 +537,13 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
 {
     const int C = D + 1;
     PsiArgs a{};
-    // coarse tiles: 8^3 (32^2 in 2-D) cells, widened axis by axis until at
-    // most kPsiMaxTiles tiles remain (cells per tile stay <= kPsiMaxCellsPerTile)
-    int pt[3] = {D == 3 ? 8 : 32, D == 3 ? 8 : 32, D == 3 ? 8 : 1};
+    // coarse tiles of kPsiMaxCellsPerTile cells: 16 x 8 x 8 (32^2 in 2-D)
+    int pt[3] = {D == 3 ? 16 : 32, D == 3 ? 8 : 32, D == 3 ? 8 : 1};
     auto ntiles = [&]() {
         int64_t nt = 1;
         for (int ax = 0; ax < D; ++ax) nt *= (m.n[ax] + pt[ax] - 1) / pt[ax];
         return nt;
     };
-    for (int it = 0; ntiles() > kPsiMaxTiles && it < 64; ++it) {
-        int ax = it % D;
-        if ((int64_t)pt[0] * pt[1] * pt[2] * 2 > kPsiMaxCellsPerTile) break;
-        if (pt[ax] < m.n[ax]) pt[ax] *= 2;
-    }
     CHECK_ARG(ntiles() <= kPsiMaxTiles, "psicell_accumulate supports at most 16384 * 1024 cells");
     for (int ax = 0; ax < 3; ++ax) {
         a.pt[ax] = ax < D ? pt[ax] : 1;

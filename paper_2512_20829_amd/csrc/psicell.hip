@@ -28,7 +28,7 @@
 // Storing each record straight into one of thousands of tile buckets would
 // leave every 20-byte store on its own and the cache lines partly written;
 // the two sorted partitions write whole runs instead.  Every pass gives each
-// thread several particles per step (kPsiUnroll, kPsiUnrollScatter) and
+// thread several particles per step (kPsiUnroll, PsiRoundPerThread) and
 // issues all their loads before any use, to keep enough reads in flight; the
 // scatter forms the binary32 source terms of binary32 records in binary32.
 #include "internal.hpp"
@@ -37,7 +37,9 @@
 namespace flp {
 
 constexpr int kPsiUnroll = 4;          // count and reduce
-constexpr int kPsiUnrollScatter = 4;   // scatter
+// particles (records) per thread in a round of the two partitions: the
+// round's records, slots and counters stay under 64 KiB of LDS
+template <typename R> struct PsiRoundPerThread { static constexpr int value = sizeof(R) == 4 ? 8 : 4; };
 constexpr uint32_t kPsiSkip = 0xFFFFFFFFu;     // cell of a skipped record in a tile bucket
 constexpr uint32_t kPsiSkipBit = 0x80000000u;  // skip mark of a binned record (codes < 2^24)
 static_assert(kPsiTilesPerBin == kWave, "the tile pass scans one tile per lane of one wave");
@@ -193,7 +195,7 @@ template <typename R, int D>
 __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
 {
     constexpr int C = D + 1;
-    constexpr int U = kPsiUnrollScatter;
+    constexpr int U = PsiRoundPerThread<R>::value;
     constexpr int RB = 256 * U;
     __shared__ PsiRec<R> stage[RB];
     __shared__ uint32_t sslot[RB];
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
 template <typename R, int D>
 __global__ __launch_bounds__(256) void k_psi_tiles(PsiArgs a)
 {
-    constexpr int U = kPsiUnroll;
+    constexpr int U = PsiRoundPerThread<R>::value;
     constexpr int RB = 256 * U;
     __shared__ PsiRec<R> stage[RB];
     __shared__ uint32_t sslot[RB];

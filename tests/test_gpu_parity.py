@@ -215,8 +215,8 @@ def test_psicell_deterministic(ctx):
 
 
 def test_psicell_many_bins_with_skipped_records_f32(ctx):
-    # 100^3 cells: 13^3 = 2197 tiles of 8^3 cells, so 35 bins of 64 tiles
-    # with a partial last bin; particles outside the closed box and records
+    # 100^3 cells: 7 x 13 x 13 = 1183 tiles of 16 x 8 x 8 cells, so 19 bins
+    # of 64 tiles with a partial last bin; particles outside the closed box and records
     # with non-finite velocity or radius are spread over all of them
     wl = W.small_random_3d(10, 100, seed=21, periodic=False)
     cloud = W.abc_cloud(2_000_000, seed=21)
