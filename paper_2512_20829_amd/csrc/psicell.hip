@@ -331,24 +331,27 @@ __global__ __launch_bounds__(256) void k_psi_tiles(PsiArgs a)
     __syncthreads();
     const PsiRec<R>* src = (const PsiRec<R>*)a.binned;
     PsiRec<R>* dst = (PsiRec<R>*)a.bucket;
-    for (int64_t r0 = beg; r0 < end; r0 += RB) {
-        R ph[U][4];
-        uint32_t lc[U];
-        int t[U];
-        unsigned int rank[U];
+    R ph[U][4], phn[U][4];
+    uint32_t lc[U], lcn[U];
+    auto load = [&](int64_t r0, R (&p)[U][4], uint32_t (&l)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = r0 + (int64_t)u * 256 + tid;
             const bool in = i < end;
             const PsiRec<R>* q = src + (in ? i : 0);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) ph[u][k] = in ? q->phi[k] : (R)0;
-            lc[u] = in ? q->loc : 0u;
-            t[u] = -1;
+            for (int k = 0; k < 4; ++k) p[u][k] = in ? q->phi[k] : (R)0;
+            l[u] = in ? q->loc : 0u;
         }
+    };
+    if (beg < end) load(beg, ph, lc);
+    for (int64_t r0 = beg; r0 < end; r0 += RB) {
+        int t[U];
+        unsigned int rank[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             rank[u] = 0;
+            t[u] = -1;
             const int64_t i = r0 + (int64_t)u * 256 + tid;
             if (i >= end) continue;
             const uint32_t code = lc[u] & ~kPsiSkipBit;
@@ -356,6 +359,8 @@ __global__ __launch_bounds__(256) void k_psi_tiles(PsiArgs a)
             lc[u] = (lc[u] & kPsiSkipBit) ? kPsiSkip : (code & cmask);
             rank[u] = atomicAdd(&cnt[t[u]], 1u);
         }
+        // the next round's records are read while this round is sorted and written
+        if (r0 + RB < end) load(r0 + RB, phn, lcn);
         __syncthreads();
         if (tid < kWave) {
             // wave 0: one tile per lane
@@ -380,6 +385,12 @@ __global__ __launch_bounds__(256) void k_psi_tiles(PsiArgs a)
         }
         __syncthreads();
         for (unsigned int i = tid; i < total; i += 256) dst[sslot[i]] = stage[i];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ph[u][k] = phn[u][k];
+            lc[u] = lcn[u];
+        }
     }
 }
 
@@ -436,6 +447,7 @@ __global__ __launch_bounds__(256) void k_psi_reduce(PsiArgs a)
     const int64_t end = a.blockhist[(int64_t)(tile + 1) * nbk];
     const PsiRec<R>* bucket = (const PsiRec<R>*)a.bucket;
     const int64_t stepw = (int64_t)blockDim.x * kPsiUnroll;
+    const bool count = a.den != nullptr;   // the per-cell counts are only an output
     for (int64_t s0 = beg + threadIdx.x; s0 < end; s0 += stepw) {
         PsiRec<R> rec[kPsiUnroll];
 #pragma unroll
@@ -453,7 +465,7 @@ __global__ __launch_bounds__(256) void k_psi_reduce(PsiArgs a)
                 long long qv = llrint((double)rec[u].phi[k] * qs[k]);
                 atomicAdd(&sacc[k * cpt + loc], (unsigned long long)qv);
             }
-            atomicAdd(&scnt[loc], 1u);
+            if (count) atomicAdd(&scnt[loc], 1u);
         }
     }
     __syncthreads();

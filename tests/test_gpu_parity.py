@@ -214,6 +214,25 @@ def test_psicell_deterministic(ctx):
     assert np.array_equal(S1, S2)
 
 
+def test_psicell_without_the_count_plane_gives_the_same_fields(ctx):
+    # the per-cell counts are an optional output; leaving them out must not
+    # change the source fields
+    import paper_2512_20829_amd as F
+    wl = W.small_random_3d(10, 40, seed=23, periodic=True)
+    cloud = W.abc_cloud(400_000, seed=23)
+    S1, _, _ = gpu_run(ctx, wl, prec="f32", psicell_cloud=cloud, weight=2.0)
+    dev = torch.device("cuda", 0)
+    st, _ = F.make_trajectories(cloud.x.to(dev).contiguous(), None, cloud.v.to(dev, torch.float32).contiguous(),
+                                cloud.ug.to(dev, torch.float32).contiguous(),
+                                cloud.r.to(dev, torch.float32).contiguous(), 1.0)
+    Sm, Sv, _ = F.alloc_fields(wl.mesh.cells, 3, torch.float32, dev)
+    p = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
+    ctx.psicell_accumulate(F.mesh_of(wl.mesh), st, 2.0, p, Sm, Sv)
+    torch.cuda.synchronize()
+    S2 = torch.stack([Sm, *Sv]).double().cpu().numpy()
+    assert np.array_equal(S1, S2)
+
+
 def test_psicell_many_bins_with_skipped_records_f32(ctx):
     # 100^3 cells: 7 x 13 x 13 = 1183 tiles of 16 x 8 x 8 cells, so 19 bins
     # of 64 tiles with a partial last bin; particles outside the closed box and records
