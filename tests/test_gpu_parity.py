@@ -233,6 +233,75 @@ def test_psicell_without_the_count_plane_gives_the_same_fields(ctx):
     assert np.array_equal(S1, S2)
 
 
+def test_psicell_edge_cases(ctx):
+    wl = W.small_random_3d(10, 12, seed=24, periodic=False)
+    base = W.abc_cloud(1000, seed=24)
+    # no particle: zero fields and counts
+    S, den, st = gpu_run(ctx, wl, prec="f32", psicell_cloud=base.subset(torch.arange(0)), weight=1.0)
+    assert np.all(S == 0.0) and np.all(den == 0.0) and st["outside"] == 0
+    # every particle outside the closed box
+    out = W.Trajectories(base.x + 2.0, base.J, base.v, base.ug, base.r, 1.0)
+    S, den, st = gpu_run(ctx, wl, prec="f32", psicell_cloud=out, weight=1.0)
+    assert np.all(S == 0.0) and np.all(den == 0.0) and st["outside"] == 1000
+    # every record skipped (non-finite radius): no cell receives anything
+    bad = W.Trajectories(base.x, base.J, base.v, base.ug, torch.full_like(base.r, float("nan")), 1.0)
+    S, den, st = gpu_run(ctx, wl, prec="f32", psicell_cloud=bad, weight=1.0)
+    assert np.all(S == 0.0) and np.all(den == 0.0) and st["outside"] == 1000
+    # one particle, with a cell scale
+    one = base.subset(torch.arange(1))
+    cs = np.linspace(0.5, 1.5, wl.mesh.cells)
+    S, den, st = gpu_run(ctx, wl, prec="f64", psicell_cloud=one, weight=3.0, cell_scale=cs)
+    Sref, counts, sk = oracle.psicell(wl.mesh, one, 3.0, wl.rho_d, wl.mu, wl.delta, cell_scale=cs)
+    assert_fields_close(S, Sref, TOL["f64"], "psicell one particle")
+    assert np.array_equal(den.astype(np.int64), counts) and counts.sum() == 1
+
+
+@pytest.mark.timeout(300)
+def test_psicell_full_size_sampled_cells(ctx):
+    """PSI-CELL over 200M particles on the 128^3 periodic mesh, launched as
+    the benchmark launches it.  Every particle is counted once, and 256
+    sampled cells match the oracle run over the particles in and next to
+    them (a cell's sums depend only on its own particles)."""
+    import paper_2512_20829_amd as F
+    dev = torch.device("cuda", 0)
+    wl = W.abc_lattice_3d(per_axis=8)      # mesh and physical constants of the 128^3 case
+    n = wl.mesh.n[0]
+    Np = 200_000_000
+    print(f"[case] psicell N={Np} mesh={wl.mesh.n}", flush=True)
+    cl = W.abc_cloud(Np, seed=0, device=dev, jacobian=False)
+    v, ug, r = (cl.v.to(torch.float32).contiguous(), cl.ug.to(torch.float32).contiguous(),
+                cl.r.to(torch.float32).contiguous())
+    st, _ = F.make_trajectories(cl.x.contiguous(), None, v, ug, r, 1.0)
+    M = wl.mesh.cells
+    Sm, Sv, den = F.alloc_fields(M, 3, torch.float32, dev)
+    w = W.N0_DEFAULT / Np
+    p = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
+    ctx.psicell_accumulate(F.mesh_of(wl.mesh), st, w, p, Sm, Sv, den)
+    torch.cuda.synchronize()
+    stats = ctx.stats()
+    assert int(den.double().sum().item()) == Np - stats["outside"]
+    S = torch.stack([Sm, *Sv]).double().cpu().numpy()
+    g = np.random.default_rng(2)
+    cells = np.sort(g.choice(M, 256, replace=False))
+    # particles whose cell lies within one cell of a sampled cell on every axis
+    near = torch.zeros((n, n, n), dtype=torch.bool, device=dev)      # [z, y, x]
+    c = torch.as_tensor(cells, device=dev)
+    cz, cy, cx = c // (n * n), (c // n) % n, c % n
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                near[(cz + dz) % n, (cy + dy) % n, (cx + dx) % n] = True
+    ix = torch.floor(cl.x * n).to(torch.int64) % n
+    pick = near[ix[2], ix[1], ix[0]]
+    del ix
+    sub = W.Trajectories(cl.x[:, pick].cpu(), torch.empty(0, dtype=torch.float64),
+                         v[:, pick].double().cpu(), ug[:, pick].double().cpu(), r[pick].double().cpu(), 1.0)
+    print(f"[case] psicell oracle over {sub.count} particles near the sampled cells", flush=True)
+    Sref, counts, _ = oracle.psicell(wl.mesh, sub, w, wl.rho_d, wl.mu, wl.delta)
+    assert_fields_close(S[:, cells], Sref[:, cells], TOL["f32"], "psicell 200M sampled")
+    assert np.array_equal(den[cells].cpu().numpy().astype(np.int64), counts[cells])
+
+
 def test_psicell_many_bins_with_skipped_records_f32(ctx):
     # 100^3 cells: 7 x 13 x 13 = 1183 tiles of 16 x 8 x 8 cells, so 19 bins
     # of 64 tiles with a partial last bin; particles outside the closed box and records
