@@ -624,7 +624,6 @@ fla_status project_backward_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& 
                                  hipStream_t s)
 {
     const int64_t N = t.count;
-    const int C = D + 1;
     uint32_t *keys, *vals;
     double4* rpos;
     R* rw;
@@ -634,7 +633,7 @@ fla_status project_backward_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& 
         vals = c.take<uint32_t>(N > 0 ? N : 1);
         rpos = c.take<double4>(N > 0 ? N : 1);
         rw = c.take<R>((size_t)(N > 0 ? N : 1) * kRecW);
-        bpl = c.take<float>((size_t)C * m.M);
+        bpl = c.take<float>((size_t)4 * m.M);   // four floats per cell (float4 aligned)
         epl = c.take<float>(m.M);
     };
     {

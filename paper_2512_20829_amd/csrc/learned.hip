@@ -297,9 +297,11 @@ __global__ __launch_bounds__(kWave * kMlpWaves) void k_features_mlp(TrajDev t, M
 
 // ---------------------------------------------------------------- estimator backward
 // Per cell: a = -scale cs / D (0 where D = 0), b_k = a g_k, e = a sum_k g_k N_k / D.
+// b is stored cell-major, four floats per cell (unused channels zero), so
+// that the trajectory pass reads it with one 16-byte load per pair.
 template <typename R>
 __global__ void k_cell_grad(int C, int64_t M, Planes S, const void* den, Planes dLdS, double scale,
-                            const void* cell_scale, float* b, float* e)
+                            const void* cell_scale, float4* b, float* e)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= M) return;
@@ -308,12 +310,14 @@ __global__ void k_cell_grad(int C, int64_t M, Planes S, const void* den, Planes 
     double f = -scale * cs;
     double a = (d > 0.0) ? f / d : 0.0;
     double ee = 0.0;
+    float bk[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int k = 0; k < C; ++k) {
         double g = (double)((const R*)dLdS.p[k])[c];
         double shat = (d > 0.0 && f != 0.0) ? (double)((const R*)S.p[k])[c] / f : 0.0;
-        b[(int64_t)k * M + c] = (float)(a * g);
+        bk[k] = (float)(a * g);
         ee += g * shat;
     }
+    b[c] = make_float4(bk[0], bk[1], bk[2], bk[3]);
     e[c] = (float)(a * ee);
 }
 
@@ -324,7 +328,7 @@ __global__ void k_cell_grad(int C, int64_t M, Planes S, const void* den, Planes 
 constexpr int kBTab = 128;
 template <typename R, int D>
 __global__ __launch_bounds__(64) void k_traj_backward(MeshDev m, double cutoff, const uint32_t* keys, uint32_t sentinel,
-                                                      const double4* rpos, const R* rw, const float* b, const float* e,
+                                                      const double4* rpos, const R* rw, const float4* b, const float* e,
                                                       float* out, int64_t N)
 {
     constexpr int C = D + 1;
@@ -370,7 +374,6 @@ __global__ __launch_bounds__(64) void k_traj_backward(MeshDev m, double cutoff, 
         cnt[a] = ihi - ilo + 1 < 0 ? 0 : ihi - ilo + 1;
     }
     double acc = 0.0;
-    const int64_t M = m.M;
     for (int64_t bz = 0; bz < cnt[2]; bz += kBTab)
     for (int64_t by = 0; by < cnt[1]; by += kBTab)
     for (int64_t bx = 0; bx < cnt[0]; bx += kBTab) {
@@ -392,12 +395,13 @@ __global__ __launch_bounds__(64) void k_traj_backward(MeshDev m, double cutoff, 
             E[2][0] = 1;
         }
         __syncthreads();
-        const int64_t tot = (int64_t)len[0] * len[1] * (D == 3 ? len[2] : 1);
-        for (int64_t j = lane; j < tot; j += kWave) {
-            int jx = (int)(j % len[0]);
-            int64_t r2 = j / len[0];
-            int jy = (int)(r2 % len[1]);
-            int jz = (int)(r2 / len[1]);
+        // at most kBTab^3 = 2^21 cells per block: 32-bit index arithmetic
+        const int tot = len[0] * len[1] * (D == 3 ? len[2] : 1);
+        for (int j = lane; j < tot; j += kWave) {
+            const int jx = j % len[0];
+            const int r2 = j / len[0];
+            const int jy = r2 % len[1];
+            const int jz = r2 / len[1];
             R s = S[0][jx] + S[1][jy];
             if (D == 3) s = s + S[2][jz];
             if (!(s <= c2)) continue;
@@ -408,9 +412,11 @@ __global__ __launch_bounds__(64) void k_traj_backward(MeshDev m, double cutoff, 
                 lin += v * st;
                 st *= m.n[a];
             }
+            const float4 bb = b[lin];
+            const float bk[4] = {bb.x, bb.y, bb.z, bb.w};
             float G = -e[lin];
 #pragma unroll
-            for (int k = 0; k < C; ++k) G += b[(int64_t)k * M + lin] * q[k];
+            for (int k = 0; k < C; ++k) G += bk[k] * q[k];
             double K = inv_h * (double)(E[0][jx] * E[1][jy] * (D == 3 ? E[2][jz] : (R)1));
             acc += K * ((double)s - 1.0) * (double)G;
         }
@@ -698,15 +704,16 @@ hipError_t launch_bandwidth_forward(const TrajDev& t, const MeshDev& m, const fl
 template <typename R, int D>
 hipError_t launch_traj_backward(const MeshDev& m, double cutoff, const uint32_t* keys, uint32_t sentinel,
                                 const double4* rpos, const R* rw, Planes S, const void* den, Planes dLdS,
-                                double scale, const void* cell_scale, float* bplanes, float* eplane, float* out,
+                                double scale, const void* cell_scale, float* bcells, float* eplane, float* out,
                                 int64_t N, hipStream_t s)
 {
     unsigned g = (unsigned)((m.M + 255) / 256);
-    hipLaunchKernelGGL((k_cell_grad<R>), dim3(g), dim3(256), 0, s, D + 1, m.M, S, den, dLdS, scale, cell_scale, bplanes,
+    float4* b4 = reinterpret_cast<float4*>(bcells);
+    hipLaunchKernelGGL((k_cell_grad<R>), dim3(g), dim3(256), 0, s, D + 1, m.M, S, den, dLdS, scale, cell_scale, b4,
                        eplane);
     if (N > 0)
         hipLaunchKernelGGL((k_traj_backward<R, D>), dim3((unsigned)N), dim3(64), 0, s, m, cutoff, keys, sentinel, rpos, rw,
-                           bplanes, eplane, out, N);
+                           (const float4*)b4, eplane, out, N);
     return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ hipError_t launch_bandwidth_forward(const TrajDev& t, const MeshDev& m, const fl
 template <typename R, int D>
 hipError_t launch_traj_backward(const MeshDev& m, double cutoff, const uint32_t* keys, uint32_t sentinel,
                                 const double4* rpos, const R* rw, Planes S, const void* den, Planes dLdS,
-                                double scale, const void* cell_scale, float* bplanes, float* eplane, float* out,
+                                double scale, const void* cell_scale, float* bcells, float* eplane, float* out,
                                 int64_t N, hipStream_t s);
 int mlp_backward_blocks(int64_t N);
 template <int D>
