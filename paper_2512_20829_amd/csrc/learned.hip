@@ -334,6 +334,7 @@ __global__ __launch_bounds__(64) void k_traj_backward(MeshDev m, double cutoff, 
     constexpr int C = D + 1;
     __shared__ R S[3][kBTab];
     __shared__ R E[3][kBTab];
+    __shared__ int64_t IX[3][kBTab];   // wrapped cell index times the axis stride
     const int64_t i = blockIdx.x;
     const int lane = threadIdx.x;
     if (keys[i] == sentinel) {
@@ -384,34 +385,46 @@ __global__ __launch_bounds__(64) void k_traj_backward(MeshDev m, double cutoff, 
             len[a] = (int)(l < kBTab ? l : kBTab);
         }
         __syncthreads();
-        for (int a = 0; a < D; ++a)
+        int64_t stride = 1;
+        for (int a = 0; a < D; ++a) {
             for (int j = lane; j < len[a]; j += kWave) {
                 int64_t ci = lo[a] + b0[a] + j;
                 if (m.periodic[a]) ci = posmod(ci, m.n[a]);
                 axis_factor<R>(m, a, ci, x[a], inv_h, S[a][j], E[a][j]);
+                IX[a][j] = ci * stride;
             }
+            stride *= m.n[a];
+        }
         if (D == 2 && lane == 0) {
             S[2][0] = 0;
             E[2][0] = 1;
+            IX[2][0] = 0;
         }
         __syncthreads();
-        // at most kBTab^3 = 2^21 cells per block: 32-bit index arithmetic
+        // at most kBTab^3 = 2^21 cells per block: 32-bit index arithmetic, the
+        // quotients by the row lengths from a binary32 reciprocal (within
+        // one of the true quotient for j < 2^21, then corrected)
         const int tot = len[0] * len[1] * (D == 3 ? len[2] : 1);
+        const float r0 = 1.0f / (float)len[0], r1 = 1.0f / (float)len[1];
+        auto divmod = [](int j, int l, float r, int& q, int& rem) {
+            q = (int)((float)j * r);
+            rem = j - q * l;
+            if (rem < 0) {
+                --q;
+                rem += l;
+            } else if (rem >= l) {
+                ++q;
+                rem -= l;
+            }
+        };
         for (int j = lane; j < tot; j += kWave) {
-            const int jx = j % len[0];
-            const int r2 = j / len[0];
-            const int jy = r2 % len[1];
-            const int jz = r2 / len[1];
+            int jx, r2, jy, jz;
+            divmod(j, len[0], r0, r2, jx);
+            divmod(r2, len[1], r1, jz, jy);
             R s = S[0][jx] + S[1][jy];
             if (D == 3) s = s + S[2][jz];
             if (!(s <= c2)) continue;
-            int64_t ci[3] = {lo[0] + b0[0] + jx, lo[1] + b0[1] + jy, lo[2] + b0[2] + jz};
-            int64_t lin = 0, st = 1;
-            for (int a = 0; a < D; ++a) {
-                int64_t v = m.periodic[a] ? posmod(ci[a], m.n[a]) : ci[a];
-                lin += v * st;
-                st *= m.n[a];
-            }
+            const int64_t lin = IX[0][jx] + IX[1][jy] + IX[2][jz];
             const float4 bb = b[lin];
             const float bk[4] = {bb.x, bb.y, bb.z, bb.w};
             float G = -e[lin];
