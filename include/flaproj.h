@@ -185,8 +185,9 @@ fla_status fla_project_sources(fla_ctx* ctx, const fla_mesh* mesh, const fla_tra
  *   S_k(c) = -(particle_weight / V_c) * cell_scale(c) * sum_{p in c} phi_pk,
  *   phi_p = [mdot_p, F_p + mdot_p v_p]   (n = 1 per droplet),
  * particle_weight being the number of real droplets one computational
- * particle stands for.  phi is evaluated in binary64 and rounded to the
- * call's precision; the sums are exact integer sums of these values
+ * particle stands for.  phi is evaluated in the call's precision (binary32
+ * arithmetic for binary32 inputs: within a few ulps of the binary64 terms
+ * rounded to binary32); the sums are exact integer sums of these values
  * quantised to 2^-e (e chosen per channel from the largest |phi| so that no
  * sum can overflow), hence order-independent.  den, if given, receives the
  * particle count per cell.  Meshes of more than 16384 * 1024 cells return
