@@ -28,15 +28,17 @@
 // Storing each record straight into one of thousands of tile buckets would
 // leave every 20-byte store on its own and the cache lines partly written;
 // the two sorted partitions write whole runs instead.  Every pass gives each
-// thread several particles per step (kPsiUnroll, PsiRoundPerThread) and
-// issues all their loads before any use, to keep enough reads in flight; the
-// scatter forms the binary32 source terms of binary32 records in binary32.
+// thread several particles per step (kPsiUnroll, PsiRoundPerThread,
+// kPsiUnrollReduce) and issues all their loads before any use, to keep
+// enough reads in flight; the scatter forms the binary32 source terms of
+// binary32 records in binary32.
 #include "internal.hpp"
 #include "kernels.hpp"
 
 namespace flp {
 
-constexpr int kPsiUnroll = 4;          // count and reduce
+constexpr int kPsiUnroll = 4;          // count
+constexpr int kPsiUnrollReduce = 8;    // reduce
 // particles (records) per thread in a round of the two partitions: the
 // round's records, slots and counters stay under 64 KiB of LDS
 template <typename R> struct PsiRoundPerThread { static constexpr int value = sizeof(R) == 4 ? 8 : 4; };
@@ -446,18 +448,18 @@ __global__ __launch_bounds__(256) void k_psi_reduce(PsiArgs a)
     const int64_t beg = a.blockhist[(int64_t)tile * nbk];
     const int64_t end = a.blockhist[(int64_t)(tile + 1) * nbk];
     const PsiRec<R>* bucket = (const PsiRec<R>*)a.bucket;
-    const int64_t stepw = (int64_t)blockDim.x * kPsiUnroll;
+    const int64_t stepw = (int64_t)blockDim.x * kPsiUnrollReduce;
     const bool count = a.den != nullptr;   // the per-cell counts are only an output
     for (int64_t s0 = beg + threadIdx.x; s0 < end; s0 += stepw) {
-        PsiRec<R> rec[kPsiUnroll];
+        PsiRec<R> rec[kPsiUnrollReduce];
 #pragma unroll
-        for (int u = 0; u < kPsiUnroll; ++u) {
+        for (int u = 0; u < kPsiUnrollReduce; ++u) {
             const int64_t sl = s0 + (int64_t)u * blockDim.x;
             if (sl < end) rec[u] = bucket[sl];
             else rec[u].loc = kPsiSkip;
         }
 #pragma unroll
-        for (int u = 0; u < kPsiUnroll; ++u) {
+        for (int u = 0; u < kPsiUnrollReduce; ++u) {
             if (rec[u].loc == kPsiSkip) continue;
             const int loc = (int)rec[u].loc;
 #pragma unroll
