@@ -541,7 +541,12 @@ def main():
         ctx.profile_enable(False)
         psi = {"particles": Np, "ms": round(psi_ms, 3),
                "particles_per_s": Np / (psi_ms * 1e-3),
-               "hbm_gbs_input": round(Np * 40 / (psi_ms * 1e-3) / 1e9, 1),
+               # inputs: x in binary64 (24 B), v, u_g, r in binary32 (28 B)
+               "hbm_gbs_input": round(Np * 52 / (psi_ms * 1e-3) / 1e9, 1),
+               # the four passes move 140 B per particle: count 24 in + 4 out,
+               # scatter 32 in + 20 out, tiles 20 in + 20 out, reduce 20 in
+               "hbm_gbs_algorithmic": round(Np * 140 / (psi_ms * 1e-3) / 1e9, 1),
+               "frac_of_hbm_peak": round(Np * 140 / (psi_ms * 1e-3) / 8.0e12, 3),
                "psicell_over_fla_time": round(psi_ms / ms_step, 3),
                "paper_context": "paper: FLA 32 CPU-h vs PSI-CELL 4030 CPU-h for the whole coupled "
                                 "solver at 100x seeding, University of Brighton CPU cluster"}
