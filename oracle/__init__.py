@@ -70,6 +70,14 @@ def _declare(L):
     L.orc_nw_cells.restype = None
     L.orc_nw_cells.argtypes = [C.POINTER(OrcMesh), C.c_int64, _dp, _dp, _dp, _ip, C.c_double,
                                C.c_int, C.c_double, _dp, C.c_int64, _lp, _dp, _dp, _lp]
+    L.orc_nw_box.restype = C.c_int
+    L.orc_nw_box.argtypes = [C.POINTER(OrcMesh), C.c_int64, _dp, _dp, _dp, _ip, C.c_double, C.c_int,
+                             C.c_double, _dp, _lp, _lp, _dp, _dp, _lp]
+    L.orc_box_cells.restype = None
+    L.orc_box_cells.argtypes = [C.POINTER(OrcMesh), _lp, _lp, _lp]
+    L.orc_deposit_scatter.restype = None
+    L.orc_deposit_scatter.argtypes = [C.POINTER(OrcMesh), C.c_int64, _dp, _dp, _dp, _dp, _ip,
+                                      C.c_double, C.c_double, C.c_int, C.c_double, _dp, _dp, _dp]
     L.orc_deposit.restype = None
     L.orc_deposit.argtypes = [C.POINTER(OrcMesh), C.c_int64, _dp, _dp, _dp, _dp, _ip,
                               C.c_double, C.c_double, C.c_int, C.c_double, _dp, _dp, _dp]
@@ -208,6 +216,67 @@ def nw_cells(mesh, x, terms: Terms, cells: Optional[np.ndarray] = None, cutoff: 
     return Projection(S, den, pairs)
 
 
+@dataclass
+class BoxProjection:
+    S: np.ndarray        # (C, B) in box order
+    den: np.ndarray      # (B,)
+    pairs: np.ndarray    # (B,) int64
+    cells: np.ndarray    # (B,) linear mesh index of each box cell
+
+
+def nw_box(mesh, x, terms: Terms, box_lo: Optional[Sequence[int]] = None,
+           box_n: Optional[Sequence[int]] = None, cutoff: float = 4.0, f32_decision: bool = False,
+           scale: float = 1.0, cell_scale: Optional[np.ndarray] = None) -> BoxProjection:
+    """Nadaraya-Watson source terms on a box of cells by the trajectory-centric
+    scatter (each trajectory visits the bounding box of its cutoff sphere).
+    The box starts at cell box_lo and spans box_n cells per axis, wrapping
+    across periodic boundaries; the default is the whole mesh.  Bit for bit
+    the result of ``nw_cells`` on the same cells."""
+    m = mesh if isinstance(mesh, OrcMesh) else mesh_from(mesh)
+    dim = m.dim
+    lo = np.zeros(3, dtype=np.int64)
+    bn = np.ones(3, dtype=np.int64)
+    for a in range(dim):
+        lo[a] = int(box_lo[a]) if box_lo is not None else 0
+        bn[a] = int(box_n[a]) if box_n is not None else m.n[a]
+    B = int(np.prod(bn))
+    x = _f64(x)
+    N = x.shape[1]
+    S = np.zeros((1 + dim, B))
+    den = np.zeros(B)
+    pairs = np.zeros(B, dtype=np.int64)
+    cells = np.zeros(B, dtype=np.int64)
+    cs = _f64(cell_scale) if cell_scale is not None else None
+    rc = lib().orc_nw_box(C.byref(m), N, _d(x), _d(terms.h), _d(np.ascontiguousarray(terms.q)),
+                          terms.valid.ctypes.data_as(_ip), cutoff, int(bool(f32_decision)), scale,
+                          _d(cs) if cs is not None else None, lo.ctypes.data_as(_lp),
+                          bn.ctypes.data_as(_lp), _d(S), _d(den), pairs.ctypes.data_as(_lp))
+    if rc != 0:
+        raise ValueError(f"box {lo[:dim]} + {bn[:dim]} does not fit the mesh")
+    lib().orc_box_cells(C.byref(m), lo.ctypes.data_as(_lp), bn.ctypes.data_as(_lp), cells.ctypes.data_as(_lp))
+    return BoxProjection(S, den, pairs, cells)
+
+
+def deposit_scatter(mesh, x, terms: Terms, seed_volume: float, cutoff: float = 4.0,
+                    f32_decision: bool = False, scale: float = 1.0,
+                    cell_scale: Optional[np.ndarray] = None):
+    """Trajectory-centric form of ``deposit`` (bit for bit the same result);
+    returns (S (C, M), Z (N,))."""
+    m = mesh if isinstance(mesh, OrcMesh) else mesh_from(mesh)
+    dim = m.dim
+    M = int(np.prod([m.n[a] for a in range(dim)]))
+    x = _f64(x)
+    N = x.shape[1]
+    S = np.zeros((1 + dim, M))
+    Z = np.zeros(N)
+    cs = _f64(cell_scale) if cell_scale is not None else None
+    lib().orc_deposit_scatter(C.byref(m), N, _d(x), _d(terms.h), _d(np.ascontiguousarray(terms.q)),
+                              _d(terms.det), terms.valid.ctypes.data_as(_ip), seed_volume, cutoff,
+                              int(bool(f32_decision)), scale, _d(cs) if cs is not None else None,
+                              _d(S), _d(Z))
+    return S, Z
+
+
 def deposit(mesh, x, terms: Terms, seed_volume: float, cutoff: float = 4.0,
             f32_decision: bool = False, scale: float = 1.0,
             cell_scale: Optional[np.ndarray] = None):
@@ -254,6 +323,14 @@ def app_a_scaling(N_ref, tau_ref, N_fla, tau_fla, V_cell, A_inj, v_inj):
     out = np.zeros(3)
     lib().orc_app_a_scaling(N_ref, tau_ref, N_fla, tau_fla, V_cell, A_inj, v_inj, _d(out))
     return float(out[0]), float(out[1]), float(out[2])
+
+
+def project_box(mesh, traj, rho_d, mu, delta, h0, cutoff=4.0, f32_decision=False, scale=1.0,
+                cell_scale=None, box_lo=None, box_n=None, h_factor=None):
+    """Whole plain path by the trajectory-centric scatter: terms, then the
+    estimator on a box of cells (the whole mesh by default)."""
+    t = trajectory_terms(traj, rho_d, mu, delta, h0, h_factor)
+    return nw_box(mesh, traj.x, t, box_lo, box_n, cutoff, f32_decision, scale, cell_scale), t
 
 
 def project(mesh, traj, rho_d, mu, delta, h0, cutoff=4.0, f32_decision=False, scale=1.0,

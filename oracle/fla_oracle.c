@@ -153,6 +153,7 @@ int64_t orc_trajectory_terms(int dim, int64_t N, const double* x, const double* 
 {
     int C = 1 + dim;
     int64_t skipped = 0;
+#pragma omp parallel for schedule(static) reduction(+ : skipped)
     for (int64_t i = 0; i < N; ++i) {
         double Ji[9], xi[3], vi[3], ui[3];
         for (int e = 0; e < dim * dim; ++e) Ji[e] = J[e * N + i];
@@ -337,6 +338,332 @@ void orc_deposit(const orc_mesh* m, int64_t N, const double* x, const double* h,
     if (Z_out)
         for (int64_t i = 0; i < N; ++i) Z_out[i] = Z[i];
     free(Z);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trajectory-centric forms (O(P) instead of O(N*M)).  The same estimator   */
+/* and deposition as above, with each trajectory visiting only the cells    */
+/* inside the bounding box of its cutoff sphere (App. B steps 1c-1d: loop   */
+/* over trajectories, each adding its kernel contributions to the cells).   */
+/* Every pair goes through the same cell_traj_weight as the brute-force     */
+/* forms and every cell adds its trajectories in ascending index order, so  */
+/* the results are those of the brute-force forms bit for bit; only the     */
+/* cells that cannot hold an included pair are never looked at.             */
+/* ------------------------------------------------------------------------ */
+
+/* Cells of axis a whose centre can lie within reach of a trajectory at      */
+/* coordinate xp with bandwidth h, in ascending index order.  A pair is      */
+/* included only if (d/h)^2 <= c^2 on every axis (binary64; the binary32     */
+/* decision differs by a few ulps), so the list widens the interval          */
+/* |d| <= c h by a relative 1e-6 and one cell on each side; the inclusion    */
+/* test itself decides.  Periodic axes wrap (minimum image), closed axes     */
+/* clip.  Returns the number of cells written to list (at most n).           */
+static int64_t axis_reach(const orc_mesh* m, int a, double xp, double h, double cutoff, int64_t* list)
+{
+    int64_t n = m->n[a];
+    double w = cell_width(m, a);
+    double u = (xp - m->lo[a]) / w - 0.5;     /* position in cell-centre index units */
+    double R = cutoff * h / w * (1.0 + 1e-6) + 1.0;
+    double klo = floor(u - R), khi = ceil(u + R);
+    if (m->periodic[a]) {
+        if (!(khi - klo + 1.0 < (double)n)) {
+            for (int64_t k = 0; k < n; ++k) list[k] = k;
+            return n;
+        }
+        /* shift the interval so that it starts in [0, n) */
+        double sh = floor(klo / (double)n) * (double)n;
+        int64_t k0 = (int64_t)(klo - sh), k1 = (int64_t)(khi - sh);
+        int64_t cnt = 0;
+        if (k1 >= n) {
+            for (int64_t k = 0; k <= k1 - n; ++k) list[cnt++] = k;
+            for (int64_t k = k0; k < n; ++k) list[cnt++] = k;
+        } else {
+            for (int64_t k = k0; k <= k1; ++k) list[cnt++] = k;
+        }
+        return cnt;
+    }
+    if (klo < 0.0) klo = 0.0;
+    if (khi > (double)(n - 1)) khi = (double)(n - 1);
+    if (klo > khi) return 0;
+    int64_t cnt = 0;
+    for (int64_t k = (int64_t)klo; k <= (int64_t)khi; ++k) list[cnt++] = k;
+    return cnt;
+}
+
+/* Position of mesh index k of axis a inside a box of cells starting at      */
+/* box_lo with box_n cells (wrapping on a periodic axis), or -1.             */
+static int64_t box_pos(const orc_mesh* m, int a, int64_t k, int64_t box_lo, int64_t box_n)
+{
+    int64_t j = k - box_lo;
+    if (m->periodic[a]) {
+        j %= m->n[a];
+        if (j < 0) j += m->n[a];
+    }
+    return (j >= 0 && j < box_n) ? j : -1;
+}
+
+/* Per-axis terms of one trajectory at the listed cells of axis a: the      */
+/* offset d to each cell centre (minimum image), d^2 and (d/h)^2, exactly   */
+/* as cell_traj_weight forms them.  A pair then sums these over the axes    */
+/* in axis order, so its weight and inclusion are those of the brute-force  */
+/* forms bit for bit; only the repeated per-axis work is done once.         */
+static void axis_terms(const orc_mesh* m, int a, const int64_t* list, int64_t cnt, double xp, double inv_h,
+                       double* dd, double* sq)
+{
+    for (int64_t e = 0; e < cnt; ++e) {
+        double d = axis_offset(m, a, cell_centre(m, a, list[e]), xp);
+        double u = d * inv_h;
+        sq[e] = u * u;
+        dd[e] = d * d;
+    }
+}
+
+/* Weight of one pair from its per-axis terms (see cell_traj_weight).        */
+static int pair_weight(int dim, const double* dd, const double* sq, double h, double cutoff, int f32_decision,
+                       double* K)
+{
+    if (!pair_included(dim, sq, cutoff, f32_decision)) return 0;
+    double r2 = 0.0;
+    for (int a = 0; a < dim; ++a) r2 += dd[a];
+    *K = gauss_kernel(r2, h);
+    return 1;
+}
+
+/* Nadaraya-Watson source terms on a box of cells (form ii).  The box starts */
+/* at cell box_lo[a] and spans box_n[a] cells on each axis (wrapping across  */
+/* a periodic boundary); results are stored in box order                    */
+/* j0 + b0*(j1 + b1*j2).  The whole field is box_lo = 0, box_n = n.         */
+/* OpenMP threads own contiguous planes of the box along its last axis; each */
+/* visits the trajectories in ascending order, so the sums of every cell    */
+/* are formed in the order of the brute-force form and are deterministic.   */
+/* Returns 0, or -1 for a box that does not fit the mesh.                   */
+int orc_nw_box(const orc_mesh* m, int64_t N, const double* x, const double* h, const double* q,
+               const int* valid, double cutoff, int f32_decision, double scale, const double* cell_scale,
+               const int64_t* box_lo, const int64_t* box_n, double* S, double* den_out, int64_t* pairs_out)
+{
+    int C = 1 + m->dim, la = m->dim - 1;
+    int64_t bn[3] = {1, 1, 1}, bl[3] = {0, 0, 0}, B = 1;
+    for (int a = 0; a < m->dim; ++a) {
+        bl[a] = box_lo[a];
+        bn[a] = box_n[a];
+        if (bn[a] < 1 || bn[a] > m->n[a]) return -1;
+        if (!m->periodic[a] && (bl[a] < 0 || bl[a] + bn[a] > m->n[a])) return -1;
+        B *= bn[a];
+    }
+    /* per cell: den, num[C], pair count (one record, so a pair touches one line) */
+    typedef struct {
+        double den, num[4];
+        int64_t np;
+    } cell_acc;
+    cell_acc* acc = (cell_acc*)calloc((size_t)B, sizeof(cell_acc));
+    int64_t nmax = 1;
+    for (int a = 0; a < m->dim; ++a) nmax = m->n[a] > nmax ? m->n[a] : nmax;
+#pragma omp parallel
+    {
+        int nt = 1, t = 0;
+#ifdef _OPENMP
+        nt = omp_get_num_threads();
+        t = omp_get_thread_num();
+#endif
+        /* planes [p0, p1) of the box along its last axis belong to thread t */
+        int64_t p0 = bn[la] * t / nt, p1 = bn[la] * (t + 1) / nt;
+        int64_t* lists = (int64_t*)malloc(sizeof(int64_t) * (size_t)(3 * nmax));
+        int64_t* pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)(3 * nmax));
+        double* dd = (double*)malloc(sizeof(double) * (size_t)(3 * nmax));
+        double* sq = (double*)malloc(sizeof(double) * (size_t)(3 * nmax));
+        for (int64_t i = 0; i < N && p0 < p1; ++i) {
+            if (!valid[i]) continue;
+            int64_t cnt[3] = {1, 1, 1};
+            int skip = 0;
+            /* the last axis first: most trajectories miss this thread's planes */
+            for (int a = la; a >= 0 && !skip; --a) {
+                int64_t* L = lists + a * nmax;
+                int64_t* P = pos + a * nmax;
+                int64_t c = axis_reach(m, a, x[a * N + i], h[i], cutoff, L);
+                int64_t kept = 0;
+                for (int64_t e = 0; e < c; ++e) {
+                    int64_t j = box_pos(m, a, L[e], bl[a], bn[a]);
+                    if (j < 0 || (a == la && (j < p0 || j >= p1))) continue;
+                    L[kept] = L[e];
+                    P[kept] = j;
+                    ++kept;
+                }
+                cnt[a] = kept;
+                if (kept == 0) skip = 1;
+            }
+            if (skip) continue;
+            double inv_h = 1.0 / h[i];
+            for (int a = 0; a < m->dim; ++a)
+                axis_terms(m, a, lists + a * nmax, cnt[a], x[a * N + i], inv_h, dd + a * nmax, sq + a * nmax);
+            double qi[4] = {0, 0, 0, 0};
+            for (int k = 0; k < C; ++k) qi[k] = q[k * N + i];
+            for (int64_t e2 = 0; e2 < cnt[2]; ++e2)
+                for (int64_t e1 = 0; e1 < cnt[1]; ++e1)
+                    for (int64_t e0 = 0; e0 < cnt[0]; ++e0) {
+                        int64_t j = pos[e0] + bn[0] * (pos[nmax + e1] + bn[1] * (m->dim == 3 ? pos[2 * nmax + e2] : 0));
+                        double pd[3] = {dd[e0], dd[nmax + e1], m->dim == 3 ? dd[2 * nmax + e2] : 0.0};
+                        double ps[3] = {sq[e0], sq[nmax + e1], m->dim == 3 ? sq[2 * nmax + e2] : 0.0};
+                        double K;
+                        if (!pair_weight(m->dim, pd, ps, h[i], cutoff, f32_decision, &K)) continue;
+                        acc[j].den += K;
+                        for (int k = 0; k < C; ++k) acc[j].num[k] += K * qi[k];
+                        ++acc[j].np;
+                    }
+        }
+        free(lists);
+        free(pos);
+        free(dd);
+        free(sq);
+    }
+    for (int64_t j = 0; j < B; ++j) {
+        int64_t jj[3] = {j % bn[0], (j / bn[0]) % bn[1], m->dim == 3 ? j / (bn[0] * bn[1]) : 0};
+        int64_t lin = 0, stride = 1;
+        for (int a = 0; a < m->dim; ++a) {
+            int64_t k = bl[a] + jj[a];
+            if (m->periodic[a]) {
+                k %= m->n[a];
+                if (k < 0) k += m->n[a];
+            }
+            lin += k * stride;
+            stride *= m->n[a];
+        }
+        double cs = cell_scale ? cell_scale[lin] : 1.0;
+        double den = acc[j].den;
+        for (int k = 0; k < C; ++k) S[k * B + j] = (den > 0.0) ? -scale * cs * (acc[j].num[k] / den) : 0.0;
+        if (den_out) den_out[j] = den;
+        if (pairs_out) pairs_out[j] = acc[j].np;
+    }
+    free(acc);
+    return 0;
+}
+
+/* Linear indices of the cells of a box (in box order), for the caller.      */
+void orc_box_cells(const orc_mesh* m, const int64_t* box_lo, const int64_t* box_n, int64_t* cells)
+{
+    int64_t bn[3] = {1, 1, 1};
+    for (int a = 0; a < m->dim; ++a) bn[a] = box_n[a];
+    int64_t B = bn[0] * bn[1] * bn[2];
+    for (int64_t j = 0; j < B; ++j) {
+        int64_t jj[3] = {j % bn[0], (j / bn[0]) % bn[1], j / (bn[0] * bn[1])};
+        int64_t lin = 0, stride = 1;
+        for (int a = 0; a < m->dim; ++a) {
+            int64_t k = box_lo[a] + jj[a];
+            if (m->periodic[a]) {
+                k %= m->n[a];
+                if (k < 0) k += m->n[a];
+            }
+            lin += k * stride;
+            stride *= m->n[a];
+        }
+        cells[j] = lin;
+    }
+}
+
+/* Normalised-kernel deposition, trajectory-centric (form ii of            */
+/* orc_deposit): Z_i sums the trajectory's kernel over the cells of its     */
+/* reach in ascending linear order (the order of the brute-force form),     */
+/* then threads owning planes along the last axis add Q_i K_ci / Z_i in     */
+/* ascending trajectory order.  Bit for bit the brute-force result.         */
+void orc_deposit_scatter(const orc_mesh* m, int64_t N, const double* x, const double* h,
+                         const double* q, const double* det, const int* valid, double seed_volume,
+                         double cutoff, int f32_decision, double scale, const double* cell_scale,
+                         double* S /* C x M */, double* Z_out)
+{
+    int C = 1 + m->dim, la = m->dim - 1;
+    int64_t M = 1, nmax = 1;
+    for (int a = 0; a < m->dim; ++a) {
+        M *= m->n[a];
+        nmax = m->n[a] > nmax ? m->n[a] : nmax;
+    }
+    double Vc = cell_volume(m);
+    double* Z = (double*)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
+    double* acc = (double*)calloc((size_t)(C * M), sizeof(double));
+#pragma omp parallel
+    {
+        int64_t* L = (int64_t*)malloc(sizeof(int64_t) * (size_t)(3 * nmax));
+        double* dd = (double*)malloc(sizeof(double) * (size_t)(3 * nmax));
+        double* sq = (double*)malloc(sizeof(double) * (size_t)(3 * nmax));
+        int64_t cnt[3];
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < N; ++i) {
+            if (!valid[i]) continue;
+            cnt[1] = cnt[2] = 1;
+            L[nmax] = L[2 * nmax] = 0;
+            double inv_h = 1.0 / h[i];
+            for (int a = 0; a < m->dim; ++a) {
+                cnt[a] = axis_reach(m, a, x[a * N + i], h[i], cutoff, L + a * nmax);
+                axis_terms(m, a, L + a * nmax, cnt[a], x[a * N + i], inv_h, dd + a * nmax, sq + a * nmax);
+            }
+            double z = 0.0;
+            for (int64_t e2 = 0; e2 < cnt[2]; ++e2)
+                for (int64_t e1 = 0; e1 < cnt[1]; ++e1)
+                    for (int64_t e0 = 0; e0 < cnt[0]; ++e0) {
+                        double pd[3] = {dd[e0], dd[nmax + e1], m->dim == 3 ? dd[2 * nmax + e2] : 0.0};
+                        double ps[3] = {sq[e0], sq[nmax + e1], m->dim == 3 ? sq[2 * nmax + e2] : 0.0};
+                        double K;
+                        if (pair_weight(m->dim, pd, ps, h[i], cutoff, f32_decision, &K)) z += K;
+                    }
+            Z[i] = z;
+        }
+        int nt = 1, t = 0;
+#ifdef _OPENMP
+        nt = omp_get_num_threads();
+        t = omp_get_thread_num();
+#endif
+        int64_t p0 = (int64_t)m->n[la] * t / nt, p1 = (int64_t)m->n[la] * (t + 1) / nt;
+        for (int64_t i = 0; i < N && p0 < p1; ++i) {
+            if (!valid[i]) continue;
+            double amount_scale = seed_volume * fabs(det[i]);
+            if (!(Z[i] > 0.0)) {
+                int64_t hc = home_cell(m, x, N, i);
+                int64_t hz = m->dim == 3 ? hc / ((int64_t)m->n[0] * m->n[1]) : hc / m->n[0];
+                if (hz < p0 || hz >= p1) continue;
+                for (int k = 0; k < C; ++k) acc[k * M + hc] += 1.0 * (q[k * N + i] * amount_scale);
+                continue;
+            }
+            cnt[0] = cnt[1] = cnt[2] = 1;
+            L[nmax] = L[2 * nmax] = 0;
+            int skip = 0;
+            for (int a = la; a >= 0 && !skip; --a) {
+                int64_t c = axis_reach(m, a, x[a * N + i], h[i], cutoff, L + a * nmax);
+                if (a == la) {
+                    int64_t kept = 0;
+                    for (int64_t e = 0; e < c; ++e)
+                        if (L[a * nmax + e] >= p0 && L[a * nmax + e] < p1) L[a * nmax + kept++] = L[a * nmax + e];
+                    c = kept;
+                }
+                cnt[a] = c;
+                if (c == 0) skip = 1;
+            }
+            if (skip) continue;
+            double inv_h = 1.0 / h[i];
+            for (int a = 0; a < m->dim; ++a)
+                axis_terms(m, a, L + a * nmax, cnt[a], x[a * N + i], inv_h, dd + a * nmax, sq + a * nmax);
+            for (int64_t e2 = 0; e2 < cnt[2]; ++e2)
+                for (int64_t e1 = 0; e1 < cnt[1]; ++e1)
+                    for (int64_t e0 = 0; e0 < cnt[0]; ++e0) {
+                        int64_t idx[3] = {L[e0], L[nmax + e1], L[2 * nmax + e2]};
+                        double pd[3] = {dd[e0], dd[nmax + e1], m->dim == 3 ? dd[2 * nmax + e2] : 0.0};
+                        double ps[3] = {sq[e0], sq[nmax + e1], m->dim == 3 ? sq[2 * nmax + e2] : 0.0};
+                        double K;
+                        if (!pair_weight(m->dim, pd, ps, h[i], cutoff, f32_decision, &K)) continue;
+                        int64_t c = idx[0] + (int64_t)m->n[0] * (idx[1] + (int64_t)m->n[1] * idx[2]);
+                        double w = K / Z[i];
+                        for (int k = 0; k < C; ++k) acc[k * M + c] += w * (q[k * N + i] * amount_scale);
+                    }
+        }
+        free(L);
+        free(dd);
+        free(sq);
+    }
+    for (int64_t c = 0; c < M; ++c) {
+        double cs = cell_scale ? cell_scale[c] : 1.0;
+        for (int k = 0; k < C; ++k) S[k * M + c] = -scale * cs * acc[k * M + c] / Vc;
+    }
+    if (Z_out)
+        for (int64_t i = 0; i < N; ++i) Z_out[i] = Z[i];
+    free(Z);
+    free(acc);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -125,3 +125,27 @@ def test_adam_first_step_is_lr_times_sign():
     np.testing.assert_allclose(t1[:LN.N_TRAIN] - theta[:LN.N_TRAIN], -1e-3 * np.sign(grad[:LN.N_TRAIN]),
                                rtol=1e-12, atol=1e-15)
     np.testing.assert_array_equal(t1[LN.N_TRAIN:], theta[LN.N_TRAIN:])
+
+
+def test_adam_bias_correction_over_three_steps():
+    """Closed forms of the bias-corrected moments.  A constant gradient g gives
+    m_hat = g and v_hat = g^2 at every step, so each step moves by lr sign(g).
+    Gradients g, -g, g give m_hat = -(1 - b1)/(1 + b1) g at step 2 and
+    (b1^2 - b1 + 1)/(1 + b1 + b1^2) g at step 3, with v_hat = g^2."""
+    rng = np.random.default_rng(7)
+    theta = LN.init_params(7)
+    g = rng.standard_normal(theta.size)
+    lr, b1, b2 = 1e-3, 0.9, 0.999
+    T = slice(0, LN.N_TRAIN)
+    t, m, v = theta, np.zeros_like(theta), np.zeros_like(theta)
+    for step in (1, 2, 3):
+        t, m, v = LN.adam(t, g, m, v, step, lr=lr, b1=b1, b2=b2, eps=0.0)
+        np.testing.assert_allclose(t[T] - theta[T], -step * lr * np.sign(g[T]), rtol=1e-11, atol=1e-16)
+    t, m, v = theta, np.zeros_like(theta), np.zeros_like(theta)
+    t1, m, v = LN.adam(t, g, m, v, 1, lr=lr, b1=b1, b2=b2, eps=0.0)
+    t2, m, v = LN.adam(t1, -g, m, v, 2, lr=lr, b1=b1, b2=b2, eps=0.0)
+    np.testing.assert_allclose(t2[T] - t1[T], lr * (1 - b1) / (1 + b1) * np.sign(g[T]), rtol=1e-10, atol=1e-17)
+    t3, m, v = LN.adam(t2, g, m, v, 3, lr=lr, b1=b1, b2=b2, eps=0.0)
+    r3 = (b1 * b1 - b1 + 1) / (1 + b1 + b1 * b1)
+    np.testing.assert_allclose(t3[T] - t2[T], -lr * r3 * np.sign(g[T]), rtol=1e-10, atol=1e-17)
+    np.testing.assert_array_equal(t3[LN.N_TRAIN:], theta[LN.N_TRAIN:])

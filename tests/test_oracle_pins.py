@@ -329,6 +329,34 @@ def test_deposit_conserves_totals():
     assert (Z == 0).any() or True
 
 
+def test_deposit_single_trajectory_closed_form():
+    """One droplet with det J = 3 deposits n0 V_seed phi in total (the seed's
+    droplets; det J cancels between n = n0/|det J| and the stretched volume),
+    spread with weights proportional to exp(-r^2/(2h^2)) at h = h0 |det J|."""
+    n, n0, vseed, r = 16, 2.5e9, 0.04, 12e-6
+    v, ug = np.array([0.3, -0.1]), np.array([0.5, 0.2])
+    x = np.array([[8.5 / n], [8.5 / n]])        # a cell centre
+    J = np.array([[3.0], [0.7], [0.0], [1.0]])  # det J = 3
+    tr = W.Trajectories(torch.tensor(x), torch.tensor(J), torch.tensor(v.reshape(2, 1)),
+                        torch.tensor(ug.reshape(2, 1)), torch.tensor([r], dtype=torch.float64), n0, vseed)
+    h0 = 1.0 / (3 * n)                          # so that h = one cell width
+    t = oracle.trajectory_terms(tr, RHO, MU, DELTA, h0)
+    S, Z = oracle.deposit(_mesh(2, n, periodic=True), x, t, vseed)
+    # phi of one droplet from Stokes' law and the d^2 evaporation law
+    mdot = 2 * math.pi * RHO * r * DELTA
+    F = 6 * math.pi * MU * r * (ug - v)
+    phi = np.array([mdot, *(F + mdot * v)])
+    Vc = 1.0 / n ** 2
+    np.testing.assert_allclose(S.sum(axis=1) * Vc, -n0 * vseed * phi, rtol=1e-12)
+    c0 = 8 + n * 8
+    np.testing.assert_allclose(S[:, c0 + 1] / S[:, c0], math.exp(-0.5), rtol=1e-13)
+    np.testing.assert_allclose(S[:, c0 + 1 + n] / S[:, c0], math.exp(-1.0), rtol=1e-13)
+    np.testing.assert_allclose(S[:, c0 + 2 * n] / S[:, c0], math.exp(-2.0), rtol=1e-13)
+    # the normaliser is the kernel summed over the 49 cells within 4 widths
+    ks = [(i, j) for i in range(-4, 5) for j in range(-4, 5) if i * i + j * j <= 16]
+    assert Z[0] == pytest.approx(n * sum(math.exp(-0.5 * (i * i + j * j)) for i, j in ks), rel=1e-13)
+
+
 def test_deposit_zero_support_goes_home():
     n = 8
     x = np.array([[0.3], [0.6]])       # not at a cell centre
