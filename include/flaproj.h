@@ -135,18 +135,26 @@ typedef struct {
  * S_mass = S_Mass, S_mom[a] = component a of S_Mom (eq. coupling-terms-
  * kernel, with the minus sign of eq. coupling-terms-averaged); den
  * (nullable) receives the estimator denominator sum_i K(x_c, x_i)
- * (FLA_NW) or, for psicell_accumulate, the particle count as a real. */
+ * (FLA_NW) or, for psicell_accumulate, the particle count as a real.
+ * pairs (nullable, uint32 per cell; fla_project_sources and
+ * fla_project_batch only, ignored elsewhere) receives the number of
+ * trajectories whose kernel reaches the cell centre (the included pairs
+ * of the truncation test; in FLA_DEPOSIT a trajectory whose support holds
+ * no centre counts once at its home cell).  Asking for it costs extra
+ * ALU work in the gather. */
 typedef struct {
     void* S_mass;
     void* S_mom[3];
     void* den;
+    uint32_t* pairs;
 } fla_fields;
 
 typedef struct {
     int64_t trajectories;     /* records seen by the last call */
     int64_t skipped;          /* det J == 0 or non-finite input */
     int64_t no_support;       /* valid, but no cell of a closed box within reach */
-    int64_t pairs;            /* included pairs (only if count_pairs was set) */
+    int64_t pairs;            /* included pairs (only if count_pairs was set or a
+                                 pairs plane was given) */
     int64_t outside;          /* PSI-CELL particles outside a closed box */
     int64_t zero_support;     /* FLA_DEPOSIT: trajectories with Z_i = 0 */
     int64_t max_class;        /* largest neighbourhood class used by the gather */

@@ -46,7 +46,7 @@ class fla_params(C.Structure):
 
 
 class fla_fields(C.Structure):
-    _fields_ = [("S_mass", C.c_void_p), ("S_mom", C.c_void_p * 3), ("den", C.c_void_p)]
+    _fields_ = [("S_mass", C.c_void_p), ("S_mom", C.c_void_p * 3), ("den", C.c_void_p), ("pairs", C.c_void_p)]
 
 
 class fla_stats(C.Structure):
@@ -222,12 +222,14 @@ def make_trajectories(x, J, v, ug, r, n0=1.0, seed_volume: float = 0.0) -> tuple
     return tr, keep
 
 
-def make_fields(S_mass, S_mom: Sequence, den=None) -> fla_fields:
+def make_fields(S_mass, S_mom: Sequence, den=None, pairs=None) -> fla_fields:
+    """pairs: optional int32 device tensor (read as uint32 per cell)."""
     f = fla_fields()
     f.S_mass = _ptr(S_mass)
     for a, t in enumerate(S_mom):
         f.S_mom[a] = _ptr(t)
     f.den = _ptr(den)
+    f.pairs = _ptr(pairs)
     return f
 
 
@@ -283,8 +285,8 @@ class Context:
 
     # -- tensor-level helpers ------------------------------------------------------------
     def project_sources(self, mesh: fla_mesh, traj: fla_trajectories, params: Params, S_mass, S_mom,
-                        den=None, stream=None):
-        st = self.project_sources_raw(mesh, traj, params.to_c(), make_fields(S_mass, S_mom, den), stream)
+                        den=None, stream=None, pairs=None):
+        st = self.project_sources_raw(mesh, traj, params.to_c(), make_fields(S_mass, S_mom, den, pairs), stream)
         self._check(st)
 
     def psicell_accumulate(self, mesh: fla_mesh, particles: fla_trajectories, weight: float,
@@ -362,7 +364,8 @@ class Context:
         M = (fla_mesh * n)(*meshes)
         T = (fla_trajectories * n)(*trajs)
         P = (fla_params * n)(*[p.to_c() if isinstance(p, Params) else p for p in params])
-        F = (fla_fields * n)(*[o if isinstance(o, fla_fields) else make_fields(o[0], o[1], o[2] if len(o) > 2 else None)
+        F = (fla_fields * n)(*[o if isinstance(o, fla_fields) else
+                               make_fields(o[0], o[1], o[2] if len(o) > 2 else None, o[3] if len(o) > 3 else None)
                                for o in outs])
         return n, M, T, P, F
 

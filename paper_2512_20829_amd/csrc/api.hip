@@ -229,6 +229,7 @@ fla_status zero_outputs(fla_ctx* ctx, const MeshDev& m, const fla_fields* out, h
     HIP_OK(launch_fill_real<R>((R*)out->S_mass, m.M, s));
     for (int a = 0; a < m.dim; ++a) HIP_OK(launch_fill_real<R>((R*)out->S_mom[a], m.M, s));
     if (out->den) HIP_OK(launch_fill_real<R>((R*)out->den, m.M, s));
+    if (out->pairs) HIP_OK(launch_fill_u32(out->pairs, m.M, 0u, s));
     return FLA_OK;
 }
 
@@ -320,6 +321,7 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
     g.out[0] = out->S_mass;
     for (int a = 0; a < D; ++a) g.out[1 + a] = out->S_mom[a];
     g.den = out->den;
+    g.pairs = out->pairs;
     g.stats = ctx->stats;
     g.tile_cost = tcost;
     g.order = order;
@@ -327,7 +329,8 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
         StageTimer tm(ctx, 3, s);
         int plan = ctx->plan[D - 2][sizeof(R) == 8 ? 1 : 0];
         if (plan < 0) plan = kDefaultPlan;
-        HIP_OK((launch_gather<R, D>(g, p->mode, p->count_pairs != 0, plan, s)));
+        if (out->pairs) HIP_OK(launch_fill_u32(out->pairs, m.M, 0u, s));
+        HIP_OK((launch_gather<R, D>(g, p->mode, p->count_pairs != 0 || out->pairs != nullptr, plan, s)));
     }
     return FLA_OK;
 }
@@ -380,7 +383,7 @@ fla_status batch_impl(fla_ctx* ctx, int nsnap, const MeshDev* md, const TrajDev*
         total += td[i].count;
         nbk += (int64_t)kClasses * md[i].ntiles;
         nwork += md[i].ntiles;
-        count = count || ps[i].count_pairs != 0;
+        count = count || ps[i].count_pairs != 0 || outs[i].pairs != nullptr;
         CHECK_ARG(total < (int64_t(1) << 31), "the batch holds 2^31 or more trajectories");
         CHECK_ARG(nbk < (int64_t(1) << 31) - 1, "the batch meshes hold too many tiles");
     }
@@ -430,6 +433,7 @@ fla_status batch_impl(fla_ctx* ctx, int nsnap, const MeshDev* md, const TrajDev*
         g.out[0] = outs[i].S_mass;
         for (int a = 0; a < D; ++a) g.out[1 + a] = outs[i].S_mom[a];
         g.den = outs[i].den;
+        g.pairs = outs[i].pairs;
         g.stats = ctx->stats;
     }
 
@@ -492,6 +496,8 @@ fla_status batch_impl(fla_ctx* ctx, int nsnap, const MeshDev* md, const TrajDev*
             HIP_OK(launch_max_class_batch(dev_items, nsnap, bstart, ctx->stats, q));
             HIP_OK(launch_permute<R>(svals, total, rpos_u, rw_u, rpos, rw, 1, q));
         }
+        for (int i = 0; i < nsnap; ++i)
+            if (outs[i].pairs) HIP_OK(launch_fill_u32(outs[i].pairs, md[i].M, 0u, q));
         {
             StageTimer tm(ctx, 3, q);
             HIP_OK((launch_gather_batch<R, D>(dev_items, nsnap, (int)nwork, chunk, count, plan, q)));

@@ -437,7 +437,10 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
             lo[b][k] = 0;
         }
     }
-    unsigned long long npairs = 0;
+    // included pairs per sub-block of this lane (counted calls only)
+    uint32_t cntb[NSB];
+#pragma unroll
+    for (int b = 0; b < NSB; ++b) cntb[b] = 0;
     const uint64_t ltmask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     __syncthreads();
 
@@ -495,7 +498,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
 #pragma unroll
                 for (int k = 0; k < NA; ++k) part[b][k] = fma(ew, wv[k], part[b][k]);
             }
-            if (COUNT) npairs += (in && live) ? 1ull : 0ull;
+            if (COUNT) cntb[b] += (in && live) ? 1u : 0u;
         };
         // x split, sub-block b = by + 2 bz: the pair (by, 0), (by, 1) shares
         // s_x + s_y and e_x e_y
@@ -515,7 +518,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
 #pragma unroll
                 for (int k = 0; k < NA; ++k) part[b][k] = fma(ew, wv[k], part[b][k]);
             }
-            if (COUNT) npairs += (in && live) ? 1ull : 0ull;
+            if (COUNT) cntb[b] += (in && live) ? 1u : 0u;
         };
         // PLAN sets the granularity of the wave-uniform skips of a record that
         // reaches the workgroup's part: 0 one branch per sub-block, 1 per
@@ -731,8 +734,8 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
             red[((wave * NSB + b) * NA + k) * kWave + lane] = kComp ? hi[b][k] + lo[b][k] : part[b][k];
     __syncthreads();
 
-    // ---- epilogue: divide (NW) or scale by 1/V_c (deposition), sign, scale
-    for (int b = wave; b < NSB; b += kGatherWaves) {
+    // linear index of the lane's cell in sub-block b; false beyond the mesh
+    auto cell_of = [&](int b, int64_t& lin) {
         int64_t cidx[3] = {0, 0, 0};
         bool inside = true;
 #pragma unroll
@@ -745,7 +748,14 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
             cidx[a] = (int64_t)tc[a] * TE + half + lc[a];
             inside = inside && cidx[a] < m.n[a];
         }
-        if (!inside) continue;
+        lin = cidx[0] + (int64_t)m.n[0] * (cidx[1] + (int64_t)m.n[1] * cidx[2]);
+        return inside;
+    };
+
+    // ---- epilogue: divide (NW) or scale by 1/V_c (deposition), sign, scale
+    for (int b = wave; b < NSB; b += kGatherWaves) {
+        int64_t lin;
+        if (!cell_of(b, lin)) continue;
         double tot[NA];
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
@@ -753,7 +763,6 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
             for (int v = 0; v < kGatherWaves; ++v) acc += (double)red[((v * NSB + b) * NA + k) * kWave + lane];
             tot[k] = acc;
         }
-        int64_t lin = cidx[0] + (int64_t)m.n[0] * (cidx[1] + (int64_t)m.n[1] * cidx[2]);
         double den = tot[0];
         double cs = g.cell_scale ? (double)((const R*)g.cell_scale)[lin] : 1.0;
         double f = -g.scale * cs;
@@ -769,6 +778,16 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
         if (g.den) ((R*)g.den)[lin] = (R)den;
     }
     if (COUNT) {
+        // every wave holds counts for all of the workgroup's cells (the
+        // waves split the candidates, not the cells); integer sums do not
+        // depend on the order of the atomic additions
+        unsigned long long npairs = 0;
+#pragma unroll
+        for (int b = 0; b < NSB; ++b) {
+            npairs += cntb[b];
+            int64_t lin;
+            if (g.pairs && cntb[b] && cell_of(b, lin)) atomicAdd(&g.pairs[lin], cntb[b]);
+        }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) npairs += __shfl_xor(npairs, o, kWave);
         if (lane == 0 && npairs) atomicAdd(&g.stats[ST_PAIRS], npairs);

@@ -17,6 +17,7 @@ struct GatherArgs {
     const void* cell_scale;
     void* out[4];
     void* den;
+    uint32_t* pairs;            // nullable per-cell included-pair counts (zeroed by the caller)
     unsigned long long* stats;
     // optional (both set or both null): workspace for the work order of the
     // single-snapshot gather, ntiles cost words and 2 * ntiles slot entries

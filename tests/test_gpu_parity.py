@@ -29,12 +29,13 @@ def _check(ctx, wl, prec=None, **kw):
     prec = prec or wl.precision
     print(f"[case] {wl.name} prec={prec} N={wl.traj.count} mesh={wl.mesh.n} periodic={wl.mesh.periodic}",
           flush=True)
-    S, den, st = gpu_run(ctx, wl, prec=prec, **kw)
+    S, den, st = gpu_run(ctx, wl, prec=prec, cell_pairs=True, **kw)
     okw = {k: v for k, v in kw.items() if k in ("scale", "cell_scale", "h_factor")}
     ref, terms = oracle_run(wl, prec=prec, **okw)
     assert_fields_close(S, ref.S, TOL[prec], wl.name)
     assert rel_l2(den, ref.den) <= TOL[prec]
     assert st["pairs"] == int(ref.pairs.sum())
+    np.testing.assert_array_equal(st["cell_pairs"], ref.pairs)
     assert st["skipped"] == terms.skipped
     assert st["trajectories"] == wl.traj.count
     return S, den, st, ref
@@ -119,39 +120,63 @@ def test_bitwise_deterministic(ctx):
     assert np.array_equal(S1, S2) and np.array_equal(d1, d2)
 
 
-def test_abc_full_size_sampled_cells(ctx):
+def test_abc_full_size_whole_field(ctx):
     """The 128^3 / 2M-trajectory ABC case in the launch configuration the
-    benchmark times, checked on 256 sampled cells computed one by one by the
-    oracle over all trajectories."""
+    benchmark times, on every one of its 2,097,152 cells against the
+    trajectory-centric oracle: per-field relative L2 and per-cell errors
+    within 1e-5, and the included pairs of every cell exactly."""
     wl = W.abc_lattice_3d()
-    S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False)
-    g = np.random.default_rng(0)
-    cells = np.sort(g.choice(wl.mesh.cells, 256, replace=False))
+    S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False, cell_pairs=True)
     oracle.set_threads(16)
-    ref, _ = oracle_run(wl, prec="f32", cells=cells)
-    assert_fields_close(S[:, cells], ref.S, TOL["f32"], "abc 128^3 sampled")
-    assert rel_l2(den[cells], ref.den) <= TOL["f32"]
-    assert st["skipped"] == 0
+    tr = as_precision(wl.traj, "f32")
+    ref, terms = oracle.project_box(wl.mesh, tr, wl.rho_d, wl.mu, wl.delta, wl.h0, cutoff=wl.cutoff,
+                                    f32_decision=True)
+    np.testing.assert_array_equal(ref.cells, np.arange(wl.mesh.cells))
+    assert_fields_close(S, ref.S, TOL["f32"], "abc 128^3 whole field")
+    assert rel_l2(den, ref.den) <= TOL["f32"]
+    np.testing.assert_array_equal(st["cell_pairs"], ref.pairs)
+    assert st["pairs"] == int(ref.pairs.sum()) and st["skipped"] == 0
+
+
+def test_abc_full_size_against_binary64_decisions(ctx):
+    """The binary32 path against the pure binary64 definition (inclusion
+    decided in binary64 too) on 16 planes of the 128^3 case: the boundary
+    pairs that binary32 rounding flips change the fields by far less than
+    the 1e-5 bar."""
+    wl = W.abc_lattice_3d()
+    S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False, cell_pairs=True)
+    oracle.set_threads(16)
+    tr = as_precision(wl.traj, "f32")
+    ref, _ = oracle.project_box(wl.mesh, tr, wl.rho_d, wl.mu, wl.delta, wl.h0, cutoff=wl.cutoff,
+                                f32_decision=False, box_lo=[0, 0, 56], box_n=[128, 128, 16])
+    flips = int(np.abs(st["cell_pairs"][ref.cells] - ref.pairs).sum())
+    errs = [rel_l2(S[k, ref.cells], ref.S[k]) for k in range(4)]
+    print(f"[f64-decision] rel L2 {' '.join(f'{e:.2e}' for e in errs)}; pair-count differences {flips} "
+          f"of {int(ref.pairs.sum())}", flush=True)
+    assert_fields_close(S[:, ref.cells], ref.S, TOL["f32"], "abc 128^3 vs binary64 decisions")
 
 
 @pytest.mark.slow
 @pytest.mark.timeout(400)
-def test_multi_vortex_full_size_sampled_cells(ctx):
+def test_multi_vortex_full_size_wrapped_block(ctx):
     """The 256^3 / 32.8M-trajectory multi-vortex case (|det J| down to ~1e-8,
-    sign changes) in the benchmark's launch configuration, checked on 256
-    sampled cells computed one by one by the oracle over all trajectories."""
+    sign changes) in the benchmark's launch configuration, on a whole 32^3
+    block of cells that straddles the periodic boundary on every axis,
+    against the trajectory-centric oracle over all trajectories."""
     dev = torch.device("cuda", 0)
     wl = W.multi_vortex_lattice_3d(device=dev)
     wl.traj = wl.traj.to("cpu")
     print(f"[case] c5 N={wl.traj.count} mesh={wl.mesh.n}", flush=True)
-    S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False)
+    S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False, cell_pairs=True)
     assert np.isfinite(S).all()
-    g = np.random.default_rng(1)
-    cells = np.sort(g.choice(wl.mesh.cells, 256, replace=False))
     oracle.set_threads(16)
-    ref, terms = oracle_run(wl, prec="f32", cells=cells)
-    assert_fields_close(S[:, cells], ref.S, TOL["f32"], "multi-vortex sampled")
-    assert rel_l2(den[cells], ref.den) <= TOL["f32"]
+    tr = as_precision(wl.traj, "f32")
+    ref, terms = oracle.project_box(wl.mesh, tr, wl.rho_d, wl.mu, wl.delta, wl.h0, cutoff=wl.cutoff,
+                                    f32_decision=True, box_lo=[240, 244, 248], box_n=[32, 32, 32])
+    assert (ref.cells % 256 < 16).any() and (ref.cells % 256 >= 240).any()
+    assert_fields_close(S[:, ref.cells], ref.S, TOL["f32"], "multi-vortex wrapped 32^3 block")
+    assert rel_l2(den[ref.cells], ref.den) <= TOL["f32"]
+    np.testing.assert_array_equal(st["cell_pairs"][ref.cells], ref.pairs)
     assert st["skipped"] == terms.skipped
     assert st["max_class"] == 7          # the widest bandwidths span whole axes
 
