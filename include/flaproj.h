@@ -185,6 +185,26 @@ fla_status fla_ctx_destroy(fla_ctx* ctx);
 fla_status fla_project_sources(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
                                const fla_params* params, const fla_fields* out, void* stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results (bit for bit, under the same gather plan) and errors as
+ * fla_project_sources, but the workspace is a fixed device array of
+ * FLA_NOALLOC_SCRATCH_BYTES compiled into the library instead of the
+ * context's grow-only workspace, so the call allocates nothing (no device
+ * memory, no events; profiling does not record it).  Each GPU holds its own
+ * copy of the array from the creation of the first context on it until the
+ * process ends.  Inputs whose workspace would not fit (144 B per binary32
+ * trajectory and 208 B per binary64 one, 8 B per channel more in
+ * FLA_DEPOSIT, plus about 44 B per tile of 8^3 or 16^2 cells) return
+ * FLA_ERR_INVALID_ARG with the size they need; nothing is written then.
+ * Every call on one GPU, from any context or thread, shares that GPU's
+ * array and its contents: calls that overlap in time on one GPU race, so
+ * the caller orders them (one stream, or events).  FLA_ERR_UNSUPPORTED if
+ * the context's device has no such array (device index >= 64). */
+#define FLA_NOALLOC_SCRATCH_BYTES (64u << 20)
+fla_status fla_project_sources_noalloc(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                                       const fla_params* params, const fla_fields* out, void* stream);
+
 /* PSI-CELL box counting (paper: eqs. vol-avg-discrete and coupling-terms-
  * definition): every particle p with finite inputs is assigned the cell
  * floor((x_p - lo)/dx) per axis (periodic axes wrap; on a closed axis

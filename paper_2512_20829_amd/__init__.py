@@ -76,6 +76,10 @@ _lib.fla_ctx_destroy.argtypes = [_vp]
 _lib.fla_project_sources.restype = C.c_int
 _lib.fla_project_sources.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories),
                                      C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
+_lib.fla_project_sources_noalloc.restype = C.c_int
+_lib.fla_project_sources_noalloc.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories),
+                                             C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
+NOALLOC_SCRATCH_BYTES = 64 << 20
 _lib.psicell_accumulate.restype = C.c_int
 _lib.psicell_accumulate.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories), C.c_double,
                                     C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
@@ -287,6 +291,14 @@ class Context:
     def project_sources(self, mesh: fla_mesh, traj: fla_trajectories, params: Params, S_mass, S_mom,
                         den=None, stream=None, pairs=None):
         st = self.project_sources_raw(mesh, traj, params.to_c(), make_fields(S_mass, S_mom, den, pairs), stream)
+        self._check(st)
+
+    def project_sources_noalloc(self, mesh: fla_mesh, traj: fla_trajectories, params: Params, S_mass, S_mom,
+                                den=None, stream=None, pairs=None):
+        """fla_project_sources on the library's fixed workspace (no allocation)."""
+        st = _lib.fla_project_sources_noalloc(self._h, C.byref(mesh), C.byref(traj), C.byref(params.to_c()),
+                                              C.byref(make_fields(S_mass, S_mom, den, pairs)),
+                                              _stream_handle(stream))
         self._check(st)
 
     def psicell_accumulate(self, mesh: fla_mesh, particles: fla_trajectories, weight: float,

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -46,6 +47,16 @@ struct fla_ctx {
 };
 
 static thread_local std::string g_create_error;
+
+// Workspace of fla_project_sources_noalloc: a fixed array in the code object,
+// one copy per GPU, held until the process ends.  Host code never uses the
+// name `scratch` as an address (on the host it is only a stand-in for the
+// symbol): the device address of each GPU's copy is looked up once, with that
+// GPU current, when the first context on it is created, and kept here.
+static __device__ __align__(256) unsigned char scratch[FLA_NOALLOC_SCRATCH_BYTES];
+static constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices] = {};
 
 // gather plan used until fla_set_plan or fla_autotune chooses one: skips at
 // the granularity of sub-block pairs, the fastest plan on the 128^3 ABC case
@@ -240,9 +251,12 @@ int bits_for(uint64_t maxval)
     return b;
 }
 
+// fixed: a caller-provided workspace of fixed_size bytes (the allocation-free
+// entry point) instead of the context's grow-only one
 template <typename R, int D>
 fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const fla_params* p,
-                        const fla_mesh* mesh, const fla_fields* out, hipStream_t s)
+                        const fla_mesh* mesh, const fla_fields* out, hipStream_t s, void* fixed = nullptr,
+                        size_t fixed_size = 0)
 {
     const int64_t N = t.count;
     const int deposit = p->mode == FLA_DEPOSIT;
@@ -279,10 +293,17 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
         Carver probe(nullptr);
         layout(probe, &keys, &vals, &keys2, &vals2, &rpos_u, &rpos, &rw_u, &rw, &qd, &bstart, &hist, &scan, &tcost,
                &order);
-        fla_status st = ensure_ws(ctx, probe.off + 256);
-        if (st != FLA_OK) return st;
+        if (fixed) {
+            CHECK_ARG(probe.off + 256 <= fixed_size,
+                      "these inputs need " + std::to_string(probe.off + 256) +
+                          " bytes of workspace, more than the fixed " + std::to_string(fixed_size) +
+                          " bytes of fla_project_sources_noalloc");
+        } else {
+            fla_status st = ensure_ws(ctx, probe.off + 256);
+            if (st != FLA_OK) return st;
+        }
     }
-    Carver c(ctx->ws);
+    Carver c(fixed ? fixed : ctx->ws);
     layout(c, &keys, &vals, &keys2, &vals2, &rpos_u, &rpos, &rw_u, &rw, &qd, &bstart, &hist, &scan, &tcost, &order);
 
     PhysDev ph{p->rho_d, p->mu, p->delta, p->h0, p->cutoff, p->scale};
@@ -732,6 +753,9 @@ fla_status batch_entry(fla_ctx* ctx, int nsnap, const fla_mesh* meshes, const fl
 }  // namespace
 
 static void drop_records(fla_ctx* ctx);
+static fla_status project_entry(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                                const fla_params* params, const fla_fields* out, void* stream, void* fixed,
+                                size_t fixed_size);
 
 extern "C" {
 
@@ -760,6 +784,15 @@ FLA_EXPORT fla_status fla_ctx_create(fla_ctx** out, int device)
     }
     ctx->device = device;
     e = hipSetDevice(device);
+    if (e == hipSuccess && device < kMaxScratchDevices) {
+        // device address of this GPU's copy of the fixed workspace (once per GPU)
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void* ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e == hipSuccess && ptr) g_scratch_ptr[device] = ptr;
+        }
+    }
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->stats, sizeof(unsigned long long) * ST_N);
     if (e == hipSuccess) e = hipMemset(ctx->stats, 0, sizeof(unsigned long long) * ST_N);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -792,6 +825,37 @@ FLA_EXPORT fla_status fla_ctx_destroy(fla_ctx* ctx)
 FLA_EXPORT fla_status fla_project_sources(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
                                const fla_params* params, const fla_fields* out, void* stream)
 {
+    return project_entry(ctx, mesh, traj, params, out, stream, nullptr, 0);
+}
+
+FLA_EXPORT fla_status fla_project_sources_noalloc(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                                                  const fla_params* params, const fla_fields* out, void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    void* ptr = nullptr;
+    if (ctx->device >= 0 && ctx->device < kMaxScratchDevices) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        ptr = g_scratch_ptr[ctx->device];
+    }
+    if (!ptr) {
+        ctx->err = "fla_project_sources_noalloc: no fixed workspace on this device";
+        return FLA_ERR_UNSUPPORTED;
+    }
+    // no profiling events here: creating them is an allocation
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    const fla_status st = project_entry(ctx, mesh, traj, params, out, stream, ptr, FLA_NOALLOC_SCRATCH_BYTES);
+    ctx->prof = prof;
+    return st;
+}
+
+}  // extern "C"
+
+static fla_status project_entry(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                                const fla_params* params, const fla_fields* out, void* stream, void* fixed,
+                                size_t fixed_size)
+{
     if (!ctx) return FLA_ERR_INVALID_ARG;
     ctx->err.clear();
     try {
@@ -816,15 +880,17 @@ FLA_EXPORT fla_status fla_project_sources(fla_ctx* ctx, const fla_mesh* mesh, co
             return f64 ? zero_outputs<double>(ctx, m, out, s) : zero_outputs<float>(ctx, m, out, s);
         }
         if (m.dim == 2)
-            return f64 ? project_impl<double, 2>(ctx, m, t, params, mesh, out, s)
-                       : project_impl<float, 2>(ctx, m, t, params, mesh, out, s);
-        return f64 ? project_impl<double, 3>(ctx, m, t, params, mesh, out, s)
-                   : project_impl<float, 3>(ctx, m, t, params, mesh, out, s);
+            return f64 ? project_impl<double, 2>(ctx, m, t, params, mesh, out, s, fixed, fixed_size)
+                       : project_impl<float, 2>(ctx, m, t, params, mesh, out, s, fixed, fixed_size);
+        return f64 ? project_impl<double, 3>(ctx, m, t, params, mesh, out, s, fixed, fixed_size)
+                   : project_impl<float, 3>(ctx, m, t, params, mesh, out, s, fixed, fixed_size);
     } catch (...) {
         ctx->err = "internal error";
         return FLA_ERR_DEVICE;
     }
 }
+
+extern "C" {
 
 FLA_EXPORT fla_status psicell_accumulate(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* particles,
                               double particle_weight, const fla_params* params, const fla_fields* out,
