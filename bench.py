@@ -1,33 +1,43 @@
 #!/usr/bin/env python3
 """Benchmark of the FLA source projection on one MI355X.
 
-Workload: the 3-D ABC-map case -- 128^3 periodic mesh on the unit cube,
-2,097,152 lattice trajectories deformed by an ABC map of amplitude 0.2 (with
-folds), radius lognormal(ln 10 um, 0.3), h0 = 1/128, cutoff 4 bandwidths,
-binary32 kernel evaluation with binary64 det J.  Inputs are synthetic and
-generated on the GPU before timing; they are resident in HBM when the timed
-region starts.
+Headline workload: the 3-D multi-vortex case -- 256^3 periodic mesh on the
+unit cube, 320^3 = 32,768,000 lattice trajectories through the composition of
+two ABC maps (folds, |det J| down to ~1e-8), radius lognormal(ln 10 um, 0.3),
+h0 = 1/320, cutoff 4 bandwidths, binary32 kernel evaluation with binary64
+det J.  Inputs are synthetic, generated on the GPU before timing, and
+resident in HBM when the timed region starts.
 
 One step = one fla_project_sources call: prepass (det J, n, h, physics,
 keys), key sort and bucket bounds, record permutation, and the gather with
 its fused epilogue.  Printed as one JSON line (rank 0):
-  value        mesh cells per second (M / step time)
+  value        mesh cells per second of the headline workload (M / step time)
   pairs_per_s  included trajectory-cell pairs per second
-  roofline     the gather kernel, timed with HIP events on the library's
-               stream: algorithmic flops per launch / average launch time
-  large        the 256^3 multi-vortex case (32.8M trajectories, caustics):
-               plain and learned throughput, plain / learned / deposition
-               errors against a 1.68G-particle PSI-CELL reference
-  cpu_baseline the FP64 oracle on a bounded sample of the same workload
+  roofline     the gather kernel of the headline workload, timed with HIP
+               events on the library's stream: algorithmic flops per launch
+               (15 per included pair) / average launch time, against the
+               157.3 TFLOP/s binary32 vector peak
+  cpu_baseline the FP64 oracle (trajectory-centric form) on a bounded sample
+               of the headline workload, with whole-field and one-thread
+               times of the 128^3 and 2-D cases beside it
+  abc128       the 128^3 ABC case (2,097,152 lattice trajectories) with its
+               own roofline
+  tg2d_f64     the 2-D Taylor-Green case in binary64 (64^2 mesh, 4096
+               trajectories) against the binary64 vector peak
   batch        64 uneven snapshots (32^3..128^3 meshes, 10k..2M trajectories)
                through fla_project_batch: graph replays, direct launches and
                one single call per snapshot, after the batch autotuner
-  psicell      PSI-CELL accumulation of a 200M-particle cloud (context)
+  psicell      PSI-CELL accumulation of a 200M-particle cloud on 128^3
   learned_vs_plain  the learned bandwidth network trained on 500 generated
                64^3 snapshots (200k trajectories, 50M-particle PSI-CELL each),
-               then plain, learned and deposition errors on the 128^3 case at
-               2M..125k lattice trajectories against the 200M-particle
-               reference, and cells/s of both forms
+               then plain, learned and deposition errors on the 128^3 case
+               from 2M down to 32k lattice trajectories against the
+               200M-particle reference, the interpolated seeding at which the
+               learned form matches the plain form's error at 2M, and the
+               cells/s of both forms there
+  large        errors of the plain, learned and deposition forms on the
+               headline workload against a 1.68G-particle PSI-CELL reference,
+               and the learned form's throughput
 """
 import argparse
 import json
@@ -41,15 +51,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "mesh cells/s + traj-cell pairs/s; learned vs plain form at fixed rel L2 error"
-# Algorithmic work of one included (cell, trajectory) pair in 3-D with C = 4
-# channels, evaluated directly from the kernel and estimator definitions:
-# 3 offsets, |d|^2 (3 mul + 2 add), scaling by 1/(2h^2) (1), exp (1), the
-# denominator add (1) and 4 numerator multiply-adds (8) = 19 flops.
-FLOPS_PER_PAIR_3D = 19
-# Non-packed fp32 vector peak: 256 CUs x 64 lanes x 2.4 GHz x 2 flops/FMA.
-# The library is compiled with packed fp32 instructions disabled, so the
-# packed figure (157.3 TFLOP/s) is out of reach by construction.
-ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 * 2 / 1e12
+# Algorithmic work of one included (cell, trajectory) pair, from the kernel
+# and estimator definitions: in 3-D with C = 4 channels, 3 offsets, 3 squares
+# and 2 additions for |d|^2, the scaling by 1/(2h^2), the denominator addition
+# and 4 numerator multiply-adds (14), plus the exponential (1) = 15; in 2-D
+# with C = 3 channels, 2 + 2 + 1 + 1 + 1 + 3 = 10, plus the exponential = 11.
+FLOPS_PER_PAIR = {3: 15, 2: 11}
+# MI355X published vector peaks (256 CUs at 2.4 GHz): binary32 157.3 TFLOP/s
+# (packed), 78.6 without packed instructions; binary64 78.6 TFLOP/s.
+FP32_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_TFLOPS = 78.6
+FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
@@ -57,11 +69,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def gather_traffic():
-    """HBM bytes per gather launch from the committed counter summary, or None
-    when the gather source changed since the counters were taken."""
+def gather_traffic(workload: str):
+    """HBM bytes per gather launch on a workload from the committed counter
+    summary profiles/gather_<workload>_hbm_traffic.md, or None when the gather
+    source changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "gather_abc128_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"gather_{workload}_hbm_traffic.md")
     src = os.path.join(ROOT, "paper_2512_20829_amd", "csrc", "gather.hip")
     if not os.path.exists(path):
         return None
@@ -77,6 +90,55 @@ def gather_traffic():
         return float(vals["bytes per launch (calibrated)"])
     except (KeyError, ValueError):
         return None
+
+
+def timed_projection(ctx, F, mesh, st, params, steps, warmup):
+    """Counted call (pairs), warm-up, then `steps` timed calls bracketed by
+    synchronisations.  Returns (ms per step from events around the loop,
+    per-stage ms per launch from the library's HIP events on the same
+    stream, the average gather launch in ms, stats of the counted call)."""
+    import torch
+    counted = F.Params(**{**params.__dict__, "count_pairs": True})
+    M = int(mesh.n[0]) * int(mesh.n[1]) * (int(mesh.n[2]) if mesh.dim == 3 else 1)
+    dt = torch.float64 if st.prec == F.FLA_F64 else torch.float32
+    S_mass, S_mom, _ = F.alloc_fields(M, mesh.dim, dt, torch.device("cuda", 0), den=False)
+    ctx.project_sources(mesh, st, counted, S_mass, S_mom)
+    torch.cuda.synchronize()
+    stats = ctx.stats()
+    for _ in range(warmup):
+        ctx.project_sources(mesh, st, params, S_mass, S_mom)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        ctx.project_sources(mesh, st, params, S_mass, S_mom)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    g_ms = prof["gather"][0] / max(prof["gather"][1], 1)
+    stages = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1]}
+    return ms_step, stages, g_ms, stats
+
+
+def gather_roofline(pairs, g_ms, dim, prec, workload):
+    """Roofline object of the gather: ALU-bound; 15 (3-D) or 11 (2-D) flops
+    per included pair over the average launch time, against the vector peak
+    of the call's precision."""
+    fpp = FLOPS_PER_PAIR[dim]
+    achieved = pairs * fpp / (g_ms * 1e-3) / 1e12
+    peak = FP64_PEAK_TFLOPS if prec == "f64" else FP32_PEAK_TFLOPS
+    r = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+         "frac": round(achieved / peak, 4), "traffic": gather_traffic(workload),
+         "kernel": f"k_gather<{'double' if prec == 'f64' else 'float'},{dim},NW>", "launch_ms": round(g_ms, 4),
+         "flops_per_pair": fpp, "pairs_per_launch": pairs}
+    if prec == "f32":
+        r["frac_of_nonpacked_78.6"] = round(achieved / FP32_NONPACKED_TFLOPS, 4)
+    return r
 
 
 def _psicell_reference(ctx, F, W, torch, mesh, abc, n_particles, seed, params, dev):
@@ -124,12 +186,28 @@ def _psicell_reference_chunked(ctx, F, torch, mesh, cloud_fn, n_particles, chunk
     return ref, floor
 
 
+def learned_crossing(rows, target):
+    """Seeding at which the learned form's error equals `target`: linear in
+    log N between the two sweep points (rows in descending N) that bracket
+    it.  Returns (N or None, note)."""
+    for a, b in zip(rows, rows[1:]):
+        if "learned" in a and "learned" in b and a["learned"] <= target < b["learned"]:
+            la, lb = math.log(a["trajectories"]), math.log(b["trajectories"])
+            t = (target - b["learned"]) / (a["learned"] - b["learned"])
+            return int(round(math.exp(lb + t * (la - lb)))), None
+    if rows and "learned" in rows[-1] and rows[-1]["learned"] <= target:
+        return None, (f"the learned error is within the target down to the smallest seeding tried, "
+                      f"{rows[-1]['trajectories']} (an upper bound on the crossing)")
+    return None, "the learned form does not reach the target within the sweep"
+
+
 def large_section(ctx, args, dev, model):
-    """The 256^3 multi-vortex case with strong caustics: 32.8M lattice
-    trajectories (320^3), plain throughput, and the plain, learned (the
-    network trained on the 64^3 ABC snapshots, if available) and deposition
-    errors against a chunked PSI-CELL reference, at 320^3, 256^3 and 200^3
-    trajectories."""
+    """The 256^3 multi-vortex case with strong caustics: the plain, learned
+    (the network trained on the 64^3 ABC snapshots, if available) and
+    deposition errors against a chunked PSI-CELL reference at 320^3 down to
+    100^3 lattice trajectories, the seeding at which the learned
+    form matches the plain form's error at 320^3, and the learned form's
+    throughput at 320^3 (the plain form's is the headline line)."""
     import numpy as np
     import torch
 
@@ -147,7 +225,7 @@ def large_section(ctx, args, dev, model):
         f"noise floor {[round(math.sqrt(f), 4) for f in floor]}")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     rows, perf = [], None
-    for pa in (320, 256, 200):
+    for pa in (320, 256, 200, 160, 128, 100):
         wl = W.multi_vortex_lattice_3d(per_axis=pa, mesh_n=256, device=dev)
         tr = wl.traj
         st, keep = F.make_trajectories(tr.x, tr.J, tr.v.float(), tr.ug.float(), tr.r.float(), tr.n0, tr.seed_volume)
@@ -158,28 +236,20 @@ def large_section(ctx, args, dev, model):
         M = wl.mesh.cells
         Sm, Sv, den = F.alloc_fields(M, 3, torch.float32, dev)
         out = {"trajectories": pa ** 3}
-        if pa == 320:
-            counted = F.Params(**{**prm.__dict__, "count_pairs": True})
-            ctx.project_sources(F.mesh_of(wl.mesh), st, counted, Sm, Sv, den)
-            torch.cuda.synchronize()
-            stt = ctx.stats()
+        if pa == 320 and model is not None:
+            # the plain form is the headline line; the learned form includes
+            # the feature and network kernels
             reps = 3
-            forms = [("plain", None)] + ([("learned", model)] if model is not None else [])
-            perf = {"pairs": stt["pairs"], "skipped": stt["skipped"], "no_support": stt["no_support"],
-                    "max_class": stt["max_class"]}
-            for name, mdl in forms:
-                ctx.project_sources(F.mesh_of(wl.mesh), st, prm, Sm, Sv)
-                torch.cuda.synchronize()
-                e0.record()
-                for _ in range(reps):
-                    h = mdl.factors(snap)[0] if mdl is not None else None
-                    ctx.project_sources(F.mesh_of(wl.mesh), st, F.Params(**{**prm.__dict__, "h_factor": h}), Sm, Sv)
-                e1.record()
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / reps
-                perf[f"ms_{name}"] = round(ms, 3)
-                perf[f"cells_per_s_{name}"] = M / (ms * 1e-3)
-            perf["pairs_per_s_plain"] = stt["pairs"] / (perf["ms_plain"] * 1e-3)
+            ctx.project_sources(F.mesh_of(wl.mesh), st, prm, Sm, Sv)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                h = model.factors(snap)[0]
+                ctx.project_sources(F.mesh_of(wl.mesh), st, F.Params(**{**prm.__dict__, "h_factor": h}), Sm, Sv)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            perf = {"ms_learned": round(ms, 3), "cells_per_s_learned": M / (ms * 1e-3)}
         helper = model if model is not None else T.BandwidthModel(ctx, T.initial_theta(0))
         forms = [("plain", None, F.FLA_NW), ("deposit", None, F.FLA_DEPOSIT)]
         if model is not None:
@@ -196,15 +266,15 @@ def large_section(ctx, args, dev, model):
         del snap, st, keep, Sm, Sv, den, wl
         torch.cuda.empty_cache()
     target = rows[0]["plain"]
-    matched = [r["trajectories"] for r in rows if "learned" in r and r["learned"] <= target]
+    crossing, note = learned_crossing(rows, target)
     return {"workload": "3-D multi-vortex map (two ABC maps, amplitudes 0.2 and 0.1, wavenumbers 1 and 2), "
                         "256^3 periodic mesh, 320^3 lattice trajectories, h0 = 1/320, FP32 kernel with FP64 det J",
-            "performance": perf,
+            "learned_performance": perf,
             "reference": {"psicell_particles": args.large_particles,
                           "noise_floor_rel_l2": [round(math.sqrt(f), 4) for f in floor]},
             "error": "mean over the 4 source fields of the noise-debiased rel L2 against dense PSI-CELL",
             "eval": rows, "plain_error_at_32.8M": target,
-            "fewest_trajectories_learned_within_plain_error": min(matched) if matched else None}
+            "learned_matches_plain_at_32.8M_with_trajectories": crossing, "crossing_note": note}
 
 
 def learned_vs_plain(ctx, args, dev):
@@ -256,8 +326,27 @@ def learned_vs_plain(ctx, args, dev):
         e = [math.sqrt(max(r[1 + 2 * k] / r[2 + 2 * k] - floor[k], 0.0)) for k in range(4)]
         return float(np.mean(e))
 
+    def time_forms(sn, mesh):
+        """cells/s of the plain and learned forms (the learned form includes
+        the feature and network kernels) on one snapshot."""
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        Sm, Sv, den = F.alloc_fields(sn.cells, 3, torch.float32, dev, den=False)
+        out = {}
+        for learned in (False, True):
+            for rep in range(args.warmup + args.steps):
+                if rep == args.warmup:
+                    e0.record()
+                h = model.factors(sn)[0] if learned else None
+                ctx.project_sources(F.mesh_of(mesh), sn.traj, F.Params(**{**sn.params.__dict__, "h_factor": h}),
+                                    Sm, Sv)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            out["cells_per_s_learned" if learned else "cells_per_s_plain"] = sn.cells / (ms * 1e-3)
+        return out
+
     rows = []
-    for pa in (128, 100, 80, 64, 50):
+    for pa in (128, 100, 80, 64, 50, 40, 32):
         wl = W.abc_lattice_3d(per_axis=pa, mesh_n=128, device=dev)
         sn = snap_of(wl, ref2)
         out = {"trajectories": pa ** 3}
@@ -268,26 +357,23 @@ def learned_vs_plain(ctx, args, dev):
             ctx.project_sources(F.mesh_of(wl.mesh), sn.traj, prm, Sm, Sv, den)
             res, _ = model.loss(sn, [Sm, *Sv], False)
             out[name] = round(deb(res), 5)
+        out.update({k: float(f"{v:.4g}") for k, v in time_forms(sn, wl.mesh).items()})
         rows.append(out)
-        if pa == 128:
-            # throughput of both forms on the full workload (the learned form
-            # includes the feature and network kernels)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            Sm, Sv, den = F.alloc_fields(sn.cells, 3, torch.float32, dev, den=False)
-            for learned in (False, True):
-                for rep in range(args.warmup + args.steps):
-                    if rep == args.warmup:
-                        e0.record()
-                    h = model.factors(sn)[0] if learned else None
-                    ctx.project_sources(F.mesh_of(wl.mesh), sn.traj, F.Params(**{**sn.params.__dict__, "h_factor": h}),
-                                        Sm, Sv)
-                e1.record()
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / args.steps
-                out["cells_per_s_learned" if learned else "cells_per_s_plain"] = sn.cells / (ms * 1e-3)
         del sn, wl
     target = rows[0]["plain"]
-    matched = [r["trajectories"] for r in rows if r["learned"] <= target]
+    crossing, note = learned_crossing(rows, target)
+    at_crossing = None
+    if crossing is not None:
+        pa = max(2, int(round(crossing ** (1.0 / 3.0))))
+        wl = W.abc_lattice_3d(per_axis=pa, mesh_n=128, device=dev)
+        sn = snap_of(wl, ref2)
+        hf = model.factors(sn)[0]
+        prm = F.Params(**{**sn.params.__dict__, "h_factor": hf})
+        Sm, Sv, den = F.alloc_fields(sn.cells, 3, torch.float32, dev)
+        ctx.project_sources(F.mesh_of(wl.mesh), sn.traj, prm, Sm, Sv, den)
+        res, _ = model.loss(sn, [Sm, *Sv], False)
+        at_crossing = {"lattice_trajectories": pa ** 3, "learned": round(deb(res), 5), **time_forms(sn, wl.mesh)}
+        del sn, wl
     return model, {
         "train": {"snapshots": args.train_snapshots, "trajectories": args.train_trajectories, "mesh": [64, 64, 64],
                   "psicell_particles": args.train_particles, "steps": args.train_steps, "seconds": round(t_train, 2)},
@@ -295,7 +381,9 @@ def learned_vs_plain(ctx, args, dev):
         "error": "mean over the 4 source fields of the noise-debiased rel L2 against dense PSI-CELL",
         "eval": rows,
         "plain_error_at_2M": target,
-        "fewest_trajectories_learned_within_plain_error_at_2M": min(matched) if matched else None,
+        "learned_matches_plain_at_2M_with_trajectories": crossing,
+        "crossing_note": note,
+        "at_crossing": at_crossing,
     }
 
 
@@ -374,7 +462,7 @@ def batch_section(ctx, args, dev):
     ctx.set_plan(3, F.FLA_F32, plan)
     ms_single = timed(singles, max(args.steps // 4, 2))
     ctx.set_plan(3, F.FLA_F32, -1)
-    achieved = P * FLOPS_PER_PAIR_3D / (g_ms * 1e-3) / 1e12
+    achieved = P * FLOPS_PER_PAIR[3] / (g_ms * 1e-3) / 1e12
     log(f"batch: graph {ms_graph:.3f} ms, direct {ms_direct:.3f} ms, 64 single calls {ms_single:.3f} ms; "
         f"stages {stages}")
     out = {"workload": "64 uneven snapshots: meshes round(32*4^u)^3 (32^3..128^3), round(1e4*200^u') random "
@@ -385,51 +473,205 @@ def batch_section(ctx, args, dev):
            "cells_per_s": M / (ms_graph * 1e-3), "pairs_per_s": P / (ms_graph * 1e-3),
            "stage_ms": stages, "plan": plan, "chunk": chunk,
            "autotune_gather_ms": [round(t, 4) for t in times],
-           "gather": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
-                      "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "launch_ms": g_ms,
+           "gather": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                      "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "launch_ms": g_ms,
+                      "frac_of_nonpacked_78.6": round(achieved / FP32_NONPACKED_TFLOPS, 4),
                       "kernel": "k_gather_batch<float,3,NW>"}}
     del wls, trajs, keeps, outs
     torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(seconds: float):
-    """FP64 oracle, brute force per cell, on a random sample of cells of the
-    same workload; full-field time extrapolated from the sample."""
-    import numpy as np
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(args, dev):
+    """The FP64 oracle in its trajectory-centric form (each trajectory visits
+    the cells of its cutoff box; OpenMP threads own planes of cells) on the
+    host cores.  Headline: a slab of whole y-planes of the 256^3 multi-vortex
+    case, all trajectories, sized to about args.cpu_seconds; the rate is the
+    sample's cells over its time plus the trajectory terms of all 32.8M
+    trajectories, as cells/s over the whole field.  Beside it, with no
+    extrapolation: the whole 128^3 field on all threads and the whole 2-D
+    Taylor-Green field; and one-thread rates (a y-slab of the 128^3 case,
+    the whole 2-D field)."""
     import torch
 
     import oracle
     import workloads as W
     cores = len(os.sched_getaffinity(0))
     oracle.set_threads(cores)
-    wl = W.abc_lattice_3d(device="cpu")
+    threads = oracle.num_threads()
     f = lambda t: t.to(torch.float32).to(torch.float64)
-    tr = W.Trajectories(wl.traj.x, wl.traj.J, f(wl.traj.v), f(wl.traj.ug), f(wl.traj.r), wl.traj.n0)
+
+    def host(tr, prec):
+        g = f if prec == "f32" else (lambda t: t)
+        return W.Trajectories(tr.x.cpu(), tr.J.cpu(), g(tr.v.cpu()), g(tr.ug.cpu()), g(tr.r.cpu()), tr.n0,
+                              tr.seed_volume)
+
+    def run(wl, tr, terms, box_lo=None, box_n=None):
+        t0 = time.perf_counter()
+        p = oracle.nw_box(wl.mesh, tr.x, terms, box_lo, box_n, wl.cutoff, wl.precision == "f32")
+        return time.perf_counter() - t0, p
+
+    # headline: 256^3 multi-vortex, y-slab sample
+    wl = W.multi_vortex_lattice_3d(device=dev)
+    tr = host(wl.traj, "f32")
+    wl.traj = None
+    torch.cuda.empty_cache()
     t0 = time.perf_counter()
     terms = oracle.trajectory_terms(tr, wl.rho_d, wl.mu, wl.delta, wl.h0)
     t_terms = time.perf_counter() - t0
+    n = wl.mesh.n
+    t1, _ = run(wl, tr, terms, [0, 0, 0], [n[0], 1, n[2]])
+    k = int(max(1, min(n[1] - 1, args.cpu_seconds / max(t1, 1e-3))))
+    t_box, p = run(wl, tr, terms, [0, 1, 0], [n[0], k, n[2]])
+    B = n[0] * k * n[2]
     M = wl.mesh.cells
-    rng = np.random.default_rng(0)
-    probe = rng.choice(M, 4 * cores, replace=False)
-    t0 = time.perf_counter()
-    oracle.nw_cells(wl.mesh, tr.x, terms, probe, wl.cutoff, True)
-    per_cell = (time.perf_counter() - t0) / probe.size
-    n = int(min(M, max(probe.size, seconds / per_cell)))
-    cells = rng.choice(M, n, replace=False)
-    t0 = time.perf_counter()
-    oracle.nw_cells(wl.mesh, tr.x, terms, cells, wl.cutoff, True)
-    t_cells = time.perf_counter() - t0
-    full = t_terms + t_cells * M / n
-    return {
+    full = t_terms + t_box * M / B
+    pairs_sample = int(p.pairs.sum())
+    del tr, terms, p, wl
+    out = {
         "value": M / full,
         "unit": "cells/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"{n} random cells of the 128^3 mesh, each by brute force over all "
-                   f"{tr.count} trajectories, plus the per-trajectory terms of all trajectories "
-                   f"({t_terms:.2f} s); full field extrapolated as t_terms + t_cells*M/n = {full:.0f} s"),
+        "sample": (f"{k} whole y-planes ({B} cells, {pairs_sample} included pairs) of the 256^3 multi-vortex "
+                   f"field, by the FP64 oracle's trajectory-centric form over all 32,768,000 trajectories on "
+                   f"{threads} threads: {t_box:.1f} s, plus {t_terms:.1f} s for the terms of every trajectory; "
+                   f"value = M / (t_terms + t_sample * M / cells)"),
+        "cpu_model": _cpu_model(),
+        "affinity_cores": cores,
     }
+    # 128^3 ABC: whole field on all threads (no extrapolation), and one thread on a y-slab
+    wl = W.abc_lattice_3d(device="cpu")
+    tr = host(wl.traj, "f32")
+    terms = oracle.trajectory_terms(tr, wl.rho_d, wl.mu, wl.delta, wl.h0)
+    t_all, p = run(wl, tr, terms)
+    out["abc128_whole_field"] = {"seconds": round(t_all, 2), "cells_per_s": wl.mesh.cells / t_all,
+                                 "pairs": int(p.pairs.sum()), "threads": threads}
+    oracle.set_threads(1)
+    t1, p1 = run(wl, tr, terms, [0, 0, 0], [128, 2, 128])
+    out["abc128_one_thread"] = {"seconds": round(t1, 2), "cells": 128 * 2 * 128,
+                                "cells_per_s": 128 * 2 * 128 / t1, "pairs": int(p1.pairs.sum()),
+                                "sample": "2 whole y-planes of the 128^3 field"}
+    # 2-D Taylor-Green in binary64: whole field, one thread and all threads
+    wl2 = W.taylor_green_2d()
+    tr2 = host(wl2.traj, "f64")
+    terms2 = oracle.trajectory_terms(tr2, wl2.rho_d, wl2.mu, wl2.delta, wl2.h0)
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run(wl2, tr2, terms2)
+    t_one = (time.perf_counter() - t0) / reps
+    oracle.set_threads(cores)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run(wl2, tr2, terms2)
+    t_many = (time.perf_counter() - t0) / reps
+    out["tg2d_f64_whole_field"] = {"one_thread_s": round(t_one, 5), "cells_per_s_one_thread": wl2.mesh.cells / t_one,
+                                   "all_threads_s": round(t_many, 5),
+                                   "cells_per_s_all_threads": wl2.mesh.cells / t_many}
+    return out
+
+
+def projection_section(ctx, args, dev, wl, prec, traffic_name):
+    """Timed fla_project_sources on one workload (inputs on the GPU), its
+    rates and the gather's roofline."""
+    import torch
+
+    import paper_2512_20829_amd as F
+    tr = wl.traj
+    dt = torch.float64 if prec == "f64" else torch.float32
+    st, keep = F.make_trajectories(tr.x.contiguous(), tr.J.contiguous(), tr.v.to(dt).contiguous(),
+                                   tr.ug.to(dt).contiguous(), tr.r.to(dt).contiguous(), tr.n0, tr.seed_volume)
+    wl.traj = None
+    del tr
+    mesh = F.mesh_of(wl.mesh)
+    params = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
+    ms, stages, g_ms, stats = timed_projection(ctx, F, mesh, st, params, args.steps, args.warmup)
+    M = wl.mesh.cells
+    P = stats["pairs"]
+    del st, keep
+    torch.cuda.empty_cache()
+    return {"ms_per_step": round(ms, 4), "cells_per_s": M / (ms * 1e-3), "pairs_per_s": P / (ms * 1e-3),
+            "pairs": P, "trajectories": stats["trajectories"], "skipped": stats["skipped"],
+            "max_class": stats["max_class"], "stage_ms": stages,
+            "roofline": gather_roofline(P, g_ms, wl.mesh.dim, prec, traffic_name)}
+
+
+def psicell_section(ctx, args, dev, fla_ms):
+    import torch
+
+    import paper_2512_20829_amd as F
+    import workloads as W
+    Np = args.psicell_particles
+    log(f"generating the {Np}-particle PSI-CELL cloud on the GPU")
+    mesh_w = W.unit_mesh(3, 128, True)
+    M = mesh_w.cells
+    mesh = F.mesh_of(mesh_w)
+    cl = W.abc_cloud(Np, seed=0, device=dev, jacobian=False)
+    cv, cu, cr = (cl.v.to(torch.float32).contiguous(), cl.ug.to(torch.float32).contiguous(),
+                  cl.r.to(torch.float32).contiguous())
+    pst, pkeep = F.make_trajectories(cl.x.contiguous(), None, cv, cu, cr, 1.0)
+    del cl
+    Pm, Pv, _ = F.alloc_fields(M, 3, torch.float32, dev, den=False)
+    w = W.N0_DEFAULT / Np
+    params = F.Params(rho_d=W.RHO_D, mu=W.MU_AIR, delta=W.DELTA_EVAP, h0=1.0 / 128)
+    ctx.psicell_accumulate(mesh, pst, w, params, Pm, Pv)
+    torch.cuda.synchronize()
+    reps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.psicell_accumulate(mesh, pst, w, params, Pm, Pv)
+    e1.record()
+    torch.cuda.synchronize()
+    psi_ms = e0.elapsed_time(e1) / reps
+    del pst, pkeep, Pm, Pv
+    torch.cuda.empty_cache()
+    # algorithmic bytes: x in binary64 (24 B) and v, u_g, r in binary32
+    # (28 B) per particle read once, 4 binary32 fields of 16 B per cell written
+    alg = Np * 52 + M * 16
+    return {"particles": Np, "ms": round(psi_ms, 3), "particles_per_s": Np / (psi_ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": round(alg / (psi_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(alg / (psi_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": psicell_traffic(), "algorithmic_bytes": alg,
+                         "note": "achieved counts 52 B per particle in and 16 B per cell out; traffic is the "
+                                 "counted bytes of the passes (records written and re-read)"},
+            "psicell_over_fla_time": round(psi_ms / fla_ms, 3) if fla_ms else None,
+            "paper_context": "paper: FLA 32 CPU-h vs PSI-CELL 4030 CPU-h for the whole coupled "
+                             "solver at 100x seeding, University of Brighton CPU cluster"}
+
+
+def psicell_traffic():
+    """Counted HBM bytes of one PSI-CELL call on the 200M-particle cloud from
+    the committed counter summary, or None when psicell.hip changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "psicell_200m_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2512_20829_amd", "csrc", "psicell.hip")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].rsplit(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("psicell.hip sha256[:16]") != digest:
+        return None
+    try:
+        return float(vals["bytes per call (calibrated)"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -438,10 +680,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--only-headline", action="store_true", help="time the headline workload only")
+    ap.add_argument("--only", choices=["headline", "abc128", "tg2d", "psicell"], default=None,
+                    help="time one projection workload only (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psicell", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch section")
-    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 multi-vortex section")
+    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 error section")
     ap.add_argument("--large-particles", type=int, default=1_677_721_600)
     ap.add_argument("--batch-snapshots", type=int, default=64)
     ap.add_argument("--psicell-particles", type=int, default=200_000_000)
@@ -458,6 +703,8 @@ def main():
               "MI355X and --gpus must be 1 (the multi-GPU sharding is a design note only).",
               file=sys.stderr)
         sys.exit(2)
+    if args.only_headline:
+        args.only = "headline"
 
     import torch
 
@@ -465,138 +712,93 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda", 0)
-    log("generating the 128^3 / 2M-trajectory ABC workload on the GPU")
-    wl = W.abc_lattice_3d(device=dev)
-    tr = wl.traj
-    x = tr.x.contiguous()
-    J = tr.J.contiguous()
-    v = tr.v.to(torch.float32).contiguous()
-    ug = tr.ug.to(torch.float32).contiguous()
-    r = tr.r.to(torch.float32).contiguous()
-    st, keep = F.make_trajectories(x, J, v, ug, r, tr.n0, tr.seed_volume)
-    M = wl.mesh.cells
-    mesh = F.mesh_of(wl.mesh)
-    S_mass, S_mom, den = F.alloc_fields(M, 3, torch.float32, dev, den=False)
     ctx = F.Context(0)
-    params = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
-    counted = F.Params(**{**params.__dict__, "count_pairs": True})
-    ctx.project_sources(mesh, st, counted, S_mass, S_mom)
-    torch.cuda.synchronize()
-    stats = ctx.stats()
-    P = stats["pairs"]
-    log(f"pairs per call: {P} ({P / tr.count:.1f} per trajectory); skipped {stats['skipped']}")
+    head = abc = tg = None
+    if args.only in (None, "headline"):
+        log("headline: generating the 256^3 / 32.8M-trajectory multi-vortex workload on the GPU")
+        head = projection_section(ctx, args, dev, W.multi_vortex_lattice_3d(device=dev), "f32", "multivortex256")
+        log(f"headline: {head['ms_per_step']:.3f} ms/step; stages {head['stage_ms']}")
+    if args.only in (None, "abc128"):
+        log("abc128: the 128^3 / 2M-trajectory ABC workload")
+        abc = projection_section(ctx, args, dev, W.abc_lattice_3d(device=dev), "f32", "abc128")
+        log(f"abc128: {abc['ms_per_step']:.3f} ms/step; stages {abc['stage_ms']}")
+    if args.only in (None, "tg2d"):
+        log("tg2d_f64: the 2-D Taylor-Green workload in binary64")
+        a2 = argparse.Namespace(**{**vars(args), "steps": max(args.steps, 200)})
+        tg = projection_section(ctx, a2, dev, W.taylor_green_2d(device=dev), "f64", "tg2d")
+        log(f"tg2d_f64: {tg['ms_per_step']:.4f} ms/step")
 
-    for _ in range(args.warmup):
-        ctx.project_sources(mesh, st, params, S_mass, S_mom)
-    torch.cuda.synchronize()
-    ctx.profile_enable(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        ctx.project_sources(mesh, st, params, S_mass, S_mom)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / args.steps
-    prof = ctx.profile_read()
-    ctx.profile_enable(False)
-    g_ms = prof["gather"][0] / max(prof["gather"][1], 1)
-    stages = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1]}
-    log(f"{ms_step:.3f} ms/step; stages (ms/launch): {stages}")
+    batch = psi = learned = large = cpu = None
+    if args.only == "psicell":
+        psi = psicell_section(ctx, args, dev, None)
+        print(json.dumps({"psicell": psi}), flush=True)
+        if args.calibration_copy_mib > 0:
+            n = args.calibration_copy_mib * (1 << 20) // 4
+            a = torch.ones(n, dtype=torch.float32, device=dev)
+            torch.empty_like(a).copy_(a)
+            torch.cuda.synchronize()
+        ctx.close()
+        return
+    if args.only is None:
+        if not args.no_batch:
+            batch = batch_section(ctx, args, dev)
+        if not args.no_psicell:
+            psi = psicell_section(ctx, args, dev, abc["ms_per_step"])
+            log(f"psicell: {psi['ms']:.3f} ms")
+        model = None
+        if not args.no_learned:
+            log("learned-vs-plain section: training the bandwidth network")
+            model, learned = learned_vs_plain(ctx, args, dev)
+            log(f"learned: {learned['eval']}")
+        if not args.no_large:
+            log("large section: errors on the 256^3 multi-vortex case")
+            large = large_section(ctx, args, dev, model)
+        if not args.no_cpu_baseline:
+            log(f"timing the FP64 oracle on host cores (~{args.cpu_seconds:.0f} s sample + whole fields)")
+            cpu = cpu_baseline(args, dev)
+            log(f"oracle: {cpu['value']:.1f} cells/s on {cpu['cores']} threads")
 
-    achieved = P * FLOPS_PER_PAIR_3D / (g_ms * 1e-3) / 1e12
-    traffic = gather_traffic()
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
-                "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_gather<float,3,NW>", "launch_ms": round(g_ms, 4),
-                "flops_per_pair": FLOPS_PER_PAIR_3D, "pairs_per_launch": P}
-
-    batch = None
-    if not args.no_batch:
-        batch = batch_section(ctx, args, dev)
-
-    psi = None
-    if not args.no_psicell:
-        Np = args.psicell_particles
-        log(f"generating the {Np}-particle PSI-CELL cloud on the GPU")
-        cl = W.abc_cloud(Np, seed=0, device=dev, jacobian=False)
-        cv, cu, cr = (cl.v.to(torch.float32).contiguous(), cl.ug.to(torch.float32).contiguous(),
-                      cl.r.to(torch.float32).contiguous())
-        pst, pkeep = F.make_trajectories(cl.x.contiguous(), None, cv, cu, cr, 1.0)
-        del cl
-        Pm, Pv, _ = F.alloc_fields(M, 3, torch.float32, dev, den=False)
-        w = W.N0_DEFAULT / Np
-        ctx.psicell_accumulate(mesh, pst, w, params, Pm, Pv)
-        torch.cuda.synchronize()
-        reps = 3
-        ctx.profile_enable(True)
-        e0.record()
-        for _ in range(reps):
-            ctx.psicell_accumulate(mesh, pst, w, params, Pm, Pv)
-        e1.record()
-        torch.cuda.synchronize()
-        psi_ms = e0.elapsed_time(e1) / reps
-        pp = ctx.profile_read()["psicell"]
-        ctx.profile_enable(False)
-        psi = {"particles": Np, "ms": round(psi_ms, 3),
-               "particles_per_s": Np / (psi_ms * 1e-3),
-               # inputs: x in binary64 (24 B), v, u_g, r in binary32 (28 B)
-               "hbm_gbs_input": round(Np * 52 / (psi_ms * 1e-3) / 1e9, 1),
-               # the four passes move 140 B per particle: count 24 in + 4 out,
-               # scatter 32 in + 20 out, tiles 20 in + 20 out, reduce 20 in
-               "hbm_gbs_algorithmic": round(Np * 140 / (psi_ms * 1e-3) / 1e9, 1),
-               "frac_of_hbm_peak": round(Np * 140 / (psi_ms * 1e-3) / 8.0e12, 3),
-               "psicell_over_fla_time": round(psi_ms / ms_step, 3),
-               "paper_context": "paper: FLA 32 CPU-h vs PSI-CELL 4030 CPU-h for the whole coupled "
-                                "solver at 100x seeding, University of Brighton CPU cluster"}
-        del pst, pkeep, Pm, Pv
-        torch.cuda.empty_cache()
-        log(f"psicell {Np}: {psi_ms:.3f} ms")
-
-    learned, model = None, None
-    if not args.no_learned:
-        log("learned-vs-plain section: training the bandwidth network")
-        model, learned = learned_vs_plain(ctx, args, dev)
-        log(f"learned: {learned['eval']}")
-
-    large = None
-    if not args.no_large:
-        log("large section: 256^3 multi-vortex case")
-        large = large_section(ctx, args, dev, model)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log(f"timing the FP64 oracle on host cores (~{args.cpu_seconds:.0f} s)")
-        cpu = cpu_baseline(args.cpu_seconds)
-        log(f"oracle: {cpu['value']:.1f} cells/s on {cpu['cores']} threads")
-
+    main_sec = head or abc or tg
+    name = {"headline": "multi-vortex 256^3", "abc128": "ABC 128^3", "tg2d": "Taylor-Green 2-D FP64"}[args.only or "headline"]
+    configs = {
+        "headline": {"workload": "3-D multi-vortex map (two ABC maps, amplitudes 0.2 and 0.1, wavenumbers 1 and 2; "
+                                 "folds, |det J| down to ~1e-8), 256^3 periodic mesh, 32,768,000 lattice "
+                                 "trajectories (320^3), FP32 kernel with FP64 det J, h0 = 1/320, cutoff 4",
+                     "mesh": [256, 256, 256], "trajectories": 320 ** 3, "mode": "NW"},
+        "abc128": {"workload": "3-D ABC map (amplitude 0.2, folds), 128^3 periodic mesh, 2,097,152 lattice "
+                               "trajectories, FP32 kernel with FP64 det J, h0 = 1/128, cutoff 4",
+                   "mesh": [128, 128, 128], "trajectories": 128 ** 3, "mode": "NW"},
+        "tg2d": {"workload": "2-D Taylor-Green map (amplitude 0.1), 64^2 mesh on the unit square, 4096 lattice "
+                             "trajectories, FP64, h0 = 1/64, cutoff 4",
+                 "mesh": [64, 64], "trajectories": 64 ** 2, "mode": "NW"},
+    }
     out = {
         "metric": METRIC,
-        "value": M / (ms_step * 1e-3),
+        "value": main_sec["cells_per_s"],
         "unit": "cells/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": main_sec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if main_sec is tg else "f32",
         "data": "synthetic",
-        "config": {"workload": "3-D ABC map (amplitude 0.2, folds), 128^3 periodic mesh, 2,097,152 "
-                               "lattice trajectories, FP32 kernel with FP64 det J, h0 = 1/128, cutoff 4",
-                   "mesh": [128, 128, 128], "trajectories": tr.count, "mode": "NW"},
-        "pairs_per_s": P / (ms_step * 1e-3),
-        "pairs": P,
-        "stage_ms": stages,
-        "roofline": roofline,
+        "config": configs[args.only or "headline"],
+        "pairs_per_s": main_sec["pairs_per_s"],
+        "pairs": main_sec["pairs"],
+        "stage_ms": main_sec["stage_ms"],
+        "roofline": main_sec["roofline"],
         "cpu_baseline": cpu,
+        "abc128": abc if main_sec is not abc else None,
+        "tg2d_f64": tg if main_sec is not tg else None,
         "batch": batch,
         "psicell": psi,
         "learned_vs_plain": learned,
         "large": large,
     }
+    log(f"main line: {name}")
     print(json.dumps(out), flush=True)
     if args.calibration_copy_mib > 0:
         n = args.calibration_copy_mib * (1 << 20) // 4

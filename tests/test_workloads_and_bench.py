@@ -2,6 +2,7 @@
 trajectory producer, so their properties are pinned here) and of the
 benchmark's reading of committed counter summaries."""
 import hashlib
+import math
 import os
 
 import pytest
@@ -75,8 +76,20 @@ def test_bench_reads_the_traffic_summary():
     assert "gather.hip sha256[:16]" in vals and "bytes per launch (calibrated)" in vals
     src = os.path.join(ROOT, "paper_2512_20829_amd", "csrc", "gather.hip")
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    got = bench.gather_traffic()
+    got = bench.gather_traffic("abc128")
     if vals["gather.hip sha256[:16]"] == digest:
         assert got == float(vals["bytes per launch (calibrated)"])
     else:
         assert got is None
+
+
+def test_bench_learned_crossing_interpolates_in_log_n():
+    import bench
+    rows = [{"trajectories": 8000, "learned": 0.5}, {"trajectories": 1000, "learned": 0.7},
+            {"trajectories": 125, "learned": 0.9}]
+    n, note = bench.learned_crossing(rows, 0.6)
+    assert n == round(math.sqrt(8000 * 1000)) and note is None
+    n, note = bench.learned_crossing(rows, 0.95)
+    assert n is None and "125" in note
+    n, note = bench.learned_crossing(rows, 0.4)
+    assert n is None and "does not reach" in note
