@@ -217,9 +217,14 @@ fla_status fla_project_sources_noalloc(fla_ctx* ctx, const fla_mesh* mesh, const
  * arithmetic for binary32 inputs: within a few ulps of the binary64 terms
  * rounded to binary32); the sums are exact integer sums of these values
  * quantised to 2^-e (e chosen per channel from the largest |phi| so that no
- * sum can overflow), hence order-independent.  den, if given, receives the
- * particle count per cell.  Meshes of more than 16384 * 1024 cells return
- * INVALID_ARG.  Other errors as fla_project_sources. */
+ * sum can overflow), hence order-independent.  Binary64 calls add a second
+ * integer word per channel for the quantisation remainders, so that the
+ * error of a particle stays below 2^-62 of the largest |phi| whatever the
+ * count.  den, if given, receives the particle count per cell.  Particles
+ * with a non-finite velocity, gas velocity, radius or source term are
+ * skipped and counted in stats.skipped; particles outside a closed box in
+ * stats.outside.  Meshes of more than 16384 * 1024 cells (16384 * 512 in
+ * binary64 3-D) return INVALID_ARG.  Other errors as fla_project_sources. */
 fla_status psicell_accumulate(fla_ctx* ctx, const fla_mesh* mesh,
                               const fla_trajectories* particles, double particle_weight,
                               const fla_params* params, const fla_fields* out, void* stream);
@@ -294,9 +299,10 @@ fla_status fla_autotune(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectori
 
 /* Features and network.  theta: device parameter block.  h_factor (device,
  * count floats, required) receives g_i (1 for skipped trajectories); z
- * (5*count, plane k = input k), o (count) and features (5*count, raw f)
- * are optional device outputs (the backward needs z and o).  The result
- * feeds fla_params.h_factor.  Errors as fla_project_sources. */
+ * (5*count, plane k = input k), o (count) and features (5*count, raw f;
+ * NaN for skipped trajectories) are optional device outputs (the backward
+ * needs z and o).  The result feeds fla_params.h_factor.  Errors as
+ * fla_project_sources. */
 fla_status fla_bandwidth_forward(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
                                  const float* theta, float* h_factor, float* z, float* o,
                                  float* features, void* stream);
@@ -322,8 +328,11 @@ fla_status fla_bandwidth_backward(fla_ctx* ctx, int dim, const float* theta, int
                                   const float* o, const float* dL_dlogh, float* grad, void* stream);
 
 /* One Adam step on the trainable entries of theta with moments m, v (all
- * device, FLA_MLP_PARAMS floats); step counts from 1 (bias correction).
- * Errors: INVALID_ARG, DEVICE. */
+ * device, FLA_MLP_PARAMS floats; the entries past the trainable ones are
+ * left untouched): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2 and
+ * theta -= lr m^ / (sqrt(v^) + eps) with m^ = m/(1 - b1^step), v^ =
+ * v/(1 - b2^step), evaluated in binary64 from the binary64 arguments and
+ * stored in binary32; step counts from 1.  Errors: INVALID_ARG, DEVICE. */
 fla_status fla_adam_step(fla_ctx* ctx, float* theta, float* m, float* v, const float* grad, int64_t step,
                          double lr, double beta1, double beta2, double eps, void* stream);
 
@@ -334,6 +343,38 @@ fla_status fla_adam_step(fla_ctx* ctx, float* theta, float* m, float* v, const f
  * formed in a fixed order (deterministic).  Errors: INVALID_ARG, DEVICE. */
 fla_status fla_rel_l2_loss(fla_ctx* ctx, int channels, int64_t cells, int prec, const fla_fields* S,
                            const fla_fields* R, const fla_fields* dL_dS, double* result, void* stream);
+
+/* Feature standardisation of the network inputs: sets mu[5] and sd[5] of
+ * theta (device parameter block; the trainable entries are left as they
+ * are) to the mean and the Bessel-corrected standard deviation plus 1e-3 of
+ * the raw features f over the valid trajectories of nsnap snapshots (host
+ * arrays of meshes and trajectories; a trajectory is valid when it is not
+ * skipped, as in fla_project_sources).  The sums are formed in binary64 in
+ * a fixed order (deterministic), the deviations in a second pass from the
+ * finished mean.  Errors: INVALID_ARG (naming the snapshot), OUT_OF_MEMORY,
+ * DEVICE. */
+fla_status fla_bandwidth_standardise(fla_ctx* ctx, int nsnap, const fla_mesh* meshes, const fla_trajectories* trajs,
+                                     float* theta, void* stream);
+
+/* One training step of the bandwidth network on one snapshot, every stage in
+ * the library's kernels on one stream: features and network
+ * (fla_bandwidth_forward) -> FLA_NW projection with the factors
+ * (fla_project_sources) -> relative-L2 loss against the reference fields ref
+ * and dL/dS (fla_rel_l2_loss; ref holds C = dim + 1 planes in the call's
+ * precision, typically a dense PSI-CELL field) -> estimator backward
+ * (fla_project_backward) -> network backward (fla_bandwidth_backward) ->
+ * one Adam step (fla_adam_step) on theta with moments m and v (device,
+ * FLA_MLP_PARAMS floats each, updated in place; step counts from 1).  The
+ * result is bit for bit that of the six calls made in that order.  params
+ * gives the physics and kernel parameters (mode FLA_NW, h_factor NULL: the
+ * step forms the factors).  loss (nullable, device, 1 + 2 C doubles)
+ * receives the loss and its per-channel terms as fla_rel_l2_loss writes
+ * them.  The intermediates live in a context-owned training workspace.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+fla_status fla_mlp_train_step(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                              const fla_params* params, const fla_fields* ref, float* theta, float* m, float* v,
+                              int64_t step, double lr, double beta1, double beta2, double eps, double* loss,
+                              void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched projection of many independent snapshots of uneven size.  Each

@@ -83,7 +83,7 @@ def _declare(L):
                               C.c_double, C.c_double, C.c_int, C.c_double, _dp, _dp, _dp]
     L.orc_psicell.restype = C.c_int64
     L.orc_psicell.argtypes = [C.POINTER(OrcMesh), C.c_int64, _dp, _dp, _dp, _dp, C.c_double,
-                              C.c_double, C.c_double, C.c_double, _dp, _dp, _lp]
+                              C.c_double, C.c_double, C.c_double, _dp, _dp, _lp, _lp]
     L.orc_psicell_cell_of.restype = C.c_int64
     L.orc_psicell_cell_of.argtypes = [C.POINTER(OrcMesh), _dp]
     L.orc_app_a_scaling.restype = None
@@ -297,8 +297,10 @@ def deposit(mesh, x, terms: Terms, seed_volume: float, cutoff: float = 4.0,
 
 
 def psicell(mesh, cloud, weight: float, rho_d: float, mu: float, delta: float,
-            cell_scale: Optional[np.ndarray] = None):
-    """PSI-CELL box counting; returns (S (C, M), counts (M,), skipped)."""
+            cell_scale: Optional[np.ndarray] = None, split: bool = False):
+    """PSI-CELL box counting; returns (S (C, M), counts (M,), skipped), or with
+    split (S, counts, outside, nonfinite): particles outside a closed box and
+    particles with a non-finite input."""
     m = mesh if isinstance(mesh, OrcMesh) else mesh_from(mesh)
     dim = m.dim
     M = int(np.prod([m.n[a] for a in range(dim)]))
@@ -307,9 +309,12 @@ def psicell(mesh, cloud, weight: float, rho_d: float, mu: float, delta: float,
     S = np.zeros((1 + dim, M))
     counts = np.zeros(M, dtype=np.int64)
     cs = _f64(cell_scale) if cell_scale is not None else None
+    nf = np.zeros(1, dtype=np.int64)
     sk = lib().orc_psicell(C.byref(m), Np, _d(x), _d(v), _d(ug), _d(r), rho_d, mu, delta,
                            weight, _d(cs) if cs is not None else None, _d(S),
-                           counts.ctypes.data_as(_lp))
+                           counts.ctypes.data_as(_lp), nf.ctypes.data_as(_lp))
+    if split:
+        return S, counts, int(sk) - int(nf[0]), int(nf[0])
     return S, counts, int(sk)
 
 

@@ -673,7 +673,8 @@ void orc_deposit_scatter(const orc_mesh* m, int64_t N, const double* x, const do
 /* droplets it stands for).  Cell of a particle: floor((x - lo)/dx) per      */
 /* axis; periodic axes wrap; on a closed axis x == hi goes to the last cell */
 /* and any other outside position is skipped.  Particles with non-finite    */
-/* inputs are skipped.  Returns the number of particles skipped.            */
+/* inputs are skipped.  Returns the number of particles skipped; of these,  */
+/* the ones with a non-finite input go to *nonfinite_out.                   */
 /* ------------------------------------------------------------------------ */
 int64_t orc_psicell_cell_of(const orc_mesh* m, const double* xp)
 {
@@ -701,8 +702,9 @@ int64_t orc_psicell_cell_of(const orc_mesh* m, const double* xp)
 int64_t orc_psicell(const orc_mesh* m, int64_t Np, const double* x, const double* v,
                     const double* ug, const double* r, double rho_d, double mu, double delta,
                     double weight, const double* cell_scale, double* S /* C x M */,
-                    int64_t* counts /* M, nullable */)
+                    int64_t* counts /* M, nullable */, int64_t* nonfinite_out /* nullable */)
 {
+    int64_t nonfinite = 0;
     int C = 1 + m->dim;
     int64_t M = 1;
     for (int a = 0; a < m->dim; ++a) M *= m->n[a];
@@ -717,13 +719,24 @@ int64_t orc_psicell(const orc_mesh* m, int64_t Np, const double* x, const double
             up[a] = ug[a * Np + p];
         }
         int64_t c = orc_psicell_cell_of(m, xp);
-        if (c < 0 || !all_finite(vp, m->dim) || !all_finite(up, m->dim) || !isfinite(r[p])) {
+        if (!all_finite(xp, m->dim)) {
             ++skipped;
+            ++nonfinite;
+            continue;
+        }
+        if (c < 0) {
+            ++skipped;
+            continue;
+        }
+        if (!all_finite(vp, m->dim) || !all_finite(up, m->dim) || !isfinite(r[p])) {
+            ++skipped;
+            ++nonfinite;
             continue;
         }
         orc_droplet_phi(m->dim, r[p], vp, up, rho_d, mu, delta, phi, 0, 0, 0);
         if (!all_finite(phi, C)) {
             ++skipped;
+            ++nonfinite;
             continue;
         }
         for (int k = 0; k < C; ++k) acc[k * M + c] += phi[k];
@@ -735,6 +748,7 @@ int64_t orc_psicell(const orc_mesh* m, int64_t Np, const double* x, const double
         for (int k = 0; k < C; ++k) S[k * M + c] = -(weight / Vc) * cs * acc[k * M + c];
     }
     free(acc);
+    if (nonfinite_out) *nonfinite_out = nonfinite;
     return skipped;
 }
 

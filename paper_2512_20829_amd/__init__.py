@@ -109,6 +109,12 @@ _lib.fla_adam_step.argtypes = [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_double, C
 _lib.fla_rel_l2_loss.restype = C.c_int
 _lib.fla_rel_l2_loss.argtypes = [_vp, C.c_int, C.c_int64, C.c_int, C.POINTER(fla_fields), C.POINTER(fla_fields),
                                  C.POINTER(fla_fields), _vp, _vp]
+_lib.fla_bandwidth_standardise.restype = C.c_int
+_lib.fla_bandwidth_standardise.argtypes = [_vp, C.c_int, C.POINTER(fla_mesh), C.POINTER(fla_trajectories), _vp, _vp]
+_lib.fla_mlp_train_step.restype = C.c_int
+_lib.fla_mlp_train_step.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories), C.POINTER(fla_params),
+                                    C.POINTER(fla_fields), _vp, _vp, _vp, C.c_int64, C.c_double, C.c_double,
+                                    C.c_double, C.c_double, _vp, _vp]
 _lib.fla_project_batch.restype = C.c_int
 _lib.fla_project_batch.argtypes = [_vp, C.c_int, C.POINTER(fla_mesh), C.POINTER(fla_trajectories),
                                    C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
@@ -366,6 +372,22 @@ class Context:
                                          C.byref(fg) if fg is not None else None, _ptr(result),
                                          _stream_handle(stream)))
         return result
+
+    def bandwidth_standardise(self, meshes: Sequence, trajs: Sequence, theta, stream=None):
+        """Fit mu, sd of the parameter block (in place) over the snapshots."""
+        n = len(meshes)
+        if n == 0 or len(trajs) != n:
+            raise ValueError("meshes and trajs must be non-empty and of equal length")
+        Ms = (fla_mesh * n)(*meshes)
+        Ts = (fla_trajectories * n)(*trajs)
+        self._check(_lib.fla_bandwidth_standardise(self._h, n, Ms, Ts, _ptr(theta), _stream_handle(stream)))
+
+    def mlp_train_step(self, mesh: fla_mesh, traj: fla_trajectories, params: Params, ref: Sequence, theta, m, v,
+                       step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, loss=None, stream=None):
+        """One training step in the library; ref: reference planes (S_mass first)."""
+        self._check(_lib.fla_mlp_train_step(self._h, C.byref(mesh), C.byref(traj), C.byref(params.to_c()),
+                                            C.byref(make_fields(ref[0], ref[1:])), _ptr(theta), _ptr(m), _ptr(v),
+                                            int(step), lr, beta1, beta2, eps, _ptr(loss), _stream_handle(stream)))
 
     # -- batched snapshots --------------------------------------------------------------
     @staticmethod

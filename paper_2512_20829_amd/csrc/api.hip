@@ -23,6 +23,10 @@ struct fla_ctx {
     std::string err;
     void* ws = nullptr;
     size_t ws_size = 0;
+    // training workspace: the intermediates of fla_mlp_train_step and
+    // fla_bandwidth_standardise, which live across calls that use ws
+    void* tws = nullptr;
+    size_t tws_size = 0;
     unsigned long long* stats = nullptr;   // ST_N counters
     int plan[2][2] = {{-1, -1}, {-1, -1}};  // gather plan per (dim - 2, precision); -1 = default
     bool prof = false;
@@ -126,6 +130,30 @@ fla_status ensure_ws(fla_ctx* ctx, size_t need)
         return FLA_ERR_OUT_OF_MEMORY;
     }
     ctx->ws_size = sz;
+    return FLA_OK;
+}
+
+fla_status ensure_tws(fla_ctx* ctx, size_t need)
+{
+    if (need <= ctx->tws_size) return FLA_OK;
+    if (ctx->tws) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            ctx->err = std::string("hipDeviceSynchronize: ") + hipGetErrorString(e);
+            return FLA_ERR_DEVICE;
+        }
+        (void)hipFree(ctx->tws);
+        ctx->tws = nullptr;
+        ctx->tws_size = 0;
+    }
+    size_t sz = need + need / 4 + (1 << 20);
+    hipError_t e = hipMalloc(&ctx->tws, sz);
+    if (e != hipSuccess) {
+        ctx->tws = nullptr;
+        ctx->err = "training workspace allocation of " + std::to_string(sz) + " bytes failed: " + hipGetErrorString(e);
+        return FLA_ERR_OUT_OF_MEMORY;
+    }
+    ctx->tws_size = sz;
     return FLA_OK;
 }
 
@@ -564,14 +592,17 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
 {
     const int C = D + 1;
     PsiArgs a{};
-    // coarse tiles of kPsiMaxCellsPerTile cells: 16 x 8 x 8 (32^2 in 2-D)
-    int pt[3] = {D == 3 ? 16 : 32, D == 3 ? 8 : 32, D == 3 ? 8 : 1};
+    // coarse tiles of kPsiMaxCellsPerTile cells: 16 x 8 x 8 (32^2 in 2-D);
+    // 8^3 for binary64 in 3-D, whose two-word sums need twice the LDS
+    int pt[3] = {D == 3 ? (sizeof(R) == 8 ? 8 : 16) : 32, D == 3 ? 8 : 32, D == 3 ? 8 : 1};
     auto ntiles = [&]() {
         int64_t nt = 1;
         for (int ax = 0; ax < D; ++ax) nt *= (m.n[ax] + pt[ax] - 1) / pt[ax];
         return nt;
     };
-    CHECK_ARG(ntiles() <= kPsiMaxTiles, "psicell_accumulate supports at most 16384 * 1024 cells");
+    CHECK_ARG(ntiles() <= kPsiMaxTiles, sizeof(R) == 8 && D == 3
+                                            ? "psicell_accumulate supports at most 16384 * 512 cells in binary64 3-D"
+                                            : "psicell_accumulate supports at most 16384 * 1024 cells");
     for (int ax = 0; ax < 3; ++ax) {
         a.pt[ax] = ax < D ? pt[ax] : 1;
         a.pnt[ax] = ax < D ? (m.n[ax] + pt[ax] - 1) / pt[ax] : 1;
@@ -590,7 +621,7 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
     const int64_t sw = scan_tmp_words(hw > hb ? hw : hb);
     auto layout = [&](Carver& c) {
         a.maxbits = c.take<unsigned long long>(4);
-        a.qscale = c.take<double>(4);
+        a.qscale = c.take<double>(5);
         a.codes = c.take<int>(N > 0 ? N : 1);
         a.blockhist = c.take<unsigned int>(hw);
         a.binhist = c.take<unsigned int>(hb);
@@ -817,6 +848,7 @@ FLA_EXPORT fla_status fla_ctx_destroy(fla_ctx* ctx)
     if (ctx->items_done) (void)hipEventDestroy(ctx->items_done);
     if (ctx->items) (void)hipFree(ctx->items);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->tws) (void)hipFree(ctx->tws);
     if (ctx->stats) (void)hipFree(ctx->stats);
     delete ctx;
     return FLA_OK;
@@ -1047,7 +1079,7 @@ FLA_EXPORT fla_status fla_adam_step(fla_ctx* ctx, float* theta, float* m, float*
     CHECK_ARG(is_fin(lr) && lr >= 0.0 && beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps >= 0.0,
               "invalid Adam hyper-parameters");
     HIP_OK(hipSetDevice(ctx->device));
-    HIP_OK(launch_adam(theta, m, v, grad, step, (float)lr, (float)beta1, (float)beta2, (float)eps, (hipStream_t)stream));
+    HIP_OK(launch_adam(theta, m, v, grad, step, lr, beta1, beta2, eps, (hipStream_t)stream));
     return FLA_OK;
 }
 
@@ -1302,6 +1334,138 @@ FLA_EXPORT fla_status fla_autotune_batch(fla_ctx* ctx, int nsnap, const fla_mesh
     ctx->batch_plan[d][pr] = best_plan;
     ctx->batch_chunk[d][pr] = best_chunk;
     return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_bandwidth_standardise(fla_ctx* ctx, int nsnap, const fla_mesh* meshes,
+                                                const fla_trajectories* trajs, float* theta, void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    try {
+        CHECK_ARG(nsnap >= 1 && meshes && trajs, "nsnap >= 1 snapshots with meshes and trajs are required");
+        CHECK_ARG(theta != nullptr, "theta is NULL");
+        int64_t nmax = 1;
+        for (int k = 0; k < nsnap; ++k) {
+            MeshDev m;
+            fla_status st = check_mesh(ctx, &meshes[k], &m, meshes[k].dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+            TrajDev t;
+            if (st == FLA_OK) st = check_traj(ctx, &trajs[k], m.dim, true, &t);
+            if (st != FLA_OK) {
+                ctx->err = "snapshot " + std::to_string(k) + ": " + ctx->err;
+                return st;
+            }
+            nmax = std::max<int64_t>(nmax, trajs[k].count);
+        }
+        HIP_OK(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        float *hf, *fr;
+        double *part, *acc0, *acc1;
+        auto layout = [&](Carver& c) {
+            hf = c.take<float>(nmax);
+            fr = c.take<float>((size_t)kFeat * nmax);
+            part = c.take<double>(kMomParts);
+            acc0 = c.take<double>(8);
+            acc1 = c.take<double>(8);
+        };
+        {
+            Carver probe(nullptr);
+            layout(probe);
+            fla_status st = ensure_tws(ctx, probe.off + 256);
+            if (st != FLA_OK) return st;
+        }
+        Carver c(ctx->tws);
+        layout(c);
+        HIP_OK(launch_fill_u64((unsigned long long*)acc0, 8, 0ull, s));
+        HIP_OK(launch_fill_u64((unsigned long long*)acc1, 8, 0ull, s));
+        // pass 0: counts and sums; pass 1: squared deviations from the mean
+        for (int pass = 0; pass < 2; ++pass)
+            for (int k = 0; k < nsnap; ++k) {
+                if (trajs[k].count == 0) continue;
+                fla_status st = fla_bandwidth_forward(ctx, &meshes[k], &trajs[k], theta, hf, nullptr, nullptr, fr, stream);
+                if (st != FLA_OK) return st;
+                HIP_OK(launch_feat_moments(fr, trajs[k].count, pass, acc0, part, pass == 0 ? acc0 : acc1, s));
+            }
+        HIP_OK(launch_feat_finish(acc0, acc1, theta, s));
+        return FLA_OK;
+    } catch (...) {
+        ctx->err = "internal error";
+        return FLA_ERR_DEVICE;
+    }
+}
+
+FLA_EXPORT fla_status fla_mlp_train_step(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
+                                         const fla_params* params, const fla_fields* ref, float* theta, float* m,
+                                         float* v, int64_t step, double lr, double beta1, double beta2, double eps,
+                                         double* loss, void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    try {
+        MeshDev md;
+        fla_status st = check_mesh(ctx, mesh, &md, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+        if (st != FLA_OK) return st;
+        TrajDev td;
+        st = check_traj(ctx, traj, md.dim, true, &td);
+        if (st != FLA_OK) return st;
+        st = check_params(ctx, params, true);
+        if (st != FLA_OK) return st;
+        CHECK_ARG(params->mode == FLA_NW, "fla_mlp_train_step trains on the FLA_NW estimator");
+        CHECK_ARG(params->h_factor == nullptr, "params.h_factor must be NULL (the step forms the factors)");
+        st = check_fields(ctx, ref, md.dim);
+        if (st != FLA_OK) return st;
+        CHECK_ARG(theta && m && v, "theta, m and v are required");
+        CHECK_ARG(step >= 1, "step counts from 1");
+        CHECK_ARG(is_fin(lr) && lr >= 0.0 && beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps >= 0.0,
+                  "invalid Adam hyper-parameters");
+        HIP_OK(hipSetDevice(ctx->device));
+        const int64_t N = traj->count, M = md.M;
+        const int C = md.dim + 1;
+        const size_t rb = traj->prec == FLA_F64 ? 8 : 4;
+        float *hf, *z, *o, *dlogh, *grad;
+        unsigned char *Sp[4], *den, *Gp[4];
+        double* res;
+        auto layout = [&](Carver& c) {
+            hf = c.take<float>(N > 0 ? N : 1);
+            z = c.take<float>((size_t)kFeat * (N > 0 ? N : 1));
+            o = c.take<float>(N > 0 ? N : 1);
+            dlogh = c.take<float>(N > 0 ? N : 1);
+            for (int k = 0; k < C; ++k) Sp[k] = c.take<unsigned char>((size_t)M * rb);
+            den = c.take<unsigned char>((size_t)M * rb);
+            for (int k = 0; k < C; ++k) Gp[k] = c.take<unsigned char>((size_t)M * rb);
+            grad = c.take<float>(kParams);
+            res = c.take<double>(1 + 2 * 4);
+        };
+        {
+            Carver probe(nullptr);
+            layout(probe);
+            st = ensure_tws(ctx, probe.off + 256);
+            if (st != FLA_OK) return st;
+        }
+        Carver c(ctx->tws);
+        layout(c);
+        fla_params p = *params;
+        p.h_factor = hf;
+        fla_fields S{}, G{};
+        S.S_mass = Sp[0];
+        G.S_mass = Gp[0];
+        for (int a = 0; a < md.dim; ++a) {
+            S.S_mom[a] = Sp[1 + a];
+            G.S_mom[a] = Gp[1 + a];
+        }
+        S.den = den;
+        // 1. features and network; 2. projection with the factors; 3. loss and
+        // dL/dS; 4. estimator backward; 5. network backward; 6. Adam
+        st = fla_bandwidth_forward(ctx, mesh, traj, theta, hf, z, o, nullptr, stream);
+        if (st == FLA_OK) st = fla_project_sources(ctx, mesh, traj, &p, &S, stream);
+        if (st == FLA_OK) st = fla_rel_l2_loss(ctx, C, M, traj->prec, &S, ref, &G, loss ? loss : res, stream);
+        if (st == FLA_OK) st = fla_project_backward(ctx, mesh, traj, &p, &S, &G, dlogh, stream);
+        if (st == FLA_OK) st = fla_bandwidth_backward(ctx, md.dim, theta, N, z, o, dlogh, grad, stream);
+        if (st == FLA_OK) st = fla_adam_step(ctx, theta, m, v, grad, step, lr, beta1, beta2, eps, stream);
+        return st;
+    } catch (...) {
+        ctx->err = "internal error";
+        return FLA_ERR_DEVICE;
+    }
 }
 
 FLA_EXPORT const char* fla_last_error(const fla_ctx* ctx)

@@ -77,7 +77,7 @@ struct PsiArgs {
     void* out[4];
     void* den;
     unsigned long long* maxbits; // C: bit patterns of max |phi_k| (binary64)
-    double* qscale;              // C: 2^e_k
+    double* qscale;              // 5: 2^e_k per channel, then 2^f (fine word of binary64 sums)
     unsigned long long* stats;
     // tile buckets
     int pt[3];                   // tile edge per axis (cells)
@@ -105,6 +105,9 @@ template <typename R> struct PsiRec {
     R phi[4];
     uint32_t loc;
 };
+
+// integer words per channel sum: binary64 records add a fine remainder word
+template <typename R> struct PsiWords { static constexpr int value = sizeof(R) == 8 ? 2 : 1; };
 
 constexpr int kPsiMaxTiles = 16384;   // LDS histogram of the count pass <= 64 KiB
 constexpr int kPsiTilesPerBinLog = 6;

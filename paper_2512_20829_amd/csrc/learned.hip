@@ -247,6 +247,9 @@ __global__ __launch_bounds__(kWave * kMlpWaves) void k_features_mlp(TrajDev t, M
                 }
             }
         }
+        if (fraw && i < N && !ok)
+#pragma unroll
+            for (int k = 0; k < kFeat; ++k) fraw[(int64_t)k * N + i] = __builtin_nanf("");
 #pragma unroll
         for (int k = 0; k < 16; ++k) Z[wave][lane][k] = (k < kFeat && ok) ? bf16_bits(f[k]) : (unsigned short)0;
         vld[wave][lane] = ok ? 1 : 0;
@@ -293,6 +296,83 @@ __global__ __launch_bounds__(kWave * kMlpWaves) void k_features_mlp(TrajDev t, M
             wave_sync();
         }
     }
+}
+
+// ---------------------------------------------------------------- feature standardisation
+// Moments of the raw features over the valid trajectories (finite features;
+// skipped trajectories carry NaN), in a fixed order: thread j of block b
+// takes trajectories b * 256 + j + k * (grid * 256), the block adds its
+// threads in a fixed tree, and k_feat_accum adds the blocks in block order.
+// pass 0: [count, sum f_k]; pass 1: [count, sum (f_k - mean_k)^2] with the
+// mean from the finished pass-0 sums.
+constexpr int kMomBlocks = 1024;
+constexpr int kMomW = 1 + kFeat;
+
+__global__ __launch_bounds__(256) void k_feat_moments(const float* __restrict__ fraw, int64_t N, int pass,
+                                                      const double* __restrict__ acc0, double* __restrict__ part)
+{
+    __shared__ double red[kMomW][256];
+    double mean[kFeat];
+#pragma unroll
+    for (int k = 0; k < kFeat; ++k) mean[k] = (pass == 1 && acc0[0] > 0.0) ? acc0[1 + k] / acc0[0] : 0.0;
+    double v[kMomW] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+        const float f0 = fraw[i];
+        if (!isfinite(f0)) continue;
+        v[0] += 1.0;
+#pragma unroll
+        for (int k = 0; k < kFeat; ++k) {
+            const double d = (double)fraw[(int64_t)k * N + i] - mean[k];
+            v[1 + k] += pass == 0 ? d : d * d;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kMomW; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < kMomW; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < kMomW) part[(int64_t)blockIdx.x * kMomW + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_feat_accum(const double* __restrict__ part, int nblk, double* __restrict__ acc)
+{
+    if (threadIdx.x >= kMomW) return;
+    double a = acc[threadIdx.x];
+    for (int b = 0; b < nblk; ++b) a += part[(int64_t)b * kMomW + threadIdx.x];
+    acc[threadIdx.x] = a;
+}
+
+// mu = mean, sd = sample standard deviation (Bessel-corrected) + 1e-3
+__global__ void k_feat_finish(const double* __restrict__ acc0, const double* __restrict__ acc1, float* theta)
+{
+    const int k = threadIdx.x;
+    if (k >= kFeat) return;
+    const double n = acc0[0];
+    const double mean = n > 0.0 ? acc0[1 + k] / n : 0.0;
+    const double var = n > 1.0 ? acc1[1 + k] / (n - 1.0) : 0.0;
+    theta[kOffMu + k] = (float)mean;
+    theta[kOffSd + k] = (float)(sqrt(var) + 1e-3);
+}
+
+hipError_t launch_feat_moments(const float* fraw, int64_t N, int pass, const double* acc0, double* part, double* acc,
+                               hipStream_t s)
+{
+    if (N <= 0) return hipSuccess;
+    int nb = (int)((N + 255) / 256);
+    if (nb > kMomBlocks) nb = kMomBlocks;
+    hipLaunchKernelGGL(k_feat_moments, dim3(nb), dim3(256), 0, s, fraw, N, pass, acc0, part);
+    hipLaunchKernelGGL(k_feat_accum, dim3(1), dim3(64), 0, s, part, nb, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_feat_finish(const double* acc0, const double* acc1, float* theta, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_feat_finish, dim3(1), dim3(64), 0, s, acc0, acc1, theta);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- estimator backward
@@ -621,19 +701,21 @@ __global__ void k_grad_reduce(const float* partial, int nblocks, float* grad)
     grad[p] = (float)acc;
 }
 
-__global__ void k_adam(float* theta, float* mm, float* vv, const float* grad, double step, float lr, float b1, float b2,
-                       float eps)
+// Moments and update in binary64 from the binary64 hyper-parameters (1 - b
+// formed from b exactly as given), stored in binary32.
+__global__ void k_adam(float* theta, float* mm, float* vv, const float* grad, double step, double lr, double b1,
+                       double b2, double eps)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= kTrain) return;
-    float g = grad[p];
-    float m = b1 * mm[p] + (1.0f - b1) * g;
-    float v = b2 * vv[p] + (1.0f - b2) * g * g;
+    const double g = (double)grad[p];
+    const float m = (float)(b1 * (double)mm[p] + (1.0 - b1) * g);
+    const float v = (float)(b2 * (double)vv[p] + (1.0 - b2) * (g * g));
     mm[p] = m;
     vv[p] = v;
-    double mh = (double)m / (1.0 - pow((double)b1, step));
-    double vh = (double)v / (1.0 - pow((double)b2, step));
-    theta[p] = (float)((double)theta[p] - (double)lr * mh / (sqrt(vh) + (double)eps));
+    double mh = (double)m / (1.0 - pow(b1, step));
+    double vh = (double)v / (1.0 - pow(b2, step));
+    theta[p] = (float)((double)theta[p] - lr * mh / (sqrt(vh) + eps));
 }
 
 // ---------------------------------------------------------------- relative-L2 loss
@@ -745,8 +827,8 @@ hipError_t launch_mlp_backward(const float* theta, int64_t N, const float* z, co
     return hipGetLastError();
 }
 
-hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int64_t step, float lr, float b1, float b2,
-                       float eps, hipStream_t s)
+hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int64_t step, double lr, double b1,
+                       double b2, double eps, hipStream_t s)
 {
     hipLaunchKernelGGL(k_adam, dim3((kTrain + 255) / 256), dim3(256), 0, s, theta, m, v, grad, (double)step, lr, b1, b2, eps);
     return hipGetLastError();

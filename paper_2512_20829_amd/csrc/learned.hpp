@@ -41,8 +41,13 @@ int mlp_backward_blocks(int64_t N);
 template <int D>
 hipError_t launch_mlp_backward(const float* theta, int64_t N, const float* z, const float* o, const float* dlogh,
                                float* partial, int nblocks, float* grad, hipStream_t s);
-hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int64_t step, float lr, float b1, float b2,
-                       float eps, hipStream_t s);
+// feature standardisation: moments over valid trajectories in a fixed order
+constexpr int kMomParts = 1024 * 6;   // doubles of per-block partials
+hipError_t launch_feat_moments(const float* fraw, int64_t N, int pass, const double* acc0, double* part, double* acc,
+                               hipStream_t s);
+hipError_t launch_feat_finish(const double* acc0, const double* acc1, float* theta, hipStream_t s);
+hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int64_t step, double lr, double b1,
+                       double b2, double eps, hipStream_t s);
 template <typename R>
 hipError_t launch_loss(int C, int64_t M, Planes S, Planes Rf, MutPlanes G, bool want_grad, double* part, double* res,
                        hipStream_t s);

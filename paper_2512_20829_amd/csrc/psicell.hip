@@ -5,14 +5,21 @@
 // each phi_k is quantised to a multiple of 2^-e_k, e_k chosen from the
 // largest |phi_k| so that count * max|phi_k| * 2^e_k < 2^62 (no partial sum
 // can overflow int64), and the integers are added.  The quantisation error of
-// one particle is at most 2^-(e_k+1).
+// one particle is at most 2^-(e_k+1), which grows with the count; binary64
+// records therefore carry a second integer word per channel: the remainder
+// phi_k 2^e_k - rint(phi_k 2^e_k), in [-1/2, 1/2], quantised to 2^-f with
+// f = 62 - ceil(log2(count + 1)) (so the remainder sums cannot overflow
+// either).  A particle's error is then at most 2^-(e_k+f+1), below 2^-62
+// max|phi_k| for any count under 2^31, and each cell's value is formed from
+// the two exact sums.
 //
 // Particles arrive in arbitrary spatial order, so the sums are not formed by
 // global atomics (one contended 64-bit atomic per particle and channel) but
 // in streaming passes over coarse tiles of cells, grouped into bins of
 // kPsiTilesPerBin consecutive tiles:
 //   count   per particle, from its position only: the (tile, cell in tile)
-//           code (-1 outside a closed box or for a non-finite position);
+//           code (-1 outside a closed box, counted as outside, or for a
+//           non-finite position, counted as skipped);
 //           per-block tile and bin histograms in LDS, written tile-major
 //           and bin-major for exclusive scans that give every tile's bucket
 //           and every (bin, block) output range;
@@ -47,15 +54,17 @@ constexpr uint32_t kPsiSkipBit = 0x80000000u;  // skip mark of a binned record (
 static_assert(kPsiTilesPerBin == kWave, "the tile pass scans one tile per lane of one wave");
 static_assert(kPsiMaxBins <= 256, "the bin scans take one bin per thread of a 256-thread block");
 
-// Cell indices of a particle from its position alone: false for a
-// non-finite position or one outside a closed box (x == hi goes to the last
-// cell).
+// Cell indices of a particle from its position alone: 1 if it has a cell,
+// 0 for a position outside a closed box (x == hi goes to the last cell), -1
+// for a non-finite position.
 template <int D>
-__device__ inline bool psi_cell(const MeshDev& m, const double* x, int* idx)
+__device__ inline int psi_cell(const MeshDev& m, const double* x, int* idx)
 {
 #pragma unroll
+    for (int ax = 0; ax < D; ++ax)
+        if (!isfinite(x[ax])) return -1;
+#pragma unroll
     for (int ax = 0; ax < D; ++ax) {
-        if (!isfinite(x[ax])) return false;
         // floor((x - lo)/w): a multiply by 1/w differs from the rounded
         // quotient by a few ulps, which can change the floor only next to an
         // integer; there the quotient is formed exactly
@@ -63,7 +72,7 @@ __device__ inline bool psi_cell(const MeshDev& m, const double* x, int* idx)
         double q = dx * (1.0 / m.w[ax]);
         if (fabs(q - rint(q)) < 1e-6 * (1.0 + fabs(q))) q = dx / m.w[ax];
         double g = floor(q);
-        if (!(fabs(g) < 9.0e15)) return false;
+        if (!(fabs(g) < 9.0e15)) return 0;
         int64_t k = (int64_t)g;
         if (m.periodic[ax]) {
             k = posmod(k, m.n[ax]);
@@ -71,11 +80,11 @@ __device__ inline bool psi_cell(const MeshDev& m, const double* x, int* idx)
             if (k == m.n[ax] && x[ax] == m.hi[ax])
                 k = m.n[ax] - 1;
             else
-                return false;
+                return 0;
         }
         idx[ax] = (int)k;
     }
-    return true;
+    return 1;
 }
 
 // (tile, cell-in-tile) code of a valid particle: tile * cpt + cell in tile
@@ -106,7 +115,7 @@ __global__ __launch_bounds__(256) void k_psi_count(PsiArgs a)
     const int64_t beg = (int64_t)blockIdx.x * chunk;
     const int64_t end = beg + chunk < N ? beg + chunk : N;
     const int64_t stepw = (int64_t)blockDim.x * kPsiUnroll;
-    unsigned long long outside = 0;
+    unsigned long long outside = 0, bad = 0;
     for (int64_t p0 = beg + threadIdx.x; p0 < end; p0 += stepw) {
         double x[kPsiUnroll][3];
 #pragma unroll
@@ -121,11 +130,14 @@ __global__ __launch_bounds__(256) void k_psi_count(PsiArgs a)
             if (p >= end) break;
             int idx[3] = {0, 0, 0};
             int code = -1;
-            if (psi_cell<D>(a.m, x[u], idx)) {
+            const int where = psi_cell<D>(a.m, x[u], idx);
+            if (where > 0) {
                 code = psi_code<D>(a, idx);
                 atomicAdd(&hist[code >> a.cptlog], 1u);
-            } else {
+            } else if (where == 0) {
                 ++outside;
+            } else {
+                ++bad;
             }
             a.codes[p] = code;
         }
@@ -146,8 +158,12 @@ __global__ __launch_bounds__(256) void k_psi_count(PsiArgs a)
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) a.binhist[(int64_t)a.pnbins * gridDim.x] = 0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) outside += __shfl_xor(outside, o, kWave);
+    for (int o = 32; o > 0; o >>= 1) {
+        outside += __shfl_xor(outside, o, kWave);
+        bad += __shfl_xor(bad, o, kWave);
+    }
     if ((threadIdx.x % kWave) == 0 && outside) atomicAdd(&a.stats[ST_OUTSIDE], outside);
+    if ((threadIdx.x % kWave) == 0 && bad) atomicAdd(&a.stats[ST_SKIPPED], bad);
 }
 
 // Exclusive prefix sum of one value per thread of a 256-thread block, and
@@ -289,7 +305,7 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, kWave);
-    if ((threadIdx.x % kWave) == 0 && bad) atomicAdd(&a.stats[ST_OUTSIDE], bad);
+    if ((threadIdx.x % kWave) == 0 && bad) atomicAdd(&a.stats[ST_SKIPPED], bad);
     // per-block maxima (a separate pass reduces them: no contended atomics)
     __shared__ double bm[256 / kWave][4];
 #pragma unroll
@@ -416,6 +432,13 @@ __global__ void k_psi_scale(PsiArgs a)
     __syncthreads();
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double n = (double)(a.p.count > 0 ? a.p.count : 1);
+    {
+        // fine word of binary64 sums: remainders of at most 2^(f-1) each,
+        // at most count of them per cell, count < 2^fx
+        int fx;
+        frexp(n + 1.0, &fx);
+        a.qscale[4] = ldexp(1.0, 62 - fx);
+    }
     for (int k = 0; k < C; ++k) {
         double mx = __longlong_as_double((long long)a.maxbits[k]);
         int e = 0;
@@ -434,14 +457,16 @@ template <typename R, int D>
 __global__ __launch_bounds__(256) void k_psi_reduce(PsiArgs a)
 {
     constexpr int C = D + 1;
-    extern __shared__ unsigned long long sacc[];    // C * cpt sums, then cpt counts (u32)
+    constexpr int W = PsiWords<R>::value;           // integer words per channel sum
+    extern __shared__ unsigned long long sacc[];    // W * C * cpt sums, then cpt counts (u32)
     const int cpt = a.cpt;
-    unsigned int* scnt = reinterpret_cast<unsigned int*>(sacc + (size_t)C * cpt);
-    for (int i = threadIdx.x; i < C * cpt; i += blockDim.x) sacc[i] = 0ull;
+    unsigned int* scnt = reinterpret_cast<unsigned int*>(sacc + (size_t)W * C * cpt);
+    for (int i = threadIdx.x; i < W * C * cpt; i += blockDim.x) sacc[i] = 0ull;
     for (int i = threadIdx.x; i < cpt; i += blockDim.x) scnt[i] = 0u;
     double qs[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) qs[k] = a.qscale[k];
+    const double qf = a.qscale[4];                  // 2^f, the fine word's scale
     __syncthreads();
     const int tile = blockIdx.x;
     const int64_t nbk = a.nblocks;
@@ -464,8 +489,14 @@ __global__ __launch_bounds__(256) void k_psi_reduce(PsiArgs a)
             const int loc = (int)rec[u].loc;
 #pragma unroll
             for (int k = 0; k < C; ++k) {
-                long long qv = llrint((double)rec[u].phi[k] * qs[k]);
-                atomicAdd(&sacc[k * cpt + loc], (unsigned long long)qv);
+                const double v = (double)rec[u].phi[k] * qs[k];   // exact: a power-of-two scale
+                const double hi = rint(v);
+                atomicAdd(&sacc[k * cpt + loc], (unsigned long long)(long long)hi);
+                if (W == 2) {
+                    // v - hi is exact (|v - hi| <= 1/2 and hi is v's nearest integer)
+                    const long long lo = llrint((v - hi) * qf);
+                    atomicAdd(&sacc[(C + k) * cpt + loc], (unsigned long long)lo);
+                }
             }
             if (count) atomicAdd(&scnt[loc], 1u);
         }
@@ -490,7 +521,9 @@ __global__ __launch_bounds__(256) void k_psi_reduce(PsiArgs a)
         double f = fw * cs;
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            double sum = (double)(long long)sacc[k * cpt + loc] / qs[k];
+            double units = (double)(long long)sacc[k * cpt + loc];
+            if (W == 2) units += (double)(long long)sacc[(C + k) * cpt + loc] / qf;
+            const double sum = units / qs[k];
             ((R*)a.out[k])[c] = (R)(f * sum);
         }
         if (a.den) ((R*)a.den)[c] = (R)scnt[loc];
@@ -566,7 +599,7 @@ hipError_t launch_psicell(const PsiArgs& a, hipStream_t s)
     hipLaunchKernelGGL((k_psi_scale<D>), dim3(1), dim3(256), 0, s, a);
     if (a.p.count > 0)
         hipLaunchKernelGGL((k_psi_tiles<R, D>), dim3(a.pnbins * a.nsplit), dim3(256), 0, s, a);
-    size_t lds_r = (sizeof(unsigned long long) * C + sizeof(unsigned int)) * (size_t)a.cpt;
+    size_t lds_r = (sizeof(unsigned long long) * C * PsiWords<R>::value + sizeof(unsigned int)) * (size_t)a.cpt;
     hipLaunchKernelGGL((k_psi_reduce<R, D>), dim3(a.pntiles), dim3(256), lds_r, s, a);
     return hipGetLastError();
 }

@@ -1,9 +1,10 @@
 """Training and evaluation of the learned bandwidth correction on the GPU.
 
-One training step (all arithmetic in the library's kernels, one stream):
-  features + network -> h factors -> estimator projection -> relative-L2
-  loss against the reference field and dL/dS -> estimator backward
-  (dL/dlog h) -> network backward (dL/dtheta) -> Adam.
+One training step is one library call, fla_mlp_train_step (all arithmetic
+in the library's kernels, one stream): features + network -> h factors ->
+estimator projection -> relative-L2 loss against the reference field and
+dL/dS -> estimator backward (dL/dlog h) -> network backward (dL/dtheta) ->
+Adam.  The feature standardisation is fla_bandwidth_standardise.
 
 The reference field of a snapshot is the PSI-CELL accumulation of a dense
 particle cloud drawn from the same flow map, computed by the same library.
@@ -99,6 +100,16 @@ class BandwidthModel:
         return res, G
 
     def train_step(self, snap: Snapshot) -> torch.Tensor:
+        """One step through fla_mlp_train_step; returns the loss terms."""
+        res = torch.empty(1 + 2 * (1 + snap.mesh.dim), dtype=torch.float64, device=DEV)
+        self.step_count += 1
+        p = Params(**{**snap.params.__dict__, "h_factor": None})
+        self.ctx.mlp_train_step(mesh_of(snap.mesh), snap.traj, p, snap.ref, self.theta, self.m, self.v,
+                                self.step_count, lr=self.lr, loss=res)
+        return res
+
+    def train_step_composed(self, snap: Snapshot) -> torch.Tensor:
+        """The same step as six separate library calls."""
         hf, z, o = self.factors(snap)
         S, den, p = self.project(snap, hf)
         res, G = self.loss(snap, S, True)
@@ -118,20 +129,11 @@ class BandwidthModel:
 
 def fit_standardisation(ctx: Context, snaps: List[Snapshot], theta: np.ndarray) -> np.ndarray:
     """Set mu, sd of the parameter block to the mean and spread of the raw
-    features over the given snapshots (valid trajectories)."""
-    feats = []
+    features over the valid trajectories of the given snapshots
+    (fla_bandwidth_standardise)."""
     th = torch.tensor(np.asarray(theta, dtype=np.float32), device=DEV)
-    for s in snaps:
-        hf = torch.empty(s.count, dtype=torch.float32, device=DEV)
-        fr = torch.empty(5 * s.count, dtype=torch.float32, device=DEV)
-        ctx.bandwidth_forward(mesh_of(s.mesh), s.traj, th, hf, None, None, fr)
-        f = fr.view(5, s.count)
-        feats.append(f[:, f[3] != 0])
-    f = torch.cat(feats, dim=1).double()
-    th = np.asarray(theta, dtype=np.float64).copy()
-    th[MLP_TRAINABLE:MLP_TRAINABLE + 5] = f.mean(dim=1).cpu().numpy()
-    th[MLP_TRAINABLE + 5:] = (f.std(dim=1) + 1e-3).cpu().numpy()
-    return th
+    ctx.bandwidth_standardise([mesh_of(s.mesh) for s in snaps], [s.traj for s in snaps], th)
+    return th.cpu().numpy().astype(np.float64)
 
 
 def initial_theta(seed: int = 0) -> np.ndarray:

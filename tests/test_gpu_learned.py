@@ -8,8 +8,12 @@ closed-form 3x3 eigen-solution, the oracle with LAPACK); network outputs to
 2e-3 absolute + relative, because a pre-activation that lands within one
 binary32 rounding of a bf16 rounding boundary may round the other way on the
 other side (a one-ulp bf16 step is 2^-8 relative); gradients through the
-estimator to 1e-5 relative L2 (FP32 per-cell planes); network gradients to
-2e-3 relative L2 (bf16 inputs; deltas carried as bf16 hi + lo pairs)."""
+estimator to 1e-6 relative L2 on the binary64 path and 1e-5 on the binary32
+one (binary32 per-cell planes); network gradients, alone and through the
+whole chain, to 1e-3 relative L2 (bf16 inputs; deltas carried as bf16 hi +
+lo pairs).  The measured errors are printed: about 6e-8 and 2e-6 for the
+estimator backward, 3e-6 for the network backward and 1e-5 through the
+chain."""
 import numpy as np
 import pytest
 import torch
@@ -154,10 +158,13 @@ def test_gradient_chain_matches_oracle(ctx, prec):
     R = Sr * (1.0 + 0.3 * rng.standard_normal(Sr.shape))        # a perturbed reference field
     res, dlogh, grad, S = _gpu_chain(ctx, wl, theta, R, prec)
     L, dlogh_ref, grad_ref, S_ref = _oracle_chain(wl, theta, R, prec)
-    assert rel_l2(S, S_ref) < 2e-3
-    assert res[0] == pytest.approx(L, rel=1e-2)
-    assert rel_l2(dlogh, dlogh_ref) < 2e-2
-    assert rel_l2(grad[:LN.N_TRAIN], grad_ref[:LN.N_TRAIN]) < 2e-2
+    eS, ed, eg = rel_l2(S, S_ref), rel_l2(dlogh, dlogh_ref), rel_l2(grad[:LN.N_TRAIN], grad_ref[:LN.N_TRAIN])
+    print(f"[gradient-chain] {prec}: S {eS:.2e} loss {abs(res[0] / L - 1):.2e} dL/dlog h {ed:.2e} "
+          f"dL/dtheta {eg:.2e}", flush=True)
+    assert eS < 1e-4
+    assert res[0] == pytest.approx(L, rel=1e-4)
+    assert ed < 1e-3
+    assert eg < 1e-3
     assert np.all(grad[LN.N_TRAIN:] == 0.0)
 
 
@@ -190,7 +197,9 @@ def test_estimator_backward_with_shared_factors(ctx):
         ctx.project_backward(mesh, st, prm, Sm, Sv, den, G[0], G[1:], out)
         torch.cuda.synchronize()
         assert float(res[0]) == pytest.approx(L, rel=1e-5 if prec == "f32" else 1e-10)
-        assert rel_l2(out.cpu().double().numpy(), ref) < 1e-5
+        e = rel_l2(out.cpu().double().numpy(), ref)
+        print(f"[estimator-backward] {prec}: rel L2 {e:.2e}", flush=True)
+        assert e < (1e-5 if prec == "f32" else 1e-6)
 
 
 def test_network_backward_and_adam(ctx):
@@ -211,7 +220,9 @@ def test_network_backward_and_adam(ctx):
     torch.cuda.synchronize()
     ref = LN.backward(theta, fw, dlogh * LN.S_MAX * (1 - np.tanh(fw.o) ** 2))
     g = grad.cpu().double().numpy()
-    assert rel_l2(g[:LN.N_TRAIN], ref[:LN.N_TRAIN]) < 2e-3
+    eg = rel_l2(g[:LN.N_TRAIN], ref[:LN.N_TRAIN])
+    print(f"[network-backward] rel L2 {eg:.2e}", flush=True)
+    assert eg < 1e-3
     # Adam on a seeded gradient
     gs = rng.standard_normal(F.MLP_PARAMS).astype(np.float32).astype(np.float64)
     m = torch.zeros(F.MLP_PARAMS, dtype=torch.float32, device=DEV)
@@ -219,8 +230,20 @@ def test_network_backward_and_adam(ctx):
     th2 = th.clone()
     ctx.adam_step(th2, m, v, torch.tensor(gs, dtype=torch.float32, device=DEV), 1, lr=1e-3)
     torch.cuda.synchronize()
-    t1, _, _ = LN.adam(theta, gs, np.zeros_like(theta), np.zeros_like(theta), 1, lr=1e-3)
+    t1, m1, v1 = LN.adam(theta, gs, np.zeros_like(theta), np.zeros_like(theta), 1, lr=1e-3)
     np.testing.assert_allclose(th2.cpu().double().numpy(), t1, rtol=1e-6, atol=1e-9)
+    # steps 2 and 3 with new gradients: the bias corrections 1 - b^step
+    tk, mk, vk = t1, m1, v1
+    for step in (2, 3):
+        gk = rng.standard_normal(F.MLP_PARAMS).astype(np.float32).astype(np.float64)
+        ctx.adam_step(th2, m, v, torch.tensor(gk, dtype=torch.float32, device=DEV), step, lr=1e-3)
+        torch.cuda.synchronize()
+        tk, mk, vk = LN.adam(tk, gk, mk, vk, step, lr=1e-3)
+        np.testing.assert_allclose(th2.cpu().double().numpy(), tk, rtol=1e-6, atol=1e-9)
+        # moments of the trainable entries (binary32 on the GPU: an absolute floor for cancellation)
+        T = slice(0, LN.N_TRAIN)
+        np.testing.assert_allclose(m.cpu().double().numpy()[T], mk[T], rtol=1e-5, atol=1e-7)
+        np.testing.assert_allclose(v.cpu().double().numpy()[T], vk[T], rtol=1e-5, atol=1e-9)
 
 
 @pytest.mark.slow

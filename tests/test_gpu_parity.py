@@ -212,10 +212,10 @@ def test_psicell_taylor_green_cloud_f64(ctx):
     cloud = W.taylor_green_cloud()
     w = W.N0_DEFAULT / cloud.count
     S, den, st = gpu_run(ctx, wl, prec="f64", psicell_cloud=cloud, weight=w)
-    Sref, counts, sk = oracle.psicell(wl.mesh, cloud, w, wl.rho_d, wl.mu, wl.delta)
+    Sref, counts, out, nf = oracle.psicell(wl.mesh, cloud, w, wl.rho_d, wl.mu, wl.delta, split=True)
     assert_fields_close(S, Sref, TOL["f64"], "psicell f64")
     assert np.array_equal(den.astype(np.int64), counts)
-    assert st["outside"] == sk
+    assert st["outside"] == out and st["skipped"] == nf
 
 
 def test_psicell_3d_f32_with_outside_particles(ctx):
@@ -225,10 +225,10 @@ def test_psicell_3d_f32_with_outside_particles(ctx):
     w = 3.0
     S, den, st = gpu_run(ctx, wl, prec="f32", psicell_cloud=cloud, weight=w)
     c64 = as_precision(cloud, "f32")
-    Sref, counts, sk = oracle.psicell(wl.mesh, c64, w, wl.rho_d, wl.mu, wl.delta)
+    Sref, counts, out, nf = oracle.psicell(wl.mesh, c64, w, wl.rho_d, wl.mu, wl.delta, split=True)
     assert_fields_close(S, Sref, TOL["f32"], "psicell f32")
     assert np.array_equal(den.astype(np.int64), counts)
-    assert st["outside"] == sk and sk > 0
+    assert st["outside"] == out and out > 0 and st["skipped"] == nf == 0
 
 
 def test_psicell_deterministic(ctx):
@@ -271,7 +271,12 @@ def test_psicell_edge_cases(ctx):
     # every record skipped (non-finite radius): no cell receives anything
     bad = W.Trajectories(base.x, base.J, base.v, base.ug, torch.full_like(base.r, float("nan")), 1.0)
     S, den, st = gpu_run(ctx, wl, prec="f32", psicell_cloud=bad, weight=1.0)
-    assert np.all(S == 0.0) and np.all(den == 0.0) and st["outside"] == 1000
+    assert np.all(S == 0.0) and np.all(den == 0.0) and st["skipped"] == 1000 and st["outside"] == 0
+    # non-finite positions are skipped too, not outside
+    nanx = W.Trajectories(base.x.clone(), base.J, base.v, base.ug, base.r, 1.0)
+    nanx.x[1, ::10] = float("nan")
+    S, den, st = gpu_run(ctx, wl, prec="f32", psicell_cloud=nanx, weight=1.0)
+    assert st["skipped"] == 100 and st["outside"] == 0 and int(den.sum()) == 900
     # one particle, with a cell scale
     one = base.subset(torch.arange(1))
     cs = np.linspace(0.5, 1.5, wl.mesh.cells)
@@ -327,6 +332,50 @@ def test_psicell_full_size_sampled_cells(ctx):
     assert np.array_equal(den[cells].cpu().numpy().astype(np.int64), counts[cells])
 
 
+@pytest.mark.timeout(300)
+def test_psicell_binary64_100m_particles_sampled_cells(ctx):
+    """Binary64 PSI-CELL over 100M particles on a 96^3 periodic mesh (about
+    113 particles per cell): the per-particle quantisation error must not
+    grow with the count, so 256 sampled cells match the oracle, run over the
+    particles in and next to them, within 1e-12."""
+    import paper_2512_20829_amd as F
+    dev = torch.device("cuda", 0)
+    wl = W.small_random_3d(10, 96, seed=26, periodic=True)
+    n = wl.mesh.n[0]
+    Np = 100_000_000
+    print(f"[case] psicell f64 N={Np} mesh={wl.mesh.n}", flush=True)
+    cl = W.abc_cloud(Np, seed=26, device=dev, jacobian=False)
+    st, _ = F.make_trajectories(cl.x.contiguous(), None, cl.v.contiguous(), cl.ug.contiguous(),
+                               cl.r.contiguous(), 1.0)
+    M = wl.mesh.cells
+    Sm, Sv, den = F.alloc_fields(M, 3, torch.float64, dev)
+    w = W.N0_DEFAULT / Np
+    p = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
+    ctx.psicell_accumulate(F.mesh_of(wl.mesh), st, w, p, Sm, Sv, den)
+    torch.cuda.synchronize()
+    stats = ctx.stats()
+    assert int(den.sum().item()) == Np and stats["outside"] == 0 and stats["skipped"] == 0
+    S = torch.stack([Sm, *Sv]).cpu().numpy()
+    g = np.random.default_rng(3)
+    cells = np.sort(g.choice(M, 256, replace=False))
+    near = torch.zeros((n, n, n), dtype=torch.bool, device=dev)      # [z, y, x]
+    c = torch.as_tensor(cells, device=dev)
+    cz, cy, cx = c // (n * n), (c // n) % n, c % n
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                near[(cz + dz) % n, (cy + dy) % n, (cx + dx) % n] = True
+    ix = torch.floor(cl.x * n).to(torch.int64) % n
+    pick = near[ix[2], ix[1], ix[0]]
+    del ix
+    sub = W.Trajectories(cl.x[:, pick].cpu(), torch.empty(0, dtype=torch.float64), cl.v[:, pick].cpu(),
+                         cl.ug[:, pick].cpu(), cl.r[pick].cpu(), 1.0)
+    print(f"[case] psicell f64 oracle over {sub.count} particles near the sampled cells", flush=True)
+    Sref, counts, _ = oracle.psicell(wl.mesh, sub, w, wl.rho_d, wl.mu, wl.delta)
+    assert_fields_close(S[:, cells], Sref[:, cells], TOL["f64"], "psicell f64 100M sampled")
+    assert np.array_equal(den[cells].cpu().numpy().astype(np.int64), counts[cells])
+
+
 def test_psicell_many_bins_with_skipped_records_f32(ctx):
     # 100^3 cells: 7 x 13 x 13 = 1183 tiles of 16 x 8 x 8 cells, so 19 bins
     # of 64 tiles with a partial last bin; particles outside the closed box and records
@@ -339,10 +388,10 @@ def test_psicell_many_bins_with_skipped_records_f32(ctx):
     w = 0.5
     S, den, st = gpu_run(ctx, wl, prec="f32", psicell_cloud=cloud, weight=w)
     c64 = as_precision(cloud, "f32")
-    Sref, counts, sk = oracle.psicell(wl.mesh, c64, w, wl.rho_d, wl.mu, wl.delta)
+    Sref, counts, out, nf = oracle.psicell(wl.mesh, c64, w, wl.rho_d, wl.mu, wl.delta, split=True)
     assert_fields_close(S, Sref, TOL["f32"], "psicell many bins f32")
     assert np.array_equal(den.astype(np.int64), counts)
-    assert st["outside"] == sk and sk > 4000
+    assert st["outside"] == out and out > 4000 and st["skipped"] == nf and nf > 2000
 
 
 def test_psicell_many_bins_2d_f64(ctx):
@@ -351,10 +400,10 @@ def test_psicell_many_bins_2d_f64(ctx):
     cloud = W.taylor_green_cloud(3_000_000, seed=22)
     w = W.N0_DEFAULT / cloud.count
     S, den, st = gpu_run(ctx, wl, prec="f64", psicell_cloud=cloud, weight=w)
-    Sref, counts, sk = oracle.psicell(wl.mesh, cloud, w, wl.rho_d, wl.mu, wl.delta)
+    Sref, counts, out, nf = oracle.psicell(wl.mesh, cloud, w, wl.rho_d, wl.mu, wl.delta, split=True)
     assert_fields_close(S, Sref, TOL["f64"], "psicell many bins f64")
     assert np.array_equal(den.astype(np.int64), counts)
-    assert st["outside"] == sk
+    assert st["outside"] == out and st["skipped"] == nf
 
 
 # ------------------------------------------------------------------ plans / autotuner

@@ -70,3 +70,83 @@ def test_checkpoint_resume_is_bitwise(setup):
         c.train_step(snaps[it % 4])
     torch.cuda.synchronize()
     assert torch.equal(b.theta, c.theta) and torch.equal(b.m, c.m) and torch.equal(b.v, c.v)
+
+
+def test_library_train_step_equals_the_six_call_composition(setup):
+    """fla_mlp_train_step against the same stages called one by one:
+    parameters, moments and loss bit for bit over several steps."""
+    from paper_2512_20829_amd import train as T
+    ctx, snaps, theta = setup
+    a = T.BandwidthModel(ctx, theta, lr=2e-3)
+    b = T.BandwidthModel(ctx, theta, lr=2e-3)
+    for it in range(7):
+        ra = a.train_step(snaps[it % 4])
+        rb = b.train_step_composed(snaps[it % 4])
+        torch.cuda.synchronize()
+        assert torch.equal(ra, rb), it
+    assert torch.equal(a.theta, b.theta) and torch.equal(a.m, b.m) and torch.equal(a.v, b.v)
+    assert not torch.equal(a.theta, torch.tensor(theta, dtype=torch.float32, device=DEV))
+
+
+def test_train_step_rejects_bad_arguments(setup):
+    import paper_2512_20829_amd as F
+    from paper_2512_20829_amd import train as T
+    ctx, snaps, theta = setup
+    model = T.BandwidthModel(ctx, theta)
+    s = snaps[0]
+    before = model.theta.clone()
+    bad = [F.Params(**{**s.params.__dict__, "mode": F.FLA_DEPOSIT}),
+           F.Params(**{**s.params.__dict__, "h_factor": torch.ones(s.count, device=DEV)}),
+           F.Params(**{**s.params.__dict__, "h0": -1.0})]
+    for p in bad:
+        with pytest.raises(F.FlaError) as e:
+            ctx.mlp_train_step(F.mesh_of(s.mesh), s.traj, p, s.ref, model.theta, model.m, model.v, 1)
+        assert e.value.status == F.FLA_ERR_INVALID_ARG
+    with pytest.raises(F.FlaError):
+        ctx.mlp_train_step(F.mesh_of(s.mesh), s.traj, s.params, s.ref, model.theta, model.m, model.v, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(model.theta, before)
+
+
+def test_standardisation_over_valid_trajectories():
+    """fla_bandwidth_standardise against numpy over the trajectories the
+    oracle finds valid, with trajectories whose |det J| is exactly 1 (raw
+    feature log(n/n0) = 0, still valid) and skipped ones (det J = 0)."""
+    import oracle
+    import oracle.learned as LN
+    import paper_2512_20829_amd as F
+    from helpers import as_precision, device_traj
+    ctx = F.Context(0)
+    try:
+        wls = [W.small_random_3d(3000, 12, seed=60 + k, periodic=True) for k in range(3)]
+        for k, wl in enumerate(wls):
+            J = wl.traj.J.clone()
+            J[:, :50] = torch.eye(3, dtype=torch.float64).reshape(9, 1)      # |det J| = 1
+            J[:, 50:60] = 0.0                                                 # det J = 0: skipped
+            wl.traj.J = J
+        feats = []
+        for wl in wls:
+            tr = as_precision(wl.traj, "f32")
+            t = oracle.trajectory_terms(tr, wl.rho_d, wl.mu, wl.delta, wl.h0)
+            f = LN.features(wl.mesh, tr.x.numpy(), tr.J.numpy(), t.valid)
+            feats.append(f[:, t.valid == 1])
+            assert (t.valid[:50] == 1).all() and (t.valid[50:60] == 0).all()
+        fall = np.concatenate(feats, axis=1)
+        mu_ref, sd_ref = fall.mean(axis=1), fall.std(axis=1, ddof=1) + 1e-3
+        structs = [device_traj(wl.traj, "f32") for wl in wls]
+        th = torch.zeros(F.MLP_PARAMS, dtype=torch.float32, device=DEV)
+        th[F.MLP_TRAINABLE + 5:] = 1.0
+        ctx.bandwidth_standardise([F.mesh_of(wl.mesh) for wl in wls], [s for s, _ in structs], th)
+        torch.cuda.synchronize()
+        got = th.cpu().double().numpy()
+        print(f"[standardise] mu {got[F.MLP_TRAINABLE:F.MLP_TRAINABLE + 5]} ref {mu_ref}", flush=True)
+        np.testing.assert_allclose(got[F.MLP_TRAINABLE:F.MLP_TRAINABLE + 5], mu_ref, rtol=2e-6, atol=2e-6)
+        np.testing.assert_allclose(got[F.MLP_TRAINABLE + 5:], sd_ref, rtol=2e-6, atol=2e-6)
+        assert np.all(got[:F.MLP_TRAINABLE] == 0.0)
+        # deterministic
+        th2 = th.clone()
+        ctx.bandwidth_standardise([F.mesh_of(wl.mesh) for wl in wls], [s for s, _ in structs], th2)
+        torch.cuda.synchronize()
+        assert torch.equal(th, th2)
+    finally:
+        ctx.close()
