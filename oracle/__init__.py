@@ -52,6 +52,11 @@ class OrcMesh(C.Structure):
                 ("hi", C.c_double * 3), ("periodic", C.c_int * 3)]
 
 
+class OrcFlow(C.Structure):
+    _fields_ = [("kind", C.c_int), ("U", C.c_double), ("k", C.c_double), ("abc", C.c_double * 3),
+                ("phase", C.c_double * 3), ("u0", C.c_double * 3), ("G", C.c_double * 9)]
+
+
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
 _lp = C.POINTER(C.c_int64)
@@ -86,6 +91,14 @@ def _declare(L):
                               C.c_double, C.c_double, C.c_double, _dp, _dp, _lp, _lp]
     L.orc_psicell_cell_of.restype = C.c_int64
     L.orc_psicell_cell_of.argtypes = [C.POINTER(OrcMesh), _dp]
+    L.orc_flow_eval.restype = None
+    L.orc_flow_eval.argtypes = [C.c_int, C.POINTER(OrcFlow), _dp, _dp, _dp]
+    L.orc_advance.restype = C.c_int64
+    L.orc_advance.argtypes = [C.c_int, C.c_int64, _dp, _dp, _dp, _dp, _dp, C.POINTER(OrcFlow), C.c_double,
+                              C.c_double, C.c_double, C.c_double, C.c_int, _dp, _ip]
+    L.orc_state_terms.restype = C.c_int64
+    L.orc_state_terms.argtypes = [C.c_int, C.c_int64, _dp, _dp, _dp, _ip, _dp, C.c_double, C.c_double, _dp, _dp,
+                                  _dp, _dp, _ip]
     L.orc_app_a_scaling.restype = None
     L.orc_app_a_scaling.argtypes = [C.c_double] * 7 + [_dp]
     L.orc_num_threads.restype = C.c_int
@@ -343,3 +356,82 @@ def project(mesh, traj, rho_d, mu, delta, h0, cutoff=4.0, f32_decision=False, sc
     """Whole plain path: terms, then the estimator at all (or listed) cells."""
     t = trajectory_terms(traj, rho_d, mu, delta, h0, h_factor)
     return nw_cells(mesh, traj.x, t, cells, cutoff, f32_decision, scale, cell_scale), t
+
+
+# ---------------------------------------------------------------------------
+# Trajectory producer (eqs. Stokes-drag, evap-model, Jacobian-evolution; App. B 1a-1b)
+FLOW_NONE, FLOW_TAYLOR_GREEN, FLOW_ABC = 0, 1, 2
+
+
+def make_flow(kind: int = FLOW_NONE, U: float = 0.0, k: float = 1.0, abc=(1.0, 1.0, 1.0), phase=(0.0, 0.0, 0.0),
+              u0=(0.0, 0.0, 0.0), G=None) -> OrcFlow:
+    """Gas field u = u0 + G x + (Taylor-Green or ABC part of amplitude U and wavenumber k)."""
+    f = OrcFlow()
+    f.kind, f.U, f.k = int(kind), float(U), float(k)
+    pad = lambda t: list(t) + [0.0] * (3 - len(t))
+    abc, phase, u0 = pad(abc), pad(phase), pad(u0)
+    for a in range(3):
+        f.abc[a], f.phase[a], f.u0[a] = float(abc[a]), float(phase[a]), float(u0[a])
+    Gm = np.zeros((3, 3)) if G is None else np.asarray(G, dtype=np.float64)
+    Gp = np.zeros((3, 3))
+    Gp[:Gm.shape[0], :Gm.shape[1]] = Gm
+    for e in range(9):
+        f.G[e] = float(Gp.reshape(-1)[e])
+    return f
+
+
+def flow_eval(dim: int, flow: OrcFlow, x):
+    """(u (dim,), grad u (dim, dim)) at one point."""
+    xv = _f64(list(x) + [0.0] * (3 - len(x)))
+    u = np.zeros(3)
+    gu = np.zeros(dim * dim)
+    lib().orc_flow_eval(dim, C.byref(flow), _d(xv), _d(u), _d(gu))
+    return u[:dim].copy(), gu.reshape(dim, dim)
+
+
+@dataclass
+class DropletState:
+    """Binary64 state planes: x, v (dim, N); J, K = dJ/dt (dim*dim, N), entry a*dim+b; r (N,)."""
+    x: np.ndarray
+    v: np.ndarray
+    J: np.ndarray
+    K: np.ndarray
+    r: np.ndarray
+
+    @property
+    def dim(self):
+        return self.x.shape[0]
+
+    def copy(self):
+        return DropletState(self.x.copy(), self.v.copy(), self.J.copy(), self.K.copy(), self.r.copy())
+
+
+def advance(state: DropletState, flow: OrcFlow, rho_d: float, mu: float, delta: float, dt: float,
+            substeps: int):
+    """Advance a copy of the state by dt (RK4, `substeps` substeps); returns
+    (new state, phibar (1 + dim, N) source rates of the step, valid (N,), skipped)."""
+    st = DropletState(*(np.ascontiguousarray(np.array(a, dtype=np.float64)) for a in
+                        (state.x, state.v, state.J, state.K, state.r)))
+    dim, N = st.x.shape
+    phibar = np.zeros((1 + dim, N))
+    valid = np.zeros(N, dtype=np.int32)
+    sk = lib().orc_advance(dim, N, _d(st.x), _d(st.v), _d(st.J), _d(st.K), _d(st.r), C.byref(flow), rho_d, mu,
+                           delta, dt, int(substeps), _d(phibar), valid.ctypes.data_as(_ip))
+    return st, phibar, valid, int(sk)
+
+
+def state_terms(state: DropletState, phibar: np.ndarray, valid: np.ndarray, n0, h0: float) -> Terms:
+    """Estimator terms of advanced droplets (q = n * phibar)."""
+    dim, N = state.x.shape
+    n0_arr = _f64(n0) if np.ndim(n0) == 1 else None
+    det_ = np.zeros(N)
+    h = np.zeros(N)
+    n = np.zeros(N)
+    q = np.zeros((1 + dim, N))
+    vout = np.zeros(N, dtype=np.int32)
+    vin = np.ascontiguousarray(valid, dtype=np.int32)
+    sk = lib().orc_state_terms(dim, N, _d(_f64(state.x)), _d(_f64(state.J)), _d(_f64(phibar)),
+                               vin.ctypes.data_as(_ip), _d(n0_arr) if n0_arr is not None else None,
+                               0.0 if n0_arr is not None else float(n0), h0, _d(det_), _d(h), _d(n), _d(q),
+                               vout.ctypes.data_as(_ip))
+    return Terms(det_, h, n, q, vout, int(sk))

@@ -753,6 +753,197 @@ int64_t orc_psicell(const orc_mesh* m, int64_t Np, const double* x, const double
 }
 
 /* ------------------------------------------------------------------------ */
+/* Trajectory producer: droplets advanced over one carrier time step in an  */
+/* analytic gas field (eqs. Stokes-drag, evap-model and Jacobian-evolution, */
+/* dimensional forms), with the droplet's mass and momentum contributions   */
+/* summed over the substeps (App. B steps 1a-1b).                           */
+/*   x' = v,  v' = (u(x) - v)/tau(r),  r' = delta/(2 r),                    */
+/*   J' = K,  K' = (grad u(x) J - K)/tau(r),                                */
+/*   Q_mass' = mdot = 4 pi rho r^2 r',  Q_mom' = F + mdot v,                */
+/*   tau = 2 rho r^2/(9 mu), F = m (u - v)/tau, m = 4/3 pi rho r^3,         */
+/* integrated with the classical fourth-order Runge-Kutta method over       */
+/* `substeps` equal substeps; the step's source rates are phibar = Q/dt.    */
+/* The gas field is u = u0 + G x + (a periodic part by kind): 0 none, 1 the */
+/* Taylor-Green vortex U (sin(w x) cos(w y), -cos(w x) sin(w y)) in 2-D, 2  */
+/* the ABC flow U (A sin(w z + pz) + C cos(w y + py), B sin(w x + px) +     */
+/* A cos(w z + pz), C sin(w y + py) + B cos(w x + px)) in 3-D; w = 2 pi k.  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int kind;
+    double U, k;
+    double abc[3];
+    double phase[3];
+    double u0[3];
+    double G[9];   /* du_a/dx_b at G[a*3 + b] */
+} orc_flow;
+
+void orc_flow_eval(int dim, const orc_flow* f, const double* x, double* u, double* gu /* dim*dim */)
+{
+    for (int a = 0; a < dim; ++a) {
+        u[a] = f->u0[a];
+        for (int b = 0; b < dim; ++b) {
+            u[a] += f->G[a * 3 + b] * x[b];
+            gu[a * dim + b] = f->G[a * 3 + b];
+        }
+    }
+    double w = 2.0 * ORC_PI * f->k, U = f->U;
+    if (f->kind == 1 && dim == 2) {
+        double sx = sin(w * x[0]), cx = cos(w * x[0]), sy = sin(w * x[1]), cy = cos(w * x[1]);
+        u[0] += U * sx * cy;
+        u[1] -= U * cx * sy;
+        gu[0] += U * w * cx * cy;
+        gu[1] -= U * w * sx * sy;
+        gu[2] += U * w * sx * sy;
+        gu[3] -= U * w * cx * cy;
+    } else if (f->kind == 2 && dim == 3) {
+        double A = f->abc[0], B = f->abc[1], C = f->abc[2];
+        double ax = w * x[0] + f->phase[0], ay = w * x[1] + f->phase[1], az = w * x[2] + f->phase[2];
+        double sx = sin(ax), cx = cos(ax), sy = sin(ay), cy = cos(ay), sz = sin(az), cz = cos(az);
+        u[0] += U * (A * sz + C * cy);
+        u[1] += U * (B * sx + A * cz);
+        u[2] += U * (C * sy + B * cx);
+        gu[0 * 3 + 1] -= U * C * w * sy;
+        gu[0 * 3 + 2] += U * A * w * cz;
+        gu[1 * 3 + 0] += U * B * w * cx;
+        gu[1 * 3 + 2] -= U * A * w * sz;
+        gu[2 * 3 + 0] -= U * B * w * sx;
+        gu[2 * 3 + 1] += U * C * w * cy;
+    }
+}
+
+/* State vector y = [x (d), v (d), r, J (d*d), K (d*d), Q (1 + d)] and its  */
+/* time derivative.                                                          */
+static void producer_rhs(int dim, const orc_flow* f, double rho, double mu, double delta, const double* y,
+                         double* dy)
+{
+    const double* x = y;
+    const double* v = y + dim;
+    double r = y[2 * dim];
+    const double* J = y + 2 * dim + 1;
+    const double* K = J + dim * dim;
+    double u[3], gu[9];
+    orc_flow_eval(dim, f, x, u, gu);
+    double tau = 2.0 * rho * r * r / (9.0 * mu);
+    double m = (4.0 / 3.0) * ORC_PI * rho * r * r * r;
+    double rdot = delta / (2.0 * r);
+    double mdot = 4.0 * ORC_PI * rho * r * r * rdot;
+    double* dx = dy;
+    double* dv = dy + dim;
+    double* dJ = dy + 2 * dim + 1;
+    double* dK = dJ + dim * dim;
+    double* dQ = dK + dim * dim;
+    for (int a = 0; a < dim; ++a) {
+        dx[a] = v[a];
+        dv[a] = (u[a] - v[a]) / tau;
+    }
+    dy[2 * dim] = rdot;
+    for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) {
+            double gJ = 0.0;
+            for (int c = 0; c < dim; ++c) gJ += gu[a * dim + c] * J[c * dim + b];
+            dJ[a * dim + b] = K[a * dim + b];
+            dK[a * dim + b] = (gJ - K[a * dim + b]) / tau;
+        }
+    dQ[0] = mdot;
+    for (int a = 0; a < dim; ++a) {
+        double F = m * (u[a] - v[a]) / tau;
+        dQ[1 + a] = F + mdot * v[a];
+    }
+}
+
+/* Advances N droplets (binary64 planes x, v: dim x N; J, K: dim*dim x N;    */
+/* r: N, updated in place) by dt in `substeps` RK4 substeps and writes the   */
+/* step's source rates phibar (1 + dim planes of N).  A droplet is skipped   */
+/* (valid = 0, state left as it was, phibar 0) if any input is not finite,   */
+/* r <= 0, it would evaporate within the step (r^2 + delta dt <= 0) or the   */
+/* result is not finite.  Returns the number skipped.                        */
+int64_t orc_advance(int dim, int64_t N, double* x, double* v, double* J, double* K, double* r,
+                    const orc_flow* flow, double rho_d, double mu, double delta, double dt, int substeps,
+                    double* phibar, int* valid)
+{
+    int C = 1 + dim;
+    int ny = 2 * dim + 1 + 2 * dim * dim + C;
+    int64_t skipped = 0;
+#pragma omp parallel for schedule(static) reduction(+ : skipped)
+    for (int64_t i = 0; i < N; ++i) {
+        double y[40], k1[40], k2[40], k3[40], k4[40], yt[40];
+        for (int a = 0; a < dim; ++a) {
+            y[a] = x[a * N + i];
+            y[dim + a] = v[a * N + i];
+        }
+        y[2 * dim] = r[i];
+        for (int e = 0; e < dim * dim; ++e) {
+            y[2 * dim + 1 + e] = J[e * N + i];
+            y[2 * dim + 1 + dim * dim + e] = K[e * N + i];
+        }
+        for (int k = 0; k < C; ++k) y[ny - C + k] = 0.0;
+        int ok = all_finite(y, ny) && r[i] > 0.0 && r[i] * r[i] + delta * dt > 0.0;
+        double h = dt / (double)substeps;
+        for (int s = 0; s < substeps && ok; ++s) {
+            producer_rhs(dim, flow, rho_d, mu, delta, y, k1);
+            for (int e = 0; e < ny; ++e) yt[e] = y[e] + 0.5 * h * k1[e];
+            producer_rhs(dim, flow, rho_d, mu, delta, yt, k2);
+            for (int e = 0; e < ny; ++e) yt[e] = y[e] + 0.5 * h * k2[e];
+            producer_rhs(dim, flow, rho_d, mu, delta, yt, k3);
+            for (int e = 0; e < ny; ++e) yt[e] = y[e] + h * k3[e];
+            producer_rhs(dim, flow, rho_d, mu, delta, yt, k4);
+            for (int e = 0; e < ny; ++e) y[e] = y[e] + (h / 6.0) * (k1[e] + 2.0 * k2[e] + 2.0 * k3[e] + k4[e]);
+        }
+        ok = ok && all_finite(y, ny) && y[2 * dim] > 0.0;
+        if (!ok) {
+            ++skipped;
+            valid[i] = 0;
+            for (int k = 0; k < C; ++k) phibar[k * N + i] = 0.0;
+            continue;
+        }
+        valid[i] = 1;
+        for (int a = 0; a < dim; ++a) {
+            x[a * N + i] = y[a];
+            v[a * N + i] = y[dim + a];
+        }
+        r[i] = y[2 * dim];
+        for (int e = 0; e < dim * dim; ++e) {
+            J[e * N + i] = y[2 * dim + 1 + e];
+            K[e * N + i] = y[2 * dim + 1 + dim * dim + e];
+        }
+        for (int k = 0; k < C; ++k) phibar[k * N + i] = y[ny - C + k] / dt;
+    }
+    return skipped;
+}
+
+/* Estimator terms of advanced droplets: det J, n = n0/|det J| (eq. FLA-COM), */
+/* h = h0 |det J| (eq. smoothing-length) and q = n phibar; a droplet is      */
+/* skipped if it was not advanced, det J = 0 or a term is not finite.        */
+int64_t orc_state_terms(int dim, int64_t N, const double* x, const double* J, const double* phibar,
+                        const int* valid_in, const double* n0, double n0_scalar, double h0, double* det_out,
+                        double* h_out, double* n_out, double* q_out, int* valid_out)
+{
+    int C = 1 + dim;
+    int64_t skipped = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        double Ji[9], xi[3], ph[4];
+        for (int e = 0; e < dim * dim; ++e) Ji[e] = J[e * N + i];
+        for (int a = 0; a < dim; ++a) xi[a] = x[a * N + i];
+        for (int k = 0; k < C; ++k) ph[k] = phibar[k * N + i];
+        double n0i = n0 ? n0[i] : n0_scalar;
+        double det = orc_det(dim, Ji);
+        double adet = fabs(det);
+        int ok = valid_in[i] && all_finite(Ji, dim * dim) && all_finite(xi, dim) && all_finite(ph, C) &&
+                 isfinite(n0i) && isfinite(det) && det != 0.0;
+        double h = h0 * adet;
+        double n = n0i / adet;
+        if (ok && !(isfinite(h) && h > 0.0 && isfinite(n))) ok = 0;
+        if (!ok) ++skipped;
+        det_out[i] = det;
+        h_out[i] = ok ? h : 0.0;
+        n_out[i] = ok ? n : 0.0;
+        for (int k = 0; k < C; ++k) q_out[k * N + i] = ok ? n * ph[k] : 0.0;
+        valid_out[i] = ok;
+    }
+    return skipped;
+}
+
+/* ------------------------------------------------------------------------ */
 /* App. A scaling factors.                                                   */
 /*   M_scal = N_ref tau_FLA / (N_FLA tau_ref)                   (eq. A.6)    */
 /*   V_scal = V_cell N_FLA / (A_inj v_inj tau_FLA)              (eq. A.12)   */
