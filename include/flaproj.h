@@ -280,6 +280,83 @@ fla_status fla_autotune(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectori
                         double* times_ms);
 
 /* ---------------------------------------------------------------------------
+ * Trajectory producer.  The droplets of the FLA are advanced over one carrier
+ * time step in an analytic gas field and projected in the same call, the
+ * integration fused with the prepass (the advanced position and Jacobian go
+ * from registers into the projection's records).
+ *
+ * Gas field (steady): u(x) = u0 + G x + a periodic part of amplitude U and
+ * wavenumber k, w = 2 pi k:
+ *   FLA_FLOW_NONE          none (uniform and linear flows)
+ *   FLA_FLOW_TAYLOR_GREEN  2-D: U (sin(w x) cos(w y), -cos(w x) sin(w y))
+ *   FLA_FLOW_ABC           3-D: U (A sin(w z + pz) + C cos(w y + py),
+ *                                  B sin(w x + px) + A cos(w z + pz),
+ *                                  C sin(w y + py) + B cos(w x + px))
+ * with abc = (A, B, C), phase = (px, py, pz), G[a*3 + b] = du_a/dx_b. */
+typedef enum { FLA_FLOW_NONE = 0, FLA_FLOW_TAYLOR_GREEN = 1, FLA_FLOW_ABC = 2 } fla_flow_kind;
+typedef struct {
+    int32_t kind;           /* fla_flow_kind */
+    int32_t reserved;
+    double U;               /* amplitude of the periodic part, m/s */
+    double k;               /* wavenumber, periods per unit length */
+    double abc[3];
+    double phase[3];
+    double u0[3];           /* uniform part */
+    double G[9];            /* linear part */
+} fla_flow;
+
+/* Droplet state: binary64 device planes of count values, updated in place
+ * when step.update_state is set.  x[a] positions, v[a] velocities, J the
+ * Jacobian dx/dx0 and dJ its time derivative (dim*dim planes, entry (a, b)
+ * at plane a*dim + b; at seeding J = I and dJ = dv0/dx0, eq.
+ * Jacobian-evolution), r radii; n0 (nullable, else n0_scalar) the initial
+ * number density; seed_volume as in fla_trajectories.  phibar (nullable,
+ * 1 + dim planes) receives the step's source rates of one droplet (see
+ * fla_advance_project; 0 for skipped droplets). */
+typedef struct {
+    int64_t count;          /* >= 0, < 2^31 */
+    double* x[3];
+    double* v[3];
+    double* J;
+    double* dJ;
+    double* r;
+    const double* n0;
+    double n0_scalar;
+    double seed_volume;
+    double* phibar;
+} fla_droplets;
+
+/* One carrier time step: length dt (s) in `substeps` equal substeps;
+ * update_state nonzero writes the advanced state back. */
+typedef struct {
+    double dt;
+    int32_t substeps;       /* 1 .. 2^20 */
+    int32_t update_state;
+} fla_step;
+
+/* Advance and project (paper: eqs. Stokes-drag, evap-model and
+ * Jacobian-evolution integrated along the trajectories, App. B steps 1a-1d
+ * and 2a-2c).  Every droplet is advanced over the step with the classical
+ * fourth-order Runge-Kutta method in binary64, in dimensional form
+ * (tau = 2 rho_d r^2/(9 mu)):
+ *   x' = v, v' = (u(x) - v)/tau, r' = delta/(2 r),
+ *   J' = dJ, dJ' = (grad u(x) J - dJ)/tau,
+ * and its contributions Q' = [mdot, F + mdot v] (F = m (u - v)/tau,
+ * mdot = 4 pi rho_d r^2 r') are integrated over the same substeps and
+ * summed over the step; the step's source rates are phibar = Q/dt.  The
+ * advanced droplets are then projected as fla_project_sources projects
+ * trajectories (params.mode, h = h0 |det J| times params.h_factor,
+ * n = n0/|det J|), with phibar in place of the instantaneous source terms;
+ * prec (fla_precision) selects the arithmetic of the projection.  A
+ * droplet is skipped and counted (stats.skipped) if an input is not finite,
+ * r <= 0, it evaporates within the step (r^2 + delta dt <= 0), the
+ * advanced state is not finite or det J = 0; its state is left as it was.
+ * Errors: INVALID_ARG (checked on the host), OUT_OF_MEMORY, DEVICE. */
+fla_status fla_advance_project(fla_ctx* ctx, const fla_mesh* mesh, const fla_droplets* drops, const fla_flow* flow,
+                               const fla_step* step, const fla_params* params, int prec, const fla_fields* out,
+                               void* stream);
+
+/* ---------------------------------------------------------------------------
  * Learned bandwidth correction.  A 5-64-64-1 network (SiLU hidden layers)
  * predicts a per-trajectory factor g_i = exp(ln4 * tanh o_i) multiplying the
  * smoothing length h_i = h0 |det J_i| of eq. (smoothing-length).  Its inputs

@@ -55,6 +55,23 @@ class fla_stats(C.Structure):
                 ("max_class", C.c_int64), ("graph_replays", C.c_int64)]
 
 
+class fla_flow(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("U", C.c_double), ("k", C.c_double),
+                ("abc", C.c_double * 3), ("phase", C.c_double * 3), ("u0", C.c_double * 3), ("G", C.c_double * 9)]
+
+
+class fla_droplets(C.Structure):
+    _fields_ = [("count", C.c_int64), ("x", C.c_void_p * 3), ("v", C.c_void_p * 3), ("J", C.c_void_p),
+                ("dJ", C.c_void_p), ("r", C.c_void_p), ("n0", C.c_void_p), ("n0_scalar", C.c_double),
+                ("seed_volume", C.c_double), ("phibar", C.c_void_p)]
+
+
+class fla_step(C.Structure):
+    _fields_ = [("dt", C.c_double), ("substeps", C.c_int32), ("update_state", C.c_int32)]
+
+
+FLA_FLOW_NONE, FLA_FLOW_TAYLOR_GREEN, FLA_FLOW_ABC = 0, 1, 2
+
 PROFILE_STAGES = ["prepass", "sort", "deposit_norm", "gather", "psicell", "mlp_forward", "proj_backward",
                   "mlp_backward"]
 MLP_TRAINABLE = 4609
@@ -109,6 +126,9 @@ _lib.fla_adam_step.argtypes = [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_double, C
 _lib.fla_rel_l2_loss.restype = C.c_int
 _lib.fla_rel_l2_loss.argtypes = [_vp, C.c_int, C.c_int64, C.c_int, C.POINTER(fla_fields), C.POINTER(fla_fields),
                                  C.POINTER(fla_fields), _vp, _vp]
+_lib.fla_advance_project.restype = C.c_int
+_lib.fla_advance_project.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_droplets), C.POINTER(fla_flow),
+                                     C.POINTER(fla_step), C.POINTER(fla_params), C.c_int, C.POINTER(fla_fields), _vp]
 _lib.fla_bandwidth_standardise.restype = C.c_int
 _lib.fla_bandwidth_standardise.argtypes = [_vp, C.c_int, C.POINTER(fla_mesh), C.POINTER(fla_trajectories), _vp, _vp]
 _lib.fla_mlp_train_step.restype = C.c_int
@@ -232,6 +252,58 @@ def make_trajectories(x, J, v, ug, r, n0=1.0, seed_volume: float = 0.0) -> tuple
     return tr, keep
 
 
+def make_flow(kind: int = FLA_FLOW_NONE, U: float = 0.0, k: float = 1.0, abc=(1.0, 1.0, 1.0),
+              phase=(0.0, 0.0, 0.0), u0=(0.0, 0.0, 0.0), G=None) -> fla_flow:
+    """Gas field u = u0 + G x + (Taylor-Green or ABC part); G: nested lists or None."""
+    f = fla_flow()
+    f.kind, f.U, f.k = int(kind), float(U), float(k)
+    pad = lambda t: [float(v) for v in t] + [0.0] * (3 - len(t))
+    for a, (A, P, U0) in enumerate(zip(pad(abc), pad(phase), pad(u0))):
+        f.abc[a], f.phase[a], f.u0[a] = A, P, U0
+    if G is not None:
+        for a, row in enumerate(G):
+            for b, g in enumerate(row):
+                f.G[a * 3 + b] = float(g)
+    return f
+
+
+def make_droplets(x, v, J, dJ, r, n0=1.0, seed_volume: float = 0.0, phibar=None) -> tuple:
+    """Droplet state from float64 device tensors x, v (dim, N), J, dJ (dim*dim, N),
+    r (N,); phibar: optional (1 + dim, N) float64 output.  The planes are used in
+    place (the tensors must be contiguous).  Returns (struct, keepalive)."""
+    import torch
+    dim, N = int(x.shape[0]), int(x.shape[1])
+    for name, t in (("x", x), ("v", v), ("J", J), ("dJ", dJ), ("r", r)):
+        if t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor")
+    d = fla_droplets()
+    d.count = N
+    keep = [x, v, J, dJ, r]
+    for a in range(dim):
+        d.x[a] = x[a].data_ptr()
+        d.v[a] = v[a].data_ptr()
+    d.J, d.dJ, d.r = J.data_ptr(), dJ.data_ptr(), r.data_ptr()
+    if isinstance(n0, (int, float)):
+        d.n0, d.n0_scalar = None, float(n0)
+    else:
+        n0c = n0.to(torch.float64).contiguous()
+        keep.append(n0c)
+        d.n0, d.n0_scalar = n0c.data_ptr(), 0.0
+    d.seed_volume = float(seed_volume)
+    if phibar is not None:
+        if phibar.dtype != torch.float64 or not phibar.is_contiguous():
+            raise ValueError("phibar must be a contiguous float64 tensor")
+        d.phibar = phibar.data_ptr()
+        keep.append(phibar)
+    return d, keep
+
+
+def make_step(dt: float, substeps: int, update_state: bool = True) -> fla_step:
+    st = fla_step()
+    st.dt, st.substeps, st.update_state = float(dt), int(substeps), int(bool(update_state))
+    return st
+
+
 def make_fields(S_mass, S_mom: Sequence, den=None, pairs=None) -> fla_fields:
     """pairs: optional int32 device tensor (read as uint32 per cell)."""
     f = fla_fields()
@@ -311,6 +383,14 @@ class Context:
                            params: Params, S_mass, S_mom, den=None, stream=None):
         st = self.psicell_raw(mesh, particles, weight, params.to_c(), make_fields(S_mass, S_mom, den), stream)
         self._check(st)
+
+    def advance_project(self, mesh: fla_mesh, drops: fla_droplets, flow: fla_flow, step: fla_step, params: Params,
+                        prec: int, S_mass, S_mom, den=None, pairs=None, stream=None):
+        """fla_advance_project: advance the droplets one carrier step and project them."""
+        self._check(_lib.fla_advance_project(self._h, C.byref(mesh), C.byref(drops), C.byref(flow), C.byref(step),
+                                             C.byref(params.to_c()), int(prec),
+                                             C.byref(make_fields(S_mass, S_mom, den, pairs)),
+                                             _stream_handle(stream)))
 
     def profile_enable(self, on: bool = True):
         self._check(_lib.fla_profile_enable(self._h, int(bool(on))))

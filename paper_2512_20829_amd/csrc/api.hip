@@ -281,10 +281,12 @@ int bits_for(uint64_t maxval)
 
 // fixed: a caller-provided workspace of fixed_size bytes (the allocation-free
 // entry point) instead of the context's grow-only one
+// prod: the trajectory producer advances the droplets and emits the records
+// in place of the prepass (fla_advance_project)
 template <typename R, int D>
 fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const fla_params* p,
                         const fla_mesh* mesh, const fla_fields* out, hipStream_t s, void* fixed = nullptr,
-                        size_t fixed_size = 0)
+                        size_t fixed_size = 0, const ProduceArgs* prod = nullptr)
 {
     const int64_t N = t.count;
     const int deposit = p->mode == FLA_DEPOSIT;
@@ -339,7 +341,11 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
     HIP_OK(launch_fill_u64(ctx->stats + ST_TRAJ, 1, (unsigned long long)N, s));
     {
         StageTimer tm(ctx, 0, s);
-        HIP_OK((launch_prepass<R, D>(t, m, ph, p->h_factor, deposit, keys, vals, rpos_u, rw_u, qd, ctx->stats, s)));
+        if (prod)
+            HIP_OK((launch_produce<R, D>(*prod, m, ph, p->h_factor, deposit, keys, vals, rpos_u, rw_u, qd, ctx->stats,
+                                         s)));
+        else
+            HIP_OK((launch_prepass<R, D>(t, m, ph, p->h_factor, deposit, keys, vals, rpos_u, rw_u, qd, ctx->stats, s)));
     }
     bool in_alt = false;
     uint32_t *skeys, *svals;
@@ -1334,6 +1340,91 @@ FLA_EXPORT fla_status fla_autotune_batch(fla_ctx* ctx, int nsnap, const fla_mesh
     ctx->batch_plan[d][pr] = best_plan;
     ctx->batch_chunk[d][pr] = best_chunk;
     return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_advance_project(fla_ctx* ctx, const fla_mesh* mesh, const fla_droplets* drops,
+                                          const fla_flow* flow, const fla_step* step, const fla_params* params,
+                                          int prec, const fla_fields* out, void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    try {
+        MeshDev m;
+        fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+        if (st != FLA_OK) return st;
+        const int D = m.dim;
+        CHECK_ARG(drops != nullptr, "droplets is NULL");
+        CHECK_ARG(drops->count >= 0 && drops->count < (int64_t(1) << 31), "count must be in [0, 2^31)");
+        if (drops->count > 0) {
+            for (int a = 0; a < D; ++a) CHECK_ARG(drops->x[a] && drops->v[a], "x and v must be non-NULL for every axis");
+            CHECK_ARG(drops->J && drops->dJ && drops->r, "J, dJ and r are required");
+            CHECK_ARG(drops->n0 != nullptr || is_fin(drops->n0_scalar), "n0_scalar must be finite when n0 is NULL");
+        }
+        CHECK_ARG(flow != nullptr, "flow is NULL");
+        CHECK_ARG(flow->kind == FLA_FLOW_NONE || (flow->kind == FLA_FLOW_TAYLOR_GREEN && D == 2) ||
+                      (flow->kind == FLA_FLOW_ABC && D == 3),
+                  "flow.kind must be FLA_FLOW_NONE, FLA_FLOW_TAYLOR_GREEN (2-D) or FLA_FLOW_ABC (3-D)");
+        bool fin = is_fin(flow->U) && is_fin(flow->k);
+        for (int a = 0; a < 3; ++a) fin = fin && is_fin(flow->abc[a]) && is_fin(flow->phase[a]) && is_fin(flow->u0[a]);
+        for (int e = 0; e < 9; ++e) fin = fin && is_fin(flow->G[e]);
+        CHECK_ARG(fin, "flow parameters must be finite");
+        CHECK_ARG(step != nullptr, "step is NULL");
+        CHECK_ARG(is_fin(step->dt) && step->dt > 0.0, "step.dt must be positive and finite");
+        CHECK_ARG(step->substeps >= 1 && step->substeps <= (1 << 20), "step.substeps must be in [1, 2^20]");
+        CHECK_ARG(prec == FLA_F32 || prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
+        st = check_params(ctx, params, true);
+        if (st != FLA_OK) return st;
+        st = check_fields(ctx, out, D);
+        if (st != FLA_OK) return st;
+        if (params->mode == FLA_DEPOSIT)
+            CHECK_ARG(is_fin(drops->seed_volume) && drops->seed_volume > 0.0,
+                      "seed_volume must be positive and finite in FLA_DEPOSIT mode");
+        HIP_OK(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        const bool f64 = prec == FLA_F64;
+        if (drops->count == 0) {
+            HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
+            return f64 ? zero_outputs<double>(ctx, m, out, s) : zero_outputs<float>(ctx, m, out, s);
+        }
+        ProduceArgs pa{};
+        pa.count = drops->count;
+        for (int a = 0; a < 3; ++a) {
+            pa.x[a] = a < D ? drops->x[a] : nullptr;
+            pa.v[a] = a < D ? drops->v[a] : nullptr;
+        }
+        pa.J = drops->J;
+        pa.dJ = drops->dJ;
+        pa.r = drops->r;
+        pa.n0 = drops->n0;
+        pa.n0_scalar = drops->n0_scalar;
+        pa.seed_volume = drops->seed_volume;
+        pa.phibar = drops->phibar;
+        pa.flow.kind = flow->kind;
+        pa.flow.U = flow->U;
+        pa.flow.k = flow->k;
+        for (int a = 0; a < 3; ++a) {
+            pa.flow.abc[a] = flow->abc[a];
+            pa.flow.phase[a] = flow->phase[a];
+            pa.flow.u0[a] = flow->u0[a];
+        }
+        for (int e = 0; e < 9; ++e) pa.flow.G[e] = flow->G[e];
+        pa.dt = step->dt;
+        pa.substeps = step->substeps;
+        pa.update = step->update_state != 0;
+        TrajDev t{};
+        t.count = drops->count;
+        t.n0 = drops->n0;
+        t.n0_scalar = drops->n0_scalar;
+        t.seed_volume = drops->seed_volume;
+        if (D == 2)
+            return f64 ? project_impl<double, 2>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa)
+                       : project_impl<float, 2>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa);
+        return f64 ? project_impl<double, 3>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa)
+                   : project_impl<float, 3>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa);
+    } catch (...) {
+        ctx->err = "internal error";
+        return FLA_ERR_DEVICE;
+    }
 }
 
 FLA_EXPORT fla_status fla_bandwidth_standardise(fla_ctx* ctx, int nsnap, const fla_mesh* meshes,

@@ -45,6 +45,38 @@ template <typename R, int D>
 hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan,
                                hipStream_t s);
 
+// Trajectory producer: the gas field and the droplet state it advances.
+struct FlowDev {
+    int kind;                 // FLA_FLOW_*
+    double U, k;
+    double abc[3], phase[3], u0[3];
+    double G[9];              // du_a/dx_b at G[a*3 + b]
+};
+struct ProduceArgs {
+    int64_t count;
+    double* x[3];
+    double* v[3];
+    double* J;                // dim*dim planes
+    double* dJ;               // dim*dim planes
+    double* r;
+    const double* n0;
+    double n0_scalar;
+    double seed_volume;
+    double* phibar;           // nullable: 1 + dim planes of the step's source rates
+    FlowDev flow;
+    double dt;
+    int substeps;
+    int update;               // write the advanced state back
+};
+
+// Advances every droplet over the step and emits the prepass records of the
+// advanced state with the step's source rates (as launch_prepass does for a
+// given state).
+template <typename R, int D>
+hipError_t launch_produce(const ProduceArgs& p, const MeshDev& m, const PhysDev& ph, const float* hfac, int deposit,
+                          uint32_t* keys, uint32_t* vals, double4* rpos, R* rw, double* qd, unsigned long long* stats,
+                          hipStream_t s);
+
 template <typename R, int D>
 hipError_t launch_prepass(const TrajDev& t, const MeshDev& m, const PhysDev& ph, const float* hfac,
                           int deposit, uint32_t* keys, uint32_t* vals, double4* rpos, R* rw,

@@ -2,33 +2,19 @@
 // per-trajectory normaliser of the conservative deposition mode.
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "prepass.hpp"
 
 namespace flp {
 
-// Adds the sum over the wave of the per-lane counts c (0 <= c < 8) to
-// stats[slot]: one ballot per bit and one atomic per wave.
-__device__ inline void wave_count_sum(unsigned long long* stats, int slot, unsigned c)
-{
-    const unsigned long long n = (unsigned long long)__popcll(__ballot(c & 1u)) +
-                                 2ull * (unsigned long long)__popcll(__ballot(c & 2u)) +
-                                 4ull * (unsigned long long)__popcll(__ballot(c & 4u));
-    if ((threadIdx.x % kWave) == 0 && n) atomicAdd(&stats[slot], n);
-}
-
 // Per-trajectory prepass of trajectory i of one snapshot, written at global
-// index gi.  Writes the sort key (key_base + neighbourhood class * ntiles +
-// home tile, or `sentinel`), the unsorted position record {x, y, z, 1/h} and
-// weight record {1/h, q/h} (or, in deposition mode, the binary64 amounts Q to
-// qd).  Adds 1 to `skipped` / `nosup` when the trajectory is skipped or
-// reaches no cell centre.
+// index gi: loads the inputs, forms the droplet source terms and emits the
+// records (prepass_emit).
 template <typename R, int D>
 __device__ inline void prepass_one(const TrajDev& t, const MeshDev& m, const PhysDev& ph, const float* hfac,
                                    int deposit, int64_t i, int64_t gi, uint32_t key_base, uint32_t sentinel,
                                    uint32_t* keys, uint32_t* vals, double4* rpos, R* rw, double* qd,
                                    unsigned long long& skipped, unsigned long long& nosup)
 {
-    constexpr int TE = Geo<D>::TE;
-    constexpr int C = D + 1;
     const int64_t N = t.count;
     double x[3] = {0, 0, 0}, J[9], v[3], ug[3];
     bool ok = true;
@@ -47,113 +33,11 @@ __device__ inline void prepass_one(const TrajDev& t, const MeshDev& m, const Phy
     double r = (double)((const R*)t.r)[i];
     double n0 = t.n0 ? t.n0[i] : t.n0_scalar;
     double fac = hfac ? (double)hfac[i] : 1.0;
-    double det = det_rn<D>(J);
-    double adet = fabs(det);
-    ok = ok && isfinite(r) && isfinite(n0) && isfinite(det) && det != 0.0 && isfinite(fac) && fac > 0.0;
-    double h, n, phi[4] = {0, 0, 0, 0};
-    {
-#pragma clang fp contract(off)
-        h = ph.h0 * adet;
-        h = h * fac;
-    }
-    n = n0 / adet;
+    ok = ok && isfinite(r);
+    double phi[4] = {0, 0, 0, 0};
     if (ok) droplet_phi<D>(r, v, ug, ph, phi);
-    if (ok) {
-        ok = isfinite(h) && h > 0.0 && isfinite(n);
-#pragma unroll
-        for (int k = 0; k < C; ++k) ok = ok && isfinite(phi[k]);
-    }
-    uint32_t key = sentinel;
-    if (!ok) {
-        skipped += 1;
-    } else {
-        double inv_h = 1.0 / h;
-        double rc = ph.cutoff * h * (1.0 + kSupportMargin);
-        int64_t ht[3] = {0, 0, 0};
-        int reach = 0;
-        bool support = true;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            // home cell by division, exactly as the gather's home_index; the
-            // support bounds (they only choose the bucket class) by a
-            // multiply with 1/w, widened by 1e-9 plus 1e-15 of the quotient,
-            // far more than the few ulps by which the product can differ
-            double g = floor((x[a] - m.lo[a]) / m.w[a]);
-            g = fmin(fmax(g, -4.0e15), 4.0e15);
-            int64_t hc = (int64_t)g;
-            const double iw = 1.0 / m.w[a];
-            const double qlo = (x[a] - rc - m.lo[a]) * iw, qhi = (x[a] + rc - m.lo[a]) * iw;
-            double flo = qlo - 0.5 - (1e-9 + 1e-15 * fabs(qlo));
-            double fhi = qhi - 0.5 + (1e-9 + 1e-15 * fabs(qhi));
-            flo = fmin(fmax(flo, -4.0e15), 4.0e15);
-            fhi = fmin(fmax(fhi, -4.0e15), 4.0e15);
-            int64_t ilo = (int64_t)ceil(flo), ihi = (int64_t)floor(fhi);
-            int64_t ra;
-            if (m.periodic[a]) {
-                // tile distances are circular: the last tile of an axis whose
-                // cell count is not a multiple of TE is short, so wrapped cells
-                // are mapped back into [0, n) before taking their tile
-                int64_t wrapped = posmod(hc, m.n[a]);
-                int64_t sh = wrapped - hc;
-                hc = wrapped;
-                ilo += sh;
-                ihi += sh;
-                ht[a] = hc / TE;
-                if (ilo > ihi) {
-                    support = false;
-                    ra = 0;
-                } else if (ihi - ilo + 1 >= m.n[a]) {
-                    ra = m.nt[a];
-                } else {
-                    int64_t tl = posmod(ilo, m.n[a]) / TE, tr = posmod(ihi, m.n[a]) / TE;
-                    int64_t dl = ilo > hc ? 0 : posmod(ht[a] - tl, m.nt[a]);
-                    int64_t dr = ihi < hc ? 0 : posmod(tr - ht[a], m.nt[a]);
-                    ra = dl > dr ? dl : dr;
-                }
-            } else {
-                hc = hc < 0 ? 0 : (hc >= m.n[a] ? m.n[a] - 1 : hc);
-                ilo = ilo < 0 ? 0 : ilo;
-                ihi = ihi >= m.n[a] ? m.n[a] - 1 : ihi;
-                if (ilo > ihi) support = false;
-                ht[a] = hc / TE;
-                int64_t tlo = floordiv(ilo, TE), thi = floordiv(ihi, TE);
-                ra = ht[a] - tlo;
-                if (thi - ht[a] > ra) ra = thi - ht[a];
-            }
-            if (ra < 0) ra = 0;
-            if (ra > kClasses) ra = kClasses;
-            if ((int)ra > reach) reach = (int)ra;
-        }
-        // In deposition mode a trajectory that reaches no cell centre still
-        // deposits its whole amount into its home cell, so it is kept.
-        if (!support) nosup += 1;
-        if (support || deposit) {
-            int cls = !support ? 0 : (reach < kClasses - 1 ? reach : kClasses - 1);
-            int64_t tl = ht[0] + (int64_t)m.nt[0] * (ht[1] + (int64_t)m.nt[1] * ht[2]);
-            key = key_base + (uint32_t)cls * (uint32_t)m.ntiles + (uint32_t)tl;
-        }
-        rpos[gi] = make_double4(x[0], x[1], x[2], inv_h);
-        // the weight record is built in registers and stored whole (16-byte stores)
-        R w[kRecW];
-#pragma unroll
-        for (int k = 0; k < kRecW; ++k) w[k] = (R)0;
-        w[0] = (R)inv_h;
-        if (deposit) {
-            double sc = t.seed_volume * adet;
-#pragma unroll
-            for (int k = 0; k < C; ++k) qd[(int64_t)k * N + i] = (n * phi[k]) * sc;
-        } else {
-#pragma unroll
-            for (int k = 0; k < C; ++k) w[1 + k] = (R)(inv_h * (n * phi[k]));
-        }
-        static_assert(kRecW * sizeof(R) % sizeof(uint4) == 0, "weight records are whole 16-byte words");
-        uint4* wd = reinterpret_cast<uint4*>(rw + gi * kRecW);
-        const uint4* ws = reinterpret_cast<const uint4*>(w);
-#pragma unroll
-        for (int k = 0; k < (int)(kRecW * sizeof(R) / sizeof(uint4)); ++k) wd[k] = ws[k];
-    }
-    keys[gi] = key;
-    vals[gi] = (uint32_t)gi;
+    prepass_emit<R, D>(m, ph, fac, deposit, N, i, gi, key_base, sentinel, x, J, n0, phi, ok, t.seed_volume, keys,
+                       vals, rpos, rw, qd, skipped, nosup);
 }
 
 // Trajectories per thread of the prepass kernels: each trajectory is one

@@ -1,0 +1,225 @@
+"""Parity of the fused trajectory producer (fla_advance_project) with the
+oracle: droplets advanced by RK4 over carrier steps in analytic gas fields,
+then projected.  Each side integrates from the same seeded initial state;
+no GPU output feeds the oracle.
+
+Bars: the advanced state (x, v, r, J, dJ) and the step's source rates within
+1e-12 relative per plane (both sides take the same binary64 operations in
+the same order, and differ only in the last bits of sin and cos); projected
+fields within 1e-12 (binary64) and 1e-5 (binary32) relative L2 and per cell,
+per-cell pair counts exact, skip counts exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from helpers import assert_fields_close, rel_l2
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2512_20829_amd as F
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def _flows():
+    import paper_2512_20829_amd as F
+    return {
+        "abc": (F.make_flow(F.FLA_FLOW_ABC, U=0.2, k=1.0, abc=(1.0, 0.8, 1.2), phase=(0.3, 1.1, 2.0)),
+                oracle.make_flow(oracle.FLOW_ABC, U=0.2, k=1.0, abc=(1.0, 0.8, 1.2), phase=(0.3, 1.1, 2.0))),
+        "tg": (F.make_flow(F.FLA_FLOW_TAYLOR_GREEN, U=0.1, k=1.0, u0=(0.02, 0.0)),
+               oracle.make_flow(oracle.FLOW_TAYLOR_GREEN, U=0.1, k=1.0, u0=(0.02, 0.0))),
+        "linear3": (F.make_flow(u0=(0.1, -0.05, 0.02), G=[[0, 30.0, 0], [-10.0, 5.0, 0], [0, 0, -5.0]]),
+                    oracle.make_flow(u0=(0.1, -0.05, 0.02), G=[[0, 30.0, 0], [-10.0, 5.0, 0], [0, 0, -5.0]])),
+    }
+
+
+class Run:
+    """Device copy of a droplet seed and its oracle twin, advanced in lockstep."""
+
+    def __init__(self, d: W.Droplets):
+        import paper_2512_20829_amd as F
+        self.dim, self.N = d.x.shape
+        g = d.to(DEV)
+        self.t = [g.x.contiguous(), g.v.contiguous(), g.J.contiguous(), g.dJ.contiguous(), g.r.contiguous()]
+        self.phibar = torch.full((1 + self.dim, self.N), float("nan"), dtype=torch.float64, device=DEV)
+        self.st, self.keep = F.make_droplets(*self.t, n0=d.n0, seed_volume=d.seed_volume, phibar=self.phibar)
+        self.ref = oracle.DropletState(d.x.numpy().copy(), d.v.numpy().copy(), d.J.numpy().copy(),
+                                       d.dJ.numpy().copy(), d.r.numpy().copy())
+        self.n0, self.seed_volume = d.n0, d.seed_volume
+
+    def gpu_state(self):
+        return [t.cpu().numpy() for t in self.t]
+
+
+def _step(ctx, run, mesh, flows, flow_name, dt, sub, prec, delta, mode=0, update=True):
+    import paper_2512_20829_amd as F
+    gflow, oflow = flows[flow_name]
+    dt_ = torch.float64 if prec == "f64" else torch.float32
+    M = mesh.cells
+    S_mass, S_mom, den = F.alloc_fields(M, run.dim, dt_, DEV)
+    pairs = torch.full((M,), -1, dtype=torch.int32, device=DEV)
+    p = F.Params(rho_d=W.RHO_D, mu=W.MU_AIR, delta=delta, h0=1.0 / round(run.N ** (1.0 / run.dim)), cutoff=4.0,
+                 mode=mode)
+    ctx.advance_project(F.mesh_of(mesh), run.st, gflow, F.make_step(dt, sub, update), p, F.FLA_F64 if prec == "f64"
+                        else F.FLA_F32, S_mass, S_mom, den, pairs)
+    torch.cuda.synchronize()
+    stats = ctx.stats()
+    new, phi, valid, sk = oracle.advance(run.ref, oflow, W.RHO_D, W.MU_AIR, delta, dt, sub)
+    S = torch.stack([S_mass, *S_mom]).double().cpu().numpy()
+    return S, den.double().cpu().numpy(), pairs.cpu().numpy().astype(np.int64), stats, new, phi, valid, sk, p
+
+
+def _check_state(run, new, phi, valid):
+    x, v, J, dJ, r = run.gpu_state()
+    ok = valid == 1
+    for name, g, o in (("x", x, new.x), ("v", v, new.v), ("J", J, new.J), ("dJ", dJ, new.K), ("r", r, new.r)):
+        err = rel_l2(g[..., ok], o[..., ok])
+        assert err <= 1e-12, f"{name}: rel L2 {err:.3e}"
+    pg = run.phibar.cpu().numpy()
+    for k in range(pg.shape[0]):
+        err = rel_l2(pg[k, ok], phi[k, ok])
+        assert err <= 1e-12, f"phibar[{k}]: rel L2 {err:.3e}"
+    assert np.all(pg[:, ~ok] == 0.0)
+    run.ref = new
+
+
+def _check_projection(S, den, pairs, stats, new, phi, valid, sk, p, mesh, prec):
+    t = oracle.state_terms(new, phi, valid, p_n0(p), p.h0)
+    ref = oracle.nw_box(mesh, new.x, t, None, None, p.cutoff, prec == "f32")
+    assert_fields_close(S, ref.S, TOL[prec], f"producer {prec}")
+    assert rel_l2(den, ref.den) <= TOL[prec]
+    np.testing.assert_array_equal(pairs, ref.pairs)
+    assert stats["skipped"] == t.skipped
+    return t
+
+
+def p_n0(p):
+    return W.N0_DEFAULT
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_abc_flow_three_steps(ctx, prec):
+    """3-D ABC flow, evaporating droplets, three carrier steps with the state
+    written back; state and projection after every step."""
+    flows = _flows()
+    d = W.seed_droplets(3, 20, seed=81, jitter=0.6)
+    run = Run(d)
+    mesh = W.unit_mesh(3, 24, True)
+    print(f"[case] producer abc prec={prec} N={run.N} mesh={mesh.n}", flush=True)
+    for it in range(3):
+        S, den, pairs, stats, new, phi, valid, sk, p = _step(ctx, run, mesh, flows, "abc", 2e-3, 16, prec, -1e-9)
+        assert sk == 0 and valid.all()
+        _check_state(run, new, phi, valid)
+        _check_projection(S, den, pairs, stats, new, phi, valid, sk, p, mesh, prec)
+
+
+def test_taylor_green_2d_closed_box_f64(ctx):
+    flows = _flows()
+    d = W.seed_droplets(2, 48, seed=82, jitter=0.8, radius="uniform")
+    run = Run(d)
+    mesh = W.Mesh(2, (40, 37), (0.0, 0.0), (1.0, 1.0), (False, False))
+    print(f"[case] producer tg2d f64 N={run.N} mesh={mesh.n}", flush=True)
+    for it in range(2):
+        S, den, pairs, stats, new, phi, valid, sk, p = _step(ctx, run, mesh, flows, "tg", 3e-3, 24, "f64", -1e-9)
+        _check_state(run, new, phi, valid)
+        _check_projection(S, den, pairs, stats, new, phi, valid, sk, p, mesh, "f64")
+
+
+def test_linear_flow_and_deposition(ctx):
+    """A linear flow with strain (det J changes) and the conservative mode."""
+    flows = _flows()
+    d = W.seed_droplets(3, 14, seed=83, jitter=0.5)
+    run = Run(d)
+    mesh = W.unit_mesh(3, 16, True)
+    S, den, pairs, stats, new, phi, valid, sk, p = _step(ctx, run, mesh, flows, "linear3", 4e-3, 32, "f64", -1e-9,
+                                                         mode=1)
+    _check_state(run, new, phi, valid)
+    t = oracle.state_terms(new, phi, valid, W.N0_DEFAULT, p.h0)
+    Sref, Z = oracle.deposit_scatter(mesh, new.x, t, d.seed_volume)
+    assert_fields_close(S, Sref, TOL["f64"], "producer deposit")
+    Q = t.q * d.seed_volume * np.abs(t.det)
+    np.testing.assert_allclose(S.sum(axis=1) * mesh.cell_volume, -Q.sum(axis=1), rtol=1e-12)
+
+
+def test_skips_and_the_state_left_as_it_was(ctx):
+    """Non-finite inputs, a droplet that evaporates within the step and a
+    degenerate Jacobian are skipped and counted; without update_state the
+    state is untouched."""
+    flows = _flows()
+    d = W.seed_droplets(3, 8, seed=84)
+    d.r[3] = float("nan")
+    d.x[1, 5] = float("inf")
+    d.r[7] = 1e-6                       # r^2 = 1e-12 < -delta dt = 4e-12: evaporates
+    d.J[:, 9] = 0.0                     # det J = 0 (advanced J stays singular: dJ = 0)
+    run = Run(d)
+    before = [t.clone() for t in run.t]
+    mesh = W.unit_mesh(3, 8, True)
+    S, den, pairs, stats, new, phi, valid, sk, p = _step(ctx, run, mesh, flows, "abc", 2e-3, 8, "f64", -2e-9,
+                                                         update=False)
+    for a, b in zip(before, run.t):
+        assert torch.equal(torch.nan_to_num(a), torch.nan_to_num(b))
+    assert valid[[3, 5, 7]].tolist() == [0, 0, 0] and valid[9] == 1
+    t = oracle.state_terms(new, phi, valid, W.N0_DEFAULT, p.h0)
+    assert t.valid[9] == 0 and stats["skipped"] == t.skipped == 4
+    ref = oracle.nw_box(mesh, new.x, t, None, None, p.cutoff, False)
+    assert_fields_close(S, ref.S, TOL["f64"], "producer skips")
+    np.testing.assert_array_equal(pairs, ref.pairs)
+
+
+def test_rejects_bad_arguments(ctx):
+    import paper_2512_20829_amd as F
+    flows = _flows()
+    d = W.seed_droplets(2, 6, seed=85)
+    run = Run(d)
+    mesh = F.mesh_of(W.unit_mesh(2, 8, True))
+    S_mass, S_mom, den = F.alloc_fields(64, 2, torch.float64, DEV)
+    S_mass.fill_(5.0)
+    p = F.Params(rho_d=W.RHO_D, mu=W.MU_AIR, delta=0.0, h0=0.1)
+    bad = [(flows["abc"][0], F.make_step(1e-3, 4)),          # ABC flow on a 2-D mesh
+           (flows["tg"][0], F.make_step(0.0, 4)),
+           (flows["tg"][0], F.make_step(1e-3, 0))]
+    for flow, step in bad:
+        with pytest.raises(F.FlaError) as e:
+            ctx.advance_project(mesh, run.st, flow, step, p, F.FLA_F64, S_mass, S_mom, den)
+        assert e.value.status == F.FLA_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert bool((S_mass == 5.0).all())
+
+
+@pytest.mark.timeout(300)
+def test_abc_full_size_one_step(ctx):
+    """2,097,152 droplets on the 128^3 lattice in the ABC flow, one carrier
+    step of 16 substeps, projected on the 128^3 mesh in binary32: state of
+    every droplet, and a 32^3 block of cells across the periodic corner
+    against the trajectory-centric oracle."""
+    import paper_2512_20829_amd as F
+    flows = _flows()
+    d = W.seed_droplets(3, 128, seed=86)
+    run = Run(d)
+    mesh = W.unit_mesh(3, 128, True)
+    print(f"[case] producer abc full size N={run.N}", flush=True)
+    oracle.set_threads(16)
+    M = mesh.cells
+    S_mass, S_mom, den = F.alloc_fields(M, 3, torch.float32, DEV)
+    pairs = torch.full((M,), -1, dtype=torch.int32, device=DEV)
+    p = F.Params(rho_d=W.RHO_D, mu=W.MU_AIR, delta=-1e-9, h0=1.0 / 128, cutoff=4.0)
+    ctx.advance_project(F.mesh_of(mesh), run.st, flows["abc"][0], F.make_step(2e-3, 16), p, F.FLA_F32, S_mass, S_mom,
+                        den, pairs)
+    torch.cuda.synchronize()
+    stats = ctx.stats()
+    new, phi, valid, sk = oracle.advance(run.ref, flows["abc"][1], W.RHO_D, W.MU_AIR, -1e-9, 2e-3, 16)
+    _check_state(run, new, phi, valid)
+    t = oracle.state_terms(new, phi, valid, W.N0_DEFAULT, p.h0)
+    ref = oracle.nw_box(mesh, new.x, t, [112, 112, 112], [32, 32, 32], 4.0, True)
+    S = torch.stack([S_mass, *S_mom]).double().cpu().numpy()
+    assert_fields_close(S[:, ref.cells], ref.S, TOL["f32"], "producer full size block")
+    np.testing.assert_array_equal(pairs.cpu().numpy()[ref.cells], ref.pairs)
+    assert stats["skipped"] == t.skipped == 0

@@ -418,3 +418,51 @@ def small_random_3d(n_traj: int, mesh_n: int, seed: int, device="cpu", periodic=
     tr = Trajectories(xp, J, v, ug, r, N0_DEFAULT, seed_volume=1.0 / n_traj)
     return Workload(f"rand3d_{n_traj}_{mesh_n}", unit_mesh(3, mesh_n, periodic), tr,
                     h0 if h0 is not None else n_traj ** (-1.0 / 3.0), "f32")
+
+
+# ---------------------------------------------------------------------------
+# Droplet seeds for the trajectory producer (initial state only: the
+# integration and the gas field belong to the method)
+@dataclass
+class Droplets:
+    """Initial droplet state (float64): x, v (dim, N); J = I, dJ (dim*dim, N);
+    r (N,); scalar n0; seed volume."""
+    x: torch.Tensor
+    v: torch.Tensor
+    J: torch.Tensor
+    dJ: torch.Tensor
+    r: torch.Tensor
+    n0: float
+    seed_volume: float
+
+    @property
+    def count(self) -> int:
+        return int(self.r.shape[0])
+
+    def to(self, device) -> "Droplets":
+        return Droplets(self.x.to(device), self.v.to(device), self.J.to(device), self.dJ.to(device),
+                        self.r.to(device), self.n0, self.seed_volume)
+
+    def clone(self) -> "Droplets":
+        return Droplets(self.x.clone(), self.v.clone(), self.J.clone(), self.dJ.clone(), self.r.clone(), self.n0,
+                        self.seed_volume)
+
+
+def seed_droplets(dim: int, per_axis: int, seed: int = 0, device="cpu", speed: float = 0.2,
+                  radius: str = "lognormal", jitter: float = 0.0) -> Droplets:
+    """Droplets on the cell-centred lattice of the unit square/cube (optionally
+    jittered by up to `jitter` pitches), injected with a velocity that does not
+    depend on position (uniform random per droplet, |v_a| <= speed), so that
+    dJ = dv0/dx0 = 0 and J = I at seeding; radius lognormal(ln 10 um, 0.3) or
+    U[5, 20] um."""
+    x0 = lattice(dim, per_axis, device)
+    N = x0.shape[1]
+    if jitter > 0.0:
+        x0 = x0 + (counter_uniform(seed, 60, N * dim, device).reshape(dim, N) - 0.5) * (jitter / per_axis)
+    v0 = (counter_uniform(seed, 61, N * dim, device).reshape(dim, N) * 2.0 - 1.0) * speed
+    J = torch.eye(dim, dtype=torch.float64, device=device).reshape(dim * dim, 1).repeat(1, N).contiguous()
+    dJ = torch.zeros((dim * dim, N), dtype=torch.float64, device=device)
+    r = radius_lognormal(N, seed, device=device) if radius == "lognormal" else \
+        radius_uniform(N, seed, 5.0, 20.0, device)
+    return Droplets(x0.contiguous(), v0.contiguous(), J, dJ, r.to(torch.float64).contiguous(), N0_DEFAULT,
+                    1.0 / N)
