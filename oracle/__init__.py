@@ -89,6 +89,9 @@ def _declare(L):
     L.orc_psicell.restype = C.c_int64
     L.orc_psicell.argtypes = [C.POINTER(OrcMesh), C.c_int64, _dp, _dp, _dp, _dp, C.c_double,
                               C.c_double, C.c_double, C.c_double, _dp, _dp, _lp, _lp]
+    L.orc_cic.restype = C.c_int64
+    L.orc_cic.argtypes = [C.POINTER(OrcMesh), C.c_int64, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                          C.c_double, _dp, _dp, _dp, _lp]
     L.orc_psicell_cell_of.restype = C.c_int64
     L.orc_psicell_cell_of.argtypes = [C.POINTER(OrcMesh), _dp]
     L.orc_flow_eval.restype = None
@@ -329,6 +332,24 @@ def psicell(mesh, cloud, weight: float, rho_d: float, mu: float, delta: float,
     if split:
         return S, counts, int(sk) - int(nf[0]), int(nf[0])
     return S, counts, int(sk)
+
+
+def cic(mesh, cloud, weight: float, rho_d: float, mu: float, delta: float,
+        cell_scale: Optional[np.ndarray] = None):
+    """Cloud-in-cell accumulation; returns (S (C, M), weight sums (M,),
+    outside, nonfinite)."""
+    m = mesh if isinstance(mesh, OrcMesh) else mesh_from(mesh)
+    dim = m.dim
+    M = int(np.prod([m.n[a] for a in range(dim)]))
+    x, v, ug, r = _f64(cloud.x), _f64(cloud.v), _f64(cloud.ug), _f64(cloud.r)
+    Np = r.shape[0]
+    S = np.zeros((1 + dim, M))
+    ws = np.zeros(M)
+    cs = _f64(cell_scale) if cell_scale is not None else None
+    nf = np.zeros(1, dtype=np.int64)
+    sk = lib().orc_cic(C.byref(m), Np, _d(x), _d(v), _d(ug), _d(r), rho_d, mu, delta, weight,
+                       _d(cs) if cs is not None else None, _d(S), _d(ws), nf.ctypes.data_as(_lp))
+    return S, ws, int(sk) - int(nf[0]), int(nf[0])
 
 
 def psicell_cell_of(mesh, xp) -> int:

@@ -753,6 +753,101 @@ int64_t orc_psicell(const orc_mesh* m, int64_t Np, const double* x, const double
 }
 
 /* ------------------------------------------------------------------------ */
+/* Cloud-in-cell (CIC) accumulation, the linear-interpolation comparator   */
+/* named beside PSI-CELL: each particle's phi is shared among the 2^dim     */
+/* cell centres around it with the per-axis hat weights 1 - |d|/dx (d the  */
+/* offset to the centre), i.e. the corners of the dual cell holding it.    */
+/* On a periodic axis the stencil wraps; on a closed axis the weight of a  */
+/* centre beyond the wall goes to the boundary cell, so every particle     */
+/* deposits its whole phi.  S(c) = -(w/V_c) cs(c) sum_p W_cp phi_p, and    */
+/* wsum(c) = sum_p W_cp.  Particles outside a closed box (x == hi belongs  */
+/* to the box) and particles with a non-finite input are skipped.          */
+/* ------------------------------------------------------------------------ */
+int64_t orc_cic(const orc_mesh* m, int64_t Np, const double* x, const double* v, const double* ug,
+                const double* r, double rho_d, double mu, double delta, double weight,
+                const double* cell_scale, double* S /* C x M */, double* wsum /* M, nullable */,
+                int64_t* nonfinite_out /* nullable */)
+{
+    int C = 1 + m->dim;
+    int64_t M = 1;
+    for (int a = 0; a < m->dim; ++a) M *= m->n[a];
+    double* acc = (double*)calloc((size_t)(C * M), sizeof(double));
+    double* ws = (double*)calloc((size_t)M, sizeof(double));
+    int64_t skipped = 0, nonfinite = 0;
+    for (int64_t p = 0; p < Np; ++p) {
+        double xp[3] = {0, 0, 0}, vp[3], up[3], phi[4];
+        for (int a = 0; a < m->dim; ++a) {
+            xp[a] = x[a * Np + p];
+            vp[a] = v[a * Np + p];
+            up[a] = ug[a * Np + p];
+        }
+        if (!all_finite(xp, m->dim) || !all_finite(vp, m->dim) || !all_finite(up, m->dim) || !isfinite(r[p])) {
+            ++skipped;
+            ++nonfinite;
+            continue;
+        }
+        if (orc_psicell_cell_of(m, xp) < 0) {
+            ++skipped;
+            continue;
+        }
+        orc_droplet_phi(m->dim, r[p], vp, up, rho_d, mu, delta, phi, 0, 0, 0);
+        if (!all_finite(phi, C)) {
+            ++skipped;
+            ++nonfinite;
+            continue;
+        }
+        /* per axis: the two centres around x and their weights */
+        int64_t kk[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+        double ww[3][2] = {{1, 0}, {1, 0}, {1, 0}};
+        for (int a = 0; a < m->dim; ++a) {
+            int64_t n = m->n[a];
+            double u = (xp[a] - m->lo[a]) / cell_width(m, a) - 0.5;
+            double fl = floor(u);
+            double f = u - fl;
+            int64_t k = (int64_t)fl;
+            if (m->periodic[a]) {
+                int64_t k0 = k % n;
+                if (k0 < 0) k0 += n;
+                kk[a][0] = k0;
+                kk[a][1] = (k0 + 1) % n;
+            } else if (k < 0) {
+                kk[a][0] = kk[a][1] = 0;
+            } else if (k >= n - 1) {
+                kk[a][0] = kk[a][1] = n - 1;
+            } else {
+                kk[a][0] = k;
+                kk[a][1] = k + 1;
+            }
+            ww[a][0] = 1.0 - f;
+            ww[a][1] = f;
+        }
+        int corners = 1 << m->dim;
+        for (int q = 0; q < corners; ++q) {
+            double W = 1.0;
+            int64_t lin = 0, stride = 1;
+            for (int a = 0; a < m->dim; ++a) {
+                int b = (q >> a) & 1;
+                W *= ww[a][b];
+                lin += kk[a][b] * stride;
+                stride *= m->n[a];
+            }
+            for (int k = 0; k < C; ++k) acc[k * M + lin] += W * phi[k];
+            ws[lin] += W;
+        }
+    }
+    double Vc = cell_volume(m);
+    for (int64_t c = 0; c < M; ++c) {
+        double cs = cell_scale ? cell_scale[c] : 1.0;
+        for (int k = 0; k < C; ++k) S[k * M + c] = -(weight / Vc) * cs * acc[k * M + c];
+        if (wsum) wsum[c] = ws[c];
+    }
+    free(acc);
+    free(ws);
+    if (nonfinite_out) *nonfinite_out = nonfinite;
+    return skipped;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Trajectory producer: droplets advanced over one carrier time step in an  */
 /* analytic gas field (eqs. Stokes-drag, evap-model and Jacobian-evolution, */
 /* dimensional forms), with the droplet's mass and momentum contributions   */
