@@ -220,14 +220,33 @@ fla_status fla_project_sources_noalloc(fla_ctx* ctx, const fla_mesh* mesh, const
  * sum can overflow), hence order-independent.  Binary64 calls add a second
  * integer word per channel for the quantisation remainders, so that the
  * error of a particle stays below 2^-62 of the largest |phi| whatever the
- * count.  den, if given, receives the particle count per cell.  Particles
- * with a non-finite velocity, gas velocity, radius or source term are
- * skipped and counted in stats.skipped; particles outside a closed box in
- * stats.outside.  Meshes of more than 16384 * 1024 cells (16384 * 512 in
+ * count.  den, if given, receives the particle count per cell.  A particle
+ * with a finite position outside a closed box is counted in stats.outside
+ * (whatever its other inputs); any other particle with a non-finite input
+ * or source term is skipped and counted in stats.skipped.  Meshes of more than 16384 * 1024 cells (16384 * 512 in
  * binary64 3-D) return INVALID_ARG.  Other errors as fla_project_sources. */
 fla_status psicell_accumulate(fla_ctx* ctx, const fla_mesh* mesh,
                               const fla_trajectories* particles, double particle_weight,
                               const fla_params* params, const fla_fields* out, void* stream);
+
+/* Cloud-in-cell accumulation, the linear-interpolation comparator the paper
+ * names beside PSI-CELL (introduction): each particle's
+ * phi_p = [mdot_p, F_p + mdot_p v_p] is shared among the 2^dim cell centres
+ * around it with per-axis hat weights 1 - |d|/dx (d the offset to the
+ * centre; the corners of the dual cell that holds the particle):
+ *   S_k(c) = -(particle_weight / V_c) * cell_scale(c) * sum_p W_cp phi_pk.
+ * Periodic axes wrap; on a closed axis a particle less than half a cell from
+ * a wall puts that axis's whole weight on the boundary cell, so every
+ * particle deposits all of phi_p.  den, if given, receives sum_p W_cp.
+ * Particles outside a closed box (x == hi belongs to it) are counted in
+ * stats.outside, other particles with a non-finite input in stats.skipped
+ * (the position decides first, as in psicell_accumulate).  The
+ * sums are exact integer sums as in psicell_accumulate (two words per
+ * channel for binary64), hence deterministic.  Meshes of more than
+ * 16384 * 1024 cells (16384 * 512 in binary64) return INVALID_ARG.  Other
+ * errors as psicell_accumulate. */
+fla_status cic_accumulate(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* particles,
+                          double particle_weight, const fla_params* params, const fla_fields* out, void* stream);
 
 /* Statistics of the last call on ctx.  Synchronises the device, then copies
  * into *out (host).  Errors: INVALID_ARG for NULL, DEVICE. */

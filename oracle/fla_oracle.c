@@ -781,13 +781,20 @@ int64_t orc_cic(const orc_mesh* m, int64_t Np, const double* x, const double* v,
             vp[a] = v[a * Np + p];
             up[a] = ug[a * Np + p];
         }
-        if (!all_finite(xp, m->dim) || !all_finite(vp, m->dim) || !all_finite(up, m->dim) || !isfinite(r[p])) {
+        /* as in PSI-CELL: the position decides first (outside a closed box */
+        /* is counted as outside whatever the other inputs)                */
+        if (!all_finite(xp, m->dim)) {
             ++skipped;
             ++nonfinite;
             continue;
         }
         if (orc_psicell_cell_of(m, xp) < 0) {
             ++skipped;
+            continue;
+        }
+        if (!all_finite(vp, m->dim) || !all_finite(up, m->dim) || !isfinite(r[p])) {
+            ++skipped;
+            ++nonfinite;
             continue;
         }
         orc_droplet_phi(m->dim, r[p], vp, up, rho_d, mu, delta, phi, 0, 0, 0);

@@ -100,6 +100,9 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 _lib.psicell_accumulate.restype = C.c_int
 _lib.psicell_accumulate.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories), C.c_double,
                                     C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
+_lib.cic_accumulate.restype = C.c_int
+_lib.cic_accumulate.argtypes = [_vp, C.POINTER(fla_mesh), C.POINTER(fla_trajectories), C.c_double,
+                                C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
 _lib.fla_get_stats.restype = C.c_int
 _lib.fla_get_stats.argtypes = [_vp, C.POINTER(fla_stats)]
 _lib.fla_profile_enable.restype = C.c_int
@@ -391,6 +394,12 @@ class Context:
                                              C.byref(params.to_c()), int(prec),
                                              C.byref(make_fields(S_mass, S_mom, den, pairs)),
                                              _stream_handle(stream)))
+
+    def cic_accumulate(self, mesh: fla_mesh, particles: fla_trajectories, weight: float, params: Params, S_mass,
+                       S_mom, den=None, stream=None):
+        st = _lib.cic_accumulate(self._h, C.byref(mesh), C.byref(particles), float(weight), C.byref(params.to_c()),
+                                 C.byref(make_fields(S_mass, S_mom, den)), _stream_handle(stream))
+        self._check(st)
 
     def profile_enable(self, on: bool = True):
         self._check(_lib.fla_profile_enable(self._h, int(bool(on))))

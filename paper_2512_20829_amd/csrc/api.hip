@@ -665,6 +665,71 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
 }
 
 template <typename R, int D>
+fla_status cic_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double weight, const fla_params* p,
+                    const fla_mesh* mesh, const fla_fields* out, hipStream_t s)
+{
+    constexpr int C = D + 1;
+    constexpr int W = PsiWords<R>::value;
+    PsiArgs a{};
+    // tiles of power-of-two edges whose upper halo fits the LDS sums:
+    // 16 x 8 x 8 (binary64: 8^3) in 3-D, 32^2 (binary64: 32 x 16) in 2-D
+    const bool f64 = sizeof(R) == 8;
+    int pt[3] = {D == 3 ? (f64 ? 8 : 16) : 32, D == 3 ? 8 : (f64 ? 16 : 32), D == 3 ? 8 : 1};
+    int64_t nt = 1;
+    for (int ax = 0; ax < D; ++ax) nt *= (m.n[ax] + pt[ax] - 1) / pt[ax];
+    CHECK_ARG(nt <= kPsiMaxTiles, f64 ? "cic_accumulate supports at most 16384 * 512 cells in binary64"
+                                      : "cic_accumulate supports at most 16384 * 1024 cells");
+    for (int ax = 0; ax < 3; ++ax) {
+        a.pt[ax] = ax < D ? pt[ax] : 1;
+        a.pnt[ax] = ax < D ? (m.n[ax] + pt[ax] - 1) / pt[ax] : 1;
+        a.ptlog[ax] = __builtin_ctz((unsigned)a.pt[ax]);
+    }
+    a.pntiles = (int)nt;
+    a.cpt = a.pt[0] * a.pt[1] * a.pt[2];
+    a.cptlog = a.ptlog[0] + a.ptlog[1] + a.ptlog[2];
+    a.nblocks = kPsiBlocks;
+    const int64_t N = t.count;
+    const int64_t hw = (int64_t)a.pntiles * a.nblocks + 1;
+    const int64_t sw = scan_tmp_words(hw);
+    auto layout = [&](Carver& c) {
+        a.maxbits = c.take<unsigned long long>(4);
+        a.qscale = c.take<double>(5);
+        a.codes = c.take<int>(N > 0 ? N : 1);
+        a.blockhist = c.take<unsigned int>(hw);
+        a.tcursor = c.take<unsigned int>(a.pntiles);
+        a.bucket = c.take<CicRec<R>>(N > 0 ? N : 1);
+        a.blockmax = c.take<unsigned long long>((size_t)a.nblocks * 4);
+        a.acc = c.take<unsigned long long>((size_t)(W * C + 1) * (size_t)m.M);
+        a.scan_tmp = c.take<uint32_t>(sw);
+    };
+    {
+        Carver probe(nullptr);
+        layout(probe);
+        fla_status st = ensure_ws(ctx, probe.off + 256);
+        if (st != FLA_OK) return st;
+    }
+    Carver c(ctx->ws);
+    layout(c);
+    a.scan_words = sw;
+    HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
+    HIP_OK(launch_fill_u64(ctx->stats + ST_TRAJ, 1, (unsigned long long)t.count, s));
+    a.m = m;
+    a.p = t;
+    a.ph = PhysDev{p->rho_d, p->mu, p->delta, p->h0, p->cutoff, p->scale};
+    a.weight = weight;
+    a.cell_scale = mesh->cell_scale;
+    a.out[0] = out->S_mass;
+    for (int ax = 0; ax < D; ++ax) a.out[1 + ax] = out->S_mom[ax];
+    a.den = out->den;
+    a.stats = ctx->stats;
+    {
+        StageTimer tm(ctx, 4, s);
+        HIP_OK((launch_cic<R, D>(a, s)));
+    }
+    return FLA_OK;
+}
+
+template <typename R, int D>
 fla_status bandwidth_forward_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const float* theta, float* hfac,
                                   float* z, float* o, float* fraw, hipStream_t s)
 {
@@ -956,6 +1021,38 @@ FLA_EXPORT fla_status psicell_accumulate(fla_ctx* ctx, const fla_mesh* mesh, con
                        : psicell_impl<float, 2>(ctx, m, t, particle_weight, params, mesh, out, s);
         return f64 ? psicell_impl<double, 3>(ctx, m, t, particle_weight, params, mesh, out, s)
                    : psicell_impl<float, 3>(ctx, m, t, particle_weight, params, mesh, out, s);
+    } catch (...) {
+        ctx->err = "internal error";
+        return FLA_ERR_DEVICE;
+    }
+}
+
+FLA_EXPORT fla_status cic_accumulate(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* particles,
+                                     double particle_weight, const fla_params* params, const fla_fields* out,
+                                     void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    try {
+        MeshDev m;
+        fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+        if (st != FLA_OK) return st;
+        TrajDev t;
+        st = check_traj(ctx, particles, m.dim, false, &t);
+        if (st != FLA_OK) return st;
+        st = check_params(ctx, params, false);
+        if (st != FLA_OK) return st;
+        st = check_fields(ctx, out, m.dim);
+        if (st != FLA_OK) return st;
+        CHECK_ARG(is_fin(particle_weight), "particle_weight must be finite");
+        HIP_OK(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        bool f64 = particles->prec == FLA_F64;
+        if (m.dim == 2)
+            return f64 ? cic_impl<double, 2>(ctx, m, t, particle_weight, params, mesh, out, s)
+                       : cic_impl<float, 2>(ctx, m, t, particle_weight, params, mesh, out, s);
+        return f64 ? cic_impl<double, 3>(ctx, m, t, particle_weight, params, mesh, out, s)
+                   : cic_impl<float, 3>(ctx, m, t, particle_weight, params, mesh, out, s);
     } catch (...) {
         ctx->err = "internal error";
         return FLA_ERR_DEVICE;

@@ -128,6 +128,7 @@ struct PsiArgs {
     void* binned;                // records grouped by bin (loc = code, top bit = skip)
     void* bucket;                // records grouped by tile (loc = cell in tile or kPsiSkip)
     unsigned long long* blockmax; // nblocks x C bit patterns of per-block max |phi_k|
+    unsigned long long* acc;     // CIC: (C + 1) channels x words x M integer sums (zeroed by the launcher)
     uint32_t* scan_tmp;
     int64_t scan_words;
 };
@@ -150,6 +151,19 @@ constexpr int kPsiBlocks = 1024;
 
 template <typename R, int D>
 hipError_t launch_psicell(const PsiArgs& a, hipStream_t s);
+
+// One bucketed CIC particle: source terms, the fractional offsets from the
+// lower-corner cell centre along each axis, and that cell in its tile.
+template <typename R> struct CicRec {
+    R phi[4];
+    R frac[3];
+    uint32_t loc;
+};
+
+// Cloud-in-cell accumulation on the PSI-CELL tile buckets (tiles of a.pt
+// cells, keyed by each particle's lower-corner cell).
+template <typename R, int D>
+hipError_t launch_cic(const PsiArgs& a, hipStream_t s);
 
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);

@@ -530,6 +530,321 @@ __global__ __launch_bounds__(256) void k_psi_reduce(PsiArgs a)
     }
 }
 
+// ---------------------------------------------------------------- cloud in cell
+// Each particle's phi is shared among the 2^D cell centres around it with
+// per-axis hat weights (1 - f, f), f the fractional offset of the particle
+// from the lower centre in cell widths; on a periodic axis the upper centre
+// of the last cell is the first cell; on a closed axis a particle less than
+// half a cell from a wall puts all of that axis's weight on the boundary
+// cell (f = 0).  The sums are exact integer sums as in PSI-CELL, formed per
+// tile in LDS over the tile's cells and a one-cell halo on the upper side
+// of every axis, then added to a global integer accumulator (one atomic
+// per halo'd cell and word, order-independent); a weight channel sums the
+// weights themselves.
+
+// Lower-corner cell and fraction along axis ax; false for a position
+// outside a closed box (x == hi belongs to the box).  Binary64, in the
+// order of the definition (u = (x - lo)/w - 1/2, k = floor(u), f = u - k).
+__device__ inline bool cic_axis(const MeshDev& m, int ax, double x, int& k0, double& f)
+{
+    const double u = (x - m.lo[ax]) / m.w[ax] - 0.5;
+    const double fl = floor(u);
+    f = u - fl;
+    if (!(fabs(fl) < 9.0e15)) return false;
+    int64_t k = (int64_t)fl;
+    const int64_t n = m.n[ax];
+    if (m.periodic[ax]) {
+        k0 = (int)posmod(k, n);
+        return true;
+    }
+    // inside the closed box: (x - lo)/w in [0, n], i.e. u in [-1/2, n - 1/2]
+    if (!(u >= -0.5 && u <= (double)n - 0.5)) return false;
+    if (k < 0) {
+        k0 = 0;
+        f = 0.0;
+    } else if (k >= n - 1) {
+        k0 = (int)(n - 1);
+        f = 0.0;
+    } else {
+        k0 = (int)k;
+    }
+    return true;
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_cic_count(PsiArgs a)
+{
+    extern __shared__ unsigned int hist[];
+    const int ntl = a.pntiles;
+    for (int t = threadIdx.x; t < ntl; t += blockDim.x) hist[t] = 0;
+    __syncthreads();
+    const int64_t N = a.p.count;
+    const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = beg + chunk < N ? beg + chunk : N;
+    unsigned long long outside = 0, bad = 0;
+    for (int64_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
+        double x[3];
+        bool fin = true;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            x[ax] = a.p.x[ax][p];
+            fin = fin && isfinite(x[ax]);
+        }
+        int code = -1;
+        if (!fin) {
+            ++bad;
+        } else {
+            int idx[3] = {0, 0, 0};
+            bool in = true;
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                double f;
+                in = in && cic_axis(a.m, ax, x[ax], idx[ax], f);
+            }
+            if (in) {
+                code = psi_code<D>(a, idx);
+                atomicAdd(&hist[code >> a.cptlog], 1u);
+            } else {
+                ++outside;
+            }
+        }
+        a.codes[p] = code;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntl; t += blockDim.x) a.blockhist[(int64_t)t * gridDim.x + blockIdx.x] = hist[t];
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.blockhist[(int64_t)ntl * gridDim.x] = 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        outside += __shfl_xor(outside, o, kWave);
+        bad += __shfl_xor(bad, o, kWave);
+    }
+    if ((threadIdx.x % kWave) == 0 && outside) atomicAdd(&a.stats[ST_OUTSIDE], outside);
+    if ((threadIdx.x % kWave) == 0 && bad) atomicAdd(&a.stats[ST_SKIPPED], bad);
+}
+
+// Records into tile buckets: the slots of a block's particles come from its
+// scanned per-tile counts, handed out by LDS cursors (the order inside a
+// bucket does not matter: the sums are integer sums).
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_cic_scatter(PsiArgs a)
+{
+    constexpr int C = D + 1;
+    extern __shared__ unsigned int cursor[];
+    const int ntl = a.pntiles;
+    for (int t = threadIdx.x; t < ntl; t += blockDim.x) cursor[t] = a.blockhist[(int64_t)t * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const int64_t N = a.p.count;
+    const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = beg + chunk < N ? beg + chunk : N;
+    CicRec<R>* bucket = (CicRec<R>*)a.bucket;
+    double mx[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) mx[k] = 0.0;
+    unsigned long long bad = 0;
+    const uint32_t cmask = (uint32_t)a.cpt - 1u;
+    for (int64_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
+        const int code = a.codes[p];
+        if (code < 0) continue;
+        R v[3], ug[3];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            v[ax] = ((const R*)a.p.v[ax])[p];
+            ug[ax] = ((const R*)a.p.ug[ax])[p];
+        }
+        const R r = ((const R*)a.p.r)[p];
+        bool ok = isfinite(r);
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) ok = ok && isfinite(v[ax]) && isfinite(ug[ax]);
+        R phi[4] = {0, 0, 0, 0};
+        if (ok) {
+            droplet_phi_t<D, R>(r, v, ug, a.ph, phi);
+#pragma unroll
+            for (int k = 0; k < C; ++k) ok = ok && isfinite(phi[k]);
+        }
+        CicRec<R> rec;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) rec.phi[k] = (ok && k < C) ? phi[k] : (R)0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) rec.frac[ax] = (R)0;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            int k0;
+            double f;
+            cic_axis(a.m, ax, a.p.x[ax][p], k0, f);
+            rec.frac[ax] = (R)f;
+        }
+        rec.loc = ok ? ((uint32_t)code & cmask) : kPsiSkip;
+        bad += ok ? 0ull : 1ull;
+#pragma unroll
+        for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], fabs((double)rec.phi[k]));
+        const unsigned int slot = atomicAdd(&cursor[code >> a.cptlog], 1u);
+        bucket[slot] = rec;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, kWave);
+    if ((threadIdx.x % kWave) == 0 && bad) atomicAdd(&a.stats[ST_SKIPPED], bad);
+    __shared__ double bm[256 / kWave][4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], __shfl_xor(mx[k], o, kWave));
+    if ((threadIdx.x % kWave) == 0)
+#pragma unroll
+        for (int k = 0; k < C; ++k) bm[threadIdx.x / kWave][k] = mx[k];
+    __syncthreads();
+    if (threadIdx.x < C) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) v = fmax(v, bm[w][threadIdx.x]);
+        a.blockmax[(int64_t)blockIdx.x * 4 + threadIdx.x] = (unsigned long long)__double_as_longlong(v);
+    }
+}
+
+// One workgroup per tile: the tile's particles deposit into LDS sums over
+// the tile and its upper halo, which are then added to the global sums.
+// Channels 0..C-1 carry phi (W words each), channel C the weights (1 word,
+// scale 2^f of the fine word: at most one unit of weight per particle).
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_cic_reduce(PsiArgs a)
+{
+    constexpr int C = D + 1;
+    constexpr int W = PsiWords<R>::value;
+    constexpr int NCH = W * C + 1;       // integer words per cell
+    extern __shared__ unsigned long long sacc[];
+    const int hx = a.pt[0] + 1, hy = a.pt[1] + 1, hz = D == 3 ? a.pt[2] + 1 : 1;
+    const int HC = hx * hy * hz;
+    for (int i = threadIdx.x; i < NCH * HC; i += blockDim.x) sacc[i] = 0ull;
+    double qs[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) qs[k] = a.qscale[k];
+    // a particle can put up to 2^D remainders (and weights) on one cell
+    // (periodic axes of one cell): 2^-D of the PSI-CELL fine scale
+    const double qf = a.qscale[4] / (double)(1 << D);
+    __syncthreads();
+    const int tile = blockIdx.x;
+    const int64_t nbk = a.nblocks;
+    const int64_t beg = a.blockhist[(int64_t)tile * nbk];
+    const int64_t end = a.blockhist[(int64_t)(tile + 1) * nbk];
+    const CicRec<R>* bucket = (const CicRec<R>*)a.bucket;
+    for (int64_t sl = beg + threadIdx.x; sl < end; sl += blockDim.x) {
+        const CicRec<R> rec = bucket[sl];
+        if (rec.loc == kPsiSkip) continue;
+        const int l0 = (int)(rec.loc & (uint32_t)(a.pt[0] - 1));
+        const int l1 = (int)((rec.loc >> a.ptlog[0]) & (uint32_t)(a.pt[1] - 1));
+        const int l2 = D == 3 ? (int)(rec.loc >> (a.ptlog[0] + a.ptlog[1])) : 0;
+        double wa[3][2];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const double f = ax < D ? (double)rec.frac[ax] : 0.0;
+            wa[ax][0] = 1.0 - f;
+            wa[ax][1] = f;
+        }
+#pragma unroll
+        for (int q = 0; q < (1 << D); ++q) {
+            const int b0 = q & 1, b1 = (q >> 1) & 1, b2 = D == 3 ? (q >> 2) & 1 : 0;
+            const double w = wa[0][b0] * wa[1][b1] * (D == 3 ? wa[2][b2] : 1.0);
+            if (w == 0.0) continue;
+            const int hc = (l0 + b0) + hx * ((l1 + b1) + hy * (l2 + b2));
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+                const double v = (double)rec.phi[k] * w * qs[k];
+                const double hi = rint(v);
+                atomicAdd(&sacc[(size_t)(W * k) * HC + hc], (unsigned long long)(long long)hi);
+                if (W == 2) {
+                    const long long lo = llrint((v - hi) * qf);
+                    atomicAdd(&sacc[(size_t)(W * k + 1) * HC + hc], (unsigned long long)lo);
+                }
+            }
+            atomicAdd(&sacc[(size_t)(W * C) * HC + hc], (unsigned long long)llrint(w * qf));
+        }
+    }
+    __syncthreads();
+    const MeshDev& m = a.m;
+    int tc[3];
+    tc[0] = tile % a.pnt[0];
+    tc[1] = (tile / a.pnt[0]) % a.pnt[1];
+    tc[2] = (D == 3) ? tile / (a.pnt[0] * a.pnt[1]) : 0;
+    const int64_t M = m.M;
+    for (int hc = threadIdx.x; hc < HC; hc += blockDim.x) {
+        const int h0 = hc % hx, h1 = (hc / hx) % hy, h2 = hc / (hx * hy);
+        int64_t i[3] = {(int64_t)tc[0] * a.pt[0] + h0, (int64_t)tc[1] * a.pt[1] + h1,
+                        D == 3 ? (int64_t)tc[2] * a.pt[2] + h2 : 0};
+        bool inside = true;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            if (i[ax] >= m.n[ax]) {
+                if (m.periodic[ax])
+                    i[ax] -= m.n[ax];
+                else
+                    inside = false;
+            }
+        }
+        if (!inside) continue;
+        const int64_t c = i[0] + (int64_t)m.n[0] * (i[1] + (int64_t)m.n[1] * i[2]);
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) {
+            const unsigned long long v = sacc[(size_t)j * HC + hc];
+            if (v) atomicAdd(&a.acc[(size_t)j * M + c], v);
+        }
+    }
+}
+
+template <typename R, int D>
+__global__ void k_cic_finish(PsiArgs a)
+{
+    constexpr int C = D + 1;
+    constexpr int W = PsiWords<R>::value;
+    const MeshDev& m = a.m;
+    const int64_t M = m.M;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= M) return;
+    const double qf = a.qscale[4] / (double)(1 << D);
+    const double cs = a.cell_scale ? (double)((const R*)a.cell_scale)[c] : 1.0;
+    const double f = -(a.weight / m.vol) * cs;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        double units = (double)(long long)a.acc[(size_t)(W * k) * M + c];
+        if (W == 2) units += (double)(long long)a.acc[(size_t)(W * k + 1) * M + c] / qf;
+        ((R*)a.out[k])[c] = (R)(f * (units / a.qscale[k]));
+    }
+    if (a.den) ((R*)a.den)[c] = (R)((double)(long long)a.acc[(size_t)(W * C) * M + c] / qf);
+}
+
+template <typename R, int D>
+hipError_t launch_cic(const PsiArgs& a, hipStream_t s)
+{
+    constexpr int C = D + 1;
+    constexpr int W = PsiWords<R>::value;
+    hipError_t e = launch_fill_u64(a.maxbits, C, 0ull, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u64(a.acc, (int64_t)(W * C + 1) * a.m.M, 0ull, s);
+    if (e != hipSuccess) return e;
+    const size_t lds_t = sizeof(unsigned int) * (size_t)a.pntiles;
+    if (a.p.count == 0) {
+        e = launch_fill_u32(a.blockhist, (int64_t)a.pntiles * a.nblocks + 1, 0u, s);
+        if (e != hipSuccess) return e;
+        e = launch_fill_u64(a.blockmax, (int64_t)a.nblocks * 4, 0ull, s);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL((k_cic_count<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
+        e = launch_exclusive_scan_u32(a.blockhist, (int64_t)a.pntiles * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_cic_scatter<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
+    }
+    hipLaunchKernelGGL((k_psi_scale<D>), dim3(1), dim3(256), 0, s, a);
+    const int hcells = (a.pt[0] + 1) * (a.pt[1] + 1) * (D == 3 ? a.pt[2] + 1 : 1);
+    const size_t lds_r = sizeof(unsigned long long) * (size_t)(W * C + 1) * (size_t)hcells;
+    hipLaunchKernelGGL((k_cic_reduce<R, D>), dim3(a.pntiles), dim3(256), lds_r, s, a);
+    hipLaunchKernelGGL((k_cic_finish<R, D>), dim3((unsigned)((a.m.M + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_cic<float, 2>(const PsiArgs&, hipStream_t);
+template hipError_t launch_cic<float, 3>(const PsiArgs&, hipStream_t);
+template hipError_t launch_cic<double, 2>(const PsiArgs&, hipStream_t);
+template hipError_t launch_cic<double, 3>(const PsiArgs&, hipStream_t);
+
 __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
