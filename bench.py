@@ -38,6 +38,9 @@ its fused epilogue.  Printed as one JSON line (rank 0):
   large        errors of the plain, learned and deposition forms on the
                headline workload against a 1.68G-particle PSI-CELL reference,
                and the learned form's throughput
+  table1       the four Table 1 cases through the trajectory producer: FLA
+               errors against a 100x box-counted reference after 2 s of
+               droplet motion in a Taylor-Green vortex, and step times
 """
 import argparse
 import json
@@ -482,6 +485,100 @@ def batch_section(ctx, args, dev):
     return out
 
 
+def table1_section(ctx, args, dev):
+    """The four Table 1 cases as a second workload.  Monodisperse droplets of
+    each case start at rest on the periodic unit square in the steady
+    Taylor-Green vortex of amplitude 1 m/s (U/L = 1 s^-1, so the relaxation
+    time equals the case's St) and are advanced by fla_advance_project over
+    2 s in 100 carrier steps (8 RK4 substeps each); evaporating cases lose
+    half of r^2 over the run (delta = -r0^2/(4 s)).  FLA: a 64^2 lattice of
+    droplets, projected every step on the 64^2 mesh.  Reference: 100 times as
+    many droplets at random positions, advanced by the same producer, each
+    step's rates box-counted (FLA_DEPOSIT with a vanishing bandwidth puts a
+    droplet's whole n0 V_seed phibar into its cell, which is PSI-CELL with
+    statistical weight n0 V_seed), as two independent half clouds for the
+    noise floor.  Reported per case: the noise-debiased errors of the FLA
+    estimator and deposition forms against the reference after 2 s, and the
+    time per carrier step of the FLA and reference runs."""
+    import numpy as np
+    import torch
+
+    import paper_2512_20829_amd as F
+    import workloads as W
+
+    mesh_w = W.unit_mesh(2, 64, True)
+    mesh = F.mesh_of(mesh_w)
+    M = mesh_w.cells
+    flow = F.make_flow(F.FLA_FLOW_TAYLOR_GREEN, U=1.0, k=1.0)
+    T, nsteps, sub = 2.0, 100, 8
+    dt = T / nsteps
+    n_fla = 64
+    n_cloud = 100 * n_fla * n_fla
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = []
+    for j, case in enumerate(W.TABLE1):
+        mu = W.TABLE1_RHO_F * case["nu"]
+        delta = -case["r_d"] ** 2 / (4.0 * T) if case["evaporating"] else 0.0
+        prm = dict(rho_d=case["rho_d"], mu=mu, delta=delta, cutoff=4.0)
+
+        def run(d, h0, mode, field_planes, last_extra=None):
+            """Advance d for nsteps, projecting every step; returns ms per step."""
+            t = [d.x.to(dev).contiguous(), d.v.to(dev).contiguous(), d.J.to(dev).contiguous(),
+                 d.dJ.to(dev).contiguous(), d.r.to(dev).contiguous()]
+            st, keep = F.make_droplets(*t, n0=d.n0, seed_volume=d.seed_volume)
+            p = F.Params(h0=h0, mode=mode, **prm)
+            step = F.make_step(dt, sub, True)
+            torch.cuda.synchronize()
+            e0.record()
+            for it in range(nsteps):
+                if it == nsteps - 1 and last_extra is not None:
+                    # the same final step, in the other mode, without updating the state
+                    ctx.advance_project(mesh, st, flow, F.make_step(dt, sub, False),
+                                        F.Params(h0=h0, mode=last_extra[0], **prm), F.FLA_F64,
+                                        last_extra[1][0], last_extra[1][1:])
+                ctx.advance_project(mesh, st, flow, step, p, F.FLA_F64, field_planes[0], field_planes[1:])
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / nsteps
+
+        planes = lambda: [torch.zeros(M, dtype=torch.float64, device=dev) for _ in range(3)]
+        fla_nw, fla_dep = planes(), planes()
+        ms_fla = run(W.table1_droplets(j, n_fla, device=dev), 1.0 / n_fla, F.FLA_NW, fla_nw,
+                     (F.FLA_DEPOSIT, fla_dep))
+        halves, ms_ref = [], 0.0
+        for h in range(2):
+            d = W.table1_droplets(j, n_cloud // 2, seed=7 + j, device=dev, lattice_seeding=False,
+                                  offset=h * (n_cloud // 2))
+            pl = planes()
+            ms_ref += run(d, 1e-12, F.FLA_DEPOSIT, pl)
+            halves.append(pl)
+        ref = [(a + b) * 0.5 for a, b in zip(*halves)]
+        chans = range(3) if case["evaporating"] else range(1, 3)
+        floor = {k: float(((halves[0][k] - halves[1][k]) ** 2).sum() / (4 * (ref[k] ** 2).sum())) for k in chans}
+
+        def deb(S):
+            e = []
+            for k in chans:
+                e2 = float(((S[k] - ref[k]) ** 2).sum() / (ref[k] ** 2).sum())
+                e.append(math.sqrt(max(e2 - floor[k], 0.0)))
+            return round(float(np.mean(e)), 5)
+
+        row = {"case": case["case"], "St": case["St"], "delta": delta, "rho_d": case["rho_d"], "r_d": case["r_d"],
+               "fla_error_nw": deb(fla_nw), "fla_error_deposit": deb(fla_dep),
+               "noise_floor": round(math.sqrt(float(np.mean(list(floor.values())))), 5),
+               "ms_per_step_fla": round(ms_fla, 4), "ms_per_step_reference": round(ms_ref, 4),
+               "reference_over_fla_time": round(ms_ref / ms_fla, 2)}
+        log(f"table1: {row}")
+        out.append(row)
+        torch.cuda.empty_cache()
+    return {"workload": "Table 1 cases: monodisperse droplets from rest in the steady Taylor-Green vortex (1 m/s, "
+                        "periodic unit square, 64^2 mesh), 2 s in 100 carrier steps of 8 RK4 substeps; FLA 4096 "
+                        "lattice droplets vs a 409,600-droplet box-counted reference",
+            "error": "mean over the source fields (momentum only without evaporation) of the noise-debiased rel "
+                     "L2 against the reference after 2 s",
+            "cases": out}
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -681,7 +778,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only-headline", action="store_true", help="time the headline workload only")
-    ap.add_argument("--only", choices=["headline", "abc128", "tg2d", "psicell"], default=None,
+    ap.add_argument("--only", choices=["headline", "abc128", "tg2d", "psicell", "table1"], default=None,
                     help="time one projection workload only (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psicell", action="store_true")
@@ -691,6 +788,7 @@ def main():
     ap.add_argument("--batch-snapshots", type=int, default=64)
     ap.add_argument("--psicell-particles", type=int, default=200_000_000)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain section")
+    ap.add_argument("--no-table1", action="store_true", help="skip the Table 1 sweep")
     ap.add_argument("--train-snapshots", type=int, default=500)
     ap.add_argument("--train-trajectories", type=int, default=200_000)
     ap.add_argument("--train-particles", type=int, default=50_000_000)
@@ -739,7 +837,14 @@ def main():
             torch.cuda.synchronize()
         ctx.close()
         return
+    if args.only == "table1":
+        print(json.dumps({"table1": table1_section(ctx, args, dev)}), flush=True)
+        ctx.close()
+        return
+    table1 = None
     if args.only is None:
+        if not args.no_table1:
+            table1 = table1_section(ctx, args, dev)
         if not args.no_batch:
             batch = batch_section(ctx, args, dev)
         if not args.no_psicell:
@@ -797,6 +902,7 @@ def main():
         "psicell": psi,
         "learned_vs_plain": learned,
         "large": large,
+        "table1": table1,
     }
     log(f"main line: {name}")
     print(json.dumps(out), flush=True)

@@ -223,3 +223,32 @@ def test_abc_full_size_one_step(ctx):
     assert_fields_close(S[:, ref.cells], ref.S, TOL["f32"], "producer full size block")
     np.testing.assert_array_equal(pairs.cpu().numpy()[ref.cells], ref.pairs)
     assert stats["skipped"] == t.skipped == 0
+
+
+def test_vanishing_bandwidth_deposition_is_box_counting(ctx):
+    """FLA_DEPOSIT with a bandwidth that reaches no cell centre puts each
+    droplet's n0 V_seed phibar into the cell that holds it: the box counting
+    of the step's rates (the reference of the Table 1 sweep)."""
+    import paper_2512_20829_amd as F
+    d = W.table1_droplets(2, 20000, seed=5, lattice_seeding=False)
+    run = Run(d)
+    mesh = W.unit_mesh(2, 16, True)
+    flow = F.make_flow(F.FLA_FLOW_TAYLOR_GREEN, U=1.0, k=1.0)
+    c = W.TABLE1[2]
+    delta = -c["r_d"] ** 2 / 8.0
+    M = mesh.cells
+    S_mass, S_mom, _ = F.alloc_fields(M, 2, torch.float64, DEV, den=False)
+    p = F.Params(rho_d=c["rho_d"], mu=c["nu"], delta=delta, h0=1e-12, mode=F.FLA_DEPOSIT)
+    ctx.advance_project(F.mesh_of(mesh), run.st, flow, F.make_step(0.02, 8), p, F.FLA_F64, S_mass, S_mom)
+    torch.cuda.synchronize()
+    S = torch.stack([S_mass, *S_mom]).cpu().numpy()
+    x = run.t[0].cpu().numpy()
+    phi = run.phibar.cpu().numpy()
+    cell = np.floor(x[0] * 16).astype(int) % 16 + 16 * (np.floor(x[1] * 16).astype(int) % 16)
+    box = np.zeros((3, M))
+    for k in range(3):
+        np.add.at(box[k], cell, d.n0 * d.seed_volume * phi[k])
+    box *= -1.0 / (1.0 / M)
+    assert ctx.stats()["zero_support"] == d.count
+    for k in range(3):
+        assert rel_l2(S[k], box[k]) <= 1e-13

@@ -93,3 +93,17 @@ def test_bench_learned_crossing_interpolates_in_log_n():
     assert n is None and "125" in note
     n, note = bench.learned_crossing(rows, 0.4)
     assert n is None and "does not reach" in note
+
+
+def test_table1_constants_match_the_printed_table():
+    """The Table 1 cases the benchmark sweeps are the printed ones, and their
+    relaxation time 2 rho r^2 / (9 rho_f nu) is the printed St (U/L = 1)."""
+    import json
+    with open(os.path.join(ROOT, "tests", "golden", "table1_parameters.json")) as f:
+        t1 = json.load(f)
+    assert len(W.TABLE1) == 4 and W.TABLE1_RHO_F == t1["rho_f"]
+    for j, c in enumerate(W.TABLE1):
+        assert (c["rho_d"], c["r_d"], c["nu"], c["St"]) == (t1["rho_d"][j], t1["r_d"][j], t1["nu"][j], t1["St"][j])
+        assert c["evaporating"] == t1["columns"][j].startswith("evaporating")
+        tau = 2 * c["rho_d"] * c["r_d"] ** 2 / (9 * W.TABLE1_RHO_F * c["nu"])
+        assert tau == pytest.approx(c["St"], rel=1e-12)

@@ -466,3 +466,34 @@ def seed_droplets(dim: int, per_axis: int, seed: int = 0, device="cpu", speed: f
         radius_uniform(N, seed, 5.0, 20.0, device)
     return Droplets(x0.contiguous(), v0.contiguous(), J, dJ, r.to(torch.float64).contiguous(), N0_DEFAULT,
                     1.0 / N)
+
+
+# ---------------------------------------------------------------------------
+# Table 1 of the paper (simulation parameters): droplet density and radius
+# (SI), carrier kinematic viscosity, Stokes number, carrier density 1, for
+# the non-evaporating and evaporating cases at Re = 20 and Re = 100.
+TABLE1 = [
+    {"case": "non-evaporating Re=20", "rho_d": 2500.0, "r_d": 0.003, "nu": 0.05, "St": 0.1, "evaporating": False},
+    {"case": "non-evaporating Re=100", "rho_d": 2000.0, "r_d": 0.0015, "nu": 0.01, "St": 0.1, "evaporating": False},
+    {"case": "evaporating Re=20", "rho_d": 2500.0, "r_d": 0.003, "nu": 0.05, "St": 0.1, "evaporating": True},
+    {"case": "evaporating Re=100", "rho_d": 2500.0, "r_d": 0.003, "nu": 0.01, "St": 0.5, "evaporating": True},
+]
+TABLE1_RHO_F = 1.0
+
+
+def table1_droplets(column: int, n: int, seed: int = 0, device="cpu", lattice_seeding: bool = True,
+                    offset: int = 0) -> Droplets:
+    """Monodisperse droplets of a Table 1 column at rest on the periodic unit
+    square (J = I, dJ = 0): n = per-axis count of a cell-centred lattice, or
+    the number of uniform random positions (counter-hash stream, `offset`
+    for disjoint sub-clouds)."""
+    c = TABLE1[column]
+    if lattice_seeding:
+        x0 = lattice(2, n, device)
+    else:
+        x0 = random_points(2, n, seed, device, offset)
+    N = x0.shape[1]
+    J = torch.eye(2, dtype=torch.float64, device=device).reshape(4, 1).repeat(1, N).contiguous()
+    z = torch.zeros((2, N), dtype=torch.float64, device=device)
+    return Droplets(x0.contiguous(), z.clone(), J, torch.zeros((4, N), dtype=torch.float64, device=device),
+                    torch.full((N,), c["r_d"], dtype=torch.float64, device=device), N0_DEFAULT, 1.0 / N)
