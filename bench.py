@@ -78,16 +78,18 @@ def gather_traffic(workload: str):
     source changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"gather_{workload}_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_2512_20829_amd", "csrc", "gather.hip")
     if not os.path.exists(path):
         return None
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("gather.hip", "internal.hpp"):     # the kernel and its compile-time constants
+        h.update(open(os.path.join(ROOT, "paper_2512_20829_amd", "csrc", name), "rb").read())
+    digest = h.hexdigest()[:16]
     vals = {}
     for line in open(path):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].rsplit(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("gather.hip sha256[:16]") != digest:
+    if vals.get("gather.hip + internal.hpp sha256[:16]") != digest:
         return None
     try:
         return float(vals["bytes per launch (calibrated)"])

@@ -9,7 +9,7 @@
 namespace flp {
 
 constexpr int kWave = 64;
-constexpr int kClasses = 8;          // neighbourhood classes (reach 0..6 tiles, 7 = whole axis)
+constexpr int kClasses = 16;         // neighbourhood classes (reach 0..14 tiles, 15 = whole axes)
 constexpr int kXcds = 8;             // XCDs per MI355X
 constexpr int kRecW = 8;             // reals per weight record: w0, wq[0..C-1], padding
 constexpr double kSupportMargin = 1e-5;  // relative widening of conservative support tests
