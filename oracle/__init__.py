@@ -75,6 +75,9 @@ def _declare(L):
     L.orc_nw_cells.restype = None
     L.orc_nw_cells.argtypes = [C.POINTER(OrcMesh), C.c_int64, _dp, _dp, _dp, _ip, C.c_double,
                                C.c_int, C.c_double, _dp, C.c_int64, _lp, _dp, _dp, _lp]
+    L.orc_nw_points.restype = None
+    L.orc_nw_points.argtypes = [C.c_int, C.c_int64, _dp, _ip, _dp, C.c_int64, _dp, _dp, _dp, _ip, C.c_double,
+                                C.c_int, C.c_double, _dp, C.c_int64, _lp, _dp, _dp, _lp]
     L.orc_nw_box.restype = C.c_int
     L.orc_nw_box.argtypes = [C.POINTER(OrcMesh), C.c_int64, _dp, _dp, _dp, _ip, C.c_double, C.c_int,
                              C.c_double, _dp, _lp, _lp, _dp, _dp, _lp]
@@ -232,6 +235,31 @@ def nw_cells(mesh, x, terms: Terms, cells: Optional[np.ndarray] = None, cutoff: 
     return Projection(S, den, pairs)
 
 
+def nw_points(cells, x, terms: Terms, sel: Optional[np.ndarray] = None, cutoff: float = 4.0,
+              f32_decision: bool = False, scale: float = 1.0,
+              cell_scale: Optional[np.ndarray] = None) -> Projection:
+    """Nadaraya-Watson source terms at the centroids of a general mesh
+    (``workloads.Cells``-like: dim, centroids (dim, M), lo, hi, periodic),
+    at the listed cells (all if None), by brute force over trajectories."""
+    dim = cells.dim
+    xc = _f64(cells.centroids)
+    M = xc.shape[1]
+    per = np.ascontiguousarray([int(bool(cells.periodic[a])) if a < dim else 0 for a in range(3)], dtype=np.int32)
+    L = np.ascontiguousarray([float(cells.hi[a]) - float(cells.lo[a]) if a < dim else 1.0 for a in range(3)])
+    sel = np.arange(M, dtype=np.int64) if sel is None else np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
+    x = _f64(x)
+    N = x.shape[1]
+    S = np.zeros((1 + dim, sel.size))
+    den = np.zeros(sel.size)
+    pairs = np.zeros(sel.size, dtype=np.int64)
+    cs = _f64(cell_scale) if cell_scale is not None else None
+    lib().orc_nw_points(dim, M, _d(xc), per.ctypes.data_as(_ip), _d(L), N, _d(x), _d(terms.h),
+                        _d(np.ascontiguousarray(terms.q)), terms.valid.ctypes.data_as(_ip), cutoff,
+                        int(bool(f32_decision)), scale, _d(cs) if cs is not None else None, sel.size,
+                        sel.ctypes.data_as(_lp), _d(S), _d(den), pairs.ctypes.data_as(_lp))
+    return Projection(S, den, pairs)
+
+
 @dataclass
 class BoxProjection:
     S: np.ndarray        # (C, B) in box order
@@ -362,6 +390,25 @@ def app_a_scaling(N_ref, tau_ref, N_fla, tau_fla, V_cell, A_inj, v_inj):
     out = np.zeros(3)
     lib().orc_app_a_scaling(N_ref, tau_ref, N_fla, tau_fla, V_cell, A_inj, v_inj, _d(out))
     return float(out[0]), float(out[1]), float(out[2])
+
+
+def nhat_cells(volume, N_ref, tau_ref, A_inj, v_inj, N_fla=1.0, tau_fla=1.0) -> np.ndarray:
+    """Per-cell factor n_hat = M_scal V_scal of App. A (eqs. mass-load-scaling,
+    vscal-def, vfla, vinj, dinj), formed from the two factors separately; the
+    FLA seeding parameters N_fla and tau_fla cancel in the product."""
+    vol = _f64(volume)
+    out = np.empty_like(vol)
+    for c in range(vol.size):
+        out[c] = app_a_scaling(N_ref, tau_ref, N_fla, tau_fla, float(vol[c]), A_inj, v_inj)[2]
+    return out
+
+
+def project_points(cells, traj, rho_d, mu, delta, h0, cutoff=4.0, f32_decision=False, scale=1.0,
+                   cell_scale=None, sel=None, h_factor=None):
+    """Whole plain path on a general mesh: terms, then the estimator at the
+    listed centroids (all by default)."""
+    t = trajectory_terms(traj, rho_d, mu, delta, h0, h_factor)
+    return nw_points(cells, traj.x, t, sel, cutoff, f32_decision, scale, cell_scale), t
 
 
 def project_box(mesh, traj, rho_d, mu, delta, h0, cutoff=4.0, f32_decision=False, scale=1.0,

@@ -262,6 +262,64 @@ void orc_nw_cells(const orc_mesh* m, int64_t N, const double* x, const double* h
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Nadaraya-Watson projection on a general mesh: the cells are given by     */
+/* their centroids (dim x M planes, xc[a*M + c]) instead of a lattice, as   */
+/* the kernel estimator needs nothing of a cell but the point where it is   */
+/* evaluated (the interpolation is meshfree; the mesh enters only through  */
+/* the per-cell factor n_hat of App. A, eq. mv-scal, passed in cell_scale). */
+/* Offsets on periodic axes take the minimum image with period L[a]; the     */
+/* estimator, truncation and epilogue are those of orc_nw_cells, so         */
+/* centroids placed at a lattice's cell centres reproduce it bit for bit.   */
+/* Outputs for the listed cells as in orc_nw_cells.                          */
+/* ------------------------------------------------------------------------ */
+static double point_offset(int periodic, double L, double xc, double xp)
+{
+    double d = xc - xp;
+    if (periodic) {
+        double k = rint(d / L);
+        double s = L * k;
+        d = d - s;
+    }
+    return d;
+}
+
+void orc_nw_points(int dim, int64_t M, const double* xc, const int* periodic, const double* L, int64_t N,
+                   const double* x, const double* h, const double* q, const int* valid, double cutoff,
+                   int f32_decision, double scale, const double* cell_scale, int64_t ncells,
+                   const int64_t* cells, double* S, double* den_out, int64_t* pairs_out)
+{
+    int C = 1 + dim;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t j = 0; j < ncells; ++j) {
+        int64_t c = cells[j];
+        double num[4] = {0, 0, 0, 0};
+        double den = 0.0;
+        int64_t np = 0;
+        for (int64_t i = 0; i < N; ++i) {
+            if (!valid[i]) continue;
+            double s[3] = {0, 0, 0};
+            double r2 = 0.0;
+            double inv_h = 1.0 / h[i];
+            for (int a = 0; a < dim; ++a) {
+                double d = point_offset(periodic[a], L[a], xc[a * M + c], x[a * N + i]);
+                double u = d * inv_h;
+                s[a] = u * u;
+                r2 += d * d;
+            }
+            if (!pair_included(dim, s, cutoff, f32_decision)) continue;
+            double K = gauss_kernel(r2, h[i]);
+            den += K;
+            for (int k = 0; k < C; ++k) num[k] += K * q[k * N + i];
+            ++np;
+        }
+        double cs = cell_scale ? cell_scale[c] : 1.0;
+        for (int k = 0; k < C; ++k) S[k * ncells + j] = (den > 0.0) ? -scale * cs * (num[k] / den) : 0.0;
+        if (den_out) den_out[j] = den;
+        if (pairs_out) pairs_out[j] = np;
+    }
+}
+
 /* Home cell of a point: the cell containing it; periodic axes wrap, other  */
 /* axes clamp to the nearest cell.                                           */
 static int64_t home_cell(const orc_mesh* m, const double* x, int64_t N, int64_t i)

@@ -117,6 +117,96 @@ def unit_mesh(dim: int, n: int, periodic: bool) -> Mesh:
     return Mesh(dim, (n,) * dim, (0.0,) * dim, (1.0,) * dim, (periodic,) * dim)
 
 
+@dataclass
+class Cells:
+    """A general mesh as the projection sees it: cell centroids (dim, M),
+    binary64, in the mesh's own cell order, and cell volumes (M,).  Every
+    centroid lies in the box [lo, hi]; axes flagged periodic repeat with
+    period hi - lo."""
+    dim: int
+    centroids: torch.Tensor
+    volume: torch.Tensor
+    lo: Tuple[float, ...]
+    hi: Tuple[float, ...]
+    periodic: Tuple[bool, ...]
+
+    @property
+    def count(self) -> int:
+        return int(self.centroids.shape[1])
+
+    @property
+    def L(self) -> Tuple[float, ...]:
+        return tuple(self.hi[a] - self.lo[a] for a in range(self.dim))
+
+    def to(self, device) -> "Cells":
+        return Cells(self.dim, self.centroids.to(device), self.volume.to(device), self.lo, self.hi, self.periodic)
+
+
+def _tensor_cells(axes_c: Sequence[torch.Tensor], axes_w: Sequence[torch.Tensor], lo, hi, periodic) -> Cells:
+    """Cells of the tensor product of per-axis centres and widths, linear
+    order with axis 0 fastest (as the Cartesian meshes)."""
+    dim = len(axes_c)
+    gc = torch.meshgrid(*axes_c, indexing="ij")
+    gw = torch.meshgrid(*axes_w, indexing="ij")
+    flat = lambda g: g.permute(*reversed(range(dim))).reshape(-1)
+    cen = torch.stack([flat(gc[a]) for a in range(dim)]).contiguous()
+    vol = flat(gw[0]).clone()
+    for a in range(1, dim):
+        vol = vol * flat(gw[a])
+    return Cells(dim, cen, vol.contiguous(), tuple(lo), tuple(hi), tuple(bool(p) for p in periodic))
+
+
+def mesh_cells(mesh: Mesh) -> Cells:
+    """The cells of a uniform Cartesian mesh as a general mesh: centres
+    lo + (i + 1/2) w with w = (hi - lo)/n, formed in that order."""
+    cs, ws = [], []
+    for a in range(mesh.dim):
+        w = (mesh.hi[a] - mesh.lo[a]) / mesh.n[a]
+        t = (torch.arange(mesh.n[a], dtype=torch.float64) + 0.5) * w
+        cs.append(mesh.lo[a] + t)
+        ws.append(torch.full((mesh.n[a],), w, dtype=torch.float64))
+    return _tensor_cells(cs, ws, mesh.lo, mesh.hi, mesh.periodic)
+
+
+def stretched_edges(n: int, lo: float, hi: float, beta: float) -> torch.Tensor:
+    """n + 1 cell edges on [lo, hi] clustered toward both ends (a tanh
+    stretching of strength beta > 0, as for a wall-resolved channel)."""
+    s = torch.linspace(-1.0, 1.0, n + 1, dtype=torch.float64)
+    e = torch.tanh(beta * s) / math.tanh(beta)
+    e = lo + (hi - lo) * 0.5 * (e + 1.0)
+    e[0], e[-1] = lo, hi
+    return e
+
+
+def rectilinear_cells(edges: Sequence[torch.Tensor], periodic: Sequence[bool]) -> Cells:
+    """A rectilinear (tensor-product, non-uniform) mesh from its per-axis
+    cell edges: centroids at edge midpoints, volumes the width products."""
+    cs = [0.5 * (e[:-1] + e[1:]) for e in edges]
+    ws = [e[1:] - e[:-1] for e in edges]
+    lo = tuple(float(e[0]) for e in edges)
+    hi = tuple(float(e[-1]) for e in edges)
+    return _tensor_cells(cs, ws, lo, hi, periodic)
+
+
+def scattered_cells(dim: int, n: int, lo, hi, periodic, seed: int, jitter: float = 0.35) -> Cells:
+    """An unstructured stand-in: the centres of an n^dim lattice each moved
+    by up to `jitter` cells in every axis (kept inside the box), with
+    volumes varying by a factor up to 2 around the lattice volume, listed
+    in a seeded random order (an unstructured mesh has no lattice order)."""
+    M = n ** dim
+    base = mesh_cells(Mesh(dim, (n,) * dim, tuple(lo), tuple(hi), tuple(periodic)))
+    cen = base.centroids.clone()
+    for a in range(dim):
+        w = (hi[a] - lo[a]) / n
+        u = counter_uniform(seed, 60 + a, M, "cpu") * 2.0 - 1.0
+        c = cen[a] + jitter * w * u
+        cen[a] = c.clamp(min=lo[a], max=hi[a])
+    vol = base.volume * (0.5 + 1.5 * counter_uniform(seed, 63, M, "cpu"))
+    perm = torch.argsort(counter_uniform(seed, 64, M, "cpu"))
+    return Cells(dim, cen[:, perm].contiguous(), vol[perm].contiguous(), tuple(lo), tuple(hi),
+                 tuple(bool(p) for p in periodic))
+
+
 def lattice(dim: int, per_axis: int, device="cpu") -> torch.Tensor:
     """Cell-centred lattice (i + 1/2)/L on the unit cube, shape (dim, L^dim);
     axis 0 varies fastest."""
