@@ -527,6 +527,82 @@ fla_status fla_autotune_batch(fla_ctx* ctx, int nsnap, const fla_mesh* meshes, c
                               const fla_params* params, const fla_fields* outs, void* stream,
                               double* times_ms);
 
+/* ------------------------------------------------------------------------
+ * General meshes (App. A, "Cell volume scaling" and "Combining the mass and
+ * volume scaling factors"): the carrier solver's cells are given by their
+ * centroids and volumes, in the solver's own cell order, as on an
+ * unstructured finite-volume mesh.  The kernel estimator is evaluated at
+ * each centroid exactly as fla_project_sources evaluates it at a Cartesian
+ * cell centre; the mesh enters only through n_hat of eq. mv-scal, which is
+ * proportional to the cell volume.
+ * ------------------------------------------------------------------------ */
+
+/* Cells of a general mesh.  centroid[a] (device, binary64, count values per
+ * axis a < dim) must lie in the box [lo, hi] on every axis (the box also
+ * gives the period hi - lo of a periodic axis, on which offsets take the
+ * minimum image); volume (device, binary64, count values, >= 0) may be NULL
+ * when no n_hat is asked for.  The arrays are read by fla_cell_index_create
+ * only: the index keeps its own copies. */
+typedef struct {
+    int32_t dim;                /* 2 or 3 */
+    int32_t periodic[3];        /* nonzero = periodic axis */
+    double lo[3];
+    double hi[3];               /* hi[a] > lo[a] */
+    int64_t count;              /* cells, in [1, 2^31) */
+    const double* centroid[3];
+    const double* volume;       /* nullable */
+} fla_cells;
+
+typedef struct fla_cell_index fla_cell_index;
+
+/* Spatial index of a general mesh, built once per mesh on ctx's device:
+ * a rectilinear grid of buckets whose per-axis edges sit at quantiles of the
+ * centroid coordinates (at most 1024 buckets per axis), aiming at about
+ * cells_per_bucket cells per bucket (<= 0: the default, 112), and the cells
+ * sorted by bucket.  Synchronises the device.  *out (host pointer) is owned
+ * by the caller and released with fla_cell_index_destroy, which must come
+ * before the context is destroyed.  Errors: INVALID_ARG (bad dim, count or
+ * box, a NULL centroid array, a centroid outside the box or not finite, a
+ * negative or non-finite volume), OUT_OF_MEMORY, DEVICE. */
+fla_status fla_cell_index_create(fla_ctx* ctx, const fla_cells* cells, int32_t cells_per_bucket,
+                                 fla_cell_index** out);
+fla_status fla_cell_index_destroy(fla_cell_index* index);
+
+/* Shape of an index: buckets per axis (nb[2] = 1 in 2-D) and the number of
+ * gather work items (runs of at most 128 cells of one bucket).  Host call.
+ * Errors: INVALID_ARG for NULL arguments. */
+fla_status fla_cell_index_shape(const fla_cell_index* index, int32_t nb[3], int64_t* work_items);
+
+/* Injection parameters of the reference (PSI-CELL) run for n_hat (eq.
+ * mv-scal): N^ref droplets injected every tau_inj^ref through a face of
+ * area A_inj at mean speed v_inj.  For a mass-flow specification (eq.
+ * mv-scal-massflow) set n_ref / tau_ref = mdot_ref / m. */
+typedef struct {
+    double n_ref;
+    double tau_ref;
+    double area;
+    double v_inj;
+} fla_injection;
+
+/* FLA source projection at the centroids of an indexed general mesh (the
+ * estimator of fla_project_sources, FLA_NW mode):
+ *   S_k(c) = -scale * n_hat(c) * num_k(c) / den(c),  0 where den(c) = 0,
+ *   n_hat(c) = V_c * n_ref / (A_inj v_inj tau_ref)   if inj is not NULL,
+ *   n_hat(c) = 1                                      if inj is NULL,
+ * with the pair offsets, the inclusion test (sum_a (d_a/h)^2 <= cutoff^2,
+ * binary32 terms and sum for FLA_F32) and the precisions of
+ * fla_project_sources.  out planes hold index's cell count values in the
+ * mesh's own cell order; den and pairs are optional as there.  Statistics:
+ * trajectories, skipped, no_support (no centroid of a closed box within
+ * reach), pairs (if counted), max_class (neighbourhood class in buckets).
+ * Uses the context's workspace; asynchronous on stream.  Errors:
+ * INVALID_ARG (as fla_project_sources; a mode other than FLA_NW; an index
+ * of another device; inj with a non-positive or non-finite entry, or with
+ * an index built without volumes), OUT_OF_MEMORY, DEVICE. */
+fla_status fla_project_cells(fla_ctx* ctx, const fla_cell_index* index, const fla_trajectories* traj,
+                             const fla_params* params, const fla_injection* inj, const fla_fields* out,
+                             void* stream);
+
 /* Message of the last error on ctx (host string owned by ctx, valid until
  * the next call on ctx); "" if the last call succeeded.  NULL ctx returns
  * the message of the last failed fla_ctx_create. */

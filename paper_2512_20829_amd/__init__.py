@@ -85,7 +85,25 @@ class fla_profile(C.Structure):
     _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
 
 
+class fla_cells(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("periodic", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("count", C.c_int64), ("centroid", C.c_void_p * 3), ("volume", C.c_void_p)]
+
+
+class fla_injection(C.Structure):
+    _fields_ = [("n_ref", C.c_double), ("tau_ref", C.c_double), ("area", C.c_double), ("v_inj", C.c_double)]
+
+
 _vp = C.c_void_p
+_lib.fla_cell_index_create.restype = C.c_int
+_lib.fla_cell_index_create.argtypes = [_vp, C.POINTER(fla_cells), C.c_int32, C.POINTER(_vp)]
+_lib.fla_cell_index_destroy.restype = C.c_int
+_lib.fla_cell_index_destroy.argtypes = [_vp]
+_lib.fla_cell_index_shape.restype = C.c_int
+_lib.fla_cell_index_shape.argtypes = [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+_lib.fla_project_cells.restype = C.c_int
+_lib.fla_project_cells.argtypes = [_vp, _vp, C.POINTER(fla_trajectories), C.POINTER(fla_params),
+                                   C.POINTER(fla_injection), C.POINTER(fla_fields), _vp]
 _lib.fla_ctx_create.restype = C.c_int
 _lib.fla_ctx_create.argtypes = [C.POINTER(_vp), C.c_int]
 _lib.fla_ctx_destroy.restype = C.c_int
@@ -255,6 +273,76 @@ def make_trajectories(x, J, v, ug, r, n0=1.0, seed_volume: float = 0.0) -> tuple
     return tr, keep
 
 
+def make_cells(dim: int, centroids, volume, lo: Sequence[float], hi: Sequence[float],
+               periodic: Sequence[bool]) -> tuple:
+    """fla_cells from device tensors: centroids (dim, M) float64, volume (M,)
+    float64 or None.  Returns (struct, keepalive)."""
+    import torch
+    if centroids.dtype != torch.float64 or (volume is not None and volume.dtype != torch.float64):
+        raise ValueError("centroids and volume must be float64")
+    c = fla_cells()
+    c.dim = dim
+    c.count = int(centroids.shape[1])
+    keep = [centroids[a].contiguous() for a in range(dim)]
+    for a in range(3):
+        c.periodic[a] = int(bool(periodic[a])) if a < dim else 0
+        c.lo[a] = float(lo[a]) if a < dim else 0.0
+        c.hi[a] = float(hi[a]) if a < dim else 1.0
+        c.centroid[a] = keep[a].data_ptr() if a < dim else None
+    if volume is not None:
+        vc = volume.contiguous()
+        keep.append(vc)
+        c.volume = vc.data_ptr()
+    return c, keep
+
+
+def cells_of(obj, device) -> tuple:
+    """fla_cells from an object with dim, centroids, volume, lo, hi, periodic
+    (tensors moved to `device`)."""
+    vol = obj.volume.to(device) if obj.volume is not None else None
+    return make_cells(obj.dim, obj.centroids.to(device), vol, obj.lo, obj.hi, obj.periodic)
+
+
+def make_injection(n_ref: float, tau_ref: float, area: float, v_inj: float) -> fla_injection:
+    j = fla_injection()
+    j.n_ref, j.tau_ref, j.area, j.v_inj = float(n_ref), float(tau_ref), float(area), float(v_inj)
+    return j
+
+
+class CellIndex:
+    """Owns one fla_cell_index (the spatial index of a general mesh)."""
+
+    def __init__(self, ctx: "Context", cells: fla_cells, cells_per_bucket: int = 0):
+        h = _vp()
+        ctx._check(_lib.fla_cell_index_create(ctx.handle, C.byref(cells), int(cells_per_bucket), C.byref(h)))
+        self._h = h
+        self.count = int(cells.count)
+        self.dim = int(cells.dim)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def shape(self) -> tuple:
+        nb = (C.c_int32 * 3)()
+        nw = C.c_int64()
+        st = _lib.fla_cell_index_shape(self._h, nb, C.byref(nw))
+        if st != FLA_OK:
+            raise FlaError(st, "fla_cell_index_shape")
+        return tuple(int(v) for v in nb), int(nw.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fla_cell_index_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def make_flow(kind: int = FLA_FLOW_NONE, U: float = 0.0, k: float = 1.0, abc=(1.0, 1.0, 1.0),
               phase=(0.0, 0.0, 0.0), u0=(0.0, 0.0, 0.0), G=None) -> fla_flow:
     """Gas field u = u0 + G x + (Taylor-Green or ABC part); G: nested lists or None."""
@@ -380,6 +468,18 @@ class Context:
         st = _lib.fla_project_sources_noalloc(self._h, C.byref(mesh), C.byref(traj), C.byref(params.to_c()),
                                               C.byref(make_fields(S_mass, S_mom, den, pairs)),
                                               _stream_handle(stream))
+        self._check(st)
+
+    def cell_index(self, cells: fla_cells, cells_per_bucket: int = 0) -> CellIndex:
+        """fla_cell_index_create: the spatial index of a general mesh."""
+        return CellIndex(self, cells, cells_per_bucket)
+
+    def project_cells(self, index: CellIndex, traj: fla_trajectories, params: Params, S_mass, S_mom, den=None,
+                      injection: Optional[fla_injection] = None, stream=None, pairs=None):
+        """fla_project_cells: the estimator at the centroids of an indexed general mesh."""
+        st = _lib.fla_project_cells(self._h, index.handle, C.byref(traj), C.byref(params.to_c()),
+                                    C.byref(injection) if injection is not None else None,
+                                    C.byref(make_fields(S_mass, S_mom, den, pairs)), _stream_handle(stream))
         self._check(st)
 
     def psicell_accumulate(self, mesh: fla_mesh, particles: fla_trajectories, weight: float,

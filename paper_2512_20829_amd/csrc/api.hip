@@ -1663,3 +1663,374 @@ FLA_EXPORT const char* fla_last_error(const fla_ctx* ctx)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// General meshes: the cell index and the projection at centroids.
+// ---------------------------------------------------------------------------
+struct fla_cell_index {
+    int device = 0;
+    int dim = 0;
+    int64_t M = 0;
+    CellGridDev g{};            // edges point into `edges`
+    double* edges = nullptr;    // dim * (kCellsMaxBuckets + 1) values
+    double* xs[3] = {nullptr, nullptr, nullptr};
+    double* vs = nullptr;       // volumes in bucket order, or NULL
+    uint32_t* perm = nullptr;
+    int4* work = nullptr;
+    int nwork = 0;
+};
+
+namespace {
+
+constexpr int kDefaultCellsPerBucket = 112;
+
+void free_index(fla_cell_index* ix)
+{
+    if (!ix) return;
+    (void)hipSetDevice(ix->device);
+    if (ix->edges) (void)hipFree(ix->edges);
+    for (int a = 0; a < 3; ++a)
+        if (ix->xs[a]) (void)hipFree(ix->xs[a]);
+    if (ix->vs) (void)hipFree(ix->vs);
+    if (ix->perm) (void)hipFree(ix->perm);
+    if (ix->work) (void)hipFree(ix->work);
+    delete ix;
+}
+
+// Interior bucket edges of one axis at the quantiles i M / nb of the
+// centroid histogram (right boundaries of the bins where the cumulative
+// count first reaches each quantile), strictly increasing and strictly
+// inside (lo, hi).  Returns lo, the interior edges, hi.
+std::vector<double> quantile_edges(const uint32_t* hist, int64_t M, int nb, double lo, double hi)
+{
+    std::vector<double> e{lo};
+    const double w = (hi - lo) / (double)kCellsHistBins;
+    int64_t cum = 0;
+    int bin = 0;
+    for (int i = 1; i < nb; ++i) {
+        const double target = (double)i * (double)M / (double)nb;
+        while (bin < kCellsHistBins && (double)(cum + hist[bin]) < target) cum += hist[bin++];
+        if (bin >= kCellsHistBins - 1) break;
+        const double edge = lo + (double)(bin + 1) * w;
+        if (edge > e.back() && edge < hi) e.push_back(edge);
+    }
+    e.push_back(hi);
+    return e;
+}
+
+fla_status cell_index_build(fla_ctx* ctx, const fla_cells* c, int32_t per_bucket, fla_cell_index* ix)
+{
+    const int D = c->dim;
+    const int64_t M = c->count;
+    const double* xc[3] = {c->centroid[0], c->centroid[1], D == 3 ? c->centroid[2] : nullptr};
+    // 1. histogram of the coordinates and validation
+    uint32_t *hist, *bad;
+    {
+        Carver probe(nullptr);
+        hist = probe.take<uint32_t>((size_t)3 * kCellsHistBins);
+        bad = probe.take<uint32_t>(1);
+        fla_status st = ensure_ws(ctx, probe.off + 256);
+        if (st != FLA_OK) return st;
+        Carver cv(ctx->ws);
+        hist = cv.take<uint32_t>((size_t)3 * kCellsHistBins);
+        bad = cv.take<uint32_t>(1);
+    }
+    hipStream_t s = nullptr;
+    HIP_OK(launch_fill_u32(hist, (int64_t)3 * kCellsHistBins, 0u, s));
+    HIP_OK(launch_fill_u32(bad, 1, 0u, s));
+    HIP_OK(launch_cells_hist(D, M, xc, c->lo, c->hi, hist, bad, c->volume, s));
+    std::vector<uint32_t> hh((size_t)3 * kCellsHistBins);
+    uint32_t nbad = 0;
+    HIP_OK(hipMemcpyAsync(hh.data(), hist, hh.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(&nbad, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    CHECK_ARG(nbad == 0, std::to_string(nbad) +
+                             " cells have a centroid outside the box or not finite, or a negative or "
+                             "non-finite volume");
+    // 2. buckets per axis: about M / per_bucket in all, shared out in
+    // proportion to the box edges, then edges at the coordinate quantiles
+    double gm = 1.0;
+    for (int a = 0; a < D; ++a) gm *= c->hi[a] - c->lo[a];
+    gm = std::pow(gm, 1.0 / D);
+    const double total = std::max(1.0, (double)M / (double)per_bucket);
+    std::vector<double> edges[3];
+    int64_t nbk = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a < D) {
+            double want = std::pow(total, 1.0 / D) * (c->hi[a] - c->lo[a]) / gm;
+            int nb = (int)std::lround(std::min(std::max(want, 1.0), (double)kCellsMaxBuckets));
+            edges[a] = quantile_edges(hh.data() + (size_t)a * kCellsHistBins, M, nb, c->lo[a], c->hi[a]);
+        } else {
+            edges[a] = {0.0, 1.0};
+        }
+        nbk *= (int64_t)edges[a].size() - 1;
+    }
+    CHECK_ARG(nbk * kClasses + 1 < (int64_t(1) << 31), "too many buckets");
+    CellGridDev g{};
+    g.dim = D;
+    g.nbuckets = (int)nbk;
+    HIP_OK(hipMalloc((void**)&ix->edges, sizeof(double) * 3 * (kCellsMaxBuckets + 1)));
+    for (int a = 0; a < 3; ++a) {
+        g.nb[a] = (int)edges[a].size() - 1;
+        g.periodic[a] = a < D ? (c->periodic[a] != 0) : 0;
+        g.lo[a] = a < D ? c->lo[a] : 0.0;
+        g.hi[a] = a < D ? c->hi[a] : 1.0;
+        g.L[a] = g.hi[a] - g.lo[a];
+        g.edges[a] = ix->edges + (size_t)a * (kCellsMaxBuckets + 1);
+        HIP_OK(hipMemcpy((void*)g.edges[a], edges[a].data(), sizeof(double) * edges[a].size(),
+                         hipMemcpyHostToDevice));
+    }
+    // 3. cells sorted by bucket
+    uint32_t *keys, *vals, *keys2, *vals2, *rh, *scan, *cstart;
+    const int64_t hist_w = radix_hist_words(M);
+    const int64_t scan_w = scan_tmp_words(std::max(hist_w, nbk + 1));
+    auto layout = [&](Carver& cv) {
+        keys = cv.take<uint32_t>(M);
+        vals = cv.take<uint32_t>(M);
+        keys2 = cv.take<uint32_t>(M);
+        vals2 = cv.take<uint32_t>(M);
+        rh = cv.take<uint32_t>(hist_w > 0 ? hist_w : 1);
+        scan = cv.take<uint32_t>(scan_w);
+        cstart = cv.take<uint32_t>((size_t)nbk + 1);
+    };
+    {
+        Carver probe(nullptr);
+        layout(probe);
+        fla_status st = ensure_ws(ctx, probe.off + 256);
+        if (st != FLA_OK) return st;
+    }
+    Carver cv(ctx->ws);
+    layout(cv);
+    HIP_OK(launch_cells_key(g, M, xc, keys, vals, s));
+    bool in_alt = false;
+    HIP_OK(radix_sort_pairs(keys, vals, keys2, vals2, M, bits_for((uint64_t)nbk), rh, hist_w, scan, scan_w, s,
+                            &in_alt));
+    const uint32_t* skeys = in_alt ? keys2 : keys;
+    const uint32_t* svals = in_alt ? vals2 : vals;
+    HIP_OK(launch_bucket_bounds(skeys, M, (uint32_t)nbk, cstart, s));
+    for (int a = 0; a < D; ++a) HIP_OK(hipMalloc((void**)&ix->xs[a], sizeof(double) * M));
+    if (c->volume) HIP_OK(hipMalloc((void**)&ix->vs, sizeof(double) * M));
+    HIP_OK(hipMalloc((void**)&ix->perm, sizeof(uint32_t) * M));
+    double* xsd[3] = {ix->xs[0], ix->xs[1], ix->xs[2]};
+    HIP_OK(launch_cells_sorted(D, M, svals, xc, c->volume, xsd, ix->vs, ix->perm, s));
+    // 4. work items: runs of at most kCellsPerItem cells of one bucket, a
+    // bucket's cells shared evenly between its items
+    std::vector<uint32_t> cs((size_t)nbk + 1);
+    HIP_OK(hipMemcpyAsync(cs.data(), cstart, sizeof(uint32_t) * cs.size(), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    std::vector<int4> work;
+    for (int64_t b = 0; b < nbk; ++b) {
+        const int n = (int)(cs[b + 1] - cs[b]);
+        if (n == 0) continue;
+        const int items = (n + kCellsPerItem - 1) / kCellsPerItem;
+        const int base = n / items, rem = n % items;
+        int first = (int)cs[b];
+        for (int k = 0; k < items; ++k) {
+            const int cnt = base + (k < rem ? 1 : 0);
+            work.push_back(make_int4((int)b, first, cnt, 0));
+            first += cnt;
+        }
+    }
+    CHECK_ARG(work.size() < (size_t)(1 << 29), "too many gather work items");
+    ix->nwork = (int)work.size();
+    HIP_OK(hipMalloc((void**)&ix->work, sizeof(int4) * std::max<size_t>(work.size(), 1)));
+    HIP_OK(hipMemcpy(ix->work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipDeviceSynchronize());
+    ix->g = g;
+    ix->dim = D;
+    ix->M = M;
+    return FLA_OK;
+}
+
+template <typename R, int D>
+fla_status project_cells_impl(fla_ctx* ctx, const fla_cell_index* ix, const TrajDev& t, const fla_params* p,
+                              double kinj, bool use_vol, const fla_fields* out, hipStream_t s)
+{
+    const int64_t N = t.count;
+    const uint32_t nb = (uint32_t)kClasses * (uint32_t)ix->g.nbuckets;
+    const int key_bits = bits_for(nb);
+    const int64_t hist_w = radix_hist_words(N);
+    const int64_t scan_w = scan_tmp_words(hist_w > (int64_t)nb + 1 ? hist_w : (int64_t)nb + 1);
+    uint32_t *keys, *vals, *keys2, *vals2, *bstart, *hist, *scan;
+    double4 *rpos_u, *rpos;
+    R *rw_u, *rw;
+    auto layout = [&](Carver& c) {
+        keys = c.take<uint32_t>(N);
+        vals = c.take<uint32_t>(N);
+        keys2 = c.take<uint32_t>(N);
+        vals2 = c.take<uint32_t>(N);
+        rpos_u = c.take<double4>(N);
+        rpos = c.take<double4>(N);
+        rw_u = c.take<R>((size_t)N * kRecW);
+        rw = c.take<R>((size_t)N * kRecW);
+        bstart = c.take<uint32_t>(nb + 1);
+        hist = c.take<uint32_t>(hist_w > 0 ? hist_w : 1);
+        scan = c.take<uint32_t>(scan_w);
+    };
+    {
+        Carver probe(nullptr);
+        layout(probe);
+        fla_status st = ensure_ws(ctx, probe.off + 256);
+        if (st != FLA_OK) return st;
+    }
+    Carver c(ctx->ws);
+    layout(c);
+    PhysDev ph{p->rho_d, p->mu, p->delta, p->h0, p->cutoff, p->scale};
+    HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
+    HIP_OK(launch_fill_u64(ctx->stats + ST_TRAJ, 1, (unsigned long long)N, s));
+    {
+        StageTimer tm(ctx, 0, s);
+        HIP_OK((launch_cells_prepass<R, D>(t, ix->g, ph, p->h_factor, keys, vals, rpos_u, rw_u, ctx->stats, s)));
+    }
+    {
+        StageTimer tm(ctx, 1, s);
+        bool in_alt = false;
+        HIP_OK(radix_sort_pairs(keys, vals, keys2, vals2, N, key_bits, hist, hist_w, scan, scan_w, s, &in_alt));
+        const uint32_t* skeys = in_alt ? keys2 : keys;
+        const uint32_t* svals = in_alt ? vals2 : vals;
+        HIP_OK(launch_bucket_bounds(skeys, N, nb, bstart, s));
+        HIP_OK(launch_max_class(bstart, ix->g.nbuckets, ctx->stats, s));
+        HIP_OK(launch_permute<R>(svals, N, rpos_u, rw_u, rpos, rw, 1, s));
+    }
+    CellsGatherArgs a{};
+    a.g = ix->g;
+    for (int ax = 0; ax < 3; ++ax) a.xc[ax] = ix->xs[ax];
+    a.vol = ix->vs;
+    a.perm = ix->perm;
+    a.work = ix->work;
+    a.nwork = ix->nwork;
+    a.rpos = rpos;
+    a.rw = rw;
+    a.bstart = bstart;
+    a.cutoff = p->cutoff;
+    const double cf = p->cutoff * (1.0 + kSupportMargin);
+    a.filt2 = cf * cf;
+    a.scale = p->scale * kinj;
+    a.use_vol = use_vol ? 1 : 0;
+    a.out[0] = out->S_mass;
+    for (int ax = 0; ax < D; ++ax) a.out[1 + ax] = out->S_mom[ax];
+    a.den = out->den;
+    a.pairs = out->pairs;
+    a.stats = ctx->stats;
+    {
+        StageTimer tm(ctx, 3, s);
+        HIP_OK((launch_cells_gather<R, D>(a, p->count_pairs != 0 || out->pairs != nullptr, s)));
+    }
+    return FLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+FLA_EXPORT fla_status fla_cell_index_create(fla_ctx* ctx, const fla_cells* cells, int32_t cells_per_bucket,
+                                            fla_cell_index** out)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(out != nullptr, "out is NULL");
+    *out = nullptr;
+    CHECK_ARG(cells != nullptr, "cells is NULL");
+    CHECK_ARG(cells->dim == 2 || cells->dim == 3, "cells.dim must be 2 or 3");
+    CHECK_ARG(cells->count >= 1 && cells->count < (int64_t(1) << 31), "cells.count must be in [1, 2^31)");
+    for (int a = 0; a < cells->dim; ++a) {
+        CHECK_ARG(is_fin(cells->lo[a]) && is_fin(cells->hi[a]) && cells->hi[a] > cells->lo[a] &&
+                      is_fin(cells->hi[a] - cells->lo[a]),
+                  "cells box: lo and hi must be finite with hi > lo");
+        CHECK_ARG(cells->centroid[a] != nullptr, "cells.centroid[a] is NULL for an axis a < dim");
+    }
+    const int32_t per = cells_per_bucket <= 0 ? kDefaultCellsPerBucket : std::min(cells_per_bucket, 1 << 20);
+    fla_cell_index* ix = new (std::nothrow) fla_cell_index();
+    if (!ix) {
+        ctx->err = "host allocation failed";
+        return FLA_ERR_OUT_OF_MEMORY;
+    }
+    ix->device = ctx->device;
+    fla_status st;
+    try {
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e != hipSuccess) {
+            ctx->err = std::string("hipSetDevice: ") + hipGetErrorString(e);
+            st = FLA_ERR_DEVICE;
+        } else {
+            st = cell_index_build(ctx, cells, per, ix);
+        }
+    } catch (...) {
+        ctx->err = "internal error";
+        st = FLA_ERR_DEVICE;
+    }
+    if (st != FLA_OK) {
+        free_index(ix);
+        return st;
+    }
+    *out = ix;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_cell_index_destroy(fla_cell_index* index)
+{
+    if (!index) return FLA_OK;
+    (void)hipSetDevice(index->device);
+    (void)hipDeviceSynchronize();
+    free_index(index);
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_cell_index_shape(const fla_cell_index* index, int32_t nb[3], int64_t* work_items)
+{
+    if (!index || !nb || !work_items) return FLA_ERR_INVALID_ARG;
+    for (int a = 0; a < 3; ++a) nb[a] = index->g.nb[a];
+    *work_items = index->nwork;
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_project_cells(fla_ctx* ctx, const fla_cell_index* index, const fla_trajectories* traj,
+                                        const fla_params* params, const fla_injection* inj, const fla_fields* out,
+                                        void* stream)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    try {
+        CHECK_ARG(index != nullptr, "index is NULL");
+        CHECK_ARG(index->device == ctx->device, "the index was built on another device");
+        const int D = index->dim;
+        TrajDev t;
+        fla_status st = check_traj(ctx, traj, D, true, &t);
+        if (st != FLA_OK) return st;
+        st = check_params(ctx, params, true);
+        if (st != FLA_OK) return st;
+        CHECK_ARG(params->mode == FLA_NW, "fla_project_cells supports FLA_NW only");
+        st = check_fields(ctx, out, D);
+        if (st != FLA_OK) return st;
+        double kinj = 1.0;
+        if (inj) {
+            CHECK_ARG(is_fin(inj->n_ref) && inj->n_ref > 0.0 && is_fin(inj->tau_ref) && inj->tau_ref > 0.0 &&
+                          is_fin(inj->area) && inj->area > 0.0 && is_fin(inj->v_inj) && inj->v_inj > 0.0,
+                      "injection parameters must be positive and finite");
+            CHECK_ARG(index->vs != nullptr, "n_hat needs cell volumes: the index was built without them");
+            kinj = inj->n_ref / (inj->area * inj->v_inj * inj->tau_ref);
+            CHECK_ARG(is_fin(kinj) && is_fin(kinj * params->scale), "n_hat per unit volume is not finite");
+        }
+        HIP_OK(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        const bool f64 = traj->prec == FLA_F64;
+        if (t.count == 0) {
+            // no trajectory: every cell has den = 0 and S = 0
+            MeshDev m{};
+            m.dim = D;
+            m.M = index->M;
+            HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
+            return f64 ? zero_outputs<double>(ctx, m, out, s) : zero_outputs<float>(ctx, m, out, s);
+        }
+        if (D == 2)
+            return f64 ? project_cells_impl<double, 2>(ctx, index, t, params, kinj, inj != nullptr, out, s)
+                       : project_cells_impl<float, 2>(ctx, index, t, params, kinj, inj != nullptr, out, s);
+        return f64 ? project_cells_impl<double, 3>(ctx, index, t, params, kinj, inj != nullptr, out, s)
+                   : project_cells_impl<float, 3>(ctx, index, t, params, kinj, inj != nullptr, out, s);
+    } catch (...) {
+        ctx->err = "internal error";
+        return FLA_ERR_DEVICE;
+    }
+}
+
+}  // extern "C"

@@ -165,6 +165,60 @@ template <typename R> struct CicRec {
 template <typename R, int D>
 hipError_t launch_cic(const PsiArgs& a, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// General meshes: cells given by their centroids.  A rectilinear grid of
+// buckets (per-axis edges at quantiles of the centroid coordinates, so that
+// the buckets hold similar numbers of cells) replaces the Cartesian tiles:
+// cells are sorted by bucket, trajectories keyed by home bucket and
+// neighbourhood class exactly as on the Cartesian mesh, with distances in
+// buckets.
+constexpr int kCellsMaxBuckets = 1024;   // per axis
+constexpr int kCellsHistBins = 65536;    // per axis, for the quantile edges
+constexpr int kCellsPerLane = 2;         // cells owned by each lane of the gather
+constexpr int kCellsPerItem = kWave * kCellsPerLane;
+
+struct CellGridDev {
+    int dim;
+    int nb[3];                // buckets per axis
+    int periodic[3];
+    int nbuckets;
+    double lo[3], hi[3], L[3];
+    const double* edges[3];   // nb[a] + 1 edges per axis: lo, interior edges, hi
+};
+
+struct CellsGatherArgs {
+    CellGridDev g;
+    const double* xc[3];      // centroids in bucket order
+    const double* vol;        // volumes in bucket order (nullable)
+    const uint32_t* perm;     // bucket order -> caller's cell index
+    const int4* work;         // {bucket, first cell (bucket order), cells, 0}
+    int nwork;
+    const double4* rpos;      // sorted trajectory records, as for the Cartesian gather
+    const void* rw;
+    const uint32_t* bstart;   // kClasses * nbuckets + 1 bucket starts
+    double cutoff;
+    double filt2;             // (c (1 + margin))^2 for the conservative record filter
+    double scale;             // multiplier of every cell: scale, or scale * (n_hat per unit volume)
+    int use_vol;              // multiply by the cell volume as well (n_hat of App. A)
+    void* out[4];
+    void* den;
+    uint32_t* pairs;
+    unsigned long long* stats;
+};
+
+hipError_t launch_cells_hist(int dim, int64_t M, const double* const* xc, const double* lo, const double* hi,
+                             uint32_t* hist, uint32_t* bad, const double* vol, hipStream_t s);
+hipError_t launch_cells_key(const CellGridDev& g, int64_t M, const double* const* xc, uint32_t* keys, uint32_t* vals,
+                            hipStream_t s);
+hipError_t launch_cells_sorted(int dim, int64_t M, const uint32_t* order, const double* const* xc, const double* vol,
+                               double* const* xs, double* vs, uint32_t* perm, hipStream_t s);
+template <typename R, int D>
+hipError_t launch_cells_prepass(const TrajDev& t, const CellGridDev& g, const PhysDev& ph, const float* hfac,
+                                uint32_t* keys, uint32_t* vals, double4* rpos, R* rw, unsigned long long* stats,
+                                hipStream_t s);
+template <typename R, int D>
+hipError_t launch_cells_gather(const CellsGatherArgs& a, bool count, hipStream_t s);
+
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);
 template <typename R>

@@ -6,38 +6,16 @@
 
 namespace flp {
 
-// Per-trajectory prepass of trajectory i of one snapshot, written at global
-// index gi: loads the inputs, forms the droplet source terms and emits the
-// records (prepass_emit).
+// Per-trajectory prepass of trajectory i of one snapshot on a Cartesian
+// mesh, written at global index gi (prepass_traj with the mesh's keyer).
 template <typename R, int D>
 __device__ inline void prepass_one(const TrajDev& t, const MeshDev& m, const PhysDev& ph, const float* hfac,
                                    int deposit, int64_t i, int64_t gi, uint32_t key_base, uint32_t sentinel,
                                    uint32_t* keys, uint32_t* vals, double4* rpos, R* rw, double* qd,
                                    unsigned long long& skipped, unsigned long long& nosup)
 {
-    const int64_t N = t.count;
-    double x[3] = {0, 0, 0}, J[9], v[3], ug[3];
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        x[a] = t.x[a][i];
-        v[a] = (double)((const R*)t.v[a])[i];
-        ug[a] = (double)((const R*)t.ug[a])[i];
-        ok = ok && isfinite(x[a]) && isfinite(v[a]) && isfinite(ug[a]);
-    }
-#pragma unroll
-    for (int e = 0; e < D * D; ++e) {
-        J[e] = t.J[(int64_t)e * N + i];
-        ok = ok && isfinite(J[e]);
-    }
-    double r = (double)((const R*)t.r)[i];
-    double n0 = t.n0 ? t.n0[i] : t.n0_scalar;
-    double fac = hfac ? (double)hfac[i] : 1.0;
-    ok = ok && isfinite(r);
-    double phi[4] = {0, 0, 0, 0};
-    if (ok) droplet_phi<D>(r, v, ug, ph, phi);
-    prepass_emit<R, D>(m, ph, fac, deposit, N, i, gi, key_base, sentinel, x, J, n0, phi, ok, t.seed_volume, keys,
-                       vals, rpos, rw, qd, skipped, nosup);
+    prepass_traj<R, D>(t, LatticeKey<D>{m}, ph, hfac, deposit, i, gi, key_base, sentinel, keys, vals, rpos, rw, qd,
+                       skipped, nosup);
 }
 
 // Trajectories per thread of the prepass kernels: each trajectory is one

@@ -18,50 +18,21 @@ __device__ inline void wave_count_sum(unsigned long long* stats, int slot, unsig
     if ((threadIdx.x % kWave) == 0 && n) atomicAdd(&stats[slot], n);
 }
 
-// Emits the prepass records of one trajectory of one snapshot (index i of
-// count N), written at global index gi, from its binary64 position x,
-// Jacobian J, initial number density n0 and source terms phi: the sort key
-// (key_base + neighbourhood class * ntiles + home tile, or `sentinel`), the
-// unsorted position record {x, y, z, 1/h} and weight record {1/h, q/h}, with
-// h = h0 |det J| fac and q = n0/|det J| phi (or, in deposition mode, the
-// binary64 amounts Q = q V_seed |det J| to qd).  ok: the inputs are valid.
-// Adds 1 to `skipped` / `nosup` when the trajectory is skipped or reaches no
-// cell centre.
-template <typename R, int D>
-__device__ inline void prepass_emit(const MeshDev& m, const PhysDev& ph, double fac, int deposit, int64_t N, int64_t i,
-                                    int64_t gi, uint32_t key_base, uint32_t sentinel, const double* x, const double* J,
-                                    double n0, const double* phi_in, bool ok, double seed_volume, uint32_t* keys,
-                                    uint32_t* vals, double4* rpos, R* rw, double* qd, unsigned long long& skipped,
-                                    unsigned long long& nosup)
-{
-    constexpr int TE = Geo<D>::TE;
-    constexpr int C = D + 1;
-    double det = det_rn<D>(J);
-    double adet = fabs(det);
-    ok = ok && isfinite(n0) && isfinite(det) && det != 0.0 && isfinite(fac) && fac > 0.0;
-    double h, n, phi[4] = {0, 0, 0, 0};
+// Sort key of a trajectory on a Cartesian mesh: its home tile (linear tile
+// index) and neighbourhood class (the largest distance in tiles, per axis,
+// from the home tile to a tile holding a cell centre within rc; circular on
+// periodic axes, where a support spanning the whole axis counts as the
+// axis's tile count).  Returns false when no cell centre of a closed box is
+// within reach.
+template <int D>
+struct LatticeKey {
+    const MeshDev& m;
+    __device__ uint32_t stride() const { return (uint32_t)m.ntiles; }
+    __device__ bool operator()(const double* x, double rc, int64_t& tl, int& reach) const
     {
-#pragma clang fp contract(off)
-        h = ph.h0 * adet;
-        h = h * fac;
-    }
-    n = n0 / adet;
-    if (ok)
-#pragma unroll
-        for (int k = 0; k < C; ++k) phi[k] = phi_in[k];
-    if (ok) {
-        ok = isfinite(h) && h > 0.0 && isfinite(n);
-#pragma unroll
-        for (int k = 0; k < C; ++k) ok = ok && isfinite(phi[k]);
-    }
-    uint32_t key = sentinel;
-    if (!ok) {
-        skipped += 1;
-    } else {
-        double inv_h = 1.0 / h;
-        double rc = ph.cutoff * h * (1.0 + kSupportMargin);
+        constexpr int TE = Geo<D>::TE;
         int64_t ht[3] = {0, 0, 0};
-        int reach = 0;
+        reach = 0;
         bool support = true;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -115,13 +86,62 @@ __device__ inline void prepass_emit(const MeshDev& m, const PhysDev& ph, double 
             if (ra > kClasses) ra = kClasses;
             if ((int)ra > reach) reach = (int)ra;
         }
+        tl = ht[0] + (int64_t)m.nt[0] * (ht[1] + (int64_t)m.nt[1] * ht[2]);
+        return support;
+    }
+};
+
+// Emits the prepass records of one trajectory of one snapshot (index i of
+// count N), written at global index gi, from its binary64 position x,
+// Jacobian J, initial number density n0 and source terms phi: the sort key
+// (key_base + neighbourhood class * key.stride() + home tile or bucket from
+// the keyer `key`, or `sentinel`), the
+// unsorted position record {x, y, z, 1/h} and weight record {1/h, q/h}, with
+// h = h0 |det J| fac and q = n0/|det J| phi (or, in deposition mode, the
+// binary64 amounts Q = q V_seed |det J| to qd).  ok: the inputs are valid.
+// Adds 1 to `skipped` / `nosup` when the trajectory is skipped or reaches no
+// cell centre.
+template <typename R, int D, typename K>
+__device__ inline void emit_records(const K& key, const PhysDev& ph, double fac, int deposit, int64_t N, int64_t i,
+                                    int64_t gi, uint32_t key_base, uint32_t sentinel, const double* x, const double* J,
+                                    double n0, const double* phi_in, bool ok, double seed_volume, uint32_t* keys,
+                                    uint32_t* vals, double4* rpos, R* rw, double* qd, unsigned long long& skipped,
+                                    unsigned long long& nosup)
+{
+    constexpr int C = D + 1;
+    double det = det_rn<D>(J);
+    double adet = fabs(det);
+    ok = ok && isfinite(n0) && isfinite(det) && det != 0.0 && isfinite(fac) && fac > 0.0;
+    double h, n, phi[4] = {0, 0, 0, 0};
+    {
+#pragma clang fp contract(off)
+        h = ph.h0 * adet;
+        h = h * fac;
+    }
+    n = n0 / adet;
+    if (ok)
+#pragma unroll
+        for (int k = 0; k < C; ++k) phi[k] = phi_in[k];
+    if (ok) {
+        ok = isfinite(h) && h > 0.0 && isfinite(n);
+#pragma unroll
+        for (int k = 0; k < C; ++k) ok = ok && isfinite(phi[k]);
+    }
+    uint32_t skey = sentinel;
+    if (!ok) {
+        skipped += 1;
+    } else {
+        double inv_h = 1.0 / h;
+        double rc = ph.cutoff * h * (1.0 + kSupportMargin);
+        int64_t tl = 0;
+        int reach = 0;
+        const bool support = key(x, rc, tl, reach);
         // In deposition mode a trajectory that reaches no cell centre still
         // deposits its whole amount into its home cell, so it is kept.
         if (!support) nosup += 1;
         if (support || deposit) {
             int cls = !support ? 0 : (reach < kClasses - 1 ? reach : kClasses - 1);
-            int64_t tl = ht[0] + (int64_t)m.nt[0] * (ht[1] + (int64_t)m.nt[1] * ht[2]);
-            key = key_base + (uint32_t)cls * (uint32_t)m.ntiles + (uint32_t)tl;
+            skey = key_base + (uint32_t)cls * key.stride() + (uint32_t)tl;
         }
         rpos[gi] = make_double4(x[0], x[1], x[2], inv_h);
         // the weight record is built in registers and stored whole (16-byte stores)
@@ -143,9 +163,54 @@ __device__ inline void prepass_emit(const MeshDev& m, const PhysDev& ph, double 
 #pragma unroll
         for (int k = 0; k < (int)(kRecW * sizeof(R) / sizeof(uint4)); ++k) wd[k] = ws[k];
     }
-    keys[gi] = key;
+    keys[gi] = skey;
     vals[gi] = (uint32_t)gi;
 }
 
+// Per-trajectory prepass of trajectory i of one snapshot, written at global
+// index gi: loads the inputs, forms the droplet source terms and emits the
+// records keyed by `key` (emit_records).
+template <typename R, int D, typename K>
+__device__ inline void prepass_traj(const TrajDev& t, const K& key, const PhysDev& ph, const float* hfac,
+                                    int deposit, int64_t i, int64_t gi, uint32_t key_base, uint32_t sentinel,
+                                    uint32_t* keys, uint32_t* vals, double4* rpos, R* rw, double* qd,
+                                    unsigned long long& skipped, unsigned long long& nosup)
+{
+    const int64_t N = t.count;
+    double x[3] = {0, 0, 0}, J[9], v[3], ug[3];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        x[a] = t.x[a][i];
+        v[a] = (double)((const R*)t.v[a])[i];
+        ug[a] = (double)((const R*)t.ug[a])[i];
+        ok = ok && isfinite(x[a]) && isfinite(v[a]) && isfinite(ug[a]);
+    }
+#pragma unroll
+    for (int e = 0; e < D * D; ++e) {
+        J[e] = t.J[(int64_t)e * N + i];
+        ok = ok && isfinite(J[e]);
+    }
+    double r = (double)((const R*)t.r)[i];
+    double n0 = t.n0 ? t.n0[i] : t.n0_scalar;
+    double fac = hfac ? (double)hfac[i] : 1.0;
+    ok = ok && isfinite(r);
+    double phi[4] = {0, 0, 0, 0};
+    if (ok) droplet_phi<D>(r, v, ug, ph, phi);
+    emit_records<R, D>(key, ph, fac, deposit, N, i, gi, key_base, sentinel, x, J, n0, phi, ok, t.seed_volume, keys,
+                       vals, rpos, rw, qd, skipped, nosup);
+}
+
+// The records of one trajectory keyed on a Cartesian mesh.
+template <typename R, int D>
+__device__ inline void prepass_emit(const MeshDev& m, const PhysDev& ph, double fac, int deposit, int64_t N, int64_t i,
+                                    int64_t gi, uint32_t key_base, uint32_t sentinel, const double* x, const double* J,
+                                    double n0, const double* phi_in, bool ok, double seed_volume, uint32_t* keys,
+                                    uint32_t* vals, double4* rpos, R* rw, double* qd, unsigned long long& skipped,
+                                    unsigned long long& nosup)
+{
+    emit_records<R, D>(LatticeKey<D>{m}, ph, fac, deposit, N, i, gi, key_base, sentinel, x, J, n0, phi_in, ok,
+                       seed_volume, keys, vals, rpos, rw, qd, skipped, nosup);
+}
 
 }  // namespace flp

@@ -65,7 +65,8 @@ def test_multi_vortex_map_caustics():
 
 def test_bench_reads_the_traffic_summary():
     """bench.py reports the gather's HBM traffic only from a summary whose
-    source hash matches gather.hip; the hash key contains a colon."""
+    source hash matches gather.hip and the compile-time constants in
+    internal.hpp; the hash key contains a colon."""
     import bench
     path = os.path.join(ROOT, "profiles", "gather_abc128_hbm_traffic.md")
     vals = {}
@@ -73,11 +74,13 @@ def test_bench_reads_the_traffic_summary():
         if ":" in line and line.startswith("- "):
             k, v = line[2:].rsplit(":", 1)
             vals[k.strip()] = v.strip()
-    assert "gather.hip sha256[:16]" in vals and "bytes per launch (calibrated)" in vals
-    src = os.path.join(ROOT, "paper_2512_20829_amd", "csrc", "gather.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    key = "gather.hip + internal.hpp sha256[:16]"
+    assert key in vals and "bytes per launch (calibrated)" in vals
+    h = hashlib.sha256()
+    for name in ("gather.hip", "internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2512_20829_amd", "csrc", name), "rb").read())
     got = bench.gather_traffic("abc128")
-    if vals["gather.hip sha256[:16]"] == digest:
+    if vals[key] == h.hexdigest()[:16]:
         assert got == float(vals["bytes per launch (calibrated)"])
     else:
         assert got is None
