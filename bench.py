@@ -707,6 +707,79 @@ def projection_section(ctx, args, dev, wl, prec, traffic_name):
             "roofline": gather_roofline(P, g_ms, wl.mesh.dim, prec, traffic_name)}
 
 
+def general_mesh_section(ctx, args, dev, cartesian_ms):
+    """fla_project_cells on the 2M-trajectory ABC workload over three
+    general meshes of 128^3 cells: the uniform mesh's centroids (same pairs
+    as the Cartesian path), a rectilinear mesh stretched toward every wall
+    and a scattered (jittered, shuffled) mesh; n_hat from the cell volumes
+    on the stretched mesh.  Times the index build once and the projection
+    per call (inputs resident on the GPU)."""
+    import time
+
+    import torch
+
+    import paper_2512_20829_amd as F
+    import workloads as W
+    wl = W.abc_lattice_3d(device=dev)
+    tr = wl.traj
+    st, keep = F.make_trajectories(tr.x.contiguous(), tr.J.contiguous(), tr.v.float().contiguous(),
+                                   tr.ug.float().contiguous(), tr.r.float().contiguous(), tr.n0, tr.seed_volume)
+    params = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
+    counted = F.Params(**{**params.__dict__, "count_pairs": True})
+    inj = F.make_injection(2.0e5, 1.0e-3, 2.5e-3, 4.0)
+    meshes = [("uniform_centroids", W.mesh_cells(wl.mesh), None),
+              ("stretched_rectilinear", W.rectilinear_cells([W.stretched_edges(128, 0.0, 1.0, 1.5)] * 3,
+                                                            (True,) * 3), inj),
+              ("scattered", W.scattered_cells(3, 128, (0.0,) * 3, (1.0,) * 3, (True,) * 3, seed=3), None)]
+    rows = {}
+    for name, cells, j in meshes:
+        cs, ck = F.cells_of(cells, dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ix = ctx.cell_index(cs)
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3
+        M = cells.count
+        Sm, Sv, _ = F.alloc_fields(M, 3, torch.float32, dev, den=False)
+        ctx.project_cells(ix, st, counted, Sm, Sv, injection=j)
+        torch.cuda.synchronize()
+        stats = ctx.stats()
+        for _ in range(args.warmup):
+            ctx.project_cells(ix, st, params, Sm, Sv, injection=j)
+        ctx.profile_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            ctx.project_cells(ix, st, params, Sm, Sv, injection=j)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        prof = ctx.profile_read()
+        ctx.profile_enable(False)
+        g_ms = prof["gather"][0] / max(prof["gather"][1], 1)
+        P = stats["pairs"]
+        fpp = FLOPS_PER_PAIR[3]
+        ach = P * fpp / (g_ms * 1e-3) / 1e12
+        nb, nwork = ix.shape()
+        rows[name] = {"cells": M, "buckets": list(nb), "work_items": nwork, "index_build_ms": round(build_ms, 2),
+                      "ms_per_step": round(ms, 3), "cells_per_s": M / (ms * 1e-3), "pairs": P,
+                      "pairs_per_s": P / (ms * 1e-3), "n_hat": j is not None,
+                      "stage_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1]},
+                      "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                                   "kernel": "k_cells_gather<float,3>", "launch_ms": round(g_ms, 4),
+                                   "flops_per_pair": fpp,
+                                   "frac_of_nonpacked_78.6": round(ach / FP32_NONPACKED_TFLOPS, 4)},
+                      "over_cartesian_time": round(ms / cartesian_ms, 2) if cartesian_ms else None}
+        log(f"general mesh {name}: {ms:.3f} ms/step, {P:.4g} pairs, index {build_ms:.1f} ms")
+        ix.close()
+        del Sm, Sv
+    del st, keep
+    torch.cuda.empty_cache()
+    return rows
+
+
 def psicell_section(ctx, args, dev, fla_ms):
     import torch
 
@@ -780,7 +853,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only-headline", action="store_true", help="time the headline workload only")
-    ap.add_argument("--only", choices=["headline", "abc128", "tg2d", "psicell", "table1"], default=None,
+    ap.add_argument("--only", choices=["headline", "abc128", "tg2d", "psicell", "table1", "cells"], default=None,
                     help="time one projection workload only (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psicell", action="store_true")
@@ -791,6 +864,7 @@ def main():
     ap.add_argument("--psicell-particles", type=int, default=200_000_000)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain section")
     ap.add_argument("--no-table1", action="store_true", help="skip the Table 1 sweep")
+    ap.add_argument("--no-cells", action="store_true", help="skip the general-mesh section")
     ap.add_argument("--train-snapshots", type=int, default=500)
     ap.add_argument("--train-trajectories", type=int, default=200_000)
     ap.add_argument("--train-particles", type=int, default=50_000_000)
@@ -839,14 +913,20 @@ def main():
             torch.cuda.synchronize()
         ctx.close()
         return
+    if args.only == "cells":
+        print(json.dumps({"general_mesh": general_mesh_section(ctx, args, dev, None)}), flush=True)
+        ctx.close()
+        return
     if args.only == "table1":
         print(json.dumps({"table1": table1_section(ctx, args, dev)}), flush=True)
         ctx.close()
         return
-    table1 = None
+    table1 = cells = None
     if args.only is None:
         if not args.no_table1:
             table1 = table1_section(ctx, args, dev)
+        if not args.no_cells:
+            cells = general_mesh_section(ctx, args, dev, abc["ms_per_step"])
         if not args.no_batch:
             batch = batch_section(ctx, args, dev)
         if not args.no_psicell:
@@ -905,6 +985,7 @@ def main():
         "learned_vs_plain": learned,
         "large": large,
         "table1": table1,
+        "general_mesh": cells,
     }
     log(f"main line: {name}")
     print(json.dumps(out), flush=True)

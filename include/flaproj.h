@@ -2,10 +2,12 @@
  * flaproj.h - C ABI of the MI355X (gfx950) FLA source-projection library.
  *
  * The library projects the mass and momentum exchange terms carried by
- * fully-Lagrangian-approach (FLA) droplet trajectories onto a uniform
- * Cartesian Eulerian mesh with the Nadaraya-Watson kernel estimator of
- * Stafford & Rybdylova (arXiv 2512.20829), and accumulates the PSI-CELL
- * box-counting source terms of a particle cloud as the comparison path.
+ * fully-Lagrangian-approach (FLA) droplet trajectories onto an Eulerian
+ * mesh (uniform Cartesian, or general: cells given by centroids and
+ * volumes) with the Nadaraya-Watson kernel estimator of Stafford &
+ * Rybdylova (arXiv 2512.20829), advances the droplets that carry them, and
+ * accumulates the PSI-CELL box-counting and cloud-in-cell source terms of a
+ * particle cloud as the comparison paths.
  *
  * Conventions shared by every entry point:
  *  - Pointers inside the argument structs are DEVICE pointers (HIP device
@@ -136,8 +138,9 @@ typedef struct {
  * kernel, with the minus sign of eq. coupling-terms-averaged); den
  * (nullable) receives the estimator denominator sum_i K(x_c, x_i)
  * (FLA_NW) or, for psicell_accumulate, the particle count as a real.
- * pairs (nullable, uint32 per cell; fla_project_sources and
- * fla_project_batch only, ignored elsewhere) receives the number of
+ * pairs (nullable, uint32 per cell; fla_project_sources, fla_project_batch,
+ * fla_advance_project and fla_project_cells only, ignored elsewhere)
+ * receives the number of
  * trajectories whose kernel reaches the cell centre (the included pairs
  * of the truncation test; in FLA_DEPOSIT a trajectory whose support holds
  * no centre counts once at its home cell).  Asking for it costs extra
@@ -163,7 +166,18 @@ typedef struct {
 } fla_stats;
 
 /* Create a context on HIP device `device` (host pointer out).  Errors:
- * INVALID_ARG for a bad device or NULL out, DEVICE if HIP fails. */
+ * INVALID_ARG for a bad device or NULL out, DEVICE if HIP fails.
+ * Two environment variables are read here:
+ *   FLA_TRACE=1       turns on the launch log for the process (=0 turns it
+ *                     off): every kernel launch (name, grid, block, LDS
+ *                     bytes, stream) and every call of the main entry
+ *                     points (arguments, status, host time) is written to
+ *                     stderr as a line starting "[flaproj]";
+ *   FLA_FAIL_ALLOC=k  testing aid for callers' error paths: the k-th device
+ *                     allocation made for this context fails as if the
+ *                     device were out of memory (the entry point returns
+ *                     FLA_ERR_OUT_OF_MEMORY before it launches anything, so
+ *                     its outputs are untouched); later allocations proceed. */
 fla_status fla_ctx_create(fla_ctx** out, int device);
 
 /* Destroy a context; waits for the device first.  NULL is accepted. */

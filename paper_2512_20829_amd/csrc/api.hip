@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -13,6 +15,7 @@
 
 #include "flaproj.h"
 #include "internal.hpp"
+#include "host_logic.hpp"
 #include "kernels.hpp"
 #include "learned.hpp"
 
@@ -48,7 +51,21 @@ struct fla_ctx {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<unsigned char> graph_key;
     int64_t graph_replays = 0;
+    // testing aid (FLA_FAIL_ALLOC=k at creation): the k-th device allocation
+    // made for this context fails as if the device were out of memory
+    int64_t fail_alloc = 0;
 };
+
+namespace flp {
+int g_trace = 0;
+
+void trace_launch(const char* kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    std::fprintf(stderr, "[flaproj] launch %s grid=(%u,%u,%u) block=(%u,%u,%u) lds=%zu stream=%p\n", kernel, grid.x,
+                 grid.y, grid.z, block.x, block.y, block.z, lds, (void*)s);
+    std::fflush(stderr);
+}
+}  // namespace flp
 
 static thread_local std::string g_create_error;
 
@@ -109,6 +126,53 @@ struct Carver {
     }
 };
 
+// Device allocation made for a context (honours the FLA_FAIL_ALLOC testing aid).
+hipError_t dev_malloc(fla_ctx* ctx, void** p, size_t bytes)
+{
+    if (ctx->fail_alloc > 0 && --ctx->fail_alloc == 0) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+// Entry-point line of the launch log: the call, a short description of its
+// arguments, its status and the host time it took.
+struct TraceCall {
+    const fla_ctx* ctx;
+    const char* name;
+    std::string what;
+    std::chrono::steady_clock::time_point t0;
+    TraceCall(const fla_ctx* c, const char* n) : ctx(c), name(n)
+    {
+        if (g_trace) t0 = std::chrono::steady_clock::now();
+    }
+    fla_status done(fla_status st)
+    {
+        if (g_trace) {
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            std::fprintf(stderr, "[flaproj] call %s %s -> %d (%.3f ms host)%s%s\n", name, what.c_str(), (int)st, ms,
+                         st != FLA_OK && ctx ? ": " : "", st != FLA_OK && ctx ? ctx->err.c_str() : "");
+            std::fflush(stderr);
+        }
+        return st;
+    }
+};
+
+std::string traj_desc(const fla_trajectories* t)
+{
+    if (!t) return "traj=NULL";
+    return "N=" + std::to_string(t->count) + (t->prec == FLA_F64 ? " f64" : " f32");
+}
+std::string mesh_desc(const fla_mesh* m)
+{
+    if (!m) return "mesh=NULL";
+    std::string r = "mesh=" + std::to_string(m->n[0]) + "x" + std::to_string(m->n[1]);
+    if (m->dim == 3) r += "x" + std::to_string(m->n[2]);
+    return r;
+}
+
 fla_status ensure_ws(fla_ctx* ctx, size_t need)
 {
     if (need <= ctx->ws_size) return FLA_OK;
@@ -123,7 +187,7 @@ fla_status ensure_ws(fla_ctx* ctx, size_t need)
         ctx->ws_size = 0;
     }
     size_t sz = need + need / 4 + (1 << 20);
-    hipError_t e = hipMalloc(&ctx->ws, sz);
+    hipError_t e = dev_malloc(ctx, &ctx->ws, sz);
     if (e != hipSuccess) {
         ctx->ws = nullptr;
         ctx->err = "workspace allocation of " + std::to_string(sz) + " bytes failed: " + hipGetErrorString(e);
@@ -147,7 +211,7 @@ fla_status ensure_tws(fla_ctx* ctx, size_t need)
         ctx->tws_size = 0;
     }
     size_t sz = need + need / 4 + (1 << 20);
-    hipError_t e = hipMalloc(&ctx->tws, sz);
+    hipError_t e = dev_malloc(ctx, &ctx->tws, sz);
     if (e != hipSuccess) {
         ctx->tws = nullptr;
         ctx->err = "training workspace allocation of " + std::to_string(sz) + " bytes failed: " + hipGetErrorString(e);
@@ -520,7 +584,7 @@ fla_status batch_impl(fla_ctx* ctx, int nsnap, const MeshDev* md, const TrajDev*
         if (ctx->items) HIP_OK(hipFree(ctx->items));
         ctx->items = nullptr;
         ctx->items_size = 0;
-        hipError_t e = hipMalloc(&ctx->items, isz);
+        hipError_t e = dev_malloc(ctx, &ctx->items, isz);
         if (e != hipSuccess) {
             ctx->items = nullptr;
             ctx->err = std::string("snapshot table allocation failed: ") + hipGetErrorString(e);
@@ -885,6 +949,8 @@ FLA_EXPORT fla_status fla_ctx_create(fla_ctx** out, int device)
         return FLA_ERR_OUT_OF_MEMORY;
     }
     ctx->device = device;
+    if (const char* t = std::getenv("FLA_TRACE")) g_trace = std::atoi(t) != 0 || t[0] == 'y';
+    if (const char* f = std::getenv("FLA_FAIL_ALLOC")) ctx->fail_alloc = std::atoll(f);
     e = hipSetDevice(device);
     if (e == hipSuccess && device < kMaxScratchDevices) {
         // device address of this GPU's copy of the fixed workspace (once per GPU)
@@ -928,29 +994,37 @@ FLA_EXPORT fla_status fla_ctx_destroy(fla_ctx* ctx)
 FLA_EXPORT fla_status fla_project_sources(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
                                const fla_params* params, const fla_fields* out, void* stream)
 {
-    return project_entry(ctx, mesh, traj, params, out, stream, nullptr, 0);
+    TraceCall tc(ctx, "fla_project_sources");
+    if (g_trace) tc.what = mesh_desc(mesh) + " " + traj_desc(traj);
+    return tc.done([&]() -> fla_status {
+        return project_entry(ctx, mesh, traj, params, out, stream, nullptr, 0);
+    }());
 }
 
 FLA_EXPORT fla_status fla_project_sources_noalloc(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
                                                   const fla_params* params, const fla_fields* out, void* stream)
 {
-    if (!ctx) return FLA_ERR_INVALID_ARG;
-    ctx->err.clear();
-    void* ptr = nullptr;
-    if (ctx->device >= 0 && ctx->device < kMaxScratchDevices) {
-        std::lock_guard<std::mutex> lock(g_scratch_mu);
-        ptr = g_scratch_ptr[ctx->device];
-    }
-    if (!ptr) {
-        ctx->err = "fla_project_sources_noalloc: no fixed workspace on this device";
-        return FLA_ERR_UNSUPPORTED;
-    }
-    // no profiling events here: creating them is an allocation
-    const bool prof = ctx->prof;
-    ctx->prof = false;
-    const fla_status st = project_entry(ctx, mesh, traj, params, out, stream, ptr, FLA_NOALLOC_SCRATCH_BYTES);
-    ctx->prof = prof;
-    return st;
+    TraceCall tc(ctx, "fla_project_sources_noalloc");
+    if (g_trace) tc.what = mesh_desc(mesh) + " " + traj_desc(traj);
+    return tc.done([&]() -> fla_status {
+        if (!ctx) return FLA_ERR_INVALID_ARG;
+        ctx->err.clear();
+        void* ptr = nullptr;
+        if (ctx->device >= 0 && ctx->device < kMaxScratchDevices) {
+            std::lock_guard<std::mutex> lock(g_scratch_mu);
+            ptr = g_scratch_ptr[ctx->device];
+        }
+        if (!ptr) {
+            ctx->err = "fla_project_sources_noalloc: no fixed workspace on this device";
+            return FLA_ERR_UNSUPPORTED;
+        }
+        // no profiling events here: creating them is an allocation
+        const bool prof = ctx->prof;
+        ctx->prof = false;
+        const fla_status st = project_entry(ctx, mesh, traj, params, out, stream, ptr, FLA_NOALLOC_SCRATCH_BYTES);
+        ctx->prof = prof;
+        return st;
+    }());
 }
 
 }  // extern "C"
@@ -999,64 +1073,72 @@ FLA_EXPORT fla_status psicell_accumulate(fla_ctx* ctx, const fla_mesh* mesh, con
                               double particle_weight, const fla_params* params, const fla_fields* out,
                               void* stream)
 {
-    if (!ctx) return FLA_ERR_INVALID_ARG;
-    ctx->err.clear();
-    try {
-        MeshDev m;
-        fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
-        if (st != FLA_OK) return st;
-        TrajDev t;
-        st = check_traj(ctx, particles, m.dim, false, &t);
-        if (st != FLA_OK) return st;
-        st = check_params(ctx, params, false);
-        if (st != FLA_OK) return st;
-        st = check_fields(ctx, out, m.dim);
-        if (st != FLA_OK) return st;
-        CHECK_ARG(is_fin(particle_weight), "particle_weight must be finite");
-        HIP_OK(hipSetDevice(ctx->device));
-        hipStream_t s = (hipStream_t)stream;
-        bool f64 = particles->prec == FLA_F64;
-        if (m.dim == 2)
-            return f64 ? psicell_impl<double, 2>(ctx, m, t, particle_weight, params, mesh, out, s)
-                       : psicell_impl<float, 2>(ctx, m, t, particle_weight, params, mesh, out, s);
-        return f64 ? psicell_impl<double, 3>(ctx, m, t, particle_weight, params, mesh, out, s)
-                   : psicell_impl<float, 3>(ctx, m, t, particle_weight, params, mesh, out, s);
-    } catch (...) {
-        ctx->err = "internal error";
-        return FLA_ERR_DEVICE;
-    }
+    TraceCall tc(ctx, "psicell_accumulate");
+    if (g_trace) tc.what = mesh_desc(mesh) + " " + traj_desc(particles);
+    return tc.done([&]() -> fla_status {
+        if (!ctx) return FLA_ERR_INVALID_ARG;
+        ctx->err.clear();
+        try {
+            MeshDev m;
+            fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+            if (st != FLA_OK) return st;
+            TrajDev t;
+            st = check_traj(ctx, particles, m.dim, false, &t);
+            if (st != FLA_OK) return st;
+            st = check_params(ctx, params, false);
+            if (st != FLA_OK) return st;
+            st = check_fields(ctx, out, m.dim);
+            if (st != FLA_OK) return st;
+            CHECK_ARG(is_fin(particle_weight), "particle_weight must be finite");
+            HIP_OK(hipSetDevice(ctx->device));
+            hipStream_t s = (hipStream_t)stream;
+            bool f64 = particles->prec == FLA_F64;
+            if (m.dim == 2)
+                return f64 ? psicell_impl<double, 2>(ctx, m, t, particle_weight, params, mesh, out, s)
+                           : psicell_impl<float, 2>(ctx, m, t, particle_weight, params, mesh, out, s);
+            return f64 ? psicell_impl<double, 3>(ctx, m, t, particle_weight, params, mesh, out, s)
+                       : psicell_impl<float, 3>(ctx, m, t, particle_weight, params, mesh, out, s);
+        } catch (...) {
+            ctx->err = "internal error";
+            return FLA_ERR_DEVICE;
+        }
+    }());
 }
 
 FLA_EXPORT fla_status cic_accumulate(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* particles,
                                      double particle_weight, const fla_params* params, const fla_fields* out,
                                      void* stream)
 {
-    if (!ctx) return FLA_ERR_INVALID_ARG;
-    ctx->err.clear();
-    try {
-        MeshDev m;
-        fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
-        if (st != FLA_OK) return st;
-        TrajDev t;
-        st = check_traj(ctx, particles, m.dim, false, &t);
-        if (st != FLA_OK) return st;
-        st = check_params(ctx, params, false);
-        if (st != FLA_OK) return st;
-        st = check_fields(ctx, out, m.dim);
-        if (st != FLA_OK) return st;
-        CHECK_ARG(is_fin(particle_weight), "particle_weight must be finite");
-        HIP_OK(hipSetDevice(ctx->device));
-        hipStream_t s = (hipStream_t)stream;
-        bool f64 = particles->prec == FLA_F64;
-        if (m.dim == 2)
-            return f64 ? cic_impl<double, 2>(ctx, m, t, particle_weight, params, mesh, out, s)
-                       : cic_impl<float, 2>(ctx, m, t, particle_weight, params, mesh, out, s);
-        return f64 ? cic_impl<double, 3>(ctx, m, t, particle_weight, params, mesh, out, s)
-                   : cic_impl<float, 3>(ctx, m, t, particle_weight, params, mesh, out, s);
-    } catch (...) {
-        ctx->err = "internal error";
-        return FLA_ERR_DEVICE;
-    }
+    TraceCall tc(ctx, "cic_accumulate");
+    if (g_trace) tc.what = mesh_desc(mesh) + " " + traj_desc(particles);
+    return tc.done([&]() -> fla_status {
+        if (!ctx) return FLA_ERR_INVALID_ARG;
+        ctx->err.clear();
+        try {
+            MeshDev m;
+            fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+            if (st != FLA_OK) return st;
+            TrajDev t;
+            st = check_traj(ctx, particles, m.dim, false, &t);
+            if (st != FLA_OK) return st;
+            st = check_params(ctx, params, false);
+            if (st != FLA_OK) return st;
+            st = check_fields(ctx, out, m.dim);
+            if (st != FLA_OK) return st;
+            CHECK_ARG(is_fin(particle_weight), "particle_weight must be finite");
+            HIP_OK(hipSetDevice(ctx->device));
+            hipStream_t s = (hipStream_t)stream;
+            bool f64 = particles->prec == FLA_F64;
+            if (m.dim == 2)
+                return f64 ? cic_impl<double, 2>(ctx, m, t, particle_weight, params, mesh, out, s)
+                           : cic_impl<float, 2>(ctx, m, t, particle_weight, params, mesh, out, s);
+            return f64 ? cic_impl<double, 3>(ctx, m, t, particle_weight, params, mesh, out, s)
+                       : cic_impl<float, 3>(ctx, m, t, particle_weight, params, mesh, out, s);
+        } catch (...) {
+            ctx->err = "internal error";
+            return FLA_ERR_DEVICE;
+        }
+    }());
 }
 
 FLA_EXPORT fla_status fla_get_stats(fla_ctx* ctx, fla_stats* out)
@@ -1082,65 +1164,73 @@ FLA_EXPORT fla_status fla_bandwidth_forward(fla_ctx* ctx, const fla_mesh* mesh, 
                                             const float* theta, float* h_factor, float* z, float* o, float* features,
                                             void* stream)
 {
-    if (!ctx) return FLA_ERR_INVALID_ARG;
-    ctx->err.clear();
-    try {
-        MeshDev m;
-        fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
-        if (st != FLA_OK) return st;
-        TrajDev t;
-        st = check_traj(ctx, traj, m.dim, true, &t);
-        if (st != FLA_OK) return st;
-        CHECK_ARG(theta != nullptr, "theta is NULL");
-        CHECK_ARG(h_factor != nullptr || t.count == 0, "h_factor is NULL");
-        HIP_OK(hipSetDevice(ctx->device));
-        hipStream_t s = (hipStream_t)stream;
-        bool f64 = traj->prec == FLA_F64;
-        if (m.dim == 2)
-            return f64 ? bandwidth_forward_impl<double, 2>(ctx, m, t, theta, h_factor, z, o, features, s)
-                       : bandwidth_forward_impl<float, 2>(ctx, m, t, theta, h_factor, z, o, features, s);
-        return f64 ? bandwidth_forward_impl<double, 3>(ctx, m, t, theta, h_factor, z, o, features, s)
-                   : bandwidth_forward_impl<float, 3>(ctx, m, t, theta, h_factor, z, o, features, s);
-    } catch (...) {
-        ctx->err = "internal error";
-        return FLA_ERR_DEVICE;
-    }
+    TraceCall tc(ctx, "fla_bandwidth_forward");
+    if (g_trace) tc.what = mesh_desc(mesh) + " " + traj_desc(traj);
+    return tc.done([&]() -> fla_status {
+        if (!ctx) return FLA_ERR_INVALID_ARG;
+        ctx->err.clear();
+        try {
+            MeshDev m;
+            fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+            if (st != FLA_OK) return st;
+            TrajDev t;
+            st = check_traj(ctx, traj, m.dim, true, &t);
+            if (st != FLA_OK) return st;
+            CHECK_ARG(theta != nullptr, "theta is NULL");
+            CHECK_ARG(h_factor != nullptr || t.count == 0, "h_factor is NULL");
+            HIP_OK(hipSetDevice(ctx->device));
+            hipStream_t s = (hipStream_t)stream;
+            bool f64 = traj->prec == FLA_F64;
+            if (m.dim == 2)
+                return f64 ? bandwidth_forward_impl<double, 2>(ctx, m, t, theta, h_factor, z, o, features, s)
+                           : bandwidth_forward_impl<float, 2>(ctx, m, t, theta, h_factor, z, o, features, s);
+            return f64 ? bandwidth_forward_impl<double, 3>(ctx, m, t, theta, h_factor, z, o, features, s)
+                       : bandwidth_forward_impl<float, 3>(ctx, m, t, theta, h_factor, z, o, features, s);
+        } catch (...) {
+            ctx->err = "internal error";
+            return FLA_ERR_DEVICE;
+        }
+    }());
 }
 
 FLA_EXPORT fla_status fla_project_backward(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
                                            const fla_params* params, const fla_fields* S, const fla_fields* dL_dS,
                                            float* dL_dlogh, void* stream)
 {
-    if (!ctx) return FLA_ERR_INVALID_ARG;
-    ctx->err.clear();
-    try {
-        MeshDev m;
-        fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
-        if (st != FLA_OK) return st;
-        TrajDev t;
-        st = check_traj(ctx, traj, m.dim, true, &t);
-        if (st != FLA_OK) return st;
-        st = check_params(ctx, params, true);
-        if (st != FLA_OK) return st;
-        CHECK_ARG(params->mode == FLA_NW, "fla_project_backward differentiates the FLA_NW estimator");
-        st = check_fields(ctx, S, m.dim);
-        if (st != FLA_OK) return st;
-        CHECK_ARG(S->den != nullptr, "S.den is required");
-        st = check_fields(ctx, dL_dS, m.dim);
-        if (st != FLA_OK) return st;
-        CHECK_ARG(dL_dlogh != nullptr || t.count == 0, "dL_dlogh is NULL");
-        HIP_OK(hipSetDevice(ctx->device));
-        hipStream_t s = (hipStream_t)stream;
-        bool f64 = traj->prec == FLA_F64;
-        if (m.dim == 2)
-            return f64 ? project_backward_impl<double, 2>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s)
-                       : project_backward_impl<float, 2>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s);
-        return f64 ? project_backward_impl<double, 3>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s)
-                   : project_backward_impl<float, 3>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s);
-    } catch (...) {
-        ctx->err = "internal error";
-        return FLA_ERR_DEVICE;
-    }
+    TraceCall tc(ctx, "fla_project_backward");
+    if (g_trace) tc.what = mesh_desc(mesh) + " " + traj_desc(traj);
+    return tc.done([&]() -> fla_status {
+        if (!ctx) return FLA_ERR_INVALID_ARG;
+        ctx->err.clear();
+        try {
+            MeshDev m;
+            fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+            if (st != FLA_OK) return st;
+            TrajDev t;
+            st = check_traj(ctx, traj, m.dim, true, &t);
+            if (st != FLA_OK) return st;
+            st = check_params(ctx, params, true);
+            if (st != FLA_OK) return st;
+            CHECK_ARG(params->mode == FLA_NW, "fla_project_backward differentiates the FLA_NW estimator");
+            st = check_fields(ctx, S, m.dim);
+            if (st != FLA_OK) return st;
+            CHECK_ARG(S->den != nullptr, "S.den is required");
+            st = check_fields(ctx, dL_dS, m.dim);
+            if (st != FLA_OK) return st;
+            CHECK_ARG(dL_dlogh != nullptr || t.count == 0, "dL_dlogh is NULL");
+            HIP_OK(hipSetDevice(ctx->device));
+            hipStream_t s = (hipStream_t)stream;
+            bool f64 = traj->prec == FLA_F64;
+            if (m.dim == 2)
+                return f64 ? project_backward_impl<double, 2>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s)
+                           : project_backward_impl<float, 2>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s);
+            return f64 ? project_backward_impl<double, 3>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s)
+                       : project_backward_impl<float, 3>(ctx, m, t, params, mesh, S, dL_dS, dL_dlogh, s);
+        } catch (...) {
+            ctx->err = "internal error";
+            return FLA_ERR_DEVICE;
+        }
+    }());
 }
 
 FLA_EXPORT fla_status fla_bandwidth_backward(fla_ctx* ctx, int dim, const float* theta, int64_t count, const float* z,
@@ -1343,14 +1433,18 @@ FLA_EXPORT fla_status fla_project_batch(fla_ctx* ctx, int nsnap, const fla_mesh*
                                         const fla_trajectories* trajs, const fla_params* params,
                                         const fla_fields* outs, void* stream)
 {
-    if (!ctx) return FLA_ERR_INVALID_ARG;
-    ctx->err.clear();
-    try {
-        return batch_entry(ctx, nsnap, meshes, trajs, params, outs, stream, -1, -1, ctx->batch_graph && !ctx->prof);
-    } catch (...) {
-        ctx->err = "internal error";
-        return FLA_ERR_DEVICE;
-    }
+    TraceCall tc(ctx, "fla_project_batch");
+    if (g_trace) tc.what = "nsnap=" + std::to_string(nsnap);
+    return tc.done([&]() -> fla_status {
+        if (!ctx) return FLA_ERR_INVALID_ARG;
+        ctx->err.clear();
+        try {
+            return batch_entry(ctx, nsnap, meshes, trajs, params, outs, stream, -1, -1, ctx->batch_graph && !ctx->prof);
+        } catch (...) {
+            ctx->err = "internal error";
+            return FLA_ERR_DEVICE;
+        }
+    }());
 }
 
 FLA_EXPORT fla_status fla_set_batch_graph(fla_ctx* ctx, int enable)
@@ -1443,85 +1537,89 @@ FLA_EXPORT fla_status fla_advance_project(fla_ctx* ctx, const fla_mesh* mesh, co
                                           const fla_flow* flow, const fla_step* step, const fla_params* params,
                                           int prec, const fla_fields* out, void* stream)
 {
-    if (!ctx) return FLA_ERR_INVALID_ARG;
-    ctx->err.clear();
-    try {
-        MeshDev m;
-        fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
-        if (st != FLA_OK) return st;
-        const int D = m.dim;
-        CHECK_ARG(drops != nullptr, "droplets is NULL");
-        CHECK_ARG(drops->count >= 0 && drops->count < (int64_t(1) << 31), "count must be in [0, 2^31)");
-        if (drops->count > 0) {
-            for (int a = 0; a < D; ++a) CHECK_ARG(drops->x[a] && drops->v[a], "x and v must be non-NULL for every axis");
-            CHECK_ARG(drops->J && drops->dJ && drops->r, "J, dJ and r are required");
-            CHECK_ARG(drops->n0 != nullptr || is_fin(drops->n0_scalar), "n0_scalar must be finite when n0 is NULL");
+    TraceCall tc(ctx, "fla_advance_project");
+    if (g_trace) tc.what = mesh_desc(mesh) + (drops ? " N=" + std::to_string(drops->count) : std::string(" drops=NULL"));
+    return tc.done([&]() -> fla_status {
+        if (!ctx) return FLA_ERR_INVALID_ARG;
+        ctx->err.clear();
+        try {
+            MeshDev m;
+            fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
+            if (st != FLA_OK) return st;
+            const int D = m.dim;
+            CHECK_ARG(drops != nullptr, "droplets is NULL");
+            CHECK_ARG(drops->count >= 0 && drops->count < (int64_t(1) << 31), "count must be in [0, 2^31)");
+            if (drops->count > 0) {
+                for (int a = 0; a < D; ++a) CHECK_ARG(drops->x[a] && drops->v[a], "x and v must be non-NULL for every axis");
+                CHECK_ARG(drops->J && drops->dJ && drops->r, "J, dJ and r are required");
+                CHECK_ARG(drops->n0 != nullptr || is_fin(drops->n0_scalar), "n0_scalar must be finite when n0 is NULL");
+            }
+            CHECK_ARG(flow != nullptr, "flow is NULL");
+            CHECK_ARG(flow->kind == FLA_FLOW_NONE || (flow->kind == FLA_FLOW_TAYLOR_GREEN && D == 2) ||
+                          (flow->kind == FLA_FLOW_ABC && D == 3),
+                      "flow.kind must be FLA_FLOW_NONE, FLA_FLOW_TAYLOR_GREEN (2-D) or FLA_FLOW_ABC (3-D)");
+            bool fin = is_fin(flow->U) && is_fin(flow->k);
+            for (int a = 0; a < 3; ++a) fin = fin && is_fin(flow->abc[a]) && is_fin(flow->phase[a]) && is_fin(flow->u0[a]);
+            for (int e = 0; e < 9; ++e) fin = fin && is_fin(flow->G[e]);
+            CHECK_ARG(fin, "flow parameters must be finite");
+            CHECK_ARG(step != nullptr, "step is NULL");
+            CHECK_ARG(is_fin(step->dt) && step->dt > 0.0, "step.dt must be positive and finite");
+            CHECK_ARG(step->substeps >= 1 && step->substeps <= (1 << 20), "step.substeps must be in [1, 2^20]");
+            CHECK_ARG(prec == FLA_F32 || prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
+            st = check_params(ctx, params, true);
+            if (st != FLA_OK) return st;
+            st = check_fields(ctx, out, D);
+            if (st != FLA_OK) return st;
+            if (params->mode == FLA_DEPOSIT)
+                CHECK_ARG(is_fin(drops->seed_volume) && drops->seed_volume > 0.0,
+                          "seed_volume must be positive and finite in FLA_DEPOSIT mode");
+            HIP_OK(hipSetDevice(ctx->device));
+            hipStream_t s = (hipStream_t)stream;
+            const bool f64 = prec == FLA_F64;
+            if (drops->count == 0) {
+                HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
+                return f64 ? zero_outputs<double>(ctx, m, out, s) : zero_outputs<float>(ctx, m, out, s);
+            }
+            ProduceArgs pa{};
+            pa.count = drops->count;
+            for (int a = 0; a < 3; ++a) {
+                pa.x[a] = a < D ? drops->x[a] : nullptr;
+                pa.v[a] = a < D ? drops->v[a] : nullptr;
+            }
+            pa.J = drops->J;
+            pa.dJ = drops->dJ;
+            pa.r = drops->r;
+            pa.n0 = drops->n0;
+            pa.n0_scalar = drops->n0_scalar;
+            pa.seed_volume = drops->seed_volume;
+            pa.phibar = drops->phibar;
+            pa.flow.kind = flow->kind;
+            pa.flow.U = flow->U;
+            pa.flow.k = flow->k;
+            for (int a = 0; a < 3; ++a) {
+                pa.flow.abc[a] = flow->abc[a];
+                pa.flow.phase[a] = flow->phase[a];
+                pa.flow.u0[a] = flow->u0[a];
+            }
+            for (int e = 0; e < 9; ++e) pa.flow.G[e] = flow->G[e];
+            pa.dt = step->dt;
+            pa.substeps = step->substeps;
+            pa.update = step->update_state != 0;
+            TrajDev t{};
+            t.count = drops->count;
+            t.n0 = drops->n0;
+            t.n0_scalar = drops->n0_scalar;
+            t.seed_volume = drops->seed_volume;
+            if (D == 2)
+                return f64 ? project_impl<double, 2>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa)
+                           : project_impl<float, 2>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa);
+            return f64 ? project_impl<double, 3>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa)
+                       : project_impl<float, 3>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa);
+        } catch (...) {
+            ctx->err = "internal error";
+            return FLA_ERR_DEVICE;
         }
-        CHECK_ARG(flow != nullptr, "flow is NULL");
-        CHECK_ARG(flow->kind == FLA_FLOW_NONE || (flow->kind == FLA_FLOW_TAYLOR_GREEN && D == 2) ||
-                      (flow->kind == FLA_FLOW_ABC && D == 3),
-                  "flow.kind must be FLA_FLOW_NONE, FLA_FLOW_TAYLOR_GREEN (2-D) or FLA_FLOW_ABC (3-D)");
-        bool fin = is_fin(flow->U) && is_fin(flow->k);
-        for (int a = 0; a < 3; ++a) fin = fin && is_fin(flow->abc[a]) && is_fin(flow->phase[a]) && is_fin(flow->u0[a]);
-        for (int e = 0; e < 9; ++e) fin = fin && is_fin(flow->G[e]);
-        CHECK_ARG(fin, "flow parameters must be finite");
-        CHECK_ARG(step != nullptr, "step is NULL");
-        CHECK_ARG(is_fin(step->dt) && step->dt > 0.0, "step.dt must be positive and finite");
-        CHECK_ARG(step->substeps >= 1 && step->substeps <= (1 << 20), "step.substeps must be in [1, 2^20]");
-        CHECK_ARG(prec == FLA_F32 || prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
-        st = check_params(ctx, params, true);
-        if (st != FLA_OK) return st;
-        st = check_fields(ctx, out, D);
-        if (st != FLA_OK) return st;
-        if (params->mode == FLA_DEPOSIT)
-            CHECK_ARG(is_fin(drops->seed_volume) && drops->seed_volume > 0.0,
-                      "seed_volume must be positive and finite in FLA_DEPOSIT mode");
-        HIP_OK(hipSetDevice(ctx->device));
-        hipStream_t s = (hipStream_t)stream;
-        const bool f64 = prec == FLA_F64;
-        if (drops->count == 0) {
-            HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
-            return f64 ? zero_outputs<double>(ctx, m, out, s) : zero_outputs<float>(ctx, m, out, s);
-        }
-        ProduceArgs pa{};
-        pa.count = drops->count;
-        for (int a = 0; a < 3; ++a) {
-            pa.x[a] = a < D ? drops->x[a] : nullptr;
-            pa.v[a] = a < D ? drops->v[a] : nullptr;
-        }
-        pa.J = drops->J;
-        pa.dJ = drops->dJ;
-        pa.r = drops->r;
-        pa.n0 = drops->n0;
-        pa.n0_scalar = drops->n0_scalar;
-        pa.seed_volume = drops->seed_volume;
-        pa.phibar = drops->phibar;
-        pa.flow.kind = flow->kind;
-        pa.flow.U = flow->U;
-        pa.flow.k = flow->k;
-        for (int a = 0; a < 3; ++a) {
-            pa.flow.abc[a] = flow->abc[a];
-            pa.flow.phase[a] = flow->phase[a];
-            pa.flow.u0[a] = flow->u0[a];
-        }
-        for (int e = 0; e < 9; ++e) pa.flow.G[e] = flow->G[e];
-        pa.dt = step->dt;
-        pa.substeps = step->substeps;
-        pa.update = step->update_state != 0;
-        TrajDev t{};
-        t.count = drops->count;
-        t.n0 = drops->n0;
-        t.n0_scalar = drops->n0_scalar;
-        t.seed_volume = drops->seed_volume;
-        if (D == 2)
-            return f64 ? project_impl<double, 2>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa)
-                       : project_impl<float, 2>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa);
-        return f64 ? project_impl<double, 3>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa)
-                   : project_impl<float, 3>(ctx, m, t, params, mesh, out, s, nullptr, 0, &pa);
-    } catch (...) {
-        ctx->err = "internal error";
-        return FLA_ERR_DEVICE;
-    }
+    }());
 }
 
 FLA_EXPORT fla_status fla_bandwidth_standardise(fla_ctx* ctx, int nsnap, const fla_mesh* meshes,
@@ -1586,74 +1684,78 @@ FLA_EXPORT fla_status fla_mlp_train_step(fla_ctx* ctx, const fla_mesh* mesh, con
                                          float* v, int64_t step, double lr, double beta1, double beta2, double eps,
                                          double* loss, void* stream)
 {
-    if (!ctx) return FLA_ERR_INVALID_ARG;
-    ctx->err.clear();
-    try {
-        MeshDev md;
-        fla_status st = check_mesh(ctx, mesh, &md, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
-        if (st != FLA_OK) return st;
-        TrajDev td;
-        st = check_traj(ctx, traj, md.dim, true, &td);
-        if (st != FLA_OK) return st;
-        st = check_params(ctx, params, true);
-        if (st != FLA_OK) return st;
-        CHECK_ARG(params->mode == FLA_NW, "fla_mlp_train_step trains on the FLA_NW estimator");
-        CHECK_ARG(params->h_factor == nullptr, "params.h_factor must be NULL (the step forms the factors)");
-        st = check_fields(ctx, ref, md.dim);
-        if (st != FLA_OK) return st;
-        CHECK_ARG(theta && m && v, "theta, m and v are required");
-        CHECK_ARG(step >= 1, "step counts from 1");
-        CHECK_ARG(is_fin(lr) && lr >= 0.0 && beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps >= 0.0,
-                  "invalid Adam hyper-parameters");
-        HIP_OK(hipSetDevice(ctx->device));
-        const int64_t N = traj->count, M = md.M;
-        const int C = md.dim + 1;
-        const size_t rb = traj->prec == FLA_F64 ? 8 : 4;
-        float *hf, *z, *o, *dlogh, *grad;
-        unsigned char *Sp[4], *den, *Gp[4];
-        double* res;
-        auto layout = [&](Carver& c) {
-            hf = c.take<float>(N > 0 ? N : 1);
-            z = c.take<float>((size_t)kFeat * (N > 0 ? N : 1));
-            o = c.take<float>(N > 0 ? N : 1);
-            dlogh = c.take<float>(N > 0 ? N : 1);
-            for (int k = 0; k < C; ++k) Sp[k] = c.take<unsigned char>((size_t)M * rb);
-            den = c.take<unsigned char>((size_t)M * rb);
-            for (int k = 0; k < C; ++k) Gp[k] = c.take<unsigned char>((size_t)M * rb);
-            grad = c.take<float>(kParams);
-            res = c.take<double>(1 + 2 * 4);
-        };
-        {
-            Carver probe(nullptr);
-            layout(probe);
-            st = ensure_tws(ctx, probe.off + 256);
+    TraceCall tc(ctx, "fla_mlp_train_step");
+    if (g_trace) tc.what = mesh_desc(mesh) + " " + traj_desc(traj);
+    return tc.done([&]() -> fla_status {
+        if (!ctx) return FLA_ERR_INVALID_ARG;
+        ctx->err.clear();
+        try {
+            MeshDev md;
+            fla_status st = check_mesh(ctx, mesh, &md, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
             if (st != FLA_OK) return st;
+            TrajDev td;
+            st = check_traj(ctx, traj, md.dim, true, &td);
+            if (st != FLA_OK) return st;
+            st = check_params(ctx, params, true);
+            if (st != FLA_OK) return st;
+            CHECK_ARG(params->mode == FLA_NW, "fla_mlp_train_step trains on the FLA_NW estimator");
+            CHECK_ARG(params->h_factor == nullptr, "params.h_factor must be NULL (the step forms the factors)");
+            st = check_fields(ctx, ref, md.dim);
+            if (st != FLA_OK) return st;
+            CHECK_ARG(theta && m && v, "theta, m and v are required");
+            CHECK_ARG(step >= 1, "step counts from 1");
+            CHECK_ARG(is_fin(lr) && lr >= 0.0 && beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps >= 0.0,
+                      "invalid Adam hyper-parameters");
+            HIP_OK(hipSetDevice(ctx->device));
+            const int64_t N = traj->count, M = md.M;
+            const int C = md.dim + 1;
+            const size_t rb = traj->prec == FLA_F64 ? 8 : 4;
+            float *hf, *z, *o, *dlogh, *grad;
+            unsigned char *Sp[4], *den, *Gp[4];
+            double* res;
+            auto layout = [&](Carver& c) {
+                hf = c.take<float>(N > 0 ? N : 1);
+                z = c.take<float>((size_t)kFeat * (N > 0 ? N : 1));
+                o = c.take<float>(N > 0 ? N : 1);
+                dlogh = c.take<float>(N > 0 ? N : 1);
+                for (int k = 0; k < C; ++k) Sp[k] = c.take<unsigned char>((size_t)M * rb);
+                den = c.take<unsigned char>((size_t)M * rb);
+                for (int k = 0; k < C; ++k) Gp[k] = c.take<unsigned char>((size_t)M * rb);
+                grad = c.take<float>(kParams);
+                res = c.take<double>(1 + 2 * 4);
+            };
+            {
+                Carver probe(nullptr);
+                layout(probe);
+                st = ensure_tws(ctx, probe.off + 256);
+                if (st != FLA_OK) return st;
+            }
+            Carver c(ctx->tws);
+            layout(c);
+            fla_params p = *params;
+            p.h_factor = hf;
+            fla_fields S{}, G{};
+            S.S_mass = Sp[0];
+            G.S_mass = Gp[0];
+            for (int a = 0; a < md.dim; ++a) {
+                S.S_mom[a] = Sp[1 + a];
+                G.S_mom[a] = Gp[1 + a];
+            }
+            S.den = den;
+            // 1. features and network; 2. projection with the factors; 3. loss and
+            // dL/dS; 4. estimator backward; 5. network backward; 6. Adam
+            st = fla_bandwidth_forward(ctx, mesh, traj, theta, hf, z, o, nullptr, stream);
+            if (st == FLA_OK) st = fla_project_sources(ctx, mesh, traj, &p, &S, stream);
+            if (st == FLA_OK) st = fla_rel_l2_loss(ctx, C, M, traj->prec, &S, ref, &G, loss ? loss : res, stream);
+            if (st == FLA_OK) st = fla_project_backward(ctx, mesh, traj, &p, &S, &G, dlogh, stream);
+            if (st == FLA_OK) st = fla_bandwidth_backward(ctx, md.dim, theta, N, z, o, dlogh, grad, stream);
+            if (st == FLA_OK) st = fla_adam_step(ctx, theta, m, v, grad, step, lr, beta1, beta2, eps, stream);
+            return st;
+        } catch (...) {
+            ctx->err = "internal error";
+            return FLA_ERR_DEVICE;
         }
-        Carver c(ctx->tws);
-        layout(c);
-        fla_params p = *params;
-        p.h_factor = hf;
-        fla_fields S{}, G{};
-        S.S_mass = Sp[0];
-        G.S_mass = Gp[0];
-        for (int a = 0; a < md.dim; ++a) {
-            S.S_mom[a] = Sp[1 + a];
-            G.S_mom[a] = Gp[1 + a];
-        }
-        S.den = den;
-        // 1. features and network; 2. projection with the factors; 3. loss and
-        // dL/dS; 4. estimator backward; 5. network backward; 6. Adam
-        st = fla_bandwidth_forward(ctx, mesh, traj, theta, hf, z, o, nullptr, stream);
-        if (st == FLA_OK) st = fla_project_sources(ctx, mesh, traj, &p, &S, stream);
-        if (st == FLA_OK) st = fla_rel_l2_loss(ctx, C, M, traj->prec, &S, ref, &G, loss ? loss : res, stream);
-        if (st == FLA_OK) st = fla_project_backward(ctx, mesh, traj, &p, &S, &G, dlogh, stream);
-        if (st == FLA_OK) st = fla_bandwidth_backward(ctx, md.dim, theta, N, z, o, dlogh, grad, stream);
-        if (st == FLA_OK) st = fla_adam_step(ctx, theta, m, v, grad, step, lr, beta1, beta2, eps, stream);
-        return st;
-    } catch (...) {
-        ctx->err = "internal error";
-        return FLA_ERR_DEVICE;
-    }
+    }());
 }
 
 FLA_EXPORT const char* fla_last_error(const fla_ctx* ctx)
@@ -1697,27 +1799,6 @@ void free_index(fla_cell_index* ix)
     delete ix;
 }
 
-// Interior bucket edges of one axis at the quantiles i M / nb of the
-// centroid histogram (right boundaries of the bins where the cumulative
-// count first reaches each quantile), strictly increasing and strictly
-// inside (lo, hi).  Returns lo, the interior edges, hi.
-std::vector<double> quantile_edges(const uint32_t* hist, int64_t M, int nb, double lo, double hi)
-{
-    std::vector<double> e{lo};
-    const double w = (hi - lo) / (double)kCellsHistBins;
-    int64_t cum = 0;
-    int bin = 0;
-    for (int i = 1; i < nb; ++i) {
-        const double target = (double)i * (double)M / (double)nb;
-        while (bin < kCellsHistBins && (double)(cum + hist[bin]) < target) cum += hist[bin++];
-        if (bin >= kCellsHistBins - 1) break;
-        const double edge = lo + (double)(bin + 1) * w;
-        if (edge > e.back() && edge < hi) e.push_back(edge);
-    }
-    e.push_back(hi);
-    return e;
-}
-
 fla_status cell_index_build(fla_ctx* ctx, const fla_cells* c, int32_t per_bucket, fla_cell_index* ix)
 {
     const int D = c->dim;
@@ -1749,27 +1830,24 @@ fla_status cell_index_build(fla_ctx* ctx, const fla_cells* c, int32_t per_bucket
                              "non-finite volume");
     // 2. buckets per axis: about M / per_bucket in all, shared out in
     // proportion to the box edges, then edges at the coordinate quantiles
-    double gm = 1.0;
-    for (int a = 0; a < D; ++a) gm *= c->hi[a] - c->lo[a];
-    gm = std::pow(gm, 1.0 / D);
-    const double total = std::max(1.0, (double)M / (double)per_bucket);
+    double Ls[3];
+    for (int a = 0; a < D; ++a) Ls[a] = c->hi[a] - c->lo[a];
+    const std::vector<int> nbw = host::bucket_counts(D, Ls, (double)M / (double)per_bucket, kCellsMaxBuckets);
     std::vector<double> edges[3];
     int64_t nbk = 1;
     for (int a = 0; a < 3; ++a) {
-        if (a < D) {
-            double want = std::pow(total, 1.0 / D) * (c->hi[a] - c->lo[a]) / gm;
-            int nb = (int)std::lround(std::min(std::max(want, 1.0), (double)kCellsMaxBuckets));
-            edges[a] = quantile_edges(hh.data() + (size_t)a * kCellsHistBins, M, nb, c->lo[a], c->hi[a]);
-        } else {
+        if (a < D)
+            edges[a] = host::quantile_edges(hh.data() + (size_t)a * kCellsHistBins, kCellsHistBins, M, nbw[a],
+                                            c->lo[a], c->hi[a]);
+        else
             edges[a] = {0.0, 1.0};
-        }
         nbk *= (int64_t)edges[a].size() - 1;
     }
     CHECK_ARG(nbk * kClasses + 1 < (int64_t(1) << 31), "too many buckets");
     CellGridDev g{};
     g.dim = D;
     g.nbuckets = (int)nbk;
-    HIP_OK(hipMalloc((void**)&ix->edges, sizeof(double) * 3 * (kCellsMaxBuckets + 1)));
+    HIP_OK(dev_malloc(ctx, (void**)&ix->edges, sizeof(double) * 3 * (kCellsMaxBuckets + 1)));
     for (int a = 0; a < 3; ++a) {
         g.nb[a] = (int)edges[a].size() - 1;
         g.periodic[a] = a < D ? (c->periodic[a] != 0) : 0;
@@ -1808,9 +1886,9 @@ fla_status cell_index_build(fla_ctx* ctx, const fla_cells* c, int32_t per_bucket
     const uint32_t* skeys = in_alt ? keys2 : keys;
     const uint32_t* svals = in_alt ? vals2 : vals;
     HIP_OK(launch_bucket_bounds(skeys, M, (uint32_t)nbk, cstart, s));
-    for (int a = 0; a < D; ++a) HIP_OK(hipMalloc((void**)&ix->xs[a], sizeof(double) * M));
-    if (c->volume) HIP_OK(hipMalloc((void**)&ix->vs, sizeof(double) * M));
-    HIP_OK(hipMalloc((void**)&ix->perm, sizeof(uint32_t) * M));
+    for (int a = 0; a < D; ++a) HIP_OK(dev_malloc(ctx, (void**)&ix->xs[a], sizeof(double) * M));
+    if (c->volume) HIP_OK(dev_malloc(ctx, (void**)&ix->vs, sizeof(double) * M));
+    HIP_OK(dev_malloc(ctx, (void**)&ix->perm, sizeof(uint32_t) * M));
     double* xsd[3] = {ix->xs[0], ix->xs[1], ix->xs[2]};
     HIP_OK(launch_cells_sorted(D, M, svals, xc, c->volume, xsd, ix->vs, ix->perm, s));
     // 4. work items: runs of at most kCellsPerItem cells of one bucket, a
@@ -1819,21 +1897,11 @@ fla_status cell_index_build(fla_ctx* ctx, const fla_cells* c, int32_t per_bucket
     HIP_OK(hipMemcpyAsync(cs.data(), cstart, sizeof(uint32_t) * cs.size(), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     std::vector<int4> work;
-    for (int64_t b = 0; b < nbk; ++b) {
-        const int n = (int)(cs[b + 1] - cs[b]);
-        if (n == 0) continue;
-        const int items = (n + kCellsPerItem - 1) / kCellsPerItem;
-        const int base = n / items, rem = n % items;
-        int first = (int)cs[b];
-        for (int k = 0; k < items; ++k) {
-            const int cnt = base + (k < rem ? 1 : 0);
-            work.push_back(make_int4((int)b, first, cnt, 0));
-            first += cnt;
-        }
-    }
+    for (const host::WorkItem& w : host::work_items(cs.data(), nbk, kCellsPerItem))
+        work.push_back(make_int4(w.bucket, w.first, w.count, 0));
     CHECK_ARG(work.size() < (size_t)(1 << 29), "too many gather work items");
     ix->nwork = (int)work.size();
-    HIP_OK(hipMalloc((void**)&ix->work, sizeof(int4) * std::max<size_t>(work.size(), 1)));
+    HIP_OK(dev_malloc(ctx, (void**)&ix->work, sizeof(int4) * std::max<size_t>(work.size(), 1)));
     HIP_OK(hipMemcpy(ix->work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
     HIP_OK(hipDeviceSynchronize());
     ix->g = g;
@@ -1926,45 +1994,49 @@ extern "C" {
 FLA_EXPORT fla_status fla_cell_index_create(fla_ctx* ctx, const fla_cells* cells, int32_t cells_per_bucket,
                                             fla_cell_index** out)
 {
-    if (!ctx) return FLA_ERR_INVALID_ARG;
-    ctx->err.clear();
-    CHECK_ARG(out != nullptr, "out is NULL");
-    *out = nullptr;
-    CHECK_ARG(cells != nullptr, "cells is NULL");
-    CHECK_ARG(cells->dim == 2 || cells->dim == 3, "cells.dim must be 2 or 3");
-    CHECK_ARG(cells->count >= 1 && cells->count < (int64_t(1) << 31), "cells.count must be in [1, 2^31)");
-    for (int a = 0; a < cells->dim; ++a) {
-        CHECK_ARG(is_fin(cells->lo[a]) && is_fin(cells->hi[a]) && cells->hi[a] > cells->lo[a] &&
-                      is_fin(cells->hi[a] - cells->lo[a]),
-                  "cells box: lo and hi must be finite with hi > lo");
-        CHECK_ARG(cells->centroid[a] != nullptr, "cells.centroid[a] is NULL for an axis a < dim");
-    }
-    const int32_t per = cells_per_bucket <= 0 ? kDefaultCellsPerBucket : std::min(cells_per_bucket, 1 << 20);
-    fla_cell_index* ix = new (std::nothrow) fla_cell_index();
-    if (!ix) {
-        ctx->err = "host allocation failed";
-        return FLA_ERR_OUT_OF_MEMORY;
-    }
-    ix->device = ctx->device;
-    fla_status st;
-    try {
-        hipError_t e = hipSetDevice(ctx->device);
-        if (e != hipSuccess) {
-            ctx->err = std::string("hipSetDevice: ") + hipGetErrorString(e);
-            st = FLA_ERR_DEVICE;
-        } else {
-            st = cell_index_build(ctx, cells, per, ix);
+    TraceCall tc(ctx, "fla_cell_index_create");
+    if (g_trace) tc.what = (cells ? "cells=" + std::to_string(cells->count) : std::string("cells=NULL"));
+    return tc.done([&]() -> fla_status {
+        if (!ctx) return FLA_ERR_INVALID_ARG;
+        ctx->err.clear();
+        CHECK_ARG(out != nullptr, "out is NULL");
+        *out = nullptr;
+        CHECK_ARG(cells != nullptr, "cells is NULL");
+        CHECK_ARG(cells->dim == 2 || cells->dim == 3, "cells.dim must be 2 or 3");
+        CHECK_ARG(cells->count >= 1 && cells->count < (int64_t(1) << 31), "cells.count must be in [1, 2^31)");
+        for (int a = 0; a < cells->dim; ++a) {
+            CHECK_ARG(is_fin(cells->lo[a]) && is_fin(cells->hi[a]) && cells->hi[a] > cells->lo[a] &&
+                          is_fin(cells->hi[a] - cells->lo[a]),
+                      "cells box: lo and hi must be finite with hi > lo");
+            CHECK_ARG(cells->centroid[a] != nullptr, "cells.centroid[a] is NULL for an axis a < dim");
         }
-    } catch (...) {
-        ctx->err = "internal error";
-        st = FLA_ERR_DEVICE;
-    }
-    if (st != FLA_OK) {
-        free_index(ix);
-        return st;
-    }
-    *out = ix;
-    return FLA_OK;
+        const int32_t per = cells_per_bucket <= 0 ? kDefaultCellsPerBucket : std::min(cells_per_bucket, 1 << 20);
+        fla_cell_index* ix = new (std::nothrow) fla_cell_index();
+        if (!ix) {
+            ctx->err = "host allocation failed";
+            return FLA_ERR_OUT_OF_MEMORY;
+        }
+        ix->device = ctx->device;
+        fla_status st;
+        try {
+            hipError_t e = hipSetDevice(ctx->device);
+            if (e != hipSuccess) {
+                ctx->err = std::string("hipSetDevice: ") + hipGetErrorString(e);
+                st = FLA_ERR_DEVICE;
+            } else {
+                st = cell_index_build(ctx, cells, per, ix);
+            }
+        } catch (...) {
+            ctx->err = "internal error";
+            st = FLA_ERR_DEVICE;
+        }
+        if (st != FLA_OK) {
+            free_index(ix);
+            return st;
+        }
+        *out = ix;
+        return FLA_OK;
+    }());
 }
 
 FLA_EXPORT fla_status fla_cell_index_destroy(fla_cell_index* index)
@@ -1988,49 +2060,53 @@ FLA_EXPORT fla_status fla_project_cells(fla_ctx* ctx, const fla_cell_index* inde
                                         const fla_params* params, const fla_injection* inj, const fla_fields* out,
                                         void* stream)
 {
-    if (!ctx) return FLA_ERR_INVALID_ARG;
-    ctx->err.clear();
-    try {
-        CHECK_ARG(index != nullptr, "index is NULL");
-        CHECK_ARG(index->device == ctx->device, "the index was built on another device");
-        const int D = index->dim;
-        TrajDev t;
-        fla_status st = check_traj(ctx, traj, D, true, &t);
-        if (st != FLA_OK) return st;
-        st = check_params(ctx, params, true);
-        if (st != FLA_OK) return st;
-        CHECK_ARG(params->mode == FLA_NW, "fla_project_cells supports FLA_NW only");
-        st = check_fields(ctx, out, D);
-        if (st != FLA_OK) return st;
-        double kinj = 1.0;
-        if (inj) {
-            CHECK_ARG(is_fin(inj->n_ref) && inj->n_ref > 0.0 && is_fin(inj->tau_ref) && inj->tau_ref > 0.0 &&
-                          is_fin(inj->area) && inj->area > 0.0 && is_fin(inj->v_inj) && inj->v_inj > 0.0,
-                      "injection parameters must be positive and finite");
-            CHECK_ARG(index->vs != nullptr, "n_hat needs cell volumes: the index was built without them");
-            kinj = inj->n_ref / (inj->area * inj->v_inj * inj->tau_ref);
-            CHECK_ARG(is_fin(kinj) && is_fin(kinj * params->scale), "n_hat per unit volume is not finite");
+    TraceCall tc(ctx, "fla_project_cells");
+    if (g_trace) tc.what = (index ? "cells=" + std::to_string(index->M) : std::string("index=NULL")) + " " + traj_desc(traj);
+    return tc.done([&]() -> fla_status {
+        if (!ctx) return FLA_ERR_INVALID_ARG;
+        ctx->err.clear();
+        try {
+            CHECK_ARG(index != nullptr, "index is NULL");
+            CHECK_ARG(index->device == ctx->device, "the index was built on another device");
+            const int D = index->dim;
+            TrajDev t;
+            fla_status st = check_traj(ctx, traj, D, true, &t);
+            if (st != FLA_OK) return st;
+            st = check_params(ctx, params, true);
+            if (st != FLA_OK) return st;
+            CHECK_ARG(params->mode == FLA_NW, "fla_project_cells supports FLA_NW only");
+            st = check_fields(ctx, out, D);
+            if (st != FLA_OK) return st;
+            double kinj = 1.0;
+            if (inj) {
+                CHECK_ARG(is_fin(inj->n_ref) && inj->n_ref > 0.0 && is_fin(inj->tau_ref) && inj->tau_ref > 0.0 &&
+                              is_fin(inj->area) && inj->area > 0.0 && is_fin(inj->v_inj) && inj->v_inj > 0.0,
+                          "injection parameters must be positive and finite");
+                CHECK_ARG(index->vs != nullptr, "n_hat needs cell volumes: the index was built without them");
+                kinj = inj->n_ref / (inj->area * inj->v_inj * inj->tau_ref);
+                CHECK_ARG(is_fin(kinj) && is_fin(kinj * params->scale), "n_hat per unit volume is not finite");
+            }
+            HIP_OK(hipSetDevice(ctx->device));
+            hipStream_t s = (hipStream_t)stream;
+            const bool f64 = traj->prec == FLA_F64;
+            if (t.count == 0) {
+                // no trajectory: every cell has den = 0 and S = 0
+                MeshDev m{};
+                m.dim = D;
+                m.M = index->M;
+                HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
+                return f64 ? zero_outputs<double>(ctx, m, out, s) : zero_outputs<float>(ctx, m, out, s);
+            }
+            if (D == 2)
+                return f64 ? project_cells_impl<double, 2>(ctx, index, t, params, kinj, inj != nullptr, out, s)
+                           : project_cells_impl<float, 2>(ctx, index, t, params, kinj, inj != nullptr, out, s);
+            return f64 ? project_cells_impl<double, 3>(ctx, index, t, params, kinj, inj != nullptr, out, s)
+                       : project_cells_impl<float, 3>(ctx, index, t, params, kinj, inj != nullptr, out, s);
+        } catch (...) {
+            ctx->err = "internal error";
+            return FLA_ERR_DEVICE;
         }
-        HIP_OK(hipSetDevice(ctx->device));
-        hipStream_t s = (hipStream_t)stream;
-        const bool f64 = traj->prec == FLA_F64;
-        if (t.count == 0) {
-            // no trajectory: every cell has den = 0 and S = 0
-            MeshDev m{};
-            m.dim = D;
-            m.M = index->M;
-            HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
-            return f64 ? zero_outputs<double>(ctx, m, out, s) : zero_outputs<float>(ctx, m, out, s);
-        }
-        if (D == 2)
-            return f64 ? project_cells_impl<double, 2>(ctx, index, t, params, kinj, inj != nullptr, out, s)
-                       : project_cells_impl<float, 2>(ctx, index, t, params, kinj, inj != nullptr, out, s);
-        return f64 ? project_cells_impl<double, 3>(ctx, index, t, params, kinj, inj != nullptr, out, s)
-                   : project_cells_impl<float, 3>(ctx, index, t, params, kinj, inj != nullptr, out, s);
-    } catch (...) {
-        ctx->err = "internal error";
-        return FLA_ERR_DEVICE;
-    }
+    }());
 }
 
 }  // extern "C"

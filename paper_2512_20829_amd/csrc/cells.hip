@@ -70,7 +70,7 @@ hipError_t launch_cells_hist(int dim, int64_t M, const double* const* xc, const 
 {
     if (M == 0) return hipSuccess;
     const int64_t blocks = (M + 255) / 256;
-    hipLaunchKernelGGL(k_cells_hist, dim3((unsigned)blocks), dim3(256), 0, s, dim, M, xc[0], xc[1],
+    FLA_LAUNCH(k_cells_hist, dim3((unsigned)blocks), dim3(256), 0, s, dim, M, xc[0], xc[1],
                        dim == 3 ? xc[2] : xc[0], lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], hist, bad, vol);
     return hipGetLastError();
 }
@@ -96,7 +96,7 @@ hipError_t launch_cells_key(const CellGridDev& g, int64_t M, const double* const
 {
     if (M == 0) return hipSuccess;
     const int64_t blocks = (M + 255) / 256;
-    hipLaunchKernelGGL(k_cells_key, dim3((unsigned)blocks), dim3(256), 0, s, g, M, xc[0], xc[1],
+    FLA_LAUNCH(k_cells_key, dim3((unsigned)blocks), dim3(256), 0, s, g, M, xc[0], xc[1],
                        g.dim == 3 ? xc[2] : xc[0], keys, vals);
     return hipGetLastError();
 }
@@ -121,7 +121,7 @@ hipError_t launch_cells_sorted(int dim, int64_t M, const uint32_t* order, const 
 {
     if (M == 0) return hipSuccess;
     const int64_t blocks = (M + 255) / 256;
-    hipLaunchKernelGGL(k_cells_sorted, dim3((unsigned)blocks), dim3(256), 0, s, dim, M, order, xc[0], xc[1],
+    FLA_LAUNCH(k_cells_sorted, dim3((unsigned)blocks), dim3(256), 0, s, dim, M, order, xc[0], xc[1],
                        dim == 3 ? xc[2] : xc[0], vol, xs[0], xs[1], dim == 3 ? xs[2] : xs[0], vs, perm);
     return hipGetLastError();
 }
@@ -210,7 +210,7 @@ hipError_t launch_cells_prepass(const TrajDev& t, const CellGridDev& g, const Ph
     if (t.count == 0) return hipSuccess;
     const int64_t per = 256 * kCellsPrepassPerThread;
     const int64_t blocks = (t.count + per - 1) / per;
-    hipLaunchKernelGGL((k_cells_prepass<R, D>), dim3((unsigned)blocks), dim3(256), 0, s, t, g, ph, hfac, keys, vals,
+    FLA_LAUNCH((k_cells_prepass<R, D>), dim3((unsigned)blocks), dim3(256), 0, s, t, g, ph, hfac, keys, vals,
                        rpos, rw, stats);
     return hipGetLastError();
 }
@@ -502,9 +502,9 @@ hipError_t launch_cells_gather(const CellsGatherArgs& a, bool count, hipStream_t
     constexpr int kWavesPerBlock = 4;
     const int blocks = (a.nwork + kWavesPerBlock - 1) / kWavesPerBlock;
     if (count)
-        hipLaunchKernelGGL((k_cells_gather<R, D, true>), dim3(blocks), dim3(kWave * kWavesPerBlock), 0, s, a);
+        FLA_LAUNCH((k_cells_gather<R, D, true>), dim3(blocks), dim3(kWave * kWavesPerBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((k_cells_gather<R, D, false>), dim3(blocks), dim3(kWave * kWavesPerBlock), 0, s, a);
+        FLA_LAUNCH((k_cells_gather<R, D, false>), dim3(blocks), dim3(kWave * kWavesPerBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -909,10 +909,10 @@ template <typename R, int D, int MODE, bool COUNT>
 static void launch_plan(const GatherArgs& g, int plan, dim3 grid, dim3 block, hipStream_t s)
 {
     switch (plan) {
-    case 1: hipLaunchKernelGGL((k_gather<R, D, MODE, COUNT, 1>), grid, block, 0, s, g); break;
-    case 2: hipLaunchKernelGGL((k_gather<R, D, MODE, COUNT, 2>), grid, block, 0, s, g); break;
-    case 3: hipLaunchKernelGGL((k_gather<R, D, MODE, COUNT, 3>), grid, block, 0, s, g); break;
-    default: hipLaunchKernelGGL((k_gather<R, D, MODE, COUNT, 0>), grid, block, 0, s, g); break;
+    case 1: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 1>), grid, block, 0, s, g); break;
+    case 2: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 2>), grid, block, 0, s, g); break;
+    case 3: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 3>), grid, block, 0, s, g); break;
+    default: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 0>), grid, block, 0, s, g); break;
     }
 }
 
@@ -921,10 +921,10 @@ static void launch_batch_plan(const BatchItem* items, int nsnap, int nwork, int 
 {
     dim3 grid((unsigned)(nwork * TileParts<D>::value)), block(kWave * GatherWaves<D>::value);
     switch (plan) {
-    case 1: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 1>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
-    case 2: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 2>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
-    case 3: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 3>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
-    default: hipLaunchKernelGGL((k_gather_batch<R, D, FLA_NW, COUNT, 0>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    case 1: FLA_LAUNCH((k_gather_batch<R, D, FLA_NW, COUNT, 1>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    case 2: FLA_LAUNCH((k_gather_batch<R, D, FLA_NW, COUNT, 2>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    case 3: FLA_LAUNCH((k_gather_batch<R, D, FLA_NW, COUNT, 3>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    default: FLA_LAUNCH((k_gather_batch<R, D, FLA_NW, COUNT, 0>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
     }
 }
 
@@ -945,8 +945,8 @@ hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hi
 {
     if (g.m.ntiles <= 0) return hipSuccess;
     if (g.order) {
-        hipLaunchKernelGGL(k_tile_cost<D>, dim3((unsigned)((g.m.ntiles + 3) / 4)), dim3(256), 0, s, g);
-        hipLaunchKernelGGL(k_tile_order, dim3(kXcds), dim3(1024), 0, s, (const uint32_t*)g.tile_cost,
+        FLA_LAUNCH(k_tile_cost<D>, dim3((unsigned)((g.m.ntiles + 3) / 4)), dim3(256), 0, s, g);
+        FLA_LAUNCH(k_tile_order, dim3(kXcds), dim3(1024), 0, s, (const uint32_t*)g.tile_cost,
                            g.m.ntiles * TileParts<D>::value, TileParts<D>::value, g.order);
     }
     dim3 grid((unsigned)(g.m.ntiles * TileParts<D>::value)), block(kWave * GatherWaves<D>::value);

@@ -51,6 +51,17 @@ struct PhysDev {
     double rho_d, mu, delta, h0, cutoff, scale;
 };
 
+// Launch log: when g_trace is nonzero (FLA_TRACE set in the environment
+// when a context is created) every kernel launch is reported on stderr with
+// its grid, block, LDS bytes and stream before it is enqueued.
+extern int g_trace;
+void trace_launch(const char* kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s);
+#define FLA_LAUNCH(kern, grid, block, lds, stream, ...)                                           \
+    do {                                                                                          \
+        if (::flp::g_trace) ::flp::trace_launch(#kern, dim3(grid), dim3(block), (size_t)(lds), (stream)); \
+        hipLaunchKernelGGL(kern, grid, block, lds, stream, __VA_ARGS__);                          \
+    } while (0)
+
 // statistics slots (device int64 array)
 enum StatSlot { ST_TRAJ = 0, ST_SKIPPED, ST_NOSUPPORT, ST_PAIRS, ST_OUTSIDE, ST_ZERO, ST_MAXCLASS, ST_N };
 

@@ -364,14 +364,14 @@ hipError_t launch_feat_moments(const float* fraw, int64_t N, int pass, const dou
     if (N <= 0) return hipSuccess;
     int nb = (int)((N + 255) / 256);
     if (nb > kMomBlocks) nb = kMomBlocks;
-    hipLaunchKernelGGL(k_feat_moments, dim3(nb), dim3(256), 0, s, fraw, N, pass, acc0, part);
-    hipLaunchKernelGGL(k_feat_accum, dim3(1), dim3(64), 0, s, part, nb, acc);
+    FLA_LAUNCH(k_feat_moments, dim3(nb), dim3(256), 0, s, fraw, N, pass, acc0, part);
+    FLA_LAUNCH(k_feat_accum, dim3(1), dim3(64), 0, s, part, nb, acc);
     return hipGetLastError();
 }
 
 hipError_t launch_feat_finish(const double* acc0, const double* acc1, float* theta, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_feat_finish, dim3(1), dim3(64), 0, s, acc0, acc1, theta);
+    FLA_LAUNCH(k_feat_finish, dim3(1), dim3(64), 0, s, acc0, acc1, theta);
     return hipGetLastError();
 }
 
@@ -789,10 +789,10 @@ hipError_t launch_bandwidth_forward(const TrajDev& t, const MeshDev& m, const fl
     hipError_t e = launch_fill_u32(cnt, m.M, 0u, s);
     if (e != hipSuccess || t.count == 0) return e;
     unsigned g = (unsigned)((t.count + 255) / 256);
-    hipLaunchKernelGGL((k_home_count<R, D>), dim3(g), dim3(256), 0, s, t, m, cnt);
+    FLA_LAUNCH((k_home_count<R, D>), dim3(g), dim3(256), 0, s, t, m, cnt);
     int64_t groups = (t.count + kWave * kMlpWaves - 1) / (kWave * kMlpWaves);
     unsigned gb = (unsigned)(groups < 2048 ? groups : 2048);
-    hipLaunchKernelGGL((k_features_mlp<R, D>), dim3(gb), dim3(kWave * kMlpWaves), 0, s, t, m, theta, cnt, hfac, z, o, fraw);
+    FLA_LAUNCH((k_features_mlp<R, D>), dim3(gb), dim3(kWave * kMlpWaves), 0, s, t, m, theta, cnt, hfac, z, o, fraw);
     return hipGetLastError();
 }
 
@@ -804,10 +804,10 @@ hipError_t launch_traj_backward(const MeshDev& m, double cutoff, const uint32_t*
 {
     unsigned g = (unsigned)((m.M + 255) / 256);
     float4* b4 = reinterpret_cast<float4*>(bcells);
-    hipLaunchKernelGGL((k_cell_grad<R>), dim3(g), dim3(256), 0, s, D + 1, m.M, S, den, dLdS, scale, cell_scale, b4,
+    FLA_LAUNCH((k_cell_grad<R>), dim3(g), dim3(256), 0, s, D + 1, m.M, S, den, dLdS, scale, cell_scale, b4,
                        eplane);
     if (N > 0)
-        hipLaunchKernelGGL((k_traj_backward<R, D>), dim3((unsigned)N), dim3(64), 0, s, m, cutoff, keys, sentinel, rpos, rw,
+        FLA_LAUNCH((k_traj_backward<R, D>), dim3((unsigned)N), dim3(64), 0, s, m, cutoff, keys, sentinel, rpos, rw,
                            (const float4*)b4, eplane, out, N);
     return hipGetLastError();
 }
@@ -822,15 +822,15 @@ template <int D>
 hipError_t launch_mlp_backward(const float* theta, int64_t N, const float* z, const float* o, const float* dlogh,
                                float* partial, int nblocks, float* grad, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_mlp_backward<D>), dim3(nblocks), dim3(kWave * kBwdWaves), 0, s, theta, N, z, o, dlogh, partial);
-    hipLaunchKernelGGL(k_grad_reduce, dim3((kParams + 255) / 256), dim3(256), 0, s, partial, nblocks, grad);
+    FLA_LAUNCH((k_mlp_backward<D>), dim3(nblocks), dim3(kWave * kBwdWaves), 0, s, theta, N, z, o, dlogh, partial);
+    FLA_LAUNCH(k_grad_reduce, dim3((kParams + 255) / 256), dim3(256), 0, s, partial, nblocks, grad);
     return hipGetLastError();
 }
 
 hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int64_t step, double lr, double b1,
                        double b2, double eps, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adam, dim3((kTrain + 255) / 256), dim3(256), 0, s, theta, m, v, grad, (double)step, lr, b1, b2, eps);
+    FLA_LAUNCH(k_adam, dim3((kTrain + 255) / 256), dim3(256), 0, s, theta, m, v, grad, (double)step, lr, b1, b2, eps);
     return hipGetLastError();
 }
 
@@ -838,11 +838,11 @@ template <typename R>
 hipError_t launch_loss(int C, int64_t M, Planes S, Planes Rf, MutPlanes G, bool want_grad, double* part, double* res,
                        hipStream_t s)
 {
-    hipLaunchKernelGGL((k_loss_partial<R>), dim3(kLossBlocks), dim3(256), 0, s, C, M, S, Rf, part);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, C, part, kLossBlocks, res);
+    FLA_LAUNCH((k_loss_partial<R>), dim3(kLossBlocks), dim3(256), 0, s, C, M, S, Rf, part);
+    FLA_LAUNCH(k_loss_final, dim3(1), dim3(64), 0, s, C, part, kLossBlocks, res);
     if (want_grad) {
         unsigned g = (unsigned)((M + 255) / 256);
-        hipLaunchKernelGGL((k_loss_grad<R>), dim3(g), dim3(256), 0, s, C, M, S, Rf, res, G);
+        FLA_LAUNCH((k_loss_grad<R>), dim3(g), dim3(256), 0, s, C, M, S, Rf, res, G);
     }
     return hipGetLastError();
 }

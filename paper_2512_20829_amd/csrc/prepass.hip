@@ -319,7 +319,7 @@ hipError_t launch_prepass(const TrajDev& t, const MeshDev& m, const PhysDev& ph,
     if (t.count == 0) return hipSuccess;
     const int64_t per_block = 256 * kPrepassPerThread;
     unsigned nb = (unsigned)((t.count + per_block - 1) / per_block);
-    hipLaunchKernelGGL((k_prepass<R, D>), dim3(nb), dim3(256), 0, s, t, m, ph, hfac, deposit, keys, vals,
+    FLA_LAUNCH((k_prepass<R, D>), dim3(nb), dim3(256), 0, s, t, m, ph, hfac, deposit, keys, vals,
                        rpos, rw, qd, stats);
     return hipGetLastError();
 }
@@ -328,20 +328,20 @@ hipError_t launch_bucket_bounds(const uint32_t* keys, int64_t n, uint32_t nb, ui
                                 hipStream_t s)
 {
     unsigned g = (unsigned)(((int64_t)nb + 1 + 255) / 256);
-    hipLaunchKernelGGL(k_bucket_bounds, dim3(g), dim3(256), 0, s, keys, n, nb, bstart);
+    FLA_LAUNCH(k_bucket_bounds, dim3(g), dim3(256), 0, s, keys, n, nb, bstart);
     return hipGetLastError();
 }
 
 hipError_t launch_max_class(const uint32_t* bstart, int ntiles, unsigned long long* stats, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_max_class, dim3(1), dim3(64), 0, s, bstart, ntiles, stats);
+    FLA_LAUNCH(k_max_class, dim3(1), dim3(64), 0, s, bstart, ntiles, stats);
     return hipGetLastError();
 }
 
 hipError_t launch_max_class_batch(const BatchItem* items, int nsnap, const uint32_t* bstart,
                                   unsigned long long* stats, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_max_class_batch, dim3(1), dim3(kWave), 0, s, items, nsnap, bstart, stats);
+    FLA_LAUNCH(k_max_class_batch, dim3(1), dim3(kWave), 0, s, items, nsnap, bstart, stats);
     return hipGetLastError();
 }
 
@@ -351,7 +351,7 @@ hipError_t launch_permute(const uint32_t* order, int64_t n, const double4* rpos_
 {
     if (n == 0) return hipSuccess;
     unsigned g = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL((k_permute<R>), dim3(g), dim3(256), 0, s, order, n, rpos_u, rw_u, rpos, rw, copy_w);
+    FLA_LAUNCH((k_permute<R>), dim3(g), dim3(256), 0, s, order, n, rpos_u, rw_u, rpos, rw, copy_w);
     return hipGetLastError();
 }
 
@@ -363,7 +363,7 @@ hipError_t launch_deposit_norm(const MeshDev& m, const PhysDev& ph, const uint32
     if (N == 0) return hipSuccess;
     const int64_t want = (N + kNormWaves - 1) / kNormWaves;
     const unsigned grid = (unsigned)(want < 8192 ? want : 8192);
-    hipLaunchKernelGGL((k_deposit_norm<R, D>), dim3(grid), dim3(kWave * kNormWaves), 0, s, m, ph, nvalid, order,
+    FLA_LAUNCH((k_deposit_norm<R, D>), dim3(grid), dim3(kWave * kNormWaves), 0, s, m, ph, nvalid, order,
                        qd, N, rpos, rw, stats);
     return hipGetLastError();
 }
@@ -375,7 +375,7 @@ hipError_t launch_prepass_batch(const BatchItem* items, int nsnap, int64_t total
     if (total == 0) return hipSuccess;
     const int64_t per_block = 256 * kPrepassPerThread;
     unsigned nb = (unsigned)((total + per_block - 1) / per_block);
-    hipLaunchKernelGGL((k_prepass_batch<R, D>), dim3(nb), dim3(256), 0, s, items, nsnap, total, sentinel, keys, vals,
+    FLA_LAUNCH((k_prepass_batch<R, D>), dim3(nb), dim3(256), 0, s, items, nsnap, total, sentinel, keys, vals,
                        rpos, rw, stats);
     return hipGetLastError();
 }

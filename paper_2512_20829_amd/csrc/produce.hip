@@ -204,7 +204,7 @@ hipError_t launch_produce(const ProduceArgs& p, const MeshDev& m, const PhysDev&
 {
     if (p.count <= 0) return hipSuccess;
     const unsigned g = (unsigned)((p.count + 255) / 256);
-    hipLaunchKernelGGL((k_produce<R, D>), dim3(g), dim3(256), 0, s, p, m, ph, hfac, deposit, keys, vals, rpos, rw, qd,
+    FLA_LAUNCH((k_produce<R, D>), dim3(g), dim3(256), 0, s, p, m, ph, hfac, deposit, keys, vals, rpos, rw, qd,
                        stats);
     return hipGetLastError();
 }

@@ -827,16 +827,16 @@ hipError_t launch_cic(const PsiArgs& a, hipStream_t s)
         e = launch_fill_u64(a.blockmax, (int64_t)a.nblocks * 4, 0ull, s);
         if (e != hipSuccess) return e;
     } else {
-        hipLaunchKernelGGL((k_cic_count<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
+        FLA_LAUNCH((k_cic_count<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
         e = launch_exclusive_scan_u32(a.blockhist, (int64_t)a.pntiles * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_cic_scatter<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
+        FLA_LAUNCH((k_cic_scatter<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
     }
-    hipLaunchKernelGGL((k_psi_scale<D>), dim3(1), dim3(256), 0, s, a);
+    FLA_LAUNCH((k_psi_scale<D>), dim3(1), dim3(256), 0, s, a);
     const int hcells = (a.pt[0] + 1) * (a.pt[1] + 1) * (D == 3 ? a.pt[2] + 1 : 1);
     const size_t lds_r = sizeof(unsigned long long) * (size_t)(W * C + 1) * (size_t)hcells;
-    hipLaunchKernelGGL((k_cic_reduce<R, D>), dim3(a.pntiles), dim3(256), lds_r, s, a);
-    hipLaunchKernelGGL((k_cic_finish<R, D>), dim3((unsigned)((a.m.M + 255) / 256)), dim3(256), 0, s, a);
+    FLA_LAUNCH((k_cic_reduce<R, D>), dim3(a.pntiles), dim3(256), lds_r, s, a);
+    FLA_LAUNCH((k_cic_finish<R, D>), dim3((unsigned)((a.m.M + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -873,20 +873,20 @@ static unsigned grid_for(int64_t n)
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    FLA_LAUNCH(k_fill_u64, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    FLA_LAUNCH(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 template <typename R>
 hipError_t launch_fill_real(R* p, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_fill_real<R>), dim3(grid_for(n)), dim3(256), 0, s, p, n);
+    FLA_LAUNCH((k_fill_real<R>), dim3(grid_for(n)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 template hipError_t launch_fill_real<float>(float*, int64_t, hipStream_t);
@@ -904,18 +904,18 @@ hipError_t launch_psicell(const PsiArgs& a, hipStream_t s)
         if (e != hipSuccess) return e;
     } else {
         size_t lds_t = sizeof(unsigned int) * (size_t)a.pntiles;
-        hipLaunchKernelGGL((k_psi_count<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
+        FLA_LAUNCH((k_psi_count<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
         e = launch_exclusive_scan_u32(a.blockhist, (int64_t)a.pntiles * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
         if (e != hipSuccess) return e;
         e = launch_exclusive_scan_u32(a.binhist, (int64_t)a.pnbins * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_psi_scatter<R, D>), dim3(a.nblocks), dim3(256), 0, s, a);
+        FLA_LAUNCH((k_psi_scatter<R, D>), dim3(a.nblocks), dim3(256), 0, s, a);
     }
-    hipLaunchKernelGGL((k_psi_scale<D>), dim3(1), dim3(256), 0, s, a);
+    FLA_LAUNCH((k_psi_scale<D>), dim3(1), dim3(256), 0, s, a);
     if (a.p.count > 0)
-        hipLaunchKernelGGL((k_psi_tiles<R, D>), dim3(a.pnbins * a.nsplit), dim3(256), 0, s, a);
+        FLA_LAUNCH((k_psi_tiles<R, D>), dim3(a.pnbins * a.nsplit), dim3(256), 0, s, a);
     size_t lds_r = (sizeof(unsigned long long) * C * PsiWords<R>::value + sizeof(unsigned int)) * (size_t)a.cpt;
-    hipLaunchKernelGGL((k_psi_reduce<R, D>), dim3(a.pntiles), dim3(256), lds_r, s, a);
+    FLA_LAUNCH((k_psi_reduce<R, D>), dim3(a.pntiles), dim3(256), lds_r, s, a);
     return hipGetLastError();
 }
 

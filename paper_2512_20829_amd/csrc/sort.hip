@@ -72,11 +72,11 @@ hipError_t launch_exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* tmp, i
     if (n <= 0) return hipSuccess;
     int64_t nb = (n + kScanBlock - 1) / kScanBlock;
     if (nb + 1 > tmp_words) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp);
+    FLA_LAUNCH(k_scan_block, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp);
     if (nb > 1) {
         hipError_t e = launch_exclusive_scan_u32(tmp, nb, tmp + nb + 1, tmp_words - nb - 1, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp);
+        FLA_LAUNCH(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp);
     }
     return hipGetLastError();
 }
@@ -167,12 +167,12 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, 
     if ((int64_t)nblocks * kDigits > hist_words) return hipErrorInvalidValue;
     uint32_t *ka = keys, *va = vals, *kb = keys_alt, *vb = vals_alt;
     for (int shift = 0; shift < key_bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, s, ka, n, shift, hist,
+        FLA_LAUNCH(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, s, ka, n, shift, hist,
                            nblocks);
         hipError_t e = launch_exclusive_scan_u32(hist, (int64_t)nblocks * kDigits, scan_tmp,
                                                  scan_tmp_words_, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, ka, va, n, shift,
+        FLA_LAUNCH(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, ka, va, n, shift,
                            hist, nblocks, kb, vb);
         uint32_t* tk = ka; ka = kb; kb = tk;
         uint32_t* tv = va; va = vb; vb = tv;
