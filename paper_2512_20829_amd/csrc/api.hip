@@ -798,16 +798,19 @@ fla_status bandwidth_forward_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev&
                                   float* z, float* o, float* fraw, hipStream_t s)
 {
     unsigned int* cnt;
+    uint4* zb;
     {
         Carver probe(nullptr);
         probe.take<unsigned int>(m.M);
+        probe.take<uint4>(t.count > 0 ? t.count : 1);
         fla_status st = ensure_ws(ctx, probe.off + 256);
         if (st != FLA_OK) return st;
     }
     Carver c(ctx->ws);
     cnt = c.take<unsigned int>(m.M);
+    zb = c.take<uint4>(t.count > 0 ? t.count : 1);
     StageTimer tm(ctx, 5, s);
-    HIP_OK((launch_bandwidth_forward<R, D>(t, m, theta, cnt, hfac, z, o, fraw, s)));
+    HIP_OK((launch_bandwidth_forward<R, D>(t, m, theta, cnt, zb, hfac, z, o, fraw, s)));
     return FLA_OK;
 }
 

@@ -37,10 +37,18 @@ __device__ inline unsigned short bf16_bits(float f)
 __device__ inline float bf16_val(unsigned short b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ inline float round_bf16(float f) { return bf16_val(bf16_bits(f)); }
 
-__device__ inline float silu_f(float a) { return a / (1.0f + expf(-a)); }
+// Logistic function from the hardware base-2 exponential and reciprocal
+// (each within about one binary32 ulp; the activations are rounded to bf16
+// for the next layer, 2^-8 relative, so the difference from the correctly
+// rounded form is immaterial).
+__device__ inline float sigmoid_f(float a)
+{
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(a * -1.44269504088896340736f));
+}
+__device__ inline float silu_f(float a) { return a * sigmoid_f(a); }
 __device__ inline float dsilu_f(float a)
 {
-    float s = 1.0f / (1.0f + expf(-a));
+    const float s = sigmoid_f(a);
     return s * (1.0f + a * (1.0f - s));
 }
 
@@ -94,8 +102,13 @@ __device__ inline bool load_terms(const TrajDev& t, int64_t i, double* x, double
 }
 
 // Singular values of J (largest first) from the eigenvalues of J^T J: the
-// closed form for a symmetric 3x3 matrix (trigonometric solution of the
-// characteristic cubic), the smallest recovered as |det J| / (s1 s2).
+// closed form for a symmetric 3x3 matrix, O. K. Smith, "Eigenvalues of a
+// symmetric 3 x 3 matrix", Communications of the ACM 4(4), 168 (1961): with
+// q = tr(A)/3 and p^2 = (|A - qI|_F^2)/6, the eigenvalues are
+// q + 2p cos(phi + 2 pi k/3), phi = acos(det((A - qI)/p)/2)/3 (the
+// trigonometric solution of the characteristic cubic).  The middle one
+// comes from the trace and the smallest singular value from
+// |det J| / (s1 s2), both free of the cubic's cancellation.
 template <int D>
 __device__ inline void singular_values(const double* J, double adet, double* s)
 {
@@ -126,11 +139,12 @@ __device__ inline void singular_values(const double* J, double adet, double* s)
     } else {
         double p2 = (A[0][0] - qm) * (A[0][0] - qm) + (A[1][1] - qm) * (A[1][1] - qm) + (A[2][2] - qm) * (A[2][2] - qm) + 2.0 * p1;
         double p = sqrt(p2 / 6.0);
+        const double ip = 1.0 / p;
         double B[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) B[a][b] = (A[a][b] - (a == b ? qm : 0.0)) / p;
+            for (int b = 0; b < 3; ++b) B[a][b] = (A[a][b] - (a == b ? qm : 0.0)) * ip;
         double r = 0.5 * (B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) - B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
                           B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]));
         r = fmin(1.0, fmax(-1.0, r));
@@ -162,9 +176,15 @@ __global__ __launch_bounds__(256) void k_home_count(TrajDev t, MeshDev m, unsign
 }
 
 // ---------------------------------------------------------------- features + network
+// LDS row strides (bf16 elements) of the staged weights and of the network's
+// activation tiles: rows padded by 4 (W1, Z) and 4 (W2, H1) elements so that
+// the 16 rows an MFMA fragment reads start in different bank pairs (a
+// 16 x 64 bf16 tile with 128-byte rows puts all 16 rows in the same banks).
+constexpr int kW1S = 20;
+constexpr int kW2S = 68;
 struct MlpW {
-    unsigned short W1[kHidden][16];      // bf16, inputs padded to 16
-    unsigned short W2[kHidden][kHidden];
+    unsigned short W1[kHidden][kW1S];    // bf16, inputs padded to 16 (columns 16.. unused)
+    unsigned short W2[kHidden][kW2S];    // columns 64.. unused
     float b1[kHidden], b2[kHidden], w3[kHidden];   // w3 rounded to bf16
     float b3, mu[kFeat], sd[kFeat];
 };
@@ -192,70 +212,121 @@ __device__ inline void stage_weights(const float* th, MlpW& W)
 
 constexpr int kMlpWaves = 4;
 
-// One wave handles 64 trajectories per step: every lane forms the features of
-// one trajectory, then four 16-trajectory groups go through the network.
+// Features of one trajectory per thread: the binary64 singular values, the
+// neighbour count over the 3^D block of cells around the home cell, the
+// standardised inputs z rounded to bf16 and packed with a validity flag into
+// one 16-byte record {z0..z4, 0, 0, valid} for the network kernel.
 template <typename R, int D>
-__global__ __launch_bounds__(kWave * kMlpWaves) void k_features_mlp(TrajDev t, MeshDev m, const float* theta,
-                                                                   const unsigned int* cnt, float* hfac, float* zout,
-                                                                   float* oout, float* fraw)
+__device__ inline void feature_one(const TrajDev& t, const MeshDev& m, const float* __restrict__ theta,
+                                   const unsigned int* __restrict__ cnt, uint4* __restrict__ zb,
+                                   float* __restrict__ zout, float* __restrict__ fraw, int64_t i)
+{
+    const int64_t N = t.count;
+    float f[kFeat] = {0, 0, 0, 0, 0};
+    double x[3] = {0, 0, 0}, J[9], det;
+    const bool ok = load_terms<R, D>(t, i, x, J, det);
+    if (ok) {
+        double adet = fabs(det), s[3];
+        singular_values<D>(J, adet, s);
+        // the 3^D block of cells around the home cell (cell indices and their
+        // neighbours fit 32 bits; a neighbour is at most one period away, so
+        // wrapping is one add or subtract)
+        int hc[3] = {0, 0, 0}, cn[3][3];
+        bool cin[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a < D) hc[a] = (int)home_index(m, a, x[a]);
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                int c = hc[a] + o - 1;
+                bool in = true;
+                if (a >= D) {
+                    c = 0;
+                    in = o == 1;
+                } else if (m.periodic[a]) {
+                    c = c < 0 ? c + m.n[a] : (c >= m.n[a] ? c - m.n[a] : c);
+                } else {
+                    in = c >= 0 && c < m.n[a];
+                }
+                cn[a][o] = c;
+                cin[a][o] = in;
+            }
+        }
+        unsigned int nb = 0;
+        const int n0 = m.n[0], n01 = m.n[0] * m.n[1];
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+                    if (cin[0][dx] && cin[1][dy] && cin[2][dz]) nb += cnt[cn[0][dx] + n0 * cn[1][dy] + n01 * cn[2][dz]];
+        // binary64 features and standardisation: z is rounded to bf16 for the
+        // network, so it is formed as exactly as the oracle forms it
+        const double fd[kFeat] = {log(s[0]), log(s[1]), D == 3 ? log(s[2]) : 0.0, -log(adet), log1p((double)nb)};
+#pragma unroll
+        for (int k = 0; k < kFeat; ++k) {
+            if (fraw) fraw[(int64_t)k * N + i] = (float)fd[k];
+            f[k] = (float)((fd[k] - (double)theta[kOffMu + k]) / (double)theta[kOffSd + k]);
+        }
+    } else if (fraw) {
+#pragma unroll
+        for (int k = 0; k < kFeat; ++k) fraw[(int64_t)k * N + i] = __builtin_nanf("");
+    }
+    unsigned short zs[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) zs[k] = (k < kFeat && ok) ? bf16_bits(f[k]) : (unsigned short)0;
+    zs[7] = ok ? 1 : 0;
+    zb[i] = make_uint4(zs[0] | ((uint32_t)zs[1] << 16), zs[2] | ((uint32_t)zs[3] << 16),
+                       zs[4] | ((uint32_t)zs[5] << 16), zs[6] | ((uint32_t)zs[7] << 16));
+    if (zout)
+#pragma unroll
+        for (int k = 0; k < kFeat; ++k) zout[(int64_t)k * N + i] = ok ? round_bf16(f[k]) : 0.0f;
+}
+
+// Two trajectories per thread, blockDim apart: two independent binary64
+// chains for the scheduler to interleave.
+constexpr int kFeatPerThread = 2;
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_features(TrajDev t, MeshDev m, const float* __restrict__ theta,
+                                                  const unsigned int* __restrict__ cnt, uint4* __restrict__ zb,
+                                                  float* __restrict__ zout, float* __restrict__ fraw)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * kFeatPerThread + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kFeatPerThread; ++u) {
+        const int64_t i = i0 + (int64_t)u * blockDim.x;
+        if (i < t.count) feature_one<R, D>(t, m, theta, cnt, zb, zout, fraw, i);
+    }
+}
+
+// The 5-64-64-1 network on bf16 MFMA.  One wave takes 64 feature records
+// per step (one per lane, into LDS), then four 16-trajectory groups go
+// through the layers; the output o gives the factor exp(s_max tanh o), 1 for
+// an invalid trajectory.
+__global__ __launch_bounds__(kWave * kMlpWaves) void k_mlp(const float* __restrict__ theta, int64_t N,
+                                                            const uint4* __restrict__ zb, float* __restrict__ hfac,
+                                                            float* __restrict__ oout)
 {
     __shared__ MlpW W;
-    __shared__ unsigned short Z[kMlpWaves][kWave][16];   // [traj][feature]
-    __shared__ unsigned short H1[kMlpWaves][16][kHidden]; // [traj][hidden]
+    __shared__ __align__(16) unsigned short Z[kMlpWaves][kWave][kW1S];   // [traj][feature]
+    __shared__ __align__(16) unsigned short H1[kMlpWaves][16][kW2S];      // [traj][hidden]
     __shared__ int vld[kMlpWaves][kWave];
     stage_weights(theta, W);
     __syncthreads();
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-    const int64_t N = t.count;
     const int r16 = lane % 16, g4 = lane / 16;
     for (int64_t base = ((int64_t)blockIdx.x * kMlpWaves + wave) * kWave; base < N;
          base += (int64_t)gridDim.x * kMlpWaves * kWave) {
         const int64_t i = base + lane;
-        float f[kFeat] = {0, 0, 0, 0, 0};
-        bool ok = false;
-        if (i < N) {
-            double x[3] = {0, 0, 0}, J[9], det;
-            ok = load_terms<R, D>(t, i, x, J, det);
-            if (ok) {
-                double adet = fabs(det), s[3];
-                singular_values<D>(J, adet, s);
-                int64_t hc[3] = {0, 0, 0};
-#pragma unroll
-                for (int a = 0; a < D; ++a) hc[a] = home_index(m, a, x[a]);
-                unsigned int nb = 0;
-                for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
-                    for (int dy = -1; dy <= 1; ++dy)
-                        for (int dx = -1; dx <= 1; ++dx) {
-                            int64_t c[3] = {hc[0] + dx, hc[1] + dy, hc[2] + dz};
-                            bool in = true;
-                            int64_t lin = 0, st = 1;
-                            for (int a = 0; a < D; ++a) {
-                                if (m.periodic[a])
-                                    c[a] = posmod(c[a], m.n[a]);
-                                else if (c[a] < 0 || c[a] >= m.n[a])
-                                    in = false;
-                                lin += c[a] * st;
-                                st *= m.n[a];
-                            }
-                            if (in) nb += cnt[lin];
-                        }
-                double fd[kFeat] = {log(s[0]), log(s[1]), D == 3 ? log(s[2]) : 0.0, -log(adet), log1p((double)nb)};
-#pragma unroll
-                for (int k = 0; k < kFeat; ++k) {
-                    if (fraw) fraw[(int64_t)k * N + i] = (float)fd[k];
-                    f[k] = (float)((fd[k] - (double)W.mu[k]) / (double)W.sd[k]);
-                }
-            }
-        }
-        if (fraw && i < N && !ok)
-#pragma unroll
-            for (int k = 0; k < kFeat; ++k) fraw[(int64_t)k * N + i] = __builtin_nanf("");
-#pragma unroll
-        for (int k = 0; k < 16; ++k) Z[wave][lane][k] = (k < kFeat && ok) ? bf16_bits(f[k]) : (unsigned short)0;
-        vld[wave][lane] = ok ? 1 : 0;
-        if (zout && i < N)
-#pragma unroll
-            for (int k = 0; k < kFeat; ++k) zout[(int64_t)k * N + i] = ok ? round_bf16(f[k]) : 0.0f;
+        const uint4 q4 = i < N ? zb[i] : make_uint4(0u, 0u, 0u, 0u);
+        // features 0..4 then zeros up to 16 (the MFMA's k padding), 8-byte stores
+        uint2* zrow = reinterpret_cast<uint2*>(&Z[wave][lane][0]);
+        zrow[0] = make_uint2(q4.x, q4.y);
+        zrow[1] = make_uint2(q4.z & 0xFFFFu, 0u);
+        zrow[2] = make_uint2(0u, 0u);
+        zrow[3] = make_uint2(0u, 0u);
+        vld[wave][lane] = (q4.w >> 16) != 0u;
         wave_sync();
         for (int q = 0; q < 4; ++q) {
             // layer 1: a1^T[64 x 16] = W1[64 x 16] * Z^T[16 x 16]
@@ -783,16 +854,18 @@ __global__ void k_loss_grad(int C, int64_t M, Planes S, Planes Rf, const double*
 
 // ---------------------------------------------------------------- launchers
 template <typename R, int D>
-hipError_t launch_bandwidth_forward(const TrajDev& t, const MeshDev& m, const float* theta, unsigned int* cnt, float* hfac,
-                                    float* z, float* o, float* fraw, hipStream_t s)
+hipError_t launch_bandwidth_forward(const TrajDev& t, const MeshDev& m, const float* theta, unsigned int* cnt, void* zb,
+                                    float* hfac, float* z, float* o, float* fraw, hipStream_t s)
 {
     hipError_t e = launch_fill_u32(cnt, m.M, 0u, s);
     if (e != hipSuccess || t.count == 0) return e;
     unsigned g = (unsigned)((t.count + 255) / 256);
     FLA_LAUNCH((k_home_count<R, D>), dim3(g), dim3(256), 0, s, t, m, cnt);
+    const unsigned gf = (unsigned)((t.count + 256 * kFeatPerThread - 1) / (256 * kFeatPerThread));
+    FLA_LAUNCH((k_features<R, D>), dim3(gf), dim3(256), 0, s, t, m, theta, cnt, (uint4*)zb, z, fraw);
     int64_t groups = (t.count + kWave * kMlpWaves - 1) / (kWave * kMlpWaves);
     unsigned gb = (unsigned)(groups < 2048 ? groups : 2048);
-    FLA_LAUNCH((k_features_mlp<R, D>), dim3(gb), dim3(kWave * kMlpWaves), 0, s, t, m, theta, cnt, hfac, z, o, fraw);
+    FLA_LAUNCH(k_mlp, dim3(gb), dim3(kWave * kMlpWaves), 0, s, theta, t.count, (const uint4*)zb, hfac, o);
     return hipGetLastError();
 }
 
@@ -849,7 +922,7 @@ hipError_t launch_loss(int C, int64_t M, Planes S, Planes Rf, MutPlanes G, bool 
 
 #define FLP_LINST(R, D)                                                                                               \
     template hipError_t launch_bandwidth_forward<R, D>(const TrajDev&, const MeshDev&, const float*, unsigned int*, \
-                                                       float*, float*, float*, float*, hipStream_t);                \
+                                                       void*, float*, float*, float*, float*, hipStream_t);         \
     template hipError_t launch_traj_backward<R, D>(const MeshDev&, double, const uint32_t*, uint32_t,              \
                                                    const double4*, const R*, Planes, const void*, Planes, double,   \
                                                    const void*, float*, float*, float*, int64_t, hipStream_t);

@@ -30,8 +30,10 @@ struct MutPlanes {
 };
 
 template <typename R, int D>
-hipError_t launch_bandwidth_forward(const TrajDev& t, const MeshDev& m, const float* theta, unsigned int* cnt, float* hfac,
-                                    float* z, float* o, float* fraw, hipStream_t s);
+// features (binary64) then the network (bf16 MFMA); zb: count 16-byte
+// feature records of workspace
+hipError_t launch_bandwidth_forward(const TrajDev& t, const MeshDev& m, const float* theta, unsigned int* cnt, void* zb,
+                                    float* hfac, float* z, float* o, float* fraw, hipStream_t s);
 template <typename R, int D>
 hipError_t launch_traj_backward(const MeshDev& m, double cutoff, const uint32_t* keys, uint32_t sentinel,
                                 const double4* rpos, const R* rw, Planes S, const void* den, Planes dLdS,

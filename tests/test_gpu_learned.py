@@ -280,7 +280,14 @@ def test_learned_form_full_size(ctx):
     assert np.all(err[v] <= bound[v]), (err[v] - bound[v]).max()
     assert np.mean(err[v] > 2e-3 * (1 + np.abs(fw.o[v]))) <= 1e-4
     assert np.median(err[v]) <= 1e-5
-    np.testing.assert_allclose(hf[v], fw.g[v], rtol=4e-3)
+    # the factor g = exp(s_max tanh o) moves by s_max sech^2(o) |do| relative
+    # to itself, so the same bound carries over (plus binary32 rounding of
+    # tanh and exp)
+    smax = np.log(4.0)
+    gbound = smax * (1.0 - np.tanh(fw.o) ** 2) * bound + 1e-6
+    assert np.all(np.abs(hf[v] - fw.g[v]) <= gbound[v] * fw.g[v]), \
+        (np.abs(hf[v] - fw.g[v]) / fw.g[v] - gbound[v]).max()
+    assert np.mean(np.abs(hf[v] - fw.g[v]) > 4e-3 * fw.g[v]) <= 1e-4
     g32 = torch.tensor(fw.g, dtype=torch.float32)
     S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False, h_factor=g32)
     cells = np.sort(np.random.default_rng(2).choice(wl.mesh.cells, 256, replace=False))
