@@ -603,11 +603,11 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_mlp_backward(const float*
                                                                     const float* o, const float* dlogh, float* partial)
 {
     __shared__ MlpW W;
-    __shared__ unsigned short W2T[kHidden][kHidden];      // W2 transposed, bf16
-    __shared__ unsigned short Zs[kBwdWaves][16][16];      // [traj][feature]
-    __shared__ unsigned short H1[kBwdWaves][16][kHidden]; // [traj][hidden]
-    __shared__ unsigned short D2h[kBwdWaves][kHidden][16], D2l[kBwdWaves][kHidden][16];   // [hidden][traj]
-    __shared__ unsigned short D1h[kBwdWaves][kHidden][16], D1l[kBwdWaves][kHidden][16];
+    __shared__ unsigned short W2T[kHidden][kW2S];         // W2 transposed, bf16 (padded rows)
+    __shared__ unsigned short Zs[kBwdWaves][16][kW1S];    // [traj][feature]
+    __shared__ unsigned short H1[kBwdWaves][16][kW2S];    // [traj][hidden]
+    __shared__ unsigned short D2h[kBwdWaves][kHidden][kW1S], D2l[kBwdWaves][kHidden][kW1S];   // [hidden][traj]
+    __shared__ unsigned short D1h[kBwdWaves][kHidden][kW1S], D1l[kBwdWaves][kHidden][kW1S];
     __shared__ float dO[kBwdWaves][16];
     __shared__ float gsum[kTrain];
     stage_weights(theta, W);
@@ -686,7 +686,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_mlp_backward(const float*
             bf16x4 al = load4(&D2l[wave][16 * mt + r16][4 * g4]);
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-                bf16x4 bb = load4s(&H1[wave][4 * g4][16 * nt + r16], kHidden);
+                bf16x4 bb = load4s(&H1[wave][4 * g4][16 * nt + r16], kW2S);
                 gW2[mt][nt] = mfma16(ah, bb, gW2[mt][nt]);
                 gW2[mt][nt] = mfma16(al, bb, gW2[mt][nt]);
             }
@@ -698,8 +698,8 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_mlp_backward(const float*
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
                 bf16x4 aa = load4(&W2T[16 * mt + r16][16 * kb + 4 * g4]);
-                acc = mfma16(aa, load4s(&D2h[wave][16 * kb + 4 * g4][r16], 16), acc);
-                acc = mfma16(aa, load4s(&D2l[wave][16 * kb + 4 * g4][r16], 16), acc);
+                acc = mfma16(aa, load4s(&D2h[wave][16 * kb + 4 * g4][r16], kW1S), acc);
+                acc = mfma16(aa, load4s(&D2l[wave][16 * kb + 4 * g4][r16], kW1S), acc);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -715,7 +715,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_mlp_backward(const float*
         // gW1[out][feat] += sum_traj d1[out][traj] z[feat][traj]
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
-            bf16x4 bb = load4s(&Zs[wave][4 * g4][r16], 16);
+            bf16x4 bb = load4s(&Zs[wave][4 * g4][r16], kW1S);
             gW1[mt] = mfma16(load4(&D1h[wave][16 * mt + r16][4 * g4]), bb, gW1[mt]);
             gW1[mt] = mfma16(load4(&D1l[wave][16 * mt + r16][4 * g4]), bb, gW1[mt]);
         }
@@ -767,8 +767,20 @@ __global__ void k_grad_reduce(const float* partial, int nblocks, float* grad)
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= kParams) return;
     double acc = 0.0;
-    if (p < kTrain)
-        for (int b = 0; b < nblocks; ++b) acc += (double)partial[(int64_t)b * kTrain + p];
+    if (p < kTrain) {
+        // the partials are added in block order; each round issues its 16
+        // loads before the first add so that they are in flight together
+        constexpr int kRound = 16;
+        int b = 0;
+        for (; b + kRound <= nblocks; b += kRound) {
+            float v[kRound];
+#pragma unroll
+            for (int k = 0; k < kRound; ++k) v[k] = partial[(int64_t)(b + k) * kTrain + p];
+#pragma unroll
+            for (int k = 0; k < kRound; ++k) acc += (double)v[k];
+        }
+        for (; b < nblocks; ++b) acc += (double)partial[(int64_t)b * kTrain + p];
+    }
     grad[p] = (float)acc;
 }
 
