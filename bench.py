@@ -780,6 +780,66 @@ def general_mesh_section(ctx, args, dev, cartesian_ms):
     return rows
 
 
+def learned_kernels_section(ctx, args, dev):
+    """Times of the learned-bandwidth calls alone: the forward (features and
+    network) and the network backward on the 2M-trajectory 128^3 ABC case,
+    and the library's whole training step on 64^3 training snapshots."""
+    import numpy as np
+    import torch
+
+    import paper_2512_20829_amd as F
+    import workloads as W
+    from paper_2512_20829_amd import train as T
+    wl = W.abc_lattice_3d(device=dev)
+    tr = wl.traj
+    st, keep = F.make_trajectories(tr.x.contiguous(), tr.J.contiguous(), tr.v.float().contiguous(),
+                                   tr.ug.float().contiguous(), tr.r.float().contiguous(), tr.n0, tr.seed_volume)
+    N = tr.count
+    th = T.initial_theta(0)
+    th[64 * 5 + 64 + 64 * 64 + 64:64 * 5 + 64 + 64 * 64 + 128] = np.random.default_rng(1).uniform(-0.2, 0.2, 64)
+    theta = torch.tensor(th, dtype=torch.float32, device=dev)     # a non-zero output layer
+    hf = torch.empty(N, dtype=torch.float32, device=dev)
+    z = torch.empty(5 * N, dtype=torch.float32, device=dev)
+    o = torch.empty(N, dtype=torch.float32, device=dev)
+    mesh = F.mesh_of(wl.mesh)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    fwd = timed(lambda: ctx.bandwidth_forward(mesh, st, theta, hf, z, o), 20)
+    dl = torch.randn(N, dtype=torch.float32, device=dev) * 1e-3
+    grad = torch.empty(theta.numel(), dtype=torch.float32, device=dev)
+    bwd = timed(lambda: ctx.bandwidth_backward(3, theta, N, z, o, dl, grad), 10)
+    del st, keep, hf, z, o, dl
+    snaps = []
+    for s in range(4):
+        w2, abc = W.training_snapshot(s, n_traj=args.train_trajectories, mesh_n=64, device=dev)
+        p = F.Params(rho_d=w2.rho_d, mu=w2.mu, delta=w2.delta, h0=w2.h0, cutoff=w2.cutoff)
+        ref, _ = _psicell_reference(ctx, F, W, torch, w2.mesh, abc, args.train_particles, 10_000 + s, p, dev)
+        t2 = w2.traj
+        s2, k2 = F.make_trajectories(t2.x, t2.J, t2.v.float(), t2.ug.float(), t2.r.float(), t2.n0, t2.seed_volume)
+        k2.append(t2)
+        snaps.append(T.Snapshot(w2.mesh, s2, k2, t2.count, p, ref))
+    model = T.BandwidthModel(ctx, T.fit_standardisation(ctx, snaps, T.initial_theta(0)), lr=1e-3)
+    it = [0]
+
+    def step():
+        model.train_step(snaps[it[0] % len(snaps)])
+        it[0] += 1
+
+    train = timed(step, 20)
+    return {"trajectories": N, "forward_ms": round(fwd, 4), "network_backward_ms": round(bwd, 4),
+            "train_step_ms_64cubed_200k": round(train, 4)}
+
+
 def psicell_section(ctx, args, dev, fla_ms):
     import torch
 
@@ -853,7 +913,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only-headline", action="store_true", help="time the headline workload only")
-    ap.add_argument("--only", choices=["headline", "abc128", "tg2d", "psicell", "table1", "cells"], default=None,
+    ap.add_argument("--only", choices=["headline", "abc128", "tg2d", "psicell", "table1", "cells", "batch", "learned"],
+                    default=None,
                     help="time one projection workload only (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-psicell", action="store_true")
@@ -911,6 +972,11 @@ def main():
             a = torch.ones(n, dtype=torch.float32, device=dev)
             torch.empty_like(a).copy_(a)
             torch.cuda.synchronize()
+        ctx.close()
+        return
+    if args.only in ("batch", "learned"):
+        sec = batch_section(ctx, args, dev) if args.only == "batch" else learned_kernels_section(ctx, args, dev)
+        print(json.dumps({args.only: sec}), flush=True)
         ctx.close()
         return
     if args.only == "cells":
