@@ -41,6 +41,13 @@ its fused epilogue.  Printed as one JSON line (rank 0):
   table1       the four Table 1 cases through the trajectory producer: FLA
                errors against a 100x box-counted reference after 2 s of
                droplet motion in a Taylor-Green vortex, and step times
+  general_mesh the estimator at the centroids of three 128^3-cell general
+               meshes (uniform centroids, stretched rectilinear with n_hat
+               from the cell volumes, scattered) with the 2M ABC
+               trajectories, and the index build time
+  producer     one carrier step of 2M droplets in the ABC flow (8 RK4
+               substeps, binary64) fused with the projection
+  (psicell also times the cloud-in-cell comparator on the same cloud)
 """
 import argparse
 import json
@@ -780,6 +787,48 @@ def general_mesh_section(ctx, args, dev, cartesian_ms):
     return rows
 
 
+def producer_section(ctx, args, dev):
+    """fla_advance_project on 2,097,152 droplets (128^3 lattice, lognormal
+    radii, random initial velocities) in the ABC flow on the 128^3 periodic
+    mesh: one carrier step of 2 ms in 8 RK4 substeps (binary64) fused with
+    the record emission, then the projection (binary32 kernel).  The state
+    is not written back, so every call advances the same droplets."""
+    import torch
+
+    import paper_2512_20829_amd as F
+    import workloads as W
+    d = W.seed_droplets(3, 128, seed=0, device=dev)
+    mesh_w = W.unit_mesh(3, 128, True)
+    mesh = F.mesh_of(mesh_w)
+    N = d.x.shape[1]
+    phibar = torch.empty((4, N), dtype=torch.float64, device=dev)
+    dr, keep = F.make_droplets(d.x, d.v, d.J, d.dJ, d.r, d.n0, d.seed_volume, phibar=phibar)
+    flow = F.make_flow(F.FLA_FLOW_ABC, U=0.2, k=1.0)
+    step = F.make_step(2e-3, 8, update_state=False)
+    p = F.Params(rho_d=W.RHO_D, mu=W.MU_AIR, delta=W.DELTA_EVAP, h0=1.0 / 128)
+    Sm, Sv, _ = F.alloc_fields(mesh_w.cells, 3, torch.float32, dev, den=False)
+    for _ in range(max(args.warmup, 1)):
+        ctx.advance_project(mesh, dr, flow, step, p, F.FLA_F32, Sm, Sv)
+    ctx.profile_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        ctx.advance_project(mesh, dr, flow, step, p, F.FLA_F32, Sm, Sv)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    stages = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items() if v[1]}
+    prod_ms = stages.get("prepass")
+    return {"droplets": N, "substeps": 8, "ms_per_step": round(ms, 4), "stage_ms": stages,
+            "producer_ms": prod_ms,
+            "droplet_substeps_per_s": N * 8 / (prod_ms * 1e-3) if prod_ms else None,
+            "note": "producer_ms is the fused kernel (RK4 of the droplet state, Jacobian and sources, then the "
+                    "records); the rest of the step is the projection of the advanced droplets"}
+
+
 def learned_kernels_section(ctx, args, dev):
     """Times of the learned-bandwidth calls alone: the forward (features and
     network) and the network backward on the 2M-trajectory 128^3 ABC case,
@@ -868,6 +917,15 @@ def psicell_section(ctx, args, dev, fla_ms):
     e1.record()
     torch.cuda.synchronize()
     psi_ms = e0.elapsed_time(e1) / reps
+    # the cloud-in-cell comparator on the same cloud
+    ctx.cic_accumulate(mesh, pst, w, params, Pm, Pv)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ctx.cic_accumulate(mesh, pst, w, params, Pm, Pv)
+    e1.record()
+    torch.cuda.synchronize()
+    cic_ms = e0.elapsed_time(e1) / reps
     del pst, pkeep, Pm, Pv
     torch.cuda.empty_cache()
     # algorithmic bytes: x in binary64 (24 B) and v, u_g, r in binary32
@@ -879,6 +937,8 @@ def psicell_section(ctx, args, dev, fla_ms):
                          "traffic": psicell_traffic(), "algorithmic_bytes": alg,
                          "note": "achieved counts 52 B per particle in and 16 B per cell out; traffic is the "
                                  "counted bytes of the passes (records written and re-read)"},
+            "cic": {"ms": round(cic_ms, 3), "particles_per_s": Np / (cic_ms * 1e-3),
+                    "frac_of_hbm_by_algorithmic_bytes": round(alg / (cic_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "psicell_over_fla_time": round(psi_ms / fla_ms, 3) if fla_ms else None,
             "paper_context": "paper: FLA 32 CPU-h vs PSI-CELL 4030 CPU-h for the whole coupled "
                              "solver at 100x seeding, University of Brighton CPU cluster"}
@@ -913,7 +973,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only-headline", action="store_true", help="time the headline workload only")
-    ap.add_argument("--only", choices=["headline", "abc128", "tg2d", "psicell", "table1", "cells", "batch", "learned"],
+    ap.add_argument("--only", choices=["headline", "abc128", "tg2d", "psicell", "table1", "cells", "batch", "learned",
+                                       "producer"],
                     default=None,
                     help="time one projection workload only (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -974,8 +1035,9 @@ def main():
             torch.cuda.synchronize()
         ctx.close()
         return
-    if args.only in ("batch", "learned"):
-        sec = batch_section(ctx, args, dev) if args.only == "batch" else learned_kernels_section(ctx, args, dev)
+    if args.only in ("batch", "learned", "producer"):
+        sec = {"batch": batch_section, "learned": learned_kernels_section,
+               "producer": producer_section}[args.only](ctx, args, dev)
         print(json.dumps({args.only: sec}), flush=True)
         ctx.close()
         return
@@ -987,12 +1049,14 @@ def main():
         print(json.dumps({"table1": table1_section(ctx, args, dev)}), flush=True)
         ctx.close()
         return
-    table1 = cells = None
+    table1 = cells = producer = None
     if args.only is None:
         if not args.no_table1:
             table1 = table1_section(ctx, args, dev)
         if not args.no_cells:
             cells = general_mesh_section(ctx, args, dev, abc["ms_per_step"])
+        producer = producer_section(ctx, args, dev)
+        log(f"producer: {producer['ms_per_step']:.3f} ms/step; stages {producer['stage_ms']}")
         if not args.no_batch:
             batch = batch_section(ctx, args, dev)
         if not args.no_psicell:
@@ -1052,6 +1116,7 @@ def main():
         "large": large,
         "table1": table1,
         "general_mesh": cells,
+        "producer": producer,
     }
     log(f"main line: {name}")
     print(json.dumps(out), flush=True)
