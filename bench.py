@@ -1105,6 +1105,7 @@ def main():
         "config": configs[args.only or "headline"],
         "pairs_per_s": main_sec["pairs_per_s"],
         "pairs": main_sec["pairs"],
+        "max_class": main_sec["max_class"],
         "stage_ms": main_sec["stage_ms"],
         "roofline": main_sec["roofline"],
         "cpu_baseline": cpu,
