@@ -782,6 +782,22 @@ def general_mesh_section(ctx, args, dev, cartesian_ms):
         log(f"general mesh {name}: {ms:.3f} ms/step, {P:.4g} pairs, index {build_ms:.1f} ms")
         ix.close()
         del Sm, Sv
+    # the stretched mesh again as a rectilinear Cartesian mesh (per-axis edges
+    # in fla_mesh): the separable gather of fla_project_sources
+    edges = [W.stretched_edges(128, 0.0, 1.0, 1.5).to(dev) for _ in range(3)]
+    mesh = F.mesh_of(W.unit_mesh(3, 128, True), edges=edges)
+    ms, stages, g_ms, stats = timed_projection(ctx, F, mesh, st, params, args.steps, args.warmup)
+    P = stats["pairs"]
+    ach = P * FLOPS_PER_PAIR[3] / (g_ms * 1e-3) / 1e12
+    rows["stretched_rectilinear_cartesian"] = {
+        "cells": 128 ** 3, "ms_per_step": round(ms, 3), "cells_per_s": 128 ** 3 / (ms * 1e-3), "pairs": P,
+        "pairs_per_s": P / (ms * 1e-3), "stage_ms": stages, "entry": "fla_project_sources with fla_mesh.edges",
+        "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None, "kernel": "k_gather<float,3,NW>",
+                     "launch_ms": round(g_ms, 4), "flops_per_pair": FLOPS_PER_PAIR[3],
+                     "frac_of_nonpacked_78.6": round(ach / FP32_NONPACKED_TFLOPS, 4)},
+        "over_cartesian_time": round(ms / cartesian_ms, 2) if cartesian_ms else None}
+    log(f"general mesh stretched, rectilinear path: {ms:.3f} ms/step, {P:.4g} pairs")
     del st, keep
     torch.cuda.empty_cache()
     return rows

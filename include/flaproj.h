@@ -67,11 +67,19 @@ typedef enum { FLA_NW = 0, FLA_DEPOSIT = 1 } fla_mode;
 
 typedef struct fla_ctx fla_ctx;
 
-/* Uniform Cartesian mesh on [lo, hi) with n[a] cells along axis a; cell
- * centres at lo + (i + 1/2)(hi - lo)/n.  Periodic axes use minimum-image
- * offsets.  cell_scale (nullable, device, M values in the call's precision)
+/* Cartesian mesh on [lo, hi) with n[a] cells along axis a; cell centres at
+ * lo + (i + 1/2)(hi - lo)/n.  Periodic axes use minimum-image offsets.
+ * cell_scale (nullable, device, M values in the call's precision)
  * multiplies every source term of a cell: the per-cell factor n_hat of
- * App. A, eqs. (A.13)-(A.14), on a mesh where it varies. */
+ * App. A, eqs. (A.13)-(A.14), on a mesh where it varies.
+ * edges[a] (nullable, device, binary64): a rectilinear (stretched) axis,
+ * its n[a] + 1 cell edges, strictly increasing, edges[a][0] = lo[a] and
+ * edges[a][n[a]] = hi[a]; the cell centres are then the edge midpoints
+ * (e[i] + e[i+1])/2.  The library reads but does not check them (memory
+ * accesses stay in bounds whatever they hold).  Rectilinear axes are taken
+ * by the FLA_NW projection (fla_project_sources, its allocation-free form,
+ * fla_project_batch, fla_advance_project); every other entry point returns
+ * FLA_ERR_INVALID_ARG for a mesh with edges. */
 typedef struct {
     int32_t dim;            /* 2 or 3 */
     int32_t n[3];           /* cells per axis, >= 1; n[2] ignored if dim == 2 */
@@ -79,6 +87,7 @@ typedef struct {
     double hi[3];           /* hi[a] > lo[a] */
     int32_t periodic[3];    /* nonzero = periodic axis */
     const void* cell_scale; /* nullable */
+    const double* edges[3]; /* nullable per axis: uniform */
 } fla_mesh;
 
 /* Trajectory (or particle) records, structure of arrays, count values each.

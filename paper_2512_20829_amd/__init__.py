@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "FLA_OK", 1: "FLA_ERR_INVALID_ARG", 2: "FLA_ERR_OUT_OF_MEMORY
 
 class fla_mesh(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
-                ("periodic", C.c_int32 * 3), ("cell_scale", C.c_void_p)]
+                ("periodic", C.c_int32 * 3), ("cell_scale", C.c_void_p), ("edges", C.c_void_p * 3)]
 
 
 class fla_trajectories(C.Structure):
@@ -213,7 +213,10 @@ class Params:
 
 
 def make_mesh(dim: int, n: Sequence[int], lo: Sequence[float], hi: Sequence[float],
-              periodic: Sequence[bool], cell_scale=None) -> fla_mesh:
+              periodic: Sequence[bool], cell_scale=None, edges=None) -> fla_mesh:
+    """edges: None, or per axis None (uniform) or a contiguous float64 device
+    tensor of n[a] + 1 increasing cell edges (a rectilinear axis); the
+    caller keeps the tensors alive."""
     m = fla_mesh()
     m.dim = dim
     for a in range(3):
@@ -222,12 +225,19 @@ def make_mesh(dim: int, n: Sequence[int], lo: Sequence[float], hi: Sequence[floa
         m.hi[a] = float(hi[a]) if a < dim else 1.0
         m.periodic[a] = int(bool(periodic[a])) if a < dim else 0
     m.cell_scale = _ptr(cell_scale)
+    for a in range(3):
+        e = edges[a] if (edges is not None and a < dim) else None
+        if e is not None:
+            import torch
+            if e.dtype != torch.float64 or e.numel() != int(n[a]) + 1:
+                raise ValueError("edges[a] must be float64 with n[a] + 1 values")
+        m.edges[a] = _ptr(e)
     return m
 
 
-def mesh_of(obj, cell_scale=None) -> fla_mesh:
+def mesh_of(obj, cell_scale=None, edges=None) -> fla_mesh:
     """From an object with dim, n, lo, hi, periodic attributes."""
-    return make_mesh(obj.dim, obj.n, obj.lo, obj.hi, obj.periodic, cell_scale)
+    return make_mesh(obj.dim, obj.n, obj.lo, obj.hi, obj.periodic, cell_scale, edges)
 
 
 def make_trajectories(x, J, v, ug, r, n0=1.0, seed_volume: float = 0.0) -> tuple:

@@ -267,6 +267,7 @@ fla_status check_mesh(fla_ctx* ctx, const fla_mesh* mesh, MeshDev* md, int te)
             m.w[a] = m.L[a] / (double)mesh->n[a];
             CHECK_ARG(m.w[a] > 0.0 && is_fin(m.w[a]), "mesh cell width is not a positive finite number");
             m.nt[a] = (mesh->n[a] + te - 1) / te;
+            m.edges[a] = mesh->edges[a];
         } else {
             m.n[a] = 1;
             m.periodic[a] = 0;
@@ -287,6 +288,13 @@ fla_status check_mesh(fla_ctx* ctx, const fla_mesh* mesh, MeshDev* md, int te)
     for (int a = 0; a < mesh->dim; ++a) m.vol *= m.w[a];
     *md = m;
     return FLA_OK;
+}
+
+bool has_edges(const fla_mesh* mesh)
+{
+    for (int a = 0; a < mesh->dim; ++a)
+        if (mesh->edges[a]) return true;
+    return false;
 }
 
 fla_status check_traj(fla_ctx* ctx, const fla_trajectories* t, int dim, bool need_J, TrajDev* td)
@@ -619,7 +627,10 @@ fla_status batch_impl(fla_ctx* ctx, int nsnap, const MeshDev* md, const TrajDev*
             if (outs[i].pairs) HIP_OK(launch_fill_u32(outs[i].pairs, md[i].M, 0u, q));
         {
             StageTimer tm(ctx, 3, q);
-            HIP_OK((launch_gather_batch<R, D>(dev_items, nsnap, (int)nwork, chunk, count, plan, q)));
+            bool general = false;     // any rectilinear axis in the batch
+            for (int i = 0; i < nsnap; ++i)
+                for (int a = 0; a < 3; ++a) general = general || md[i].edges[a] != nullptr;
+            HIP_OK((launch_gather_batch<R, D>(dev_items, nsnap, (int)nwork, chunk, count, plan, general, q)));
         }
         return FLA_OK;
     };
@@ -1042,6 +1053,8 @@ static fla_status project_entry(fla_ctx* ctx, const fla_mesh* mesh, const fla_tr
         MeshDev m;
         fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
         if (st != FLA_OK) return st;
+        CHECK_ARG(!(params && params->mode == FLA_DEPOSIT && has_edges(mesh)),
+                  "FLA_DEPOSIT needs a uniform mesh (divides by one cell volume); edges were given");
         TrajDev t;
         st = check_traj(ctx, traj, m.dim, true, &t);
         if (st != FLA_OK) return st;
@@ -1085,6 +1098,7 @@ FLA_EXPORT fla_status psicell_accumulate(fla_ctx* ctx, const fla_mesh* mesh, con
             MeshDev m;
             fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
             if (st != FLA_OK) return st;
+            CHECK_ARG(!has_edges(mesh), "rectilinear mesh edges are taken by the FLA_NW projection only");
             TrajDev t;
             st = check_traj(ctx, particles, m.dim, false, &t);
             if (st != FLA_OK) return st;
@@ -1121,6 +1135,7 @@ FLA_EXPORT fla_status cic_accumulate(fla_ctx* ctx, const fla_mesh* mesh, const f
             MeshDev m;
             fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
             if (st != FLA_OK) return st;
+            CHECK_ARG(!has_edges(mesh), "rectilinear mesh edges are taken by the FLA_NW projection only");
             TrajDev t;
             st = check_traj(ctx, particles, m.dim, false, &t);
             if (st != FLA_OK) return st;
@@ -1176,6 +1191,7 @@ FLA_EXPORT fla_status fla_bandwidth_forward(fla_ctx* ctx, const fla_mesh* mesh, 
             MeshDev m;
             fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
             if (st != FLA_OK) return st;
+            CHECK_ARG(!has_edges(mesh), "rectilinear mesh edges are taken by the FLA_NW projection only");
             TrajDev t;
             st = check_traj(ctx, traj, m.dim, true, &t);
             if (st != FLA_OK) return st;
@@ -1209,6 +1225,7 @@ FLA_EXPORT fla_status fla_project_backward(fla_ctx* ctx, const fla_mesh* mesh, c
             MeshDev m;
             fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
             if (st != FLA_OK) return st;
+            CHECK_ARG(!has_edges(mesh), "rectilinear mesh edges are taken by the FLA_NW projection only");
             TrajDev t;
             st = check_traj(ctx, traj, m.dim, true, &t);
             if (st != FLA_OK) return st;
@@ -1549,6 +1566,8 @@ FLA_EXPORT fla_status fla_advance_project(fla_ctx* ctx, const fla_mesh* mesh, co
             MeshDev m;
             fla_status st = check_mesh(ctx, mesh, &m, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
             if (st != FLA_OK) return st;
+            CHECK_ARG(!(params && params->mode == FLA_DEPOSIT && has_edges(mesh)),
+                      "FLA_DEPOSIT needs a uniform mesh (divides by one cell volume); edges were given");
             const int D = m.dim;
             CHECK_ARG(drops != nullptr, "droplets is NULL");
             CHECK_ARG(drops->count >= 0 && drops->count < (int64_t(1) << 31), "count must be in [0, 2^31)");
@@ -1640,6 +1659,7 @@ FLA_EXPORT fla_status fla_bandwidth_standardise(fla_ctx* ctx, int nsnap, const f
             TrajDev t;
             if (st == FLA_OK) st = check_traj(ctx, &trajs[k], m.dim, true, &t);
             if (st != FLA_OK) {
+            CHECK_ARG(!has_edges(&meshes[k]), "rectilinear mesh edges are taken by the FLA_NW projection only");
                 ctx->err = "snapshot " + std::to_string(k) + ": " + ctx->err;
                 return st;
             }
@@ -1696,6 +1716,7 @@ FLA_EXPORT fla_status fla_mlp_train_step(fla_ctx* ctx, const fla_mesh* mesh, con
             MeshDev md;
             fla_status st = check_mesh(ctx, mesh, &md, mesh && mesh->dim == 2 ? Geo<2>::TE : Geo<3>::TE);
             if (st != FLA_OK) return st;
+            CHECK_ARG(!has_edges(mesh), "rectilinear mesh edges are taken by the FLA_NW projection only");
             TrajDev td;
             st = check_traj(ctx, traj, md.dim, true, &td);
             if (st != FLA_OK) return st;

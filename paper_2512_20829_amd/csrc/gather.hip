@@ -37,6 +37,10 @@
 
 namespace flp {
 
+// Gather mode of the Nadaraya-Watson estimator on any mesh (uniform or
+// rectilinear axes); FLA_NW itself assumes uniform axes.
+constexpr int kNwGeneral = 2;
+
 constexpr int kCap = 2 * kWave;
 
 typedef float F4 __attribute__((ext_vector_type(4)));
@@ -386,10 +390,14 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
     // a part lying wholly beyond the mesh has no cells (uniform over the workgroup)
     if (TP == 2 && (int64_t)tc[0] * TE + soff >= m.n[0]) return;
 
+    // kNwGeneral takes any mesh (rectilinear axes read their edges); the
+    // other modes assume uniform axes and compute the centres
+    constexpr bool kGeneral = MODE == kNwGeneral;
     if (threadIdx.x < D * TE) {
         int a = threadIdx.x / TE, p = threadIdx.x % TE;
         int64_t idx = (int64_t)tc[a] * TE + p;
-        xcs[a][p] = idx < m.n[a] ? cell_centre(m, a, idx) : __builtin_nan("");
+        xcs[a][p] = idx < m.n[a] ? (kGeneral ? cell_centre(m, a, idx) : uniform_centre(m, a, idx))
+                                 : __builtin_nan("");
     }
     int lc[3];
     if (D == 3) {
@@ -406,15 +414,32 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
         R c = (R)g.cutoff;
         c2 = uniform_value(c * c);
     }
-    // conservative tile box of cell centres for the candidate filter
+    // conservative tile box of cell centres for the candidate filter: on
+    // uniform axes from the formula (extrapolated past the last cell), on
+    // rectilinear axes from the existing centres in the table.  (The box
+    // decides which records are staged, hence where the binary32 partial
+    // sums are folded: a uniform axis gets the same box in either mode, so
+    // a uniform snapshot of a batch that also holds rectilinear ones keeps
+    // the bits of its own call.)
+    if (kGeneral) __syncthreads();
     double bmid[3] = {0, 0, 0}, bhalf[3] = {0, 0, 0};
     bool faxis[3] = {false, false, false};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         const bool one = TP == 2 && a == 0;
-        const int64_t c0 = (int64_t)tc[a] * TE + (one ? soff : 0);
-        double f = cell_centre(m, a, c0);
-        double l = cell_centre(m, a, c0 + (one ? SB : TE) - 1);
+        double f, l;
+        if (kGeneral && m.edges[a]) {
+            const int p0 = one ? soff : 0;
+            int p1 = p0 + (one ? SB : TE) - 1;
+            const int last = (int)(m.n[a] - 1 - (int64_t)tc[a] * TE);
+            if (p1 > last) p1 = last;
+            f = xcs[a][p0];
+            l = xcs[a][p1];
+        } else {
+            const int64_t c0 = (int64_t)tc[a] * TE + (one ? soff : 0);
+            f = uniform_centre(m, a, c0);
+            l = uniform_centre(m, a, c0 + (one ? SB : TE) - 1);
+        }
         bmid[a] = uniform_value(0.5 * (f + l));
         bhalf[a] = uniform_value(0.5 * (l - f));
         faxis[a] = !(m.periodic[a] && 4.0 * bhalf[a] >= m.L[a]);
@@ -769,7 +794,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
 #pragma unroll
         for (int k = 0; k < C; ++k) {
             double val;
-            if (MODE == FLA_NW)
+            if (MODE != FLA_DEPOSIT)
                 val = (den > 0.0) ? f * (tot[1 + k] / den) : 0.0;
             else
                 val = f * tot[1 + k] / m.vol;
@@ -916,27 +941,34 @@ static void launch_plan(const GatherArgs& g, int plan, dim3 grid, dim3 block, hi
     }
 }
 
-template <typename R, int D, bool COUNT>
+template <typename R, int D, int MODE, bool COUNT>
 static void launch_batch_plan(const BatchItem* items, int nsnap, int nwork, int chunk, int plan, hipStream_t s)
 {
     dim3 grid((unsigned)(nwork * TileParts<D>::value)), block(kWave * GatherWaves<D>::value);
     switch (plan) {
-    case 1: FLA_LAUNCH((k_gather_batch<R, D, FLA_NW, COUNT, 1>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
-    case 2: FLA_LAUNCH((k_gather_batch<R, D, FLA_NW, COUNT, 2>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
-    case 3: FLA_LAUNCH((k_gather_batch<R, D, FLA_NW, COUNT, 3>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
-    default: FLA_LAUNCH((k_gather_batch<R, D, FLA_NW, COUNT, 0>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    case 1: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 1>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    case 2: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 2>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    case 3: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 3>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    default: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 0>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
     }
 }
 
 template <typename R, int D>
 hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan,
-                               hipStream_t s)
+                               bool general, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
-    if (count)
-        launch_batch_plan<R, D, true>(items, nsnap, nwork, chunk, plan, s);
-    else
-        launch_batch_plan<R, D, false>(items, nsnap, nwork, chunk, plan, s);
+    if (general) {
+        if (count)
+            launch_batch_plan<R, D, kNwGeneral, true>(items, nsnap, nwork, chunk, plan, s);
+        else
+            launch_batch_plan<R, D, kNwGeneral, false>(items, nsnap, nwork, chunk, plan, s);
+    } else {
+        if (count)
+            launch_batch_plan<R, D, FLA_NW, true>(items, nsnap, nwork, chunk, plan, s);
+        else
+            launch_batch_plan<R, D, FLA_NW, false>(items, nsnap, nwork, chunk, plan, s);
+    }
     return hipGetLastError();
 }
 
@@ -950,7 +982,13 @@ hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hi
                            g.m.ntiles * TileParts<D>::value, TileParts<D>::value, g.order);
     }
     dim3 grid((unsigned)(g.m.ntiles * TileParts<D>::value)), block(kWave * GatherWaves<D>::value);
-    if (mode == FLA_NW) {
+    const bool general = g.m.edges[0] || g.m.edges[1] || g.m.edges[2];
+    if (mode == FLA_NW && general) {
+        if (count)
+            launch_plan<R, D, kNwGeneral, true>(g, plan, grid, block, s);
+        else
+            launch_plan<R, D, kNwGeneral, false>(g, plan, grid, block, s);
+    } else if (mode == FLA_NW) {
         if (count)
             launch_plan<R, D, FLA_NW, true>(g, plan, grid, block, s);
         else
@@ -968,9 +1006,9 @@ template hipError_t launch_gather<float, 2>(const GatherArgs&, int, bool, int, h
 template hipError_t launch_gather<float, 3>(const GatherArgs&, int, bool, int, hipStream_t);
 template hipError_t launch_gather<double, 2>(const GatherArgs&, int, bool, int, hipStream_t);
 template hipError_t launch_gather<double, 3>(const GatherArgs&, int, bool, int, hipStream_t);
-template hipError_t launch_gather_batch<float, 2>(const BatchItem*, int, int, int, bool, int, hipStream_t);
-template hipError_t launch_gather_batch<float, 3>(const BatchItem*, int, int, int, bool, int, hipStream_t);
-template hipError_t launch_gather_batch<double, 2>(const BatchItem*, int, int, int, bool, int, hipStream_t);
-template hipError_t launch_gather_batch<double, 3>(const BatchItem*, int, int, int, bool, int, hipStream_t);
+template hipError_t launch_gather_batch<float, 2>(const BatchItem*, int, int, int, bool, int, bool, hipStream_t);
+template hipError_t launch_gather_batch<float, 3>(const BatchItem*, int, int, int, bool, int, bool, hipStream_t);
+template hipError_t launch_gather_batch<double, 2>(const BatchItem*, int, int, int, bool, int, bool, hipStream_t);
+template hipError_t launch_gather_batch<double, 3>(const BatchItem*, int, int, int, bool, int, bool, hipStream_t);
 
 }  // namespace flp

@@ -32,7 +32,10 @@ struct MeshDev {
     double hi[3];
     double w[3];     // cell width (hi - lo)/n, computed on the host
     double L[3];     // box length hi - lo
-    double vol;      // cell volume
+    double vol;      // cell volume (uniform axes)
+    // rectilinear axes: n[a] + 1 increasing cell edges (device, binary64),
+    // NULL for a uniform axis; cell centres at the edge midpoints
+    const double* edges[3];
 };
 
 struct TrajDev {
@@ -69,11 +72,75 @@ enum StatSlot { ST_TRAJ = 0, ST_SKIPPED, ST_NOSUPPORT, ST_PAIRS, ST_OUTSIDE, ST_
 // Exact-arithmetic helpers: binary64 operations whose rounding must not be
 // altered by multiply-add contraction (they decide which pairs are included).
 // ---------------------------------------------------------------------------
-__device__ inline double cell_centre(const MeshDev& m, int a, int64_t i)
+// Centre of cell i on a uniform axis.
+__device__ inline double uniform_centre(const MeshDev& m, int a, int64_t i)
 {
 #pragma clang fp contract(off)
     double t = ((double)i + 0.5) * m.w[a];
     return m.lo[a] + t;
+}
+
+// Centre of cell i on a uniform or a rectilinear axis.
+__device__ inline double cell_centre(const MeshDev& m, int a, int64_t i)
+{
+#pragma clang fp contract(off)
+    if (m.edges[a]) {
+        const double* e = m.edges[a];
+        return 0.5 * (e[i] + e[i + 1]);
+    }
+    double t = ((double)i + 0.5) * m.w[a];
+    return m.lo[a] + t;
+}
+
+// Rectilinear axes.  The cell holding p: the last edge e[i] <= p, clamped
+// to [0, n - 1].
+__device__ inline int64_t edge_cell(const double* e, int n, double p)
+{
+    int l = 0, r = n - 1;
+    while (l < r) {
+        const int mid = (l + r + 1) >> 1;
+        if (e[mid] <= p)
+            l = mid;
+        else
+            r = mid - 1;
+    }
+    return l;
+}
+// The first cell whose centre is >= p (n if none), and the last cell whose
+// centre is <= p (-1 if none), over one period of the axis.
+__device__ inline int64_t centre_at_or_above(const double* e, int n, double p)
+{
+    int l = 0, r = n;
+    while (l < r) {
+        const int mid = (l + r) >> 1;
+        double c;
+        {
+#pragma clang fp contract(off)
+            c = 0.5 * (e[mid] + e[mid + 1]);
+        }
+        if (c >= p)
+            r = mid;
+        else
+            l = mid + 1;
+    }
+    return l;
+}
+__device__ inline int64_t centre_at_or_below(const double* e, int n, double p)
+{
+    int l = -1, r = n - 1;
+    while (l < r) {
+        const int mid = (l + r + 1) >> 1;
+        double c;
+        {
+#pragma clang fp contract(off)
+            c = 0.5 * (e[mid] + e[mid + 1]);
+        }
+        if (c <= p)
+            l = mid;
+        else
+            r = mid - 1;
+    }
+    return l;
 }
 
 // Minimum image d - L rint(d/L) of an offset d on a periodic axis of length

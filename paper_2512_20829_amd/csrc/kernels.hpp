@@ -43,7 +43,7 @@ hipError_t launch_max_class_batch(const BatchItem* items, int nsnap, const uint3
                                   unsigned long long* stats, hipStream_t s);
 template <typename R, int D>
 hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan,
-                               hipStream_t s);
+                               bool general, hipStream_t s);
 
 // Trajectory producer: the gas field and the droplet state it advances.
 struct FlowDev {

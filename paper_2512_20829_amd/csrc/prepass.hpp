@@ -36,20 +36,47 @@ struct LatticeKey {
         bool support = true;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            // home cell by division, exactly as the gather's home_index; the
-            // support bounds (they only choose the bucket class) by a
-            // multiply with 1/w, widened by 1e-9 plus 1e-15 of the quotient,
-            // far more than the few ulps by which the product can differ
-            double g = floor((x[a] - m.lo[a]) / m.w[a]);
-            g = fmin(fmax(g, -4.0e15), 4.0e15);
-            int64_t hc = (int64_t)g;
-            const double iw = 1.0 / m.w[a];
-            const double qlo = (x[a] - rc - m.lo[a]) * iw, qhi = (x[a] + rc - m.lo[a]) * iw;
-            double flo = qlo - 0.5 - (1e-9 + 1e-15 * fabs(qlo));
-            double fhi = qhi - 0.5 + (1e-9 + 1e-15 * fabs(qhi));
-            flo = fmin(fmax(flo, -4.0e15), 4.0e15);
-            fhi = fmin(fmax(fhi, -4.0e15), 4.0e15);
-            int64_t ilo = (int64_t)ceil(flo), ihi = (int64_t)floor(fhi);
+            int64_t hc, ilo, ihi;
+            if (m.edges[a]) {
+                // rectilinear axis: the home cell and the cells whose centres
+                // can lie within rc by binary search, over the periodic
+                // extension on a periodic axis (index i of period k is
+                // i + k n); the support interval is widened by 1e-12 of
+                // |x| + rc + L, far more than the rounding of x -+ rc and of
+                // the wrap
+                const double* e = m.edges[a];
+                const int n = m.n[a];
+                const double sl = 1e-12 * (fabs(x[a]) + rc + m.L[a]);
+                const double plo = x[a] - rc - sl, phi = x[a] + rc + sl;
+                if (m.periodic[a]) {
+                    const double kx = fmin(fmax(floor((x[a] - m.lo[a]) / m.L[a]), -1.0e12), 1.0e12);
+                    const double kl = fmin(fmax(floor((plo - m.lo[a]) / m.L[a]), -1.0e12), 1.0e12);
+                    const double kh = fmin(fmax(floor((phi - m.lo[a]) / m.L[a]), -1.0e12), 1.0e12);
+                    hc = edge_cell(e, n, x[a] - kx * m.L[a]) + (int64_t)kx * n;
+                    ilo = centre_at_or_above(e, n, plo - kl * m.L[a]) + (int64_t)kl * n;
+                    ihi = centre_at_or_below(e, n, phi - kh * m.L[a]) + (int64_t)kh * n;
+                } else {
+                    hc = edge_cell(e, n, x[a]);
+                    ilo = centre_at_or_above(e, n, plo);
+                    ihi = centre_at_or_below(e, n, phi);
+                }
+            } else {
+                // home cell by division, exactly as the gather's home_index; the
+                // support bounds (they only choose the bucket class) by a
+                // multiply with 1/w, widened by 1e-9 plus 1e-15 of the quotient,
+                // far more than the few ulps by which the product can differ
+                double g = floor((x[a] - m.lo[a]) / m.w[a]);
+                g = fmin(fmax(g, -4.0e15), 4.0e15);
+                hc = (int64_t)g;
+                const double iw = 1.0 / m.w[a];
+                const double qlo = (x[a] - rc - m.lo[a]) * iw, qhi = (x[a] + rc - m.lo[a]) * iw;
+                double flo = qlo - 0.5 - (1e-9 + 1e-15 * fabs(qlo));
+                double fhi = qhi - 0.5 + (1e-9 + 1e-15 * fabs(qhi));
+                flo = fmin(fmax(flo, -4.0e15), 4.0e15);
+                fhi = fmin(fmax(fhi, -4.0e15), 4.0e15);
+                ilo = (int64_t)ceil(flo);
+                ihi = (int64_t)floor(fhi);
+            }
             int64_t ra;
             if (m.periodic[a]) {
                 // tile distances are circular: the last tile of an axis whose
