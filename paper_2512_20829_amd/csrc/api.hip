@@ -673,14 +673,26 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
 {
     const int C = D + 1;
     PsiArgs a{};
-    // coarse tiles of kPsiMaxCellsPerTile cells: 16 x 8 x 8 (32^2 in 2-D);
-    // 8^3 for binary64 in 3-D, whose two-word sums need twice the LDS
-    int pt[3] = {D == 3 ? (sizeof(R) == 8 ? 8 : 16) : 32, D == 3 ? 8 : 32, D == 3 ? 8 : 1};
-    auto ntiles = [&]() {
+    constexpr bool f64 = sizeof(R) == 8;
+    auto ntiles_of = [&](const int* t) {
         int64_t nt = 1;
-        for (int ax = 0; ax < D; ++ax) nt *= (m.n[ax] + pt[ax] - 1) / pt[ax];
+        for (int ax = 0; ax < D; ++ax) nt *= (m.n[ax] + t[ax] - 1) / t[ax];
         return nt;
     };
+    // direct: tiles as large as one workgroup's LDS sums allow (16^3 cells,
+    // 64^2 in 2-D; half that for binary64, whose sums take two words), when
+    // the mesh needs at most kPsiMaxBins of them; otherwise coarse tiles of
+    // kPsiMaxCellsPerTile cells (16 x 8 x 8, 32^2 in 2-D; 8^3 for binary64
+    // in 3-D) grouped into bins of kPsiTilesPerBin
+    const int ptd[3] = {D == 3 ? 16 : 64, D == 3 ? 16 : (f64 ? 32 : 64), D == 3 ? (f64 ? 8 : 16) : 1};
+    int max_lds = 0;
+    HIP_OK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    const int64_t lds_direct = (int64_t)(8 * C * PsiWords<R>::value + 4) * ptd[0] * ptd[1] * ptd[2];
+    const bool direct = ntiles_of(ptd) <= kPsiMaxBins && lds_direct <= max_lds;
+    int pt[3] = {D == 3 ? (f64 ? 8 : 16) : 32, D == 3 ? 8 : 32, D == 3 ? 8 : 1};
+    if (direct)
+        for (int ax = 0; ax < 3; ++ax) pt[ax] = ptd[ax];
+    auto ntiles = [&]() { return ntiles_of(pt); };
     CHECK_ARG(ntiles() <= kPsiMaxTiles, sizeof(R) == 8 && D == 3
                                             ? "psicell_accumulate supports at most 16384 * 512 cells in binary64 3-D"
                                             : "psicell_accumulate supports at most 16384 * 1024 cells");
@@ -693,12 +705,14 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
     for (int ax = 0; ax < 3; ++ax) a.ptlog[ax] = __builtin_ctz((unsigned)a.pt[ax]);
     a.cptlog = a.ptlog[0] + a.ptlog[1] + a.ptlog[2];
     a.nblocks = kPsiBlocks;
-    a.pnbins = (a.pntiles + kPsiTilesPerBin - 1) / kPsiTilesPerBin;
+    a.direct = direct ? 1 : 0;
+    a.binlog = direct ? 0 : kPsiTilesPerBinLog;
+    a.pnbins = direct ? a.pntiles : (a.pntiles + kPsiTilesPerBin - 1) / kPsiTilesPerBin;
     // about 2048 workgroups in the tile pass
     a.nsplit = a.pnbins >= 2048 ? 1 : 2048 / a.pnbins;
     const int64_t N = t.count;
     const int64_t hw = (int64_t)a.pntiles * a.nblocks + 1;
-    const int64_t hb = (int64_t)a.pnbins * a.nblocks + 1;
+    const int64_t hb = direct ? 1 : (int64_t)a.pnbins * a.nblocks + 1;
     const int64_t sw = scan_tmp_words(hw > hb ? hw : hb);
     auto layout = [&](Carver& c) {
         a.maxbits = c.take<unsigned long long>(4);
@@ -707,8 +721,13 @@ fla_status psicell_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double
         a.blockhist = c.take<unsigned int>(hw);
         a.binhist = c.take<unsigned int>(hb);
         a.tcursor = c.take<unsigned int>(a.pntiles);
-        a.binned = c.take<PsiRec<R>>(N > 0 ? N : 1);
+        a.binned = c.take<PsiRec<R>>(direct || N <= 0 ? 1 : N);
         a.bucket = c.take<PsiRec<R>>(N > 0 ? N : 1);
+        if (direct) {
+            // the scatter's bins are the tiles: their counts, and their buckets
+            a.binhist = a.blockhist;
+            a.binned = a.bucket;
+        }
         a.blockmax = c.take<unsigned long long>((size_t)a.nblocks * 4);
         a.scan_tmp = c.take<uint32_t>(sw);
     };

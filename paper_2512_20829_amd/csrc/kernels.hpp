@@ -121,7 +121,9 @@ struct PsiArgs {
     int nblocks;                 // blocks of the count / scatter passes
     int* codes;                  // per particle: tile * cpt + cell in tile, or -1
     unsigned int* blockhist;     // pntiles * nblocks + 1, scanned in place
-    int pnbins;                  // bins of kPsiTilesPerBin consecutive tiles
+    int pnbins;                  // bins of 2^binlog consecutive tiles
+    int binlog;                  // log2 tiles per bin: kPsiTilesPerBinLog, or 0 when direct
+    int direct;                  // the scatter writes the tile buckets itself (bins are tiles; no tile pass)
     int nsplit;                  // workgroups per bin in the tile pass
     unsigned int* binhist;       // pnbins * nblocks + 1, scanned in place
     unsigned int* tcursor;       // pntiles: next free slot of each tile bucket
@@ -145,8 +147,10 @@ template <typename R> struct PsiWords { static constexpr int value = sizeof(R) =
 constexpr int kPsiMaxTiles = 16384;   // LDS histogram of the count pass <= 64 KiB
 constexpr int kPsiTilesPerBinLog = 6;
 constexpr int kPsiTilesPerBin = 1 << kPsiTilesPerBinLog;    // tiles per bin of the first partition
-constexpr int kPsiMaxBins = kPsiMaxTiles / kPsiTilesPerBin; // one bin per thread in the bin scans
+constexpr int kPsiMaxBins = 512;       // bins of the scatter: two per thread in its bin scans
+static_assert(kPsiMaxTiles / kPsiTilesPerBin <= kPsiMaxBins, "the bins of the tile partition must fit the scatter");
 constexpr int kPsiMaxCellsPerTile = 1024;  // LDS sums of the reduce pass <= 36 KiB
+constexpr int kPsiDirectThreads = 1024;    // threads of a reduce workgroup over one large tile
 constexpr int kPsiBlocks = 1024;
 
 template <typename R, int D>

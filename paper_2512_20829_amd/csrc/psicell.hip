@@ -34,7 +34,11 @@
 //           then scale by -w/V_c and write the tile's cells.
 // Storing each record straight into one of thousands of tile buckets would
 // leave every 20-byte store on its own and the cache lines partly written;
-// the two sorted partitions write whole runs instead.  Every pass gives each
+// the two sorted partitions write whole runs instead.  A mesh that takes at
+// most kPsiMaxBins tiles as large as one workgroup's LDS sums allow (4096
+// cells for binary32 records, 2048 for binary64) is run direct: the bins are
+// those tiles, the scatter's runs are the tile buckets, and the tile pass
+// (one more write and read of every record) is not needed.  Every pass gives each
 // thread several particles per step (kPsiUnroll, PsiRoundPerThread,
 // kPsiUnrollReduce) and issues all their loads before any use, to keep
 // enough reads in flight; the scatter forms the binary32 source terms of
@@ -46,13 +50,15 @@ namespace flp {
 
 constexpr int kPsiUnroll = 4;          // count
 constexpr int kPsiUnrollReduce = 8;    // reduce
-// particles (records) per thread in a round of the two partitions: the
-// round's records, slots and counters stay under 64 KiB of LDS
-template <typename R> struct PsiRoundPerThread { static constexpr int value = sizeof(R) == 4 ? 8 : 4; };
+// particles (records) per thread in a round of the two partitions: a
+// round's records take 120 KiB of LDS (one block per compute unit); the
+// longer a round, the longer its run per bin, and the fewer partly written
+// cache lines (with 512 direct tiles, rounds of 2048, 4096 and 6144
+// binary32 records took the 200M-particle call to 6.72, 6.36 and 6.25 ms)
+template <typename R> struct PsiRoundPerThread { static constexpr int value = sizeof(R) == 4 ? 24 : 12; };
 constexpr uint32_t kPsiSkip = 0xFFFFFFFFu;     // cell of a skipped record in a tile bucket
 constexpr uint32_t kPsiSkipBit = 0x80000000u;  // skip mark of a binned record (codes < 2^24)
 static_assert(kPsiTilesPerBin == kWave, "the tile pass scans one tile per lane of one wave");
-static_assert(kPsiMaxBins <= 256, "the bin scans take one bin per thread of a 256-thread block");
 
 // Cell indices of a particle from its position alone: 1 if it has a cell,
 // 0 for a position outside a closed box (x == hi goes to the last cell), -1
@@ -146,8 +152,9 @@ __global__ __launch_bounds__(256) void k_psi_count(PsiArgs a)
     for (int t = threadIdx.x; t < ntl; t += blockDim.x) a.blockhist[(int64_t)t * gridDim.x + blockIdx.x] = hist[t];
     if (blockIdx.x == 0 && threadIdx.x == 0) a.blockhist[(int64_t)ntl * gridDim.x] = 0;
     // the same counts summed over the tiles of each bin (the tiles are read
-    // in a rotated order so that the lanes hit different LDS banks)
-    for (int c = threadIdx.x; c < a.pnbins; c += blockDim.x) {
+    // in a rotated order so that the lanes hit different LDS banks); direct
+    // runs use the tile counts themselves
+    for (int c = threadIdx.x; c < (a.direct ? 0 : a.pnbins); c += blockDim.x) {
         const int t0 = c << kPsiTilesPerBinLog;
         unsigned int sum = 0;
         for (int j = 0; j < kPsiTilesPerBin; ++j) {
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(256) void k_psi_count(PsiArgs a)
         }
         a.binhist[(int64_t)c * gridDim.x + blockIdx.x] = sum;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.binhist[(int64_t)a.pnbins * gridDim.x] = 0;
+    if (!a.direct && blockIdx.x == 0 && threadIdx.x == 0) a.binhist[(int64_t)a.pnbins * gridDim.x] = 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         outside += __shfl_xor(outside, o, kWave);
@@ -205,26 +212,29 @@ __device__ inline unsigned int wave_exclusive_sum(unsigned int v, unsigned int& 
 }
 
 // First partition: each block takes its contiguous range of particles in
-// rounds of kPsiRound, forms their records, orders a round's records by bin
-// in LDS (counting sort) and writes them out bin by bin, so a round gives
-// one contiguous run of records per bin and the stores are coalesced.  The
-// slots come from the scanned per-block bin counts of the count pass.
+// rounds of 256 U, forms their records, orders a round's records by bin in
+// LDS (counting sort) and writes them out bin by bin, so a round gives one
+// contiguous run of records per bin and the stores are coalesced.  The
+// slots come from the scanned per-block bin counts of the count pass (a
+// block's share of a bin is one contiguous range, filled round by round).
 template <typename R, int D>
 __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
 {
     constexpr int C = D + 1;
     constexpr int U = PsiRoundPerThread<R>::value;
     constexpr int RB = 256 * U;
+    static_assert(kPsiMaxBins <= 2 * 256, "two bins per thread in the bin scan");
     __shared__ PsiRec<R> stage[RB];
-    __shared__ uint32_t sslot[RB];
-    __shared__ unsigned int cnt[kPsiMaxBins], off[kPsiMaxBins], gbase[kPsiMaxBins], cursor[kPsiMaxBins];
+    // per bin: this round's count, its first position in the stage, global
+    // slot minus stage position, and the block's next global slot
+    __shared__ unsigned int cnt[kPsiMaxBins], off[kPsiMaxBins], delta[kPsiMaxBins], cursor[kPsiMaxBins];
     __shared__ unsigned int ws[4];
     const int tid = threadIdx.x;
     const int nbin = a.pnbins;
-    const int bsh = a.cptlog + kPsiTilesPerBinLog;
-    if (tid < nbin) {
-        cursor[tid] = a.binhist[(int64_t)tid * gridDim.x + blockIdx.x];
-        cnt[tid] = 0;
+    const int bsh = a.cptlog + a.binlog;
+    for (int b = tid; b < nbin; b += 256) {
+        cursor[b] = a.binhist[(int64_t)b * gridDim.x + blockIdx.x];
+        cnt[b] = 0;
     }
     __syncthreads();
     const int64_t N = a.p.count;
@@ -282,26 +292,34 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
             rank[u] = atomicAdd(&cnt[code[u] >> bsh], 1u);
         }
         __syncthreads();
-        const unsigned int c = tid < nbin ? cnt[tid] : 0u;
+        // bins 2 tid and 2 tid + 1
+        const int b0 = 2 * tid;
+        const unsigned int c0 = b0 < nbin ? cnt[b0] : 0u, c1 = b0 + 1 < nbin ? cnt[b0 + 1] : 0u;
         unsigned int total;
-        const unsigned int ex = block_exclusive_sum(c, ws, total);
-        if (tid < nbin) {
-            off[tid] = ex;
-            gbase[tid] = cursor[tid];
-            cursor[tid] += c;
-            cnt[tid] = 0;
+        const unsigned int ex = block_exclusive_sum(c0 + c1, ws, total);
+        if (b0 < nbin) {
+            off[b0] = ex;
+            delta[b0] = cursor[b0] - ex;
+            cursor[b0] += c0;
+            cnt[b0] = 0;
+        }
+        if (b0 + 1 < nbin) {
+            off[b0 + 1] = ex + c0;
+            delta[b0 + 1] = cursor[b0 + 1] - (ex + c0);
+            cursor[b0 + 1] += c1;
+            cnt[b0 + 1] = 0;
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (code[u] < 0) continue;
-            const int b = code[u] >> bsh;
-            const unsigned int pos = off[b] + rank[u];
-            stage[pos] = rec[u];
-            sslot[pos] = gbase[b] + rank[u];
+            stage[off[code[u] >> bsh] + rank[u]] = rec[u];
         }
         __syncthreads();
-        for (unsigned int i = tid; i < total; i += 256) binned[sslot[i]] = stage[i];
+        for (unsigned int i = tid; i < total; i += 256) {
+            const PsiRec<R> r = stage[i];
+            binned[delta[(r.loc & ~kPsiSkipBit) >> bsh] + i] = r;
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, kWave);
@@ -453,8 +471,11 @@ __global__ void k_psi_scale(PsiArgs a)
 }
 
 // One workgroup per tile: exact integer sums in LDS, then the tile's cells.
-template <typename R, int D>
-__global__ __launch_bounds__(256) void k_psi_reduce(PsiArgs a)
+// Records come from the tile pass (cell in tile, or kPsiSkip) or straight
+// from the scatter (the whole code, with the skip bit); both carry the cell
+// in the low bits and the skip bit set when skipped.
+template <typename R, int D, int NT>
+__global__ __launch_bounds__(NT) void k_psi_reduce(PsiArgs a)
 {
     constexpr int C = D + 1;
     constexpr int W = PsiWords<R>::value;           // integer words per channel sum
@@ -485,8 +506,8 @@ __global__ __launch_bounds__(256) void k_psi_reduce(PsiArgs a)
         }
 #pragma unroll
         for (int u = 0; u < kPsiUnrollReduce; ++u) {
-            if (rec[u].loc == kPsiSkip) continue;
-            const int loc = (int)rec[u].loc;
+            if (rec[u].loc & kPsiSkipBit) continue;
+            const int loc = (int)(rec[u].loc & (uint32_t)(cpt - 1));
 #pragma unroll
             for (int k = 0; k < C; ++k) {
                 const double v = (double)rec[u].phi[k] * qs[k];   // exact: a power-of-two scale
@@ -907,15 +928,24 @@ hipError_t launch_psicell(const PsiArgs& a, hipStream_t s)
         FLA_LAUNCH((k_psi_count<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
         e = launch_exclusive_scan_u32(a.blockhist, (int64_t)a.pntiles * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
         if (e != hipSuccess) return e;
-        e = launch_exclusive_scan_u32(a.binhist, (int64_t)a.pnbins * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
-        if (e != hipSuccess) return e;
+        if (!a.direct) {
+            e = launch_exclusive_scan_u32(a.binhist, (int64_t)a.pnbins * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
+            if (e != hipSuccess) return e;
+        }
         FLA_LAUNCH((k_psi_scatter<R, D>), dim3(a.nblocks), dim3(256), 0, s, a);
     }
     FLA_LAUNCH((k_psi_scale<D>), dim3(1), dim3(256), 0, s, a);
-    if (a.p.count > 0)
+    if (a.p.count > 0 && !a.direct)
         FLA_LAUNCH((k_psi_tiles<R, D>), dim3(a.pnbins * a.nsplit), dim3(256), 0, s, a);
     size_t lds_r = (sizeof(unsigned long long) * C * PsiWords<R>::value + sizeof(unsigned int)) * (size_t)a.cpt;
-    FLA_LAUNCH((k_psi_reduce<R, D>), dim3(a.pntiles), dim3(256), lds_r, s, a);
+    if (a.direct) {
+        e = hipFuncSetAttribute((const void*)k_psi_reduce<R, D, kPsiDirectThreads>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
+        if (e != hipSuccess) return e;
+        FLA_LAUNCH((k_psi_reduce<R, D, kPsiDirectThreads>), dim3(a.pntiles), dim3(kPsiDirectThreads), lds_r, s, a);
+    }
+    else
+        FLA_LAUNCH((k_psi_reduce<R, D, 256>), dim3(a.pntiles), dim3(256), lds_r, s, a);
     return hipGetLastError();
 }
 

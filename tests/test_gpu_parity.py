@@ -376,11 +376,16 @@ def test_psicell_binary64_100m_particles_sampled_cells(ctx):
     assert np.array_equal(den[cells].cpu().numpy().astype(np.int64), counts[cells])
 
 
-def test_psicell_many_bins_with_skipped_records_f32(ctx):
-    # 100^3 cells: 7 x 13 x 13 = 1183 tiles of 16 x 8 x 8 cells, so 19 bins
-    # of 64 tiles with a partial last bin; particles outside the closed box and records
-    # with non-finite velocity or radius are spread over all of them
-    wl = W.small_random_3d(10, 100, seed=21, periodic=False)
+@pytest.mark.parametrize("n", [100, 160])
+def test_psicell_many_bins_with_skipped_records_f32(ctx, n):
+    # 100^3 cells: 7^3 = 343 tiles of 16^3 cells with partial tiles on every
+    # axis, few enough to be the scatter's bins (no tile pass); 160^3 cells
+    # would take 1000 such tiles, so the two partitions run: 10 x 20 x 20 =
+    # 4000 tiles of 16 x 8 x 8 cells in 63 bins of 64 with a partial last bin.
+    # Particles outside the closed box and records with non-finite velocity
+    # or radius are spread over all of them
+    print(f"[case] psicell many bins f32 n={n}", flush=True)
+    wl = W.small_random_3d(10, n, seed=21, periodic=False)
     cloud = W.abc_cloud(2_000_000, seed=21)
     cloud.x = cloud.x * 1.1 - 0.05
     cloud.r[::997] = float("nan")
@@ -394,9 +399,14 @@ def test_psicell_many_bins_with_skipped_records_f32(ctx):
     assert st["outside"] == out and out > 4000 and st["skipped"] == nf and nf > 2000
 
 
-def test_psicell_many_bins_2d_f64(ctx):
-    # 2-D tiles are 32^2 cells: a 1000 x 1000 mesh has 32^2 = 1024 tiles in 16 bins
-    wl = W.taylor_green_2d(per_axis=8, mesh_n=1000)
+@pytest.mark.parametrize("mesh_n", [1000, 1500])
+def test_psicell_many_bins_2d_f64(ctx, mesh_n):
+    # binary64 2-D: 1000^2 cells are 16 x 32 = 512 tiles of 64 x 32 cells,
+    # the scatter's bins themselves; 1500^2 cells would take 24 x 47 = 1128
+    # such tiles, so the two partitions run over 47^2 = 2209 tiles of 32^2
+    # cells in 35 bins
+    print(f"[case] psicell many bins 2-D f64 n={mesh_n}", flush=True)
+    wl = W.taylor_green_2d(per_axis=8, mesh_n=mesh_n)
     cloud = W.taylor_green_cloud(3_000_000, seed=22)
     w = W.N0_DEFAULT / cloud.count
     S, den, st = gpu_run(ctx, wl, prec="f64", psicell_cloud=cloud, weight=w)
