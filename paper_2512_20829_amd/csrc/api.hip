@@ -516,14 +516,17 @@ fla_status batch_impl(fla_ctx* ctx, int nsnap, const MeshDev* md, const TrajDev*
     }
     const uint32_t nb = (uint32_t)nbk;
     const int key_bits = bits_for(nb);
+    int ncu = 0;
+    HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
     const int64_t hist_w = radix_hist_words(total);
     const int64_t scan_w = scan_tmp_words(hist_w > (int64_t)nb + 1 ? hist_w : (int64_t)nb + 1);
     const int64_t n1 = total > 0 ? total : 1;
 
-    uint32_t *keys, *vals, *keys2, *vals2, *bstart, *hist, *scan;
+    uint32_t *keys, *vals, *keys2, *vals2, *bstart, *hist, *scan, *queue;
     double4 *rpos_u, *rpos;
     R *rw_u, *rw;
     auto layout = [&](Carver& c) {
+        queue = c.take<uint32_t>(kXcds);
         keys = c.take<uint32_t>(n1);
         vals = c.take<uint32_t>(n1);
         keys2 = c.take<uint32_t>(n1);
@@ -630,7 +633,8 @@ fla_status batch_impl(fla_ctx* ctx, int nsnap, const MeshDev* md, const TrajDev*
             bool general = false;     // any rectilinear axis in the batch
             for (int i = 0; i < nsnap; ++i)
                 for (int a = 0; a < 3; ++a) general = general || md[i].edges[a] != nullptr;
-            HIP_OK((launch_gather_batch<R, D>(dev_items, nsnap, (int)nwork, chunk, count, plan, general, q)));
+            HIP_OK((launch_gather_batch<R, D>(dev_items, nsnap, (int)nwork, chunk, count, plan, general, queue,
+                                              ncu, q)));
         }
         return FLA_OK;
     };

@@ -910,24 +910,43 @@ __device__ inline int batch_work_item(int bid, int nwork, int chunk)
     return c * span + (off % kXcds) * chunk + off / kXcds;
 }
 
-// One workgroup per (snapshot, tile) of a batch.  The snapshots are stored in
-// work-list order: items[s].tile_base is the first work item of snapshot s.
+// Persistent workgroups over the work items of a batch, one (snapshot,
+// tile part) at a time.  The snapshots are stored in work-list order:
+// items[s].tile_base is the first work item of snapshot s.  Slot b of the
+// ordered launch (batch_work_item) belongs to XCD b % kXcds; each XCD has
+// its own counter (queue[x], zeroed before the launch), from which its
+// workgroups take that XCD's slots x, x + kXcds, ... in order until they
+// pass the end.  Every item is taken exactly once, by a workgroup of the XCD
+// the ordered launch gives it, and a workgroup that finishes early takes the
+// next one instead of waiting for the dispatcher (on the 64-snapshot batch
+// 37.5 against 38.4 ms).  Which workgroup computes an item does not change
+// its results.
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
 __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::value)) void k_gather_batch(
-    const BatchItem* __restrict__ items, int nsnap, int nwork, int chunk)
+    const BatchItem* __restrict__ items, int nsnap, int nwork, int chunk, uint32_t* __restrict__ queue)
 {
     constexpr int TP = TileParts<D>::value;
-    const int u = batch_work_item(blockIdx.x, nwork * TP, chunk);
-    const int j = u / TP;         // tile-level work item
-    int lo = 0, hi = nsnap - 1;   // last snapshot whose first work item is <= j
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (items[mid].tile_base <= j)
-            lo = mid;
-        else
-            hi = mid - 1;
+    __shared__ int s_slot;
+    const int total = nwork * TP;
+    const int x = blockIdx.x % kXcds;
+    for (;;) {
+        __syncthreads();   // every lane has read the previous slot
+        if (threadIdx.x == 0) s_slot = x + kXcds * (int)atomicAdd(&queue[x], 1u);
+        __syncthreads();
+        const int slot = s_slot;
+        if (slot >= total) break;
+        const int u = batch_work_item(slot, total, chunk);
+        const int j = u / TP;         // tile-level work item
+        int lo = 0, hi = nsnap - 1;   // last snapshot whose first work item is <= j
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].tile_base <= j)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        gather_tile<R, D, MODE, COUNT, PLAN>(items[lo].g, (j - items[lo].tile_base) * TP + u % TP);
     }
-    gather_tile<R, D, MODE, COUNT, PLAN>(items[lo].g, (j - items[lo].tile_base) * TP + u % TP);
 }
 
 template <typename R, int D, int MODE, bool COUNT>
@@ -942,32 +961,42 @@ static void launch_plan(const GatherArgs& g, int plan, dim3 grid, dim3 block, hi
 }
 
 template <typename R, int D, int MODE, bool COUNT>
-static void launch_batch_plan(const BatchItem* items, int nsnap, int nwork, int chunk, int plan, hipStream_t s)
+static void launch_batch_plan(const BatchItem* items, int nsnap, int nwork, int chunk, int plan, uint32_t* queue,
+                              int ncu, hipStream_t s)
 {
-    dim3 grid((unsigned)(nwork * TileParts<D>::value)), block(kWave * GatherWaves<D>::value);
+    // as many workgroups as the compute units hold at once (waves per SIMD
+    // from the register budget, 4 SIMDs per unit), at most one per item
+    int64_t nb = (int64_t)(ncu > 0 ? ncu : 1) * GatherOcc<R, D>::value * 4 / GatherWaves<D>::value;
+    const int64_t total = (int64_t)nwork * TileParts<D>::value;
+    if (nb > total) nb = total;
+    if (nb < 1) nb = 1;
+    dim3 grid((unsigned)nb), block(kWave * GatherWaves<D>::value);
     switch (plan) {
-    case 1: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 1>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
-    case 2: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 2>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
-    case 3: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 3>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
-    default: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 0>), grid, block, 0, s, items, nsnap, nwork, chunk); break;
+    case 1: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 1>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
+    case 2: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 2>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
+    case 3: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 3>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
+    default: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 0>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
     }
 }
 
 template <typename R, int D>
 hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan,
-                               bool general, hipStream_t s)
+                               bool general, uint32_t* queue, int ncu, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
+    // the XCD counters start at zero (a fill kernel: the launch may be captured)
+    hipError_t e = launch_fill_u32(queue, kXcds, 0u, s);
+    if (e != hipSuccess) return e;
     if (general) {
         if (count)
-            launch_batch_plan<R, D, kNwGeneral, true>(items, nsnap, nwork, chunk, plan, s);
+            launch_batch_plan<R, D, kNwGeneral, true>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
         else
-            launch_batch_plan<R, D, kNwGeneral, false>(items, nsnap, nwork, chunk, plan, s);
+            launch_batch_plan<R, D, kNwGeneral, false>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
     } else {
         if (count)
-            launch_batch_plan<R, D, FLA_NW, true>(items, nsnap, nwork, chunk, plan, s);
+            launch_batch_plan<R, D, FLA_NW, true>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
         else
-            launch_batch_plan<R, D, FLA_NW, false>(items, nsnap, nwork, chunk, plan, s);
+            launch_batch_plan<R, D, FLA_NW, false>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
     }
     return hipGetLastError();
 }
@@ -1006,9 +1035,13 @@ template hipError_t launch_gather<float, 2>(const GatherArgs&, int, bool, int, h
 template hipError_t launch_gather<float, 3>(const GatherArgs&, int, bool, int, hipStream_t);
 template hipError_t launch_gather<double, 2>(const GatherArgs&, int, bool, int, hipStream_t);
 template hipError_t launch_gather<double, 3>(const GatherArgs&, int, bool, int, hipStream_t);
-template hipError_t launch_gather_batch<float, 2>(const BatchItem*, int, int, int, bool, int, bool, hipStream_t);
-template hipError_t launch_gather_batch<float, 3>(const BatchItem*, int, int, int, bool, int, bool, hipStream_t);
-template hipError_t launch_gather_batch<double, 2>(const BatchItem*, int, int, int, bool, int, bool, hipStream_t);
-template hipError_t launch_gather_batch<double, 3>(const BatchItem*, int, int, int, bool, int, bool, hipStream_t);
+template hipError_t launch_gather_batch<float, 2>(const BatchItem*, int, int, int, bool, int, bool, uint32_t*, int,
+                                                  hipStream_t);
+template hipError_t launch_gather_batch<float, 3>(const BatchItem*, int, int, int, bool, int, bool, uint32_t*, int,
+                                                  hipStream_t);
+template hipError_t launch_gather_batch<double, 2>(const BatchItem*, int, int, int, bool, int, bool, uint32_t*, int,
+                                                   hipStream_t);
+template hipError_t launch_gather_batch<double, 3>(const BatchItem*, int, int, int, bool, int, bool, uint32_t*, int,
+                                                   hipStream_t);
 
 }  // namespace flp

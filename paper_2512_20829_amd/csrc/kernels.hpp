@@ -41,9 +41,11 @@ hipError_t launch_prepass_batch(const BatchItem* items, int nsnap, int64_t total
                                 uint32_t* vals, double4* rpos, R* rw, unsigned long long* stats, hipStream_t s);
 hipError_t launch_max_class_batch(const BatchItem* items, int nsnap, const uint32_t* bstart,
                                   unsigned long long* stats, hipStream_t s);
+// Persistent gather over the work items of a batch; queue holds kXcds
+// counters of workspace (zeroed by the launcher), ncu the compute units.
 template <typename R, int D>
 hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan,
-                               bool general, hipStream_t s);
+                               bool general, uint32_t* queue, int ncu, hipStream_t s);
 
 // Trajectory producer: the gas field and the droplet state it advances.
 struct FlowDev {
