@@ -370,7 +370,7 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
 
     auto layout = [&](Carver& c, uint32_t** keys, uint32_t** vals, uint32_t** keys2, uint32_t** vals2,
                       double4** rpos_u, double4** rpos, R** rw_u, R** rw, double** qd, uint32_t** bstart,
-                      uint32_t** hist, uint32_t** scan, uint32_t** tcost, int** order) {
+                      uint32_t** hist, uint32_t** scan, uint32_t** tcost, int** order, uint32_t** queue) {
         *keys = c.take<uint32_t>(N);
         *vals = c.take<uint32_t>(N);
         *keys2 = c.take<uint32_t>(N);
@@ -385,8 +385,9 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
         *scan = c.take<uint32_t>(scan_w);
         *tcost = c.take<uint32_t>(m.ntiles > 0 ? m.ntiles : 1);
         *order = c.take<int>(m.ntiles > 0 ? 2 * (size_t)m.ntiles : 1);
+        *queue = c.take<uint32_t>(kXcds);
     };
-    uint32_t *keys, *vals, *keys2, *vals2, *bstart, *hist, *scan, *tcost;
+    uint32_t *keys, *vals, *keys2, *vals2, *bstart, *hist, *scan, *tcost, *queue;
     int* order;
     double4 *rpos_u, *rpos;
     R *rw_u, *rw;
@@ -394,7 +395,7 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
     {
         Carver probe(nullptr);
         layout(probe, &keys, &vals, &keys2, &vals2, &rpos_u, &rpos, &rw_u, &rw, &qd, &bstart, &hist, &scan, &tcost,
-               &order);
+               &order, &queue);
         if (fixed) {
             CHECK_ARG(probe.off + 256 <= fixed_size,
                       "these inputs need " + std::to_string(probe.off + 256) +
@@ -406,7 +407,8 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
         }
     }
     Carver c(fixed ? fixed : ctx->ws);
-    layout(c, &keys, &vals, &keys2, &vals2, &rpos_u, &rpos, &rw_u, &rw, &qd, &bstart, &hist, &scan, &tcost, &order);
+    layout(c, &keys, &vals, &keys2, &vals2, &rpos_u, &rpos, &rw_u, &rw, &qd, &bstart, &hist, &scan, &tcost, &order,
+           &queue);
 
     PhysDev ph{p->rho_d, p->mu, p->delta, p->h0, p->cutoff, p->scale};
     HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
@@ -452,6 +454,8 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
     g.stats = ctx->stats;
     g.tile_cost = tcost;
     g.order = order;
+    g.queue = queue;
+    HIP_OK(hipDeviceGetAttribute(&g.ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
     {
         StageTimer tm(ctx, 3, s);
         int plan = ctx->plan[D - 2][sizeof(R) == 8 ? 1 : 0];

@@ -819,12 +819,35 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
     }
 }
 
+// Slot b of the launch belongs to XCD b % kXcds and computes the work item
+// order[xcd_remap(b)] (the heaviest items of each XCD first).  Without a
+// queue every workgroup takes its own slot; with one, the workgroups (as many
+// as the compute units hold) take their XCD's slots x, x + kXcds, ... in
+// order from that XCD's counter until they pass the end, so a workgroup that
+// finishes early starts the next item at once (128^3: 4.93 -> 4.80 ms).  Which
+// workgroup computes an item does not change its results.
 template <typename R, int D, int MODE, bool COUNT, int PLAN>
 __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::value)) void k_gather(GatherArgs g)
 {
-    int w = xcd_remap(blockIdx.x, g.m.ntiles * TileParts<D>::value);
-    if (g.order) w = g.order[w];
-    gather_tile<R, D, MODE, COUNT, PLAN>(g, w);
+    const int total = g.m.ntiles * TileParts<D>::value;
+    if (!g.queue) {
+        int w = xcd_remap(blockIdx.x, total);
+        if (g.order) w = g.order[w];
+        gather_tile<R, D, MODE, COUNT, PLAN>(g, w);
+        return;
+    }
+    __shared__ int s_slot;
+    const int x = blockIdx.x % kXcds;
+    for (;;) {
+        __syncthreads();   // every lane has read the previous slot
+        if (threadIdx.x == 0) s_slot = x + kXcds * (int)atomicAdd(&g.queue[x], 1u);
+        __syncthreads();
+        const int slot = s_slot;
+        if (slot >= total) break;
+        int w = xcd_remap(slot, total);
+        if (g.order) w = g.order[w];
+        gather_tile<R, D, MODE, COUNT, PLAN>(g, w);
+    }
 }
 
 // Estimated work of every tile: the number of candidate records its scan
@@ -1010,7 +1033,16 @@ hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hi
         FLA_LAUNCH(k_tile_order, dim3(kXcds), dim3(1024), 0, s, (const uint32_t*)g.tile_cost,
                            g.m.ntiles * TileParts<D>::value, TileParts<D>::value, g.order);
     }
-    dim3 grid((unsigned)(g.m.ntiles * TileParts<D>::value)), block(kWave * GatherWaves<D>::value);
+    int64_t nb = (int64_t)g.m.ntiles * TileParts<D>::value;
+    if (g.queue) {
+        // as many workgroups as the compute units hold at once; the XCD
+        // counters start at zero (a fill kernel: the launch may be captured)
+        const int64_t fit = (int64_t)(g.ncu > 0 ? g.ncu : 1) * GatherOcc<R, D>::value * 4 / GatherWaves<D>::value;
+        if (fit < nb) nb = fit;
+        hipError_t e = launch_fill_u32(g.queue, kXcds, 0u, s);
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid((unsigned)nb), block(kWave * GatherWaves<D>::value);
     const bool general = g.m.edges[0] || g.m.edges[1] || g.m.edges[2];
     if (mode == FLA_NW && general) {
         if (count)

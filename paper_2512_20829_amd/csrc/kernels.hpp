@@ -23,6 +23,10 @@ struct GatherArgs {
     // single-snapshot gather, ntiles cost words and 2 * ntiles slot entries
     uint32_t* tile_cost;
     int* order;
+    // optional: kXcds counters of workspace for a persistent launch of ncu
+    // compute units' worth of workgroups (null: one workgroup per work item)
+    uint32_t* queue;
+    int ncu;
 };
 
 // One snapshot of a batched projection (device table entry).
