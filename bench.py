@@ -88,7 +88,7 @@ def gather_traffic(workload: str):
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
-    for name in ("gather.hip", "internal.hpp"):     # the kernel and its compile-time constants
+    for name in ("gather.hpp", "internal.hpp"):     # the kernel and its compile-time constants
         h.update(open(os.path.join(ROOT, "paper_2512_20829_amd", "csrc", name), "rb").read())
     digest = h.hexdigest()[:16]
     vals = {}
@@ -96,7 +96,7 @@ def gather_traffic(workload: str):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].rsplit(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("gather.hip + internal.hpp sha256[:16]") != digest:
+    if vals.get("gather.hpp + internal.hpp sha256[:16]") != digest:
         return None
     try:
         return float(vals["bytes per launch (calibrated)"])

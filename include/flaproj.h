@@ -295,28 +295,40 @@ typedef struct {
 fla_status fla_profile_enable(fla_ctx* ctx, int on);
 fla_status fla_profile_read(fla_ctx* ctx, fla_profile* out);
 
-/* Gather plan: the granularity at which the gather skips the sub-blocks
- * (blocks of 4^3 or 8^2 cells) that a trajectory cannot reach.  In 3-D a
- * workgroup owns half of a tile along x (4 sub-blocks); in 2-D a whole tile
- * (4 sub-blocks).
+/* Gather plan code: plan + FLA_GATHER_PLANS * shape.
+ * The plan is the granularity at which the gather skips the sub-blocks
+ * (blocks of 4^3 or 8^2 cells) that a trajectory cannot reach:
  *   0: each sub-block;
  *   1: pairs of sub-blocks along z (3-D, the default; the binary32 loop,
  *      which takes four trajectories per step, adds a test per sub-block);
  *   2, 3: only the workgroup's whole part.
- * In 2-D, plans 1-3 skip only the whole tile.  Every plan produces the same
- * values (up to the sign of zero); they differ only in speed.  Plans are
- * kept per (dim, prec) in the context; -1 restores the library default.
+ * In 2-D, plans 1-3 skip only the whole tile.
+ * The shape is the part of a tile (8^3 or 16^2 cells) one workgroup owns:
+ *   0: in 3-D half a tile along x (4 sub-blocks; the default), in 2-D the
+ *      whole tile;
+ *   1: the whole tile in 3-D (8 sub-blocks: the candidates are scanned and
+ *      staged once per tile instead of once per half, with fewer workgroups
+ *      per compute unit); not in 2-D.
+ * So codes 0..7 are valid in 3-D and 0..3 in 2-D.  Under one shape every
+ * plan produces the same values (up to the sign of zero); they differ only
+ * in speed.  Between shapes, binary64 values are the same as well; binary32
+ * values can differ by the rounding of the compensated sums, whose partial
+ * sums are folded at other points.  Codes are kept per (dim, prec) in the
+ * context; -1 restores the library default (code 1).
  * Errors: INVALID_ARG for out-of-range arguments. */
 #define FLA_GATHER_PLANS 4
+#define FLA_GATHER_SHAPES 2
+#define FLA_GATHER_CONFIGS (FLA_GATHER_PLANS * FLA_GATHER_SHAPES)
 fla_status fla_set_plan(fla_ctx* ctx, int dim, int prec, int gather_plan);
 fla_status fla_get_plan(fla_ctx* ctx, int dim, int prec, int* gather_plan);
 
-/* Autotuner: runs fla_project_sources once per gather plan on the given
- * inputs (a warm-up call, then a call timed with HIP events), keeps the
- * fastest plan for (mesh->dim, traj->prec) in the context and, if times_ms
- * (host, FLA_GATHER_PLANS values) is not NULL, returns the gather time of
- * each plan.  Synchronises the device.  out receives the projection.
- * Errors as fla_project_sources. */
+/* Autotuner: runs fla_project_sources once per gather plan code of the
+ * mesh's dimension on the given inputs (a warm-up call, then a call timed
+ * with HIP events), keeps the fastest code for (mesh->dim, traj->prec) in the
+ * context and, if times_ms (host, FLA_GATHER_CONFIGS values, index = code) is
+ * not NULL, returns the gather time of each code (-1 for codes the
+ * dimension does not have).  Synchronises the device.  out receives the
+ * projection.  Errors as fla_project_sources. */
 fla_status fla_autotune(fla_ctx* ctx, const fla_mesh* mesh, const fla_trajectories* traj,
                         const fla_params* params, const fla_fields* out, void* stream,
                         double* times_ms);
@@ -530,7 +542,7 @@ fla_status fla_project_batch(fla_ctx* ctx, int nsnap, const fla_mesh* meshes, co
  * launches directly.  Drops the cached graph.  Errors: INVALID_ARG. */
 fla_status fla_set_batch_graph(fla_ctx* ctx, int enable);
 
-/* Batch plan per (dim, prec): the gather plan (as fla_set_plan) and the
+/* Batch plan per (dim, prec): the gather plan code (as fla_set_plan) and the
  * XCD chunk, the number of consecutive work items (tiles) that one of the
  * eight XCDs receives from each run of 8 * chunk items, 1..4096.
  * gather_plan == -1 restores the library defaults (chunk is then ignored).
@@ -539,12 +551,13 @@ fla_status fla_set_batch_plan(fla_ctx* ctx, int dim, int prec, int gather_plan, 
 fla_status fla_get_batch_plan(fla_ctx* ctx, int dim, int prec, int* gather_plan, int* chunk);
 
 /* Batch autotuner: runs fla_project_batch directly (no graph) for every
- * gather plan and every chunk in {1, 4, 16, 64} (a warm-up call, then a call
- * whose gather launch is timed with HIP events), keeps the fastest pair for
- * (dim, prec) and, if times_ms (host, FLA_GATHER_PLANS * FLA_BATCH_CHUNKS
- * values, index plan * FLA_BATCH_CHUNKS + chunk index) is not NULL, returns
- * every gather time.  Synchronises the device; outs receive the projection.
- * Errors as fla_project_batch. */
+ * gather plan code of the dimension and every chunk in {1, 4, 16, 64} (a
+ * warm-up call, then a call whose gather launch is timed with HIP events),
+ * keeps the fastest pair for (dim, prec) and, if times_ms (host,
+ * FLA_GATHER_CONFIGS * FLA_BATCH_CHUNKS values, index code *
+ * FLA_BATCH_CHUNKS + chunk index, -1 for codes the dimension does not have)
+ * is not NULL, returns every gather time.  Synchronises the device; outs
+ * receive the projection.  Errors as fla_project_batch. */
 #define FLA_BATCH_CHUNKS 4
 fla_status fla_autotune_batch(fla_ctx* ctx, int nsnap, const fla_mesh* meshes, const fla_trajectories* trajs,
                               const fla_params* params, const fla_fields* outs, void* stream,

@@ -77,6 +77,8 @@ PROFILE_STAGES = ["prepass", "sort", "deposit_norm", "gather", "psicell", "mlp_f
 MLP_TRAINABLE = 4609
 MLP_PARAMS = 4619
 GATHER_PLANS = 4
+GATHER_SHAPES = 2
+GATHER_CONFIGS = GATHER_PLANS * GATHER_SHAPES   # plan codes: plan + GATHER_PLANS * shape
 BATCH_CHUNKS = 4
 BATCH_MAX = 65536
 
@@ -530,8 +532,9 @@ class Context:
 
     def autotune(self, mesh: fla_mesh, traj: fla_trajectories, params: Params, S_mass, S_mom, den=None,
                  stream=None):
-        """Time every gather plan on these inputs, keep the fastest; returns the per-plan ms."""
-        t = (C.c_double * GATHER_PLANS)()
+        """Time every gather plan code on these inputs, keep the fastest; returns the ms per code
+        (GATHER_CONFIGS values, -1 for codes the dimension does not have)."""
+        t = (C.c_double * GATHER_CONFIGS)()
         self._check(_lib.fla_autotune(self._h, C.byref(mesh), C.byref(traj), C.byref(params.to_c()),
                                       C.byref(make_fields(S_mass, S_mom, den)), _stream_handle(stream), t))
         return [float(v) for v in t]
@@ -620,9 +623,9 @@ class Context:
 
     def autotune_batch(self, meshes: Sequence, trajs: Sequence, params: Sequence, outs: Sequence,
                        stream=None) -> list:
-        """Returns the gather time (ms) of every (plan, chunk) tried, plan-major."""
+        """Returns the gather time (ms) of every (plan code, chunk), code-major (-1: not tried)."""
         n, M, T, P, F = self._batch_arrays(meshes, trajs, params, outs)
-        times = (C.c_double * (GATHER_PLANS * BATCH_CHUNKS))()
+        times = (C.c_double * (GATHER_CONFIGS * BATCH_CHUNKS))()
         self._check(_lib.fla_autotune_batch(self._h, n, M, T, P, F, _stream_handle(stream), times))
         return list(times)
 

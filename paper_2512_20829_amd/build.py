@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libflaproj.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "prepass.hip", "produce.hip", "sort.hip", "gather.hip", "psicell.hip", "learned.hip", "cells.hip"]
+SOURCES = ["gather_f32_3d.hip", "gather_f64_3d.hip", "gather_f32_2d.hip", "gather_f64_2d.hip", "api.hip",
+           "prepass.hip", "produce.hip", "sort.hip", "psicell.hip", "learned.hip", "cells.hip"]
 
 CFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fno-fast-math",

@@ -1403,13 +1403,17 @@ FLA_EXPORT fla_status fla_profile_read(fla_ctx* ctx, fla_profile* out)
     return FLA_OK;
 }
 
+// gather plan codes of a dimension: plan + kGatherPlans * shape
+static_assert(FLA_GATHER_PLANS == kGatherPlans && FLA_GATHER_SHAPES == kGatherShapes, "plan codes of the header");
+static int plan_codes(int dim) { return dim == 3 ? gather_plan_codes<3>() : gather_plan_codes<2>(); }
+
 FLA_EXPORT fla_status fla_set_plan(fla_ctx* ctx, int dim, int prec, int gather_plan)
 {
     if (!ctx) return FLA_ERR_INVALID_ARG;
     ctx->err.clear();
     CHECK_ARG(dim == 2 || dim == 3, "dim must be 2 or 3");
     CHECK_ARG(prec == FLA_F32 || prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
-    CHECK_ARG(gather_plan >= -1 && gather_plan < kGatherPlans, "gather_plan out of range");
+    CHECK_ARG(gather_plan >= -1 && gather_plan < plan_codes(dim), "gather_plan out of range");
     ctx->plan[dim - 2][prec] = gather_plan;
     return FLA_OK;
 }
@@ -1444,7 +1448,9 @@ FLA_EXPORT fla_status fla_autotune(fla_ctx* ctx, const fla_mesh* mesh, const fla
     if (st != FLA_OK) return st;
     double best = 1e300;
     int best_plan = saved < 0 ? kDefaultPlan : saved;
-    for (int plan = 0; plan < kGatherPlans; ++plan) {
+    if (times_ms)
+        for (int k = 0; k < FLA_GATHER_CONFIGS; ++k) times_ms[k] = -1.0;
+    for (int plan = 0; plan < plan_codes(mesh->dim); ++plan) {
         ctx->plan[d][pr] = plan;
         // first call warms the workspace, the second is timed
         for (int rep = 0; rep < 2; ++rep) {
@@ -1512,7 +1518,7 @@ FLA_EXPORT fla_status fla_set_batch_plan(fla_ctx* ctx, int dim, int prec, int ga
     ctx->err.clear();
     CHECK_ARG(dim == 2 || dim == 3, "dim must be 2 or 3");
     CHECK_ARG(prec == FLA_F32 || prec == FLA_F64, "prec must be FLA_F32 or FLA_F64");
-    CHECK_ARG(gather_plan >= -1 && gather_plan < kGatherPlans, "gather_plan out of range");
+    CHECK_ARG(gather_plan >= -1 && gather_plan < plan_codes(dim), "gather_plan out of range");
     CHECK_ARG(gather_plan == -1 || (chunk >= 1 && chunk <= 4096), "chunk must be in [1, 4096]");
     ctx->batch_plan[dim - 2][prec] = gather_plan;
     ctx->batch_chunk[dim - 2][prec] = gather_plan < 0 ? -1 : chunk;
@@ -1547,7 +1553,9 @@ FLA_EXPORT fla_status fla_autotune_batch(fla_ctx* ctx, int nsnap, const fla_mesh
     int best_plan = -1, best_chunk = -1;
     fla_status st = FLA_OK;
     try {
-        for (int plan = 0; plan < kGatherPlans && st == FLA_OK; ++plan)
+        if (times_ms)
+            for (int k = 0; k < FLA_GATHER_CONFIGS * FLA_BATCH_CHUNKS; ++k) times_ms[k] = -1.0;
+        for (int plan = 0; plan < plan_codes(meshes[0].dim) && st == FLA_OK; ++plan)
             for (int ci = 0; ci < FLA_BATCH_CHUNKS && st == FLA_OK; ++ci) {
                 // first call warms the workspace, the second is timed
                 st = fla_profile_enable(ctx, 0);

@@ -32,6 +32,15 @@
 //    two lane permutations of the masks);
 //  * binary32 partial sums of one batch are folded into compensated
 //    (TwoSum) totals, binary64 sums need no compensation.
+//
+// The tile part a workgroup owns is its shape: half a tile along x (the 3-D
+// default, TP = 2) or the whole tile (TP = 1; always in 2-D).  Plan codes
+// plan + kGatherPlans * shape select both (fla_autotune times them all).
+//
+// This header holds the kernels and their launchers; the units
+// gather_{f32,f64}_{2d,3d}.hip instantiate them per precision and dimension,
+// so that they compile in parallel.
+#pragma once
 #include "internal.hpp"
 #include "kernels.hpp"
 
@@ -77,23 +86,24 @@ __device__ inline void two_sum_acc(R& hi, R& lo, R p)
 // tiles have twice the cells per axis and whose staging tables are larger
 template <int D> struct GatherWaves { static constexpr int value = D == 3 ? 4 : 2; };
 
-// Workgroups per tile: in 3-D each workgroup owns one half of the tile along
-// x (4 of its 8 sub-blocks), which halves the registers of its sums and its
-// staging space, so that more workgroups share a compute unit.  (Along x: the
-// inclusion sum is ((s_x + s_y) + s_z), so sub-blocks paired along z still
-// share their partial sum s_x + s_y.)
-template <int D> struct TileParts { static constexpr int value = D == 3 ? 2 : 1; };
+// Workgroups per tile (the shape).  With TP = 2 (3-D only) each workgroup
+// owns one half of the tile along x (4 of its 8 sub-blocks), which halves
+// the registers of its sums and its staging space, so that more workgroups
+// share a compute unit, at the cost of scanning and staging every candidate
+// once per half.  (Along x: the inclusion sum is ((s_x + s_y) + s_z), so
+// sub-blocks paired along z still share their partial sum s_x + s_y.)
+__host__ __device__ constexpr int tile_parts(int D, int shape) { return D == 3 && shape == 0 ? 2 : 1; }
 
 // Waves per SIMD the register allocation is held to.
-template <typename R, int D> struct GatherOcc {
-    static constexpr int value = sizeof(R) == 4 ? (TileParts<D>::value == 2 ? 3 : 2) : 1;
+template <typename R, int D, int TP> struct GatherOcc {
+    static constexpr int value = sizeof(R) == 4 ? (TP == 2 ? 3 : 2) : 1;
 };
 
-template <typename R, int D>
+template <typename R, int D, int TP>
 struct GatherLds {
     using R4 = typename V4<R>::T;
     using R2 = typename V2<R>::T;
-    static constexpr int SB = Geo<D>::SB, NA = D + 2, TP = TileParts<D>::value;
+    static constexpr int SB = Geo<D>::SB, NA = D + 2;
     static constexpr int NT = TP == 2 ? D - 1 : D;   // axes staged for both halves (split: y, z)
     uint32_t cand[kCap];               // compacted candidate record indices
     R4 tab[kWave][NT][SB];             // {s, e} at in-block position l and l + SB
@@ -111,13 +121,13 @@ struct GatherLds {
 // workgroup's sub-blocks: bit b is set iff the sum of the per-axis minima of
 // s over sub-block b passes the cutoff (sums are monotone in each term, so
 // no sub-block holding an included pair is skipped).
-template <typename R, int D>
+template <typename R, int D, int TP>
 __device__ __forceinline__ int stage_record(const MeshDev& m, const double (*xcs)[Geo<D>::TE], const int* tc,
                                             const int soff, const double4 P, const R c2,
                                             typename V4<R>::T (*tab)[Geo<D>::SB], typename V2<R>::T* tabs)
 {
     using G = Geo<D>;
-    constexpr int TE = G::TE, SB = G::SB, NP = 2 * SB, TP = TileParts<D>::value, NSB = G::NSB / TP;
+    constexpr int TE = G::TE, SB = G::SB, NP = 2 * SB, NSB = G::NSB / TP;
     using R4 = typename V4<R>::T;
     using R2 = typename V2<R>::T;
     double x[3] = {P.x, P.y, P.z};
@@ -360,18 +370,18 @@ __device__ __forceinline__ bool candidate_ok(const MeshDev& m, const double4 P, 
 
 // The work of one workgroup: every cell of its part `work % TP` of tile
 // `work / TP` of the mesh of g.
-template <typename R, int D, int MODE, bool COUNT, int PLAN>
+template <typename R, int D, int MODE, bool COUNT, int PLAN, int TP>
 __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
 {
     constexpr int kGatherWaves = GatherWaves<D>::value;
     using G = Geo<D>;
-    constexpr int TP = TileParts<D>::value;
+    static_assert(TP == 1 || D == 3, "tiles are split along x in 3-D only");
     constexpr int TE = G::TE, SB = G::SB, NSB = G::NSB / TP, C = D + 1, NA = C + 1;
-    constexpr int NT = GatherLds<R, D>::NT;
+    constexpr int NT = GatherLds<R, D, TP>::NT;
     constexpr bool kComp = sizeof(R) == 4;
     using R4 = typename V4<R>::T;
     using R2 = typename V2<R>::T;
-    using L = GatherLds<R, D>;
+    using L = GatherLds<R, D, TP>;
     static_assert(sizeof(L) * kGatherWaves >= sizeof(R) * kGatherWaves * NSB * NA * kWave,
                   "reduction buffer must fit in the staging space");
     __shared__ L lds[kGatherWaves];
@@ -478,7 +488,7 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
             const R* w = (const R*)g.rw + (size_t)p * kRecW;
 #pragma unroll
             for (int k = 0; k < NA; ++k) my.wts[lane][k] = w[k];
-            my.mask[lane] = stage_record<R, D>(m, xcs, tc, soff, P, c2, my.tab[lane], my.tabs[lane]);
+            my.mask[lane] = stage_record<R, D, TP>(m, xcs, tc, soff, P, c2, my.tab[lane], my.tabs[lane]);
         }
         wave_sync();
         // every lane keeps the mask of one staged record (read with readlane,
@@ -826,14 +836,14 @@ __device__ __forceinline__ void gather_tile(const GatherArgs& g, const int work)
 // order from that XCD's counter until they pass the end, so a workgroup that
 // finishes early starts the next item at once (128^3: 4.93 -> 4.80 ms).  Which
 // workgroup computes an item does not change its results.
-template <typename R, int D, int MODE, bool COUNT, int PLAN>
-__global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::value)) void k_gather(GatherArgs g)
+template <typename R, int D, int MODE, bool COUNT, int PLAN, int TP>
+static __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D, TP>::value)) void k_gather(GatherArgs g)
 {
-    const int total = g.m.ntiles * TileParts<D>::value;
+    const int total = g.m.ntiles * TP;
     if (!g.queue) {
         int w = xcd_remap(blockIdx.x, total);
         if (g.order) w = g.order[w];
-        gather_tile<R, D, MODE, COUNT, PLAN>(g, w);
+        gather_tile<R, D, MODE, COUNT, PLAN, TP>(g, w);
         return;
     }
     __shared__ int s_slot;
@@ -846,7 +856,7 @@ __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::va
         if (slot >= total) break;
         int w = xcd_remap(slot, total);
         if (g.order) w = g.order[w];
-        gather_tile<R, D, MODE, COUNT, PLAN>(g, w);
+        gather_tile<R, D, MODE, COUNT, PLAN, TP>(g, w);
     }
 }
 
@@ -854,7 +864,7 @@ __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::va
 // visits (the bucket sizes over its class neighbourhoods).  One wave per
 // tile, a row per lane.
 template <int D>
-__global__ __launch_bounds__(256) void k_tile_cost(GatherArgs g)
+static __global__ __launch_bounds__(256) void k_tile_cost(GatherArgs g)
 {
     const MeshDev& m = g.m;
     const int tile = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
@@ -889,7 +899,7 @@ __global__ __launch_bounds__(256) void k_tile_cost(GatherArgs g)
 // ones fill the end.  The order inside a class is immaterial: a work unit's
 // results do not depend on the slot that computes it.
 constexpr int kOrderBins = 33 * 4;
-__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ cost, int nunits, int zs,
+static __global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ cost, int nunits, int zs,
                                                      int* __restrict__ order)
 {
     __shared__ uint32_t cnt[kOrderBins];
@@ -925,7 +935,7 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict_
 // kXcds * chunk items, XCD x receives the `chunk` consecutive items
 // x * chunk ... x * chunk + chunk - 1, so neighbouring tiles of one snapshot
 // share an L2 while the chunks still start in work-list order.
-__device__ inline int batch_work_item(int bid, int nwork, int chunk)
+static __device__ inline int batch_work_item(int bid, int nwork, int chunk)
 {
     const int span = kXcds * chunk;
     const int c = bid / span, off = bid % span;
@@ -944,11 +954,10 @@ __device__ inline int batch_work_item(int bid, int nwork, int chunk)
 // next one instead of waiting for the dispatcher (on the 64-snapshot batch
 // 37.5 against 38.4 ms).  Which workgroup computes an item does not change
 // its results.
-template <typename R, int D, int MODE, bool COUNT, int PLAN>
-__global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::value)) void k_gather_batch(
+template <typename R, int D, int MODE, bool COUNT, int PLAN, int TP>
+static __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D, TP>::value)) void k_gather_batch(
     const BatchItem* __restrict__ items, int nsnap, int nwork, int chunk, uint32_t* __restrict__ queue)
 {
-    constexpr int TP = TileParts<D>::value;
     __shared__ int s_slot;
     const int total = nwork * TP;
     const int x = blockIdx.x % kXcds;
@@ -968,76 +977,97 @@ __global__ __launch_bounds__(kWave * GatherWaves<D>::value, (GatherOcc<R, D>::va
             else
                 hi = mid - 1;
         }
-        gather_tile<R, D, MODE, COUNT, PLAN>(items[lo].g, (j - items[lo].tile_base) * TP + u % TP);
+        gather_tile<R, D, MODE, COUNT, PLAN, TP>(items[lo].g, (j - items[lo].tile_base) * TP + u % TP);
     }
 }
 
-template <typename R, int D, int MODE, bool COUNT>
+template <typename R, int D, int MODE, bool COUNT, int TP>
 static void launch_plan(const GatherArgs& g, int plan, dim3 grid, dim3 block, hipStream_t s)
 {
     switch (plan) {
-    case 1: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 1>), grid, block, 0, s, g); break;
-    case 2: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 2>), grid, block, 0, s, g); break;
-    case 3: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 3>), grid, block, 0, s, g); break;
-    default: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 0>), grid, block, 0, s, g); break;
+    case 1: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 1, TP>), grid, block, 0, s, g); break;
+    case 2: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 2, TP>), grid, block, 0, s, g); break;
+    case 3: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 3, TP>), grid, block, 0, s, g); break;
+    default: FLA_LAUNCH((k_gather<R, D, MODE, COUNT, 0, TP>), grid, block, 0, s, g); break;
     }
 }
 
-template <typename R, int D, int MODE, bool COUNT>
+// Workgroups that the compute units hold at once (waves per SIMD from the
+// register budget, 4 SIMDs per unit).
+template <typename R, int D, int TP>
+static int64_t resident_workgroups(int ncu)
+{
+    return (int64_t)(ncu > 0 ? ncu : 1) * GatherOcc<R, D, TP>::value * 4 / GatherWaves<D>::value;
+}
+
+template <typename R, int D, int MODE, bool COUNT, int TP>
 static void launch_batch_plan(const BatchItem* items, int nsnap, int nwork, int chunk, int plan, uint32_t* queue,
                               int ncu, hipStream_t s)
 {
-    // as many workgroups as the compute units hold at once (waves per SIMD
-    // from the register budget, 4 SIMDs per unit), at most one per item
-    int64_t nb = (int64_t)(ncu > 0 ? ncu : 1) * GatherOcc<R, D>::value * 4 / GatherWaves<D>::value;
-    const int64_t total = (int64_t)nwork * TileParts<D>::value;
+    // as many workgroups as the compute units hold, at most one per item
+    int64_t nb = resident_workgroups<R, D, TP>(ncu);
+    const int64_t total = (int64_t)nwork * TP;
     if (nb > total) nb = total;
     if (nb < 1) nb = 1;
     dim3 grid((unsigned)nb), block(kWave * GatherWaves<D>::value);
     switch (plan) {
-    case 1: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 1>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
-    case 2: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 2>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
-    case 3: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 3>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
-    default: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 0>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
+    case 1: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 1, TP>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
+    case 2: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 2, TP>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
+    case 3: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 3, TP>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
+    default: FLA_LAUNCH((k_gather_batch<R, D, MODE, COUNT, 0, TP>), grid, block, 0, s, items, nsnap, nwork, chunk, queue); break;
     }
 }
 
+template <typename R, int D, int TP>
+static void launch_batch_shape(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan,
+                               bool general, uint32_t* queue, int ncu, hipStream_t s)
+{
+    if (general) {
+        if (count)
+            launch_batch_plan<R, D, kNwGeneral, true, TP>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
+        else
+            launch_batch_plan<R, D, kNwGeneral, false, TP>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
+    } else {
+        if (count)
+            launch_batch_plan<R, D, FLA_NW, true, TP>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
+        else
+            launch_batch_plan<R, D, FLA_NW, false, TP>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
+    }
+}
+
+// plan_code = plan + kGatherPlans * shape (shape 1: whole tiles, 3-D only)
 template <typename R, int D>
-hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan,
+hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan_code,
                                bool general, uint32_t* queue, int ncu, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
+    const int plan = plan_code % kGatherPlans, shape = plan_code / kGatherPlans;
     // the XCD counters start at zero (a fill kernel: the launch may be captured)
     hipError_t e = launch_fill_u32(queue, kXcds, 0u, s);
     if (e != hipSuccess) return e;
-    if (general) {
-        if (count)
-            launch_batch_plan<R, D, kNwGeneral, true>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
-        else
-            launch_batch_plan<R, D, kNwGeneral, false>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
-    } else {
-        if (count)
-            launch_batch_plan<R, D, FLA_NW, true>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
-        else
-            launch_batch_plan<R, D, FLA_NW, false>(items, nsnap, nwork, chunk, plan, queue, ncu, s);
+    if constexpr (D == 3) {
+        if (tile_parts(D, shape) == 2) {
+            launch_batch_shape<R, D, 2>(items, nsnap, nwork, chunk, count, plan, general, queue, ncu, s);
+            return hipGetLastError();
+        }
     }
+    launch_batch_shape<R, D, 1>(items, nsnap, nwork, chunk, count, plan, general, queue, ncu, s);
     return hipGetLastError();
 }
 
-template <typename R, int D>
-hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hipStream_t s)
+template <typename R, int D, int TP>
+static hipError_t launch_gather_shape(const GatherArgs& g, int mode, bool count, int plan, hipStream_t s)
 {
-    if (g.m.ntiles <= 0) return hipSuccess;
     if (g.order) {
         FLA_LAUNCH(k_tile_cost<D>, dim3((unsigned)((g.m.ntiles + 3) / 4)), dim3(256), 0, s, g);
-        FLA_LAUNCH(k_tile_order, dim3(kXcds), dim3(1024), 0, s, (const uint32_t*)g.tile_cost,
-                           g.m.ntiles * TileParts<D>::value, TileParts<D>::value, g.order);
+        FLA_LAUNCH(k_tile_order, dim3(kXcds), dim3(1024), 0, s, (const uint32_t*)g.tile_cost, g.m.ntiles * TP, TP,
+                   g.order);
     }
-    int64_t nb = (int64_t)g.m.ntiles * TileParts<D>::value;
+    int64_t nb = (int64_t)g.m.ntiles * TP;
     if (g.queue) {
         // as many workgroups as the compute units hold at once; the XCD
         // counters start at zero (a fill kernel: the launch may be captured)
-        const int64_t fit = (int64_t)(g.ncu > 0 ? g.ncu : 1) * GatherOcc<R, D>::value * 4 / GatherWaves<D>::value;
+        const int64_t fit = resident_workgroups<R, D, TP>(g.ncu);
         if (fit < nb) nb = fit;
         hipError_t e = launch_fill_u32(g.queue, kXcds, 0u, s);
         if (e != hipSuccess) return e;
@@ -1046,34 +1076,32 @@ hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hi
     const bool general = g.m.edges[0] || g.m.edges[1] || g.m.edges[2];
     if (mode == FLA_NW && general) {
         if (count)
-            launch_plan<R, D, kNwGeneral, true>(g, plan, grid, block, s);
+            launch_plan<R, D, kNwGeneral, true, TP>(g, plan, grid, block, s);
         else
-            launch_plan<R, D, kNwGeneral, false>(g, plan, grid, block, s);
+            launch_plan<R, D, kNwGeneral, false, TP>(g, plan, grid, block, s);
     } else if (mode == FLA_NW) {
         if (count)
-            launch_plan<R, D, FLA_NW, true>(g, plan, grid, block, s);
+            launch_plan<R, D, FLA_NW, true, TP>(g, plan, grid, block, s);
         else
-            launch_plan<R, D, FLA_NW, false>(g, plan, grid, block, s);
+            launch_plan<R, D, FLA_NW, false, TP>(g, plan, grid, block, s);
     } else {
         if (count)
-            launch_plan<R, D, FLA_DEPOSIT, true>(g, plan, grid, block, s);
+            launch_plan<R, D, FLA_DEPOSIT, true, TP>(g, plan, grid, block, s);
         else
-            launch_plan<R, D, FLA_DEPOSIT, false>(g, plan, grid, block, s);
+            launch_plan<R, D, FLA_DEPOSIT, false, TP>(g, plan, grid, block, s);
     }
     return hipGetLastError();
 }
 
-template hipError_t launch_gather<float, 2>(const GatherArgs&, int, bool, int, hipStream_t);
-template hipError_t launch_gather<float, 3>(const GatherArgs&, int, bool, int, hipStream_t);
-template hipError_t launch_gather<double, 2>(const GatherArgs&, int, bool, int, hipStream_t);
-template hipError_t launch_gather<double, 3>(const GatherArgs&, int, bool, int, hipStream_t);
-template hipError_t launch_gather_batch<float, 2>(const BatchItem*, int, int, int, bool, int, bool, uint32_t*, int,
-                                                  hipStream_t);
-template hipError_t launch_gather_batch<float, 3>(const BatchItem*, int, int, int, bool, int, bool, uint32_t*, int,
-                                                  hipStream_t);
-template hipError_t launch_gather_batch<double, 2>(const BatchItem*, int, int, int, bool, int, bool, uint32_t*, int,
-                                                   hipStream_t);
-template hipError_t launch_gather_batch<double, 3>(const BatchItem*, int, int, int, bool, int, bool, uint32_t*, int,
-                                                   hipStream_t);
+template <typename R, int D>
+hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan_code, hipStream_t s)
+{
+    if (g.m.ntiles <= 0) return hipSuccess;
+    const int plan = plan_code % kGatherPlans, shape = plan_code / kGatherPlans;
+    if constexpr (D == 3) {
+        if (tile_parts(D, shape) == 2) return launch_gather_shape<R, D, 2>(g, mode, count, plan, s);
+    }
+    return launch_gather_shape<R, D, 1>(g, mode, count, plan, s);
+}
 
 }  // namespace flp

@@ -48,7 +48,7 @@ hipError_t launch_max_class_batch(const BatchItem* items, int nsnap, const uint3
 // Persistent gather over the work items of a batch; queue holds kXcds
 // counters of workspace (zeroed by the launcher), ncu the compute units.
 template <typename R, int D>
-hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan,
+hipError_t launch_gather_batch(const BatchItem* items, int nsnap, int nwork, int chunk, bool count, int plan_code,
                                bool general, uint32_t* queue, int ncu, hipStream_t s);
 
 // Trajectory producer: the gas field and the droplet state it advances.
@@ -101,9 +101,15 @@ hipError_t launch_deposit_norm(const MeshDev& m, const PhysDev& ph, const uint32
                                const uint32_t* order, const double* qd, int64_t N, double4* rpos, R* rw,
                                unsigned long long* stats, hipStream_t s);
 
+// Gather plan codes: plan + kGatherPlans * shape.  The plan sets how finely
+// the gather skips unreachable sub-blocks; the shape the part of a tile one
+// workgroup owns (0: half a tile along x in 3-D, the whole tile in 2-D;
+// 1: the whole tile, 3-D only).
 constexpr int kGatherPlans = 4;
+constexpr int kGatherShapes = 2;
+template <int D> constexpr int gather_plan_codes() { return D == 3 ? kGatherPlans * kGatherShapes : kGatherPlans; }
 template <typename R, int D>
-hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan, hipStream_t s);
+hipError_t launch_gather(const GatherArgs& g, int mode, bool count, int plan_code, hipStream_t s);
 
 // PSI-CELL
 struct PsiArgs {

@@ -209,7 +209,7 @@ def test_autotune_batch(ctx):
     import paper_2512_20829_amd as F
     b = Batch(_snapshots_3d(), "f32")
     times = ctx.autotune_batch(b.meshes, b.trajs, b.params, b.outs)
-    assert len(times) == F.GATHER_PLANS * F.BATCH_CHUNKS and all(t > 0 for t in times)
+    assert len(times) == F.GATHER_CONFIGS * F.BATCH_CHUNKS and all(t > 0 for t in times)
     plan, chunk = ctx.get_batch_plan(3, F.FLA_F32)
     k = int(np.argmin(times))
     assert plan == k // F.BATCH_CHUNKS and chunk == [1, 4, 16, 64][k % F.BATCH_CHUNKS]
@@ -218,6 +218,23 @@ def test_autotune_batch(ctx):
     _assert_same_as_single_plan(ctx, b, plan)
     ctx.set_batch_plan(3, F.FLA_F32, -1, 0)
     assert ctx.get_batch_plan(3, F.FLA_F32) == (1, 16)
+
+
+@pytest.mark.parametrize("code", [1, 5])
+def test_batch_equals_single_calls_under_each_shape(ctx, code):
+    """Half tiles (code 1) and whole tiles (code 5, plan 1): every snapshot of
+    the batch equals its single call under the same plan code."""
+    import paper_2512_20829_amd as F
+    print(f"[case] batch plan code {code}", flush=True)
+    b = Batch(_snapshots_3d(), "f32")
+    ctx.set_batch_graph(False)
+    ctx.set_batch_plan(3, F.FLA_F32, code, 4)
+    try:
+        b.run(ctx)
+        torch.cuda.synchronize()
+        _assert_same_as_single_plan(ctx, b, code)
+    finally:
+        ctx.set_batch_plan(3, F.FLA_F32, -1, 0)
 
 
 def _assert_same_as_single_plan(ctx, b, plan):

@@ -419,18 +419,36 @@ def test_psicell_many_bins_2d_f64(ctx, mesh_n):
 # ------------------------------------------------------------------ plans / autotuner
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_every_gather_plan_gives_the_same_values(ctx, prec):
+    """Plan codes plan + 4 * shape: under one shape (half tiles, whole tiles)
+    every plan gives the same bits; between shapes binary64 gives the same
+    bits and binary32 the same decisions with sums folded at other points."""
     import paper_2512_20829_amd as F
     wl = W.small_random_3d(6000, 30, seed=15)
+    pr = F.FLA_F64 if prec == "f64" else F.FLA_F32
     outs = []
-    for plan in range(4):
-        ctx.set_plan(3, F.FLA_F64 if prec == "f64" else F.FLA_F32, plan)
-        S, den, st = gpu_run(ctx, wl, prec=prec)
-        outs.append((S, den, st["pairs"]))
-    ctx.set_plan(3, F.FLA_F64 if prec == "f64" else F.FLA_F32, -1)
-    for S, den, P in outs[1:]:
-        assert np.array_equal(S, outs[0][0]) and np.array_equal(den, outs[0][1]) and P == outs[0][2]
+    for code in range(F.GATHER_CONFIGS):
+        print(f"[case] plan code {code} {prec}", flush=True)
+        ctx.set_plan(3, pr, code)
+        assert ctx.get_plan(3, pr) == code
+        S, den, st = gpu_run(ctx, wl, prec=prec, cell_pairs=True)
+        outs.append((S, den, st["pairs"], st["cell_pairs"]))
+    ctx.set_plan(3, pr, -1)
+    for code, (S, den, P, cp) in enumerate(outs):
+        base = outs[code - code % F.GATHER_PLANS]
+        assert np.array_equal(S, base[0]) and np.array_equal(den, base[1]) and P == base[2]
+        np.testing.assert_array_equal(cp, outs[0][3])
+        if prec == "f64":
+            assert np.array_equal(S, outs[0][0]) and np.array_equal(den, outs[0][1])
+        else:
+            assert_fields_close(S, outs[0][0], 1e-6, f"shape of code {code}")
     ref, _ = oracle_run(wl, prec=prec)
-    assert_fields_close(outs[0][0], ref.S, TOL[prec], "plans")
+    for code in (0, F.GATHER_PLANS):
+        assert_fields_close(outs[code][0], ref.S, TOL[prec], f"plan code {code}")
+    # 2-D has whole tiles only: codes 0..3
+    with pytest.raises(F.FlaError, match="INVALID_ARG"):
+        ctx.set_plan(2, pr, F.GATHER_PLANS)
+    ctx.set_plan(2, pr, F.GATHER_PLANS - 1)
+    ctx.set_plan(2, pr, -1)
 
 
 def test_autotune_picks_a_plan(ctx):
@@ -444,6 +462,6 @@ def test_autotune_picks_a_plan(ctx):
     S, Sm, den = F.alloc_fields(wl.mesh.cells, 3, torch.float32, dev)
     p = F.Params(rho_d=wl.rho_d, mu=wl.mu, delta=wl.delta, h0=wl.h0, cutoff=wl.cutoff)
     times = ctx.autotune(F.mesh_of(wl.mesh), st, p, S, Sm, den)
-    assert all(t > 0 for t in times)
+    assert len(times) == F.GATHER_CONFIGS and all(t > 0 for t in times)
     assert ctx.get_plan(3, F.FLA_F32) == int(np.argmin(times))
     ctx.set_plan(3, F.FLA_F32, -1)

@@ -65,7 +65,7 @@ def test_multi_vortex_map_caustics():
 
 def test_bench_reads_the_traffic_summary():
     """bench.py reports the gather's HBM traffic only from a summary whose
-    source hash matches gather.hip and the compile-time constants in
+    source hash matches gather.hpp and the compile-time constants in
     internal.hpp; the hash key contains a colon."""
     import bench
     path = os.path.join(ROOT, "profiles", "gather_abc128_hbm_traffic.md")
@@ -74,10 +74,10 @@ def test_bench_reads_the_traffic_summary():
         if ":" in line and line.startswith("- "):
             k, v = line[2:].rsplit(":", 1)
             vals[k.strip()] = v.strip()
-    key = "gather.hip + internal.hpp sha256[:16]"
+    key = "gather.hpp + internal.hpp sha256[:16]"
     assert key in vals and "bytes per launch (calibrated)" in vals
     h = hashlib.sha256()
-    for name in ("gather.hip", "internal.hpp"):
+    for name in ("gather.hpp", "internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2512_20829_amd", "csrc", name), "rb").read())
     got = bench.gather_traffic("abc128")
     if vals[key] == h.hexdigest()[:16]:
