@@ -839,13 +839,13 @@ fla_status bandwidth_forward_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev&
     uint4* zb;
     {
         Carver probe(nullptr);
-        probe.take<unsigned int>(m.M);
+        probe.take<unsigned int>(2 * (size_t)m.M);
         probe.take<uint4>(t.count > 0 ? t.count : 1);
         fla_status st = ensure_ws(ctx, probe.off + 256);
         if (st != FLA_OK) return st;
     }
     Carver c(ctx->ws);
-    cnt = c.take<unsigned int>(m.M);
+    cnt = c.take<unsigned int>(2 * (size_t)m.M);   // counts, then their box sums
     zb = c.take<uint4>(t.count > 0 ? t.count : 1);
     StageTimer tm(ctx, 5, s);
     HIP_OK((launch_bandwidth_forward<R, D>(t, m, theta, cnt, zb, hfac, z, o, fraw, s)));

@@ -175,6 +175,34 @@ __global__ __launch_bounds__(256) void k_home_count(TrajDev t, MeshDev m, unsign
     atomicAdd(&cnt[c], 1u);
 }
 
+// One axis of the 3^D box sum of the per-cell counts: out[c] = in[c - s] +
+// in[c] + in[c + s] along axis a (stride s), wrapping on a periodic axis
+// (on an axis of one or two cells a neighbour can be the cell itself or the
+// same cell twice, as for the neighbours of a home cell) and leaving out
+// cells beyond a closed one.  After one pass per axis, each cell holds the
+// count over the 3^D block around it; the integer sums are exact, so the
+// order of the passes does not matter.
+__global__ __launch_bounds__(256) void k_box_axis(MeshDev m, int a, const unsigned int* __restrict__ in,
+                                                  unsigned int* __restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m.M) return;
+    int64_t st = 1;
+    for (int b = 0; b < a; ++b) st *= m.n[b];
+    const int64_t n = m.n[a];
+    const int64_t i = (c / st) % n;
+    unsigned int v = in[c];
+    if (i > 0)
+        v += in[c - st];
+    else if (m.periodic[a])
+        v += in[c + (n - 1) * st];
+    if (i < n - 1)
+        v += in[c + st];
+    else if (m.periodic[a])
+        v += in[c - (n - 1) * st];
+    out[c] = v;
+}
+
 // ---------------------------------------------------------------- features + network
 // LDS row strides (bf16 elements) of the staged weights and of the network's
 // activation tiles: rows padded by 4 (W1, Z) and 4 (W2, H1) elements so that
@@ -213,7 +241,8 @@ __device__ inline void stage_weights(const float* th, MlpW& W)
 constexpr int kMlpWaves = 4;
 
 // Features of one trajectory per thread: the binary64 singular values, the
-// neighbour count over the 3^D block of cells around the home cell, the
+// neighbour count over the 3^D block of cells around the home cell (one read
+// of the box-summed counts), the
 // standardised inputs z rounded to bf16 and packed with a validity flag into
 // one 16-byte record {z0..z4, 0, 0, valid} for the network kernel.
 template <typename R, int D>
@@ -228,39 +257,14 @@ __device__ inline void feature_one(const TrajDev& t, const MeshDev& m, const flo
     if (ok) {
         double adet = fabs(det), s[3];
         singular_values<D>(J, adet, s);
-        // the 3^D block of cells around the home cell (cell indices and their
-        // neighbours fit 32 bits; a neighbour is at most one period away, so
-        // wrapping is one add or subtract)
-        int hc[3] = {0, 0, 0}, cn[3][3];
-        bool cin[3][3];
+        // the box-summed count at the home cell (home_index clamps into the mesh)
+        int64_t hc = 0, hs = 1;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (a < D) hc[a] = (int)home_index(m, a, x[a]);
-#pragma unroll
-            for (int o = 0; o < 3; ++o) {
-                int c = hc[a] + o - 1;
-                bool in = true;
-                if (a >= D) {
-                    c = 0;
-                    in = o == 1;
-                } else if (m.periodic[a]) {
-                    c = c < 0 ? c + m.n[a] : (c >= m.n[a] ? c - m.n[a] : c);
-                } else {
-                    in = c >= 0 && c < m.n[a];
-                }
-                cn[a][o] = c;
-                cin[a][o] = in;
-            }
+        for (int a = 0; a < D; ++a) {
+            hc += home_index(m, a, x[a]) * hs;
+            hs *= m.n[a];
         }
-        unsigned int nb = 0;
-        const int n0 = m.n[0], n01 = m.n[0] * m.n[1];
-#pragma unroll
-        for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx)
-                    if (cin[0][dx] && cin[1][dy] && cin[2][dz]) nb += cnt[cn[0][dx] + n0 * cn[1][dy] + n01 * cn[2][dz]];
+        const unsigned int nb = cnt[hc];
         // binary64 features and standardisation: z is rounded to bf16 for the
         // network, so it is formed as exactly as the oracle forms it
         const double fd[kFeat] = {log(s[0]), log(s[1]), D == 3 ? log(s[2]) : 0.0, -log(adet), log1p((double)nb)};
@@ -873,8 +877,15 @@ hipError_t launch_bandwidth_forward(const TrajDev& t, const MeshDev& m, const fl
     if (e != hipSuccess || t.count == 0) return e;
     unsigned g = (unsigned)((t.count + 255) / 256);
     FLA_LAUNCH((k_home_count<R, D>), dim3(g), dim3(256), 0, s, t, m, cnt);
+    // box sums over the 3^D neighbourhoods, one pass per axis between the two
+    // halves of cnt (2 M words)
+    unsigned int* buf[2] = {cnt, cnt + m.M};
+    const unsigned gm = (unsigned)((m.M + 255) / 256);
+    for (int a = 0; a < D; ++a)
+        FLA_LAUNCH(k_box_axis, dim3(gm), dim3(256), 0, s, m, a, (const unsigned int*)buf[a & 1], buf[(a + 1) & 1]);
+    const unsigned int* box = buf[D & 1];
     const unsigned gf = (unsigned)((t.count + 256 * kFeatPerThread - 1) / (256 * kFeatPerThread));
-    FLA_LAUNCH((k_features<R, D>), dim3(gf), dim3(256), 0, s, t, m, theta, cnt, (uint4*)zb, z, fraw);
+    FLA_LAUNCH((k_features<R, D>), dim3(gf), dim3(256), 0, s, t, m, theta, box, (uint4*)zb, z, fraw);
     int64_t groups = (t.count + kWave * kMlpWaves - 1) / (kWave * kMlpWaves);
     unsigned gb = (unsigned)(groups < 2048 ? groups : 2048);
     FLA_LAUNCH(k_mlp, dim3(gb), dim3(kWave * kMlpWaves), 0, s, theta, t.count, (const uint4*)zb, hfac, o);

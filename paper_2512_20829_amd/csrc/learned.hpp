@@ -30,8 +30,8 @@ struct MutPlanes {
 };
 
 template <typename R, int D>
-// features (binary64) then the network (bf16 MFMA); zb: count 16-byte
-// feature records of workspace
+// features (binary64) then the network (bf16 MFMA); cnt: 2 M words and zb:
+// count 16-byte feature records of workspace
 hipError_t launch_bandwidth_forward(const TrajDev& t, const MeshDev& m, const float* theta, unsigned int* cnt, void* zb,
                                     float* hfac, float* z, float* o, float* fraw, hipStream_t s);
 template <typename R, int D>
