@@ -340,6 +340,17 @@ __global__ __launch_bounds__(kWave * kMlpWaves) void k_mlp(const float* __restri
     __syncthreads();
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int r16 = lane % 16, g4 = lane / 16;
+    // the biases and output weights of the lane's hidden rows 16 mt + 4 g4 + j
+    float b1r[4][4], b2r[4][4], w3r[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int hrow = 16 * mt + 4 * g4 + j;
+            b1r[mt][j] = W.b1[hrow];
+            b2r[mt][j] = W.b2[hrow];
+            w3r[mt][j] = W.w3[hrow];
+        }
     for (int64_t base = ((int64_t)blockIdx.x * kMlpWaves + wave) * kWave; base < N;
          base += (int64_t)gridDim.x * kMlpWaves * kWave) {
         const int64_t i = base + lane;
@@ -358,11 +369,12 @@ __global__ __launch_bounds__(kWave * kMlpWaves) void k_mlp(const float* __restri
             for (int mt = 0; mt < 4; ++mt) {
                 f32x4 acc = {0, 0, 0, 0};
                 acc = mfma16(load4(&W.W1[16 * mt + r16][4 * g4]), load4(&Z[wave][16 * q + r16][4 * g4]), acc);
+                uint32_t hb[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    int hrow = 16 * mt + 4 * g4 + j;
-                    H1[wave][r16][hrow] = bf16_bits(silu_f(acc[j] + W.b1[hrow]));
-                }
+                for (int j = 0; j < 4; ++j) hb[j] = bf16_bits(silu_f(acc[j] + b1r[mt][j]));
+                // hidden rows 16 mt + 4 g4 .. + 3 of trajectory r16: one 8-byte store
+                *reinterpret_cast<uint2*>(&H1[wave][r16][16 * mt + 4 * g4]) =
+                    make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
             }
             wave_sync();
             // layer 2 and the output dot product
@@ -374,10 +386,7 @@ __global__ __launch_bounds__(kWave * kMlpWaves) void k_mlp(const float* __restri
                 for (int kb = 0; kb < 4; ++kb)
                     acc = mfma16(load4(&W.W2[16 * mt + r16][16 * kb + 4 * g4]), load4(&H1[wave][r16][16 * kb + 4 * g4]), acc);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    int hrow = 16 * mt + 4 * g4 + j;
-                    op += W.w3[hrow] * silu_f(acc[j] + W.b2[hrow]);
-                }
+                for (int j = 0; j < 4; ++j) op += w3r[mt][j] * silu_f(acc[j] + b2r[mt][j]);
             }
             op += __shfl_xor(op, 16, kWave);
             op += __shfl_xor(op, 32, kWave);
