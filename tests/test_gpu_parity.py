@@ -399,6 +399,24 @@ def test_psicell_many_bins_with_skipped_records_f32(ctx, n):
     assert st["outside"] == out and out > 4000 and st["skipped"] == nf and nf > 2000
 
 
+def test_psicell_direct_tiles_3d_f64(ctx):
+    # binary64 3-D: 80^3 cells are 5 x 5 x 10 = 250 tiles of 16 x 16 x 8
+    # cells (two-word sums, 136 KiB of LDS per tile), the scatter's bins
+    # themselves; ragged last tiles on x and y, particles outside the closed
+    # box and non-finite records throughout
+    print("[case] psicell direct tiles 3-D f64 n=80", flush=True)
+    wl = W.small_random_3d(10, 80, seed=23, periodic=False)
+    cloud = W.abc_cloud(2_000_000, seed=23)
+    cloud.x = cloud.x * 1.1 - 0.05
+    cloud.r[::1009] = float("nan")
+    w = 0.25
+    S, den, st = gpu_run(ctx, wl, prec="f64", psicell_cloud=cloud, weight=w)
+    Sref, counts, out, nf = oracle.psicell(wl.mesh, cloud, w, wl.rho_d, wl.mu, wl.delta, split=True)
+    assert_fields_close(S, Sref, TOL["f64"], "psicell direct 3-D f64")
+    assert np.array_equal(den.astype(np.int64), counts)
+    assert st["outside"] == out and out > 0 and st["skipped"] == nf and nf > 1000
+
+
 @pytest.mark.parametrize("mesh_n", [1000, 1500])
 def test_psicell_many_bins_2d_f64(ctx, mesh_n):
     # binary64 2-D: 1000^2 cells are 16 x 32 = 512 tiles of 64 x 32 cells,
