@@ -56,6 +56,8 @@ constexpr int kPsiUnrollReduce = 8;    // reduce
 // cache lines (with 512 direct tiles, rounds of 2048, 4096 and 6144
 // binary32 records took the 200M-particle call to 6.72, 6.36 and 6.25 ms)
 template <typename R> struct PsiRoundPerThread { static constexpr int value = sizeof(R) == 4 ? 24 : 12; };
+// threads of a scatter block (a round is kPsiScatterThreads * U records)
+constexpr int kPsiScatterThreads = 256;
 constexpr uint32_t kPsiSkip = 0xFFFFFFFFu;     // cell of a skipped record in a tile bucket
 constexpr uint32_t kPsiSkipBit = 0x80000000u;  // skip mark of a binned record (codes < 2^24)
 static_assert(kPsiTilesPerBin == kWave, "the tile pass scans one tile per lane of one wave");
@@ -173,8 +175,10 @@ __global__ __launch_bounds__(256) void k_psi_count(PsiArgs a)
     if ((threadIdx.x % kWave) == 0 && bad) atomicAdd(&a.stats[ST_SKIPPED], bad);
 }
 
-// Exclusive prefix sum of one value per thread of a 256-thread block, and
-// the block total.  ws holds 4 words of LDS; the call contains a barrier.
+// Exclusive prefix sum of one value per thread of an NT-thread block, and
+// the block total.  ws holds NT / 64 words of LDS; the call contains a
+// barrier.
+template <int NT>
 __device__ inline unsigned int block_exclusive_sum(unsigned int v, unsigned int* ws, unsigned int& total)
 {
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -189,7 +193,7 @@ __device__ inline unsigned int block_exclusive_sum(unsigned int v, unsigned int*
     unsigned int pre = 0;
     total = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NT / kWave; ++j) {
         const unsigned int t = ws[j];
         pre += j < w ? t : 0u;
         total += t;
@@ -218,21 +222,22 @@ __device__ inline unsigned int wave_exclusive_sum(unsigned int v, unsigned int& 
 // slots come from the scanned per-block bin counts of the count pass (a
 // block's share of a bin is one contiguous range, filled round by round).
 template <typename R, int D>
-__global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
+__global__ __launch_bounds__(kPsiScatterThreads) void k_psi_scatter(PsiArgs a)
 {
     constexpr int C = D + 1;
-    constexpr int U = PsiRoundPerThread<R>::value;
-    constexpr int RB = 256 * U;
-    static_assert(kPsiMaxBins <= 2 * 256, "two bins per thread in the bin scan");
+    constexpr int NT = kPsiScatterThreads;
+    constexpr int U = PsiRoundPerThread<R>::value * 256 / NT;
+    constexpr int RB = NT * U;
+    constexpr int BPT = (kPsiMaxBins + NT - 1) / NT;   // bins per thread in the bin scan
     __shared__ PsiRec<R> stage[RB];
     // per bin: this round's count, its first position in the stage, global
     // slot minus stage position, and the block's next global slot
     __shared__ unsigned int cnt[kPsiMaxBins], off[kPsiMaxBins], delta[kPsiMaxBins], cursor[kPsiMaxBins];
-    __shared__ unsigned int ws[4];
+    __shared__ unsigned int ws[NT / kWave];
     const int tid = threadIdx.x;
     const int nbin = a.pnbins;
     const int bsh = a.cptlog + a.binlog;
-    for (int b = tid; b < nbin; b += 256) {
+    for (int b = tid; b < nbin; b += NT) {
         cursor[b] = a.binhist[(int64_t)b * gridDim.x + blockIdx.x];
         cnt[b] = 0;
     }
@@ -251,12 +256,12 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
         R v[U][3], ug[U][3], r[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t p = r0 + (int64_t)u * 256 + tid;
+            const int64_t p = r0 + (int64_t)u * NT + tid;
             code[u] = p < end ? a.codes[p] : -1;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t p = r0 + (int64_t)u * 256 + tid;
+            const int64_t p = r0 + (int64_t)u * NT + tid;
             const bool live = code[u] >= 0;
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) {
@@ -292,22 +297,25 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
             rank[u] = atomicAdd(&cnt[code[u] >> bsh], 1u);
         }
         __syncthreads();
-        // bins 2 tid and 2 tid + 1
-        const int b0 = 2 * tid;
-        const unsigned int c0 = b0 < nbin ? cnt[b0] : 0u, c1 = b0 + 1 < nbin ? cnt[b0 + 1] : 0u;
-        unsigned int total;
-        const unsigned int ex = block_exclusive_sum(c0 + c1, ws, total);
-        if (b0 < nbin) {
-            off[b0] = ex;
-            delta[b0] = cursor[b0] - ex;
-            cursor[b0] += c0;
-            cnt[b0] = 0;
+        // bins BPT tid .. BPT tid + BPT - 1
+        const int b0 = BPT * tid;
+        unsigned int c[BPT], sum = 0;
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            c[k] = b0 + k < nbin ? cnt[b0 + k] : 0u;
+            sum += c[k];
         }
-        if (b0 + 1 < nbin) {
-            off[b0 + 1] = ex + c0;
-            delta[b0 + 1] = cursor[b0 + 1] - (ex + c0);
-            cursor[b0 + 1] += c1;
-            cnt[b0 + 1] = 0;
+        unsigned int total;
+        unsigned int ex = block_exclusive_sum<NT>(sum, ws, total);
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            if (b0 + k < nbin) {
+                off[b0 + k] = ex;
+                delta[b0 + k] = cursor[b0 + k] - ex;
+                cursor[b0 + k] += c[k];
+                cnt[b0 + k] = 0;
+            }
+            ex += c[k];
         }
         __syncthreads();
 #pragma unroll
@@ -316,7 +324,7 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
             stage[off[code[u] >> bsh] + rank[u]] = rec[u];
         }
         __syncthreads();
-        for (unsigned int i = tid; i < total; i += 256) {
+        for (unsigned int i = tid; i < total; i += NT) {
             const PsiRec<R> r = stage[i];
             binned[delta[(r.loc & ~kPsiSkipBit) >> bsh] + i] = r;
         }
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(256) void k_psi_scatter(PsiArgs a)
     for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, kWave);
     if ((threadIdx.x % kWave) == 0 && bad) atomicAdd(&a.stats[ST_SKIPPED], bad);
     // per-block maxima (a separate pass reduces them: no contended atomics)
-    __shared__ double bm[256 / kWave][4];
+    __shared__ double bm[NT / kWave][4];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
@@ -932,7 +940,7 @@ hipError_t launch_psicell(const PsiArgs& a, hipStream_t s)
             e = launch_exclusive_scan_u32(a.binhist, (int64_t)a.pnbins * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
             if (e != hipSuccess) return e;
         }
-        FLA_LAUNCH((k_psi_scatter<R, D>), dim3(a.nblocks), dim3(256), 0, s, a);
+        FLA_LAUNCH((k_psi_scatter<R, D>), dim3(a.nblocks), dim3(kPsiScatterThreads), 0, s, a);
     }
     FLA_LAUNCH((k_psi_scale<D>), dim3(1), dim3(256), 0, s, a);
     if (a.p.count > 0 && !a.direct)
