@@ -23,7 +23,8 @@ its fused epilogue.  Printed as one JSON line (rank 0):
   abc128       the 128^3 ABC case (2,097,152 lattice trajectories) with its
                own roofline
   tg2d_f64     the 2-D Taylor-Green case in binary64 (64^2 mesh, 4096
-               trajectories) against the binary64 vector peak
+               trajectories) against the binary64 vector peak, and the same
+               calls replayed as a HIP graph (launch-latency bound)
   batch        64 uneven snapshots (32^3..128^3 meshes, 10k..2M trajectories)
                through fla_project_batch: graph replays, direct launches and
                one single call per snapshot, after the batch autotuner
@@ -689,9 +690,11 @@ def cpu_baseline(args, dev):
     return out
 
 
-def projection_section(ctx, args, dev, wl, prec, traffic_name):
+def projection_section(ctx, args, dev, wl, prec, traffic_name, graph=False):
     """Timed fla_project_sources on one workload (inputs on the GPU), its
-    rates and the gather's roofline."""
+    rates and the gather's roofline.  With graph, also the time per call of
+    the same calls replayed as a HIP graph (fla_set_graph; profiling off),
+    beside the direct calls without profiling."""
     import torch
 
     import paper_2512_20829_amd as F
@@ -706,12 +709,37 @@ def projection_section(ctx, args, dev, wl, prec, traffic_name):
     ms, stages, g_ms, stats = timed_projection(ctx, F, mesh, st, params, args.steps, args.warmup)
     M = wl.mesh.cells
     P = stats["pairs"]
+    extra = {}
+    if graph:
+        dt = torch.float64 if prec == "f64" else torch.float32
+        Sm, Sv, _ = F.alloc_fields(M, wl.mesh.dim, dt, dev, den=False)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+        def loop():
+            for _ in range(3):
+                ctx.project_sources(mesh, st, params, Sm, Sv)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                ctx.project_sources(mesh, st, params, Sm, Sv)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / args.steps
+
+        ms_direct = loop()
+        ctx.set_graph(True)
+        r0 = ctx.stats()["graph_replays"]
+        ms_graph = loop()
+        replays = ctx.stats()["graph_replays"] - r0
+        ctx.set_graph(False)
+        extra = {"ms_per_step_direct_unprofiled": round(ms_direct, 4), "ms_per_step_graph": round(ms_graph, 4),
+                 "cells_per_s_graph": M / (ms_graph * 1e-3), "graph_replays": replays}
     del st, keep
     torch.cuda.empty_cache()
     return {"ms_per_step": round(ms, 4), "cells_per_s": M / (ms * 1e-3), "pairs_per_s": P / (ms * 1e-3),
             "pairs": P, "trajectories": stats["trajectories"], "skipped": stats["skipped"],
             "max_class": stats["max_class"], "stage_ms": stages,
-            "roofline": gather_roofline(P, g_ms, wl.mesh.dim, prec, traffic_name)}
+            "roofline": gather_roofline(P, g_ms, wl.mesh.dim, prec, traffic_name), **extra}
 
 
 def general_mesh_section(ctx, args, dev, cartesian_ms):
@@ -1037,8 +1065,8 @@ def main():
     if args.only in (None, "tg2d"):
         log("tg2d_f64: the 2-D Taylor-Green workload in binary64")
         a2 = argparse.Namespace(**{**vars(args), "steps": max(args.steps, 200)})
-        tg = projection_section(ctx, a2, dev, W.taylor_green_2d(device=dev), "f64", "tg2d")
-        log(f"tg2d_f64: {tg['ms_per_step']:.4f} ms/step")
+        tg = projection_section(ctx, a2, dev, W.taylor_green_2d(device=dev), "f64", "tg2d", graph=True)
+        log(f"tg2d_f64: {tg['ms_per_step']:.4f} ms/step ({tg['ms_per_step_graph']:.4f} as graph replays)")
 
     batch = psi = learned = large = cpu = None
     if args.only == "psicell":

@@ -170,8 +170,9 @@ typedef struct {
     int64_t outside;          /* PSI-CELL particles outside a closed box */
     int64_t zero_support;     /* FLA_DEPOSIT: trajectories with Z_i = 0 */
     int64_t max_class;        /* largest neighbourhood class used by the gather */
-    int64_t graph_replays;    /* fla_project_batch calls on this context that replayed
-                                 a captured graph (host counter, never reset) */
+    int64_t graph_replays;    /* fla_project_batch and fla_project_sources calls on this
+                                 context that replayed a captured graph (host counter,
+                                 never reset) */
 } fla_stats;
 
 /* Create a context on HIP device `device` (host pointer out).  Errors:
@@ -541,6 +542,21 @@ fla_status fla_project_batch(fla_ctx* ctx, int nsnap, const fla_mesh* meshes, co
  * enable == 0: every batch call uploads its table and enqueues the
  * launches directly.  Drops the cached graph.  Errors: INVALID_ARG. */
 fla_status fla_set_batch_graph(fla_ctx* ctx, int enable);
+
+/* Graphs for single calls of fla_project_sources (default off; for callers
+ * that repeat a small projection, whose time is mostly launch latency).
+ * While enabled, and while profiling and FLA_TRACE are off, the first call
+ * with a given set of arguments (every field of the mesh, trajectory,
+ * parameter and field structs, the stream, the gather plan code, the
+ * context's workspace) runs directly; the next call with the same arguments
+ * captures its launch sequence into a HIP graph and launches it, and later
+ * identical calls only launch that graph (counted in
+ * fla_stats.graph_replays).  Buffer contents may change between such calls;
+ * pointers, sizes and parameters may not (a change is a new set of
+ * arguments).  One graph is kept per context.  fla_project_sources_noalloc
+ * never uses it.  Synchronises the device and drops the cached graph.
+ * Errors: INVALID_ARG. */
+fla_status fla_set_graph(fla_ctx* ctx, int enable);
 
 /* Batch plan per (dim, prec): the gather plan code (as fla_set_plan) and the
  * XCD chunk, the number of consecutive work items (tiles) that one of the

@@ -163,6 +163,8 @@ _lib.fla_project_batch.argtypes = [_vp, C.c_int, C.POINTER(fla_mesh), C.POINTER(
                                    C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
 _lib.fla_set_batch_graph.restype = C.c_int
 _lib.fla_set_batch_graph.argtypes = [_vp, C.c_int]
+_lib.fla_set_graph.restype = C.c_int
+_lib.fla_set_graph.argtypes = [_vp, C.c_int]
 _lib.fla_set_batch_plan.restype = C.c_int
 _lib.fla_set_batch_plan.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int]
 _lib.fla_get_batch_plan.restype = C.c_int
@@ -609,6 +611,10 @@ class Context:
         """outs[s]: fla_fields or (S_mass, [S_mom...], den or None)."""
         n, M, T, P, F = self._batch_arrays(meshes, trajs, params, outs)
         self._check(_lib.fla_project_batch(self._h, n, M, T, P, F, _stream_handle(stream)))
+
+    def set_graph(self, enable: bool):
+        """Capture and replay graphs of repeated identical fla_project_sources calls."""
+        self._check(_lib.fla_set_graph(self._h, int(bool(enable))))
 
     def set_batch_graph(self, enable: bool):
         self._check(_lib.fla_set_batch_graph(self._h, int(bool(enable))))

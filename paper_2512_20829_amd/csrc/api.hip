@@ -51,6 +51,12 @@ struct fla_ctx {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<unsigned char> graph_key;
     int64_t graph_replays = 0;
+    // single calls (fla_set_graph): the cached graph of fla_project_sources,
+    // its argument key, and the key of the last direct call
+    bool single_graph = false;
+    hipGraph_t sgraph = nullptr;
+    hipGraphExec_t sgraph_exec = nullptr;
+    std::vector<unsigned char> sgraph_key, sgraph_seen;
     // testing aid (FLA_FAIL_ALLOC=k at creation): the k-th device allocation
     // made for this context fails as if the device were out of memory
     int64_t fail_alloc = 0;
@@ -464,6 +470,16 @@ fla_status project_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, const 
         HIP_OK((launch_gather<R, D>(g, p->mode, p->count_pairs != 0 || out->pairs != nullptr, plan, s)));
     }
     return FLA_OK;
+}
+
+void drop_single_graph(fla_ctx* ctx)
+{
+    if (ctx->sgraph_exec) (void)hipGraphExecDestroy(ctx->sgraph_exec);
+    if (ctx->sgraph) (void)hipGraphDestroy(ctx->sgraph);
+    ctx->sgraph_exec = nullptr;
+    ctx->sgraph = nullptr;
+    ctx->sgraph_key.clear();
+    ctx->sgraph_seen.clear();
 }
 
 void drop_graph(fla_ctx* ctx)
@@ -1022,6 +1038,7 @@ FLA_EXPORT fla_status fla_ctx_destroy(fla_ctx* ctx)
     (void)hipDeviceSynchronize();
     drop_records(ctx);
     drop_graph(ctx);
+    drop_single_graph(ctx);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     if (ctx->items_done) (void)hipEventDestroy(ctx->items_done);
     if (ctx->items) (void)hipFree(ctx->items);
@@ -1099,11 +1116,70 @@ static fla_status project_entry(fla_ctx* ctx, const fla_mesh* mesh, const fla_tr
             HIP_OK(launch_fill_u64(ctx->stats, ST_N, 0ull, s));
             return f64 ? zero_outputs<double>(ctx, m, out, s) : zero_outputs<float>(ctx, m, out, s);
         }
-        if (m.dim == 2)
-            return f64 ? project_impl<double, 2>(ctx, m, t, params, mesh, out, s, fixed, fixed_size)
-                       : project_impl<float, 2>(ctx, m, t, params, mesh, out, s, fixed, fixed_size);
-        return f64 ? project_impl<double, 3>(ctx, m, t, params, mesh, out, s, fixed, fixed_size)
-                   : project_impl<float, 3>(ctx, m, t, params, mesh, out, s, fixed, fixed_size);
+        auto run = [&](hipStream_t q) -> fla_status {
+            if (m.dim == 2)
+                return f64 ? project_impl<double, 2>(ctx, m, t, params, mesh, out, q, fixed, fixed_size)
+                           : project_impl<float, 2>(ctx, m, t, params, mesh, out, q, fixed, fixed_size);
+            return f64 ? project_impl<double, 3>(ctx, m, t, params, mesh, out, q, fixed, fixed_size)
+                       : project_impl<float, 3>(ctx, m, t, params, mesh, out, q, fixed, fixed_size);
+        };
+        // single-call graphs: not on a fixed workspace, while profiling (stage
+        // events) or while tracing (a replay launches nothing the log sees)
+        if (!ctx->single_graph || fixed || ctx->prof || g_trace) return run(s);
+        auto make_key = [&]() {
+            std::vector<unsigned char> k;
+            auto put = [&](const void* p, size_t n) {
+                const unsigned char* b = (const unsigned char*)p;
+                k.insert(k.end(), b, b + n);
+            };
+            put(mesh, sizeof(*mesh));
+            put(traj, sizeof(*traj));
+            put(params, sizeof(*params));
+            put(out, sizeof(*out));
+            put(&s, sizeof(s));
+            put(&ctx->ws, sizeof(ctx->ws));
+            put(&ctx->plan[m.dim - 2][traj->prec], sizeof(int));
+            return k;
+        };
+        std::vector<unsigned char> key = make_key();
+        if (ctx->sgraph_exec && key == ctx->sgraph_key) {
+            HIP_OK(hipGraphLaunch(ctx->sgraph_exec, s));
+            ++ctx->graph_replays;
+            return FLA_OK;
+        }
+        if (key != ctx->sgraph_seen) {
+            // a new set of arguments runs directly once (it may grow the
+            // workspace, which a capture must not do); its key is taken after
+            // the call, with the workspace it left
+            const fla_status dst = run(s);
+            if (dst == FLA_OK) ctx->sgraph_seen = make_key();
+            return dst;
+        }
+        // the same arguments again: capture, keep and launch
+        drop_single_graph(ctx);
+        if (!ctx->capture) HIP_OK(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+        HIP_OK(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+        const fla_status cst = run(ctx->capture);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
+        if (cst != FLA_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            if (cst != FLA_OK) return cst;
+            ctx->err = std::string("graph capture failed: ") + hipGetErrorString(e);
+            return FLA_ERR_DEVICE;
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            ctx->err = std::string("graph instantiation failed: ") + hipGetErrorString(ei);
+            return FLA_ERR_DEVICE;
+        }
+        ctx->sgraph = graph;
+        ctx->sgraph_exec = exec;
+        ctx->sgraph_key.swap(key);
+        HIP_OK(hipGraphLaunch(exec, s));
+        return FLA_OK;
     } catch (...) {
         ctx->err = "internal error";
         return FLA_ERR_DEVICE;
@@ -1498,6 +1574,17 @@ FLA_EXPORT fla_status fla_project_batch(fla_ctx* ctx, int nsnap, const fla_mesh*
             return FLA_ERR_DEVICE;
         }
     }());
+}
+
+FLA_EXPORT fla_status fla_set_graph(fla_ctx* ctx, int enable)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    HIP_OK(hipSetDevice(ctx->device));
+    HIP_OK(hipDeviceSynchronize());
+    drop_single_graph(ctx);
+    ctx->single_graph = enable != 0;
+    return FLA_OK;
 }
 
 FLA_EXPORT fla_status fla_set_batch_graph(fla_ctx* ctx, int enable)
