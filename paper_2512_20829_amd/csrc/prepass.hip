@@ -144,13 +144,13 @@ __global__ void k_permute(const uint32_t* order, int64_t n, const double4* rpos_
 constexpr int kZTab = 128;
 
 // Deposition normaliser Z_i = sum over the cells in reach of the kernel
-// factors, one wave per valid trajectory (sorted order; the waves of a
-// workgroup take trajectories in turn), written into its weight record as
+// factors, one half wave per valid trajectory (sorted order; the half waves
+// of a workgroup take trajectories in turn), written into its weight record as
 // {1/h, Q/(h Z)} (the 1/h factors cancel); with Z = 0 the record becomes a
 // delta record {0, Q} flagged by 1/h < 0.  Per-axis factors of the cells in
 // the trajectory's support box go to LDS (same binary64 offsets and the same
 // inclusion test as the gather), lanes sweep the rows, and a fixed butterfly
-// reduces the wave.  The support box is swept in blocks of
+// reduces the half wave.  The support box is swept in blocks of
 // at most kZTab cells per axis.  Within a block, a cell (jx, jy, jz) is
 // included iff (S0[jx] + S1[jy]) + S2[jz] <= c^2, evaluated in the working
 // precision exactly as the gather does.  Floating-point addition is monotone,
@@ -168,10 +168,17 @@ struct NormLds {
     double Pf[kZTab + 1];      // Pf[k] = sum of E0 over the k smallest S0
     R Es[kZTab];
 };
-// Waves per workgroup of the normaliser; each wave takes trajectories
-// p = wave id, wave id + all waves, ... with its own LDS tables, so the
-// workgroups are few and long-lived rather than one short one per trajectory.
+// Waves per workgroup of the normaliser; each half wave (kNormLanes lanes)
+// takes trajectories p = 2 (wave id) + half, + all half waves, ... with its
+// own LDS tables, so the workgroups are few and long-lived rather than one
+// short one per trajectory.  A support box spans about 2 c h |det J| / w
+// cells per axis (tens), so half a wave covers an axis table in one pass
+// and the two halves of a wave work on two trajectories at once.
 constexpr int kNormWaves = 4;
+constexpr int kNormLanes = 32;
+constexpr int kNormPerWave = kWave / kNormLanes;
+constexpr int kNormRanksPerLane = kZTab / kNormLanes;
+static_assert(kZTab % kNormLanes == 0 && kWave % kNormLanes == 0, "ranks and half waves tile evenly");
 
 template <typename R, int D>
 __global__ __launch_bounds__(kWave * kNormWaves) void k_deposit_norm(MeshDev m, PhysDev ph, const uint32_t* nvalid,
@@ -180,130 +187,145 @@ __global__ __launch_bounds__(kWave * kNormWaves) void k_deposit_norm(MeshDev m, 
                                                                     unsigned long long* stats)
 {
     constexpr int C = D + 1;
-    __shared__ NormLds<R> lds[kNormWaves];
+    constexpr int NL = kNormLanes;
+    __shared__ NormLds<R> lds[kNormWaves][kNormPerWave];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    R (*S)[kZTab] = lds[wave].S;
-    R (*E)[kZTab] = lds[wave].E;
-    R* Ss = lds[wave].Ss;
-    double* Pf = lds[wave].Pf;
-    R* Es = lds[wave].Es;
+    const int sub = lane / NL, sl = lane % NL;
+    R (*S)[kZTab] = lds[wave][sub].S;
+    R (*E)[kZTab] = lds[wave][sub].E;
+    R* Ss = lds[wave][sub].Ss;
+    double* Pf = lds[wave][sub].Pf;
+    R* Es = lds[wave][sub].Es;
     const int64_t nv = (int64_t)*nvalid;
-    for (int64_t p = (int64_t)blockIdx.x * kNormWaves + wave; p < nv; p += (int64_t)gridDim.x * kNormWaves) {
-        double4 P = rpos[p];
-        double x[3] = {P.x, P.y, P.z};
-        double inv_h = P.w;
-        double h = 1.0 / inv_h;
-        double rc = ph.cutoff * h * (1.0 + kSupportMargin);
-        R c2;
-        {
-            R c = (R)ph.cutoff;
-            c2 = c * c;
-        }
-        int64_t lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
-        for (int a = 0; a < D; ++a) {
-            double flo = (x[a] - rc - m.lo[a]) / m.w[a] - 0.5 - 1e-9;
-            double fhi = (x[a] + rc - m.lo[a]) / m.w[a] - 0.5 + 1e-9;
-            flo = fmin(fmax(flo, -4.0e15), 4.0e15);
-            fhi = fmin(fmax(fhi, -4.0e15), 4.0e15);
-            int64_t ilo = (int64_t)ceil(flo), ihi = (int64_t)floor(fhi);
-            if (m.periodic[a]) {
-                if (ihi - ilo + 1 >= m.n[a]) { ilo = 0; ihi = m.n[a] - 1; }
-            } else {
-                ilo = ilo < 0 ? 0 : ilo;
-                ihi = ihi >= m.n[a] ? m.n[a] - 1 : ihi;
-            }
-            lo[a] = ilo;
-            cnt[a] = ihi - ilo + 1;
-            if (cnt[a] < 0) cnt[a] = 0;
-        }
-        double z = 0.0;
-        for (int64_t bz = 0; bz < cnt[2]; bz += kZTab)
-        for (int64_t by = 0; by < cnt[1]; by += kZTab)
-        for (int64_t bx = 0; bx < cnt[0]; bx += kZTab) {
-            int64_t b0[3] = {bx, by, bz};
-            int len[3];
-            for (int a = 0; a < 3; ++a) {
-                int64_t l = cnt[a] - b0[a];
-                len[a] = (int)(l < kZTab ? l : kZTab);
-            }
-            wave_sync();
-            for (int a = 0; a < D; ++a) {
-                for (int j = lane; j < len[a]; j += kWave) {
-                    int64_t ci = lo[a] + b0[a] + j;
-                    if (m.periodic[a]) ci = posmod(ci, m.n[a]);
-                    axis_factor<R>(m, a, ci, x[a], inv_h, S[a][j], E[a][j]);
-                }
-            }
-            if (D == 2 && lane == 0) { S[2][0] = 0; E[2][0] = 1; }
-            wave_sync();
-            // rank of each S0 (ties broken by index): a permutation of 0..len0-1
-            for (int j = lane; j < len[0]; j += kWave) {
-                const R v = S[0][j];
-                int r = 0;
-                for (int i = 0; i < len[0]; ++i) {
-                    const R u = S[0][i];
-                    r += (u < v || (u == v && i < j)) ? 1 : 0;
-                }
-                Ss[r] = v;
-                Es[r] = E[0][j];
-            }
-            wave_sync();
-            // prefix sums of E0 in rank order: lane l owns ranks 2l and 2l + 1
+    const int64_t stride = (int64_t)gridDim.x * kNormWaves * kNormPerWave;
+    for (int64_t p0 = ((int64_t)blockIdx.x * kNormWaves + wave) * kNormPerWave; p0 < nv; p0 += stride) {
+        const int64_t p = p0 + sub;
+        if (p < nv) {
+            double4 P = rpos[p];
+            double x[3] = {P.x, P.y, P.z};
+            double inv_h = P.w;
+            double h = 1.0 / inv_h;
+            double rc = ph.cutoff * h * (1.0 + kSupportMargin);
+            R c2;
             {
-                const int r0 = 2 * lane, r1 = 2 * lane + 1;
-                const double e0 = r0 < len[0] ? (double)Es[r0] : 0.0;
-                const double e1 = r1 < len[0] ? (double)Es[r1] : 0.0;
-                double incl = e0 + e1;
-#pragma unroll
-                for (int o = 1; o < kWave; o <<= 1) {
-                    double t = __shfl_up(incl, o, kWave);
-                    if (lane >= o) incl += t;
-                }
-                const double excl = incl - (e0 + e1);
-                if (lane == 0) Pf[0] = 0.0;
-                if (r0 < len[0]) Pf[r0 + 1] = excl + e0;
-                if (r1 < len[0]) Pf[r1 + 1] = incl;
+                R c = (R)ph.cutoff;
+                c2 = c * c;
             }
-            wave_sync();
-            const int n0 = len[0];
-            const R smin = Ss[0];
-            const int64_t rows = (int64_t)len[1] * (D == 3 ? len[2] : 1);
-            for (int64_t j = lane; j < rows; j += kWave) {
-                const int jy = (int)(j % len[1]);
-                const int jz = (int)(j / len[1]);
-                const R sy = S[1][jy], sz = S[2][jz];
-                // number of ranks k with (Ss[k] + sy) + sz <= c^2 (a prefix)
-                R s = smin + sy;
-                if (D == 3) s = s + sz;
-                if (!(s <= c2)) continue;
-                int klo = 1, khi = n0;
-                while (klo < khi) {
-                    const int mid = (klo + khi + 1) >> 1;
-                    R t = Ss[mid - 1] + sy;
-                    if (D == 3) t = t + sz;
-                    if (t <= c2)
-                        klo = mid;
-                    else
-                        khi = mid - 1;
+            int64_t lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+            for (int a = 0; a < D; ++a) {
+                double flo = (x[a] - rc - m.lo[a]) / m.w[a] - 0.5 - 1e-9;
+                double fhi = (x[a] + rc - m.lo[a]) / m.w[a] - 0.5 + 1e-9;
+                flo = fmin(fmax(flo, -4.0e15), 4.0e15);
+                fhi = fmin(fmax(fhi, -4.0e15), 4.0e15);
+                int64_t ilo = (int64_t)ceil(flo), ihi = (int64_t)floor(fhi);
+                if (m.periodic[a]) {
+                    if (ihi - ilo + 1 >= m.n[a]) { ilo = 0; ihi = m.n[a] - 1; }
+                } else {
+                    ilo = ilo < 0 ? 0 : ilo;
+                    ihi = ihi >= m.n[a] ? m.n[a] - 1 : ihi;
                 }
-                z += Pf[klo] * ((double)E[1][jy] * (double)E[2][jz]);
+                lo[a] = ilo;
+                cnt[a] = ihi - ilo + 1;
+                if (cnt[a] < 0) cnt[a] = 0;
             }
-        }
+            double z = 0.0;
+            for (int64_t bz = 0; bz < cnt[2]; bz += kZTab)
+            for (int64_t by = 0; by < cnt[1]; by += kZTab)
+            for (int64_t bx = 0; bx < cnt[0]; bx += kZTab) {
+                int64_t b0[3] = {bx, by, bz};
+                int len[3];
+                for (int a = 0; a < 3; ++a) {
+                    int64_t l = cnt[a] - b0[a];
+                    len[a] = (int)(l < kZTab ? l : kZTab);
+                }
+                wave_sync();
+                for (int a = 0; a < D; ++a) {
+                    for (int j = sl; j < len[a]; j += NL) {
+                        int64_t ci = lo[a] + b0[a] + j;
+                        if (m.periodic[a]) ci = posmod(ci, m.n[a]);
+                        axis_factor<R>(m, a, ci, x[a], inv_h, S[a][j], E[a][j]);
+                    }
+                }
+                if (D == 2 && sl == 0) { S[2][0] = 0; E[2][0] = 1; }
+                wave_sync();
+                // rank of each S0 (ties broken by index): a permutation of 0..len0-1
+                for (int j = sl; j < len[0]; j += NL) {
+                    const R v = S[0][j];
+                    int r = 0;
+                    for (int i = 0; i < len[0]; ++i) {
+                        const R u = S[0][i];
+                        r += (u < v || (u == v && i < j)) ? 1 : 0;
+                    }
+                    Ss[r] = v;
+                    Es[r] = E[0][j];
+                }
+                wave_sync();
+                // prefix sums of E0 in rank order: lane sl owns ranks
+                // kNormRanksPerLane sl .. + kNormRanksPerLane - 1
+                {
+                    double e[kNormRanksPerLane], part = 0.0;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o, kWave);
-        if (lane == 0) {
-            // K_ci / Z_i = E_ci / z_i with z_i = sum_c E_ci (the 1/h factors cancel)
-            uint32_t i = order[p];
-            R* w = rw + p * kRecW;
-            if (z > 0.0) {
-                w[0] = (R)inv_h;
-                for (int k = 0; k < C; ++k) w[1 + k] = (R)(qd[(int64_t)k * N + i] / z);
-            } else {
-                w[0] = (R)0;
-                for (int k = 0; k < C; ++k) w[1 + k] = (R)qd[(int64_t)k * N + i];
-                rpos[p].w = -inv_h;
-                atomicAdd(&stats[ST_ZERO], 1ull);
+                    for (int q = 0; q < kNormRanksPerLane; ++q) {
+                        const int r = kNormRanksPerLane * sl + q;
+                        e[q] = r < len[0] ? (double)Es[r] : 0.0;
+                        part += e[q];
+                    }
+                    double incl = part;
+#pragma unroll
+                    for (int o = 1; o < NL; o <<= 1) {
+                        double t = __shfl_up(incl, o, NL);
+                        if (sl >= o) incl += t;
+                    }
+                    double run = incl - part;
+                    if (sl == 0) Pf[0] = 0.0;
+#pragma unroll
+                    for (int q = 0; q < kNormRanksPerLane; ++q) {
+                        const int r = kNormRanksPerLane * sl + q;
+                        run += e[q];
+                        if (r < len[0]) Pf[r + 1] = run;
+                    }
+                }
+                wave_sync();
+                const int n0 = len[0];
+                const R smin = Ss[0];
+                const int64_t rows = (int64_t)len[1] * (D == 3 ? len[2] : 1);
+                for (int64_t j = sl; j < rows; j += NL) {
+                    const int jy = (int)(j % len[1]);
+                    const int jz = (int)(j / len[1]);
+                    const R sy = S[1][jy], sz = S[2][jz];
+                    // number of ranks k with (Ss[k] + sy) + sz <= c^2 (a prefix)
+                    R s = smin + sy;
+                    if (D == 3) s = s + sz;
+                    if (!(s <= c2)) continue;
+                    int klo = 1, khi = n0;
+                    while (klo < khi) {
+                        const int mid = (klo + khi + 1) >> 1;
+                        R t = Ss[mid - 1] + sy;
+                        if (D == 3) t = t + sz;
+                        if (t <= c2)
+                            klo = mid;
+                        else
+                            khi = mid - 1;
+                    }
+                    z += Pf[klo] * ((double)E[1][jy] * (double)E[2][jz]);
+                }
+            }
+#pragma unroll
+            for (int o = NL / 2; o > 0; o >>= 1) z += __shfl_xor(z, o, NL);
+            if (sl == 0) {
+                // K_ci / Z_i = E_ci / z_i with z_i = sum_c E_ci (the 1/h factors cancel)
+                uint32_t i = order[p];
+                R* w = rw + p * kRecW;
+                if (z > 0.0) {
+                    w[0] = (R)inv_h;
+                    for (int k = 0; k < C; ++k) w[1 + k] = (R)(qd[(int64_t)k * N + i] / z);
+                } else {
+                    w[0] = (R)0;
+                    for (int k = 0; k < C; ++k) w[1 + k] = (R)qd[(int64_t)k * N + i];
+                    rpos[p].w = -inv_h;
+                    atomicAdd(&stats[ST_ZERO], 1ull);
+                }
             }
         }
         wave_sync();   // the tables are rewritten for the next trajectory
@@ -361,7 +383,7 @@ hipError_t launch_deposit_norm(const MeshDev& m, const PhysDev& ph, const uint32
                                unsigned long long* stats, hipStream_t s)
 {
     if (N == 0) return hipSuccess;
-    const int64_t want = (N + kNormWaves - 1) / kNormWaves;
+    const int64_t want = (N + kNormWaves * kNormPerWave - 1) / (kNormWaves * kNormPerWave);
     const unsigned grid = (unsigned)(want < 8192 ? want : 8192);
     FLA_LAUNCH((k_deposit_norm<R, D>), dim3(grid), dim3(kWave * kNormWaves), 0, s, m, ph, nvalid, order,
                        qd, N, rpos, rw, stats);
