@@ -141,7 +141,7 @@ __global__ void k_permute(const uint32_t* order, int64_t n, const double4* rpos_
     }
 }
 
-constexpr int kZTab = 128;
+constexpr int kZTab = 64;
 
 // Deposition normaliser Z_i = sum over the cells in reach of the kernel
 // factors, one half wave per valid trajectory (sorted order; the half waves

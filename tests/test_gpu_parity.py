@@ -196,6 +196,22 @@ def test_deposit_matches_oracle_and_conserves(ctx, prec):
     assert st["zero_support"] == int((Z[t.valid == 1] == 0).sum())
 
 
+@pytest.mark.parametrize("periodic", [True, False])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_deposit_wide_supports_span_several_blocks(ctx, prec, periodic):
+    # h0 = 0.15 on 70^3 cells: supports of 2 c h |det J| ~ 80 cells per axis
+    # and more, wider than the normaliser's 64-cell blocks (the whole axis
+    # on a periodic mesh, clipped at the walls of a closed one)
+    print(f"[case] deposit wide supports {prec} periodic={periodic}", flush=True)
+    wl = W.small_random_3d(200, 70, seed=17, periodic=periodic, h0=0.15)
+    S, den, st = gpu_run(ctx, wl, prec=prec, mode=1)
+    tr = as_precision(wl.traj, prec)
+    t = oracle.trajectory_terms(tr, wl.rho_d, wl.mu, wl.delta, wl.h0)
+    Sref, Z = oracle.deposit(wl.mesh, tr.x, t, tr.seed_volume, f32_decision=(prec == "f32"))
+    assert_fields_close(S, Sref, TOL[prec], "deposit wide")
+    assert st["zero_support"] == int((Z[t.valid == 1] == 0).sum())
+
+
 def test_deposit_zero_support_goes_home(ctx):
     wl = W.small_random_3d(800, 12, seed=12, periodic=False, h0=0.004)
     S, _, st = gpu_run(ctx, wl, prec="f64", mode=1)
