@@ -5,10 +5,11 @@
 // the trajectories of its tile in a fixed order, so results are bitwise
 // reproducible.
 //
-// Work decomposition (one workgroup of four 64-lane waves per half tile in
-// 3-D, the tile cut across x; two waves per tile in 2-D; the waves take the
-// candidate chunks in turn and their partial sums are added in wave order at
-// the end):
+// Work decomposition (one workgroup of four 64-lane waves per part of a tile
+// in 3-D: half the tile, cut across x, by default, or the whole tile; two
+// waves per tile in 2-D; the waves take the candidate chunks in turn and
+// their partial sums are added in wave order at the end; the workgroups are
+// persistent and take their XCD's parts in heaviest-first order, k_gather):
 //  * a tile is TE^D cells, split into 2^D sub-blocks of SB^D cells; lane l
 //    owns the cell with in-block coordinates lc(l) in every sub-block of its
 //    workgroup;
