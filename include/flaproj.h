@@ -579,6 +579,20 @@ fla_status fla_autotune_batch(fla_ctx* ctx, int nsnap, const fla_mesh* meshes, c
                               const fla_params* params, const fla_fields* outs, void* stream,
                               double* times_ms);
 
+/* Saving the plans: callers keep the autotuners' choices across processes.
+ * fla_save_plans writes, to the text file at path, the context's gather
+ * plan code and batch plan (code and chunk) for every (dim, prec), -1 where
+ * the library default is in use, keyed by the device's architecture name
+ * (for example gfx950): a header line "flaproj-plans 1", then one line
+ * "<arch> <dim> <prec> <plan code> <batch plan code> <chunk>" each.
+ * fla_load_plans reads such a file and sets the plans of the lines for this
+ * device's architecture (lines for other architectures are ignored).  A
+ * file that cannot be read, lacks the header or holds a malformed or
+ * out-of-range line changes nothing and returns INVALID_ARG (message in
+ * fla_last_error).  Host files only; no device work. */
+fla_status fla_save_plans(fla_ctx* ctx, const char* path);
+fla_status fla_load_plans(fla_ctx* ctx, const char* path);
+
 /* ------------------------------------------------------------------------
  * General meshes (App. A, "Cell volume scaling" and "Combining the mass and
  * volume scaling factors"): the carrier solver's cells are given by their

@@ -163,6 +163,10 @@ _lib.fla_project_batch.argtypes = [_vp, C.c_int, C.POINTER(fla_mesh), C.POINTER(
                                    C.POINTER(fla_params), C.POINTER(fla_fields), _vp]
 _lib.fla_set_batch_graph.restype = C.c_int
 _lib.fla_set_batch_graph.argtypes = [_vp, C.c_int]
+_lib.fla_save_plans.restype = C.c_int
+_lib.fla_save_plans.argtypes = [_vp, C.c_char_p]
+_lib.fla_load_plans.restype = C.c_int
+_lib.fla_load_plans.argtypes = [_vp, C.c_char_p]
 _lib.fla_set_graph.restype = C.c_int
 _lib.fla_set_graph.argtypes = [_vp, C.c_int]
 _lib.fla_set_batch_plan.restype = C.c_int
@@ -611,6 +615,14 @@ class Context:
         """outs[s]: fla_fields or (S_mass, [S_mom...], den or None)."""
         n, M, T, P, F = self._batch_arrays(meshes, trajs, params, outs)
         self._check(_lib.fla_project_batch(self._h, n, M, T, P, F, _stream_handle(stream)))
+
+    def save_plans(self, path: str):
+        """Write the context's gather and batch plans (per dim, precision) for this device's architecture."""
+        self._check(_lib.fla_save_plans(self._h, os.fsencode(path)))
+
+    def load_plans(self, path: str):
+        """Set the plans saved for this device's architecture; a bad file changes nothing."""
+        self._check(_lib.fla_load_plans(self._h, os.fsencode(path)))
 
     def set_graph(self, enable: bool):
         """Capture and replay graphs of repeated identical fla_project_sources calls."""

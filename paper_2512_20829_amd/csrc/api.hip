@@ -1625,6 +1625,88 @@ FLA_EXPORT fla_status fla_get_batch_plan(fla_ctx* ctx, int dim, int prec, int* g
     return FLA_OK;
 }
 
+// Architecture name of the context's device (the key of saved plans).
+static fla_status device_arch(fla_ctx* ctx, std::string& arch)
+{
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, ctx->device));
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);   // target features do not change the plans
+    if (arch.empty()) arch = "unknown";
+    return FLA_OK;
+}
+
+static const char* kPlansHeader = "flaproj-plans 1";
+
+FLA_EXPORT fla_status fla_save_plans(fla_ctx* ctx, const char* path)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(path != nullptr, "path is NULL");
+    std::string arch;
+    fla_status st = device_arch(ctx, arch);
+    if (st != FLA_OK) return st;
+    FILE* f = std::fopen(path, "w");
+    CHECK_ARG(f != nullptr, std::string("cannot open ") + path + " for writing");
+    std::fprintf(f, "%s\n", kPlansHeader);
+    for (int d = 0; d < 2; ++d)
+        for (int pr = 0; pr < 2; ++pr)
+            std::fprintf(f, "%s %d %d %d %d %d\n", arch.c_str(), d + 2, pr, ctx->plan[d][pr], ctx->batch_plan[d][pr],
+                         ctx->batch_chunk[d][pr]);
+    const bool ok = std::fflush(f) == 0 && !std::ferror(f);
+    std::fclose(f);
+    CHECK_ARG(ok, std::string("cannot write ") + path);
+    return FLA_OK;
+}
+
+FLA_EXPORT fla_status fla_load_plans(fla_ctx* ctx, const char* path)
+{
+    if (!ctx) return FLA_ERR_INVALID_ARG;
+    ctx->err.clear();
+    CHECK_ARG(path != nullptr, "path is NULL");
+    std::string arch;
+    fla_status st = device_arch(ctx, arch);
+    if (st != FLA_OK) return st;
+    FILE* f = std::fopen(path, "r");
+    CHECK_ARG(f != nullptr, std::string("cannot open ") + path);
+    struct Entry {
+        int d, pr, plan, bplan, chunk;
+    };
+    std::vector<Entry> take;
+    char line[512];
+    bool header = false, bad = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        std::string l(line);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        if (l.empty()) continue;
+        if (!header) {
+            header = l == kPlansHeader;
+            if (!header) bad = true;
+            if (bad) break;
+            continue;
+        }
+        char a[256];
+        int dim, pr, plan, bplan, chunk;
+        char extra;
+        if (std::sscanf(l.c_str(), "%255s %d %d %d %d %d %c", a, &dim, &pr, &plan, &bplan, &chunk, &extra) != 6 ||
+            (dim != 2 && dim != 3) || (pr != FLA_F32 && pr != FLA_F64) || plan < -1 || plan >= plan_codes(dim) ||
+            bplan < -1 || bplan >= plan_codes(dim) || (bplan >= 0 && (chunk < 1 || chunk > 4096))) {
+            bad = true;
+            break;
+        }
+        if (arch == a) take.push_back({dim - 2, pr, plan, bplan, bplan < 0 ? -1 : chunk});
+    }
+    std::fclose(f);
+    CHECK_ARG(header && !bad, std::string(path) + " is not a plan file of this library (nothing was changed)");
+    for (const Entry& e : take) {
+        ctx->plan[e.d][e.pr] = e.plan;
+        ctx->batch_plan[e.d][e.pr] = e.bplan;
+        ctx->batch_chunk[e.d][e.pr] = e.chunk;
+    }
+    return FLA_OK;
+}
+
 FLA_EXPORT fla_status fla_autotune_batch(fla_ctx* ctx, int nsnap, const fla_mesh* meshes,
                                          const fla_trajectories* trajs, const fla_params* params,
                                          const fla_fields* outs, void* stream, double* times_ms)
