@@ -218,7 +218,7 @@ def large_section(ctx, args, dev, model):
     """The 256^3 multi-vortex case with strong caustics: the plain, learned
     (the network trained on the 64^3 ABC snapshots, if available) and
     deposition errors against a chunked PSI-CELL reference at 320^3 down to
-    100^3 lattice trajectories, the seeding at which the learned
+    16^3 lattice trajectories, the seeding at which the learned
     form matches the plain form's error at 320^3, and the learned form's
     throughput at 320^3 (the plain form's is the headline line)."""
     import numpy as np
@@ -238,7 +238,7 @@ def large_section(ctx, args, dev, model):
         f"noise floor {[round(math.sqrt(f), 4) for f in floor]}")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     rows, perf = [], None
-    for pa in (320, 256, 200, 160, 128, 100):
+    for pa in (320, 256, 200, 160, 128, 100, 80, 64, 50, 40, 32, 25, 20, 16):
         wl = W.multi_vortex_lattice_3d(per_axis=pa, mesh_n=256, device=dev)
         tr = wl.traj
         st, keep = F.make_trajectories(tr.x, tr.J, tr.v.float(), tr.ug.float(), tr.r.float(), tr.n0, tr.seed_volume)
