@@ -790,11 +790,25 @@ fla_status cic_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double wei
     constexpr int W = PsiWords<R>::value;
     PsiArgs a{};
     // tiles of power-of-two edges whose upper halo fits the LDS sums:
-    // 16 x 8 x 8 (binary64: 8^3) in 3-D, 32^2 (binary64: 32 x 16) in 2-D
+    // 16 x 8 x 8 (binary64: 8^3) in 3-D, 32^2 (binary64: 32 x 16) in 2-D;
+    // or, sorted, the larger tiles 16 x 16 x 8 (binary64: 16 x 8 x 8) in 3-D,
+    // 64^2 (binary64: 64 x 32) in 2-D, when the mesh needs at most
+    // kCicMaxBins of them and the device allows their LDS sums
     const bool f64 = sizeof(R) == 8;
+    auto tiles_of = [&](const int* t) {
+        int64_t n = 1;
+        for (int ax = 0; ax < D; ++ax) n *= (m.n[ax] + t[ax] - 1) / t[ax];
+        return n;
+    };
+    const int pts[3] = {D == 3 ? 16 : 64, D == 3 ? (f64 ? 8 : 16) : (f64 ? 32 : 64), D == 3 ? 8 : 1};
+    int max_lds = 0;
+    HIP_OK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    const int64_t halo_s = (int64_t)(pts[0] + 1) * (pts[1] + 1) * (D == 3 ? pts[2] + 1 : 1);
+    const bool sorted = tiles_of(pts) <= kCicMaxBins && halo_s * (W * (C + 1)) * 8 <= max_lds;
     int pt[3] = {D == 3 ? (f64 ? 8 : 16) : 32, D == 3 ? 8 : (f64 ? 16 : 32), D == 3 ? 8 : 1};
-    int64_t nt = 1;
-    for (int ax = 0; ax < D; ++ax) nt *= (m.n[ax] + pt[ax] - 1) / pt[ax];
+    if (sorted)
+        for (int ax = 0; ax < 3; ++ax) pt[ax] = pts[ax];
+    const int64_t nt = tiles_of(pt);
     CHECK_ARG(nt <= kPsiMaxTiles, f64 ? "cic_accumulate supports at most 16384 * 512 cells in binary64"
                                       : "cic_accumulate supports at most 16384 * 1024 cells");
     for (int ax = 0; ax < 3; ++ax) {
@@ -806,6 +820,7 @@ fla_status cic_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double wei
     a.cpt = a.pt[0] * a.pt[1] * a.pt[2];
     a.cptlog = a.ptlog[0] + a.ptlog[1] + a.ptlog[2];
     a.nblocks = kPsiBlocks;
+    a.direct = sorted ? 1 : 0;
     const int64_t N = t.count;
     const int64_t hw = (int64_t)a.pntiles * a.nblocks + 1;
     const int64_t sw = scan_tmp_words(hw);
@@ -817,7 +832,7 @@ fla_status cic_impl(fla_ctx* ctx, const MeshDev& m, const TrajDev& t, double wei
         a.tcursor = c.take<unsigned int>(a.pntiles);
         a.bucket = c.take<CicRec<R>>(N > 0 ? N : 1);
         a.blockmax = c.take<unsigned long long>((size_t)a.nblocks * 4);
-        a.acc = c.take<unsigned long long>((size_t)(W * C + 1) * (size_t)m.M);
+        a.acc = c.take<unsigned long long>((size_t)(W * (C + 1)) * (size_t)m.M);
         a.scan_tmp = c.take<uint32_t>(sw);
     };
     {

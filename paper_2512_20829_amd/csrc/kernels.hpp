@@ -177,7 +177,9 @@ template <typename R> struct CicRec {
 };
 
 // Cloud-in-cell accumulation on the PSI-CELL tile buckets (tiles of a.pt
-// cells, keyed by each particle's lower-corner cell).
+// cells, keyed by each particle's lower-corner cell).  With a.direct the
+// scatter sorts its rounds by tile in LDS (at most kCicMaxBins tiles).
+constexpr int kCicMaxBins = 1024;
 template <typename R, int D>
 hipError_t launch_cic(const PsiArgs& a, hipStream_t s);
 

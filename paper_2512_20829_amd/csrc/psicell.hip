@@ -730,16 +730,158 @@ __global__ __launch_bounds__(256) void k_cic_scatter(PsiArgs a)
     }
 }
 
+// Records into tile buckets, sorted: each block takes its contiguous range
+// of particles in rounds, orders a round's records by tile in LDS (counting
+// sort) and writes them out as one contiguous run per tile, at the slots of
+// its scanned per-tile counts (as the PSI-CELL scatter does with its bins;
+// here the bins are the tiles, at most kCicMaxBins of them).  Records keep
+// their whole code (tile and cell) with the skip bit.
+template <typename R> struct CicRoundPerThread { static constexpr int value = sizeof(R) == 4 ? 14 : 7; };
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_cic_scatter_sorted(PsiArgs a)
+{
+    constexpr int C = D + 1;
+    constexpr int NT = 256;
+    constexpr int U = CicRoundPerThread<R>::value;
+    constexpr int RB = NT * U;
+    constexpr int BPT = kCicMaxBins / NT;
+    __shared__ CicRec<R> stage[RB];
+    __shared__ unsigned int cnt[kCicMaxBins], off[kCicMaxBins], delta[kCicMaxBins], cursor[kCicMaxBins];
+    __shared__ unsigned int ws[NT / kWave];
+    const int tid = threadIdx.x;
+    const int nbin = a.pntiles;
+    const int bsh = a.cptlog;
+    for (int b = tid; b < nbin; b += NT) {
+        cursor[b] = a.blockhist[(int64_t)b * gridDim.x + blockIdx.x];
+        cnt[b] = 0;
+    }
+    __syncthreads();
+    const int64_t N = a.p.count;
+    const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = beg + chunk < N ? beg + chunk : N;
+    CicRec<R>* bucket = (CicRec<R>*)a.bucket;
+    double mx[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) mx[k] = 0.0;
+    unsigned long long bad = 0;
+    for (int64_t r0 = beg; r0 < end; r0 += RB) {
+        int code[U];
+        unsigned int rank[U];
+        CicRec<R> rec[U];
+        R v[U][3], ug[U][3], rr[U];
+        double xp[U][3];
+        // the round's loads first: codes, then the inputs of every live particle
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = r0 + (int64_t)u * NT + tid;
+            code[u] = p < end ? a.codes[p] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = r0 + (int64_t)u * NT + tid;
+            const bool live = code[u] >= 0;
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                v[u][ax] = live ? ((const R*)a.p.v[ax])[p] : (R)0;
+                ug[u][ax] = live ? ((const R*)a.p.ug[ax])[p] : (R)0;
+                xp[u][ax] = live ? a.p.x[ax][p] : 0.0;
+            }
+            rr[u] = live ? ((const R*)a.p.r)[p] : (R)1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            rank[u] = 0;
+            if (code[u] < 0) continue;
+            bool ok = isfinite(rr[u]);
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) ok = ok && isfinite(v[u][ax]) && isfinite(ug[u][ax]);
+            R phi[4] = {0, 0, 0, 0};
+            if (ok) {
+                droplet_phi_t<D, R>(rr[u], v[u], ug[u], a.ph, phi);
+#pragma unroll
+                for (int k = 0; k < C; ++k) ok = ok && isfinite(phi[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rec[u].phi[k] = (ok && k < C) ? phi[k] : (R)0;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) rec[u].frac[ax] = (R)0;
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                int k0;
+                double f;
+                cic_axis(a.m, ax, xp[u][ax], k0, f);
+                rec[u].frac[ax] = (R)f;
+            }
+            rec[u].loc = (uint32_t)code[u] | (ok ? 0u : kPsiSkipBit);
+            bad += ok ? 0ull : 1ull;
+#pragma unroll
+            for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], fabs((double)rec[u].phi[k]));
+            rank[u] = atomicAdd(&cnt[code[u] >> bsh], 1u);
+        }
+        __syncthreads();
+        // tiles BPT tid .. BPT tid + BPT - 1
+        const int b0 = BPT * tid;
+        unsigned int c[BPT], sum = 0;
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            c[k] = b0 + k < nbin ? cnt[b0 + k] : 0u;
+            sum += c[k];
+        }
+        unsigned int total;
+        unsigned int ex = block_exclusive_sum<NT>(sum, ws, total);
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            if (b0 + k < nbin) {
+                off[b0 + k] = ex;
+                delta[b0 + k] = cursor[b0 + k] - ex;
+                cursor[b0 + k] += c[k];
+                cnt[b0 + k] = 0;
+            }
+            ex += c[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (code[u] < 0) continue;
+            stage[off[code[u] >> bsh] + rank[u]] = rec[u];
+        }
+        __syncthreads();
+        for (unsigned int i = tid; i < total; i += NT) {
+            const CicRec<R> q = stage[i];
+            bucket[delta[(q.loc & ~kPsiSkipBit) >> bsh] + i] = q;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, kWave);
+    if ((threadIdx.x % kWave) == 0 && bad) atomicAdd(&a.stats[ST_SKIPPED], bad);
+    __shared__ double bm[NT / kWave][4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < C; ++k) mx[k] = fmax(mx[k], __shfl_xor(mx[k], o, kWave));
+    if ((threadIdx.x % kWave) == 0)
+#pragma unroll
+        for (int k = 0; k < C; ++k) bm[threadIdx.x / kWave][k] = mx[k];
+    __syncthreads();
+    if (threadIdx.x < C) {
+        double v = 0.0;
+        for (int w = 0; w < NT / kWave; ++w) v = fmax(v, bm[w][threadIdx.x]);
+        a.blockmax[(int64_t)blockIdx.x * 4 + threadIdx.x] = (unsigned long long)__double_as_longlong(v);
+    }
+}
+
 // One workgroup per tile: the tile's particles deposit into LDS sums over
 // the tile and its upper halo, which are then added to the global sums.
-// Channels 0..C-1 carry phi (W words each), channel C the weights (1 word,
-// scale 2^f of the fine word: at most one unit of weight per particle).
-template <typename R, int D>
-__global__ __launch_bounds__(256) void k_cic_reduce(PsiArgs a)
+// Channels 0..C-1 carry phi (W words each), channel C the weights (W words,
+// at the scale of the fine word: at most one unit of weight per particle and
+// corner).
+template <typename R, int D, int NT>
+__global__ __launch_bounds__(NT) void k_cic_reduce(PsiArgs a)
 {
     constexpr int C = D + 1;
     constexpr int W = PsiWords<R>::value;
-    constexpr int NCH = W * C + 1;       // integer words per cell
+    constexpr int NCH = W * (C + 1);     // integer words per cell: C channels, then the weights
     extern __shared__ unsigned long long sacc[];
     const int hx = a.pt[0] + 1, hy = a.pt[1] + 1, hz = D == 3 ? a.pt[2] + 1 : 1;
     const int HC = hx * hy * hz;
@@ -758,10 +900,13 @@ __global__ __launch_bounds__(256) void k_cic_reduce(PsiArgs a)
     const CicRec<R>* bucket = (const CicRec<R>*)a.bucket;
     for (int64_t sl = beg + threadIdx.x; sl < end; sl += blockDim.x) {
         const CicRec<R> rec = bucket[sl];
-        if (rec.loc == kPsiSkip) continue;
-        const int l0 = (int)(rec.loc & (uint32_t)(a.pt[0] - 1));
-        const int l1 = (int)((rec.loc >> a.ptlog[0]) & (uint32_t)(a.pt[1] - 1));
-        const int l2 = D == 3 ? (int)(rec.loc >> (a.ptlog[0] + a.ptlog[1])) : 0;
+        // the cell in the tile: the low bits of a full code (sorted scatter)
+        // or of the cell itself; skipped records carry the skip bit
+        if (rec.loc & kPsiSkipBit) continue;
+        const uint32_t cl = rec.loc & (uint32_t)(a.cpt - 1);
+        const int l0 = (int)(cl & (uint32_t)(a.pt[0] - 1));
+        const int l1 = (int)((cl >> a.ptlog[0]) & (uint32_t)(a.pt[1] - 1));
+        const int l2 = D == 3 ? (int)(cl >> (a.ptlog[0] + a.ptlog[1])) : 0;
         double wa[3][2];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
@@ -785,7 +930,13 @@ __global__ __launch_bounds__(256) void k_cic_reduce(PsiArgs a)
                     atomicAdd(&sacc[(size_t)(W * k + 1) * HC + hc], (unsigned long long)lo);
                 }
             }
-            atomicAdd(&sacc[(size_t)(W * C) * HC + hc], (unsigned long long)llrint(w * qf));
+            // the weights, W words as the channels (the fine word keeps the
+            // remainder of each quantised weight, so sparse cells keep their
+            // relative accuracy)
+            const double wq = w * qf;
+            const double wh = rint(wq);
+            atomicAdd(&sacc[(size_t)(W * C) * HC + hc], (unsigned long long)(long long)wh);
+            if (W == 2) atomicAdd(&sacc[(size_t)(W * C + 1) * HC + hc], (unsigned long long)llrint((wq - wh) * qf));
         }
     }
     __syncthreads();
@@ -837,7 +988,11 @@ __global__ void k_cic_finish(PsiArgs a)
         if (W == 2) units += (double)(long long)a.acc[(size_t)(W * k + 1) * M + c] / qf;
         ((R*)a.out[k])[c] = (R)(f * (units / a.qscale[k]));
     }
-    if (a.den) ((R*)a.den)[c] = (R)((double)(long long)a.acc[(size_t)(W * C) * M + c] / qf);
+    if (a.den) {
+        double units = (double)(long long)a.acc[(size_t)(W * C) * M + c];
+        if (W == 2) units += (double)(long long)a.acc[(size_t)(W * C + 1) * M + c] / qf;
+        ((R*)a.den)[c] = (R)(units / qf);
+    }
 }
 
 template <typename R, int D>
@@ -847,7 +1002,7 @@ hipError_t launch_cic(const PsiArgs& a, hipStream_t s)
     constexpr int W = PsiWords<R>::value;
     hipError_t e = launch_fill_u64(a.maxbits, C, 0ull, s);
     if (e != hipSuccess) return e;
-    e = launch_fill_u64(a.acc, (int64_t)(W * C + 1) * a.m.M, 0ull, s);
+    e = launch_fill_u64(a.acc, (int64_t)(W * (C + 1)) * a.m.M, 0ull, s);
     if (e != hipSuccess) return e;
     const size_t lds_t = sizeof(unsigned int) * (size_t)a.pntiles;
     if (a.p.count == 0) {
@@ -859,12 +1014,24 @@ hipError_t launch_cic(const PsiArgs& a, hipStream_t s)
         FLA_LAUNCH((k_cic_count<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
         e = launch_exclusive_scan_u32(a.blockhist, (int64_t)a.pntiles * a.nblocks + 1, a.scan_tmp, a.scan_words, s);
         if (e != hipSuccess) return e;
-        FLA_LAUNCH((k_cic_scatter<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
+        if (a.direct)
+            FLA_LAUNCH((k_cic_scatter_sorted<R, D>), dim3(a.nblocks), dim3(256), 0, s, a);
+        else
+            FLA_LAUNCH((k_cic_scatter<R, D>), dim3(a.nblocks), dim3(256), lds_t, s, a);
     }
     FLA_LAUNCH((k_psi_scale<D>), dim3(1), dim3(256), 0, s, a);
     const int hcells = (a.pt[0] + 1) * (a.pt[1] + 1) * (D == 3 ? a.pt[2] + 1 : 1);
-    const size_t lds_r = sizeof(unsigned long long) * (size_t)(W * C + 1) * (size_t)hcells;
-    FLA_LAUNCH((k_cic_reduce<R, D>), dim3(a.pntiles), dim3(256), lds_r, s, a);
+    const size_t lds_r = sizeof(unsigned long long) * (size_t)(W * (C + 1)) * (size_t)hcells;
+    // large (sorted) tiles: one workgroup of 1024 threads per compute unit,
+    // so that enough waves issue the LDS atomics
+    if (a.direct) {
+        e = hipFuncSetAttribute((const void*)k_cic_reduce<R, D, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds_r);
+        if (e != hipSuccess) return e;
+        FLA_LAUNCH((k_cic_reduce<R, D, 1024>), dim3(a.pntiles), dim3(1024), lds_r, s, a);
+    } else {
+        FLA_LAUNCH((k_cic_reduce<R, D, 256>), dim3(a.pntiles), dim3(256), lds_r, s, a);
+    }
     FLA_LAUNCH((k_cic_finish<R, D>), dim3((unsigned)((a.m.M + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -61,6 +61,19 @@ def test_3d_ragged(ctx, prec, periodic):
     assert nf > 0 and (out > 0) == (not periodic)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_3d_many_tiles_unsorted_scatter(ctx, prec):
+    # 170 x 160 x 140 cells need more than 1024 of the sorted scatter's tiles
+    # (16 x 16 x 8; 16 x 8 x 8 in binary64), so the records take the
+    # unsorted scatter into the smaller tiles; ragged last tiles on every axis
+    mesh = W.Mesh(3, (170, 160, 140), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (True, False, True))
+    cloud = W.abc_cloud(600_000, seed=33)
+    cloud.x = cloud.x * 1.04 - 0.02
+    cloud.r[::997] = float("nan")
+    out, nf = _check(ctx, mesh, cloud, prec, 0.3, "3-D many tiles")
+    assert nf > 0 and out > 0
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_2d_taylor_green(ctx, prec):
     mesh = W.Mesh(2, (64, 45), (0.0, 0.0), (1.0, 1.0), (False, True))
