@@ -80,25 +80,33 @@ template <typename R, int D>
 __device__ inline bool load_terms(const TrajDev& t, int64_t i, double* x, double* J, double& det)
 {
     const int64_t N = t.count;
-    bool ok = true;
+    // every input is read, then tested with non-short-circuit ands, so that
+    // the loads issue together instead of one test's branch at a time
     double v[3], ug[3];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         x[a] = t.x[a][i];
         v[a] = (double)((const R*)t.v[a])[i];
         ug[a] = (double)((const R*)t.ug[a])[i];
-        ok = ok && isfinite(x[a]) && isfinite(v[a]) && isfinite(ug[a]);
     }
 #pragma unroll
-    for (int e = 0; e < D * D; ++e) {
-        J[e] = t.J[(int64_t)e * N + i];
-        ok = ok && isfinite(J[e]);
-    }
-    double r = (double)((const R*)t.r)[i];
-    double n0 = t.n0 ? t.n0[i] : t.n0_scalar;
+    for (int e = 0; e < D * D; ++e) J[e] = t.J[(int64_t)e * N + i];
+    const double r = (double)((const R*)t.r)[i];
+    const double n0 = t.n0 ? t.n0[i] : t.n0_scalar;
     det = det_rn<D>(J);
-    ok = ok && isfinite(r) && isfinite(n0) && isfinite(det) && det != 0.0;
-    return ok;
+    int fin = isfinite(r);
+    fin &= isfinite(n0);
+    fin &= isfinite(det);
+    fin &= det != 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        fin &= isfinite(x[a]);
+        fin &= isfinite(v[a]);
+        fin &= isfinite(ug[a]);
+    }
+#pragma unroll
+    for (int e = 0; e < D * D; ++e) fin &= isfinite(J[e]);
+    return fin != 0;
 }
 
 // Singular values of J (largest first) from the eigenvalues of J^T J: the
@@ -158,43 +166,58 @@ __device__ inline void singular_values(const double* J, double adet, double* s)
     s[2] = adet / (s[0] * s[1]);
 }
 
-// ---------------------------------------------------------------- neighbour counts
-// Home-cell counts of the valid trajectories (the prepass's validity); one
-// trajectory per thread (2 and 4 per thread, blockDim apart with all loads
-// issued first, took 119 and 126 against 114 us at 2M).  The home cell of
-// each trajectory, or kNoHome for an invalid one,
-// goes to the first word of its 16-byte feature record slot, where the
-// feature pass reads it before writing the record.
-constexpr int kHomePerThread = 1;
+// ---------------------------------------------------------------- counts and features
+// One trajectory per thread (2 and 4 per thread, blockDim apart with all
+// loads issued first, were slower).  The pass counts the valid trajectories
+// (the prepass's validity) per home cell with integer atomics and, from the
+// J it has loaded, forms the four features that do not need the counts: the
+// binary64 singular values and det J, standardised and rounded to bf16 as
+// the oracle forms them.  Its 16-byte record per trajectory is
+// {z0 z1, z2 z3, home cell, valid << 16}, with zeros and kNoHome for an
+// invalid trajectory; the network kernel replaces the home cell by z4, the
+// standardised log(1 + neighbour count), once the counts are box-summed.
 constexpr uint32_t kNoHome = 0xFFFFFFFFu;
 template <typename R, int D>
-__global__ __launch_bounds__(256) void k_home_count(TrajDev t, MeshDev m, unsigned int* cnt, uint32_t* home)
+__global__ __launch_bounds__(256) void k_home_count(TrajDev t, MeshDev m, const float* __restrict__ theta,
+                                                    unsigned int* __restrict__ cnt, uint4* __restrict__ zb,
+                                                    float* __restrict__ zout, float* __restrict__ fraw)
 {
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * kHomePerThread + threadIdx.x;
-    double x[kHomePerThread][3], J[kHomePerThread][9], det[kHomePerThread];
-    bool ok[kHomePerThread];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = t.count;
+    if (i >= N) return;
+    double x[3], J[9], det;
+    const bool ok = load_terms<R, D>(t, i, x, J, det);
+    uint4 rec = make_uint4(0u, 0u, kNoHome, 0u);
+    float f[4] = {0, 0, 0, 0};
+    if (ok) {
+        int64_t c = 0, st = 1;
 #pragma unroll
-    for (int u = 0; u < kHomePerThread; ++u) {
-        const int64_t i = i0 + (int64_t)u * blockDim.x;
-        ok[u] = i < t.count && load_terms<R, D>(t, i, x[u], J[u], det[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < kHomePerThread; ++u) {
-        const int64_t i = i0 + (int64_t)u * blockDim.x;
-        if (i >= t.count) break;
-        uint32_t h = kNoHome;
-        if (ok[u]) {
-            int64_t c = 0, st = 1;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                c += home_index(m, a, x[u][a]) * st;
-                st *= m.n[a];
-            }
-            atomicAdd(&cnt[c], 1u);
-            h = (uint32_t)c;
+        for (int a = 0; a < D; ++a) {
+            c += home_index(m, a, x[a]) * st;
+            st *= m.n[a];
         }
-        home[4 * i] = h;
+        atomicAdd(&cnt[c], 1u);
+        const double adet = fabs(det);
+        double s[3];
+        singular_values<D>(J, adet, s);
+        // binary64 features and standardisation: z is rounded to bf16 for the
+        // network, so it is formed as exactly as the oracle forms it
+        const double fd[4] = {log(s[0]), log(s[1]), D == 3 ? log(s[2]) : 0.0, -log(adet)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (fraw) fraw[(int64_t)k * N + i] = (float)fd[k];
+            f[k] = (float)((fd[k] - (double)theta[kOffMu + k]) / (double)theta[kOffSd + k]);
+        }
+        rec = make_uint4(bf16_bits(f[0]) | ((uint32_t)bf16_bits(f[1]) << 16),
+                         bf16_bits(f[2]) | ((uint32_t)bf16_bits(f[3]) << 16), (uint32_t)c, 1u << 16);
+    } else if (fraw) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fraw[(int64_t)k * N + i] = __builtin_nanf("");
     }
+    zb[i] = rec;
+    if (zout)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zout[(int64_t)k * N + i] = ok ? round_bf16(f[k]) : 0.0f;
 }
 
 // One axis of the 3^D box sum of the per-cell counts: out[c] = in[c - s] +
@@ -262,75 +285,18 @@ __device__ inline void stage_weights(const float* th, MlpW& W)
 
 constexpr int kMlpWaves = 4;
 
-// Features of one trajectory per thread: the binary64 singular values, the
-// neighbour count over the 3^D block of cells around the home cell (one read
-// of the box-summed counts), the
-// standardised inputs z rounded to bf16 and packed with a validity flag into
-// one 16-byte record {z0..z4, 0, 0, valid} for the network kernel.
-template <typename R, int D>
-__device__ inline void feature_one(const TrajDev& t, const MeshDev& m, const float* __restrict__ theta,
-                                   const unsigned int* __restrict__ cnt, uint4* __restrict__ zb,
-                                   float* __restrict__ zout, float* __restrict__ fraw, int64_t i)
-{
-    const int64_t N = t.count;
-    float f[kFeat] = {0, 0, 0, 0, 0};
-    // validity and home cell from the count pass (first word of the slot)
-    const uint32_t home = reinterpret_cast<const uint32_t*>(zb)[4 * i];
-    const bool ok = home != kNoHome;
-    if (ok) {
-        double J[9];
-#pragma unroll
-        for (int e = 0; e < D * D; ++e) J[e] = t.J[(int64_t)e * N + i];
-        double adet = fabs(det_rn<D>(J)), s[3];
-        singular_values<D>(J, adet, s);
-        // the box-summed count at the home cell
-        const unsigned int nb = cnt[home];
-        // binary64 features and standardisation: z is rounded to bf16 for the
-        // network, so it is formed as exactly as the oracle forms it
-        const double fd[kFeat] = {log(s[0]), log(s[1]), D == 3 ? log(s[2]) : 0.0, -log(adet), log1p((double)nb)};
-#pragma unroll
-        for (int k = 0; k < kFeat; ++k) {
-            if (fraw) fraw[(int64_t)k * N + i] = (float)fd[k];
-            f[k] = (float)((fd[k] - (double)theta[kOffMu + k]) / (double)theta[kOffSd + k]);
-        }
-    } else if (fraw) {
-#pragma unroll
-        for (int k = 0; k < kFeat; ++k) fraw[(int64_t)k * N + i] = __builtin_nanf("");
-    }
-    unsigned short zs[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) zs[k] = (k < kFeat && ok) ? bf16_bits(f[k]) : (unsigned short)0;
-    zs[7] = ok ? 1 : 0;
-    zb[i] = make_uint4(zs[0] | ((uint32_t)zs[1] << 16), zs[2] | ((uint32_t)zs[3] << 16),
-                       zs[4] | ((uint32_t)zs[5] << 16), zs[6] | ((uint32_t)zs[7] << 16));
-    if (zout)
-#pragma unroll
-        for (int k = 0; k < kFeat; ++k) zout[(int64_t)k * N + i] = ok ? round_bf16(f[k]) : 0.0f;
-}
-
-// Two trajectories per thread, blockDim apart: two independent binary64
-// chains for the scheduler to interleave.
-constexpr int kFeatPerThread = 2;
-template <typename R, int D>
-__global__ __launch_bounds__(256) void k_features(TrajDev t, MeshDev m, const float* __restrict__ theta,
-                                                  const unsigned int* __restrict__ cnt, uint4* __restrict__ zb,
-                                                  float* __restrict__ zout, float* __restrict__ fraw)
-{
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * kFeatPerThread + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < kFeatPerThread; ++u) {
-        const int64_t i = i0 + (int64_t)u * blockDim.x;
-        if (i < t.count) feature_one<R, D>(t, m, theta, cnt, zb, zout, fraw, i);
-    }
-}
-
-// The 5-64-64-1 network on bf16 MFMA.  One wave takes 64 feature records
-// per step (one per lane, into LDS), then four 16-trajectory groups go
-// through the layers; the output o gives the factor exp(s_max tanh o), 1 for
-// an invalid trajectory.
-__global__ __launch_bounds__(kWave * kMlpWaves) void k_mlp(const float* __restrict__ theta, int64_t N,
-                                                            const uint4* __restrict__ zb, float* __restrict__ hfac,
-                                                            float* __restrict__ oout)
+// The 5-64-64-1 network on bf16 MFMA, held to 128 registers for four waves
+// per SIMD (the binary32 activations bound it; 136 -> 125 us at 2M with a
+// few bytes of spill).  One wave takes 64 feature records
+// per step (one per lane, into LDS), completing each with its fifth input,
+// log(1 + N_nbr) from one read of the box-summed counts at the home cell;
+// then four 16-trajectory groups go through the layers.  The output o gives
+// the factor exp(s_max tanh o), 1 for an invalid trajectory.
+__global__ __launch_bounds__(kWave * kMlpWaves, 4) void k_mlp(const float* __restrict__ theta, int64_t N,
+                                                            const uint4* __restrict__ zb,
+                                                            const unsigned int* __restrict__ box,
+                                                            float* __restrict__ hfac, float* __restrict__ oout,
+                                                            float* __restrict__ zout, float* __restrict__ fraw)
 {
     __shared__ MlpW W;
     __shared__ __align__(16) unsigned short Z[kMlpWaves][kWave][kW1S];   // [traj][feature]
@@ -340,7 +306,8 @@ __global__ __launch_bounds__(kWave * kMlpWaves) void k_mlp(const float* __restri
     __syncthreads();
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int r16 = lane % 16, g4 = lane / 16;
-    // the biases and output weights of the lane's hidden rows 16 mt + 4 g4 + j
+    // the biases (each layer's accumulator starts from them) and output
+    // weights of the lane's hidden rows 16 mt + 4 g4 + j
     float b1r[4][4], b2r[4][4], w3r[4][4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -351,42 +318,63 @@ __global__ __launch_bounds__(kWave * kMlpWaves) void k_mlp(const float* __restri
             b2r[mt][j] = W.b2[hrow];
             w3r[mt][j] = W.w3[hrow];
         }
-    for (int64_t base = ((int64_t)blockIdx.x * kMlpWaves + wave) * kWave; base < N;
-         base += (int64_t)gridDim.x * kMlpWaves * kWave) {
+    // the record and box count of the wave's next step are loaded one step
+    // ahead (the count read depends on the record)
+    const int64_t stride = (int64_t)gridDim.x * kMlpWaves * kWave;
+    int64_t base = ((int64_t)blockIdx.x * kMlpWaves + wave) * kWave;
+    uint4 q4 = base + lane < N ? zb[base + lane] : make_uint4(0u, 0u, kNoHome, 0u);
+    unsigned int nbox = (q4.w >> 16) != 0u ? box[q4.z] : 0u;
+    for (; base < N; base += stride) {
         const int64_t i = base + lane;
-        const uint4 q4 = i < N ? zb[i] : make_uint4(0u, 0u, 0u, 0u);
+        const bool valid = (q4.w >> 16) != 0u;
+        const int64_t inext = i + stride;
+        const uint4 q4n = inext < N ? zb[inext] : make_uint4(0u, 0u, kNoHome, 0u);
+        // the fifth input from the box-summed count at the home cell, in
+        // binary64 as the oracle forms it
+        uint32_t z4 = 0u;
+        if (valid) {
+            const double fd = log1p((double)nbox);
+            const float f = (float)((fd - (double)W.mu[4]) / (double)W.sd[4]);
+            z4 = bf16_bits(f);
+            if (fraw) fraw[4 * N + i] = (float)fd;
+            if (zout) zout[4 * N + i] = bf16_val((unsigned short)z4);
+        } else if (i < N) {
+            if (fraw) fraw[4 * N + i] = __builtin_nanf("");
+            if (zout) zout[4 * N + i] = 0.0f;
+        }
         // features 0..4 then zeros up to 16 (the MFMA's k padding), 8-byte stores
         uint2* zrow = reinterpret_cast<uint2*>(&Z[wave][lane][0]);
         zrow[0] = make_uint2(q4.x, q4.y);
-        zrow[1] = make_uint2(q4.z & 0xFFFFu, 0u);
+        zrow[1] = make_uint2(z4, 0u);
         zrow[2] = make_uint2(0u, 0u);
         zrow[3] = make_uint2(0u, 0u);
-        vld[wave][lane] = (q4.w >> 16) != 0u;
+        vld[wave][lane] = valid;
         wave_sync();
         for (int q = 0; q < 4; ++q) {
             // layer 1: a1^T[64 x 16] = W1[64 x 16] * Z^T[16 x 16]
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                f32x4 acc = {0, 0, 0, 0};
+                f32x4 acc = {b1r[mt][0], b1r[mt][1], b1r[mt][2], b1r[mt][3]};
                 acc = mfma16(load4(&W.W1[16 * mt + r16][4 * g4]), load4(&Z[wave][16 * q + r16][4 * g4]), acc);
                 uint32_t hb[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) hb[j] = bf16_bits(silu_f(acc[j] + b1r[mt][j]));
+                for (int j = 0; j < 4; ++j) hb[j] = bf16_bits(silu_f(acc[j]));
                 // hidden rows 16 mt + 4 g4 .. + 3 of trajectory r16: one 8-byte store
                 *reinterpret_cast<uint2*>(&H1[wave][r16][16 * mt + 4 * g4]) =
                     make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
             }
             wave_sync();
+            if (q == 0) nbox = (q4n.w >> 16) != 0u ? box[q4n.z] : 0u;
             // layer 2 and the output dot product
             float op = 0.0f;
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                f32x4 acc = {0, 0, 0, 0};
+                f32x4 acc = {b2r[mt][0], b2r[mt][1], b2r[mt][2], b2r[mt][3]};
 #pragma unroll
                 for (int kb = 0; kb < 4; ++kb)
                     acc = mfma16(load4(&W.W2[16 * mt + r16][16 * kb + 4 * g4]), load4(&H1[wave][r16][16 * kb + 4 * g4]), acc);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) op += w3r[mt][j] * silu_f(acc[j] + b2r[mt][j]);
+                for (int j = 0; j < 4; ++j) op += w3r[mt][j] * silu_f(acc[j]);
             }
             op += __shfl_xor(op, 16, kWave);
             op += __shfl_xor(op, 32, kWave);
@@ -399,6 +387,7 @@ __global__ __launch_bounds__(kWave * kMlpWaves) void k_mlp(const float* __restri
             }
             wave_sync();
         }
+        q4 = q4n;
     }
 }
 
@@ -442,12 +431,28 @@ __global__ __launch_bounds__(256) void k_feat_moments(const float* __restrict__ 
     if (threadIdx.x < kMomW) part[(int64_t)blockIdx.x * kMomW + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// a + p[0] + p[stride] + ... + p[(n - 1) stride], added in that order; each
+// round issues its 16 loads before the first add so that they are in flight
+// together
+__device__ inline double ordered_column_sum(double a, const double* __restrict__ p, int n, int stride)
+{
+    constexpr int kRound = 16;
+    int i = 0;
+    for (; i + kRound <= n; i += kRound) {
+        double v[kRound];
+#pragma unroll
+        for (int k = 0; k < kRound; ++k) v[k] = p[(int64_t)(i + k) * stride];
+#pragma unroll
+        for (int k = 0; k < kRound; ++k) a += v[k];
+    }
+    for (; i < n; ++i) a += p[(int64_t)i * stride];
+    return a;
+}
+
 __global__ void k_feat_accum(const double* __restrict__ part, int nblk, double* __restrict__ acc)
 {
     if (threadIdx.x >= kMomW) return;
-    double a = acc[threadIdx.x];
-    for (int b = 0; b < nblk; ++b) a += part[(int64_t)b * kMomW + threadIdx.x];
-    acc[threadIdx.x] = a;
+    acc[threadIdx.x] = ordered_column_sum(acc[threadIdx.x], part + threadIdx.x, nblk, kMomW);
 }
 
 // mu = mean, sd = sample standard deviation (Bessel-corrected) + 1e-3
@@ -868,21 +873,22 @@ __global__ __launch_bounds__(256) void k_loss_partial(int C, int64_t M, Planes S
     }
 }
 
-__global__ void k_loss_final(int C, const double* part, int nb, double* out)   // out: loss, then |S-R|^2, |R|^2 per channel
+// out: the loss, then |S - R|^2 and |R|^2 of each channel; thread j adds
+// column j of the block partials in block order
+__global__ void k_loss_final(int C, const double* part, int nb, double* out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double loss = 0.0;
-    for (int k = 0; k < C; ++k) {
-        double a = 0.0, b = 0.0;
-        for (int i = 0; i < nb; ++i) {
-            a += part[(int64_t)i * 8 + 2 * k];
-            b += part[(int64_t)i * 8 + 2 * k + 1];
-        }
-        out[1 + 2 * k] = a;
-        out[2 + 2 * k] = b;
-        loss += b > 0.0 ? a / b : 0.0;
+    __shared__ double col[8];
+    const int j = threadIdx.x;
+    if (j < 2 * C) {
+        col[j] = ordered_column_sum(0.0, part + j, nb, 8);
+        out[1 + j] = col[j];
     }
-    out[0] = loss;
+    __syncthreads();
+    if (j == 0) {
+        double loss = 0.0;
+        for (int k = 0; k < C; ++k) loss += col[2 * k + 1] > 0.0 ? col[2 * k] / col[2 * k + 1] : 0.0;
+        out[0] = loss;
+    }
 }
 
 template <typename R>
@@ -904,8 +910,8 @@ hipError_t launch_bandwidth_forward(const TrajDev& t, const MeshDev& m, const fl
 {
     hipError_t e = launch_fill_u32(cnt, m.M, 0u, s);
     if (e != hipSuccess || t.count == 0) return e;
-    unsigned g = (unsigned)((t.count + 256 * kHomePerThread - 1) / (256 * kHomePerThread));
-    FLA_LAUNCH((k_home_count<R, D>), dim3(g), dim3(256), 0, s, t, m, cnt, (uint32_t*)zb);
+    const unsigned g = (unsigned)((t.count + 255) / 256);
+    FLA_LAUNCH((k_home_count<R, D>), dim3(g), dim3(256), 0, s, t, m, theta, cnt, (uint4*)zb, z, fraw);
     // box sums over the 3^D neighbourhoods, one pass per axis between the two
     // halves of cnt (2 M words)
     unsigned int* buf[2] = {cnt, cnt + m.M};
@@ -913,11 +919,10 @@ hipError_t launch_bandwidth_forward(const TrajDev& t, const MeshDev& m, const fl
     for (int a = 0; a < D; ++a)
         FLA_LAUNCH(k_box_axis, dim3(gm), dim3(256), 0, s, m, a, (const unsigned int*)buf[a & 1], buf[(a + 1) & 1]);
     const unsigned int* box = buf[D & 1];
-    const unsigned gf = (unsigned)((t.count + 256 * kFeatPerThread - 1) / (256 * kFeatPerThread));
-    FLA_LAUNCH((k_features<R, D>), dim3(gf), dim3(256), 0, s, t, m, theta, box, (uint4*)zb, z, fraw);
     int64_t groups = (t.count + kWave * kMlpWaves - 1) / (kWave * kMlpWaves);
     unsigned gb = (unsigned)(groups < 2048 ? groups : 2048);
-    FLA_LAUNCH(k_mlp, dim3(gb), dim3(kWave * kMlpWaves), 0, s, theta, t.count, (const uint4*)zb, hfac, o);
+    FLA_LAUNCH(k_mlp, dim3(gb), dim3(kWave * kMlpWaves), 0, s, theta, t.count, (const uint4*)zb, box, hfac, o, z,
+               fraw);
     return hipGetLastError();
 }
 

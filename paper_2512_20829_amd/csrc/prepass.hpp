@@ -205,23 +205,29 @@ __device__ inline void prepass_traj(const TrajDev& t, const K& key, const PhysDe
 {
     const int64_t N = t.count;
     double x[3] = {0, 0, 0}, J[9], v[3], ug[3];
-    bool ok = true;
+    // every input is read, then tested with non-short-circuit ands, so that
+    // the loads issue together instead of one test's branch at a time
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         x[a] = t.x[a][i];
         v[a] = (double)((const R*)t.v[a])[i];
         ug[a] = (double)((const R*)t.ug[a])[i];
-        ok = ok && isfinite(x[a]) && isfinite(v[a]) && isfinite(ug[a]);
     }
 #pragma unroll
-    for (int e = 0; e < D * D; ++e) {
-        J[e] = t.J[(int64_t)e * N + i];
-        ok = ok && isfinite(J[e]);
+    for (int e = 0; e < D * D; ++e) J[e] = t.J[(int64_t)e * N + i];
+    const double r = (double)((const R*)t.r)[i];
+    const double n0 = t.n0 ? t.n0[i] : t.n0_scalar;
+    const double fac = hfac ? (double)hfac[i] : 1.0;
+    int fin = isfinite(r);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        fin &= isfinite(x[a]);
+        fin &= isfinite(v[a]);
+        fin &= isfinite(ug[a]);
     }
-    double r = (double)((const R*)t.r)[i];
-    double n0 = t.n0 ? t.n0[i] : t.n0_scalar;
-    double fac = hfac ? (double)hfac[i] : 1.0;
-    ok = ok && isfinite(r);
+#pragma unroll
+    for (int e = 0; e < D * D; ++e) fin &= isfinite(J[e]);
+    const bool ok = fin != 0;
     double phi[4] = {0, 0, 0, 0};
     if (ok) droplet_phi<D>(r, v, ug, ph, phi);
     emit_records<R, D>(key, ph, fac, deposit, N, i, gi, key_base, sentinel, x, J, n0, phi, ok, t.seed_volume, keys,
