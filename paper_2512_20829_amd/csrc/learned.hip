@@ -636,22 +636,40 @@ __global__ __launch_bounds__(64) void k_traj_backward(MeshDev m, double cutoff, 
 // writes one partial gradient; a second kernel adds the partials in block
 // order.
 constexpr int kBwdWaves = 4;
+// Held to 256 registers (a few bytes of spill) so that, with the shared
+// tiles below, two workgroups fit on a CU (one wave per SIMD took 1.7x as
+// long at 2M).
 template <int D>
-__global__ __launch_bounds__(kWave * kBwdWaves) void k_mlp_backward(const float* theta, int64_t N, const float* z,
+__global__ __launch_bounds__(kWave * kBwdWaves, 2) void k_mlp_backward(const float* theta, int64_t N, const float* z,
                                                                     const float* o, const float* dlogh, float* partial)
 {
     __shared__ MlpW W;
     __shared__ unsigned short W2T[kHidden][kW2S];         // W2 transposed, bf16 (padded rows)
-    __shared__ unsigned short Zs[kBwdWaves][16][kW1S];    // [traj][feature]
-    __shared__ unsigned short H1[kBwdWaves][16][kW2S];    // [traj][hidden]
-    __shared__ unsigned short D2h[kBwdWaves][kHidden][kW1S], D2l[kBwdWaves][kHidden][kW1S];   // [hidden][traj]
-    __shared__ unsigned short D1h[kBwdWaves][kHidden][kW1S], D1l[kBwdWaves][kHidden][kW1S];
-    __shared__ float dO[kBwdWaves][16];
-    __shared__ float gsum[kTrain];
+    // the waves' tiles of the loop and, after it, the block's gradient sum
+    // share one buffer (LDS for two workgroups per CU)
+    struct Tiles {
+        unsigned short Zs[kBwdWaves][16][kW1S];    // [traj][feature]
+        unsigned short H1[kBwdWaves][16][kW2S];    // [traj][hidden]
+        unsigned short D2h[kBwdWaves][kHidden][kW1S], D2l[kBwdWaves][kHidden][kW1S];   // [hidden][traj]
+        unsigned short D1h[kBwdWaves][kHidden][kW1S], D1l[kBwdWaves][kHidden][kW1S];
+        float dO[kBwdWaves][16];
+    };
+    union Shared {
+        Tiles t;
+        float gsum[kTrain];
+    };
+    __shared__ Shared U;
+    auto& Zs = U.t.Zs;
+    auto& H1 = U.t.H1;
+    auto& D2h = U.t.D2h;
+    auto& D2l = U.t.D2l;
+    auto& D1h = U.t.D1h;
+    auto& D1l = U.t.D1l;
+    auto& dO = U.t.dO;
+    float* gsum = U.gsum;
     stage_weights(theta, W);
     for (int e = threadIdx.x; e < kHidden * kHidden; e += blockDim.x)
         W2T[e % kHidden][e / kHidden] = bf16_bits(theta[kOffW2 + e]);
-    for (int e = threadIdx.x; e < kTrain; e += blockDim.x) gsum[e] = 0.0f;
     __syncthreads();
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     const int r16 = lane % 16, g4 = lane / 16;
@@ -772,7 +790,11 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_mlp_backward(const float*
             }
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) gb3 += __shfl_xor(gb3, off, kWave);
-    // waves add into the block sum one after the other (fixed order)
+    // waves add into the block sum one after the other (fixed order), once
+    // every wave has left the loop's tiles
+    __syncthreads();
+    for (int e = threadIdx.x; e < kTrain; e += blockDim.x) gsum[e] = 0.0f;
+    __syncthreads();
     for (int w = 0; w < kBwdWaves; ++w) {
         if (wave == w) {
 #pragma unroll
