@@ -101,8 +101,11 @@ __device__ inline void producer_rhs(const FlowDev& f, const PhysDev& ph, const d
     }
 }
 
+// Held to 256 registers so that two waves share a SIMD (the binary64 RK4
+// chains are long; a few bytes of spill): 1.64 -> 1.35 ms for 2M droplets
+// in 3-D; at 168 registers the spills made it twice as slow.
 template <typename R, int D>
-__global__ __launch_bounds__(256) void k_produce(ProduceArgs p, MeshDev m, PhysDev ph, const float* hfac, int deposit,
+__global__ __launch_bounds__(256, 2) void k_produce(ProduceArgs p, MeshDev m, PhysDev ph, const float* hfac, int deposit,
                                                  uint32_t* keys, uint32_t* vals, double4* rpos, R* rw, double* qd,
                                                  unsigned long long* stats)
 {
