@@ -1121,7 +1121,7 @@ def main():
 
     main_sec = head or abc or tg
     name = {"headline": "multi-vortex 256^3", "abc128": "ABC 128^3", "tg2d": "Taylor-Green 2-D FP64"}[args.only or "headline"]
-    configs = {
+    workload_configs = {
         "headline": {"workload": "3-D multi-vortex map (two ABC maps, amplitudes 0.2 and 0.1, wavenumbers 1 and 2; "
                                  "folds, |det J| down to ~1e-8), 256^3 periodic mesh, 32,768,000 lattice "
                                  "trajectories (320^3), FP32 kernel with FP64 det J, h0 = 1/320, cutoff 4",
@@ -1146,7 +1146,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_sec is tg else "f32",
         "data": "synthetic",
-        "config": configs[args.only or "headline"],
+        "config": workload_configs[args.only or "headline"],
         "pairs_per_s": main_sec["pairs_per_s"],
         "pairs": main_sec["pairs"],
         "max_class": main_sec["max_class"],
