@@ -146,7 +146,11 @@ def features(mesh, x: np.ndarray, J: np.ndarray, valid: np.ndarray) -> np.ndarra
     meshes the third singular value is taken as 1 (log = 0)."""
     dim = mesh.dim
     N = x.shape[1]
+    v = valid.astype(bool)
     Jm = np.moveaxis(J.reshape(dim, dim, N), 2, 0)         # (N, dim, dim), row-major a*dim+b
+    # a skipped trajectory's J may be non-finite, which the SVD cannot take;
+    # its features are zero whatever stands in for it
+    Jm = np.where(v[:, None, None], Jm, np.eye(dim))
     s = np.linalg.svd(Jm, compute_uv=False)                 # descending
     f = np.zeros((N_FEAT, N))
     for k in range(dim):
@@ -154,7 +158,7 @@ def features(mesh, x: np.ndarray, J: np.ndarray, valid: np.ndarray) -> np.ndarra
     adet = np.abs(np.linalg.det(Jm))
     f[3] = -np.log(adet)                                    # log(n / n0) = -log|det J| (eq. FLA-COM)
     f[4] = np.log1p(neighbour_counts(mesh, x, valid))
-    f[:, ~valid.astype(bool)] = 0.0
+    f[:, ~v] = 0.0
     return f
 
 

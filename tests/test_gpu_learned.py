@@ -260,6 +260,39 @@ def test_learned_form_full_size(ctx):
     theta = _theta(23, f0)
     hf, z, o, fr = _gpu_forward(ctx, wl, theta)
     fw, f, t = _oracle_forward(wl, theta)
+    _check_large_forward(theta, hf, z, o, fr, fw, f, t)
+    g32 = torch.tensor(fw.g, dtype=torch.float32)
+    S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False, h_factor=g32)
+    cells = np.sort(np.random.default_rng(2).choice(wl.mesh.cells, 256, replace=False))
+    oracle.set_threads(16)
+    ref, _ = oracle_run(wl, prec="f32", cells=cells, h_factor=g32)
+    for k in range(ref.S.shape[0]):
+        assert rel_l2(S[k, cells], ref.S[k]) <= 1e-5, k
+    assert rel_l2(den[cells], ref.den) <= 1e-5
+
+
+def test_forward_ragged_steps_with_invalid_trajectories(ctx):
+    """700,001 random trajectories (more than one wave step of the network
+    kernel, the last one partial), every 997th with a non-finite J entry:
+    features, network output and factor against the oracle, and factor 1
+    for the invalid ones."""
+    wl = W.small_random_3d(700_001, 64, seed=31)
+    bad = np.arange(5, wl.traj.count, 997)
+    wl.traj.J[4, torch.from_numpy(bad)] = float("nan")
+    print(f"[case] learned ragged N={wl.traj.count}, {bad.size} invalid", flush=True)
+    _, f0, _ = _oracle_forward(wl, LN.init_params(0))
+    theta = _theta(31, f0)
+    hf, z, o, fr = _gpu_forward(ctx, wl, theta)
+    fw, f, t = _oracle_forward(wl, theta)
+    assert np.all(t.valid[bad] == 0) and int(np.sum(t.valid == 0)) == bad.size
+    _check_large_forward(theta, hf, z, o, fr, fw, f, t)
+    assert np.all(hf[bad] == 1.0) and np.all(o[bad] == 0.0)
+    assert np.all(np.isnan(fr[:, bad])) and np.all(z[:, bad] == 0.0)
+
+
+def _check_large_forward(theta, hf, z, o, fr, fw, f, t):
+    """Features, bf16 inputs, network output and factor of a large forward
+    against the oracle, within the bound of first-layer bf16 flips."""
     v = t.valid == 1
     np.testing.assert_allclose(fr[:, v], f[:, v], rtol=1e-6, atol=1e-6)
     assert np.mean(z[:, v] == fw.z[:, v]) > 0.999
@@ -288,11 +321,3 @@ def test_learned_form_full_size(ctx):
     assert np.all(np.abs(hf[v] - fw.g[v]) <= gbound[v] * fw.g[v]), \
         (np.abs(hf[v] - fw.g[v]) / fw.g[v] - gbound[v]).max()
     assert np.mean(np.abs(hf[v] - fw.g[v]) > 4e-3 * fw.g[v]) <= 1e-4
-    g32 = torch.tensor(fw.g, dtype=torch.float32)
-    S, den, st = gpu_run(ctx, wl, prec="f32", count_pairs=False, h_factor=g32)
-    cells = np.sort(np.random.default_rng(2).choice(wl.mesh.cells, 256, replace=False))
-    oracle.set_threads(16)
-    ref, _ = oracle_run(wl, prec="f32", cells=cells, h_factor=g32)
-    for k in range(ref.S.shape[0]):
-        assert rel_l2(S[k, cells], ref.S[k]) <= 1e-5, k
-    assert rel_l2(den[cells], ref.den) <= 1e-5

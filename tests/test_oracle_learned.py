@@ -41,6 +41,29 @@ def test_singular_value_and_density_features():
     np.testing.assert_allclose(f[3], -np.log(np.prod(svals, axis=1)), rtol=1e-10, atol=1e-12)
 
 
+def test_skipped_trajectories_have_zero_features_whatever_their_J():
+    """A skipped trajectory (non-finite J included) has zero features, and
+    the valid trajectories' singular values and det J do not depend on it;
+    only the neighbour counts see validity."""
+    rng = np.random.default_rng(3)
+    N = 40
+    J = rng.standard_normal((9, N)) + 2.0 * np.eye(3).reshape(9, 1)
+    x = rng.uniform(0, 1, (3, N))
+    mesh = W.unit_mesh(3, 6, True)
+    valid = np.ones(N, dtype=np.int32)
+    valid[[3, 17]] = 0
+    f_ok = LN.features(mesh, x, J, valid)
+    Jb = J.copy()
+    Jb[4, 3] = np.nan
+    Jb[0, 17] = np.inf
+    f_bad = LN.features(mesh, x, Jb, valid)
+    assert np.all(f_bad[:, [3, 17]] == 0.0)
+    np.testing.assert_array_equal(f_bad, f_ok)
+    f_all = LN.features(mesh, x, J, np.ones(N, dtype=np.int32))
+    v = valid == 1
+    np.testing.assert_array_equal(f_bad[:4, v], f_all[:4, v])
+
+
 def test_neighbour_count_brute_force():
     rng = np.random.default_rng(2)
     for periodic in (True, False):
